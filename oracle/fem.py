@@ -1,0 +1,159 @@
+"""Finite-element mass and stiffness matrices (FP64, CPU).  Test infrastructure.
+
+Follows the space discretization of the paper (Section "Cardiac
+electrophysiology: numerical discretization"): M_jk is the integral of
+phi_k phi_j over the domain, K_jk the integral of D grad(phi_k) . grad(phi_j),
+with Gauss quadrature of the fewest points that integrate M exactly:
+2x2x2 Gauss-Legendre points for trilinear hexahedra (Q1) and the symmetric
+4-point degree-2 rule for linear tetrahedra (P1).
+
+The diffusion tensor is the one of the monodomain model (eq. of the diffusion
+tensor): D = sigma_l f f^T + sigma_t s s^T + sigma_n n n^T, rescaled by
+1/(chi C_m) (the rescaling stated below the dimensional monodomain equation).
+Nodal tensors are interpolated to quadrature points with the FE basis.
+
+Pins: closed-form Q1 / P1 element matrices, K 1 = 0, 1^T M 1 = |Omega|,
+the cosine eigenmode of the slab, the 7-point stencil of the Kuhn-split
+lattice (tests/test_oracle_fem.py).
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+
+
+def nodal_diffusion(f0, s0, n0, sigma_l, sigma_t, sigma_n, chi, cm):
+    """D at every node, [n_nodes, 3, 3], in mm^2/ms (eq. of the diffusion tensor
+    divided by chi*C_m)."""
+    f0 = np.asarray(f0, np.float64)
+    s0 = np.asarray(s0, np.float64)
+    n0 = np.asarray(n0, np.float64)
+    D = (sigma_l * np.einsum("ni,nj->nij", f0, f0)
+         + sigma_t * np.einsum("ni,nj->nij", s0, s0)
+         + sigma_n * np.einsum("ni,nj->nij", n0, n0))
+    return D / (chi * cm)
+
+
+# ---------------------------------------------------------------------------
+# Q1 hexahedra
+# ---------------------------------------------------------------------------
+
+def _q1_reference():
+    """Shape values [q, 8] and reference gradients [q, 8, 3] at the 2x2x2
+    Gauss points of [-1, 1]^3 (weights all 1).  Local node k = a + 2b + 4c at
+    the corner (2a-1, 2b-1, 2c-1)."""
+    g = 1.0 / np.sqrt(3.0)
+    pts = [(x, y, z) for z in (-g, g) for y in (-g, g) for x in (-g, g)]
+    N = np.zeros((8, 8))
+    dN = np.zeros((8, 8, 3))
+    for q, (x, y, z) in enumerate(pts):
+        for c in (0, 1):
+            for b in (0, 1):
+                for a in (0, 1):
+                    k = a + 2 * b + 4 * c
+                    sa, sb, sc = 2 * a - 1, 2 * b - 1, 2 * c - 1
+                    fx, fy, fz = 1 + sa * x, 1 + sb * y, 1 + sc * z
+                    N[q, k] = fx * fy * fz / 8.0
+                    dN[q, k] = (sa * fy * fz / 8.0, sb * fx * fz / 8.0, sc * fx * fy / 8.0)
+    w = np.ones(8)
+    return N, dN, w
+
+
+def q1_element_matrices(X, Dn):
+    """Element mass and stiffness for a batch of trilinear hexahedra.
+
+    X  : [E, 8, 3] corner coordinates (lexicographic local order)
+    Dn : [E, 8, 3, 3] nodal diffusion tensors of the element's corners
+    returns Me [E, 8, 8], Ke [E, 8, 8]
+    """
+    N, dN, w = _q1_reference()
+    E = X.shape[0]
+    Me = np.zeros((E, 8, 8))
+    Ke = np.zeros((E, 8, 8))
+    for q in range(N.shape[0]):
+        # J[e, i, j] = d x_j / d xi_i
+        J = np.einsum("ki,ekj->eij", dN[q], X)
+        detJ = np.linalg.det(J)
+        Jinv = np.linalg.inv(J)
+        # physical gradients G[e, k, :] = J^{-1} dN_ref[k]
+        G = np.einsum("eij,kj->eki", Jinv, dN[q])
+        Dq = np.einsum("k,ekij->eij", N[q], Dn)
+        wq = w[q] * detJ
+        Me += wq[:, None, None] * np.outer(N[q], N[q])[None]
+        Ke += wq[:, None, None] * np.einsum("eai,eij,ebj->eab", G, Dq, G)
+    return Me, Ke
+
+
+# ---------------------------------------------------------------------------
+# P1 tetrahedra
+# ---------------------------------------------------------------------------
+
+_TET_A = 0.5854101966249685
+_TET_B = 0.1381966011250105
+
+
+def _p1_rule():
+    """Barycentric points [4, 4] and weights (fractions of the volume) of the
+    symmetric 4-point rule, exact for polynomials of degree 2."""
+    L = np.full((4, 4), _TET_B)
+    np.fill_diagonal(L, _TET_A)
+    return L, np.full(4, 0.25)
+
+
+def p1_element_matrices(X, Dn):
+    """Element mass and stiffness for a batch of linear tetrahedra.
+
+    X  : [E, 4, 3]; Dn : [E, 4, 3, 3]
+    """
+    E = X.shape[0]
+    T = np.stack([X[:, 1] - X[:, 0], X[:, 2] - X[:, 0], X[:, 3] - X[:, 0]], axis=1)  # rows = edges
+    detT = np.linalg.det(T)
+    vol = np.abs(detT) / 6.0
+    Tinv = np.linalg.inv(T)
+    # gradients of barycentric coordinates: grad L_{1..3} = columns of T^{-1}
+    G = np.zeros((E, 4, 3))
+    G[:, 1:, :] = np.transpose(Tinv, (0, 2, 1))
+    G[:, 0, :] = -G[:, 1:, :].sum(axis=1)
+    L, w = _p1_rule()
+    Me = np.zeros((E, 4, 4))
+    Ke = np.zeros((E, 4, 4))
+    for q in range(4):
+        Dq = np.einsum("k,ekij->eij", L[q], Dn)
+        wq = w[q] * vol
+        Me += wq[:, None, None] * np.outer(L[q], L[q])[None]
+        Ke += wq[:, None, None] * np.einsum("eai,eij,ebj->eab", G, Dq, G)
+    return Me, Ke
+
+
+# ---------------------------------------------------------------------------
+# Assembly
+# ---------------------------------------------------------------------------
+
+def assemble(xyz, conn, Dnodal, chunk: int = 200000):
+    """Global M and K (scipy CSR, FP64) by summing element contributions."""
+    xyz = np.asarray(xyz, np.float64)
+    conn = np.asarray(conn, np.int64)
+    n = xyz.shape[0]
+    npe = conn.shape[1]
+    rows, cols, mv, kv = [], [], [], []
+    for e0 in range(0, conn.shape[0], chunk):
+        c = conn[e0:e0 + chunk]
+        X = xyz[c]
+        Dn = Dnodal[c]
+        if npe == 8:
+            Me, Ke = q1_element_matrices(X, Dn)
+        elif npe == 4:
+            Me, Ke = p1_element_matrices(X, Dn)
+        else:
+            raise ValueError("element type")
+        rows.append(np.repeat(c, npe, axis=1).ravel())
+        cols.append(np.tile(c, (1, npe)).ravel())
+        mv.append(Me.ravel())
+        kv.append(Ke.ravel())
+    r = np.concatenate(rows)
+    cidx = np.concatenate(cols)
+    M = sp.coo_matrix((np.concatenate(mv), (r, cidx)), shape=(n, n)).tocsr()
+    K = sp.coo_matrix((np.concatenate(kv), (r, cidx)), shape=(n, n)).tocsr()
+    M.sum_duplicates()
+    K.sum_duplicates()
+    return M, K

@@ -1,0 +1,175 @@
+"""Pins of the oracle's finite-element assembly against closed forms.
+
+Each check comes from the mathematics, not from the oracle's own formulas:
+tensor-product 1D matrices, exact integrals of linear functions, Neumann
+row sums, the domain volume, the slab's cosine eigenmodes and the 7-point
+stencil of the Kuhn-split lattice.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import workloads as W
+from oracle import fem
+
+
+def _m1(h):
+    return h / 6.0 * np.array([[2.0, 1.0], [1.0, 2.0]])
+
+
+def _k1(h):
+    return 1.0 / h * np.array([[1.0, -1.0], [-1.0, 1.0]])
+
+
+def _box(hx, hy, hz):
+    X = np.zeros((8, 3))
+    for c in (0, 1):
+        for b in (0, 1):
+            for a in (0, 1):
+                X[a + 2 * b + 4 * c] = (a * hx, b * hy, c * hz)
+    return X
+
+
+def test_q1_box_matches_tensor_product():
+    hx, hy, hz = 0.3, 0.7, 1.1
+    dx, dy, dz = 0.9, 0.2, 0.05
+    X = _box(hx, hy, hz)[None]
+    Dn = np.tile(np.diag([dx, dy, dz]), (1, 8, 1, 1))
+    Me, Ke = fem.q1_element_matrices(X, Dn)
+    # local index a + 2b + 4c -> kron(z, kron(y, x))
+    M_ref = np.kron(_m1(hz), np.kron(_m1(hy), _m1(hx)))
+    K_ref = (dx * np.kron(_m1(hz), np.kron(_m1(hy), _k1(hx)))
+             + dy * np.kron(_m1(hz), np.kron(_k1(hy), _m1(hx)))
+             + dz * np.kron(_k1(hz), np.kron(_m1(hy), _m1(hx))))
+    assert np.max(np.abs(Me[0] - M_ref)) < 1e-15
+    assert np.max(np.abs(Ke[0] - K_ref)) < 1e-14
+
+
+def test_q1_parallelepiped_linear_fields():
+    """On an affine hexahedron, linear fields are in the Q1 space, so
+    v^T K v = vol a^T D a and v^T M v = integral of (a.x + c)^2 exactly."""
+    rng = np.random.default_rng(0)
+    B = np.array([[1.0, 0.2, 0.1], [0.3, 0.8, -0.2], [0.1, 0.25, 1.3]])
+    X = _box(1.0, 1.0, 1.0) @ B.T + np.array([0.4, -1.0, 2.0])
+    vol = abs(np.linalg.det(B))
+    Dm = rng.normal(size=(3, 3))
+    D = Dm @ Dm.T + np.eye(3)
+    Me, Ke = fem.q1_element_matrices(X[None], np.tile(D, (1, 8, 1, 1)))
+    a = np.array([0.7, -1.2, 0.4])
+    v = X @ a
+    assert abs(v @ Ke[0] @ v - vol * a @ D @ a) < 1e-12
+    assert abs(np.sum(Me[0]) - vol) < 1e-14
+    # integral of (a.x)^2 over the parallelepiped via an independent tensor Gauss rule
+    g, w = np.polynomial.legendre.leggauss(4)
+    s = (g + 1) / 2
+    acc = 0.0
+    for i, x in enumerate(s):
+        for j, y in enumerate(s):
+            for k, z in enumerate(s):
+                p = B @ np.array([x, y, z]) + np.array([0.4, -1.0, 2.0])
+                acc += w[i] * w[j] * w[k] / 8.0 * (a @ p) ** 2
+    acc *= vol
+    assert abs(v @ Me[0] @ v - acc) < 1e-12
+
+
+def test_p1_reference_tet():
+    X = np.array([[0.0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]])[None]
+    Me, Ke = fem.p1_element_matrices(X, np.tile(np.eye(3), (1, 4, 1, 1)))
+    K_ref = np.array([[3, -1, -1, -1], [-1, 1, 0, 0], [-1, 0, 1, 0], [-1, 0, 0, 1]]) / 6.0
+    M_ref = (1.0 / 6.0) / 20.0 * (np.ones((4, 4)) + np.eye(4))
+    assert np.max(np.abs(Ke[0] - K_ref)) < 1e-15
+    assert np.max(np.abs(Me[0] - M_ref)) < 1e-16
+
+
+def test_p1_general_tet_linear_fields():
+    rng = np.random.default_rng(1)
+    X = rng.normal(size=(4, 3))
+    vol = abs(np.linalg.det(np.stack([X[1] - X[0], X[2] - X[0], X[3] - X[0]]))) / 6.0
+    Dm = rng.normal(size=(3, 3))
+    D = Dm @ Dm.T + 0.1 * np.eye(3)
+    Me, Ke = fem.p1_element_matrices(X[None], np.tile(D, (1, 4, 1, 1)))
+    a = rng.normal(size=3)
+    v = X @ a
+    assert abs(v @ Ke[0] @ v - vol * a @ D @ a) < 1e-12 * max(1.0, vol * a @ D @ a)
+    assert np.max(np.abs(Me[0] - vol / 20.0 * (np.ones((4, 4)) + np.eye(4)))) < 1e-15
+
+
+def _slab_mk(h=0.5, D=(0.12, 0.013, 0.009)):
+    m = W.slab_q1(20.0, 7.0, 3.0, h)
+    f, s, n = W.uniform_fibers(m.n_nodes)
+    Dn = fem.nodal_diffusion(f, s, n, D[0], D[1], D[2], 1.0, 1.0)
+    M, K = fem.assemble(m.xyz, m.conn, Dn)
+    return m, M, K
+
+
+def test_neumann_row_sums_and_volume():
+    m, M, K = _slab_mk()
+    assert np.max(np.abs(K @ np.ones(m.n_nodes))) < 1e-14
+    assert abs(np.ones(m.n_nodes) @ (M @ np.ones(m.n_nodes)) - 20.0 * 7.0 * 3.0) < 1e-10
+    assert abs(M - M.T).max() < 1e-17 and abs(K - K.T).max() < 1e-17
+
+
+def test_system_matrix_spd_small():
+    m = W.slab_q1(2.0, 1.5, 1.0, 0.5)
+    f, s, n = W.random_fibers(m.n_nodes, 3)
+    Dn = fem.nodal_diffusion(f, s, n, 0.17, 0.019, 0.01, 140.0, 0.01)
+    M, K = fem.assemble(m.xyz, m.conn, Dn)
+    A = (1.5 / 0.05) * M + K
+    ev = np.linalg.eigvalsh(A.toarray())
+    assert ev.min() > 0
+    evk = np.linalg.eigvalsh(K.toarray())
+    assert abs(evk.min()) < 1e-13 and np.sort(evk)[1] > 1e-6   # one-dimensional kernel
+
+
+@pytest.mark.parametrize("k", [1, 3, 7])
+def test_cosine_mode_is_generalized_eigenvector(k):
+    D = (0.12, 0.013, 0.009)
+    m, M, K = _slab_mk(0.5, D)
+    nx = m.dims[0]
+    h = 20.0 / (nx - 1)
+    theta = k * np.pi / (nx - 1)
+    lam = 6.0 / h ** 2 * (1 - np.cos(theta)) / (2 + np.cos(theta))
+    v = np.cos(k * np.pi * m.xyz[:, 0] / 20.0)
+    r = K @ v - D[0] * lam * (M @ v)
+    assert np.max(np.abs(r)) < 1e-13
+
+
+def test_kuhn_lattice_p1_is_seven_point_stencil():
+    h, d = 0.25, 0.7
+    m = W.slab_p1(2.0, 2.0, 2.0, h)
+    f, s, n = W.uniform_fibers(m.n_nodes)
+    Dn = fem.nodal_diffusion(f, s, n, d, d, d, 1.0, 1.0)
+    _, K = fem.assemble(m.xyz, m.conn, Dn)
+    nx, ny, nz = m.dims
+    K = K.tocsr()
+    interior = [ix + nx * (iy + ny * iz) for iz in range(1, nz - 1) for iy in range(1, ny - 1)
+                for ix in range(1, nx - 1)]
+    for i in interior[::7]:
+        row = K.getrow(i)
+        ent = dict(zip(row.indices, row.data))
+        expect = {i: 6 * h * d, i - 1: -h * d, i + 1: -h * d, i - nx: -h * d, i + nx: -h * d,
+                  i - nx * ny: -h * d, i + nx * ny: -h * d}
+        for j, val in ent.items():
+            assert abs(val - expect.get(j, 0.0)) < 1e-14, (i, j, val)
+        for j in expect:
+            assert j in ent
+    # total volume
+    M, _ = fem.assemble(m.xyz, m.conn, Dn)
+    assert abs(M.sum() - 8.0) < 1e-12
+
+
+def test_lv_shell_mesh_is_valid():
+    m, (f, s, n), endo = W.lv_shell(4, 24, 10)
+    X = m.xyz[m.conn]
+    vol = np.einsum("ij,ij->i", np.cross(X[:, 1] - X[:, 0], X[:, 2] - X[:, 0]), X[:, 3] - X[:, 0]) / 6
+    assert vol.min() > 0
+    # orthonormal fibers
+    for a, b in ((f, s), (f, n), (s, n)):
+        assert np.max(np.abs(np.sum(a * b, axis=1))) < 1e-12
+    for a in (f, s, n):
+        assert np.max(np.abs(np.linalg.norm(a, axis=1) - 1)) < 1e-12
+    # conforming: every interior face shared by exactly two tets
+    faces = np.sort(np.concatenate([m.conn[:, [0, 1, 2]], m.conn[:, [0, 1, 3]],
+                                    m.conn[:, [0, 2, 3]], m.conn[:, [1, 2, 3]]]), axis=1)
+    _, cnt = np.unique(faces, axis=0, return_counts=True)
+    assert cnt.max() == 2
