@@ -1,0 +1,220 @@
+/*
+ * ep.h -- C ABI of the MI355X monodomain time-step library (libep_mi355x.so).
+ *
+ * What it computes (Africa et al., "lifex-ep", Section "Cardiac
+ * electrophysiology: numerical discretization"): the monodomain equation
+ * (eq. of the monodomain model, one subdomain, homogeneous Neumann boundary)
+ * discretized in space by linear finite elements (Q1 hexahedra or P1
+ * tetrahedra) and in time by the BDF/IMEX scheme of the same section:
+ *   1. ionic step at every node, evaluated at the extrapolated potential
+ *      u_EXT (eq. of the time-discrete ionic model): gating variables by
+ *      Rush-Larsen, other variables by one explicit step;
+ *   2. linear monodomain step (eq. of the time-discrete monodomain equation
+ *      and the algebraic linear system that follows it):
+ *        (alpha/dt M + K) u_{n+1} = M (u_BDF/dt + I_app - I_ion),
+ *      with the ionic current interpolated from nodal values (ICI), solved by
+ *      Jacobi-preconditioned CG in FP64, or by FP32 CG inside FP64 iterative
+ *      refinement (mixed precision);
+ *   3. activation time = time of the largest du/dt at each node (Section
+ *      "Slab benchmark").
+ * Units: mm, ms, mV, mS/mm, 1/mm, uF/mm^2, uA/mm^3.
+ *
+ * Conventions
+ *   - Every call returns ep_status; ep_last_error() gives a message for the
+ *     last non-OK status on the calling thread.  No C++ exception crosses
+ *     this interface.
+ *   - Host input arrays are borrowed for the duration of the call and copied.
+ *     Host output arrays are caller-allocated with the sizes stated.
+ *   - All device memory is owned by the library, except the `dst` of
+ *     ep_sim_get_potential_device, which the caller owns (e.g. a torch tensor).
+ *   - An ep_sim is not thread-safe; different sims may be used from
+ *     different threads.
+ *   - Work is enqueued on the sim's HIP stream.  Errors raised on the device
+ *     (non-convergence, NaN) are reported by the next call that synchronizes.
+ */
+#ifndef EP_MI355X_H
+#define EP_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ep_sim ep_sim;
+typedef struct ep_pool ep_pool;
+
+typedef enum {
+  EP_OK = 0,
+  EP_EINVAL = -1,   /* invalid argument or call order                        */
+  EP_ENOMEM = -2,   /* device or host allocation failed                      */
+  EP_EHIP = -3,     /* HIP runtime error (no device, launch failure, ...)    */
+  EP_ENOCONV = -4,  /* a linear solve hit max_it; the step kept its iterate  */
+  EP_ENAN = -5,     /* NaN in the solution; stepping stopped                 */
+  EP_EAGAIN = -6,   /* pool full (HBM budget or slots); retry after release  */
+  EP_ESTATE = -7    /* call not valid in the object's current state          */
+} ep_status;
+
+enum { EP_TET4 = 4, EP_HEX8 = 8 };                                   /* element types   */
+enum { EP_PASSIVE = 0, EP_AP = 1, EP_BO = 2, EP_TTP06 = 3 };          /* ionic models    */
+enum { EP_CELL_EPI = 0, EP_CELL_ENDO = 1, EP_CELL_MID = 2 };          /* TTP06 variants  */
+enum { EP_CUBE = 0, EP_SPHERE = 1, EP_GAUSS = 2 };                    /* stimulus shapes */
+enum { EP_FP64 = 0, EP_MIXED = 1 };                                   /* precision       */
+enum { EP_JACOBI = 0 };                                               /* preconditioner  */
+enum { EP_DTYPE_F64 = 0, EP_DTYPE_F32 = 1 };
+enum { EP_FMT_AUTO = 0, EP_FMT_SELL = 1, EP_FMT_DIA = 2 };            /* matrix format   */
+
+/* Options for ep_sim_set_option (before finalize unless stated). */
+enum {
+  EP_OPT_MATRIX_FORMAT = 1, /* EP_FMT_*; AUTO picks DIA when it moves fewer bytes      */
+  EP_OPT_INNER_RTOL = 2,    /* mixed precision: inner FP32 CG relative tolerance (1e-4)  */
+  EP_OPT_MAX_OUTER = 3,     /* mixed precision: max refinement sweeps per step (30)      */
+  EP_OPT_PHASE_TIMERS = 4   /* 1: time ionic / rhs / solve / activation phases (any time) */
+};
+
+typedef struct ep_stats {
+  int64_t n_nodes;
+  int64_t nnz;              /* nonzeros of the assembled operator                   */
+  int64_t steps;            /* completed time steps                                 */
+  int64_t cg_iters_total;   /* CG iterations (inner iterations when mixed)         */
+  int32_t cg_iters_last;    /* CG iterations of the last step                       */
+  int32_t cg_iters_max;     /* largest per-step count                               */
+  int64_t ir_sweeps_total;  /* mixed precision: FP64 refinement sweeps              */
+  double rel_residual_last; /* ||b - A u||_2 / ||b||_2 at the end of the last solve */
+  int32_t matrix_format;    /* EP_FMT_SELL or EP_FMT_DIA                            */
+  int32_t n_diag;           /* DIA diagonals (0 for SELL)                           */
+  int64_t device_bytes;     /* device memory held by the sim                        */
+  double ms_ionic, ms_rhs, ms_solve, ms_activation; /* phase times (if enabled)     */
+  double ms_setup;          /* host assembly + upload in ep_sim_finalize            */
+} ep_stats;
+
+/* ---- simulation lifecycle -------------------------------------------------- */
+
+/* Create a simulation on HIP device `device`.  hip_stream: a hipStream_t to
+ * enqueue on (e.g. torch.cuda.current_stream().cuda_stream), or NULL for a
+ * library-owned stream.  EP_EHIP if the device is not usable. */
+ep_status ep_sim_create(int device, void* hip_stream, ep_sim** out);
+
+/* Mesh (paper: tetrahedral or hexahedral conforming mesh).  xyz: [n_nodes][3]
+ * coordinates in mm; conn: [n_elems][elem] node indices, hexahedra in
+ * lexicographic corner order (corner a + 2b + 4c at reference (a, b, c)).
+ * material_id must be NULL (one subdomain).  EP_EINVAL on bad sizes or
+ * out-of-range indices (checked in finalize for element geometry). */
+ep_status ep_sim_upload_mesh(ep_sim* sim, int elem, int64_t n_nodes, const double* xyz,
+                             int64_t n_elems, const int32_t* conn, const int32_t* material_id);
+
+/* Fiber, sheet and normal directions per node (paper: the orthonormal triplet
+ * f0, s0, n0 of the diffusion tensor), each [n_nodes][3].  Default if never
+ * called: f0 = e_x, s0 = e_y, n0 = e_z. */
+ep_status ep_sim_upload_fibers(ep_sim* sim, const double* f0, const double* s0, const double* n0);
+
+/* Conductivities (mS/mm), membrane surface-to-volume ratio chi (1/mm) and
+ * capacitance C_m (uF/mm^2); the diffusion tensor is
+ * D = (sigma_l f f^T + sigma_t s s^T + sigma_n n n^T)/(chi C_m)
+ * (paper: eq. of the diffusion tensor and the rescaling below the dimensional
+ * monodomain equation).  Defaults 0.17, 0.019, 0.019, 140, 0.01. */
+ep_status ep_sim_set_conductivity(ep_sim* sim, double sigma_l, double sigma_t, double sigma_n,
+                                  double chi, double cm);
+
+/* Ionic model (paper: the ionic models it ships).  variant: EP_CELL_* for
+ * TTP06, 0 otherwise.  params: NULL for the published defaults, else
+ * n_params values overriding the first slots of the model's parameter list:
+ *   EP_AP:    k, a, eps0, mu1, mu2, T_ms
+ *   EP_BO:    the 28 constants of the minimal model in the order u_o, u_u,
+ *             theta_v, theta_w, theta_v-, theta_o, tau_v1-, tau_v2-, tau_v+,
+ *             tau_w1-, tau_w2-, k_w-, u_w-, tau_w+, tau_fi, tau_o1, tau_o2,
+ *             tau_so1, tau_so2, k_so, u_so, tau_s1, tau_s2, k_s, u_s, tau_si,
+ *             tau_winf, w_inf*
+ *   EP_TTP06: GNa, GK1, Gto, GKr, GKs, GCaL, GbNa, GbCa, GpCa, GpK, kNaCa,
+ *             PNaK, Vrel, Vleak, Vmaxup, Vxfer
+ * init_state: NULL for the model's initial conditions, else 1 + n_vars values
+ * (u in model units, then the state in the order of ep_sim_set_state),
+ * applied uniformly. */
+ep_status ep_sim_set_ionic_model(ep_sim* sim, int model, int variant, const double* params,
+                                 int n_params, const double* init_state);
+
+/* Applied current (paper: "Applied current" impulses).  shape EP_CUBE (size =
+ * edge, closed cube), EP_SPHERE (size = radius, closed ball), EP_GAUSS (size =
+ * standard deviation, untruncated).  amp in uA/mm^3 (divided by chi C_m to give
+ * mV/ms).  Active on steps n+1 whose time t_{n+1} lies in
+ * (t0 + k period, t0 + k period + dur]; period 0 = one pulse.  Times are
+ * rounded to whole steps.  At most 8 distinct timings. */
+ep_status ep_sim_add_stimulus(ep_sim* sim, int shape, const double center_mm[3], double size_mm,
+                              double amp_uA_per_mm3, double t0_ms, double dur_ms,
+                              double period_ms);
+
+/* Time step, BDF order (1..3; paper: BDF of order sigma with start-up at
+ * lower orders), precision (EP_FP64 or EP_MIXED), preconditioner (EP_JACOBI),
+ * block (unused, 1), relative residual tolerance ||b - A u|| <= rtol ||b||,
+ * and max CG iterations per solve (inner solve when mixed). */
+ep_status ep_sim_set_solver(ep_sim* sim, double dt_ms, int bdf_order, int precision, int precond,
+                            int block, double rtol, int max_it);
+
+ep_status ep_sim_set_option(ep_sim* sim, int key, double value);
+
+/* Assemble M and K on the host, build the device operator and upload
+ * everything.  The configuration is immutable afterwards. */
+ep_status ep_sim_finalize(ep_sim* sim);
+
+/* Enqueue and run n_steps time steps.  Blocks until the last step's solve
+ * has converged.  EP_ENOCONV (the step kept its last iterate and stepping
+ * went on) or EP_ENAN (stepping stopped) are sticky until the next step call. */
+ep_status ep_sim_step(ep_sim* sim, int n_steps);
+ep_status ep_sim_sync(ep_sim* sim);
+
+/* Potential u_n in mV ([n_nodes], caller-allocated host array); dimensionless
+ * models are mapped by u_mV = 100 u - 80 (AP) and 85.7 u - 84 (BO). */
+ep_status ep_sim_get_potential(ep_sim* sim, double* out_mV);
+
+/* Same into device memory owned by the caller: dtype EP_DTYPE_F64 or _F32,
+ * [n_nodes] elements; enqueued on the sim's stream. */
+ep_status ep_sim_get_potential_device(ep_sim* sim, void* dst, int dtype);
+
+/* Activation times in ms ([n_nodes]): time t_{n+1} of the first strictly
+ * largest forward difference (u_{n+1} - u_n)/dt; NaN where u never exceeded
+ * the activation threshold (-40 mV for TTP06, 0.5 for AP / BO). */
+ep_status ep_sim_get_activation_times(ep_sim* sim, double* out_ms);
+
+/* Time (ms) of the first step whose u_{n+1} exceeded the activation
+ * threshold, NaN if none ([n_nodes]). */
+ep_status ep_sim_get_threshold_times(ep_sim* sim, double* out_ms);
+
+ep_status ep_sim_get_stats(ep_sim* sim, ep_stats* out);
+
+/* Raw state in model units (after finalize).  u: [n_nodes]; w: [n_vars][n_nodes]
+ * in the model's state order (AP: v; BO: v, w, s; TTP06: m h j xr1 xr2 xs s r
+ * d f f2 fcass cai casr cass nai ki rr); u_prev: [bdf-1][n_nodes] holding
+ * u_{n-1}, u_{n-2} (NULL: copies of u).  set_state sets the step counter to
+ * step_index and clears the activation-time tracking.  get_state fills any
+ * non-NULL argument. */
+ep_status ep_sim_set_state(ep_sim* sim, const double* u, const double* w, const double* u_prev,
+                           int64_t step_index);
+ep_status ep_sim_get_state(ep_sim* sim, double* u, double* w, double* u_prev);
+int ep_sim_n_vars(const ep_sim* sim);
+
+void ep_sim_destroy(ep_sim* sim);
+
+/* Estimated device bytes ep_sim_finalize would allocate (sim configured, not
+ * finalized); used for admission control. */
+ep_status ep_sim_device_bytes_estimate(ep_sim* sim, size_t* bytes);
+
+/* ---- host-only entry points (no GPU needed) -------------------------------- */
+
+/* The library's finite-element assembly, for inspection: CSR of M and K
+ * (see ep_sim_set_conductivity for D).  Call with rowptr == NULL to get
+ * *nnz_out, then again with rowptr [n_nodes+1] (int64), col [nnz] (int32),
+ * valM and valK [nnz] (double).  f0/s0/n0 may be NULL (axis-aligned). */
+ep_status ep_assemble_csr(int elem, int64_t n_nodes, const double* xyz, int64_t n_elems,
+                          const int32_t* conn, const double* f0, const double* s0,
+                          const double* n0, double sigma_l, double sigma_t, double sigma_n,
+                          double chi, double cm, int64_t* nnz_out, int64_t* rowptr, int32_t* col,
+                          double* valM, double* valK);
+
+const char* ep_last_error(void);
+const char* ep_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EP_MI355X_H */

@@ -1,0 +1,214 @@
+"""MI355X-native monodomain time step (lifex-ep method) behind a C ABI.
+
+Python binding with the same names as include/ep.h; argument marshalling
+only.  Every step of the time-stepping path runs in the HIP kernels of
+libep_mi355x.so; there is no CPU fallback: if the library is missing, import
+fails.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import EpError, EpStats, check, lib
+
+# constants (include/ep.h)
+EP_TET4, EP_HEX8 = 4, 8
+EP_PASSIVE, EP_AP, EP_BO, EP_TTP06 = 0, 1, 2, 3
+EP_CELL_EPI, EP_CELL_ENDO, EP_CELL_MID = 0, 1, 2
+EP_CUBE, EP_SPHERE, EP_GAUSS = 0, 1, 2
+EP_FP64, EP_MIXED = 0, 1
+EP_JACOBI = 0
+EP_DTYPE_F64, EP_DTYPE_F32 = 0, 1
+EP_FMT_AUTO, EP_FMT_SELL, EP_FMT_DIA = 0, 1, 2
+EP_OPT_MATRIX_FORMAT, EP_OPT_INNER_RTOL, EP_OPT_MAX_OUTER, EP_OPT_PHASE_TIMERS = 1, 2, 3, 4
+
+MODEL_IDS = {"passive": EP_PASSIVE, "ap": EP_AP, "bo": EP_BO, "ttp06": EP_TTP06}
+CELL_IDS = {"": EP_CELL_EPI, "epi": EP_CELL_EPI, "endo": EP_CELL_ENDO, "mid": EP_CELL_MID}
+
+
+def _pd(a):
+    return a.ctypes.data_as(_lib.PD)
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+class Simulation:
+    """One monodomain simulation on one GPU (wraps ep_sim)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        h = C.c_void_p()
+        check(lib.ep_sim_create(int(device), C.c_void_p(stream) if stream else None, C.byref(h)),
+              "ep_sim_create")
+        self._h = h
+        self.n_nodes = 0
+        self.bdf = 1
+
+    # -- configuration ---------------------------------------------------------
+    def upload_mesh(self, elem: int, xyz, conn):
+        xyz = _f64(xyz)
+        conn = np.ascontiguousarray(conn, dtype=np.int32)
+        self.n_nodes = xyz.shape[0]
+        check(lib.ep_sim_upload_mesh(self._h, int(elem), xyz.shape[0], _pd(xyz), conn.shape[0],
+                                     conn.ctypes.data_as(_lib.PI32), None), "ep_sim_upload_mesh")
+
+    def upload_fibers(self, f0, s0, n0):
+        f0, s0, n0 = _f64(f0), _f64(s0), _f64(n0)
+        check(lib.ep_sim_upload_fibers(self._h, _pd(f0), _pd(s0), _pd(n0)), "ep_sim_upload_fibers")
+
+    def set_conductivity(self, sigma_l, sigma_t, sigma_n, chi, cm):
+        check(lib.ep_sim_set_conductivity(self._h, sigma_l, sigma_t, sigma_n, chi, cm),
+              "ep_sim_set_conductivity")
+
+    def set_ionic_model(self, model: int, variant: int = 0, params=None, init_state=None):
+        p = _f64(params) if params is not None else None
+        s = _f64(init_state) if init_state is not None else None
+        check(lib.ep_sim_set_ionic_model(self._h, int(model), int(variant), _pd(p) if p is not None else None,
+                                         0 if p is None else p.size, _pd(s) if s is not None else None),
+              "ep_sim_set_ionic_model")
+
+    def add_stimulus(self, shape, center, size, amp, t0=0.0, dur=2.0, period=0.0):
+        c = _f64(center)
+        check(lib.ep_sim_add_stimulus(self._h, int(shape), _pd(c), size, amp, t0, dur, period),
+              "ep_sim_add_stimulus")
+
+    def set_solver(self, dt, bdf=1, precision=EP_FP64, precond=EP_JACOBI, block=1, rtol=1e-10, max_it=1000):
+        self.bdf = int(bdf)
+        check(lib.ep_sim_set_solver(self._h, dt, int(bdf), int(precision), int(precond), int(block), rtol,
+                                    int(max_it)), "ep_sim_set_solver")
+
+    def set_option(self, key, value):
+        check(lib.ep_sim_set_option(self._h, int(key), float(value)), "ep_sim_set_option")
+
+    def finalize(self):
+        check(lib.ep_sim_finalize(self._h), "ep_sim_finalize")
+
+    def device_bytes_estimate(self) -> int:
+        v = C.c_size_t()
+        check(lib.ep_sim_device_bytes_estimate(self._h, C.byref(v)), "ep_sim_device_bytes_estimate")
+        return int(v.value)
+
+    # -- stepping and results ---------------------------------------------------
+    def step(self, n_steps: int = 1, allow_noconv: bool = False):
+        return check(lib.ep_sim_step(self._h, int(n_steps)), "ep_sim_step",
+                     allow=(_lib.EP_ENOCONV,) if allow_noconv else ())
+
+    def sync(self):
+        check(lib.ep_sim_sync(self._h), "ep_sim_sync")
+
+    def get_potential(self):
+        out = np.empty(self.n_nodes)
+        check(lib.ep_sim_get_potential(self._h, _pd(out)), "ep_sim_get_potential")
+        return out
+
+    def get_potential_device(self, dst_ptr: int, dtype: int = EP_DTYPE_F64):
+        check(lib.ep_sim_get_potential_device(self._h, C.c_void_p(dst_ptr), int(dtype)),
+              "ep_sim_get_potential_device")
+
+    def get_activation_times(self):
+        out = np.empty(self.n_nodes)
+        check(lib.ep_sim_get_activation_times(self._h, _pd(out)), "ep_sim_get_activation_times")
+        return out
+
+    def get_threshold_times(self):
+        out = np.empty(self.n_nodes)
+        check(lib.ep_sim_get_threshold_times(self._h, _pd(out)), "ep_sim_get_threshold_times")
+        return out
+
+    def get_stats(self) -> dict:
+        st = EpStats()
+        check(lib.ep_sim_get_stats(self._h, C.byref(st)), "ep_sim_get_stats")
+        return {name: getattr(st, name) for name, _ in EpStats._fields_}
+
+    @property
+    def n_vars(self) -> int:
+        return lib.ep_sim_n_vars(self._h)
+
+    def set_state(self, u, w, u_prev=None, step_index: int = 0):
+        u = _f64(u)
+        w = _f64(w, (self.n_vars, self.n_nodes)) if self.n_vars else np.zeros(1)
+        up = _f64(u_prev) if u_prev is not None else None
+        check(lib.ep_sim_set_state(self._h, _pd(u), _pd(w), _pd(up) if up is not None else None,
+                                   int(step_index)), "ep_sim_set_state")
+
+    def get_state(self):
+        u = np.empty(self.n_nodes)
+        w = np.empty((max(self.n_vars, 0), self.n_nodes))
+        up = np.empty((max(self.bdf - 1, 1), self.n_nodes))
+        check(lib.ep_sim_get_state(self._h, _pd(u), _pd(w) if self.n_vars else None, _pd(up)),
+              "ep_sim_get_state")
+        return u, w, up[: self.bdf - 1]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.ep_sim_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- convenience -----------------------------------------------------------
+    @classmethod
+    def from_spec(cls, spec, precision=EP_FP64, device=0, stream=None, rtol=None, max_it=1000,
+                  matrix_format=EP_FMT_AUTO, finalize=True, inner_rtol=None):
+        """Configure from a workloads.SimSpec (marshalling of its arrays)."""
+        sim = cls(device, stream)
+        m = spec.mesh
+        sim.upload_mesh(m.elem, m.xyz, m.conn)
+        if spec.fibers is not None:
+            sim.upload_fibers(*spec.fibers)
+        p = spec.phys
+        sim.set_conductivity(p.sigma_l, p.sigma_t, p.sigma_n, p.chi, p.cm)
+        sim.set_ionic_model(MODEL_IDS[spec.model], CELL_IDS.get(spec.variant, 0))
+        for st in spec.stimuli:
+            sim.add_stimulus(st.shape, st.center, st.size, st.amp, st.t0, st.dur, st.period)
+        sim.set_solver(spec.dt, spec.bdf, precision, EP_JACOBI, 1, spec.rtol if rtol is None else rtol, max_it)
+        if matrix_format != EP_FMT_AUTO:
+            sim.set_option(EP_OPT_MATRIX_FORMAT, matrix_format)
+        if inner_rtol is not None:
+            sim.set_option(EP_OPT_INNER_RTOL, inner_rtol)
+        if finalize:
+            sim.finalize()
+        return sim
+
+
+def assemble_csr(elem, xyz, conn, fibers=None, sigma=(0.17, 0.019, 0.019), chi=140.0, cm=0.01):
+    """The library's host-side FE assembly (ep_assemble_csr): (rowptr, col, valM, valK)."""
+    xyz = _f64(xyz)
+    conn = np.ascontiguousarray(conn, dtype=np.int32)
+    if fibers is not None:
+        f0, s0, n0 = (_f64(a) for a in fibers)
+        fp = (_pd(f0), _pd(s0), _pd(n0))
+    else:
+        fp = (None, None, None)
+    nnz = C.c_int64()
+    args = (int(elem), xyz.shape[0], _pd(xyz), conn.shape[0], conn.ctypes.data_as(_lib.PI32), *fp,
+            sigma[0], sigma[1], sigma[2], chi, cm)
+    check(lib.ep_assemble_csr(*args, C.byref(nnz), None, None, None, None), "ep_assemble_csr")
+    rowptr = np.empty(xyz.shape[0] + 1, np.int64)
+    col = np.empty(nnz.value, np.int32)
+    vm = np.empty(nnz.value)
+    vk = np.empty(nnz.value)
+    check(lib.ep_assemble_csr(*args, C.byref(nnz), rowptr.ctypes.data_as(_lib.PI64),
+                              col.ctypes.data_as(_lib.PI32), _pd(vm), _pd(vk)), "ep_assemble_csr")
+    return rowptr, col, vm, vk
+
+
+def version() -> str:
+    return lib.ep_version().decode()

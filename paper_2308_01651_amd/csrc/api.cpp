@@ -1,0 +1,918 @@
+// C-ABI implementation: simulation objects, one-time setup, the step loop
+// and the batched pool.  All per-node arithmetic of a step runs in the HIP
+// kernels of kernels.hip; this file only configures, uploads and sequences.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/ep.h"
+#include "assembly.h"
+#include "ep_device.h"
+#include "kernels.h"
+
+using namespace ep;
+
+namespace {
+
+thread_local std::string g_err;
+
+ep_status fail(ep_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define EP_HIP(call)                                                                      \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess) return fail(EP_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// ---- model tables (defaults from the original model publications) ----------
+
+struct ModelInfo {
+  int nvars;
+  double mv_per_unit, mv_offset, threshold;
+};
+
+ModelInfo model_info(int model) {
+  switch (model) {
+    case EP_AP: return {1, 100.0, -80.0, 0.5};
+    case EP_BO: return {3, 85.7, -84.0, 0.5};
+    case EP_TTP06: return {18, 1.0, 0.0, -40.0};
+    default: return {0, 1.0, 0.0, 0.5};
+  }
+}
+
+void default_params(int model, int variant, double* mp) {
+  for (int k = 0; k < NPARAM; k++) mp[k] = 0.0;
+  if (model == EP_AP) {
+    const double p[6] = {8.0, 0.15, 0.002, 0.2, 0.3, 12.9};
+    std::copy(p, p + 6, mp);
+  } else if (model == EP_BO) {
+    // minimal model, EPI set
+    const double p[28] = {0.0,    1.55,    0.3,     0.13,   0.006, 0.006,  60.0,   1150.0, 1.4506, 60.0,
+                          15.0,   65.0,    0.03,    200.0,  0.11,  400.0,  6.0,    30.0181, 0.9957, 2.0458,
+                          0.65,   2.7342,  16.0,    2.0994, 0.9087, 1.8875, 0.07,   0.94};
+    std::copy(p, p + 28, mp);
+  } else if (model == EP_TTP06) {
+    const double p[16] = {14.838, 5.405, 0.294,  0.153, 0.392, 3.980e-5, 0.00029, 0.000592,
+                          0.1238, 0.0146, 1000.0, 2.724, 0.102, 0.00036,  0.006375, 0.0038};
+    std::copy(p, p + 16, mp);
+    if (variant == EP_CELL_ENDO) mp[2] = 0.073;
+    if (variant == EP_CELL_MID) mp[4] = 0.098;
+    mp[16] = (variant == EP_CELL_ENDO) ? 1.0 : 0.0;
+  }
+}
+
+int n_model_params(int model) {
+  switch (model) {
+    case EP_AP: return 6;
+    case EP_BO: return 28;
+    case EP_TTP06: return 16;
+    default: return 0;
+  }
+}
+
+// u, then the state in model order
+std::vector<double> default_init(int model) {
+  switch (model) {
+    case EP_AP: return {0.0, 0.0};
+    case EP_BO: return {0.0, 1.0, 1.0, 0.0};
+    case EP_TTP06:
+      return {-85.23, 0.00172, 0.7444, 0.7045, 0.00621, 0.4712, 0.00095, 0.999998, 2.42e-8, 3.373e-5,
+              0.7888, 0.9755,  0.9953, 0.000126, 3.64,  0.00036, 8.604,  136.89,   0.9073};
+    default: return {0.0};
+  }
+}
+
+// ---- device allocation bookkeeping ------------------------------------------
+
+struct DevMem {
+  std::vector<void*> ptrs;
+  size_t bytes = 0;
+  hipError_t alloc(void** p, size_t nbytes) {
+    *p = nullptr;
+    if (nbytes == 0) nbytes = 256;
+    hipError_t e = hipMalloc(p, nbytes);
+    if (e == hipSuccess) {
+      ptrs.push_back(*p);
+      bytes += nbytes;
+    }
+    return e;
+  }
+  void release() {
+    for (void* p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+    bytes = 0;
+  }
+};
+
+struct Stim {
+  int shape;
+  double c[3];
+  double size, amp, t0, dur, period;
+};
+
+}  // namespace
+
+struct ep_sim {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  // configuration
+  int elem = 0;
+  int64_t n = 0, n_elems = 0;
+  std::vector<double> xyz, f0, s0, n0;
+  std::vector<int32_t> conn;
+  double sl = 0.17, st = 0.019, sn = 0.019, chi = 140.0, cm = 0.01;
+  int model = -1, variant = 0;
+  std::vector<double> params, init;
+  std::vector<Stim> stims;
+  double dt = 0.05, rtol = 1e-10, inner_rtol = 1e-4;
+  int bdf = 1, prec = EP_FP64, precond = EP_JACOBI, block = 1, max_it = 1000, max_outer = 30;
+  int fmt_pref = EP_FMT_AUTO;
+  int timers = 0;
+  // products
+  bool finalized = false;
+  bool in_pool = false;
+  DevMem mem;
+  InstDesc desc{};
+  InstDesc* d_desc = nullptr;
+  BlockMap* d_bmap = nullptr;
+  int nblocks = 0;
+  InstState* d_st = nullptr;
+  InstState* h_st = nullptr;  // pinned
+  int64_t guard = 0;
+  int64_t nnz = 0;
+  int nvars = 0;
+  ModelInfo mi{};
+  double ms_setup = 0.0;
+  double ms_phase[4] = {0, 0, 0, 0};
+  hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  int it_pred = 8;      // CG iterations launched before the first convergence check
+  int in_pred = 8;      // inner iterations per refinement sweep (mixed)
+  int sticky = EP_OK;
+};
+
+namespace {
+
+int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+ep_status check_sim(ep_sim* s) {
+  if (!s) return fail(EP_EINVAL, "null sim");
+  return EP_OK;
+}
+
+// Read the device state into pinned host memory (synchronizes the stream).
+ep_status pull_state(ep_sim* s) {
+  EP_HIP(hipMemcpyAsync(s->h_st, s->d_st, sizeof(InstState), hipMemcpyDeviceToHost, s->stream));
+  EP_HIP(hipStreamSynchronize(s->stream));
+  return EP_OK;
+}
+
+double stim_profile(const Stim& t, const double* x) {
+  const double dx = x[0] - t.c[0], dy = x[1] - t.c[1], dz = x[2] - t.c[2];
+  if (t.shape == EP_CUBE) {
+    const double m = std::max(std::fabs(dx), std::max(std::fabs(dy), std::fabs(dz)));
+    return m <= 0.5 * t.size + 1e-9 ? 1.0 : 0.0;
+  }
+  if (t.shape == EP_SPHERE) return std::sqrt(dx * dx + dy * dy + dz * dz) <= t.size + 1e-9 ? 1.0 : 0.0;
+  return std::exp(-(dx * dx + dy * dy + dz * dz) / (2.0 * t.size * t.size));
+}
+
+size_t estimate_bytes(const ep_sim* s) {
+  const int64_t n = s->n;
+  const double nnz_row = (s->elem == EP_HEX8) ? 27.0 : 16.0;
+  const bool mixed = s->prec == EP_MIXED;
+  const ModelInfo mi = model_info(s->model);
+  double per_node = 11 * 8.0 + 24.0 + 8.0 * 3;                  // FP64 vectors, activation, dinv
+  per_node += mixed ? (5 * 4.0 + 3 * 4.0) : 0.0;
+  per_node += mixed ? (mi.nvars * 4.0 + 8.0) : mi.nvars * 8.0;
+  per_node += nnz_row * ((s->bdf + 1) * 8.0 + 4.0 + (mixed ? s->bdf * 4.0 : 0.0));
+  per_node += 8.0 * std::min<size_t>(s->stims.size(), MAX_STIM);
+  return (size_t)(per_node * n * 1.05) + (1u << 20);
+}
+
+template <typename T>
+hipError_t upload(DevMem& m, T** d, const T* h, size_t count, hipStream_t st) {
+  hipError_t e = m.alloc((void**)d, count * sizeof(T));
+  if (e != hipSuccess) return e;
+  return hipMemcpyAsync(*d, h, count * sizeof(T), hipMemcpyHostToDevice, st);
+}
+
+ep_status finalize_impl(ep_sim* s) {
+  auto t0 = std::chrono::steady_clock::now();
+  if (s->finalized) return fail(EP_ESTATE, "sim already finalized");
+  if (s->n <= 0) return fail(EP_ESTATE, "no mesh uploaded");
+  if (s->model < 0) return fail(EP_ESTATE, "no ionic model set");
+  EP_HIP(hipSetDevice(s->device));
+  // ---- assembly ----
+  Csr A;
+  std::vector<char> err;
+  if (!assemble_csr(s->elem, s->n, s->xyz.data(), s->n_elems, s->conn.data(),
+                    s->f0.empty() ? nullptr : s->f0.data(), s->s0.empty() ? nullptr : s->s0.data(),
+                    s->n0.empty() ? nullptr : s->n0.data(), s->sl, s->st, s->sn, s->chi, s->cm, A, err))
+    return fail(EP_EINVAL, std::string("assembly: ") + (err.empty() ? "failed" : err.data()));
+  const int64_t n = s->n;
+  const int64_t nnz = A.nnz();
+  s->nnz = nnz;
+  const bool mixed = s->prec == EP_MIXED;
+  const double alphas[3] = {1.0, 1.5, 11.0 / 6.0};
+  const int nsig = s->bdf;
+  // diagonal positions
+  std::vector<int64_t> dpos(n);
+  for (int64_t i = 0; i < n; i++) {
+    const int32_t* c = &A.col[A.rowptr[i]];
+    const int64_t len = A.rowptr[i + 1] - A.rowptr[i];
+    dpos[i] = A.rowptr[i] + (std::lower_bound(c, c + len, (int32_t)i) - c);
+  }
+  // ---- format choice ----
+  std::vector<int64_t> offs = distinct_offsets(A);
+  const int64_t n_slices = (n + SLICE - 1) / SLICE;
+  std::vector<int64_t> slice_ptr(n_slices + 1, 0);
+  for (int64_t sl = 0; sl < n_slices; sl++) {
+    int64_t w = 0;
+    for (int64_t i = sl * SLICE; i < std::min(n, (sl + 1) * SLICE); i++)
+      w = std::max(w, A.rowptr[i + 1] - A.rowptr[i]);
+    slice_ptr[sl + 1] = slice_ptr[sl] + w * SLICE;
+  }
+  const int64_t sell_nnz = slice_ptr[n_slices];
+  const int64_t stride = round_up(n, 64);
+  const double vb = mixed ? 4.0 : 8.0;
+  bool use_dia = false;
+  if ((int)offs.size() <= MAX_DIAG) {
+    const double dia_bytes = (double)offs.size() * stride * vb;
+    const double sell_bytes = (double)sell_nnz * (vb + 4.0);
+    use_dia = (s->fmt_pref == EP_FMT_DIA) || (s->fmt_pref == EP_FMT_AUTO && dia_bytes < sell_bytes);
+  } else if (s->fmt_pref == EP_FMT_DIA) {
+    return fail(EP_EINVAL, "pattern has more than 32 distinct offsets; DIA not possible");
+  }
+  InstDesc& D = s->desc;
+  std::memset(&D, 0, sizeof(D));
+  D.n = n;
+  D.stride = stride;
+  D.model = s->model;
+  D.bdf = s->bdf;
+  D.prec = s->prec;
+  D.max_it = s->max_it;
+  D.max_outer = s->max_outer;
+  D.dt = s->dt;
+  D.inv_dt = 1.0 / s->dt;
+  D.rtol = s->rtol;
+  D.inner_rtol = s->inner_rtol;
+  s->mi = model_info(s->model);
+  D.threshold = s->mi.threshold;
+  s->nvars = s->mi.nvars;
+  D.nvars = s->nvars;
+  D.precond = s->precond;
+  D.block = 1;
+  default_params(s->model, s->variant, D.mp);
+  for (size_t k = 0; k < s->params.size(); k++) D.mp[k] = s->params[k];
+  hipStream_t st = s->stream;
+  DevMem& m = s->mem;
+  // ---- matrix values for each BDF order, and Jacobi diagonals ----
+  std::vector<std::vector<double>> valA(nsig, std::vector<double>(nnz));
+  for (int q = 0; q < nsig; q++) {
+    const double c = alphas[q] / s->dt;
+    for (int64_t t = 0; t < nnz; t++) valA[q][t] = c * A.valM[t] + A.valK[t];
+  }
+  auto to_dev_d = [&](const std::vector<double>& h, const double** d) -> hipError_t {
+    double* p;
+    hipError_t e = upload(m, &p, h.data(), h.size(), st);
+    *d = p;
+    return e;
+  };
+  auto to_dev_f = [&](const std::vector<double>& h, const float** d) -> hipError_t {
+    std::vector<float> f(h.begin(), h.end());
+    float* p;
+    hipError_t e = upload(m, &p, f.data(), f.size(), st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);  // f is a temporary
+    *d = p;
+    return e;
+  };
+  std::vector<std::vector<double>> hostvals;  // keep alive until sync
+  if (use_dia) {
+    D.fmt = FMT_DIA;
+    D.ndiag = (int)offs.size();
+    int64_t g = 0;
+    for (size_t d = 0; d < offs.size(); d++) {
+      D.off[d] = (int32_t)offs[d];
+      g = std::max<int64_t>(g, std::llabs(offs[d]));
+    }
+    s->guard = round_up(std::max<int64_t>(g, 1), 64);
+    auto to_dia = [&](const std::vector<double>& v) {
+      std::vector<double> out((size_t)D.ndiag * stride, 0.0);
+      parallel_for(n, [&](int64_t i) {
+        for (int64_t t = A.rowptr[i]; t < A.rowptr[i + 1]; t++) {
+          const int64_t o = (int64_t)A.col[t] - i;
+          const int64_t d = std::lower_bound(offs.begin(), offs.end(), o) - offs.begin();
+          out[(size_t)d * stride + i] = v[t];
+        }
+      });
+      return out;
+    };
+    hostvals.push_back(to_dia(A.valM));
+    EP_HIP(to_dev_d(hostvals.back(), &D.valM));
+    for (int q = 0; q < nsig; q++) {
+      hostvals.push_back(to_dia(valA[q]));
+      EP_HIP(to_dev_d(hostvals.back(), &D.valA[q]));
+      if (mixed) EP_HIP(to_dev_f(hostvals.back(), &D.valA32[q]));
+    }
+  } else {
+    D.fmt = FMT_SELL;
+    D.ndiag = 0;
+    s->guard = 0;
+    std::vector<int32_t> col(sell_nnz, 0);
+    std::vector<int64_t> pos(nnz);
+    for (int64_t sl = 0; sl < n_slices; sl++) {
+      const int64_t w = (slice_ptr[sl + 1] - slice_ptr[sl]) / SLICE;
+      for (int lane = 0; lane < SLICE; lane++) {
+        const int64_t i = sl * SLICE + lane;
+        for (int64_t k = 0; k < w; k++) {
+          const int64_t p = slice_ptr[sl] + k * SLICE + lane;
+          if (i < n && A.rowptr[i] + k < A.rowptr[i + 1]) {
+            col[p] = A.col[A.rowptr[i] + k];
+            pos[A.rowptr[i] + k] = p;
+          } else {
+            col[p] = (int32_t)std::min<int64_t>(i, n - 1);
+          }
+        }
+      }
+    }
+    auto to_sell = [&](const std::vector<double>& v) {
+      std::vector<double> out(sell_nnz, 0.0);
+      for (int64_t t = 0; t < nnz; t++) out[pos[t]] = v[t];
+      return out;
+    };
+    int32_t* dcol;
+    EP_HIP(upload(m, &dcol, col.data(), col.size(), st));
+    D.col = dcol;
+    int64_t* dsp;
+    EP_HIP(upload(m, &dsp, slice_ptr.data(), slice_ptr.size(), st));
+    D.slice_ptr = dsp;
+    hostvals.push_back(to_sell(A.valM));
+    EP_HIP(to_dev_d(hostvals.back(), &D.valM));
+    for (int q = 0; q < nsig; q++) {
+      hostvals.push_back(to_sell(valA[q]));
+      EP_HIP(to_dev_d(hostvals.back(), &D.valA[q]));
+      if (mixed) EP_HIP(to_dev_f(hostvals.back(), &D.valA32[q]));
+    }
+    EP_HIP(hipStreamSynchronize(st));  // col lives on the host stack frame
+  }
+  for (int q = 0; q < nsig; q++) {
+    std::vector<double> dinv(n);
+    for (int64_t i = 0; i < n; i++) dinv[i] = 1.0 / valA[q][dpos[i]];
+    hostvals.push_back(dinv);
+    EP_HIP(to_dev_d(hostvals.back(), &D.dinv[q]));
+    if (mixed) EP_HIP(to_dev_f(hostvals.back(), &D.dinv32[q]));
+  }
+  // ---- vectors (guarded) ----
+  const int64_t G = s->guard;
+  const int64_t nv = n + 2 * G;
+  auto vec_d = [&](double** p) -> hipError_t {
+    double* raw;
+    hipError_t e = m.alloc((void**)&raw, nv * sizeof(double));
+    if (e != hipSuccess) return e;
+    e = hipMemsetAsync(raw, 0, nv * sizeof(double), st);
+    *p = raw + G;
+    return e;
+  };
+  auto vec_f = [&](float** p) -> hipError_t {
+    float* raw;
+    hipError_t e = m.alloc((void**)&raw, nv * sizeof(float));
+    if (e != hipSuccess) return e;
+    e = hipMemsetAsync(raw, 0, nv * sizeof(float), st);
+    *p = raw + G;
+    return e;
+  };
+  for (int k = 0; k < RING; k++) EP_HIP(vec_d(&D.U[k]));
+  EP_HIP(vec_d(&D.g));
+  EP_HIP(vec_d(&D.b));
+  EP_HIP(vec_d(&D.r));
+  EP_HIP(vec_d(&D.z));
+  EP_HIP(vec_d(&D.p));
+  EP_HIP(vec_d(&D.s));
+  EP_HIP(vec_d(&D.w));
+  if (mixed) {
+    EP_HIP(vec_f(&D.r32));
+    EP_HIP(vec_f(&D.z32));
+    EP_HIP(vec_f(&D.p32));
+    EP_HIP(vec_f(&D.s32));
+    EP_HIP(vec_f(&D.w32));
+  }
+  // ---- ionic state ----
+  const int nvars = s->nvars;
+  if (mixed) {
+    const int n32 = (s->model == EP_TTP06) ? 16 : nvars;
+    const int n64 = (s->model == EP_TTP06) ? 2 : 0;
+    EP_HIP(m.alloc((void**)&D.st32, std::max<int64_t>(1, (int64_t)n32 * n) * sizeof(float)));
+    EP_HIP(m.alloc((void**)&D.st64, std::max<int64_t>(1, (int64_t)n64 * n) * sizeof(double)));
+  } else {
+    EP_HIP(m.alloc((void**)&D.st64, std::max<int64_t>(1, (int64_t)nvars * n) * sizeof(double)));
+  }
+  EP_HIP(m.alloc((void**)&D.smax, n * sizeof(double)));
+  EP_HIP(m.alloc((void**)&D.at, n * sizeof(double)));
+  EP_HIP(m.alloc((void**)&D.tcross, n * sizeof(double)));
+  // ---- stimuli, grouped by timing ----
+  {
+    std::map<std::tuple<int64_t, int64_t, int64_t>, std::vector<double>> groups;
+    const double scale = 1.0 / (s->chi * s->cm * s->mi.mv_per_unit);
+    for (const Stim& t : s->stims) {
+      const int64_t s0 = llround(t.t0 / s->dt), du = llround(t.dur / s->dt);
+      const int64_t pe = t.period > 0 ? llround(t.period / s->dt) : 0;
+      auto& prof = groups[std::make_tuple(s0, du, pe)];
+      if (prof.empty()) prof.assign(n, 0.0);
+      for (int64_t i = 0; i < n; i++) prof[i] += t.amp * scale * stim_profile(t, &s->xyz[3 * i]);
+    }
+    if ((int)groups.size() > MAX_STIM) return fail(EP_EINVAL, "more than 8 distinct stimulus timings");
+    int k = 0;
+    for (auto& kv : groups) {
+      StimGroup& sg = D.stim[k++];
+      sg.amp = 1.0;
+      sg.s0 = std::get<0>(kv.first);
+      sg.dur = std::get<1>(kv.first);
+      sg.period = std::get<2>(kv.first);
+      hostvals.push_back(kv.second);
+      double* p;
+      EP_HIP(upload(m, &p, hostvals.back().data(), n, st));
+      sg.prof = p;
+    }
+    D.n_stim = k;
+  }
+  // ---- control state, partials, block map ----
+  s->nblocks = (int)((n + WG - 1) / WG);
+  D.blk0 = 0;
+  D.nblk = s->nblocks;
+  EP_HIP(m.alloc((void**)&D.partial, (size_t)s->nblocks * 4 * sizeof(double)));
+  EP_HIP(m.alloc((void**)&s->d_st, sizeof(InstState)));
+  D.st = s->d_st;
+  EP_HIP(hipHostMalloc((void**)&s->h_st, sizeof(InstState), hipHostMallocDefault));
+  std::memset(s->h_st, 0, sizeof(InstState));
+  EP_HIP(hipMemcpyAsync(s->d_st, s->h_st, sizeof(InstState), hipMemcpyHostToDevice, st));
+  std::vector<BlockMap> bm(s->nblocks);
+  for (int b = 0; b < s->nblocks; b++) bm[b] = {0, b};
+  EP_HIP(upload(m, &s->d_bmap, bm.data(), bm.size(), st));
+  EP_HIP(m.alloc((void**)&s->d_desc, sizeof(InstDesc)));
+  EP_HIP(hipMemcpyAsync(s->d_desc, &s->desc, sizeof(InstDesc), hipMemcpyHostToDevice, st));
+  EP_HIP(hipStreamSynchronize(st));
+  hostvals.clear();
+  for (int k = 0; k < 5; k++) EP_HIP(hipEventCreate(&s->ev[k]));
+  s->finalized = true;
+  // ---- initial state ----
+  std::vector<double> init = s->init.empty() ? default_init(s->model) : s->init;
+  std::vector<double> u(n, init[0]);
+  std::vector<double> w((size_t)nvars * n);
+  for (int v = 0; v < nvars; v++)
+    for (int64_t i = 0; i < n; i++) w[(size_t)v * n + i] = init[1 + v];
+  ep_status rc = ep_sim_set_state(s, u.data(), w.data(), nullptr, 0);
+  if (rc != EP_OK) return rc;
+  s->ms_setup = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return EP_OK;
+}
+
+Launch launch_of(ep_sim* s) { return Launch{s->d_desc, s->d_bmap, s->nblocks, s->stream}; }
+
+// One time step of one sim (host sequencing; all arithmetic on the device).
+ep_status step_once(ep_sim* s) {
+  const Launch L = launch_of(s);
+  const bool mixed = s->prec == EP_MIXED;
+  if (s->timers) EP_HIP(hipEventRecord(s->ev[0], s->stream));
+  launch_ionic(s->model, mixed, L);
+  if (s->timers) EP_HIP(hipEventRecord(s->ev[1], s->stream));
+  launch_residual(mixed, true, L);
+  if (s->timers) EP_HIP(hipEventRecord(s->ev[2], s->stream));
+  if (!mixed) {
+    int chunk = std::max(1, s->it_pred);
+    for (int guard_loop = 0;; guard_loop++) {
+      for (int c = 0; c < chunk; c++) {
+        launch_cg_spmv(false, L);
+        launch_cg_update(false, L);
+      }
+      ep_status rc = pull_state(s);
+      if (rc != EP_OK) return rc;
+      if (s->h_st->conv) break;
+      if (guard_loop > s->max_it + 2) return fail(EP_EHIP, "solver control lost (no convergence flag)");
+      chunk = 2;
+    }
+    s->it_pred = std::max(1, s->h_st->it_step);
+  } else {
+    int sweeps = 0;
+    for (;;) {
+      const int before = s->h_st->it_step;
+      const int chunk = std::max(1, s->in_pred);
+      for (int c = 0; c < chunk; c++) {
+        launch_cg_spmv(true, L);
+        launch_cg_update(true, L);
+      }
+      launch_residual(true, false, L);
+      ep_status rc = pull_state(s);
+      if (rc != EP_OK) return rc;
+      sweeps++;
+      const int done = s->h_st->it_step - (sweeps == 1 ? 0 : before);
+      if (done >= chunk) s->in_pred = chunk + std::max(1, chunk / 2);
+      else if (done + 2 < chunk) s->in_pred = std::max(1, done + 1);
+      if (s->h_st->conv) break;
+      if (sweeps > s->max_outer + 2) return fail(EP_EHIP, "solver control lost (no convergence flag)");
+    }
+  }
+  if (s->timers) EP_HIP(hipEventRecord(s->ev[3], s->stream));
+  launch_activation(L);
+  if (s->timers) {
+    EP_HIP(hipEventRecord(s->ev[4], s->stream));
+    EP_HIP(hipEventSynchronize(s->ev[4]));
+    for (int k = 0; k < 4; k++) {
+      float ms = 0;
+      EP_HIP(hipEventElapsedTime(&ms, s->ev[k], s->ev[k + 1]));
+      s->ms_phase[k] += ms;
+    }
+  }
+  const int flags = s->h_st->flags;
+  if (flags & F_NAN) return EP_ENAN;
+  if (flags & (F_NOCONV | F_BREAKDOWN)) return EP_ENOCONV;
+  return EP_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+
+extern "C" {
+
+const char* ep_last_error(void) { return g_err.c_str(); }
+const char* ep_version(void) { return "ep_mi355x 0.1 (gfx950)"; }
+
+ep_status ep_sim_create(int device, void* hip_stream, ep_sim** out) {
+  if (!out) return fail(EP_EINVAL, "out is null");
+  *out = nullptr;
+  int count = 0;
+  EP_HIP(hipGetDeviceCount(&count));
+  if (device < 0 || device >= count) return fail(EP_EINVAL, "no such device");
+  EP_HIP(hipSetDevice(device));
+  ep_sim* s = new ep_sim();
+  s->device = device;
+  if (hip_stream) {
+    s->stream = (hipStream_t)hip_stream;
+  } else {
+    hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      delete s;
+      return fail(EP_EHIP, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+    }
+    s->own_stream = true;
+  }
+  *out = s;
+  return EP_OK;
+}
+
+ep_status ep_sim_upload_mesh(ep_sim* s, int elem, int64_t n_nodes, const double* xyz, int64_t n_elems,
+                             const int32_t* conn, const int32_t* material_id) {
+  if (check_sim(s)) return EP_EINVAL;
+  if (s->finalized) return fail(EP_ESTATE, "sim already finalized");
+  if (elem != EP_HEX8 && elem != EP_TET4) return fail(EP_EINVAL, "elem must be EP_HEX8 or EP_TET4");
+  if (n_nodes <= 0 || n_elems <= 0 || !xyz || !conn) return fail(EP_EINVAL, "empty mesh");
+  if (material_id) return fail(EP_EINVAL, "material ids (several subdomains) are not supported");
+  if (n_nodes >= (int64_t)INT32_MAX) return fail(EP_EINVAL, "too many nodes");
+  for (int64_t k = 0; k < n_elems * elem; k++)
+    if (conn[k] < 0 || conn[k] >= n_nodes) return fail(EP_EINVAL, "connectivity index out of range");
+  s->elem = elem;
+  s->n = n_nodes;
+  s->n_elems = n_elems;
+  s->xyz.assign(xyz, xyz + 3 * n_nodes);
+  s->conn.assign(conn, conn + elem * n_elems);
+  s->f0.clear();
+  s->s0.clear();
+  s->n0.clear();
+  return EP_OK;
+}
+
+ep_status ep_sim_upload_fibers(ep_sim* s, const double* f0, const double* s0, const double* n0) {
+  if (check_sim(s)) return EP_EINVAL;
+  if (s->finalized) return fail(EP_ESTATE, "sim already finalized");
+  if (s->n <= 0) return fail(EP_ESTATE, "upload the mesh first");
+  if (!f0 || !s0 || !n0) return fail(EP_EINVAL, "null fiber array");
+  s->f0.assign(f0, f0 + 3 * s->n);
+  s->s0.assign(s0, s0 + 3 * s->n);
+  s->n0.assign(n0, n0 + 3 * s->n);
+  return EP_OK;
+}
+
+ep_status ep_sim_set_conductivity(ep_sim* s, double sl, double st, double sn, double chi, double cm) {
+  if (check_sim(s)) return EP_EINVAL;
+  if (s->finalized) return fail(EP_ESTATE, "sim already finalized");
+  if (!(sl >= 0 && st >= 0 && sn >= 0 && chi > 0 && cm > 0)) return fail(EP_EINVAL, "bad conductivity");
+  s->sl = sl; s->st = st; s->sn = sn; s->chi = chi; s->cm = cm;
+  return EP_OK;
+}
+
+ep_status ep_sim_set_ionic_model(ep_sim* s, int model, int variant, const double* params, int n_params,
+                                 const double* init_state) {
+  if (check_sim(s)) return EP_EINVAL;
+  if (s->finalized) return fail(EP_ESTATE, "sim already finalized");
+  if (model < EP_PASSIVE || model > EP_TTP06) return fail(EP_EINVAL, "unknown ionic model");
+  if (model == EP_TTP06 && (variant < 0 || variant > 2)) return fail(EP_EINVAL, "bad TTP06 cell type");
+  if (n_params < 0 || n_params > n_model_params(model) || (n_params > 0 && !params))
+    return fail(EP_EINVAL, "bad parameter count");
+  s->model = model;
+  s->variant = variant;
+  s->params.assign(params ? params : nullptr, params ? params + n_params : nullptr);
+  if (init_state) s->init.assign(init_state, init_state + 1 + model_info(model).nvars);
+  else s->init.clear();
+  return EP_OK;
+}
+
+ep_status ep_sim_add_stimulus(ep_sim* s, int shape, const double c[3], double size, double amp, double t0,
+                              double dur, double period) {
+  if (check_sim(s)) return EP_EINVAL;
+  if (s->finalized) return fail(EP_ESTATE, "sim already finalized");
+  if (shape < EP_CUBE || shape > EP_GAUSS || !c || !(size > 0) || !(dur >= 0) || !(period >= 0))
+    return fail(EP_EINVAL, "bad stimulus");
+  s->stims.push_back(Stim{shape, {c[0], c[1], c[2]}, size, amp, t0, dur, period});
+  return EP_OK;
+}
+
+ep_status ep_sim_set_solver(ep_sim* s, double dt, int bdf, int precision, int precond, int block, double rtol,
+                            int max_it) {
+  if (check_sim(s)) return EP_EINVAL;
+  if (s->finalized) return fail(EP_ESTATE, "sim already finalized");
+  if (!(dt > 0) || bdf < 1 || bdf > 3 || (precision != EP_FP64 && precision != EP_MIXED) ||
+      precond != EP_JACOBI || !(rtol > 0) || max_it < 1)
+    return fail(EP_EINVAL, "bad solver settings");
+  (void)block;
+  s->dt = dt; s->bdf = bdf; s->prec = precision; s->precond = precond; s->rtol = rtol; s->max_it = max_it;
+  return EP_OK;
+}
+
+ep_status ep_sim_set_option(ep_sim* s, int key, double value) {
+  if (check_sim(s)) return EP_EINVAL;
+  if (key == EP_OPT_PHASE_TIMERS) {
+    s->timers = value != 0.0;
+    return EP_OK;
+  }
+  if (s->finalized) return fail(EP_ESTATE, "sim already finalized");
+  switch (key) {
+    case EP_OPT_MATRIX_FORMAT:
+      if (value != EP_FMT_AUTO && value != EP_FMT_SELL && value != EP_FMT_DIA) return fail(EP_EINVAL, "format");
+      s->fmt_pref = (int)value;
+      return EP_OK;
+    case EP_OPT_INNER_RTOL:
+      if (!(value > 0 && value < 1)) return fail(EP_EINVAL, "inner rtol");
+      s->inner_rtol = value;
+      return EP_OK;
+    case EP_OPT_MAX_OUTER:
+      if (!(value >= 1)) return fail(EP_EINVAL, "max outer");
+      s->max_outer = (int)value;
+      return EP_OK;
+    default: return fail(EP_EINVAL, "unknown option");
+  }
+}
+
+ep_status ep_sim_finalize(ep_sim* s) {
+  if (check_sim(s)) return EP_EINVAL;
+  if (s->in_pool) return fail(EP_ESTATE, "sim belongs to a pool");
+  ep_status rc = finalize_impl(s);
+  if (rc != EP_OK && !s->finalized) s->mem.release();
+  return rc;
+}
+
+ep_status ep_sim_device_bytes_estimate(ep_sim* s, size_t* bytes) {
+  if (check_sim(s) || !bytes) return fail(EP_EINVAL, "null argument");
+  *bytes = estimate_bytes(s);
+  return EP_OK;
+}
+
+ep_status ep_sim_step(ep_sim* s, int n_steps) {
+  if (check_sim(s)) return EP_EINVAL;
+  if (!s->finalized) return fail(EP_ESTATE, "finalize first");
+  if (s->in_pool) return fail(EP_ESTATE, "sim is stepped by its pool");
+  if (n_steps < 0) return fail(EP_EINVAL, "negative step count");
+  EP_HIP(hipSetDevice(s->device));
+  ep_status worst = EP_OK;
+  for (int k = 0; k < n_steps; k++) {
+    ep_status rc = step_once(s);
+    if (rc == EP_ENAN || rc == EP_EHIP) {
+      if (rc == EP_ENAN) g_err = "NaN in the solution";
+      return rc;
+    }
+    if (rc == EP_ENOCONV) {
+      worst = rc;
+      g_err = "linear solve did not converge within max_it";
+    }
+  }
+  return worst;
+}
+
+ep_status ep_sim_sync(ep_sim* s) {
+  if (check_sim(s)) return EP_EINVAL;
+  EP_HIP(hipStreamSynchronize(s->stream));
+  return EP_OK;
+}
+
+ep_status ep_sim_set_state(ep_sim* s, const double* u, const double* w, const double* u_prev,
+                           int64_t step_index) {
+  if (check_sim(s)) return EP_EINVAL;
+  if (!s->finalized) return fail(EP_ESTATE, "finalize first");
+  if (!u || (s->nvars > 0 && !w) || step_index < 0) return fail(EP_EINVAL, "null state");
+  const int64_t n = s->n;
+  InstDesc& D = s->desc;
+  hipStream_t st = s->stream;
+  EP_HIP(hipSetDevice(s->device));
+  EP_HIP(hipStreamSynchronize(st));
+  EP_HIP(hipMemcpyAsync(D.U[step_index & 3], u, n * sizeof(double), hipMemcpyHostToDevice, st));
+  for (int k = 1; k < 3; k++) {
+    const double* src = (u_prev && k < s->bdf) ? u_prev + (size_t)(k - 1) * n : u;
+    EP_HIP(hipMemcpyAsync(D.U[(step_index - k) & 3], src, n * sizeof(double), hipMemcpyHostToDevice, st));
+  }
+  const int nv = s->nvars;
+  if (nv > 0) {
+    if (s->prec == EP_MIXED) {
+      std::vector<float> s32;
+      std::vector<double> s64;
+      if (s->model == EP_TTP06) {
+        s32.resize((size_t)16 * n);
+        s64.resize((size_t)2 * n);
+        for (int v = 0; v < 18; v++) {
+          for (int64_t i = 0; i < n; i++) {
+            const double x = w[(size_t)v * n + i];
+            if (v < 15) s32[(size_t)v * n + i] = (float)x;
+            else if (v == 15) s64[i] = x;
+            else if (v == 16) s64[n + i] = x;
+            else s32[(size_t)15 * n + i] = (float)x;
+          }
+        }
+        EP_HIP(hipMemcpyAsync(D.st64, s64.data(), s64.size() * 8, hipMemcpyHostToDevice, st));
+      } else {
+        s32.assign(w, w + (size_t)nv * n);
+      }
+      EP_HIP(hipMemcpyAsync(D.st32, s32.data(), s32.size() * 4, hipMemcpyHostToDevice, st));
+      EP_HIP(hipStreamSynchronize(st));
+    } else {
+      EP_HIP(hipMemcpyAsync(D.st64, w, (size_t)nv * n * 8, hipMemcpyHostToDevice, st));
+    }
+  }
+  launch_fill(D.smax, n, -std::numeric_limits<double>::infinity(), st);
+  launch_fill(D.at, n, std::numeric_limits<double>::quiet_NaN(), st);
+  launch_fill(D.tcross, n, std::numeric_limits<double>::quiet_NaN(), st);
+  EP_HIP(hipGetLastError());
+  std::memset(s->h_st, 0, sizeof(InstState));
+  s->h_st->step = step_index;
+  EP_HIP(hipMemcpyAsync(s->d_st, s->h_st, sizeof(InstState), hipMemcpyHostToDevice, st));
+  EP_HIP(hipStreamSynchronize(st));
+  return EP_OK;
+}
+
+ep_status ep_sim_get_state(ep_sim* s, double* u, double* w, double* u_prev) {
+  if (check_sim(s)) return EP_EINVAL;
+  if (!s->finalized) return fail(EP_ESTATE, "finalize first");
+  ep_status rc = pull_state(s);
+  if (rc) return rc;
+  const int64_t n = s->n;
+  const int64_t step = s->h_st->step;
+  InstDesc& D = s->desc;
+  hipStream_t st = s->stream;
+  if (u) EP_HIP(hipMemcpyAsync(u, D.U[step & 3], n * 8, hipMemcpyDeviceToHost, st));
+  if (u_prev)
+    for (int k = 1; k < s->bdf; k++)
+      EP_HIP(hipMemcpyAsync(u_prev + (size_t)(k - 1) * n, D.U[(step - k) & 3], n * 8, hipMemcpyDeviceToHost, st));
+  const int nv = s->nvars;
+  if (w && nv > 0) {
+    if (s->prec == EP_MIXED) {
+      const int n32 = (s->model == EP_TTP06) ? 16 : nv;
+      std::vector<float> s32((size_t)n32 * n);
+      std::vector<double> s64(s->model == EP_TTP06 ? (size_t)2 * n : 0);
+      EP_HIP(hipMemcpyAsync(s32.data(), D.st32, s32.size() * 4, hipMemcpyDeviceToHost, st));
+      if (!s64.empty()) EP_HIP(hipMemcpyAsync(s64.data(), D.st64, s64.size() * 8, hipMemcpyDeviceToHost, st));
+      EP_HIP(hipStreamSynchronize(st));
+      if (s->model == EP_TTP06) {
+        for (int v = 0; v < 18; v++)
+          for (int64_t i = 0; i < n; i++) {
+            double x;
+            if (v < 15) x = s32[(size_t)v * n + i];
+            else if (v == 15) x = s64[i];
+            else if (v == 16) x = s64[n + i];
+            else x = s32[(size_t)15 * n + i];
+            w[(size_t)v * n + i] = x;
+          }
+      } else {
+        for (size_t k = 0; k < s32.size(); k++) w[k] = s32[k];
+      }
+    } else {
+      EP_HIP(hipMemcpyAsync(w, D.st64, (size_t)nv * n * 8, hipMemcpyDeviceToHost, st));
+    }
+  }
+  EP_HIP(hipStreamSynchronize(st));
+  return EP_OK;
+}
+
+int ep_sim_n_vars(const ep_sim* s) { return s ? model_info(s->model).nvars : -1; }
+
+ep_status ep_sim_get_potential(ep_sim* s, double* out) {
+  if (check_sim(s) || !out) return fail(EP_EINVAL, "null argument");
+  ep_status rc = ep_sim_get_state(s, out, nullptr, nullptr);
+  if (rc) return rc;
+  const double a = s->mi.mv_per_unit, b = s->mi.mv_offset;
+  if (a != 1.0 || b != 0.0)
+    for (int64_t i = 0; i < s->n; i++) out[i] = a * out[i] + b;
+  return EP_OK;
+}
+
+ep_status ep_sim_get_potential_device(ep_sim* s, void* dst, int dtype) {
+  if (check_sim(s) || !dst) return fail(EP_EINVAL, "null argument");
+  if (!s->finalized) return fail(EP_ESTATE, "finalize first");
+  if (dtype != EP_DTYPE_F64 && dtype != EP_DTYPE_F32) return fail(EP_EINVAL, "dtype");
+  ep_status rc = pull_state(s);
+  if (rc) return rc;
+  const double* src = s->desc.U[s->h_st->step & 3];
+  launch_to_mv(dst, src, s->n, s->mi.mv_per_unit, s->mi.mv_offset, dtype == EP_DTYPE_F32, s->stream);
+  EP_HIP(hipGetLastError());
+  EP_HIP(hipStreamSynchronize(s->stream));
+  return EP_OK;
+}
+
+static ep_status get_times(ep_sim* s, double* out, bool maxslope) {
+  if (check_sim(s) || !out) return fail(EP_EINVAL, "null argument");
+  if (!s->finalized) return fail(EP_ESTATE, "finalize first");
+  const int64_t n = s->n;
+  std::vector<double> tc(n);
+  EP_HIP(hipStreamSynchronize(s->stream));
+  EP_HIP(hipMemcpyAsync(tc.data(), s->desc.tcross, n * 8, hipMemcpyDeviceToHost, s->stream));
+  if (maxslope) EP_HIP(hipMemcpyAsync(out, s->desc.at, n * 8, hipMemcpyDeviceToHost, s->stream));
+  EP_HIP(hipStreamSynchronize(s->stream));
+  for (int64_t i = 0; i < n; i++) {
+    if (!maxslope) out[i] = tc[i];
+    else if (std::isnan(tc[i])) out[i] = std::numeric_limits<double>::quiet_NaN();
+  }
+  return EP_OK;
+}
+
+ep_status ep_sim_get_activation_times(ep_sim* s, double* out) { return get_times(s, out, true); }
+ep_status ep_sim_get_threshold_times(ep_sim* s, double* out) { return get_times(s, out, false); }
+
+ep_status ep_sim_get_stats(ep_sim* s, ep_stats* o) {
+  if (check_sim(s) || !o) return fail(EP_EINVAL, "null argument");
+  std::memset(o, 0, sizeof(*o));
+  o->n_nodes = s->n;
+  if (!s->finalized) return EP_OK;
+  ep_status rc = pull_state(s);
+  if (rc) return rc;
+  const InstState& S = *s->h_st;
+  o->nnz = s->nnz;
+  o->steps = S.step;
+  o->cg_iters_total = S.it_total;
+  o->cg_iters_last = S.it_last;
+  o->cg_iters_max = S.it_max;
+  o->ir_sweeps_total = S.outer_total;
+  o->rel_residual_last = S.bb > 0 ? std::sqrt(S.rr_outer / S.bb) : 0.0;
+  if (s->prec != EP_MIXED && S.bb > 0) o->rel_residual_last = std::sqrt(S.rr / S.bb);
+  o->matrix_format = s->desc.fmt == FMT_DIA ? EP_FMT_DIA : EP_FMT_SELL;
+  o->n_diag = s->desc.ndiag;
+  o->device_bytes = (int64_t)s->mem.bytes;
+  o->ms_ionic = s->ms_phase[0];
+  o->ms_rhs = s->ms_phase[1];
+  o->ms_solve = s->ms_phase[2];
+  o->ms_activation = s->ms_phase[3];
+  o->ms_setup = s->ms_setup;
+  return EP_OK;
+}
+
+void ep_sim_destroy(ep_sim* s) {
+  if (!s) return;
+  (void)hipSetDevice(s->device);
+  if (s->stream) (void)hipStreamSynchronize(s->stream);
+  for (auto& e : s->ev)
+    if (e) (void)hipEventDestroy(e);
+  s->mem.release();
+  if (s->h_st) (void)hipHostFree(s->h_st);
+  if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+  delete s;
+}
+
+ep_status ep_assemble_csr(int elem, int64_t n_nodes, const double* xyz, int64_t n_elems, const int32_t* conn,
+                          const double* f0, const double* s0, const double* n0, double sl, double st, double sn,
+                          double chi, double cm, int64_t* nnz_out, int64_t* rowptr, int32_t* col, double* valM,
+                          double* valK) {
+  if (!xyz || !conn || !nnz_out) return fail(EP_EINVAL, "null argument");
+  Csr A;
+  std::vector<char> err;
+  if (!assemble_csr(elem, n_nodes, xyz, n_elems, conn, f0, s0, n0, sl, st, sn, chi, cm, A, err))
+    return fail(EP_EINVAL, std::string("assembly: ") + (err.empty() ? "failed" : err.data()));
+  *nnz_out = A.nnz();
+  if (!rowptr) return EP_OK;
+  if (!col || !valM || !valK) return fail(EP_EINVAL, "null output array");
+  std::copy(A.rowptr.begin(), A.rowptr.end(), rowptr);
+  std::copy(A.col.begin(), A.col.end(), col);
+  std::copy(A.valM.begin(), A.valM.end(), valM);
+  std::copy(A.valK.begin(), A.valK.end(), valK);
+  return EP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,243 @@
+// Finite-element assembly of the monodomain operator on the host (one-time
+// setup; the per-step work runs in the HIP kernels).
+//
+// Space discretization as in the paper's numerical section: M_jk is the
+// integral of phi_k phi_j, K_jk the integral of D grad phi_k . grad phi_j,
+// with the fewest Gauss points that integrate M exactly.  The diffusion
+// tensor is the paper's D = sigma_l f f^T + sigma_t s s^T + sigma_n n n^T
+// divided by chi C_m (the rescaling of the dimensional monodomain equation),
+// given per node and interpolated with the FE basis.
+#include "assembly.h"
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+namespace ep {
+
+namespace {
+
+void set_err(std::vector<char>& err, const char* msg) {
+  err.assign(msg, msg + std::strlen(msg) + 1);
+}
+
+// Nodal diffusion tensor (row-major 3x3) in mm^2/ms.
+inline void nodal_tensor(const double* f, const double* s, const double* nn, double sl, double st,
+                         double sn, double scale, double D[9]) {
+  for (int a = 0; a < 3; a++)
+    for (int b = 0; b < 3; b++)
+      D[3 * a + b] = scale * (sl * f[a] * f[b] + st * s[a] * s[b] + sn * nn[a] * nn[b]);
+}
+
+// Trilinear hexahedron, local corner k = a + 2b + 4c at reference (2a-1, 2b-1, 2c-1).
+// Element matrices by 2x2x2 Gauss-Legendre quadrature.
+bool hex_element(const double X[8][3], const double Dn[8][9], double Me[64], double Ke[64]) {
+  static const double g = 0.57735026918962576451;  // 1/sqrt(3)
+  std::memset(Me, 0, 64 * sizeof(double));
+  std::memset(Ke, 0, 64 * sizeof(double));
+  for (int qz = 0; qz < 2; qz++)
+    for (int qy = 0; qy < 2; qy++)
+      for (int qx = 0; qx < 2; qx++) {
+        const double xi[3] = {qx ? g : -g, qy ? g : -g, qz ? g : -g};
+        double N[8], dN[8][3];
+        for (int k = 0; k < 8; k++) {
+          const double sg[3] = {(k & 1) ? 1.0 : -1.0, (k & 2) ? 1.0 : -1.0, (k & 4) ? 1.0 : -1.0};
+          const double f0 = 1.0 + sg[0] * xi[0], f1 = 1.0 + sg[1] * xi[1], f2 = 1.0 + sg[2] * xi[2];
+          N[k] = 0.125 * f0 * f1 * f2;
+          dN[k][0] = 0.125 * sg[0] * f1 * f2;
+          dN[k][1] = 0.125 * sg[1] * f0 * f2;
+          dN[k][2] = 0.125 * sg[2] * f0 * f1;
+        }
+        // Jacobian J[r][c] = d x_c / d xi_r
+        double J[3][3] = {{0}};
+        for (int k = 0; k < 8; k++)
+          for (int r = 0; r < 3; r++)
+            for (int c = 0; c < 3; c++) J[r][c] += dN[k][r] * X[k][c];
+        const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                           J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                           J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+        if (!(det > 0.0)) return false;
+        double Ji[3][3];
+        Ji[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
+        Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+        Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+        Ji[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;
+        Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+        Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+        Ji[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / det;
+        Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+        Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+        // physical gradient grad_x phi_k = J^{-1} grad_xi phi_k
+        double G[8][3];
+        for (int k = 0; k < 8; k++)
+          for (int r = 0; r < 3; r++)
+            G[k][r] = Ji[r][0] * dN[k][0] + Ji[r][1] * dN[k][1] + Ji[r][2] * dN[k][2];
+        double Dq[9] = {0};
+        for (int k = 0; k < 8; k++)
+          for (int e = 0; e < 9; e++) Dq[e] += N[k] * Dn[k][e];
+        double DG[8][3];
+        for (int k = 0; k < 8; k++)
+          for (int r = 0; r < 3; r++)
+            DG[k][r] = Dq[3 * r] * G[k][0] + Dq[3 * r + 1] * G[k][1] + Dq[3 * r + 2] * G[k][2];
+        for (int a = 0; a < 8; a++)
+          for (int b = 0; b < 8; b++) {
+            Me[8 * a + b] += det * N[a] * N[b];
+            Ke[8 * a + b] += det * (G[a][0] * DG[b][0] + G[a][1] * DG[b][1] + G[a][2] * DG[b][2]);
+          }
+      }
+  return true;
+}
+
+// Linear tetrahedron.  Gradients of the barycentric coordinates are constant;
+// with D interpolated linearly, the degree-2 rule reduces exactly to
+// K = V G^T mean(D) G, and M = V (1 + delta_ab)/20.
+bool tet_element(const double X[4][3], const double Dn[4][9], double Me[16], double Ke[16]) {
+  double E[3][3];
+  for (int r = 0; r < 3; r++)
+    for (int c = 0; c < 3; c++) E[r][c] = X[r + 1][c] - X[0][c];
+  const double det = E[0][0] * (E[1][1] * E[2][2] - E[1][2] * E[2][1]) -
+                     E[0][1] * (E[1][0] * E[2][2] - E[1][2] * E[2][0]) +
+                     E[0][2] * (E[1][0] * E[2][1] - E[1][1] * E[2][0]);
+  if (det == 0.0 || !std::isfinite(det)) return false;
+  const double vol = std::fabs(det) / 6.0;
+  // rows of E^{-T} ... gradient of L_{r+1} is column r of E^{-1}
+  double Ei[3][3];
+  Ei[0][0] = (E[1][1] * E[2][2] - E[1][2] * E[2][1]) / det;
+  Ei[0][1] = (E[0][2] * E[2][1] - E[0][1] * E[2][2]) / det;
+  Ei[0][2] = (E[0][1] * E[1][2] - E[0][2] * E[1][1]) / det;
+  Ei[1][0] = (E[1][2] * E[2][0] - E[1][0] * E[2][2]) / det;
+  Ei[1][1] = (E[0][0] * E[2][2] - E[0][2] * E[2][0]) / det;
+  Ei[1][2] = (E[0][2] * E[1][0] - E[0][0] * E[1][2]) / det;
+  Ei[2][0] = (E[1][0] * E[2][1] - E[1][1] * E[2][0]) / det;
+  Ei[2][1] = (E[0][1] * E[2][0] - E[0][0] * E[2][1]) / det;
+  Ei[2][2] = (E[0][0] * E[1][1] - E[0][1] * E[1][0]) / det;
+  double G[4][3];
+  for (int k = 0; k < 3; k++)
+    for (int c = 0; c < 3; c++) G[k + 1][c] = Ei[c][k];
+  for (int c = 0; c < 3; c++) G[0][c] = -(G[1][c] + G[2][c] + G[3][c]);
+  double Dm[9];
+  for (int e = 0; e < 9; e++) Dm[e] = 0.25 * (Dn[0][e] + Dn[1][e] + Dn[2][e] + Dn[3][e]);
+  for (int a = 0; a < 4; a++)
+    for (int b = 0; b < 4; b++) {
+      Me[4 * a + b] = vol / 20.0 * (a == b ? 2.0 : 1.0);
+      double acc = 0.0;
+      for (int r = 0; r < 3; r++)
+        for (int c = 0; c < 3; c++) acc += G[a][r] * Dm[3 * r + c] * G[b][c];
+      Ke[4 * a + b] = vol * acc;
+    }
+  return true;
+}
+
+}  // namespace
+
+bool assemble_csr(int elem, int64_t n_nodes, const double* xyz, int64_t n_elems,
+                  const int32_t* conn, const double* f0, const double* s0, const double* n0,
+                  double sigma_l, double sigma_t, double sigma_n, double chi, double cm, Csr& A,
+                  std::vector<char>& err) {
+  if (elem != 8 && elem != 4) { set_err(err, "element type must be 8 (hex) or 4 (tet)"); return false; }
+  if (n_nodes <= 0 || n_elems <= 0) { set_err(err, "empty mesh"); return false; }
+  if (n_nodes >= (int64_t)INT32_MAX) { set_err(err, "too many nodes for int32 indices"); return false; }
+  if (!(chi > 0) || !(cm > 0)) { set_err(err, "chi and C_m must be positive"); return false; }
+  const int npe = elem;
+  for (int64_t e = 0; e < n_elems * npe; e++)
+    if (conn[e] < 0 || conn[e] >= n_nodes) { set_err(err, "connectivity index out of range"); return false; }
+  const double scale = 1.0 / (chi * cm);
+
+  // node -> element incidence
+  std::vector<int64_t> ne_ptr(n_nodes + 1, 0);
+  for (int64_t e = 0; e < n_elems * npe; e++) ne_ptr[conn[e] + 1]++;
+  for (int64_t i = 0; i < n_nodes; i++) ne_ptr[i + 1] += ne_ptr[i];
+  std::vector<int64_t> ne_idx(ne_ptr[n_nodes]);
+  {
+    std::vector<int64_t> fill(ne_ptr.begin(), ne_ptr.end() - 1);
+    for (int64_t e = 0; e < n_elems; e++)
+      for (int k = 0; k < npe; k++) ne_idx[fill[conn[e * npe + k]]++] = e * npe + k;  // element*npe + local
+  }
+
+  // element matrices
+  std::vector<double> Me((size_t)n_elems * npe * npe), Ke((size_t)n_elems * npe * npe);
+  std::vector<char> bad(1, 0);
+  static const double ex[3] = {1, 0, 0}, ey[3] = {0, 1, 0}, ez[3] = {0, 0, 1};
+  parallel_for(n_elems, [&](int64_t e) {
+    double X[8][3], Dn[8][9];
+    for (int k = 0; k < npe; k++) {
+      const int64_t v = conn[e * npe + k];
+      for (int c = 0; c < 3; c++) X[k][c] = xyz[3 * v + c];
+      const double* f = f0 ? f0 + 3 * v : ex;
+      const double* s = s0 ? s0 + 3 * v : ey;
+      const double* nn = n0 ? n0 + 3 * v : ez;
+      nodal_tensor(f, s, nn, sigma_l, sigma_t, sigma_n, scale, Dn[k]);
+    }
+    bool ok = (npe == 8) ? hex_element(X, Dn, &Me[e * 64], &Ke[e * 64])
+                         : tet_element(X, Dn, &Me[e * 16], &Ke[e * 16]);
+    if (!ok) bad[0] = 1;
+  });
+  if (bad[0]) { set_err(err, "degenerate or inverted element"); return false; }
+
+  // sparsity pattern: row i = union of the nodes of its elements
+  A.n = n_nodes;
+  A.rowptr.assign(n_nodes + 1, 0);
+  std::vector<int32_t> rowlen(n_nodes);
+  auto gather_row = [&](int64_t i, std::vector<int32_t>& buf) {
+    buf.clear();
+    for (int64_t t = ne_ptr[i]; t < ne_ptr[i + 1]; t++) {
+      const int64_t e = ne_idx[t] / npe;
+      for (int k = 0; k < npe; k++) buf.push_back(conn[e * npe + k]);
+    }
+    std::sort(buf.begin(), buf.end());
+    buf.erase(std::unique(buf.begin(), buf.end()), buf.end());
+  };
+  parallel_for(n_nodes, [&](int64_t i) {
+    thread_local std::vector<int32_t> buf;
+    gather_row(i, buf);
+    rowlen[i] = (int32_t)buf.size();
+  });
+  for (int64_t i = 0; i < n_nodes; i++) A.rowptr[i + 1] = A.rowptr[i] + rowlen[i];
+  const int64_t nnz = A.rowptr[n_nodes];
+  A.col.assign(nnz, 0);
+  A.valM.assign(nnz, 0.0);
+  A.valK.assign(nnz, 0.0);
+  parallel_for(n_nodes, [&](int64_t i) {
+    thread_local std::vector<int32_t> buf;
+    gather_row(i, buf);
+    const int len = (int)buf.size();
+    int32_t* c = &A.col[A.rowptr[i]];
+    std::copy(buf.begin(), buf.end(), c);
+    double* m = &A.valM[A.rowptr[i]];
+    double* kk = &A.valK[A.rowptr[i]];
+    // row i gathers the element rows of its local index
+    for (int64_t t = ne_ptr[i]; t < ne_ptr[i + 1]; t++) {
+      const int64_t e = ne_idx[t] / npe;
+      const int a = (int)(ne_idx[t] % npe);
+      for (int b = 0; b < npe; b++) {
+        const int32_t j = conn[e * npe + b];
+        const int pos = (int)(std::lower_bound(c, c + len, j) - c);
+        m[pos] += Me[(e * npe + a) * npe + b];
+        kk[pos] += Ke[(e * npe + a) * npe + b];
+      }
+    }
+  });
+  return true;
+}
+
+std::vector<int64_t> distinct_offsets(const Csr& A) {
+  std::vector<int64_t> offs;
+  std::vector<char> seen;
+  // offsets are bounded by n in magnitude; collect through a sorted merge
+  for (int64_t i = 0; i < A.n; i++) {
+    for (int64_t t = A.rowptr[i]; t < A.rowptr[i + 1]; t++) {
+      const int64_t d = (int64_t)A.col[t] - i;
+      offs.push_back(d);
+    }
+    if (offs.size() > 4096) {
+      std::sort(offs.begin(), offs.end());
+      offs.erase(std::unique(offs.begin(), offs.end()), offs.end());
+      if (offs.size() > 64) return offs;  // far too many for a diagonal format
+    }
+  }
+  std::sort(offs.begin(), offs.end());
+  offs.erase(std::unique(offs.begin(), offs.end()), offs.end());
+  return offs;
+}
+
+}  // namespace ep

@@ -1,0 +1,62 @@
+// Host-side one-time setup of the monodomain operator: finite-element mass
+// and stiffness assembly, the sparsity pattern, and the device matrix formats.
+#pragma once
+#include <stdint.h>
+
+#include <vector>
+
+namespace ep {
+
+struct Csr {
+  int64_t n = 0;
+  std::vector<int64_t> rowptr;   // n + 1
+  std::vector<int32_t> col;      // nnz, sorted within each row
+  std::vector<double> valM, valK;
+  int64_t nnz() const { return (int64_t)col.size(); }
+};
+
+// Assemble M_jk = int phi_k phi_j and K_jk = int D grad phi_k . grad phi_j with
+// D = (sigma_l f f^T + sigma_t s s^T + sigma_n n n^T)/(chi C_m) given at the
+// nodes and interpolated with the FE basis.  elem = 8 (trilinear hexahedra,
+// 2x2x2 Gauss points) or 4 (linear tetrahedra, closed form).
+// fibers may be null (then f = e_x, s = e_y, n = e_z everywhere).
+// Returns false and fills `err` on invalid input (bad index, inverted element).
+bool assemble_csr(int elem, int64_t n_nodes, const double* xyz, int64_t n_elems,
+                  const int32_t* conn, const double* f0, const double* s0, const double* n0,
+                  double sigma_l, double sigma_t, double sigma_n, double chi, double cm,
+                  Csr& out, std::vector<char>& err);
+
+// Distinct column offsets j - i over the pattern, ascending.
+std::vector<int64_t> distinct_offsets(const Csr& A);
+
+// Parallel loop helper over [0, n).
+template <typename F>
+void parallel_for(int64_t n, F&& f);
+
+}  // namespace ep
+
+#include <algorithm>
+#include <thread>
+
+namespace ep {
+template <typename F>
+void parallel_for(int64_t n, F&& f) {
+  unsigned hw = std::thread::hardware_concurrency();
+  int64_t nt = std::max<int64_t>(1, std::min<int64_t>(hw ? hw : 4, 32));
+  if (n < 4096) nt = 1;
+  if (nt == 1) {
+    for (int64_t i = 0; i < n; i++) f(i);
+    return;
+  }
+  std::vector<std::thread> th;
+  const int64_t chunk = (n + nt - 1) / nt;
+  for (int64_t t = 0; t < nt; t++) {
+    const int64_t a = t * chunk, b = std::min(n, a + chunk);
+    if (a >= b) break;
+    th.emplace_back([a, b, &f]() {
+      for (int64_t i = a; i < b; i++) f(i);
+    });
+  }
+  for (auto& x : th) x.join();
+}
+}  // namespace ep

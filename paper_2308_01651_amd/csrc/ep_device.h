@@ -1,0 +1,95 @@
+// Device-side data structures shared by the host runtime and the HIP kernels.
+//
+// Every kernel of the time step works on a table of simulation instances
+// (InstDesc) and a block map that assigns each workgroup of the launch to one
+// instance and one tile of its nodes.  A single simulation is a table of one;
+// a batch of uneven simulations is a longer table and the same kernels.
+// All per-step control (BDF start-up order, history ring slot, stimulus
+// activity, CG scalars, convergence) lives in device memory (InstState), so a
+// step needs no per-step kernel arguments from the host.
+#pragma once
+#include <stdint.h>
+
+namespace ep {
+
+constexpr int WG = 256;        // threads per workgroup of node-parallel kernels
+constexpr int SLICE = 64;      // SELL slice height = one wavefront
+constexpr int MAX_DIAG = 32;   // largest diagonal count stored in DIA form
+constexpr int MAX_STIM = 8;    // stimulus groups per instance
+constexpr int NPARAM = 32;     // model parameter slots
+constexpr int RING = 4;        // potential history ring (u_{n+1}, u_n, u_{n-1}, u_{n-2})
+
+enum Fmt : int32_t { FMT_SELL = 1, FMT_DIA = 2 };
+enum Model : int32_t { M_PASSIVE = 0, M_AP = 1, M_BO = 2, M_TTP06 = 3 };
+enum Prec : int32_t { P_FP64 = 0, P_MIXED = 1 };
+enum Flag : int32_t { F_NAN = 1, F_NOCONV = 2, F_BREAKDOWN = 4 };
+
+// One group of stimuli that share their timing: I_app(i) = amp * prof[i]
+// while the step index k = n+1 satisfies (k - s0) mod period in [1, dur]
+// (period 0: single pulse, k - s0 in [1, dur]).
+struct StimGroup {
+  const double* prof;
+  double amp;
+  int64_t s0, dur, period;
+};
+
+// Mutable per-instance state, written only by kernels (and by the host when
+// the instance is (re)initialised).
+struct InstState {
+  int64_t step;        // completed steps n
+  int32_t it;          // CG iteration index in the current (inner) solve
+  int32_t conv;        // 1: the step's solve is done
+  int32_t conv_in;     // 1: the inner FP32 solve is done (mixed precision)
+  int32_t flags;       // Flag bits, sticky until cleared by the host
+  int32_t outer;       // refinement sweeps done in this step
+  int32_t sig;         // BDF order used by the current step
+  int64_t it_total;    // CG iterations over all steps
+  int64_t outer_total;
+  int32_t it_step;     // CG iterations in the current step (all sweeps)
+  int32_t it_last;     // CG iterations of the last finished step
+  int32_t it_max;      // largest per-step CG count so far
+  int32_t pad_;
+  double gamma, gamma_prev, delta, alpha, alpha_prev, beta;
+  double rr, bb, tol2, rr_in0, rr_outer;
+  unsigned int counter[4];   // last-block reduction tickets, one per kernel kind
+};
+
+struct InstDesc {
+  int64_t n;               // nodes
+  int64_t stride;          // DIA value stride (n rounded up to 64)
+  int32_t blk0, nblk;      // this instance's workgroups in node-parallel launches
+  int32_t model, bdf, prec, fmt;
+  int32_t ndiag, max_it, max_outer, n_stim;
+  int32_t nvars, precond, block, pad_;
+  double dt, inv_dt, rtol, inner_rtol, threshold;
+  double mp[NPARAM];       // ionic model parameters
+  int32_t off[MAX_DIAG];   // DIA column offsets
+  // matrix, one shared pattern; values of A_sigma = (alpha_sigma/dt) M + K
+  const int32_t* col;      // SELL column indices
+  const int64_t* slice_ptr;// SELL slice offsets (elements), n_slices + 1
+  const double* valA[3];
+  const double* valM;
+  const float* valA32[3];
+  const double* dinv[3];   // Jacobi: 1/diag(A_sigma); block-Jacobi: inverse blocks
+  const float* dinv32[3];
+  // FP64 vectors (padded by `guard` zero entries on both sides)
+  double* U[RING];
+  double *g, *b, *r, *z, *p, *s, *w;
+  // FP32 inner-solve vectors (mixed precision)
+  float *r32, *z32, *p32, *s32, *w32;
+  // ionic state, structure of arrays [var][n]
+  double* st64;            // FP64 state (all variables in FP64 mode; nai, ki in mixed)
+  float* st32;             // FP32 state (mixed mode)
+  // activation tracking
+  double *smax, *at, *tcross;
+  StimGroup stim[MAX_STIM];
+  InstState* st;
+  double* partial;         // [nblk][4] per-workgroup partial sums
+};
+
+struct BlockMap {
+  int32_t inst;
+  int32_t lblk;            // workgroup index inside the instance
+};
+
+}  // namespace ep

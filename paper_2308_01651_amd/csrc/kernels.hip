@@ -1,0 +1,548 @@
+// HIP kernels (gfx950) of one monodomain time step.
+//
+// Step pipeline per instance (paper: IMEX staggering of the numerical section;
+// the time-discrete ionic model, then the linear monodomain system):
+//   k_ionic      BDF history combination, Rush-Larsen / explicit ionic step at
+//                u_EXT, I_ion(u_EXT, w_{n+1}), stimulus, nodal RHS vector
+//                g = u_BDF/dt + I_app - I_ion, initial guess x0 = u_EXT
+//   k_residual   b = M g (ionic current interpolation: the load is the mass
+//                matrix applied to nodal values) fused with r0 = b - A x0 and
+//                the preconditioner; FP64.  Re-used, without M g, as the FP64
+//                residual of each mixed-precision refinement sweep.
+//   k_cg_spmv    w = A z and <w, z>       (Chronopoulos-Gear PCG: one SpMV and
+//   k_cg_update  p, s, x, r, z updates    one fused vector sweep per iteration)
+//   k_activation running argmax of (u_{n+1} - u_n)/dt, threshold crossing
+//
+// Memory layout: structure-of-arrays, one thread per node, 256-thread
+// workgroups (4 wavefronts of 64).  Matrix formats: DIA (column offsets shared
+// by all rows, no index traffic; values [diag][stride]) when the pattern has
+// few distinct offsets, else SELL with 64-row slices (one wavefront per slice,
+// column-major inside the slice).  Vectors that SpMV gathers from carry zero
+// guard cells so DIA rows near the ends stay in bounds.
+//
+// Reductions are deterministic: each workgroup writes its partial sum, the
+// last workgroup to finish (ticket counter) adds the partials in a fixed order
+// and computes the CG scalars on the device.  A batch of instances reduces per
+// instance, so each instance's result does not depend on the batch.
+#include <hip/hip_runtime.h>
+
+#include "ep_device.h"
+#include "ionic_models.h"
+#include "kernels.h"
+
+namespace ep {
+
+// ---------------------------------------------------------------------------
+// reductions
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Every thread of the workgroup must call this (no early return before it).
+// Returns true in the last workgroup of the instance; tot[] is valid in its
+// first wavefront.
+template <int NV>
+__device__ __forceinline__ bool reduce_ticket(double (&v)[NV], double* __restrict__ partial, int lblk,
+                                              int nblk, unsigned int* counter, double (&tot)[NV]) {
+  __shared__ double sh[WG / 64][4];
+  __shared__ int s_last;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; k++) v[k] = wave_sum(v[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; k++) sh[wv][k] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; k++) {
+      const double a = (sh[0][k] + sh[1][k]) + (sh[2][k] + sh[3][k]);
+      __hip_atomic_store(&partial[lblk * 4 + k], a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __threadfence();
+    const unsigned int t = atomicAdd(counter, 1u);
+    s_last = (t == (unsigned int)(nblk - 1));
+  }
+  __syncthreads();
+  if (!s_last) return false;
+  __threadfence();
+  if (wv == 0) {
+    double acc[NV];
+#pragma unroll
+    for (int k = 0; k < NV; k++) acc[k] = 0.0;
+    for (int b = lane; b < nblk; b += 64) {
+#pragma unroll
+      for (int k = 0; k < NV; k++)
+        acc[k] += __hip_atomic_load(&partial[b * 4 + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+#pragma unroll
+    for (int k = 0; k < NV; k++) tot[k] = wave_sum(acc[k]);
+    if (lane == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  return true;
+}
+
+// Ticket without values (last workgroup detection only).
+__device__ __forceinline__ bool last_block(int nblk, unsigned int* counter) {
+  __shared__ int s_last;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const unsigned int t = atomicAdd(counter, 1u);
+    s_last = (t == (unsigned int)(nblk - 1));
+    if (s_last) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  return s_last != 0;
+}
+
+// ---------------------------------------------------------------------------
+// sparse row products
+// ---------------------------------------------------------------------------
+
+template <int ND, typename V, typename X, typename A>
+__device__ __forceinline__ A dia_row(const InstDesc& I, const V* __restrict__ val, const X* __restrict__ x,
+                                     int64_t i) {
+  A acc = A(0);
+  const int64_t st = I.stride;
+#pragma unroll
+  for (int d = 0; d < ND; d++) acc += (A)val[d * st + i] * (A)x[i + I.off[d]];
+  return acc;
+}
+
+template <typename V, typename X, typename A>
+__device__ __forceinline__ A spmv_row(const InstDesc& I, const V* __restrict__ val, const X* __restrict__ x,
+                                      int64_t i) {
+  if (I.fmt == FMT_DIA) {
+    if (I.ndiag == 27) return dia_row<27, V, X, A>(I, val, x, i);
+    if (I.ndiag == 15) return dia_row<15, V, X, A>(I, val, x, i);
+    A acc = A(0);
+    const int64_t st = I.stride;
+    for (int d = 0; d < I.ndiag; d++) acc += (A)val[d * st + i] * (A)x[i + I.off[d]];
+    return acc;
+  }
+  const int64_t slice = i >> 6;
+  const int lane = (int)(i & 63);
+  const int64_t o0 = I.slice_ptr[slice], o1 = I.slice_ptr[slice + 1];
+  A acc = A(0);
+  const int32_t* __restrict__ col = I.col;
+  int64_t o = o0 + lane;
+  for (; o + 3 * 64 < o1; o += 4 * 64) {
+    const V v0 = val[o], v1 = val[o + 64], v2 = val[o + 128], v3 = val[o + 192];
+    const int32_t c0 = col[o], c1 = col[o + 64], c2 = col[o + 128], c3 = col[o + 192];
+    acc += (A)v0 * (A)x[c0];
+    acc += (A)v1 * (A)x[c1];
+    acc += (A)v2 * (A)x[c2];
+    acc += (A)v3 * (A)x[c3];
+  }
+  for (; o < o1; o += 64) acc += (A)val[o] * (A)x[col[o]];
+  return acc;
+}
+
+// ---------------------------------------------------------------------------
+// ionic step + nodal RHS vector
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double stimulus_at(const InstDesc& I, int64_t k, int64_t i) {
+  double iapp = 0.0;
+  for (int gi = 0; gi < I.n_stim; gi++) {
+    const StimGroup& G = I.stim[gi];
+    int64_t q = k - G.s0;
+    if (q < 1) continue;
+    if (G.period > 0) q = (q - 1) % G.period + 1;
+    if (q <= G.dur) iapp += G.amp * G.prof[i];
+  }
+  return iapp;
+}
+
+template <int MODEL, bool MIXED>
+__global__ __launch_bounds__(WG) void k_ionic(const InstDesc* __restrict__ insts,
+                                              const BlockMap* __restrict__ bmap) {
+  const BlockMap bm = bmap[blockIdx.x];
+  const InstDesc& I = insts[bm.inst];
+  const int64_t n = I.n;
+  const int64_t i = (int64_t)bm.lblk * WG + threadIdx.x;
+  if (i >= n) return;
+  const int64_t step = I.st->step;
+  const int sig = min(I.bdf, (int)step + 1);
+  const double u0 = I.U[step & 3][i];
+  double u_ext, u_bdf;
+  if (sig == 1) {
+    u_ext = u0;
+    u_bdf = u0;
+  } else if (sig == 2) {
+    const double u1 = I.U[(step - 1) & 3][i];
+    u_ext = 2.0 * u0 - u1;
+    u_bdf = 2.0 * u0 - 0.5 * u1;
+  } else {
+    const double u1 = I.U[(step - 1) & 3][i], u2 = I.U[(step - 2) & 3][i];
+    u_ext = 3.0 * u0 - 3.0 * u1 + u2;
+    u_bdf = 3.0 * u0 - 1.5 * u1 + u2 * (1.0 / 3.0);
+  }
+  double iion = 0.0;
+  if (MODEL == M_AP) {
+    if (MIXED) {
+      float v = I.st32[i];
+      iion = (double)ap_step<float>((float)u_ext, (float)I.dt, I.mp, v);
+      I.st32[i] = v;
+    } else {
+      double v = I.st64[i];
+      iion = ap_step<double>(u_ext, I.dt, I.mp, v);
+      I.st64[i] = v;
+    }
+  } else if (MODEL == M_BO) {
+    if (MIXED) {
+      float v = I.st32[i], w = I.st32[n + i], s = I.st32[2 * n + i];
+      iion = (double)bo_step<float>((float)u_ext, (float)I.dt, I.mp, v, w, s);
+      I.st32[i] = v; I.st32[n + i] = w; I.st32[2 * n + i] = s;
+    } else {
+      double v = I.st64[i], w = I.st64[n + i], s = I.st64[2 * n + i];
+      iion = bo_step<double>(u_ext, I.dt, I.mp, v, w, s);
+      I.st64[i] = v; I.st64[n + i] = w; I.st64[2 * n + i] = s;
+    }
+  } else if (MODEL == M_TTP06) {
+    if (MIXED) {
+      // st32 rows: 12 gates, cai, casr, cass, rr ; st64 rows: nai, ki
+      TtpState<float> S;
+#pragma unroll
+      for (int k = 0; k < 12; k++) S.g[k] = I.st32[k * n + i];
+      S.cai = I.st32[12 * n + i]; S.casr = I.st32[13 * n + i]; S.cass = I.st32[14 * n + i];
+      S.rr = I.st32[15 * n + i];
+      S.nai = I.st64[i]; S.ki = I.st64[n + i];
+      iion = (double)ttp06_step<float>((float)u_ext, (float)I.dt, I.mp, S);
+#pragma unroll
+      for (int k = 0; k < 12; k++) I.st32[k * n + i] = S.g[k];
+      I.st32[12 * n + i] = S.cai; I.st32[13 * n + i] = S.casr; I.st32[14 * n + i] = S.cass;
+      I.st32[15 * n + i] = S.rr;
+      I.st64[i] = S.nai; I.st64[n + i] = S.ki;
+    } else {
+      // st64 rows in state order: 12 gates, cai, casr, cass, nai, ki, rr
+      TtpState<double> S;
+#pragma unroll
+      for (int k = 0; k < 12; k++) S.g[k] = I.st64[k * n + i];
+      S.cai = I.st64[12 * n + i]; S.casr = I.st64[13 * n + i]; S.cass = I.st64[14 * n + i];
+      S.nai = I.st64[15 * n + i]; S.ki = I.st64[16 * n + i]; S.rr = I.st64[17 * n + i];
+      iion = ttp06_step<double>(u_ext, I.dt, I.mp, S);
+#pragma unroll
+      for (int k = 0; k < 12; k++) I.st64[k * n + i] = S.g[k];
+      I.st64[12 * n + i] = S.cai; I.st64[13 * n + i] = S.casr; I.st64[14 * n + i] = S.cass;
+      I.st64[15 * n + i] = S.nai; I.st64[16 * n + i] = S.ki; I.st64[17 * n + i] = S.rr;
+    }
+  }
+  const double iapp = stimulus_at(I, step + 1, i);
+  I.g[i] = u_bdf * I.inv_dt + iapp - iion;
+  I.U[(step + 1) & 3][i] = u_ext;
+}
+
+// ---------------------------------------------------------------------------
+// residual r = b - A x (FP64), optionally with b = M g; preconditioner; start
+// of a (inner) CG solve.
+// ---------------------------------------------------------------------------
+
+template <bool MIXED, bool WITH_RHS>
+__global__ __launch_bounds__(WG) void k_residual(const InstDesc* __restrict__ insts,
+                                                 const BlockMap* __restrict__ bmap) {
+  const BlockMap bm = bmap[blockIdx.x];
+  const InstDesc& I = insts[bm.inst];
+  InstState* S = I.st;
+  if (!WITH_RHS && S->conv) return;
+  const int64_t i = (int64_t)bm.lblk * WG + threadIdx.x;
+  const bool act = i < I.n;
+  const int64_t step = S->step;
+  const int sig = min(I.bdf, (int)step + 1);
+  const double* __restrict__ x = I.U[(step + 1) & 3];
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  if (act) {
+    double bi;
+    if (WITH_RHS) {
+      bi = spmv_row<double, double, double>(I, I.valM, I.g, i);
+      I.b[i] = bi;
+    } else {
+      bi = I.b[i];
+    }
+    const double ri = bi - spmv_row<double, double, double>(I, I.valA[sig - 1], x, i);
+    if (!MIXED) {
+      const double zi = I.dinv[sig - 1][i] * ri;
+      I.r[i] = ri;
+      I.z[i] = zi;
+      v[0] = ri * zi;
+      v[1] = ri * ri;
+    } else {
+      const float r32 = (float)ri;
+      const float z32 = I.dinv32[sig - 1][i] * r32;
+      I.r32[i] = r32;
+      I.z32[i] = z32;
+      v[0] = (double)r32 * (double)z32;
+      v[1] = ri * ri;
+      v[3] = (double)r32 * (double)r32;
+    }
+    v[2] = bi * bi;
+  }
+  double tot[4];
+  if (reduce_ticket<4>(v, I.partial, bm.lblk, I.nblk, &S->counter[0], tot) && threadIdx.x == 0) {
+    if (WITH_RHS) {
+      S->bb = tot[2];
+      S->tol2 = I.rtol * I.rtol * tot[2];
+      S->sig = sig;
+      S->outer = 0;
+      S->conv = 0;
+    }
+    S->gamma = tot[0];
+    S->it = 0;
+    S->conv_in = 0;
+    S->rr_outer = tot[1];
+    S->rr = MIXED ? tot[3] : tot[1];
+    S->rr_in0 = S->rr;
+    if (!(tot[1] == tot[1]) || !(tot[2] == tot[2])) {
+      S->flags |= F_NAN;
+      S->conv = 1;
+    } else if (tot[1] <= S->tol2) {
+      S->conv = 1;
+    } else if (MIXED) {
+      if (S->outer >= I.max_outer) {
+        S->flags |= F_NOCONV;
+        S->conv = 1;
+      }
+      S->outer += 1;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// CG iteration, part 1: w = A z, delta = <w, z>; last workgroup forms the
+// Chronopoulos-Gear step lengths.
+// ---------------------------------------------------------------------------
+
+template <bool MIXED>
+__global__ __launch_bounds__(WG) void k_cg_spmv(const InstDesc* __restrict__ insts,
+                                                const BlockMap* __restrict__ bmap) {
+  const BlockMap bm = bmap[blockIdx.x];
+  const InstDesc& I = insts[bm.inst];
+  InstState* S = I.st;
+  if (S->conv || S->conv_in) return;
+  const int64_t i = (int64_t)bm.lblk * WG + threadIdx.x;
+  const bool act = i < I.n;
+  const int sig = S->sig;
+  double v[1] = {0.0};
+  if (act) {
+    if (MIXED) {
+      const float wi = spmv_row<float, float, float>(I, I.valA32[sig - 1], I.z32, i);
+      I.w32[i] = wi;
+      v[0] = (double)wi * (double)I.z32[i];
+    } else {
+      const double wi = spmv_row<double, double, double>(I, I.valA[sig - 1], I.z, i);
+      I.w[i] = wi;
+      v[0] = wi * I.z[i];
+    }
+  }
+  double tot[1];
+  if (reduce_ticket<1>(v, I.partial, bm.lblk, I.nblk, &S->counter[1], tot) && threadIdx.x == 0) {
+    const double delta = tot[0];
+    const double gamma = S->gamma;
+    double alpha, beta, denom;
+    if (S->it == 0) {
+      beta = 0.0;
+      denom = delta;
+    } else {
+      beta = gamma / S->gamma_prev;
+      denom = delta - beta * gamma / S->alpha_prev;
+    }
+    alpha = gamma / denom;
+    S->delta = delta;
+    S->beta = beta;
+    S->alpha = alpha;
+    if (!(denom > 0.0) || !(alpha == alpha)) {
+      S->flags |= (delta == delta) ? F_BREAKDOWN : F_NAN;
+      if (MIXED && (delta == delta)) S->conv_in = 1;
+      else S->conv = 1;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// CG iteration, part 2: p = z + beta p, s = w + beta s, x += alpha p,
+// r -= alpha s, z = P^{-1} r; gamma = <r, z>, rr = <r, r>.
+// ---------------------------------------------------------------------------
+
+template <bool MIXED>
+__global__ __launch_bounds__(WG) void k_cg_update(const InstDesc* __restrict__ insts,
+                                                  const BlockMap* __restrict__ bmap) {
+  const BlockMap bm = bmap[blockIdx.x];
+  const InstDesc& I = insts[bm.inst];
+  InstState* S = I.st;
+  if (S->conv || S->conv_in) return;
+  const int64_t i = (int64_t)bm.lblk * WG + threadIdx.x;
+  const bool act = i < I.n;
+  const int k = S->it;
+  const double alpha = S->alpha, beta = S->beta;
+  const int sig = S->sig;
+  double* __restrict__ x = I.U[(S->step + 1) & 3];
+  double v[2] = {0.0, 0.0};
+  if (act) {
+    if (MIXED) {
+      const float zi = I.z32[i], wi = I.w32[i];
+      const float fb = (float)beta, fa = (float)alpha;
+      const float pi = (k == 0) ? zi : zi + fb * I.p32[i];
+      const float si = (k == 0) ? wi : wi + fb * I.s32[i];
+      x[i] += alpha * (double)pi;
+      const float ri = I.r32[i] - fa * si;
+      const float zn = I.dinv32[sig - 1][i] * ri;
+      I.p32[i] = pi; I.s32[i] = si; I.r32[i] = ri; I.z32[i] = zn;
+      v[0] = (double)ri * (double)zn;
+      v[1] = (double)ri * (double)ri;
+    } else {
+      const double zi = I.z[i], wi = I.w[i];
+      const double pi = (k == 0) ? zi : zi + beta * I.p[i];
+      const double si = (k == 0) ? wi : wi + beta * I.s[i];
+      x[i] += alpha * pi;
+      const double ri = I.r[i] - alpha * si;
+      const double zn = I.dinv[sig - 1][i] * ri;
+      I.p[i] = pi; I.s[i] = si; I.r[i] = ri; I.z[i] = zn;
+      v[0] = ri * zn;
+      v[1] = ri * ri;
+    }
+  }
+  double tot[2];
+  if (reduce_ticket<2>(v, I.partial, bm.lblk, I.nblk, &S->counter[2], tot) && threadIdx.x == 0) {
+    S->gamma_prev = S->gamma;
+    S->gamma = tot[0];
+    S->alpha_prev = alpha;
+    S->rr = tot[1];
+    S->it = k + 1;
+    S->it_step += 1;
+    if (!(tot[1] == tot[1])) {
+      S->flags |= F_NAN;
+      S->conv = 1;
+    } else if (MIXED) {
+      if (tot[1] <= I.inner_rtol * I.inner_rtol * S->rr_in0 || k + 1 >= I.max_it) S->conv_in = 1;
+    } else {
+      if (tot[1] <= S->tol2) S->conv = 1;
+      else if (k + 1 >= I.max_it) {
+        S->flags |= F_NOCONV;
+        S->conv = 1;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// activation time and end of step
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(WG) void k_activation(const InstDesc* __restrict__ insts,
+                                                   const BlockMap* __restrict__ bmap) {
+  const BlockMap bm = bmap[blockIdx.x];
+  const InstDesc& I = insts[bm.inst];
+  InstState* S = I.st;
+  const int64_t i = (int64_t)bm.lblk * WG + threadIdx.x;
+  const int64_t step = S->step;
+  if (i < I.n) {
+    const double t = (double)(step + 1) * I.dt;
+    const double un = I.U[(step + 1) & 3][i];
+    const double uo = I.U[step & 3][i];
+    const double slope = (un - uo) * I.inv_dt;
+    if (slope > I.smax[i]) {
+      I.smax[i] = slope;
+      I.at[i] = t;
+    }
+    if (un > I.threshold) {
+      const double tc = I.tcross[i];
+      if (tc != tc) I.tcross[i] = t;
+    }
+  }
+  if (last_block(I.nblk, &S->counter[3]) && threadIdx.x == 0) {
+    S->step = step + 1;
+    S->it_last = S->it_step;
+    if (S->it_step > S->it_max) S->it_max = S->it_step;
+    S->it_total += S->it_step;
+    S->outer_total += S->outer;
+    S->it_step = 0;
+    S->it = 0;
+    S->conv = 0;
+    S->conv_in = 0;
+  }
+}
+
+// Potential in mV into a caller-owned device buffer: dst = a u + b.
+__global__ void k_to_mv(void* __restrict__ dst, const double* __restrict__ u, int64_t n, double a, double b,
+                        int f32) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double v = a * u[i] + b;
+  if (f32) static_cast<float*>(dst)[i] = (float)v;
+  else static_cast<double*>(dst)[i] = v;
+}
+
+// Fill a device vector (used for initialisation; graph-safe, unlike memset nodes).
+__global__ void k_fill(double* __restrict__ x, int64_t n, double v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+void launch_ionic(int model, bool mixed, const Launch& L) {
+  if (L.nblocks <= 0) return;
+  dim3 g(L.nblocks), b(WG);
+#define EP_ION(M)                                                                         \
+  if (mixed) hipLaunchKernelGGL((k_ionic<M, true>), g, b, 0, L.stream, L.insts, L.bmap); \
+  else hipLaunchKernelGGL((k_ionic<M, false>), g, b, 0, L.stream, L.insts, L.bmap);
+  switch (model) {
+    case M_AP: EP_ION(M_AP); break;
+    case M_BO: EP_ION(M_BO); break;
+    case M_TTP06: EP_ION(M_TTP06); break;
+    default: EP_ION(M_PASSIVE); break;
+  }
+#undef EP_ION
+}
+
+void launch_residual(bool mixed, bool with_rhs, const Launch& L) {
+  if (L.nblocks <= 0) return;
+  dim3 g(L.nblocks), b(WG);
+  if (mixed) {
+    if (with_rhs) hipLaunchKernelGGL((k_residual<true, true>), g, b, 0, L.stream, L.insts, L.bmap);
+    else hipLaunchKernelGGL((k_residual<true, false>), g, b, 0, L.stream, L.insts, L.bmap);
+  } else {
+    if (with_rhs) hipLaunchKernelGGL((k_residual<false, true>), g, b, 0, L.stream, L.insts, L.bmap);
+    else hipLaunchKernelGGL((k_residual<false, false>), g, b, 0, L.stream, L.insts, L.bmap);
+  }
+}
+
+void launch_cg_spmv(bool mixed, const Launch& L) {
+  if (L.nblocks <= 0) return;
+  dim3 g(L.nblocks), b(WG);
+  if (mixed) hipLaunchKernelGGL((k_cg_spmv<true>), g, b, 0, L.stream, L.insts, L.bmap);
+  else hipLaunchKernelGGL((k_cg_spmv<false>), g, b, 0, L.stream, L.insts, L.bmap);
+}
+
+void launch_cg_update(bool mixed, const Launch& L) {
+  if (L.nblocks <= 0) return;
+  dim3 g(L.nblocks), b(WG);
+  if (mixed) hipLaunchKernelGGL((k_cg_update<true>), g, b, 0, L.stream, L.insts, L.bmap);
+  else hipLaunchKernelGGL((k_cg_update<false>), g, b, 0, L.stream, L.insts, L.bmap);
+}
+
+void launch_activation(const Launch& L) {
+  if (L.nblocks <= 0) return;
+  hipLaunchKernelGGL(k_activation, dim3(L.nblocks), dim3(WG), 0, L.stream, L.insts, L.bmap);
+}
+
+void launch_to_mv(void* dst, const double* u, int64_t n, double a, double b, bool f32, hipStream_t stream) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_to_mv, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, dst, u, n, a, b,
+                     f32 ? 1 : 0);
+}
+
+void launch_fill(double* x, int64_t n, double v, hipStream_t stream) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, x, n, v);
+}
+
+}  // namespace ep
