@@ -1,0 +1,287 @@
+#!/usr/bin/env python3
+"""Benchmark: monodomain node-steps/s on one MI355X.
+
+Workload (default): TTP06 endocardial monodomain on the 20 x 7 x 3 mm slab
+at h = 0.1 mm (201 x 71 x 31 = 442,401 Q1 nodes), corner-cube stimulus,
+BDF2 IMEX, dt = 0.05 ms, Jacobi-PCG to rtol 1e-10.  A step is one full
+time step (ionic update, ICI right-hand side, linear solve, activation).
+Inputs are synthetic (generated mesh, model initial conditions) and resident
+in HBM before timing starts.
+
+Timed: `--warmup` untimed steps, then exactly `--steps` steps bracketed by
+device synchronization.  `value` is FP64 plain node-steps/s; the mixed
+precision (FP32 ionic + inner CG, FP64 refinement) run of the same workload
+is reported beside it.  A second, instrumented region of the same length
+brackets every kernel launch with HIP events for the roofline of the
+dominant kernel.  The oracle (FP64 CPU) is timed on a bounded sample of the
+same workload in a one-thread subprocess.
+
+Prints one JSON line.
+"""
+import argparse
+import hashlib
+import json
+import os
+import subprocess
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _workload(name):
+    import workloads as W
+    if name == "c1":
+        return W.config_c1(h=0.1, n_steps=2000), "ttp06-slab-20x7x3mm-h0.1-442401nodes-bdf2-dt0.05"
+    if name == "c1big":
+        return W.config_c1(h=0.05, n_steps=200), "ttp06-slab-20x7x3mm-h0.05-3449001nodes-bdf2-dt0.05"
+    if name == "c0":
+        return W.config_c0(), "ap-slab-20x7x3mm-h0.5-4305nodes-bdf1-dt0.05"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def kernel_bytes(kind, n, nnz, mixed, nvars_model):
+    """Algorithmic HBM bytes per launch of each kernel: every array the kernel
+    must touch read or written once (matrix values once per nonzero; DIA needs
+    no column indices)."""
+    if kind == "cg_spmv":
+        return nnz * (4 if mixed else 8) + n * (8 if mixed else 16)
+    if kind == "cg_update":
+        return n * (56 if mixed else 96)
+    if kind == "rhs":
+        return 2 * nnz * 8 + n * (36 if mixed else 48)
+    if kind == "ir_residual":
+        return nnz * 8 + n * 28
+    if kind == "ionic":
+        if nvars_model == 18:
+            return n * (192 if mixed else 320)
+        return n * (16 + 2 * nvars_model * (4 if mixed else 8) + 16)
+    if kind == "activation":
+        return n * 32
+    return 0
+
+
+def _src_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2308_01651_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def _traffic(kernel_kind, precision, workload):
+    """HBM bytes per launch from committed rocprofv3 counter runs (FETCH_SIZE,
+    WRITE_SIZE, scaled by the copy-kernel calibration), or None when no run
+    exists for the current kernel sources."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+    except Exception:
+        return None
+    key = f"{workload}:{precision}:{kernel_kind}"
+    e = d.get("entries", {}).get(key)
+    if not e or e.get("src_hash") != _src_hash():
+        return None
+    f = d.get("copy_calibration", {})
+    ff, fw = f.get("fetch_factor"), f.get("write_factor")
+    if not ff or not fw:
+        return None
+    return (e["fetch_kib_per_dispatch"] * ff + e["write_kib_per_dispatch"] * fw) * 1024.0
+
+
+def run_gpu(spec, precision, steps, warmup, instrument_steps):
+    import paper_2308_01651_amd as ep
+    import torch
+    sim = ep.Simulation.from_spec(spec, precision=precision)
+    st0 = sim.get_stats()
+    sim.step(warmup)
+    sim.sync()
+    torch.cuda.synchronize()
+    it0 = sim.get_stats()["cg_iters_total"]
+    lat = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        a = time.perf_counter()
+        sim.step(1)
+        lat.append(time.perf_counter() - a)
+    sim.sync()
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    st = sim.get_stats()
+    u_end = sim.get_potential()
+    at_end = sim.get_activation_times()
+    res = {
+        "seconds": T,
+        "node_steps_per_s": spec.mesh.n_nodes * steps / T,
+        "ms_per_step": 1e3 * T / steps,
+        "step_latency_ms_p50": 1e3 * float(np.percentile(lat, 50)),
+        "step_latency_ms_p99": 1e3 * float(np.percentile(lat, 99)),
+        "cg_iters_per_step": (st["cg_iters_total"] - it0) / steps,
+        "ir_sweeps_total": st["ir_sweeps_total"],
+        "rel_residual_last": st["rel_residual_last"],
+        "matrix_format": {1: "SELL", 2: "DIA"}[st["matrix_format"]],
+        "n_diag": st["n_diag"],
+        "nnz": st["nnz"],
+        "device_bytes": st["device_bytes"],
+        "setup_ms": st0["ms_setup"],
+    }
+    # instrumented region: HIP events around every launch
+    kt = None
+    if instrument_steps > 0:
+        sim.set_option(ep.EP_OPT_KERNEL_TIMERS, 1)
+        it1 = sim.get_stats()["cg_iters_total"]
+        sim.step(instrument_steps)
+        sim.sync()
+        kt = sim.get_kernel_times()
+        res["instrumented_steps"] = instrument_steps
+        res["instrumented_cg_iters"] = sim.get_stats()["cg_iters_total"] - it1
+        res["kernel_ms"] = {k: v[0] for k, v in kt.items()}
+        res["kernel_launches"] = {k: v[1] for k, v in kt.items()}
+        sim.set_option(ep.EP_OPT_KERNEL_TIMERS, 0)
+    sim.close()
+    return res, u_end, at_end
+
+
+def roofline(res, spec, precision_name, workload_key):
+    n = spec.mesh.n_nodes
+    nnz = res["nnz"]
+    mixed = precision_name == "mixed"
+    nv = {"ttp06": 18, "bo": 3, "ap": 1, "passive": 0}[spec.model]
+    ms = res["kernel_ms"]
+    cnt = res["kernel_launches"]
+    kinds = [k for k in ms if cnt[k] > 0]
+    dom = max(kinds, key=lambda k: ms[k])
+    bytes_per = kernel_bytes(dom, n, nnz, mixed, nv)
+    avg_s = ms[dom] / 1e3 / cnt[dom]
+    achieved = bytes_per / avg_s / 1e9
+    per_kernel = {}
+    for k in kinds:
+        b = kernel_bytes(k, n, nnz, mixed, nv)
+        a = ms[k] / 1e3 / cnt[k]
+        per_kernel[k] = {"avg_us": 1e6 * a, "launches": cnt[k], "share": ms[k] / sum(ms.values()),
+                         "GBps": b / a / 1e9 if b else None, "algo_bytes": b}
+    tr = _traffic(dom, precision_name, workload_key)
+    return {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": tr, "algo_bytes_per_launch": bytes_per,
+            "avg_launch_us": 1e6 * avg_s}, per_kernel
+
+
+CPU_SAMPLE = r"""
+import json, os, sys, time
+sys.path.insert(0, {root!r})
+import workloads as W
+from oracle import monodomain as OM
+spec = W.config_c1(h={h}, n_steps=1)
+o = OM.from_spec(spec, solver="cg", rtol=spec.rtol)
+o.step()                      # untimed first step
+budget = {budget}
+t0 = time.perf_counter(); k = 0
+while True:
+    o.step(); k += 1
+    if time.perf_counter() - t0 > budget and k >= 3:
+        break
+T = time.perf_counter() - t0
+print(json.dumps({{"steps": k, "seconds": T, "n": spec.mesh.n_nodes}}))
+"""
+
+
+def cpu_baseline(h, budget_s):
+    env = dict(os.environ)
+    for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "NUMEXPR_NUM_THREADS"):
+        env[v] = "1"
+    code = CPU_SAMPLE.format(root=ROOT, h=h, budget=budget_s)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=900)
+    if r.returncode != 0:
+        return {"error": r.stderr[-500:]}
+    d = json.loads(r.stdout.strip().splitlines()[-1])
+    return {"value": d["n"] * d["steps"] / d["seconds"], "unit": "node-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"steps 2..{d['steps'] + 1} of the same {d['n']}-node TTP06 slab from rest "
+                      f"(FP64 NumPy/SciPy, Jacobi-PCG to rtol 1e-10, one thread), {d['seconds']:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="c1")
+    ap.add_argument("--precision", default="both", choices=["fp64", "mixed", "both"])
+    ap.add_argument("--instrument-steps", type=int, default=-1,
+                    help="length of the event-instrumented region (default: same as --steps)")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is designed, not built",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import paper_2308_01651_amd as ep
+    spec, wname = _workload(args.workload)
+    instr = args.steps if args.instrument_steps < 0 else args.instrument_steps
+    out = {}
+    fields = {}
+    precs = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
+    for pn in precs:
+        print(f"[bench] {wname} {pn}: warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
+        res, u, at = run_gpu(spec, ep.EP_FP64 if pn == "fp64" else ep.EP_MIXED, args.steps, args.warmup, instr)
+        if instr > 0:
+            rl, pk = roofline(res, spec, pn, args.workload)
+            res["roofline"] = rl
+            res["per_kernel"] = pk
+        else:
+            rl = {"kernel": None, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                  "frac": None, "traffic": None}
+            res["roofline"] = rl
+        out[pn] = res
+        fields[pn] = (u, at)
+        print(f"[bench] {pn}: {res['node_steps_per_s']:.4g} node-steps/s, {res['ms_per_step']:.3f} ms/step, "
+              f"dominant {rl['kernel']} {rl['achieved']} GB/s", file=sys.stderr, flush=True)
+    if "fp64" in fields and "mixed" in fields:
+        du = fields["mixed"][0] - fields["fp64"][0]
+        a64, a32 = fields["fp64"][1], fields["mixed"][1]
+        ok = ~np.isnan(a64) & ~np.isnan(a32)
+        out["mixed"]["vs_fp64"] = {
+            "rms_mV": float(np.sqrt(np.mean(du ** 2))), "max_abs_mV": float(np.max(np.abs(du))),
+            "max_abs_dAT_ms": float(np.max(np.abs(a64[ok] - a32[ok]))) if ok.any() else None,
+            "activated_nodes_equal": bool(np.array_equal(np.isnan(a64), np.isnan(a32)))}
+    cpu = None
+    if not args.no_cpu_baseline and args.workload in ("c1", "c1big"):
+        print("[bench] cpu baseline (oracle, 1 thread)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(spec.mesh.xyz[1, 0] - spec.mesh.xyz[0, 0], args.cpu_budget)
+    main_res = out["fp64"] if "fp64" in out else out["mixed"]
+    line = {
+        "metric": "monodomain node-steps/s (TTP06, 442k nodes) plain vs batched/FP32; p99 latency",
+        "value": main_res["node_steps_per_s"],
+        "unit": "node-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_res["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if "fp64" in out else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": wname, "n_nodes": spec.mesh.n_nodes, "model": spec.model,
+                   "variant": spec.variant, "bdf": spec.bdf, "dt_ms": spec.dt, "rtol": spec.rtol,
+                   "precision": "fp64" if "fp64" in out else "mixed", "parallelism": "single-gpu"},
+        "p50_step_latency_ms": main_res["step_latency_ms_p50"],
+        "p99_step_latency_ms": main_res["step_latency_ms_p99"],
+        "roofline": {k: main_res["roofline"][k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
+        "roofline_kernel": main_res["roofline"]["kernel"],
+        "cpu_baseline": cpu,
+        "variants": out,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -70,7 +70,19 @@ enum {
   EP_OPT_MATRIX_FORMAT = 1, /* EP_FMT_*; AUTO picks DIA when it moves fewer bytes      */
   EP_OPT_INNER_RTOL = 2,    /* mixed precision: inner FP32 CG relative tolerance (1e-4)  */
   EP_OPT_MAX_OUTER = 3,     /* mixed precision: max refinement sweeps per step (30)      */
-  EP_OPT_PHASE_TIMERS = 4   /* 1: time ionic / rhs / solve / activation phases (any time) */
+  EP_OPT_PHASE_TIMERS = 4,  /* 1: time ionic / rhs / solve / activation phases (any time) */
+  EP_OPT_KERNEL_TIMERS = 5  /* 1: bracket every kernel launch with HIP events and sum
+                               their durations per kernel (any time; resets the sums) */
+};
+
+/* Kernel kinds reported by ep_sim_get_kernel_times. */
+enum {
+  EP_K_IONIC = 0,      /* ionic step + nodal right-hand side               */
+  EP_K_RHS = 1,        /* b = M g and r0 = b - A x0 (dual SpMV)            */
+  EP_K_CG_SPMV = 2,    /* w = A z with <w, z>                              */
+  EP_K_CG_UPDATE = 3,  /* fused CG vector update with <r, z>, <r, r>       */
+  EP_K_ACTIVATION = 4, /* activation-time tracking, end of step            */
+  EP_K_IR_RESIDUAL = 5 /* FP64 refinement residual (mixed precision)       */
 };
 
 typedef struct ep_stats {
@@ -181,6 +193,12 @@ ep_status ep_sim_get_activation_times(ep_sim* sim, double* out_ms);
 ep_status ep_sim_get_threshold_times(ep_sim* sim, double* out_ms);
 
 ep_status ep_sim_get_stats(ep_sim* sim, ep_stats* out);
+
+/* Summed durations (ms, from HIP events on the sim's stream) and launch
+ * counts per kernel kind (EP_K_*), both arrays [6], since
+ * EP_OPT_KERNEL_TIMERS was last set.  Launches that found their solve already
+ * converged return at once and are counted too. */
+ep_status ep_sim_get_kernel_times(ep_sim* sim, double* ms, int64_t* launches);
 
 /* Raw state in model units (after finalize).  u: [n_nodes]; w: [n_vars][n_nodes]
  * in the model's state order (AP: v; BO: v, w, s; TTP06: m h j xr1 xr2 xs s r

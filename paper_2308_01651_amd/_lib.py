@@ -35,7 +35,7 @@ class EpStats(C.Structure):
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
-                      "(python -m paper_2308_01651_amd.build)")
+                      "(python paper_2308_01651_amd/build.py)")
 
 # PyTorch ships its own HIP runtime with the same soname as the system one.
 # Loading torch first makes this library bind to that runtime, so that one
@@ -70,6 +70,7 @@ _SIGS = {
     "ep_sim_get_activation_times": [P, PD],
     "ep_sim_get_threshold_times": [P, PD],
     "ep_sim_get_stats": [P, C.POINTER(EpStats)],
+    "ep_sim_get_kernel_times": [P, PD, PI64],
     "ep_sim_set_state": [P, PD, PD, PD, C.c_int64],
     "ep_sim_get_state": [P, PD, PD, PD],
     "ep_sim_device_bytes_estimate": [P, C.POINTER(C.c_size_t)],

@@ -1,6 +1,6 @@
 """Build libep_mi355x.so (HIP for gfx950) in the package directory.
 
-    python -m paper_2308_01651_amd.build
+    python paper_2308_01651_amd/build.py
 
 Compiles every source under csrc/ with hipcc into objects under _build/ and
 links them into paper_2308_01651_amd/libep_mi355x.so.  Always recompiles.

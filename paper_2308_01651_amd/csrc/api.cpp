@@ -157,6 +157,14 @@ struct ep_sim {
   double ms_setup = 0.0;
   double ms_phase[4] = {0, 0, 0, 0};
   hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  // per-kernel event timers: kinds 0 ionic, 1 rhs residual, 2 cg spmv,
+  // 3 cg update, 4 activation, 5 refinement residual
+  int ktimers = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> kt_pending[6];
+  std::vector<hipEvent_t> kt_free;
+  double kt_ms[6] = {0, 0, 0, 0, 0, 0};
+  int64_t kt_count[6] = {0, 0, 0, 0, 0, 0};
+  int32_t* d_ids = nullptr;  // device list {0}: the instance advanced by k_end_step
   int it_pred = 8;      // CG iterations launched before the first convergence check
   int in_pred = 8;      // inner iterations per refinement sweep (mixed)
   int sticky = EP_OK;
@@ -172,9 +180,12 @@ ep_status check_sim(ep_sim* s) {
 }
 
 // Read the device state into pinned host memory (synchronizes the stream).
+void kt_harvest(ep_sim* s);
+
 ep_status pull_state(ep_sim* s) {
   EP_HIP(hipMemcpyAsync(s->h_st, s->d_st, sizeof(InstState), hipMemcpyDeviceToHost, s->stream));
   EP_HIP(hipStreamSynchronize(s->stream));
+  if (s->ktimers) kt_harvest(s);
   return EP_OK;
 }
 
@@ -451,7 +462,12 @@ ep_status finalize_impl(ep_sim* s) {
   s->nblocks = (int)((n + WG - 1) / WG);
   D.blk0 = 0;
   D.nblk = s->nblocks;
-  EP_HIP(m.alloc((void**)&D.partial, (size_t)s->nblocks * 4 * sizeof(double)));
+  EP_HIP(m.alloc((void**)&D.partial, (size_t)s->nblocks * PART_DOUBLES * sizeof(double)));
+  {
+    const int32_t zero = 0;
+    EP_HIP(upload(m, &s->d_ids, &zero, 1, st));
+    EP_HIP(hipStreamSynchronize(st));
+  }
   EP_HIP(m.alloc((void**)&s->d_st, sizeof(InstState)));
   D.st = s->d_st;
   EP_HIP(hipHostMalloc((void**)&s->h_st, sizeof(InstState), hipHostMallocDefault));
@@ -480,51 +496,102 @@ ep_status finalize_impl(ep_sim* s) {
 
 Launch launch_of(ep_sim* s) { return Launch{s->d_desc, s->d_bmap, s->nblocks, s->stream}; }
 
+hipEvent_t kt_event(ep_sim* s) {
+  if (!s->kt_free.empty()) {
+    hipEvent_t e = s->kt_free.back();
+    s->kt_free.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Launch `fn` bracketed by events when kernel timers are on.
+template <typename F>
+void timed(ep_sim* s, int kind, F&& fn) {
+  if (!s->ktimers) {
+    fn();
+    return;
+  }
+  hipEvent_t a = kt_event(s), b = kt_event(s);
+  if (!a || !b) {
+    fn();
+    return;
+  }
+  (void)hipEventRecord(a, s->stream);
+  fn();
+  (void)hipEventRecord(b, s->stream);
+  s->kt_pending[kind].emplace_back(a, b);
+}
+
+// Harvest completed event pairs (call after a stream synchronization).
+void kt_harvest(ep_sim* s) {
+  for (int k = 0; k < 6; k++) {
+    for (auto& pr : s->kt_pending[k]) {
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) {
+        s->kt_ms[k] += ms;
+        s->kt_count[k] += 1;
+      }
+      s->kt_free.push_back(pr.first);
+      s->kt_free.push_back(pr.second);
+    }
+    s->kt_pending[k].clear();
+  }
+}
+
 // One time step of one sim (host sequencing; all arithmetic on the device).
+// Kernel order: ionic, residual(+rhs), then CG as SpMV, {update, SpMV}*;
+// every SpMV kernel first decides convergence from the preceding kernel's
+// partial sums, so the host checks the device flag after an SpMV kernel.
+// Mixed precision inserts an FP64 refinement residual after each inner sweep.
 ep_status step_once(ep_sim* s) {
   const Launch L = launch_of(s);
   const bool mixed = s->prec == EP_MIXED;
   if (s->timers) EP_HIP(hipEventRecord(s->ev[0], s->stream));
-  launch_ionic(s->model, mixed, L);
+  timed(s, 0, [&] { launch_ionic(s->model, mixed, L); });
   if (s->timers) EP_HIP(hipEventRecord(s->ev[1], s->stream));
-  launch_residual(mixed, true, L);
+  timed(s, 1, [&] { launch_residual(mixed, true, L); });
   if (s->timers) EP_HIP(hipEventRecord(s->ev[2], s->stream));
+  timed(s, 2, [&] { launch_cg_spmv(mixed, L); });
   if (!mixed) {
     int chunk = std::max(1, s->it_pred);
-    for (int guard_loop = 0;; guard_loop++) {
+    for (int rounds = 0;; rounds++) {
       for (int c = 0; c < chunk; c++) {
-        launch_cg_spmv(false, L);
-        launch_cg_update(false, L);
+        timed(s, 3, [&] { launch_cg_update(false, L); });
+        timed(s, 2, [&] { launch_cg_spmv(false, L); });
       }
       ep_status rc = pull_state(s);
       if (rc != EP_OK) return rc;
       if (s->h_st->conv) break;
-      if (guard_loop > s->max_it + 2) return fail(EP_EHIP, "solver control lost (no convergence flag)");
+      if (rounds > s->max_it + 2) return fail(EP_EHIP, "solver control lost (no convergence flag)");
       chunk = 2;
     }
     s->it_pred = std::max(1, s->h_st->it_step);
   } else {
-    int sweeps = 0;
-    for (;;) {
-      const int before = s->h_st->it_step;
+    int before = 0;
+    for (int sweeps = 0;; sweeps++) {
       const int chunk = std::max(1, s->in_pred);
       for (int c = 0; c < chunk; c++) {
-        launch_cg_spmv(true, L);
-        launch_cg_update(true, L);
+        timed(s, 3, [&] { launch_cg_update(true, L); });
+        timed(s, 2, [&] { launch_cg_spmv(true, L); });
       }
-      launch_residual(true, false, L);
+      timed(s, 5, [&] { launch_residual(true, false, L); });
+      timed(s, 2, [&] { launch_cg_spmv(true, L); });
       ep_status rc = pull_state(s);
       if (rc != EP_OK) return rc;
-      sweeps++;
-      const int done = s->h_st->it_step - (sweeps == 1 ? 0 : before);
+      const int done = s->h_st->it_step - before;
+      before = s->h_st->it_step;
       if (done >= chunk) s->in_pred = chunk + std::max(1, chunk / 2);
-      else if (done + 2 < chunk) s->in_pred = std::max(1, done + 1);
+      else if (done > 0 && done + 2 < chunk) s->in_pred = done + 1;
       if (s->h_st->conv) break;
       if (sweeps > s->max_outer + 2) return fail(EP_EHIP, "solver control lost (no convergence flag)");
     }
   }
   if (s->timers) EP_HIP(hipEventRecord(s->ev[3], s->stream));
-  launch_activation(L);
+  timed(s, 4, [&] { launch_activation(L); });
+  launch_end_step(s->d_desc, s->d_ids, 1, s->stream);
   if (s->timers) {
     EP_HIP(hipEventRecord(s->ev[4], s->stream));
     EP_HIP(hipEventSynchronize(s->ev[4]));
@@ -656,6 +723,16 @@ ep_status ep_sim_set_option(ep_sim* s, int key, double value) {
   if (check_sim(s)) return EP_EINVAL;
   if (key == EP_OPT_PHASE_TIMERS) {
     s->timers = value != 0.0;
+    return EP_OK;
+  }
+  if (key == EP_OPT_KERNEL_TIMERS) {
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    kt_harvest(s);
+    s->ktimers = value != 0.0;
+    for (int k = 0; k < 6; k++) {
+      s->kt_ms[k] = 0.0;
+      s->kt_count[k] = 0;
+    }
     return EP_OK;
   }
   if (s->finalized) return fail(EP_ESTATE, "sim already finalized");
@@ -873,6 +950,7 @@ ep_status ep_sim_get_stats(ep_sim* s, ep_stats* o) {
   o->ir_sweeps_total = S.outer_total;
   o->rel_residual_last = S.bb > 0 ? std::sqrt(S.rr_outer / S.bb) : 0.0;
   if (s->prec != EP_MIXED && S.bb > 0) o->rel_residual_last = std::sqrt(S.rr / S.bb);
+  if (s->prec != EP_MIXED && S.bb == 0) o->rel_residual_last = 0.0;
   o->matrix_format = s->desc.fmt == FMT_DIA ? EP_FMT_DIA : EP_FMT_SELL;
   o->n_diag = s->desc.ndiag;
   o->device_bytes = (int64_t)s->mem.bytes;
@@ -884,10 +962,23 @@ ep_status ep_sim_get_stats(ep_sim* s, ep_stats* o) {
   return EP_OK;
 }
 
+ep_status ep_sim_get_kernel_times(ep_sim* s, double* ms, int64_t* launches) {
+  if (check_sim(s) || !ms || !launches) return fail(EP_EINVAL, "null argument");
+  if (s->stream) EP_HIP(hipStreamSynchronize(s->stream));
+  kt_harvest(s);
+  for (int k = 0; k < 6; k++) {
+    ms[k] = s->kt_ms[k];
+    launches[k] = s->kt_count[k];
+  }
+  return EP_OK;
+}
+
 void ep_sim_destroy(ep_sim* s) {
   if (!s) return;
   (void)hipSetDevice(s->device);
   if (s->stream) (void)hipStreamSynchronize(s->stream);
+  kt_harvest(s);
+  for (auto e : s->kt_free) (void)hipEventDestroy(e);
   for (auto& e : s->ev)
     if (e) (void)hipEventDestroy(e);
   s->mem.release();

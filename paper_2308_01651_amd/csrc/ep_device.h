@@ -33,27 +33,28 @@ struct StimGroup {
   int64_t s0, dur, period;
 };
 
-// Mutable per-instance state, written only by kernels (and by the host when
-// the instance is (re)initialised).
+// Mutable per-instance state.  Scalars are written only by workgroup 0 of an
+// instance (lblk == 0) and only into fields that no workgroup of the same
+// kernel reads; values needed across iterations are double-buffered by the
+// iteration parity.  Kernel boundaries make the writes visible.
 struct InstState {
-  int64_t step;        // completed steps n
-  int32_t it;          // CG iteration index in the current (inner) solve
+  int64_t step;        // completed steps n (advanced by k_end_step only)
+  int32_t it;          // CG iteration index, written by the update kernel
+  int32_t it_spmv;     // iteration index seen by the last SpMV kernel
   int32_t conv;        // 1: the step's solve is done
-  int32_t conv_in;     // 1: the inner FP32 solve is done (mixed precision)
+  int32_t conv_in;     // 1: the inner FP32 solve of this sweep is done
   int32_t flags;       // Flag bits, sticky until cleared by the host
-  int32_t outer;       // refinement sweeps done in this step
-  int32_t sig;         // BDF order used by the current step
-  int64_t it_total;    // CG iterations over all steps
-  int64_t outer_total;
+  int32_t outer;       // refinement sweeps started in this step
   int32_t it_step;     // CG iterations in the current step (all sweeps)
   int32_t it_last;     // CG iterations of the last finished step
   int32_t it_max;      // largest per-step CG count so far
   int32_t pad_;
-  double gamma, gamma_prev, delta, alpha, alpha_prev, beta;
+  int64_t it_total;    // CG iterations over all steps
+  int64_t outer_total;
+  double gamma[2];     // <r, z> at iteration k, slot k & 1
+  double alpha[2];     // step length of iteration k, slot k & 1
   double rr, bb, tol2, rr_in0, rr_outer;
-  unsigned int counter[4];   // last-block reduction tickets, one per kernel kind
 };
-
 struct InstDesc {
   int64_t n;               // nodes
   int64_t stride;          // DIA value stride (n rounded up to 64)
@@ -84,8 +85,12 @@ struct InstDesc {
   double *smax, *at, *tcross;
   StimGroup stim[MAX_STIM];
   InstState* st;
-  double* partial;         // [nblk][4] per-workgroup partial sums
+  double* partial;         // per-workgroup partial sums, PART_DOUBLES * nblk
 };
+
+// Partial-sum layout inside InstDesc::partial, in units of nblk doubles:
+// residual kernel [4][nblk], SpMV [1][nblk], update (parity 0, 1) [2][2][nblk].
+constexpr int PART_RES = 0, PART_SPMV = 4, PART_UPD = 5, PART_DOUBLES = 9;
 
 struct BlockMap {
   int32_t inst;

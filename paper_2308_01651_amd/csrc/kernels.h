@@ -20,6 +20,8 @@ void launch_residual(bool mixed, bool with_rhs, const Launch& L);
 void launch_cg_spmv(bool mixed, const Launch& L);
 void launch_cg_update(bool mixed, const Launch& L);
 void launch_activation(const Launch& L);
+// ids: device array of instance indices to advance by one step
+void launch_end_step(const InstDesc* insts, const int32_t* ids, int n_ids, hipStream_t stream);
 void launch_fill(double* x, int64_t n, double v, hipStream_t stream);
 void launch_to_mv(void* dst, const double* u, int64_t n, double a, double b, bool f32, hipStream_t stream);
 

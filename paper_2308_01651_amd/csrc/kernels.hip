@@ -20,10 +20,13 @@
 // column-major inside the slice).  Vectors that SpMV gathers from carry zero
 // guard cells so DIA rows near the ends stay in bounds.
 //
-// Reductions are deterministic: each workgroup writes its partial sum, the
-// last workgroup to finish (ticket counter) adds the partials in a fixed order
-// and computes the CG scalars on the device.  A batch of instances reduces per
-// instance, so each instance's result does not depend on the batch.
+// Reductions are deterministic and need no cross-workgroup synchronization
+// inside a kernel: each workgroup writes its partial sum; the next kernel of
+// the sequence adds all partials of the instance in a fixed order in every
+// workgroup (so all workgroups take identical decisions), and workgroup 0
+// alone persists the scalars the following kernels need.  A batch of
+// instances reduces per instance, so each instance's result does not depend
+// on the batch.
 #include <hip/hip_runtime.h>
 
 #include "ep_device.h"
@@ -42,63 +45,51 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Every thread of the workgroup must call this (no early return before it).
-// Returns true in the last workgroup of the instance; tot[] is valid in its
-// first wavefront.
+// Workgroup sum of v[], stored by thread 0 at P[c * nblk + lblk].
+// Every thread of the workgroup must call it.
 template <int NV>
-__device__ __forceinline__ bool reduce_ticket(double (&v)[NV], double* __restrict__ partial, int lblk,
-                                              int nblk, unsigned int* counter, double (&tot)[NV]) {
-  __shared__ double sh[WG / 64][4];
-  __shared__ int s_last;
+__device__ __forceinline__ void write_partials(double (&v)[NV], double* __restrict__ P, int nblk, int lblk) {
+  __shared__ double sh[WG / 64][NV];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-  for (int k = 0; k < NV; k++) v[k] = wave_sum(v[k]);
+  for (int c = 0; c < NV; c++) v[c] = wave_sum(v[c]);
   if (lane == 0) {
 #pragma unroll
-    for (int k = 0; k < NV; k++) sh[wv][k] = v[k];
+    for (int c = 0; c < NV; c++) sh[wv][c] = v[c];
   }
   __syncthreads();
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int k = 0; k < NV; k++) {
-      const double a = (sh[0][k] + sh[1][k]) + (sh[2][k] + sh[3][k]);
-      __hip_atomic_store(&partial[lblk * 4 + k], a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __threadfence();
-    const unsigned int t = atomicAdd(counter, 1u);
-    s_last = (t == (unsigned int)(nblk - 1));
+    for (int c = 0; c < NV; c++) P[(int64_t)c * nblk + lblk] = (sh[0][c] + sh[1][c]) + (sh[2][c] + sh[3][c]);
   }
-  __syncthreads();
-  if (!s_last) return false;
-  __threadfence();
-  if (wv == 0) {
-    double acc[NV];
-#pragma unroll
-    for (int k = 0; k < NV; k++) acc[k] = 0.0;
-    for (int b = lane; b < nblk; b += 64) {
-#pragma unroll
-      for (int k = 0; k < NV; k++)
-        acc[k] += __hip_atomic_load(&partial[b * 4 + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-#pragma unroll
-    for (int k = 0; k < NV; k++) tot[k] = wave_sum(acc[k]);
-    if (lane == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  return true;
 }
 
-// Ticket without values (last workgroup detection only).
-__device__ __forceinline__ bool last_block(int nblk, unsigned int* counter) {
-  __shared__ int s_last;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const unsigned int t = atomicAdd(counter, 1u);
-    s_last = (t == (unsigned int)(nblk - 1));
-    if (s_last) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Sum of the partials P[c * nblk + b], b < nblk, in a fixed order; every
+// thread of every workgroup obtains bitwise the same totals.
+template <int NV>
+__device__ __forceinline__ void reduce_partials(const double* __restrict__ P, int nblk, double (&out)[NV]) {
+  __shared__ double sh[WG / 64][NV];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double acc[NV];
+#pragma unroll
+  for (int c = 0; c < NV; c++) acc[c] = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += WG) {
+#pragma unroll
+    for (int c = 0; c < NV; c++) acc[c] += P[(int64_t)c * nblk + b];
+  }
+#pragma unroll
+  for (int c = 0; c < NV; c++) acc[c] = wave_sum(acc[c]);
+  if (lane == 0) {
+#pragma unroll
+    for (int c = 0; c < NV; c++) sh[wv][c] = acc[c];
   }
   __syncthreads();
-  return s_last != 0;
+#pragma unroll
+  for (int c = 0; c < NV; c++) out[c] = (sh[0][c] + sh[1][c]) + (sh[2][c] + sh[3][c]);
+}
+
+__device__ __forceinline__ int ld_flag(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ---------------------------------------------------------------------------
@@ -241,7 +232,7 @@ __global__ __launch_bounds__(WG) void k_ionic(const InstDesc* __restrict__ insts
 
 // ---------------------------------------------------------------------------
 // residual r = b - A x (FP64), optionally with b = M g; preconditioner; start
-// of a (inner) CG solve.
+// of a (inner) CG solve.  Partials: <r,z>, <r,r>, <b,b>, <r32,r32>.
 // ---------------------------------------------------------------------------
 
 template <bool MIXED, bool WITH_RHS>
@@ -250,7 +241,7 @@ __global__ __launch_bounds__(WG) void k_residual(const InstDesc* __restrict__ in
   const BlockMap bm = bmap[blockIdx.x];
   const InstDesc& I = insts[bm.inst];
   InstState* S = I.st;
-  if (!WITH_RHS && S->conv) return;
+  if (!WITH_RHS && ld_flag(&S->conv)) return;
   const int64_t i = (int64_t)bm.lblk * WG + threadIdx.x;
   const bool act = i < I.n;
   const int64_t step = S->step;
@@ -281,41 +272,23 @@ __global__ __launch_bounds__(WG) void k_residual(const InstDesc* __restrict__ in
       v[1] = ri * ri;
       v[3] = (double)r32 * (double)r32;
     }
-    v[2] = bi * bi;
+    if (WITH_RHS) v[2] = bi * bi;
   }
-  double tot[4];
-  if (reduce_ticket<4>(v, I.partial, bm.lblk, I.nblk, &S->counter[0], tot) && threadIdx.x == 0) {
-    if (WITH_RHS) {
-      S->bb = tot[2];
-      S->tol2 = I.rtol * I.rtol * tot[2];
-      S->sig = sig;
-      S->outer = 0;
-      S->conv = 0;
-    }
-    S->gamma = tot[0];
+  write_partials<4>(v, I.partial + (int64_t)PART_RES * I.nblk, I.nblk, bm.lblk);
+  if (bm.lblk == 0 && threadIdx.x == 0) {
+    // a new (inner) solve starts at iteration 0
     S->it = 0;
     S->conv_in = 0;
-    S->rr_outer = tot[1];
-    S->rr = MIXED ? tot[3] : tot[1];
-    S->rr_in0 = S->rr;
-    if (!(tot[1] == tot[1]) || !(tot[2] == tot[2])) {
-      S->flags |= F_NAN;
-      S->conv = 1;
-    } else if (tot[1] <= S->tol2) {
-      S->conv = 1;
-    } else if (MIXED) {
-      if (S->outer >= I.max_outer) {
-        S->flags |= F_NOCONV;
-        S->conv = 1;
-      }
-      S->outer += 1;
+    if (WITH_RHS) {
+      S->conv = 0;
+      S->outer = 0;
     }
   }
 }
 
 // ---------------------------------------------------------------------------
-// CG iteration, part 1: w = A z, delta = <w, z>; last workgroup forms the
-// Chronopoulos-Gear step lengths.
+// CG iteration k, part 1: decide convergence from the previous kernel's
+// partials, then w = A z and <w, z>.
 // ---------------------------------------------------------------------------
 
 template <bool MIXED>
@@ -324,12 +297,70 @@ __global__ __launch_bounds__(WG) void k_cg_spmv(const InstDesc* __restrict__ ins
   const BlockMap bm = bmap[blockIdx.x];
   const InstDesc& I = insts[bm.inst];
   InstState* S = I.st;
-  if (S->conv || S->conv_in) return;
+  if (ld_flag(&S->conv) || ld_flag(&S->conv_in)) return;
+  const int k = S->it;
+  const int nblk = I.nblk;
+  const bool lead = bm.lblk == 0 && threadIdx.x == 0;
+  double gamma, rr;
+  bool done = false, stop_in = false;
+  int flag = 0;
+  if (k == 0) {
+    double t[4];
+    reduce_partials<4>(I.partial + (int64_t)PART_RES * nblk, nblk, t);
+    gamma = t[0];
+    // first sweep of the step: the right-hand side norm fixes the tolerance
+    const bool first = MIXED ? (S->outer == 0) : true;
+    const double tol2 = first ? I.rtol * I.rtol * t[2] : S->tol2;
+    const double rr_outer = t[1];
+    rr = MIXED ? t[3] : t[1];
+    if (!(rr_outer == rr_outer) || !(gamma == gamma)) {
+      done = true;
+      flag = F_NAN;
+    } else if (rr_outer <= tol2) {
+      done = true;
+    } else if (MIXED && S->outer >= I.max_outer) {
+      done = true;
+      flag = F_NOCONV;
+    }
+    if (lead) {
+      if (first) {
+        S->bb = t[2];
+        S->tol2 = tol2;
+      }
+      S->rr_outer = rr_outer;
+      S->rr_in0 = rr;
+      if (MIXED && !done) S->outer += 1;
+    }
+  } else {
+    double t[2];
+    reduce_partials<2>(I.partial + (int64_t)(PART_UPD + 2 * (k & 1)) * nblk, nblk, t);
+    gamma = t[0];
+    rr = t[1];
+    if (!(rr == rr)) {
+      done = true;
+      flag = F_NAN;
+    } else if (MIXED) {
+      stop_in = rr <= I.inner_rtol * I.inner_rtol * S->rr_in0 || k >= I.max_it;
+    } else if (rr <= S->tol2) {
+      done = true;
+    } else if (k >= I.max_it) {
+      done = true;
+      flag = F_NOCONV;
+    }
+  }
+  if (lead) {
+    S->it_spmv = k;
+    S->gamma[k & 1] = gamma;
+    S->rr = rr;
+    if (flag) S->flags |= flag;
+    if (done) __hip_atomic_store(&S->conv, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (stop_in) __hip_atomic_store(&S->conv_in, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (done || stop_in) return;   // uniform over the instance
   const int64_t i = (int64_t)bm.lblk * WG + threadIdx.x;
-  const bool act = i < I.n;
-  const int sig = S->sig;
+  const int sig = min(I.bdf, (int)S->step + 1);
   double v[1] = {0.0};
-  if (act) {
+  if (i < I.n) {
     if (MIXED) {
       const float wi = spmv_row<float, float, float>(I, I.valA32[sig - 1], I.z32, i);
       I.w32[i] = wi;
@@ -340,33 +371,13 @@ __global__ __launch_bounds__(WG) void k_cg_spmv(const InstDesc* __restrict__ ins
       v[0] = wi * I.z[i];
     }
   }
-  double tot[1];
-  if (reduce_ticket<1>(v, I.partial, bm.lblk, I.nblk, &S->counter[1], tot) && threadIdx.x == 0) {
-    const double delta = tot[0];
-    const double gamma = S->gamma;
-    double alpha, beta, denom;
-    if (S->it == 0) {
-      beta = 0.0;
-      denom = delta;
-    } else {
-      beta = gamma / S->gamma_prev;
-      denom = delta - beta * gamma / S->alpha_prev;
-    }
-    alpha = gamma / denom;
-    S->delta = delta;
-    S->beta = beta;
-    S->alpha = alpha;
-    if (!(denom > 0.0) || !(alpha == alpha)) {
-      S->flags |= (delta == delta) ? F_BREAKDOWN : F_NAN;
-      if (MIXED && (delta == delta)) S->conv_in = 1;
-      else S->conv = 1;
-    }
-  }
+  write_partials<1>(v, I.partial + (int64_t)PART_SPMV * nblk, nblk, bm.lblk);
 }
 
 // ---------------------------------------------------------------------------
-// CG iteration, part 2: p = z + beta p, s = w + beta s, x += alpha p,
-// r -= alpha s, z = P^{-1} r; gamma = <r, z>, rr = <r, r>.
+// CG iteration k, part 2 (Chronopoulos-Gear): step lengths from <w,z> and the
+// stored gammas; p = z + beta p, s = w + beta s, x += alpha p, r -= alpha s,
+// z = P^{-1} r; partials <r, z>, <r, r>.
 // ---------------------------------------------------------------------------
 
 template <bool MIXED>
@@ -375,15 +386,36 @@ __global__ __launch_bounds__(WG) void k_cg_update(const InstDesc* __restrict__ i
   const BlockMap bm = bmap[blockIdx.x];
   const InstDesc& I = insts[bm.inst];
   InstState* S = I.st;
-  if (S->conv || S->conv_in) return;
+  if (ld_flag(&S->conv) || ld_flag(&S->conv_in)) return;
+  const int k = S->it_spmv;
+  const int nblk = I.nblk;
+  double t[1];
+  reduce_partials<1>(I.partial + (int64_t)PART_SPMV * nblk, nblk, t);
+  const double delta = t[0];
+  const double gamma = S->gamma[k & 1];
+  double beta, denom;
+  if (k == 0) {
+    beta = 0.0;
+    denom = delta;
+  } else {
+    beta = gamma / S->gamma[(k - 1) & 1];
+    denom = delta - beta * gamma / S->alpha[(k - 1) & 1];
+  }
+  const double alpha = gamma / denom;
+  const bool lead = bm.lblk == 0 && threadIdx.x == 0;
+  if (!(denom > 0.0) || !(alpha == alpha)) {
+    if (lead) {
+      S->flags |= (delta == delta) ? F_BREAKDOWN : F_NAN;
+      if (MIXED && (delta == delta)) __hip_atomic_store(&S->conv_in, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      else __hip_atomic_store(&S->conv, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return;
+  }
   const int64_t i = (int64_t)bm.lblk * WG + threadIdx.x;
-  const bool act = i < I.n;
-  const int k = S->it;
-  const double alpha = S->alpha, beta = S->beta;
-  const int sig = S->sig;
+  const int sig = min(I.bdf, (int)S->step + 1);
   double* __restrict__ x = I.U[(S->step + 1) & 3];
   double v[2] = {0.0, 0.0};
-  if (act) {
+  if (i < I.n) {
     if (MIXED) {
       const float zi = I.z32[i], wi = I.w32[i];
       const float fb = (float)beta, fa = (float)alpha;
@@ -407,65 +439,53 @@ __global__ __launch_bounds__(WG) void k_cg_update(const InstDesc* __restrict__ i
       v[1] = ri * ri;
     }
   }
-  double tot[2];
-  if (reduce_ticket<2>(v, I.partial, bm.lblk, I.nblk, &S->counter[2], tot) && threadIdx.x == 0) {
-    S->gamma_prev = S->gamma;
-    S->gamma = tot[0];
-    S->alpha_prev = alpha;
-    S->rr = tot[1];
+  write_partials<2>(v, I.partial + (int64_t)(PART_UPD + 2 * ((k + 1) & 1)) * nblk, nblk, bm.lblk);
+  if (lead) {
+    S->alpha[k & 1] = alpha;
     S->it = k + 1;
     S->it_step += 1;
-    if (!(tot[1] == tot[1])) {
-      S->flags |= F_NAN;
-      S->conv = 1;
-    } else if (MIXED) {
-      if (tot[1] <= I.inner_rtol * I.inner_rtol * S->rr_in0 || k + 1 >= I.max_it) S->conv_in = 1;
-    } else {
-      if (tot[1] <= S->tol2) S->conv = 1;
-      else if (k + 1 >= I.max_it) {
-        S->flags |= F_NOCONV;
-        S->conv = 1;
-      }
-    }
   }
 }
 
 // ---------------------------------------------------------------------------
-// activation time and end of step
+// activation time; end of step
 // ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(WG) void k_activation(const InstDesc* __restrict__ insts,
                                                    const BlockMap* __restrict__ bmap) {
   const BlockMap bm = bmap[blockIdx.x];
   const InstDesc& I = insts[bm.inst];
-  InstState* S = I.st;
   const int64_t i = (int64_t)bm.lblk * WG + threadIdx.x;
-  const int64_t step = S->step;
-  if (i < I.n) {
-    const double t = (double)(step + 1) * I.dt;
-    const double un = I.U[(step + 1) & 3][i];
-    const double uo = I.U[step & 3][i];
-    const double slope = (un - uo) * I.inv_dt;
-    if (slope > I.smax[i]) {
-      I.smax[i] = slope;
-      I.at[i] = t;
-    }
-    if (un > I.threshold) {
-      const double tc = I.tcross[i];
-      if (tc != tc) I.tcross[i] = t;
-    }
+  if (i >= I.n) return;
+  const int64_t step = I.st->step;
+  const double t = (double)(step + 1) * I.dt;
+  const double un = I.U[(step + 1) & 3][i];
+  const double uo = I.U[step & 3][i];
+  const double slope = (un - uo) * I.inv_dt;
+  if (slope > I.smax[i]) {
+    I.smax[i] = slope;
+    I.at[i] = t;
   }
-  if (last_block(I.nblk, &S->counter[3]) && threadIdx.x == 0) {
-    S->step = step + 1;
-    S->it_last = S->it_step;
-    if (S->it_step > S->it_max) S->it_max = S->it_step;
-    S->it_total += S->it_step;
-    S->outer_total += S->outer;
-    S->it_step = 0;
-    S->it = 0;
-    S->conv = 0;
-    S->conv_in = 0;
+  if (un > I.threshold) {
+    const double tc = I.tcross[i];
+    if (tc != tc) I.tcross[i] = t;
   }
+}
+
+// One thread per instance: advance the step counter and the statistics.
+__global__ void k_end_step(const InstDesc* __restrict__ insts, const int32_t* __restrict__ ids, int n_ids) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_ids) return;
+  InstState* S = insts[ids[t]].st;
+  S->step += 1;
+  S->it_last = S->it_step;
+  if (S->it_step > S->it_max) S->it_max = S->it_step;
+  S->it_total += S->it_step;
+  S->outer_total += S->outer;
+  S->it_step = 0;
+  S->it = 0;
+  S->conv = 0;
+  S->conv_in = 0;
 }
 
 // Potential in mV into a caller-owned device buffer: dst = a u + b.
@@ -532,6 +552,11 @@ void launch_cg_update(bool mixed, const Launch& L) {
 void launch_activation(const Launch& L) {
   if (L.nblocks <= 0) return;
   hipLaunchKernelGGL(k_activation, dim3(L.nblocks), dim3(WG), 0, L.stream, L.insts, L.bmap);
+}
+
+void launch_end_step(const InstDesc* insts, const int32_t* ids, int n_ids, hipStream_t stream) {
+  if (n_ids <= 0) return;
+  hipLaunchKernelGGL(k_end_step, dim3((unsigned)((n_ids + 63) / 64)), dim3(64), 0, stream, insts, ids, n_ids);
 }
 
 void launch_to_mv(void* dst, const double* u, int64_t n, double a, double b, bool f32, hipStream_t stream) {
