@@ -82,7 +82,8 @@ enum {
   EP_K_CG_SPMV = 2,    /* w = A z with <w, z>                              */
   EP_K_CG_UPDATE = 3,  /* fused CG vector update with <r, z>, <r, r>       */
   EP_K_ACTIVATION = 4, /* activation-time tracking, end of step            */
-  EP_K_IR_RESIDUAL = 5 /* FP64 refinement residual (mixed precision)       */
+  EP_K_IR_RESIDUAL = 5,/* FP64 refinement residual (mixed precision)       */
+  EP_K_CG_FINALIZE = 6 /* per-instance reduction, convergence, step lengths */
 };
 
 typedef struct ep_stats {
@@ -195,7 +196,7 @@ ep_status ep_sim_get_threshold_times(ep_sim* sim, double* out_ms);
 ep_status ep_sim_get_stats(ep_sim* sim, ep_stats* out);
 
 /* Summed durations (ms, from HIP events on the sim's stream) and launch
- * counts per kernel kind (EP_K_*), both arrays [6], since
+ * counts per kernel kind (EP_K_*), both arrays [7], since
  * EP_OPT_KERNEL_TIMERS was last set.  Launches that found their solve already
  * converged return at once and are counted too. */
 ep_status ep_sim_get_kernel_times(ep_sim* sim, double* ms, int64_t* launches);

@@ -25,7 +25,7 @@ EP_DTYPE_F64, EP_DTYPE_F32 = 0, 1
 EP_FMT_AUTO, EP_FMT_SELL, EP_FMT_DIA = 0, 1, 2
 EP_OPT_MATRIX_FORMAT, EP_OPT_INNER_RTOL, EP_OPT_MAX_OUTER, EP_OPT_PHASE_TIMERS = 1, 2, 3, 4
 EP_OPT_KERNEL_TIMERS = 5
-KERNEL_KINDS = ["ionic", "rhs", "cg_spmv", "cg_update", "activation", "ir_residual"]
+KERNEL_KINDS = ["ionic", "rhs", "cg_spmv", "cg_update", "activation", "ir_residual", "cg_finalize"]
 
 MODEL_IDS = {"passive": EP_PASSIVE, "ap": EP_AP, "bo": EP_BO, "ttp06": EP_TTP06}
 CELL_IDS = {"": EP_CELL_EPI, "epi": EP_CELL_EPI, "endo": EP_CELL_ENDO, "mid": EP_CELL_MID}
@@ -130,8 +130,8 @@ class Simulation:
         return {name: getattr(st, name) for name, _ in EpStats._fields_}
 
     def get_kernel_times(self) -> dict:
-        ms = np.zeros(6)
-        cnt = np.zeros(6, np.int64)
+        ms = np.zeros(7)
+        cnt = np.zeros(7, np.int64)
         check(lib.ep_sim_get_kernel_times(self._h, _pd(ms), cnt.ctypes.data_as(_lib.PI64)),
               "ep_sim_get_kernel_times")
         return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(KERNEL_KINDS)}

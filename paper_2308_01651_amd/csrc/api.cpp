@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstddef>
 #include <cmath>
 #include <cstring>
 #include <limits>
@@ -158,12 +159,12 @@ struct ep_sim {
   double ms_phase[4] = {0, 0, 0, 0};
   hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   // per-kernel event timers: kinds 0 ionic, 1 rhs residual, 2 cg spmv,
-  // 3 cg update, 4 activation, 5 refinement residual
+  // 3 cg update, 4 activation, 5 refinement residual, 6 cg finalize
   int ktimers = 0;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> kt_pending[6];
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> kt_pending[7];
   std::vector<hipEvent_t> kt_free;
-  double kt_ms[6] = {0, 0, 0, 0, 0, 0};
-  int64_t kt_count[6] = {0, 0, 0, 0, 0, 0};
+  double kt_ms[7] = {0, 0, 0, 0, 0, 0, 0};
+  int64_t kt_count[7] = {0, 0, 0, 0, 0, 0, 0};
   int32_t* d_ids = nullptr;  // device list {0}: the instance advanced by k_end_step
   int it_pred = 8;      // CG iterations launched before the first convergence check
   int in_pred = 8;      // inner iterations per refinement sweep (mixed)
@@ -258,9 +259,17 @@ ep_status finalize_impl(ep_sim* s) {
   const int64_t sell_nnz = slice_ptr[n_slices];
   const int64_t stride = round_up(n, 64);
   const double vb = mixed ? 4.0 : 8.0;
+  // symmetric DIA keeps the offsets >= 0; the pattern of an FE operator is
+  // symmetric, so every stored offset o > 0 also stands for -o
+  std::vector<int64_t> up;
+  bool sym_pattern = true;
+  for (int64_t o : offs)
+    if (o >= 0) up.push_back(o);
+  for (int64_t o : up)
+    if (o > 0 && !std::binary_search(offs.begin(), offs.end(), -o)) sym_pattern = false;
   bool use_dia = false;
-  if ((int)offs.size() <= MAX_DIAG) {
-    const double dia_bytes = (double)offs.size() * stride * vb;
+  if (sym_pattern && (int)offs.size() <= MAX_DIAG && (int)up.size() <= MAX_UP) {
+    const double dia_bytes = (double)up.size() * stride * vb;
     const double sell_bytes = (double)sell_nnz * (vb + 4.0);
     use_dia = (s->fmt_pref == EP_FMT_DIA) || (s->fmt_pref == EP_FMT_AUTO && dia_bytes < sell_bytes);
   } else if (s->fmt_pref == EP_FMT_DIA) {
@@ -269,7 +278,6 @@ ep_status finalize_impl(ep_sim* s) {
   InstDesc& D = s->desc;
   std::memset(&D, 0, sizeof(D));
   D.n = n;
-  D.stride = stride;
   D.model = s->model;
   D.bdf = s->bdf;
   D.prec = s->prec;
@@ -312,34 +320,60 @@ ep_status finalize_impl(ep_sim* s) {
   std::vector<std::vector<double>> hostvals;  // keep alive until sync
   if (use_dia) {
     D.fmt = FMT_DIA;
-    D.ndiag = (int)offs.size();
-    int64_t g = 0;
-    for (size_t d = 0; d < offs.size(); d++) {
-      D.off[d] = (int32_t)offs[d];
-      g = std::max<int64_t>(g, std::llabs(offs[d]));
-    }
+    D.nup = (int)up.size();
+    const int64_t g = up.back();
+    for (size_t d = 0; d < up.size(); d++) D.off[d] = (int32_t)up[d];
     s->guard = round_up(std::max<int64_t>(g, 1), 64);
+    const int64_t G = s->guard;
+    const int64_t ld = stride + G;
+    D.ld = ld;
+    // value of (i, i + o) stored at row i; symmetrized (A + A^T)/2 so that
+    // the last-bit asymmetry of the element integrals does not matter
     auto to_dia = [&](const std::vector<double>& v) {
-      std::vector<double> out((size_t)D.ndiag * stride, 0.0);
+      std::vector<double> out((size_t)D.nup * ld + G, 0.0);
+      double* p = out.data() + G;
       parallel_for(n, [&](int64_t i) {
-        for (int64_t t = A.rowptr[i]; t < A.rowptr[i + 1]; t++) {
-          const int64_t o = (int64_t)A.col[t] - i;
-          const int64_t d = std::lower_bound(offs.begin(), offs.end(), o) - offs.begin();
-          out[(size_t)d * stride + i] = v[t];
+        const int32_t* c = &A.col[A.rowptr[i]];
+        const int64_t len = A.rowptr[i + 1] - A.rowptr[i];
+        for (int d = 0; d < D.nup; d++) {
+          const int64_t j = i + up[d];
+          if (j >= n) continue;
+          const int32_t* f = std::lower_bound(c, c + len, (int32_t)j);
+          if (f == c + len || *f != j) continue;
+          const double aij = v[A.rowptr[i] + (f - c)];
+          const int32_t* cj = &A.col[A.rowptr[j]];
+          const int64_t lj = A.rowptr[j + 1] - A.rowptr[j];
+          const int32_t* fj = std::lower_bound(cj, cj + lj, (int32_t)i);
+          const double aji = (fj != cj + lj && *fj == i) ? v[A.rowptr[j] + (fj - cj)] : aij;
+          p[(size_t)d * ld + i] = 0.5 * (aij + aji);
         }
       });
       return out;
     };
+    auto dev_dia = [&](const std::vector<double>& h, const double** d) -> hipError_t {
+      double* base;
+      hipError_t e = upload(m, &base, h.data(), h.size(), st);
+      *d = base + G;
+      return e;
+    };
+    auto dev_dia_f = [&](const std::vector<double>& h, const float** d) -> hipError_t {
+      std::vector<float> f(h.begin(), h.end());
+      float* base;
+      hipError_t e = upload(m, &base, f.data(), f.size(), st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      *d = base + G;
+      return e;
+    };
     hostvals.push_back(to_dia(A.valM));
-    EP_HIP(to_dev_d(hostvals.back(), &D.valM));
+    EP_HIP(dev_dia(hostvals.back(), &D.valM));
     for (int q = 0; q < nsig; q++) {
       hostvals.push_back(to_dia(valA[q]));
-      EP_HIP(to_dev_d(hostvals.back(), &D.valA[q]));
-      if (mixed) EP_HIP(to_dev_f(hostvals.back(), &D.valA32[q]));
+      EP_HIP(dev_dia(hostvals.back(), &D.valA[q]));
+      if (mixed) EP_HIP(dev_dia_f(hostvals.back(), &D.valA32[q]));
     }
   } else {
     D.fmt = FMT_SELL;
-    D.ndiag = 0;
+    D.nup = 0;
     s->guard = 0;
     std::vector<int32_t> col(sell_nnz, 0);
     std::vector<int64_t> pos(nnz);
@@ -459,25 +493,25 @@ ep_status finalize_impl(ep_sim* s) {
     D.n_stim = k;
   }
   // ---- control state, partials, block map ----
-  s->nblocks = (int)((n + WG - 1) / WG);
+  const int ntiles = (int)((n + TILE - 1) / TILE);
   D.blk0 = 0;
-  D.nblk = s->nblocks;
-  EP_HIP(m.alloc((void**)&D.partial, (size_t)s->nblocks * PART_DOUBLES * sizeof(double)));
+  D.nblk = ntiles;
+  // single-instance launches cover N_XCD * ceil(tiles / N_XCD) workgroups
+  s->nblocks = N_XCD * ((ntiles + N_XCD - 1) / N_XCD);
+  EP_HIP(m.alloc((void**)&D.partial, (size_t)ntiles * PART_DOUBLES * sizeof(double)));
   {
     const int32_t zero = 0;
     EP_HIP(upload(m, &s->d_ids, &zero, 1, st));
     EP_HIP(hipStreamSynchronize(st));
   }
-  EP_HIP(m.alloc((void**)&s->d_st, sizeof(InstState)));
-  D.st = s->d_st;
   EP_HIP(hipHostMalloc((void**)&s->h_st, sizeof(InstState), hipHostMallocDefault));
   std::memset(s->h_st, 0, sizeof(InstState));
-  EP_HIP(hipMemcpyAsync(s->d_st, s->h_st, sizeof(InstState), hipMemcpyHostToDevice, st));
-  std::vector<BlockMap> bm(s->nblocks);
-  for (int b = 0; b < s->nblocks; b++) bm[b] = {0, b};
+  std::vector<BlockMap> bm(ntiles);
+  for (int b = 0; b < ntiles; b++) bm[b] = {0, b};
   EP_HIP(upload(m, &s->d_bmap, bm.data(), bm.size(), st));
   EP_HIP(m.alloc((void**)&s->d_desc, sizeof(InstDesc)));
-  EP_HIP(hipMemcpyAsync(s->d_desc, &s->desc, sizeof(InstDesc), hipMemcpyHostToDevice, st));
+  // the state lives inside the device descriptor (its first member)
+  s->d_st = reinterpret_cast<InstState*>(reinterpret_cast<char*>(s->d_desc) + offsetof(InstDesc, st));
   EP_HIP(hipStreamSynchronize(st));
   hostvals.clear();
   for (int k = 0; k < 5; k++) EP_HIP(hipEventCreate(&s->ev[k]));
@@ -494,7 +528,7 @@ ep_status finalize_impl(ep_sim* s) {
   return EP_OK;
 }
 
-Launch launch_of(ep_sim* s) { return Launch{s->d_desc, s->d_bmap, s->nblocks, s->stream}; }
+Launch launch_of(ep_sim* s) { return Launch{s->d_desc, s->d_bmap, s->nblocks, s->stream, true}; }
 
 hipEvent_t kt_event(ep_sim* s) {
   if (!s->kt_free.empty()) {
@@ -527,7 +561,7 @@ void timed(ep_sim* s, int kind, F&& fn) {
 
 // Harvest completed event pairs (call after a stream synchronization).
 void kt_harvest(ep_sim* s) {
-  for (int k = 0; k < 6; k++) {
+  for (int k = 0; k < 7; k++) {
     for (auto& pr : s->kt_pending[k]) {
       float ms = 0.0f;
       if (hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) {
@@ -542,26 +576,31 @@ void kt_harvest(ep_sim* s) {
 }
 
 // One time step of one sim (host sequencing; all arithmetic on the device).
-// Kernel order: ionic, residual(+rhs), then CG as SpMV, {update, SpMV}*;
-// every SpMV kernel first decides convergence from the preceding kernel's
-// partial sums, so the host checks the device flag after an SpMV kernel.
-// Mixed precision inserts an FP64 refinement residual after each inner sweep.
+// Kernel order: ionic, residual(+rhs), SpMV, finalize, then rounds of
+// {update, SpMV, finalize}; each finalize decides convergence on the device,
+// and the host reads that flag after a chunk of rounds.  Mixed precision
+// appends an FP64 refinement residual (+ SpMV, finalize) after each inner
+// sweep.
 ep_status step_once(ep_sim* s) {
   const Launch L = launch_of(s);
   const bool mixed = s->prec == EP_MIXED;
+  auto fin = [&] { timed(s, 6, [&] { launch_cg_finalize(mixed, s->d_desc, s->d_ids, 1, s->stream); }); };
+  auto round = [&] {
+    timed(s, 3, [&] { launch_cg_update(mixed, L); });
+    timed(s, 2, [&] { launch_cg_spmv(mixed, L); });
+    fin();
+  };
   if (s->timers) EP_HIP(hipEventRecord(s->ev[0], s->stream));
   timed(s, 0, [&] { launch_ionic(s->model, mixed, L); });
   if (s->timers) EP_HIP(hipEventRecord(s->ev[1], s->stream));
   timed(s, 1, [&] { launch_residual(mixed, true, L); });
   if (s->timers) EP_HIP(hipEventRecord(s->ev[2], s->stream));
   timed(s, 2, [&] { launch_cg_spmv(mixed, L); });
+  fin();
   if (!mixed) {
     int chunk = std::max(1, s->it_pred);
     for (int rounds = 0;; rounds++) {
-      for (int c = 0; c < chunk; c++) {
-        timed(s, 3, [&] { launch_cg_update(false, L); });
-        timed(s, 2, [&] { launch_cg_spmv(false, L); });
-      }
+      for (int c = 0; c < chunk; c++) round();
       ep_status rc = pull_state(s);
       if (rc != EP_OK) return rc;
       if (s->h_st->conv) break;
@@ -573,12 +612,10 @@ ep_status step_once(ep_sim* s) {
     int before = 0;
     for (int sweeps = 0;; sweeps++) {
       const int chunk = std::max(1, s->in_pred);
-      for (int c = 0; c < chunk; c++) {
-        timed(s, 3, [&] { launch_cg_update(true, L); });
-        timed(s, 2, [&] { launch_cg_spmv(true, L); });
-      }
+      for (int c = 0; c < chunk; c++) round();
       timed(s, 5, [&] { launch_residual(true, false, L); });
       timed(s, 2, [&] { launch_cg_spmv(true, L); });
+      fin();
       ep_status rc = pull_state(s);
       if (rc != EP_OK) return rc;
       const int done = s->h_st->it_step - before;
@@ -729,7 +766,7 @@ ep_status ep_sim_set_option(ep_sim* s, int key, double value) {
     if (s->stream) (void)hipStreamSynchronize(s->stream);
     kt_harvest(s);
     s->ktimers = value != 0.0;
-    for (int k = 0; k < 6; k++) {
+    for (int k = 0; k < 7; k++) {
       s->kt_ms[k] = 0.0;
       s->kt_count[k] = 0;
     }
@@ -842,7 +879,13 @@ ep_status ep_sim_set_state(ep_sim* s, const double* u, const double* w, const do
   EP_HIP(hipGetLastError());
   std::memset(s->h_st, 0, sizeof(InstState));
   s->h_st->step = step_index;
-  EP_HIP(hipMemcpyAsync(s->d_st, s->h_st, sizeof(InstState), hipMemcpyHostToDevice, st));
+  // descriptor with a fresh control state and the history slots of step n
+  D.st = *s->h_st;
+  D.u_new = D.U[(step_index + 1) & 3];
+  D.u_cur = D.U[step_index & 3];
+  D.u_prev1 = D.U[(step_index - 1) & 3];
+  D.u_prev2 = D.U[(step_index - 2) & 3];
+  EP_HIP(hipMemcpyAsync(s->d_desc, &D, sizeof(InstDesc), hipMemcpyHostToDevice, st));
   EP_HIP(hipStreamSynchronize(st));
   return EP_OK;
 }
@@ -952,7 +995,7 @@ ep_status ep_sim_get_stats(ep_sim* s, ep_stats* o) {
   if (s->prec != EP_MIXED && S.bb > 0) o->rel_residual_last = std::sqrt(S.rr / S.bb);
   if (s->prec != EP_MIXED && S.bb == 0) o->rel_residual_last = 0.0;
   o->matrix_format = s->desc.fmt == FMT_DIA ? EP_FMT_DIA : EP_FMT_SELL;
-  o->n_diag = s->desc.ndiag;
+  o->n_diag = s->desc.fmt == FMT_DIA ? 2 * s->desc.nup - 1 : 0;
   o->device_bytes = (int64_t)s->mem.bytes;
   o->ms_ionic = s->ms_phase[0];
   o->ms_rhs = s->ms_phase[1];
@@ -966,7 +1009,7 @@ ep_status ep_sim_get_kernel_times(ep_sim* s, double* ms, int64_t* launches) {
   if (check_sim(s) || !ms || !launches) return fail(EP_EINVAL, "null argument");
   if (s->stream) EP_HIP(hipStreamSynchronize(s->stream));
   kt_harvest(s);
-  for (int k = 0; k < 6; k++) {
+  for (int k = 0; k < 7; k++) {
     ms[k] = s->kt_ms[k];
     launches[k] = s->kt_count[k];
   }

@@ -13,8 +13,13 @@
 namespace ep {
 
 constexpr int WG = 256;        // threads per workgroup of node-parallel kernels
+constexpr int RPT = 2;         // rows (nodes) per thread in the solver kernels
+constexpr int TILE = WG * RPT; // nodes per workgroup; thread t owns rows t and t + WG
+constexpr int FIN_WG = 1024;   // threads of the one-workgroup-per-instance finalize
 constexpr int SLICE = 64;      // SELL slice height = one wavefront
-constexpr int MAX_DIAG = 32;   // largest diagonal count stored in DIA form
+constexpr int MAX_DIAG = 32;   // largest diagonal count of a DIA-stored pattern
+constexpr int MAX_UP = (MAX_DIAG + 1) / 2;  // stored (upper) diagonals of a symmetric DIA
+constexpr int N_XCD = 8;       // accelerator complex dies; workgroups go round-robin
 constexpr int MAX_STIM = 8;    // stimulus groups per instance
 constexpr int NPARAM = 32;     // model parameter slots
 constexpr int RING = 4;        // potential history ring (u_{n+1}, u_n, u_{n-1}, u_{n-2})
@@ -33,39 +38,48 @@ struct StimGroup {
   int64_t s0, dur, period;
 };
 
-// Mutable per-instance state.  Scalars are written only by workgroup 0 of an
-// instance (lblk == 0) and only into fields that no workgroup of the same
-// kernel reads; values needed across iterations are double-buffered by the
-// iteration parity.  Kernel boundaries make the writes visible.
+// Mutable per-instance state.  The CG scalars are owned by the one-workgroup
+// finalize kernel; the wide kernels only read them (and workgroup 0 of the
+// update kernel advances the iteration counters, which no workgroup of that
+// kernel reads).  Kernel boundaries make the writes visible.
 struct InstState {
   int64_t step;        // completed steps n (advanced by k_end_step only)
-  int32_t it;          // CG iteration index, written by the update kernel
-  int32_t it_spmv;     // iteration index seen by the last SpMV kernel
+  int32_t it;          // CG iterations done in the current (inner) solve
+  int32_t it_f;        // iteration index whose step lengths the finalize set
   int32_t conv;        // 1: the step's solve is done
   int32_t conv_in;     // 1: the inner FP32 solve of this sweep is done
   int32_t flags;       // Flag bits, sticky until cleared by the host
-  int32_t outer;       // refinement sweeps started in this step
+  int32_t outer;       // refinement sweeps in this step
   int32_t it_step;     // CG iterations in the current step (all sweeps)
   int32_t it_last;     // CG iterations of the last finished step
   int32_t it_max;      // largest per-step CG count so far
   int32_t pad_;
   int64_t it_total;    // CG iterations over all steps
   int64_t outer_total;
-  double gamma[2];     // <r, z> at iteration k, slot k & 1
-  double alpha[2];     // step length of iteration k, slot k & 1
+  double gamma, gamma_prev, alpha, alpha_prev, beta;
   double rr, bb, tol2, rr_in0, rr_outer;
 };
+// Per-instance descriptor.  The mutable state sits inside it (first member),
+// so kernels reach it without another pointer hop; the potential history
+// slots are rotated on the device at the end of every step, so kernels do not
+// need the step counter to find them: u_new = U[(n+1)&3], u_cur = U[n&3],
+// u_prev1 = U[(n-1)&3], u_prev2 = U[(n-2)&3].
 struct InstDesc {
+  InstState st;
+  double *u_new, *u_cur, *u_prev1, *u_prev2;
   int64_t n;               // nodes
-  int64_t stride;          // DIA value stride (n rounded up to 64)
+  int64_t ld;              // DIA: leading dimension of one stored diagonal
   int32_t blk0, nblk;      // this instance's workgroups in node-parallel launches
   int32_t model, bdf, prec, fmt;
-  int32_t ndiag, max_it, max_outer, n_stim;
+  int32_t nup, max_it, max_outer, n_stim;   // nup: stored (upper) DIA diagonals
   int32_t nvars, precond, block, pad_;
   double dt, inv_dt, rtol, inner_rtol, threshold;
   double mp[NPARAM];       // ionic model parameters
-  int32_t off[MAX_DIAG];   // DIA column offsets
-  // matrix, one shared pattern; values of A_sigma = (alpha_sigma/dt) M + K
+  int32_t off[MAX_UP];     // DIA: offsets >= 0 of the stored diagonals, off[0] = 0
+  // matrix, one shared pattern; values of A_sigma = (alpha_sigma/dt) M + K.
+  // DIA (symmetric): value of row i, stored diagonal d at val[d * ld + i] for
+  // i in [-guard, n); A(i, i + off[d]) = A(i + off[d], i) = val[d*ld + i], so
+  // the mirrored entry A(i, i - off[d]) is val[d*ld + i - off[d]].
   const int32_t* col;      // SELL column indices
   const int64_t* slice_ptr;// SELL slice offsets (elements), n_slices + 1
   const double* valA[3];
@@ -84,13 +98,12 @@ struct InstDesc {
   // activation tracking
   double *smax, *at, *tcross;
   StimGroup stim[MAX_STIM];
-  InstState* st;
   double* partial;         // per-workgroup partial sums, PART_DOUBLES * nblk
 };
 
 // Partial-sum layout inside InstDesc::partial, in units of nblk doubles:
-// residual kernel [4][nblk], SpMV [1][nblk], update (parity 0, 1) [2][2][nblk].
-constexpr int PART_RES = 0, PART_SPMV = 4, PART_UPD = 5, PART_DOUBLES = 9;
+// residual kernel [4][nblk], SpMV [1][nblk], update [2][nblk].
+constexpr int PART_RES = 0, PART_SPMV = 4, PART_UPD = 5, PART_DOUBLES = 7;
 
 struct BlockMap {
   int32_t inst;

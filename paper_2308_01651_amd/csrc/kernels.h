@@ -6,22 +6,26 @@
 
 namespace ep {
 
-// One launch over a block map: nblocks workgroups of WG threads, workgroup b
-// working on instance bmap[b].inst, node tile bmap[b].lblk.
+// One launch over a block map: nblocks workgroups, workgroup b working on
+// instance bmap[b].inst, node tile bmap[b].lblk.  single: the table holds one
+// instance and workgroup b works on its tile b (no block map read).
 struct Launch {
-  const InstDesc* insts;
+  InstDesc* insts;
   const BlockMap* bmap;
   int nblocks;
   hipStream_t stream;
+  bool single;
 };
 
 void launch_ionic(int model, bool mixed, const Launch& L);
 void launch_residual(bool mixed, bool with_rhs, const Launch& L);
 void launch_cg_spmv(bool mixed, const Launch& L);
 void launch_cg_update(bool mixed, const Launch& L);
+// one workgroup per instance listed in ids (device array of n_ids indices)
+void launch_cg_finalize(bool mixed, InstDesc* insts, const int32_t* ids, int n_ids, hipStream_t stream);
 void launch_activation(const Launch& L);
 // ids: device array of instance indices to advance by one step
-void launch_end_step(const InstDesc* insts, const int32_t* ids, int n_ids, hipStream_t stream);
+void launch_end_step(InstDesc* insts, const int32_t* ids, int n_ids, hipStream_t stream);
 void launch_fill(double* x, int64_t n, double v, hipStream_t stream);
 void launch_to_mv(void* dst, const double* u, int64_t n, double a, double b, bool f32, hipStream_t stream);
 

@@ -20,13 +20,12 @@
 // column-major inside the slice).  Vectors that SpMV gathers from carry zero
 // guard cells so DIA rows near the ends stay in bounds.
 //
-// Reductions are deterministic and need no cross-workgroup synchronization
-// inside a kernel: each workgroup writes its partial sum; the next kernel of
-// the sequence adds all partials of the instance in a fixed order in every
-// workgroup (so all workgroups take identical decisions), and workgroup 0
-// alone persists the scalars the following kernels need.  A batch of
-// instances reduces per instance, so each instance's result does not depend
-// on the batch.
+// Reductions are deterministic and need no synchronization between
+// workgroups inside a kernel: each workgroup writes its partial sum, and a
+// one-workgroup-per-instance finalize kernel adds the instance's partials in
+// a fixed order, decides convergence and forms the CG step lengths.  A batch
+// of instances reduces per instance, so each instance's result does not
+// depend on the batch.
 #include <hip/hip_runtime.h>
 
 #include "ep_device.h"
@@ -65,15 +64,15 @@ __device__ __forceinline__ void write_partials(double (&v)[NV], double* __restri
 }
 
 // Sum of the partials P[c * nblk + b], b < nblk, in a fixed order; every
-// thread of every workgroup obtains bitwise the same totals.
-template <int NV>
+// thread of the (NT-thread) workgroup obtains bitwise the same totals.
+template <int NT, int NV>
 __device__ __forceinline__ void reduce_partials(const double* __restrict__ P, int nblk, double (&out)[NV]) {
-  __shared__ double sh[WG / 64][NV];
+  __shared__ double sh[NT / 64][NV];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   double acc[NV];
 #pragma unroll
   for (int c = 0; c < NV; c++) acc[c] = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += WG) {
+  for (int b = threadIdx.x; b < nblk; b += NT) {
 #pragma unroll
     for (int c = 0; c < NV; c++) acc[c] += P[(int64_t)c * nblk + b];
   }
@@ -85,7 +84,12 @@ __device__ __forceinline__ void reduce_partials(const double* __restrict__ P, in
   }
   __syncthreads();
 #pragma unroll
-  for (int c = 0; c < NV; c++) out[c] = (sh[0][c] + sh[1][c]) + (sh[2][c] + sh[3][c]);
+  for (int c = 0; c < NV; c++) {
+    double a = 0.0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; w++) a += sh[w][c];
+    out[c] = a;
+  }
 }
 
 __device__ __forceinline__ int ld_flag(const int32_t* p) {
@@ -96,13 +100,21 @@ __device__ __forceinline__ int ld_flag(const int32_t* p) {
 // sparse row products
 // ---------------------------------------------------------------------------
 
-template <int ND, typename V, typename X, typename A>
+// Symmetric DIA: diagonal 0 plus, for each stored offset o > 0, the entry at
+// +o (stored at row i) and its mirror at -o (stored at row i - o).
+template <int NU, typename V, typename X, typename A>
 __device__ __forceinline__ A dia_row(const InstDesc& I, const V* __restrict__ val, const X* __restrict__ x,
-                                     int64_t i) {
-  A acc = A(0);
-  const int64_t st = I.stride;
+                                     int64_t i, int nu) {
+  const int64_t ld = I.ld;
+  A acc = (A)val[i] * (A)x[i];
+  const int n_up = NU > 0 ? NU : nu;
 #pragma unroll
-  for (int d = 0; d < ND; d++) acc += (A)val[d * st + i] * (A)x[i + I.off[d]];
+  for (int d = 1; d < (NU > 0 ? NU : MAX_UP); d++) {
+    if (NU == 0 && d >= n_up) break;
+    const int o = I.off[d];
+    acc += (A)val[d * ld + i] * (A)x[i + o];
+    acc += (A)val[d * ld + i - o] * (A)x[i - o];
+  }
   return acc;
 }
 
@@ -110,12 +122,9 @@ template <typename V, typename X, typename A>
 __device__ __forceinline__ A spmv_row(const InstDesc& I, const V* __restrict__ val, const X* __restrict__ x,
                                       int64_t i) {
   if (I.fmt == FMT_DIA) {
-    if (I.ndiag == 27) return dia_row<27, V, X, A>(I, val, x, i);
-    if (I.ndiag == 15) return dia_row<15, V, X, A>(I, val, x, i);
-    A acc = A(0);
-    const int64_t st = I.stride;
-    for (int d = 0; d < I.ndiag; d++) acc += (A)val[d * st + i] * (A)x[i + I.off[d]];
-    return acc;
+    if (I.nup == 14) return dia_row<14, V, X, A>(I, val, x, i, 14);   // 27-point (Q1 lattice)
+    if (I.nup == 8) return dia_row<8, V, X, A>(I, val, x, i, 8);      // 15-point (P1 Kuhn lattice)
+    return dia_row<0, V, X, A>(I, val, x, i, I.nup);
   }
   const int64_t slice = i >> 6;
   const int lane = (int)(i & 63);
@@ -136,7 +145,31 @@ __device__ __forceinline__ A spmv_row(const InstDesc& I, const V* __restrict__ v
 }
 
 // ---------------------------------------------------------------------------
-// ionic step + nodal RHS vector
+// instance lookup: a single instance (no block map) or a batch
+// ---------------------------------------------------------------------------
+
+// Single instance: workgroups are dispatched round-robin over the N_XCD dies;
+// tile = (b mod N_XCD) * per + b / N_XCD gives each die a contiguous range of
+// tiles, so stencil neighbours of a tile mostly sit in the same die's L2.
+// The launch has N_XCD * per workgroups; those past the last tile get
+// lblk = -1 and must leave at once.
+template <bool SINGLE>
+__device__ __forceinline__ InstDesc& instance(InstDesc* __restrict__ insts, const BlockMap* __restrict__ bmap,
+                                              int& lblk) {
+  if (SINGLE) {
+    InstDesc& I = insts[0];
+    const int per = (I.nblk + N_XCD - 1) / N_XCD;
+    const int t = (int)(blockIdx.x % N_XCD) * per + (int)(blockIdx.x / N_XCD);
+    lblk = t < I.nblk ? t : -1;
+    return I;
+  }
+  const BlockMap bm = bmap[blockIdx.x];
+  lblk = bm.lblk;
+  return insts[bm.inst];
+}
+
+// ---------------------------------------------------------------------------
+// ionic step + nodal RHS vector (one node per thread, TILE threads)
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ double stimulus_at(const InstDesc& I, int64_t k, int64_t i) {
@@ -152,26 +185,19 @@ __device__ __forceinline__ double stimulus_at(const InstDesc& I, int64_t k, int6
 }
 
 template <int MODEL, bool MIXED>
-__global__ __launch_bounds__(WG) void k_ionic(const InstDesc* __restrict__ insts,
-                                              const BlockMap* __restrict__ bmap) {
-  const BlockMap bm = bmap[blockIdx.x];
-  const InstDesc& I = insts[bm.inst];
-  const int64_t n = I.n;
-  const int64_t i = (int64_t)bm.lblk * WG + threadIdx.x;
-  if (i >= n) return;
-  const int64_t step = I.st->step;
+__device__ __forceinline__ void ionic_node(const InstDesc& I, int64_t n, int64_t step, int64_t i) {
   const int sig = min(I.bdf, (int)step + 1);
-  const double u0 = I.U[step & 3][i];
+  const double u0 = I.u_cur[i];
   double u_ext, u_bdf;
   if (sig == 1) {
     u_ext = u0;
     u_bdf = u0;
   } else if (sig == 2) {
-    const double u1 = I.U[(step - 1) & 3][i];
+    const double u1 = I.u_prev1[i];
     u_ext = 2.0 * u0 - u1;
     u_bdf = 2.0 * u0 - 0.5 * u1;
   } else {
-    const double u1 = I.U[(step - 1) & 3][i], u2 = I.U[(step - 2) & 3][i];
+    const double u1 = I.u_prev1[i], u2 = I.u_prev2[i];
     u_ext = 3.0 * u0 - 3.0 * u1 + u2;
     u_bdf = 3.0 * u0 - 1.5 * u1 + u2 * (1.0 / 3.0);
   }
@@ -227,7 +253,16 @@ __global__ __launch_bounds__(WG) void k_ionic(const InstDesc* __restrict__ insts
   }
   const double iapp = stimulus_at(I, step + 1, i);
   I.g[i] = u_bdf * I.inv_dt + iapp - iion;
-  I.U[(step + 1) & 3][i] = u_ext;
+  I.u_new[i] = u_ext;
+}
+
+template <int MODEL, bool MIXED, bool SINGLE>
+__global__ __launch_bounds__(TILE) void k_ionic(InstDesc* __restrict__ insts, const BlockMap* __restrict__ bmap) {
+  int lblk;
+  const InstDesc& I = instance<SINGLE>(insts, bmap, lblk);
+  if (lblk < 0) return;
+  const int64_t i = (int64_t)lblk * TILE + threadIdx.x;
+  if (i < I.n) ionic_node<MODEL, MIXED>(I, I.n, I.st.step, i);
 }
 
 // ---------------------------------------------------------------------------
@@ -235,20 +270,21 @@ __global__ __launch_bounds__(WG) void k_ionic(const InstDesc* __restrict__ insts
 // of a (inner) CG solve.  Partials: <r,z>, <r,r>, <b,b>, <r32,r32>.
 // ---------------------------------------------------------------------------
 
-template <bool MIXED, bool WITH_RHS>
-__global__ __launch_bounds__(WG) void k_residual(const InstDesc* __restrict__ insts,
-                                                 const BlockMap* __restrict__ bmap) {
-  const BlockMap bm = bmap[blockIdx.x];
-  const InstDesc& I = insts[bm.inst];
-  InstState* S = I.st;
-  if (!WITH_RHS && ld_flag(&S->conv)) return;
-  const int64_t i = (int64_t)bm.lblk * WG + threadIdx.x;
-  const bool act = i < I.n;
-  const int64_t step = S->step;
-  const int sig = min(I.bdf, (int)step + 1);
-  const double* __restrict__ x = I.U[(step + 1) & 3];
+template <bool MIXED, bool WITH_RHS, bool SINGLE>
+__global__ __launch_bounds__(WG) void k_residual(InstDesc* __restrict__ insts, const BlockMap* __restrict__ bmap) {
+  int lblk;
+  InstDesc& I = instance<SINGLE>(insts, bmap, lblk);
+  if (lblk < 0) return;
+  InstState& S = I.st;
+  if (!WITH_RHS && ld_flag(&S.conv)) return;
+  const int sig = min(I.bdf, (int)S.step + 1);
+  const double* __restrict__ x = I.u_new;
   double v[4] = {0.0, 0.0, 0.0, 0.0};
-  if (act) {
+  const int64_t i0 = (int64_t)lblk * TILE + threadIdx.x;
+#pragma unroll
+  for (int rw = 0; rw < RPT; rw++) {
+    const int64_t i = i0 + rw * WG;
+    if (i >= I.n) break;
     double bi;
     if (WITH_RHS) {
       bi = spmv_row<double, double, double>(I, I.valM, I.g, i);
@@ -261,189 +297,214 @@ __global__ __launch_bounds__(WG) void k_residual(const InstDesc* __restrict__ in
       const double zi = I.dinv[sig - 1][i] * ri;
       I.r[i] = ri;
       I.z[i] = zi;
-      v[0] = ri * zi;
-      v[1] = ri * ri;
+      v[0] += ri * zi;
+      v[1] += ri * ri;
     } else {
       const float r32 = (float)ri;
       const float z32 = I.dinv32[sig - 1][i] * r32;
       I.r32[i] = r32;
       I.z32[i] = z32;
-      v[0] = (double)r32 * (double)z32;
-      v[1] = ri * ri;
-      v[3] = (double)r32 * (double)r32;
+      v[0] += (double)r32 * (double)z32;
+      v[1] += ri * ri;
+      v[3] += (double)r32 * (double)r32;
     }
-    if (WITH_RHS) v[2] = bi * bi;
+    if (WITH_RHS) v[2] += bi * bi;
   }
-  write_partials<4>(v, I.partial + (int64_t)PART_RES * I.nblk, I.nblk, bm.lblk);
-  if (bm.lblk == 0 && threadIdx.x == 0) {
+  write_partials<4>(v, I.partial + (int64_t)PART_RES * I.nblk, I.nblk, lblk);
+  if (lblk == 0 && threadIdx.x == 0) {
     // a new (inner) solve starts at iteration 0
-    S->it = 0;
-    S->conv_in = 0;
+    S.it = 0;
+    S.conv_in = 0;
     if (WITH_RHS) {
-      S->conv = 0;
-      S->outer = 0;
+      S.conv = 0;
+      S.outer = 0;
+    } else {
+      S.outer += 1;   // a refinement sweep; read only by later kernels
     }
   }
 }
 
 // ---------------------------------------------------------------------------
-// CG iteration k, part 1: decide convergence from the previous kernel's
-// partials, then w = A z and <w, z>.
+// CG iteration, part 1: w = A z and the partials of <w, z>.
+// ---------------------------------------------------------------------------
+
+template <bool MIXED, bool SINGLE>
+__global__ __launch_bounds__(WG) void k_cg_spmv(InstDesc* __restrict__ insts, const BlockMap* __restrict__ bmap) {
+  int lblk;
+  InstDesc& I = instance<SINGLE>(insts, bmap, lblk);
+  if (lblk < 0) return;
+  InstState& S = I.st;
+  if (ld_flag(&S.conv) || ld_flag(&S.conv_in)) return;
+  const int sig = min(I.bdf, (int)S.step + 1);
+  const int64_t i0 = (int64_t)lblk * TILE + threadIdx.x;
+  double v[1] = {0.0};
+#pragma unroll
+  for (int rw = 0; rw < RPT; rw++) {
+    const int64_t i = i0 + rw * WG;
+    if (i >= I.n) break;
+    if (MIXED) {
+      const float wi = spmv_row<float, float, float>(I, I.valA32[sig - 1], I.z32, i);
+      I.w32[i] = wi;
+      v[0] += (double)wi * (double)I.z32[i];
+    } else {
+      const double wi = spmv_row<double, double, double>(I, I.valA[sig - 1], I.z, i);
+      I.w[i] = wi;
+      v[0] += wi * I.z[i];
+    }
+  }
+  write_partials<1>(v, I.partial + (int64_t)PART_SPMV * I.nblk, I.nblk, lblk);
+}
+
+// ---------------------------------------------------------------------------
+// CG iteration, part 2: one workgroup per instance.  Adds the partials of the
+// kernels since the last finalize (residual or update, then SpMV), decides
+// convergence of iteration k's residual and forms the Chronopoulos-Gear step
+// lengths beta_k = gamma_k / gamma_{k-1},
+// alpha_k = gamma_k / (delta_k - beta_k gamma_k / alpha_{k-1}).
 // ---------------------------------------------------------------------------
 
 template <bool MIXED>
-__global__ __launch_bounds__(WG) void k_cg_spmv(const InstDesc* __restrict__ insts,
-                                                const BlockMap* __restrict__ bmap) {
-  const BlockMap bm = bmap[blockIdx.x];
-  const InstDesc& I = insts[bm.inst];
-  InstState* S = I.st;
-  if (ld_flag(&S->conv) || ld_flag(&S->conv_in)) return;
-  const int k = S->it;
+__global__ __launch_bounds__(FIN_WG) void k_cg_finalize(InstDesc* __restrict__ insts,
+                                                        const int32_t* __restrict__ ids) {
+  InstDesc& I = insts[ids[blockIdx.x]];
+  InstState& S = I.st;
+  if (ld_flag(&S.conv) || ld_flag(&S.conv_in)) return;
   const int nblk = I.nblk;
-  const bool lead = bm.lblk == 0 && threadIdx.x == 0;
-  double gamma, rr;
+  const int k = S.it;
+  double t[4];
+  double dl[1];
+  reduce_partials<FIN_WG, 1>(I.partial + (int64_t)PART_SPMV * nblk, nblk, dl);
+  if (k == 0) {
+    reduce_partials<FIN_WG, 4>(I.partial + (int64_t)PART_RES * nblk, nblk, t);
+  } else {
+    double u[2];
+    reduce_partials<FIN_WG, 2>(I.partial + (int64_t)PART_UPD * nblk, nblk, u);
+    t[0] = u[0];
+    t[1] = u[1];
+    t[2] = t[3] = 0.0;
+  }
+  if (threadIdx.x != 0) return;
+  const double delta = dl[0];
+  const double gamma = t[0];
   bool done = false, stop_in = false;
   int flag = 0;
+  double rr;
   if (k == 0) {
-    double t[4];
-    reduce_partials<4>(I.partial + (int64_t)PART_RES * nblk, nblk, t);
-    gamma = t[0];
-    // first sweep of the step: the right-hand side norm fixes the tolerance
-    const bool first = MIXED ? (S->outer == 0) : true;
-    const double tol2 = first ? I.rtol * I.rtol * t[2] : S->tol2;
+    const bool first = MIXED ? (S.outer == 0) : true;
+    if (first) {
+      S.bb = t[2];
+      S.tol2 = I.rtol * I.rtol * t[2];
+    }
     const double rr_outer = t[1];
     rr = MIXED ? t[3] : t[1];
+    S.rr_outer = rr_outer;
+    S.rr_in0 = rr;
     if (!(rr_outer == rr_outer) || !(gamma == gamma)) {
       done = true;
       flag = F_NAN;
-    } else if (rr_outer <= tol2) {
+    } else if (rr_outer <= S.tol2) {
       done = true;
-    } else if (MIXED && S->outer >= I.max_outer) {
+    } else if (MIXED && S.outer > I.max_outer) {
       done = true;
       flag = F_NOCONV;
     }
-    if (lead) {
-      if (first) {
-        S->bb = t[2];
-        S->tol2 = tol2;
-      }
-      S->rr_outer = rr_outer;
-      S->rr_in0 = rr;
-      if (MIXED && !done) S->outer += 1;
-    }
   } else {
-    double t[2];
-    reduce_partials<2>(I.partial + (int64_t)(PART_UPD + 2 * (k & 1)) * nblk, nblk, t);
-    gamma = t[0];
     rr = t[1];
     if (!(rr == rr)) {
       done = true;
       flag = F_NAN;
     } else if (MIXED) {
-      stop_in = rr <= I.inner_rtol * I.inner_rtol * S->rr_in0 || k >= I.max_it;
-    } else if (rr <= S->tol2) {
+      stop_in = rr <= I.inner_rtol * I.inner_rtol * S.rr_in0 || k >= I.max_it;
+    } else if (rr <= S.tol2) {
       done = true;
     } else if (k >= I.max_it) {
       done = true;
       flag = F_NOCONV;
     }
   }
-  if (lead) {
-    S->it_spmv = k;
-    S->gamma[k & 1] = gamma;
-    S->rr = rr;
-    if (flag) S->flags |= flag;
-    if (done) __hip_atomic_store(&S->conv, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (stop_in) __hip_atomic_store(&S->conv_in, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  if (done || stop_in) return;   // uniform over the instance
-  const int64_t i = (int64_t)bm.lblk * WG + threadIdx.x;
-  const int sig = min(I.bdf, (int)S->step + 1);
-  double v[1] = {0.0};
-  if (i < I.n) {
-    if (MIXED) {
-      const float wi = spmv_row<float, float, float>(I, I.valA32[sig - 1], I.z32, i);
-      I.w32[i] = wi;
-      v[0] = (double)wi * (double)I.z32[i];
+  S.rr = rr;
+  if (!done && !stop_in) {
+    double beta, denom;
+    if (k == 0) {
+      beta = 0.0;
+      denom = delta;
     } else {
-      const double wi = spmv_row<double, double, double>(I, I.valA[sig - 1], I.z, i);
-      I.w[i] = wi;
-      v[0] = wi * I.z[i];
+      beta = gamma / S.gamma;
+      denom = delta - beta * gamma / S.alpha;
+    }
+    const double alpha = gamma / denom;
+    if (!(denom > 0.0) || !(alpha == alpha)) {
+      if (delta == delta) {
+        flag |= F_BREAKDOWN;
+        if (MIXED) stop_in = true;
+        else done = true;
+      } else {
+        flag |= F_NAN;
+        done = true;
+      }
+    } else {
+      S.gamma_prev = S.gamma;
+      S.alpha_prev = S.alpha;
+      S.gamma = gamma;
+      S.alpha = alpha;
+      S.beta = beta;
+      S.it_f = k;
     }
   }
-  write_partials<1>(v, I.partial + (int64_t)PART_SPMV * nblk, nblk, bm.lblk);
+  if (flag) S.flags |= flag;
+  if (done) S.conv = 1;
+  if (stop_in) S.conv_in = 1;
 }
 
 // ---------------------------------------------------------------------------
-// CG iteration k, part 2 (Chronopoulos-Gear): step lengths from <w,z> and the
-// stored gammas; p = z + beta p, s = w + beta s, x += alpha p, r -= alpha s,
-// z = P^{-1} r; partials <r, z>, <r, r>.
+// CG iteration, part 3: p = z + beta p, s = w + beta s, x += alpha p,
+// r -= alpha s, z = P^{-1} r; partials <r, z>, <r, r>.
 // ---------------------------------------------------------------------------
 
-template <bool MIXED>
-__global__ __launch_bounds__(WG) void k_cg_update(const InstDesc* __restrict__ insts,
-                                                  const BlockMap* __restrict__ bmap) {
-  const BlockMap bm = bmap[blockIdx.x];
-  const InstDesc& I = insts[bm.inst];
-  InstState* S = I.st;
-  if (ld_flag(&S->conv) || ld_flag(&S->conv_in)) return;
-  const int k = S->it_spmv;
-  const int nblk = I.nblk;
-  double t[1];
-  reduce_partials<1>(I.partial + (int64_t)PART_SPMV * nblk, nblk, t);
-  const double delta = t[0];
-  const double gamma = S->gamma[k & 1];
-  double beta, denom;
-  if (k == 0) {
-    beta = 0.0;
-    denom = delta;
-  } else {
-    beta = gamma / S->gamma[(k - 1) & 1];
-    denom = delta - beta * gamma / S->alpha[(k - 1) & 1];
-  }
-  const double alpha = gamma / denom;
-  const bool lead = bm.lblk == 0 && threadIdx.x == 0;
-  if (!(denom > 0.0) || !(alpha == alpha)) {
-    if (lead) {
-      S->flags |= (delta == delta) ? F_BREAKDOWN : F_NAN;
-      if (MIXED && (delta == delta)) __hip_atomic_store(&S->conv_in, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      else __hip_atomic_store(&S->conv, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    return;
-  }
-  const int64_t i = (int64_t)bm.lblk * WG + threadIdx.x;
-  const int sig = min(I.bdf, (int)S->step + 1);
-  double* __restrict__ x = I.U[(S->step + 1) & 3];
+template <bool MIXED, bool SINGLE>
+__global__ __launch_bounds__(WG) void k_cg_update(InstDesc* __restrict__ insts, const BlockMap* __restrict__ bmap) {
+  int lblk;
+  InstDesc& I = instance<SINGLE>(insts, bmap, lblk);
+  if (lblk < 0) return;
+  InstState& S = I.st;
+  if (ld_flag(&S.conv) || ld_flag(&S.conv_in)) return;
+  const int k = S.it_f;
+  const double alpha = S.alpha, beta = S.beta;
+  const int sig = min(I.bdf, (int)S.step + 1);
+  double* __restrict__ x = I.u_new;
+  const int64_t i0 = (int64_t)lblk * TILE + threadIdx.x;
   double v[2] = {0.0, 0.0};
-  if (i < I.n) {
+#pragma unroll
+  for (int rw = 0; rw < RPT; rw++) {
+    const int64_t i = i0 + rw * WG;
+    if (i >= I.n) break;
     if (MIXED) {
-      const float zi = I.z32[i], wi = I.w32[i];
       const float fb = (float)beta, fa = (float)alpha;
-      const float pi = (k == 0) ? zi : zi + fb * I.p32[i];
-      const float si = (k == 0) ? wi : wi + fb * I.s32[i];
-      x[i] += alpha * (double)pi;
-      const float ri = I.r32[i] - fa * si;
-      const float zn = I.dinv32[sig - 1][i] * ri;
-      I.p32[i] = pi; I.s32[i] = si; I.r32[i] = ri; I.z32[i] = zn;
-      v[0] = (double)ri * (double)zn;
-      v[1] = (double)ri * (double)ri;
+      const float z = I.z32[i], w = I.w32[i];
+      const float pn = (k == 0) ? z : z + fb * I.p32[i];
+      const float sn = (k == 0) ? w : w + fb * I.s32[i];
+      x[i] += alpha * (double)pn;
+      const float rn = I.r32[i] - fa * sn;
+      const float zn = I.dinv32[sig - 1][i] * rn;
+      I.p32[i] = pn; I.s32[i] = sn; I.r32[i] = rn; I.z32[i] = zn;
+      v[0] += (double)rn * (double)zn;
+      v[1] += (double)rn * (double)rn;
     } else {
-      const double zi = I.z[i], wi = I.w[i];
-      const double pi = (k == 0) ? zi : zi + beta * I.p[i];
-      const double si = (k == 0) ? wi : wi + beta * I.s[i];
-      x[i] += alpha * pi;
-      const double ri = I.r[i] - alpha * si;
-      const double zn = I.dinv[sig - 1][i] * ri;
-      I.p[i] = pi; I.s[i] = si; I.r[i] = ri; I.z[i] = zn;
-      v[0] = ri * zn;
-      v[1] = ri * ri;
+      const double z = I.z[i], w = I.w[i];
+      const double pn = (k == 0) ? z : z + beta * I.p[i];
+      const double sn = (k == 0) ? w : w + beta * I.s[i];
+      x[i] += alpha * pn;
+      const double rn = I.r[i] - alpha * sn;
+      const double zn = I.dinv[sig - 1][i] * rn;
+      I.p[i] = pn; I.s[i] = sn; I.r[i] = rn; I.z[i] = zn;
+      v[0] += rn * zn;
+      v[1] += rn * rn;
     }
   }
-  write_partials<2>(v, I.partial + (int64_t)(PART_UPD + 2 * ((k + 1) & 1)) * nblk, nblk, bm.lblk);
-  if (lead) {
-    S->alpha[k & 1] = alpha;
-    S->it = k + 1;
-    S->it_step += 1;
+  write_partials<2>(v, I.partial + (int64_t)PART_UPD * I.nblk, I.nblk, lblk);
+  if (lblk == 0 && threadIdx.x == 0) {
+    S.it = k + 1;
+    S.it_step += 1;
   }
 }
 
@@ -451,17 +512,16 @@ __global__ __launch_bounds__(WG) void k_cg_update(const InstDesc* __restrict__ i
 // activation time; end of step
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(WG) void k_activation(const InstDesc* __restrict__ insts,
-                                                   const BlockMap* __restrict__ bmap) {
-  const BlockMap bm = bmap[blockIdx.x];
-  const InstDesc& I = insts[bm.inst];
-  const int64_t i = (int64_t)bm.lblk * WG + threadIdx.x;
+template <bool SINGLE>
+__global__ __launch_bounds__(TILE) void k_activation(InstDesc* __restrict__ insts, const BlockMap* __restrict__ bmap) {
+  int lblk;
+  const InstDesc& I = instance<SINGLE>(insts, bmap, lblk);
+  if (lblk < 0) return;
+  const int64_t i = (int64_t)lblk * TILE + threadIdx.x;
   if (i >= I.n) return;
-  const int64_t step = I.st->step;
-  const double t = (double)(step + 1) * I.dt;
-  const double un = I.U[(step + 1) & 3][i];
-  const double uo = I.U[step & 3][i];
-  const double slope = (un - uo) * I.inv_dt;
+  const double t = (double)(I.st.step + 1) * I.dt;
+  const double un = I.u_new[i];
+  const double slope = (un - I.u_cur[i]) * I.inv_dt;
   if (slope > I.smax[i]) {
     I.smax[i] = slope;
     I.at[i] = t;
@@ -472,20 +532,27 @@ __global__ __launch_bounds__(WG) void k_activation(const InstDesc* __restrict__ 
   }
 }
 
-// One thread per instance: advance the step counter and the statistics.
-__global__ void k_end_step(const InstDesc* __restrict__ insts, const int32_t* __restrict__ ids, int n_ids) {
+// One thread per instance: advance the step counter, rotate the potential
+// history slots and update the statistics.
+__global__ void k_end_step(InstDesc* __restrict__ insts, const int32_t* __restrict__ ids, int n_ids) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n_ids) return;
-  InstState* S = insts[ids[t]].st;
-  S->step += 1;
-  S->it_last = S->it_step;
-  if (S->it_step > S->it_max) S->it_max = S->it_step;
-  S->it_total += S->it_step;
-  S->outer_total += S->outer;
-  S->it_step = 0;
-  S->it = 0;
-  S->conv = 0;
-  S->conv_in = 0;
+  InstDesc& I = insts[ids[t]];
+  InstState& S = I.st;
+  double* freed = I.u_prev2;
+  I.u_prev2 = I.u_prev1;
+  I.u_prev1 = I.u_cur;
+  I.u_cur = I.u_new;
+  I.u_new = freed;
+  S.step += 1;
+  S.it_last = S.it_step;
+  if (S.it_step > S.it_max) S.it_max = S.it_step;
+  S.it_total += S.it_step;
+  S.outer_total += S.outer;
+  S.it_step = 0;
+  S.it = 0;
+  S.conv = 0;
+  S.conv_in = 0;
 }
 
 // Potential in mV into a caller-owned device buffer: dst = a u + b.
@@ -508,53 +575,74 @@ __global__ void k_fill(double* __restrict__ x, int64_t n, double v) {
 // launchers
 // ---------------------------------------------------------------------------
 
+#define EP_LAUNCH2(KER, GRID, BLOCK, L)                                                     \
+  do {                                                                                    \
+    if ((L).single) hipLaunchKernelGGL((KER<true>), GRID, BLOCK, 0, (L).stream, (L).insts, (L).bmap); \
+    else hipLaunchKernelGGL((KER<false>), GRID, BLOCK, 0, (L).stream, (L).insts, (L).bmap);        \
+  } while (0)
+
+template <int M, bool MX>
+static void ionic_dispatch(const Launch& L) {
+  if (L.single) hipLaunchKernelGGL((k_ionic<M, MX, true>), dim3(L.nblocks), dim3(TILE), 0, L.stream, L.insts, L.bmap);
+  else hipLaunchKernelGGL((k_ionic<M, MX, false>), dim3(L.nblocks), dim3(TILE), 0, L.stream, L.insts, L.bmap);
+}
+
 void launch_ionic(int model, bool mixed, const Launch& L) {
   if (L.nblocks <= 0) return;
-  dim3 g(L.nblocks), b(WG);
-#define EP_ION(M)                                                                         \
-  if (mixed) hipLaunchKernelGGL((k_ionic<M, true>), g, b, 0, L.stream, L.insts, L.bmap); \
-  else hipLaunchKernelGGL((k_ionic<M, false>), g, b, 0, L.stream, L.insts, L.bmap);
   switch (model) {
-    case M_AP: EP_ION(M_AP); break;
-    case M_BO: EP_ION(M_BO); break;
-    case M_TTP06: EP_ION(M_TTP06); break;
-    default: EP_ION(M_PASSIVE); break;
+    case M_AP: mixed ? ionic_dispatch<M_AP, true>(L) : ionic_dispatch<M_AP, false>(L); break;
+    case M_BO: mixed ? ionic_dispatch<M_BO, true>(L) : ionic_dispatch<M_BO, false>(L); break;
+    case M_TTP06: mixed ? ionic_dispatch<M_TTP06, true>(L) : ionic_dispatch<M_TTP06, false>(L); break;
+    default: mixed ? ionic_dispatch<M_PASSIVE, true>(L) : ionic_dispatch<M_PASSIVE, false>(L); break;
   }
-#undef EP_ION
+}
+
+template <bool MX, bool RHS>
+static void residual_dispatch(const Launch& L) {
+  if (L.single) hipLaunchKernelGGL((k_residual<MX, RHS, true>), dim3(L.nblocks), dim3(WG), 0, L.stream, L.insts, L.bmap);
+  else hipLaunchKernelGGL((k_residual<MX, RHS, false>), dim3(L.nblocks), dim3(WG), 0, L.stream, L.insts, L.bmap);
 }
 
 void launch_residual(bool mixed, bool with_rhs, const Launch& L) {
   if (L.nblocks <= 0) return;
-  dim3 g(L.nblocks), b(WG);
-  if (mixed) {
-    if (with_rhs) hipLaunchKernelGGL((k_residual<true, true>), g, b, 0, L.stream, L.insts, L.bmap);
-    else hipLaunchKernelGGL((k_residual<true, false>), g, b, 0, L.stream, L.insts, L.bmap);
-  } else {
-    if (with_rhs) hipLaunchKernelGGL((k_residual<false, true>), g, b, 0, L.stream, L.insts, L.bmap);
-    else hipLaunchKernelGGL((k_residual<false, false>), g, b, 0, L.stream, L.insts, L.bmap);
-  }
+  if (mixed) with_rhs ? residual_dispatch<true, true>(L) : residual_dispatch<true, false>(L);
+  else with_rhs ? residual_dispatch<false, true>(L) : residual_dispatch<false, false>(L);
 }
 
 void launch_cg_spmv(bool mixed, const Launch& L) {
   if (L.nblocks <= 0) return;
-  dim3 g(L.nblocks), b(WG);
-  if (mixed) hipLaunchKernelGGL((k_cg_spmv<true>), g, b, 0, L.stream, L.insts, L.bmap);
-  else hipLaunchKernelGGL((k_cg_spmv<false>), g, b, 0, L.stream, L.insts, L.bmap);
+  if (mixed) {
+    if (L.single) hipLaunchKernelGGL((k_cg_spmv<true, true>), dim3(L.nblocks), dim3(WG), 0, L.stream, L.insts, L.bmap);
+    else hipLaunchKernelGGL((k_cg_spmv<true, false>), dim3(L.nblocks), dim3(WG), 0, L.stream, L.insts, L.bmap);
+  } else {
+    if (L.single) hipLaunchKernelGGL((k_cg_spmv<false, true>), dim3(L.nblocks), dim3(WG), 0, L.stream, L.insts, L.bmap);
+    else hipLaunchKernelGGL((k_cg_spmv<false, false>), dim3(L.nblocks), dim3(WG), 0, L.stream, L.insts, L.bmap);
+  }
+}
+
+void launch_cg_finalize(bool mixed, InstDesc* insts, const int32_t* ids, int n_ids, hipStream_t stream) {
+  if (n_ids <= 0) return;
+  if (mixed) hipLaunchKernelGGL((k_cg_finalize<true>), dim3(n_ids), dim3(FIN_WG), 0, stream, insts, ids);
+  else hipLaunchKernelGGL((k_cg_finalize<false>), dim3(n_ids), dim3(FIN_WG), 0, stream, insts, ids);
 }
 
 void launch_cg_update(bool mixed, const Launch& L) {
   if (L.nblocks <= 0) return;
-  dim3 g(L.nblocks), b(WG);
-  if (mixed) hipLaunchKernelGGL((k_cg_update<true>), g, b, 0, L.stream, L.insts, L.bmap);
-  else hipLaunchKernelGGL((k_cg_update<false>), g, b, 0, L.stream, L.insts, L.bmap);
+  if (mixed) {
+    if (L.single) hipLaunchKernelGGL((k_cg_update<true, true>), dim3(L.nblocks), dim3(WG), 0, L.stream, L.insts, L.bmap);
+    else hipLaunchKernelGGL((k_cg_update<true, false>), dim3(L.nblocks), dim3(WG), 0, L.stream, L.insts, L.bmap);
+  } else {
+    if (L.single) hipLaunchKernelGGL((k_cg_update<false, true>), dim3(L.nblocks), dim3(WG), 0, L.stream, L.insts, L.bmap);
+    else hipLaunchKernelGGL((k_cg_update<false, false>), dim3(L.nblocks), dim3(WG), 0, L.stream, L.insts, L.bmap);
+  }
 }
 
 void launch_activation(const Launch& L) {
   if (L.nblocks <= 0) return;
-  hipLaunchKernelGGL(k_activation, dim3(L.nblocks), dim3(WG), 0, L.stream, L.insts, L.bmap);
+  EP_LAUNCH2(k_activation, dim3(L.nblocks), dim3(TILE), L);
 }
 
-void launch_end_step(const InstDesc* insts, const int32_t* ids, int n_ids, hipStream_t stream) {
+void launch_end_step(InstDesc* insts, const int32_t* ids, int n_ids, hipStream_t stream) {
   if (n_ids <= 0) return;
   hipLaunchKernelGGL(k_end_step, dim3((unsigned)((n_ids + 63) / 64)), dim3(64), 0, stream, insts, ids, n_ids);
 }
