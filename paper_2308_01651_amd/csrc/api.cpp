@@ -528,6 +528,41 @@ ep_status finalize_impl(ep_sim* s) {
   return EP_OK;
 }
 
+// Host-side consistency check of a descriptor before kernels use it: every
+// array the configured path touches is present and the DIA geometry keeps all
+// shifted accesses inside the guard cells.  A failure is a library bug; it
+// is reported instead of launching.
+ep_status validate_desc(const InstDesc& D, int64_t guard) {
+  auto bad = [](const char* what) { return fail(EP_EHIP, std::string("internal descriptor check: ") + what); };
+  if (D.n <= 0 || D.nblk != (int)((D.n + TILE - 1) / TILE)) return bad("tile count");
+  if (D.bdf < 1 || D.bdf > 3) return bad("bdf");
+  if (!D.partial || !D.g || !D.b || !D.r || !D.z || !D.p || !D.s || !D.w) return bad("vectors");
+  for (int k = 0; k < RING; k++)
+    if (!D.U[k]) return bad("history ring");
+  if (!D.u_new || !D.u_cur || !D.u_prev1 || !D.u_prev2) return bad("history slots");
+  if (!D.valM || !D.smax || !D.at || !D.tcross) return bad("arrays");
+  for (int q = 0; q < D.bdf; q++) {
+    if (!D.valA[q] || !D.dinv[q]) return bad("operator values");
+    if (D.prec == P_MIXED && (!D.valA32[q] || !D.dinv32[q])) return bad("FP32 operator values");
+  }
+  if (D.prec == P_MIXED && (!D.r32 || !D.z32 || !D.p32 || !D.s32 || !D.w32 || !D.st32)) return bad("FP32 vectors");
+  if (D.nvars > 0 && !D.st64 && !D.st32) return bad("ionic state");
+  if (D.fmt == FMT_DIA) {
+    if (D.nup < 1 || D.nup > MAX_UP || D.off[0] != 0) return bad("DIA diagonals");
+    for (int d = 1; d < D.nup; d++)
+      if (D.off[d] <= D.off[d - 1] || D.off[d] > guard) return bad("DIA offsets exceed the guard");
+    if (D.ld < ((D.n + 63) / 64) * 64 + guard) return bad("DIA leading dimension");
+  } else if (D.fmt == FMT_SELL) {
+    if (!D.col || !D.slice_ptr) return bad("SELL arrays");
+  } else {
+    return bad("matrix format");
+  }
+  if (D.n_stim < 0 || D.n_stim > MAX_STIM) return bad("stimuli");
+  for (int k = 0; k < D.n_stim; k++)
+    if (!D.stim[k].prof) return bad("stimulus profile");
+  return EP_OK;
+}
+
 Launch launch_of(ep_sim* s) { return Launch{s->d_desc, s->d_bmap, s->nblocks, s->stream, true}; }
 
 hipEvent_t kt_event(ep_sim* s) {
@@ -885,6 +920,10 @@ ep_status ep_sim_set_state(ep_sim* s, const double* u, const double* w, const do
   D.u_cur = D.U[step_index & 3];
   D.u_prev1 = D.U[(step_index - 1) & 3];
   D.u_prev2 = D.U[(step_index - 2) & 3];
+  {
+    ep_status vr = validate_desc(D, s->guard);
+    if (vr != EP_OK) return vr;
+  }
   EP_HIP(hipMemcpyAsync(s->d_desc, &D, sizeof(InstDesc), hipMemcpyHostToDevice, st));
   EP_HIP(hipStreamSynchronize(st));
   return EP_OK;
