@@ -214,6 +214,34 @@ int ep_sim_n_vars(const ep_sim* sim);
 
 void ep_sim_destroy(ep_sim* sim);
 
+/* ---- batched / serving pool (many uneven simulations, one launch per phase) */
+
+/* Pool on `device` with an HBM budget in bytes and at most max_slots
+ * resident simulations, all of one precision. */
+ep_status ep_pool_create(int device, void* hip_stream, size_t hbm_budget_bytes, int max_slots,
+                         int precision, ep_pool** out);
+
+/* Admit a configured, NOT yet finalized sim: the pool finalizes it if its
+ * device footprint fits the remaining budget and a slot is free, else returns
+ * EP_EAGAIN without allocating.  n_steps_total: steps to run before the slot
+ * counts as done.  The pool does not take ownership: destroy the sim after
+ * releasing it. */
+ep_status ep_pool_admit(ep_pool* pool, ep_sim* sim, int64_t n_steps_total, int* slot);
+
+/* Advance every active, unfinished slot by up to n_steps steps together. */
+ep_status ep_pool_step(ep_pool* pool, int n_steps);
+
+/* Slots that reached their step count: writes up to cap slot ids. */
+ep_status ep_pool_poll(ep_pool* pool, int* done_slots, int cap, int* n_done);
+
+/* Remove a slot from the pool and return its sim (results stay readable). */
+ep_status ep_pool_release(ep_pool* pool, int slot, ep_sim** sim_out);
+/* (returns the slot's final status: EP_OK, EP_ENAN or EP_ENOCONV; the sim is
+ * released either way) */
+
+ep_status ep_pool_get_info(ep_pool* pool, int* n_active, size_t* bytes_in_use);
+void ep_pool_destroy(ep_pool* pool);
+
 /* Estimated device bytes ep_sim_finalize would allocate (sim configured, not
  * finalized); used for admission control. */
 ep_status ep_sim_device_bytes_estimate(ep_sim* sim, size_t* bytes);

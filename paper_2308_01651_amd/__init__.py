@@ -197,6 +197,62 @@ class Simulation:
         return sim
 
 
+class Pool:
+    """Batched / serving container of resident simulations (wraps ep_pool)."""
+
+    def __init__(self, hbm_budget_bytes: int, max_slots: int, precision: int = EP_FP64, device: int = 0,
+                 stream=None):
+        h = C.c_void_p()
+        check(lib.ep_pool_create(int(device), C.c_void_p(stream) if stream else None, int(hbm_budget_bytes),
+                                 int(max_slots), int(precision), C.byref(h)), "ep_pool_create")
+        self._h = h
+        self.sims = {}
+
+    def admit(self, sim: "Simulation", n_steps_total: int):
+        """Slot id, or None when the pool is full (EP_EAGAIN)."""
+        slot = C.c_int32()
+        st = check(lib.ep_pool_admit(self._h, sim._h, int(n_steps_total), C.byref(slot)), "ep_pool_admit",
+                   allow=(_lib.EP_EAGAIN,))
+        if st == _lib.EP_EAGAIN:
+            return None
+        self.sims[slot.value] = sim
+        return slot.value
+
+    def step(self, n_steps: int = 1):
+        check(lib.ep_pool_step(self._h, int(n_steps)), "ep_pool_step")
+
+    def poll(self):
+        cap = max(1, len(self.sims))
+        buf = np.zeros(cap, np.int32)
+        n = C.c_int32()
+        check(lib.ep_pool_poll(self._h, buf.ctypes.data_as(_lib.PI32), cap, C.byref(n)), "ep_pool_poll")
+        return [int(x) for x in buf[: n.value]]
+
+    def release(self, slot: int, allow_error: bool = False):
+        """Remove a slot; returns (sim, status)."""
+        out = C.c_void_p()
+        st = check(lib.ep_pool_release(self._h, int(slot), C.byref(out)), "ep_pool_release",
+                   allow=(_lib.EP_ENAN, _lib.EP_ENOCONV) if allow_error else ())
+        return self.sims.pop(slot), st
+
+    def info(self):
+        a = C.c_int32()
+        b = C.c_size_t()
+        check(lib.ep_pool_get_info(self._h, C.byref(a), C.byref(b)), "ep_pool_get_info")
+        return {"active": a.value, "bytes_in_use": b.value}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.ep_pool_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def assemble_csr(elem, xyz, conn, fibers=None, sigma=(0.17, 0.019, 0.019), chi=140.0, cm=0.01):
     """The library's host-side FE assembly (ep_assemble_csr): (rowptr, col, valM, valK)."""
     xyz = _f64(xyz)

@@ -74,6 +74,12 @@ _SIGS = {
     "ep_sim_set_state": [P, PD, PD, PD, C.c_int64],
     "ep_sim_get_state": [P, PD, PD, PD],
     "ep_sim_device_bytes_estimate": [P, C.POINTER(C.c_size_t)],
+    "ep_pool_create": [C.c_int, P, C.c_size_t, C.c_int, C.c_int, PP],
+    "ep_pool_admit": [P, P, C.c_int64, PI32],
+    "ep_pool_step": [P, C.c_int],
+    "ep_pool_poll": [P, PI32, C.c_int, PI32],
+    "ep_pool_release": [P, C.c_int, PP],
+    "ep_pool_get_info": [P, PI32, C.POINTER(C.c_size_t)],
     "ep_assemble_csr": [C.c_int, C.c_int64, PD, C.c_int64, PI32, PD, PD, PD, C.c_double, C.c_double,
                         C.c_double, C.c_double, C.c_double, PI64, PI64, PI32, PD, PD],
 }
@@ -84,6 +90,8 @@ for _name, _args in _SIGS.items():
 
 lib.ep_sim_destroy.argtypes = [P]
 lib.ep_sim_destroy.restype = None
+lib.ep_pool_destroy.argtypes = [P]
+lib.ep_pool_destroy.restype = None
 lib.ep_sim_n_vars.argtypes = [P]
 lib.ep_sim_n_vars.restype = C.c_int
 lib.ep_last_error.argtypes = []
@@ -100,4 +108,5 @@ def check(status: int, where: str, allow=()):
 
 def exported_names():
     """Names the header declares; used by the symbol-export test."""
-    return sorted(_SIGS) + ["ep_sim_destroy", "ep_sim_n_vars", "ep_last_error", "ep_version"]
+    return sorted(_SIGS) + ["ep_sim_destroy", "ep_pool_destroy", "ep_sim_n_vars", "ep_last_error",
+                            "ep_version"]

@@ -166,6 +166,9 @@ struct ep_sim {
   double kt_ms[7] = {0, 0, 0, 0, 0, 0, 0};
   int64_t kt_count[7] = {0, 0, 0, 0, 0, 0, 0};
   int32_t* d_ids = nullptr;  // device list {0}: the instance advanced by k_end_step
+  InstDesc* d_desc_own = nullptr;  // the sim's own descriptor (d_desc points into a pool table while pooled)
+  hipStream_t stream_own = nullptr;
+  int pool_slot = -1;
   int it_pred = 8;      // CG iterations launched before the first convergence check
   int in_pred = 8;      // inner iterations per refinement sweep (mixed)
   int sticky = EP_OK;
@@ -510,6 +513,7 @@ ep_status finalize_impl(ep_sim* s) {
   for (int b = 0; b < ntiles; b++) bm[b] = {0, b};
   EP_HIP(upload(m, &s->d_bmap, bm.data(), bm.size(), st));
   EP_HIP(m.alloc((void**)&s->d_desc, sizeof(InstDesc)));
+  s->d_desc_own = s->d_desc;
   // the state lives inside the device descriptor (its first member)
   s->d_st = reinterpret_cast<InstState*>(reinterpret_cast<char*>(s->d_desc) + offsetof(InstDesc, st));
   EP_HIP(hipStreamSynchronize(st));
@@ -1086,6 +1090,327 @@ ep_status ep_assemble_csr(int elem, int64_t n_nodes, const double* xyz, int64_t 
   std::copy(A.valM.begin(), A.valM.end(), valM);
   std::copy(A.valK.begin(), A.valK.end(), valK);
   return EP_OK;
+}
+
+
+}  // extern "C"
+
+// ============================================================================
+// Batched / serving pool.  Resident simulations share one descriptor table;
+// every phase of a step is one launch over all active instances (per ionic
+// model for the ionic kernel), each instance converging on its own.
+// ============================================================================
+
+struct ep_pool {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  size_t budget = 0, in_use = 0;
+  int max_slots = 0;
+  int prec = EP_FP64;
+  struct Slot {
+    ep_sim* sim = nullptr;
+    int64_t target = 0;
+    int64_t done_steps = 0;
+    bool done = false;
+    int status = EP_OK;
+  };
+  std::vector<Slot> slots;
+  InstDesc* d_table = nullptr;
+  InstState* h_states = nullptr;  // pinned, one per slot
+  DevMem mem;                     // table
+  DevMem maps;                    // launch tables, rebuilt on membership change
+  bool dirty = true;
+  std::vector<int> active;
+  BlockMap* d_all = nullptr;
+  int nb_all = 0;
+  BlockMap* d_model[4] = {nullptr, nullptr, nullptr, nullptr};
+  int nb_model[4] = {0, 0, 0, 0};
+  int32_t* d_ids = nullptr;
+  int it_pred = 8, in_pred = 8;
+};
+
+namespace {
+
+// Workgroup -> (instance, tile) list in XCD order: each die receives a
+// contiguous run of the list; padding entries carry lblk = -1.
+std::vector<BlockMap> xcd_order(const std::vector<BlockMap>& items) {
+  const int T = (int)items.size();
+  const int per = (T + N_XCD - 1) / N_XCD;
+  std::vector<BlockMap> out((size_t)per * N_XCD, BlockMap{items.empty() ? 0 : items[0].inst, -1});
+  for (int b = 0; b < per * N_XCD; b++) {
+    const int t = (b % N_XCD) * per + b / N_XCD;
+    if (t < T) out[b] = items[t];
+  }
+  return out;
+}
+
+ep_status pool_rebuild(ep_pool* P) {
+  // kernels of the previous step may still read the old tables
+  EP_HIP(hipStreamSynchronize(P->stream));
+  P->maps.release();
+  P->active.clear();
+  for (int k = 0; k < P->max_slots; k++)
+    if (P->slots[k].sim && !P->slots[k].done) P->active.push_back(k);
+  std::vector<BlockMap> all, per_model[4];
+  for (int k : P->active) {
+    const ep_sim* s = P->slots[k].sim;
+    const int nt = s->desc.nblk;
+    for (int t = 0; t < nt; t++) {
+      all.push_back(BlockMap{k, t});
+      per_model[s->model].push_back(BlockMap{k, t});
+    }
+  }
+  auto put = [&](const std::vector<BlockMap>& v, BlockMap** d, int* nb) -> hipError_t {
+    *nb = 0;
+    *d = nullptr;
+    if (v.empty()) return hipSuccess;
+    std::vector<BlockMap> o = xcd_order(v);
+    *nb = (int)o.size();
+    hipError_t e = P->maps.alloc((void**)d, o.size() * sizeof(BlockMap));
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(*d, o.data(), o.size() * sizeof(BlockMap), hipMemcpyHostToDevice, P->stream);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(P->stream);
+  };
+  EP_HIP(put(all, &P->d_all, &P->nb_all));
+  for (int m = 0; m < 4; m++) EP_HIP(put(per_model[m], &P->d_model[m], &P->nb_model[m]));
+  std::vector<int32_t> ids(P->active.begin(), P->active.end());
+  if (!ids.empty()) {
+    EP_HIP(P->maps.alloc((void**)&P->d_ids, ids.size() * sizeof(int32_t)));
+    EP_HIP(hipMemcpyAsync(P->d_ids, ids.data(), ids.size() * sizeof(int32_t), hipMemcpyHostToDevice, P->stream));
+    EP_HIP(hipStreamSynchronize(P->stream));
+  }
+  P->dirty = false;
+  return EP_OK;
+}
+
+ep_status pool_pull(ep_pool* P) {
+  EP_HIP(hipMemcpy2DAsync(P->h_states, sizeof(InstState), P->d_table, sizeof(InstDesc), sizeof(InstState),
+                          (size_t)P->max_slots, hipMemcpyDeviceToHost, P->stream));
+  EP_HIP(hipStreamSynchronize(P->stream));
+  return EP_OK;
+}
+
+bool pool_all_conv(ep_pool* P) {
+  for (int k : P->active)
+    if (!P->h_states[k].conv) return false;
+  return true;
+}
+
+int pool_iters(ep_pool* P) {
+  int m = 0;
+  for (int k : P->active) m = std::max(m, P->h_states[k].it_step);
+  return m;
+}
+
+ep_status pool_step_once(ep_pool* P) {
+  const bool mixed = P->prec == EP_MIXED;
+  const int ni = (int)P->active.size();
+  const Launch L{P->d_table, P->d_all, P->nb_all, P->stream, false};
+  auto fin = [&] { launch_cg_finalize(mixed, P->d_table, P->d_ids, ni, P->stream); };
+  auto round = [&] {
+    launch_cg_update(mixed, L);
+    launch_cg_spmv(mixed, L);
+    fin();
+  };
+  for (int m = 0; m < 4; m++)
+    if (P->nb_model[m] > 0) launch_ionic(m, mixed, Launch{P->d_table, P->d_model[m], P->nb_model[m], P->stream, false});
+  launch_residual(mixed, true, L);
+  launch_cg_spmv(mixed, L);
+  fin();
+  int chunk = std::max(1, mixed ? P->in_pred : P->it_pred);
+  for (int rounds = 0;; rounds++) {
+    for (int c = 0; c < chunk; c++) round();
+    if (mixed) {
+      launch_residual(true, false, L);
+      launch_cg_spmv(true, L);
+      fin();
+    }
+    ep_status rc = pool_pull(P);
+    if (rc != EP_OK) return rc;
+    if (pool_all_conv(P)) break;
+    if (rounds > 20000) return fail(EP_EHIP, "pool solver control lost (no convergence flag)");
+    if (!mixed) chunk = 2;
+  }
+  if (!mixed) P->it_pred = std::max(1, pool_iters(P));
+  launch_activation(L);
+  launch_end_step(P->d_table, P->d_ids, ni, P->stream);
+  EP_HIP(hipGetLastError());
+  bool changed = false;
+  for (int k : P->active) {
+    ep_pool::Slot& sl = P->slots[k];
+    sl.done_steps += 1;
+    const int fl = P->h_states[k].flags;
+    if (fl & F_NAN) {
+      sl.status = EP_ENAN;
+      sl.done = true;
+      changed = true;
+    } else if (fl & (F_NOCONV | F_BREAKDOWN)) {
+      sl.status = EP_ENOCONV;
+    }
+    if (sl.done_steps >= sl.target && !sl.done) {
+      sl.done = true;
+      changed = true;
+    }
+  }
+  if (changed) P->dirty = true;
+  return EP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ep_status ep_pool_create(int device, void* hip_stream, size_t hbm_budget_bytes, int max_slots, int precision,
+                         ep_pool** out) {
+  if (!out || max_slots < 1 || max_slots > 4096 || (precision != EP_FP64 && precision != EP_MIXED))
+    return fail(EP_EINVAL, "bad pool arguments");
+  *out = nullptr;
+  int count = 0;
+  EP_HIP(hipGetDeviceCount(&count));
+  if (device < 0 || device >= count) return fail(EP_EINVAL, "no such device");
+  EP_HIP(hipSetDevice(device));
+  ep_pool* P = new ep_pool();
+  P->device = device;
+  P->budget = hbm_budget_bytes;
+  P->max_slots = max_slots;
+  P->prec = precision;
+  P->slots.resize(max_slots);
+  if (hip_stream) {
+    P->stream = (hipStream_t)hip_stream;
+  } else if (hipStreamCreateWithFlags(&P->stream, hipStreamNonBlocking) != hipSuccess) {
+    delete P;
+    return fail(EP_EHIP, "hipStreamCreate failed");
+  } else {
+    P->own_stream = true;
+  }
+  if (P->mem.alloc((void**)&P->d_table, (size_t)max_slots * sizeof(InstDesc)) != hipSuccess ||
+      hipHostMalloc((void**)&P->h_states, (size_t)max_slots * sizeof(InstState), hipHostMallocDefault) != hipSuccess) {
+    P->mem.release();
+    if (P->own_stream) (void)hipStreamDestroy(P->stream);
+    delete P;
+    return fail(EP_ENOMEM, "pool table allocation failed");
+  }
+  std::memset(P->h_states, 0, (size_t)max_slots * sizeof(InstState));
+  *out = P;
+  return EP_OK;
+}
+
+ep_status ep_pool_admit(ep_pool* P, ep_sim* s, int64_t n_steps_total, int* slot) {
+  if (!P || !s || !slot || n_steps_total < 1) return fail(EP_EINVAL, "bad admit arguments");
+  if (s->finalized || s->in_pool) return fail(EP_ESTATE, "admit a configured, not yet finalized sim");
+  if (s->prec != P->prec) return fail(EP_EINVAL, "sim precision differs from the pool's");
+  if (s->device != P->device) return fail(EP_EINVAL, "sim device differs from the pool's");
+  int free_slot = -1;
+  for (int k = 0; k < P->max_slots; k++)
+    if (!P->slots[k].sim) {
+      free_slot = k;
+      break;
+    }
+  const size_t need = estimate_bytes(s);
+  if (free_slot < 0 || P->in_use + need > P->budget) return fail(EP_EAGAIN, "pool full (slots or HBM budget)");
+  EP_HIP(hipSetDevice(P->device));
+  // the sim runs on the pool's stream while pooled
+  s->stream_own = s->stream;
+  s->stream = P->stream;
+  ep_status rc = finalize_impl(s);
+  if (rc != EP_OK) {
+    if (!s->finalized) s->mem.release();
+    s->stream = s->stream_own;
+    return rc;
+  }
+  InstDesc* dst = P->d_table + free_slot;
+  EP_HIP(hipMemcpyAsync(dst, s->d_desc_own, sizeof(InstDesc), hipMemcpyDeviceToDevice, P->stream));
+  EP_HIP(hipStreamSynchronize(P->stream));
+  s->d_desc = dst;
+  s->d_st = reinterpret_cast<InstState*>(reinterpret_cast<char*>(dst) + offsetof(InstDesc, st));
+  s->in_pool = true;
+  s->pool_slot = free_slot;
+  ep_pool::Slot& sl = P->slots[free_slot];
+  sl.sim = s;
+  sl.target = n_steps_total;
+  sl.done_steps = 0;
+  sl.done = false;
+  sl.status = EP_OK;
+  P->in_use += std::max(need, s->mem.bytes);
+  P->dirty = true;
+  *slot = free_slot;
+  return EP_OK;
+}
+
+ep_status ep_pool_step(ep_pool* P, int n_steps) {
+  if (!P || n_steps < 0) return fail(EP_EINVAL, "bad pool step arguments");
+  EP_HIP(hipSetDevice(P->device));
+  for (int k = 0; k < n_steps; k++) {
+    if (P->dirty) {
+      ep_status rc = pool_rebuild(P);
+      if (rc != EP_OK) return rc;
+    }
+    if (P->active.empty()) break;
+    ep_status rc = pool_step_once(P);
+    if (rc != EP_OK) return rc;
+  }
+  return EP_OK;
+}
+
+ep_status ep_pool_poll(ep_pool* P, int* done_slots, int cap, int* n_done) {
+  if (!P || !n_done || (cap > 0 && !done_slots)) return fail(EP_EINVAL, "bad poll arguments");
+  int c = 0;
+  for (int k = 0; k < P->max_slots; k++)
+    if (P->slots[k].sim && P->slots[k].done) {
+      if (c < cap) done_slots[c] = k;
+      c++;
+    }
+  *n_done = std::min(c, std::max(cap, 0));
+  return EP_OK;
+}
+
+ep_status ep_pool_release(ep_pool* P, int slot, ep_sim** sim_out) {
+  if (!P || slot < 0 || slot >= P->max_slots || !P->slots[slot].sim) return fail(EP_EINVAL, "no sim in that slot");
+  ep_sim* s = P->slots[slot].sim;
+  EP_HIP(hipStreamSynchronize(P->stream));
+  EP_HIP(hipMemcpyAsync(s->d_desc_own, P->d_table + slot, sizeof(InstDesc), hipMemcpyDeviceToDevice, P->stream));
+  EP_HIP(hipStreamSynchronize(P->stream));
+  s->d_desc = s->d_desc_own;
+  s->d_st = reinterpret_cast<InstState*>(reinterpret_cast<char*>(s->d_desc) + offsetof(InstDesc, st));
+  s->stream = s->stream_own;
+  s->in_pool = false;
+  s->pool_slot = -1;
+  const size_t need = estimate_bytes(s);
+  P->in_use -= std::min(P->in_use, std::max(need, s->mem.bytes));
+  const int status = P->slots[slot].status;
+  P->slots[slot] = ep_pool::Slot{};
+  P->dirty = true;
+  if (sim_out) *sim_out = s;
+  if (status != EP_OK) {
+    g_err = status == EP_ENAN ? "the simulation produced NaN" : "a linear solve did not converge";
+    return (ep_status)status;
+  }
+  return EP_OK;
+}
+
+ep_status ep_pool_get_info(ep_pool* P, int* n_active, size_t* bytes_in_use) {
+  if (!P) return fail(EP_EINVAL, "null pool");
+  int a = 0;
+  for (auto& sl : P->slots)
+    if (sl.sim && !sl.done) a++;
+  if (n_active) *n_active = a;
+  if (bytes_in_use) *bytes_in_use = P->in_use;
+  return EP_OK;
+}
+
+void ep_pool_destroy(ep_pool* P) {
+  if (!P) return;
+  (void)hipSetDevice(P->device);
+  (void)hipStreamSynchronize(P->stream);
+  for (int k = 0; k < P->max_slots; k++)
+    if (P->slots[k].sim) (void)ep_pool_release(P, k, nullptr);
+  P->maps.release();
+  P->mem.release();
+  if (P->h_states) (void)hipHostFree(P->h_states);
+  if (P->own_stream) (void)hipStreamDestroy(P->stream);
+  delete P;
 }
 
 }  // extern "C"

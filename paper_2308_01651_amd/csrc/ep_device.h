@@ -56,10 +56,12 @@ struct InstState {
   int32_t it_step;     // CG iterations in the current step (all sweeps)
   int32_t it_last;     // CG iterations of the last finished step
   int32_t it_max;      // largest per-step CG count so far
-  int32_t pad_;
+  int32_t restart;     // 1: a refinement residual restarted the inner solve
   int64_t it_total;    // CG iterations over all steps
   int64_t outer_total;
-  double gamma, gamma_prev, alpha, alpha_prev, beta;
+  // step lengths of the current iteration (finalize) and of the previous
+  // one (shifted by the update kernel), so that the finalize is idempotent
+  double gamma_cur, alpha_cur, beta, gamma_prev, alpha_prev;
   double rr, bb, tol2, rr_in0, rr_outer;
 };
 // Per-instance descriptor.  The mutable state sits inside it (first member),

@@ -276,7 +276,8 @@ __global__ __launch_bounds__(WG) void k_residual(InstDesc* __restrict__ insts, c
   InstDesc& I = instance<SINGLE>(insts, bmap, lblk);
   if (lblk < 0) return;
   InstState& S = I.st;
-  if (!WITH_RHS && ld_flag(&S.conv)) return;
+  // a refinement sweep only restarts an instance whose inner solve is done
+  if (!WITH_RHS && (ld_flag(&S.conv) || !ld_flag(&S.conv_in))) return;
   const int sig = min(I.bdf, (int)S.step + 1);
   const double* __restrict__ x = I.u_new;
   double v[4] = {0.0, 0.0, 0.0, 0.0};
@@ -312,14 +313,17 @@ __global__ __launch_bounds__(WG) void k_residual(InstDesc* __restrict__ insts, c
   }
   write_partials<4>(v, I.partial + (int64_t)PART_RES * I.nblk, I.nblk, lblk);
   if (lblk == 0 && threadIdx.x == 0) {
-    // a new (inner) solve starts at iteration 0
+    // a new (inner) solve starts at iteration 0; fields read by no workgroup
+    // of this kernel (conv_in is cleared by the finalize that follows)
     S.it = 0;
-    S.conv_in = 0;
     if (WITH_RHS) {
       S.conv = 0;
+      S.conv_in = 0;
       S.outer = 0;
+      S.restart = 0;
     } else {
-      S.outer += 1;   // a refinement sweep; read only by later kernels
+      S.outer += 1;
+      S.restart = 1;
     }
   }
 }
@@ -334,7 +338,7 @@ __global__ __launch_bounds__(WG) void k_cg_spmv(InstDesc* __restrict__ insts, co
   InstDesc& I = instance<SINGLE>(insts, bmap, lblk);
   if (lblk < 0) return;
   InstState& S = I.st;
-  if (ld_flag(&S.conv) || ld_flag(&S.conv_in)) return;
+  if (ld_flag(&S.conv) || (ld_flag(&S.conv_in) && !ld_flag(&S.restart))) return;
   const int sig = min(I.bdf, (int)S.step + 1);
   const int64_t i0 = (int64_t)lblk * TILE + threadIdx.x;
   double v[1] = {0.0};
@@ -368,7 +372,7 @@ __global__ __launch_bounds__(FIN_WG) void k_cg_finalize(InstDesc* __restrict__ i
                                                         const int32_t* __restrict__ ids) {
   InstDesc& I = insts[ids[blockIdx.x]];
   InstState& S = I.st;
-  if (ld_flag(&S.conv) || ld_flag(&S.conv_in)) return;
+  if (ld_flag(&S.conv) || (ld_flag(&S.conv_in) && !ld_flag(&S.restart))) return;
   const int nblk = I.nblk;
   const int k = S.it;
   double t[4];
@@ -384,6 +388,8 @@ __global__ __launch_bounds__(FIN_WG) void k_cg_finalize(InstDesc* __restrict__ i
     t[2] = t[3] = 0.0;
   }
   if (threadIdx.x != 0) return;
+  S.restart = 0;
+  S.conv_in = 0;
   const double delta = dl[0];
   const double gamma = t[0];
   bool done = false, stop_in = false;
@@ -429,8 +435,8 @@ __global__ __launch_bounds__(FIN_WG) void k_cg_finalize(InstDesc* __restrict__ i
       beta = 0.0;
       denom = delta;
     } else {
-      beta = gamma / S.gamma;
-      denom = delta - beta * gamma / S.alpha;
+      beta = gamma / S.gamma_prev;
+      denom = delta - beta * gamma / S.alpha_prev;
     }
     const double alpha = gamma / denom;
     if (!(denom > 0.0) || !(alpha == alpha)) {
@@ -443,10 +449,8 @@ __global__ __launch_bounds__(FIN_WG) void k_cg_finalize(InstDesc* __restrict__ i
         done = true;
       }
     } else {
-      S.gamma_prev = S.gamma;
-      S.alpha_prev = S.alpha;
-      S.gamma = gamma;
-      S.alpha = alpha;
+      S.gamma_cur = gamma;
+      S.alpha_cur = alpha;
       S.beta = beta;
       S.it_f = k;
     }
@@ -467,9 +471,9 @@ __global__ __launch_bounds__(WG) void k_cg_update(InstDesc* __restrict__ insts, 
   InstDesc& I = instance<SINGLE>(insts, bmap, lblk);
   if (lblk < 0) return;
   InstState& S = I.st;
-  if (ld_flag(&S.conv) || ld_flag(&S.conv_in)) return;
+  if (ld_flag(&S.conv) || (ld_flag(&S.conv_in) && !ld_flag(&S.restart))) return;
   const int k = S.it_f;
-  const double alpha = S.alpha, beta = S.beta;
+  const double alpha = S.alpha_cur, beta = S.beta;
   const int sig = min(I.bdf, (int)S.step + 1);
   double* __restrict__ x = I.u_new;
   const int64_t i0 = (int64_t)lblk * TILE + threadIdx.x;
@@ -503,6 +507,9 @@ __global__ __launch_bounds__(WG) void k_cg_update(InstDesc* __restrict__ insts, 
   }
   write_partials<2>(v, I.partial + (int64_t)PART_UPD * I.nblk, I.nblk, lblk);
   if (lblk == 0 && threadIdx.x == 0) {
+    // read by the next finalize only
+    S.gamma_prev = S.gamma_cur;
+    S.alpha_prev = S.alpha_cur;
     S.it = k + 1;
     S.it_step += 1;
   }
@@ -553,6 +560,7 @@ __global__ void k_end_step(InstDesc* __restrict__ insts, const int32_t* __restri
   S.it = 0;
   S.conv = 0;
   S.conv_in = 0;
+  S.restart = 0;
 }
 
 // Potential in mV into a caller-owned device buffer: dst = a u + b.
