@@ -174,6 +174,48 @@ def roofline(res, spec, precision_name, workload_key):
             "avg_launch_us": 1e6 * avg_s}, per_kernel
 
 
+def run_batched(specs, precision, steps, warmup):
+    """All instances resident in one pool, stepped together (one launch per phase)."""
+    import paper_2308_01651_amd as ep
+    import torch
+    pool = ep.Pool(200 << 30, len(specs), precision)
+    sims = []
+    t0 = time.perf_counter()
+    for sp in specs:
+        s = ep.Simulation.from_spec(sp, precision=precision, finalize=False)
+        if pool.admit(s, warmup + steps + 1) is None:
+            raise RuntimeError("batched instance did not fit the pool")
+        sims.append(s)
+    setup = time.perf_counter() - t0
+    pool.step(warmup)
+    torch.cuda.synchronize()
+    it0 = sum(s.get_stats()["cg_iters_total"] for s in sims)
+    t0 = time.perf_counter()
+    pool.step(steps)
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    n_tot = sum(sp.mesh.n_nodes for sp in specs)
+    its = (sum(s.get_stats()["cg_iters_total"] for s in sims) - it0) / (steps * len(sims))
+    fields = [(s.get_state()[0], s.get_activation_times()) for s in sims]
+    for slot in list(pool.sims):
+        pool.release(slot)
+    for s in sims:
+        s.close()
+    pool.close()
+    return {"instances": len(specs), "total_nodes": n_tot, "steps": steps, "warmup": warmup, "seconds": T,
+            "node_steps_per_s": n_tot * steps / T, "ms_per_step": 1e3 * T / steps,
+            "cg_iters_per_instance_step": its, "setup_s": setup}, fields
+
+
+def run_serving(precision, max_slots, trace):
+    import paper_2308_01651_amd as ep
+    from paper_2308_01651_amd import serve
+    out = serve.serve(trace, 200 << 30, max_slots, precision, steps_per_tick=20,
+                      progress=lambda m: print("[bench] " + m, file=sys.stderr, flush=True))
+    out.pop("records")
+    return out
+
+
 CPU_SAMPLE = r"""
 import json, os, sys, time
 sys.path.insert(0, {root!r})
@@ -218,6 +260,12 @@ def main():
                     help="length of the event-instrumented region (default: same as --steps)")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--batched-steps", type=int, default=400)
+    ap.add_argument("--serve-requests", type=int, default=32)
+    ap.add_argument("--serve-full", action="store_true",
+                    help="the configured trace: 128 requests, 1e4-1e6 nodes, 50-500 ms (long)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 512 MiB five times (counter calibration)")
     args = ap.parse_args()
@@ -263,6 +311,41 @@ def main():
             "rms_mV": float(np.sqrt(np.mean(du ** 2))), "max_abs_mV": float(np.max(np.abs(du))),
             "max_abs_dAT_ms": float(np.max(np.abs(a64[ok] - a32[ok]))) if ok.any() else None,
             "activated_nodes_equal": bool(np.array_equal(np.isnan(a64), np.isnan(a32)))}
+    import workloads as W
+    batched = None
+    if not args.no_batched and args.workload == "c1":
+        specs = W.config_c3()
+        batched = {}
+        bf = {}
+        for pn in ("fp64", "mixed"):
+            print(f"[bench] batched: 64 slab instances, {pn}", file=sys.stderr, flush=True)
+            r, f = run_batched(specs, ep.EP_FP64 if pn == "fp64" else ep.EP_MIXED, args.batched_steps, 20)
+            batched[pn] = r
+            bf[pn] = f
+            print(f"[bench] batched {pn}: {r['node_steps_per_s']:.4g} node-steps/s", file=sys.stderr, flush=True)
+        d2 = [float(np.mean((a[0] - b[0]) ** 2)) for a, b in zip(bf["fp64"], bf["mixed"])]
+        mv = [100.0 if sp.model == "ap" else 1.0 for sp in specs]   # mV per model unit
+        rms = float(np.sqrt(np.mean([d * m * m for d, m in zip(d2, mv)])))
+        dat = []
+        for a, b in zip(bf["fp64"], bf["mixed"]):
+            ok = ~np.isnan(a[1]) & ~np.isnan(b[1])
+            if ok.any():
+                dat.append(float(np.max(np.abs(a[1][ok] - b[1][ok]))))
+        batched["mixed"]["vs_fp64"] = {"rms_mV": rms, "max_abs_dAT_ms": max(dat) if dat else None}
+    serving = None
+    if not args.no_serve and args.workload == "c1":
+        nreq, nmax, tmin, tmax = ((128, 1e6, 50.0, 500.0) if args.serve_full
+                                  else (args.serve_requests, 3e5, 50.0, 200.0))
+        trace = W.serving_trace(seed=5, n_req=nreq, rate_per_s=4.0, n_min=1e4, n_max=nmax,
+                                t_min=tmin, t_max=tmax)
+        offered = sum(r.spec.mesh.n_nodes * r.spec.n_steps for r in trace) / max(r.arrival_s for r in trace)
+        serving = {"trace": {"requests": nreq, "rate_per_s": 4.0, "nodes": [1e4, nmax],
+                             "simulated_ms": [tmin, tmax], "models": "ttp06|bo", "geometry": "slab|lv",
+                             "seed": 5, "offered_node_steps_per_s": offered}}
+        print("[bench] serving: continuous batching, mixed precision", file=sys.stderr, flush=True)
+        serving["batched_mixed"] = run_serving(ep.EP_MIXED, 32, trace)
+        print("[bench] serving: sequential plain FP64", file=sys.stderr, flush=True)
+        serving["sequential_fp64"] = run_serving(ep.EP_FP64, 1, trace)
     cpu = None
     if not args.no_cpu_baseline and args.workload in ("c1", "c1big"):
         print("[bench] cpu baseline (oracle, 1 thread)", file=sys.stderr, flush=True)
@@ -290,6 +373,8 @@ def main():
         "roofline_kernel": main_res["roofline"]["kernel"],
         "cpu_baseline": cpu,
         "variants": out,
+        "batched": batched,
+        "serving": serving,
     }
     print(json.dumps(line))
 
