@@ -11,7 +11,7 @@ in HBM before timing starts.
 Timed: `--warmup` untimed steps, then exactly `--steps` steps bracketed by
 device synchronization.  `value` is FP64 plain node-steps/s; the mixed
 precision (FP32 ionic + inner CG, FP64 refinement) run of the same workload
-is reported beside it.  A second, instrumented region of the same length
+is reported beside it.  A second, instrumented pass over the same window
 brackets every kernel launch with HIP events for the roofline of the
 dominant kernel.  The oracle (FP64 CPU) is timed on a bounded sample of the
 same workload in a one-thread subprocess.
@@ -133,9 +133,14 @@ def run_gpu(spec, precision, steps, warmup, instrument_steps):
         "device_bytes": st["device_bytes"],
         "setup_ms": st0["ms_setup"],
     }
-    # instrumented region: HIP events around every launch
-    kt = None
+    sim.close()
+    # instrumented pass: a fresh simulation over the same window (same warmup,
+    # same steps) with HIP events around every launch, so the per-kernel
+    # breakdown describes the timed steps and not a later phase of the beat
     if instrument_steps > 0:
+        sim = ep.Simulation.from_spec(spec, precision=precision)
+        sim.step(warmup)
+        sim.sync()
         sim.set_option(ep.EP_OPT_KERNEL_TIMERS, 1)
         it1 = sim.get_stats()["cg_iters_total"]
         sim.step(instrument_steps)
@@ -145,8 +150,7 @@ def run_gpu(spec, precision, steps, warmup, instrument_steps):
         res["instrumented_cg_iters"] = sim.get_stats()["cg_iters_total"] - it1
         res["kernel_ms"] = {k: v[0] for k, v in kt.items()}
         res["kernel_launches"] = {k: v[1] for k, v in kt.items()}
-        sim.set_option(ep.EP_OPT_KERNEL_TIMERS, 0)
-    sim.close()
+        sim.close()
     return res, u_end, at_end
 
 
