@@ -61,7 +61,7 @@ enum { EP_PASSIVE = 0, EP_AP = 1, EP_BO = 2, EP_TTP06 = 3 };          /* ionic m
 enum { EP_CELL_EPI = 0, EP_CELL_ENDO = 1, EP_CELL_MID = 2 };          /* TTP06 variants  */
 enum { EP_CUBE = 0, EP_SPHERE = 1, EP_GAUSS = 2 };                    /* stimulus shapes */
 enum { EP_FP64 = 0, EP_MIXED = 1 };                                   /* precision       */
-enum { EP_JACOBI = 0 };                                               /* preconditioner  */
+enum { EP_JACOBI = 0, EP_BJACOBI = 1 };                               /* preconditioner  */
 enum { EP_DTYPE_F64 = 0, EP_DTYPE_F32 = 1 };
 enum { EP_FMT_AUTO = 0, EP_FMT_SELL = 1, EP_FMT_DIA = 2 };            /* matrix format   */
 
@@ -158,9 +158,15 @@ ep_status ep_sim_add_stimulus(ep_sim* sim, int shape, const double center_mm[3],
                               double period_ms);
 
 /* Time step, BDF order (1..3; paper: BDF of order sigma with start-up at
- * lower orders), precision (EP_FP64 or EP_MIXED), preconditioner (EP_JACOBI),
- * block (unused, 1), relative residual tolerance ||b - A u|| <= rtol ||b||,
- * and max CG iterations per solve (inner solve when mixed). */
+ * lower orders), precision (EP_FP64 or EP_MIXED), preconditioner and block
+ * size, relative residual tolerance ||b - A u|| <= rtol ||b||, and max CG
+ * iterations per solve (inner solve when mixed).  Preconditioners (paper:
+ * the software overview names block Jacobi among the preconditioners of its
+ * CG solver): EP_JACOBI (block must be 1) or EP_BJACOBI, the
+ * exact inverse of each diagonal block of `block` consecutive rows of the
+ * system matrix (block 1, 2, 4, 8, 16, 32 or 64; 1 is Jacobi; the last
+ * block may be shorter).  The inverses take block x 8 bytes per node per
+ * BDF order (plus block x 4 in mixed precision).  EP_EINVAL otherwise. */
 ep_status ep_sim_set_solver(ep_sim* sim, double dt_ms, int bdf_order, int precision, int precond,
                             int block, double rtol, int max_it);
 

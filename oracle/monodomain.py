@@ -78,7 +78,7 @@ class Monodomain:
     """One monodomain simulation on one subdomain."""
 
     def __init__(self, xyz, conn, fibers, sigma, chi, cm, model, variant="", stimuli=(),
-                 dt=0.05, bdf=1, solver="auto", rtol=1e-13, max_it=5000):
+                 dt=0.05, bdf=1, solver="auto", rtol=1e-13, max_it=5000, block=1):
         self.xyz = np.asarray(xyz, np.float64)
         self.n = self.xyz.shape[0]
         self.model = IonicModel(model, variant)
@@ -95,7 +95,9 @@ class Monodomain:
         self.solver = solver
         self.rtol = rtol
         self.max_it = max_it
+        self.block = int(block)
         self._lu = {}
+        self._prec = {}
         self.cg_iters = []
         # stimuli: (profile in model units per unit amplitude, t0, dur, period, amp)
         scale = 1.0 / (chi * cm * self.model.mv_per_unit)
@@ -141,16 +143,52 @@ class Monodomain:
             if s not in self._lu:
                 self._lu[s] = spla.splu(A.tocsc())
             return self._lu[s].solve(b)
-        return self.pcg(A, b, x0)
+        return self.pcg(A, b, x0, s)
 
-    def pcg(self, A, b, x0):
-        """Jacobi-preconditioned conjugate gradients (Hestenes-Stiefel form);
-        stops when ||b - A x||_2 <= rtol ||b||_2 (recursive residual)."""
-        dinv = 1.0 / A.diagonal()
+    def preconditioner(self, s):
+        """Inverse of the preconditioner of A_s as a function r -> z.
+
+        block == 1: Jacobi, z = r / diag(A).  block > 1: block Jacobi over
+        consecutive runs of `block` rows (the last run may be shorter), each
+        diagonal block of A inverted exactly.
+        """
+        if s in self._prec:
+            return self._prec[s]
+        A = self.A[s]
+        b = self.block
+        if b <= 1:
+            dinv = 1.0 / A.diagonal()
+            f = lambda r: dinv * r
+        else:
+            n = self.n
+            nb = (n + b - 1) // b
+            blocks = np.zeros((nb, b, b))
+            idx = np.arange(nb * b)
+            C = A.tocoo()
+            same = (C.row // b) == (C.col // b)
+            blocks[C.row[same] // b, C.row[same] % b, C.col[same] % b] = C.data[same]
+            pad = idx[idx >= n]
+            blocks[pad // b, pad % b, pad % b] = 1.0  # identity rows of the ragged last block
+            inv = np.linalg.inv(blocks)
+
+            def f(r):
+                rp = np.zeros(nb * b)
+                rp[:n] = r
+                return np.einsum("kij,kj->ki", inv, rp.reshape(nb, b)).ravel()[:n]
+        self._prec[s] = f
+        return f
+
+    def pcg(self, A, b, x0, s=None):
+        """Preconditioned conjugate gradients (Hestenes-Stiefel form), Jacobi
+        or block Jacobi; stops when ||b - A x||_2 <= rtol ||b||_2 (recursive
+        residual)."""
+        if s is None:
+            s = next(k for k, v in self.A.items() if v is A)
+        P = self.preconditioner(s)
         x = x0.copy()
         r = b - A @ x
         bnorm = np.linalg.norm(b)
-        z = dinv * r
+        z = P(r)
         p = z.copy()
         rz = r @ z
         it = 0
@@ -159,7 +197,7 @@ class Monodomain:
             alpha = rz / (p @ q)
             x += alpha * p
             r -= alpha * q
-            z = dinv * r
+            z = P(r)
             rz_new = r @ z
             p = z + (rz_new / rz) * p
             rz = rz_new
@@ -204,9 +242,9 @@ class Monodomain:
             -80.0 if self.model.name == "ap" else (-84.0 if self.model.name == "bo" else 0.0))
 
 
-def from_spec(spec, solver="auto", rtol=1e-13):
+def from_spec(spec, solver="auto", rtol=1e-13, block=1):
     """Build an oracle simulation from a workloads.SimSpec."""
     p = spec.phys
     return Monodomain(spec.mesh.xyz, spec.mesh.conn, spec.fibers,
                       (p.sigma_l, p.sigma_t, p.sigma_n), p.chi, p.cm, spec.model,
-                      spec.variant, spec.stimuli, spec.dt, spec.bdf, solver, rtol)
+                      spec.variant, spec.stimuli, spec.dt, spec.bdf, solver, rtol, block=block)

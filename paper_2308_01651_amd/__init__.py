@@ -21,6 +21,7 @@ EP_CELL_EPI, EP_CELL_ENDO, EP_CELL_MID = 0, 1, 2
 EP_CUBE, EP_SPHERE, EP_GAUSS = 0, 1, 2
 EP_FP64, EP_MIXED = 0, 1
 EP_JACOBI = 0
+EP_BJACOBI = 1
 EP_DTYPE_F64, EP_DTYPE_F32 = 0, 1
 EP_FMT_AUTO, EP_FMT_SELL, EP_FMT_DIA = 0, 1, 2
 EP_OPT_MATRIX_FORMAT, EP_OPT_INNER_RTOL, EP_OPT_MAX_OUTER, EP_OPT_PHASE_TIMERS = 1, 2, 3, 4
@@ -175,8 +176,9 @@ class Simulation:
     # -- convenience -----------------------------------------------------------
     @classmethod
     def from_spec(cls, spec, precision=EP_FP64, device=0, stream=None, rtol=None, max_it=1000,
-                  matrix_format=EP_FMT_AUTO, finalize=True, inner_rtol=None):
-        """Configure from a workloads.SimSpec (marshalling of its arrays)."""
+                  matrix_format=EP_FMT_AUTO, finalize=True, inner_rtol=None, block=1):
+        """Configure from a workloads.SimSpec (marshalling of its arrays).
+        block > 1 selects block-Jacobi preconditioning with that block size."""
         sim = cls(device, stream)
         m = spec.mesh
         sim.upload_mesh(m.elem, m.xyz, m.conn)
@@ -187,7 +189,8 @@ class Simulation:
         sim.set_ionic_model(MODEL_IDS[spec.model], CELL_IDS.get(spec.variant, 0))
         for st in spec.stimuli:
             sim.add_stimulus(st.shape, st.center, st.size, st.amp, st.t0, st.dur, st.period)
-        sim.set_solver(spec.dt, spec.bdf, precision, EP_JACOBI, 1, spec.rtol if rtol is None else rtol, max_it)
+        sim.set_solver(spec.dt, spec.bdf, precision, EP_BJACOBI if block > 1 else EP_JACOBI, int(block),
+                       spec.rtol if rtol is None else rtol, max_it)
         if matrix_format != EP_FMT_AUTO:
             sim.set_option(EP_OPT_MATRIX_FORMAT, matrix_format)
         if inner_rtol is not None:

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cstddef>
 #include <cmath>
@@ -208,8 +209,9 @@ size_t estimate_bytes(const ep_sim* s) {
   const double nnz_row = (s->elem == EP_HEX8) ? 27.0 : 16.0;
   const bool mixed = s->prec == EP_MIXED;
   const ModelInfo mi = model_info(s->model);
-  double per_node = 11 * 8.0 + 24.0 + 8.0 * 3;                  // FP64 vectors, activation, dinv
-  per_node += mixed ? (5 * 4.0 + 3 * 4.0) : 0.0;
+  double per_node = 11 * 8.0 + 24.0;                            // FP64 vectors, activation
+  per_node += (double)s->bdf * s->block * (mixed ? 12.0 : 8.0);  // preconditioner(s)
+  per_node += mixed ? 5 * 4.0 : 0.0;
   per_node += mixed ? (mi.nvars * 4.0 + 8.0) : mi.nvars * 8.0;
   per_node += nnz_row * ((s->bdf + 1) * 8.0 + 4.0 + (mixed ? s->bdf * 4.0 : 0.0));
   per_node += 8.0 * std::min<size_t>(s->stims.size(), MAX_STIM);
@@ -221,6 +223,69 @@ hipError_t upload(DevMem& m, T** d, const T* h, size_t count, hipStream_t st) {
   hipError_t e = m.alloc((void**)d, count * sizeof(T));
   if (e != hipSuccess) return e;
   return hipMemcpyAsync(*d, h, count * sizeof(T), hipMemcpyHostToDevice, st);
+}
+
+// Block-Jacobi preconditioner: for every run of bs consecutive rows (the
+// last run may be shorter) the exact inverse of the diagonal block of the
+// symmetrized operator (A + A^T)/2, by Cholesky factorization, stored
+// column-wise: out[j * ld + i] = (B^-1)(i - i0, j).  False if a block is not
+// positive definite.
+bool block_inverses(const Csr& A, const std::vector<double>& val, int bs, int64_t ld, std::vector<double>& out) {
+  const int64_t n = (int64_t)A.rowptr.size() - 1;
+  const int64_t nb = (n + bs - 1) / bs;
+  out.assign((size_t)bs * ld, 0.0);
+  std::atomic<bool> ok{true};
+  parallel_for(nb, [&](int64_t k) {
+    thread_local std::vector<double> B, L, X;
+    const int64_t i0 = k * bs;
+    const int m = (int)std::min<int64_t>(bs, n - i0);
+    B.assign((size_t)m * m, 0.0);
+    L.assign((size_t)m * m, 0.0);
+    X.assign((size_t)m * m, 0.0);
+    for (int a = 0; a < m; a++) {
+      const int64_t r = i0 + a;
+      for (int64_t t = A.rowptr[r]; t < A.rowptr[r + 1]; t++) {
+        const int64_t c = A.col[t] - i0;
+        if (c < 0 || c >= m) continue;
+        B[(size_t)a * m + c] += 0.5 * val[t];
+        B[(size_t)c * m + a] += 0.5 * val[t];
+      }
+    }
+    // B = L L^T
+    for (int j = 0; j < m; j++) {
+      double d = B[(size_t)j * m + j];
+      for (int t = 0; t < j; t++) d -= L[(size_t)j * m + t] * L[(size_t)j * m + t];
+      if (!(d > 0.0)) {
+        ok = false;
+        return;
+      }
+      const double ljj = std::sqrt(d);
+      L[(size_t)j * m + j] = ljj;
+      for (int a = j + 1; a < m; a++) {
+        double v = B[(size_t)a * m + j];
+        for (int t = 0; t < j; t++) v -= L[(size_t)a * m + t] * L[(size_t)j * m + t];
+        L[(size_t)a * m + j] = v / ljj;
+      }
+    }
+    // columns of B^-1: L y = e_c, then L^T x = y
+    std::vector<double> y(m);
+    for (int c = 0; c < m; c++) {
+      for (int a = 0; a < m; a++) {
+        double v = (a == c) ? 1.0 : 0.0;
+        for (int t = 0; t < a; t++) v -= L[(size_t)a * m + t] * y[t];
+        y[a] = v / L[(size_t)a * m + a];
+      }
+      for (int a = m - 1; a >= 0; a--) {
+        double v = y[a];
+        for (int t = a + 1; t < m; t++) v -= L[(size_t)t * m + a] * X[(size_t)t * m + c];
+        X[(size_t)a * m + c] = v / L[(size_t)a * m + a];
+      }
+    }
+    for (int a = 0; a < m; a++)
+      for (int c = 0; c < m; c++)
+        out[(size_t)c * ld + i0 + a] = 0.5 * (X[(size_t)a * m + c] + X[(size_t)c * m + a]);
+  });
+  return ok;
 }
 
 ep_status finalize_impl(ep_sim* s) {
@@ -295,7 +360,8 @@ ep_status finalize_impl(ep_sim* s) {
   s->nvars = s->mi.nvars;
   D.nvars = s->nvars;
   D.precond = s->precond;
-  D.block = 1;
+  D.block = s->block;
+  D.bld = round_up(n, 64);
   default_params(s->model, s->variant, D.mp);
   for (size_t k = 0; k < s->params.size(); k++) D.mp[k] = s->params[k];
   hipStream_t st = s->stream;
@@ -416,9 +482,16 @@ ep_status finalize_impl(ep_sim* s) {
     EP_HIP(hipStreamSynchronize(st));  // col lives on the host stack frame
   }
   for (int q = 0; q < nsig; q++) {
-    std::vector<double> dinv(n);
-    for (int64_t i = 0; i < n; i++) dinv[i] = 1.0 / valA[q][dpos[i]];
-    hostvals.push_back(dinv);
+    if (s->block == 1) {
+      std::vector<double> dinv(n);
+      for (int64_t i = 0; i < n; i++) dinv[i] = 1.0 / valA[q][dpos[i]];
+      hostvals.push_back(dinv);
+    } else {
+      std::vector<double> binv;
+      if (!block_inverses(A, valA[q], s->block, D.bld, binv))
+        return fail(EP_EINVAL, "a diagonal block of the system matrix is not positive definite");
+      hostvals.push_back(std::move(binv));
+    }
     EP_HIP(to_dev_d(hostvals.back(), &D.dinv[q]));
     if (mixed) EP_HIP(to_dev_f(hostvals.back(), &D.dinv32[q]));
   }
@@ -550,6 +623,8 @@ ep_status validate_desc(const InstDesc& D, int64_t guard) {
     if (D.prec == P_MIXED && (!D.valA32[q] || !D.dinv32[q])) return bad("FP32 operator values");
   }
   if (D.prec == P_MIXED && (!D.r32 || !D.z32 || !D.p32 || !D.s32 || !D.w32 || !D.st32)) return bad("FP32 vectors");
+  if (D.block < 1 || D.block > 64 || (D.block & (D.block - 1)) != 0 || D.bld < ((D.n + 63) / 64) * 64)
+    return bad("preconditioner blocks");
   if (D.nvars > 0 && !D.st64 && !D.st32) return bad("ionic state");
   if (D.fmt == FMT_DIA) {
     if (D.nup < 1 || D.nup > MAX_UP || D.off[0] != 0) return bad("DIA diagonals");
@@ -788,10 +863,13 @@ ep_status ep_sim_set_solver(ep_sim* s, double dt, int bdf, int precision, int pr
   if (check_sim(s)) return EP_EINVAL;
   if (s->finalized) return fail(EP_ESTATE, "sim already finalized");
   if (!(dt > 0) || bdf < 1 || bdf > 3 || (precision != EP_FP64 && precision != EP_MIXED) ||
-      precond != EP_JACOBI || !(rtol > 0) || max_it < 1)
+      (precond != EP_JACOBI && precond != EP_BJACOBI) || !(rtol > 0) || max_it < 1)
     return fail(EP_EINVAL, "bad solver settings");
-  (void)block;
-  s->dt = dt; s->bdf = bdf; s->prec = precision; s->precond = precond; s->rtol = rtol; s->max_it = max_it;
+  const bool pow2 = block >= 1 && block <= 64 && (block & (block - 1)) == 0;
+  if ((precond == EP_JACOBI && block != 1) || (precond == EP_BJACOBI && !pow2))
+    return fail(EP_EINVAL, "block must be 1 for Jacobi and one of 1, 2, 4, ..., 64 for block Jacobi");
+  s->dt = dt; s->bdf = bdf; s->prec = precision; s->precond = precond; s->block = block;
+  s->rtol = rtol; s->max_it = max_it;
   return EP_OK;
 }
 

@@ -77,7 +77,8 @@ struct InstDesc {
   int32_t blk0, nblk;      // this instance's workgroups in node-parallel launches
   int32_t model, bdf, prec, fmt;
   int32_t nup, max_it, max_outer, n_stim;   // nup: stored (upper) DIA diagonals
-  int32_t nvars, precond, block, pad_;
+  int32_t nvars, precond, block, pad_;   // block: rows per preconditioner block (1: Jacobi)
+  int64_t bld;             // block Jacobi: leading dimension of the inverse-block columns
   double dt, inv_dt, rtol, inner_rtol, threshold;
   double mp[NPARAM];       // ionic model parameters
   int32_t off[MAX_UP];     // DIA: offsets >= 0 of the stored diagonals, off[0] = 0
@@ -90,7 +91,12 @@ struct InstDesc {
   const double* valA[3];
   const double* valM;
   const float* valA32[3];
-  const double* dinv[3];   // Jacobi: 1/diag(A_sigma); block-Jacobi: inverse blocks
+  // preconditioner of A_sigma.  Jacobi: dinv[i] = 1/A(i, i).  Block Jacobi
+  // over consecutive runs of `block` rows (block divides 64, so a run never
+  // leaves a wavefront): dinv[j * bld + i] = (B^-1)(i - i0, j), B the
+  // diagonal block of A_sigma whose first row is i0 = i - i % block
+  // (columns past a ragged last block hold 0).
+  const double* dinv[3];
   const float* dinv32[3];
   // FP64 vectors (padded by `guard` zero entries on both sides)
   double* U[RING];

@@ -96,6 +96,25 @@ __device__ __forceinline__ int ld_flag(const int32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// z = P^{-1} r for the row i this lane owns.  Jacobi (block 1): one scaling.
+// Block Jacobi: a block of `bs` consecutive rows lies inside one wavefront
+// (bs divides 64 and tiles start at multiples of 64), so the block's
+// residual entries are gathered by lane shuffles and the row of the inverse
+// block is read column by column (coalesced across the wavefront).  Every
+// lane of the wavefront must call this (r = 0 on lanes without a row).
+template <typename T>
+__device__ __forceinline__ T precond_apply(const T* __restrict__ pinv, int64_t bld, int bs, int64_t i, bool valid,
+                                           T r) {
+  if (bs == 1) return valid ? pinv[i] * r : T(0);
+  const int base = (int)(threadIdx.x & 63) & ~(bs - 1);
+  T acc = T(0);
+  for (int j = 0; j < bs; j++) {
+    const T rj = __shfl(r, base + j, 64);
+    if (valid) acc += pinv[(int64_t)j * bld + i] * rj;
+  }
+  return acc;
+}
+
 // ---------------------------------------------------------------------------
 // sparse row products
 // ---------------------------------------------------------------------------
@@ -285,29 +304,35 @@ __global__ __launch_bounds__(WG) void k_residual(InstDesc* __restrict__ insts, c
 #pragma unroll
   for (int rw = 0; rw < RPT; rw++) {
     const int64_t i = i0 + rw * WG;
-    if (i >= I.n) break;
-    double bi;
-    if (WITH_RHS) {
-      bi = spmv_row<double, double, double>(I, I.valM, I.g, i);
-      I.b[i] = bi;
-    } else {
-      bi = I.b[i];
+    const bool valid = i < I.n;
+    double bi = 0.0, ri = 0.0;
+    if (valid) {
+      if (WITH_RHS) {
+        bi = spmv_row<double, double, double>(I, I.valM, I.g, i);
+        I.b[i] = bi;
+      } else {
+        bi = I.b[i];
+      }
+      ri = bi - spmv_row<double, double, double>(I, I.valA[sig - 1], x, i);
     }
-    const double ri = bi - spmv_row<double, double, double>(I, I.valA[sig - 1], x, i);
     if (!MIXED) {
-      const double zi = I.dinv[sig - 1][i] * ri;
-      I.r[i] = ri;
-      I.z[i] = zi;
-      v[0] += ri * zi;
-      v[1] += ri * ri;
+      const double zi = precond_apply<double>(I.dinv[sig - 1], I.bld, I.block, i, valid, ri);
+      if (valid) {
+        I.r[i] = ri;
+        I.z[i] = zi;
+        v[0] += ri * zi;
+        v[1] += ri * ri;
+      }
     } else {
       const float r32 = (float)ri;
-      const float z32 = I.dinv32[sig - 1][i] * r32;
-      I.r32[i] = r32;
-      I.z32[i] = z32;
-      v[0] += (double)r32 * (double)z32;
-      v[1] += ri * ri;
-      v[3] += (double)r32 * (double)r32;
+      const float z32 = precond_apply<float>(I.dinv32[sig - 1], I.bld, I.block, i, valid, r32);
+      if (valid) {
+        I.r32[i] = r32;
+        I.z32[i] = z32;
+        v[0] += (double)r32 * (double)z32;
+        v[1] += ri * ri;
+        v[3] += (double)r32 * (double)r32;
+      }
     }
     if (WITH_RHS) v[2] += bi * bi;
   }
@@ -481,28 +506,40 @@ __global__ __launch_bounds__(WG) void k_cg_update(InstDesc* __restrict__ insts, 
 #pragma unroll
   for (int rw = 0; rw < RPT; rw++) {
     const int64_t i = i0 + rw * WG;
-    if (i >= I.n) break;
+    const bool valid = i < I.n;
     if (MIXED) {
       const float fb = (float)beta, fa = (float)alpha;
-      const float z = I.z32[i], w = I.w32[i];
-      const float pn = (k == 0) ? z : z + fb * I.p32[i];
-      const float sn = (k == 0) ? w : w + fb * I.s32[i];
-      x[i] += alpha * (double)pn;
-      const float rn = I.r32[i] - fa * sn;
-      const float zn = I.dinv32[sig - 1][i] * rn;
-      I.p32[i] = pn; I.s32[i] = sn; I.r32[i] = rn; I.z32[i] = zn;
-      v[0] += (double)rn * (double)zn;
-      v[1] += (double)rn * (double)rn;
+      float rn = 0.0f;
+      if (valid) {
+        const float z = I.z32[i], w = I.w32[i];
+        const float pn = (k == 0) ? z : z + fb * I.p32[i];
+        const float sn = (k == 0) ? w : w + fb * I.s32[i];
+        x[i] += alpha * (double)pn;
+        rn = I.r32[i] - fa * sn;
+        I.p32[i] = pn; I.s32[i] = sn; I.r32[i] = rn;
+      }
+      const float zn = precond_apply<float>(I.dinv32[sig - 1], I.bld, I.block, i, valid, rn);
+      if (valid) {
+        I.z32[i] = zn;
+        v[0] += (double)rn * (double)zn;
+        v[1] += (double)rn * (double)rn;
+      }
     } else {
-      const double z = I.z[i], w = I.w[i];
-      const double pn = (k == 0) ? z : z + beta * I.p[i];
-      const double sn = (k == 0) ? w : w + beta * I.s[i];
-      x[i] += alpha * pn;
-      const double rn = I.r[i] - alpha * sn;
-      const double zn = I.dinv[sig - 1][i] * rn;
-      I.p[i] = pn; I.s[i] = sn; I.r[i] = rn; I.z[i] = zn;
-      v[0] += rn * zn;
-      v[1] += rn * rn;
+      double rn = 0.0;
+      if (valid) {
+        const double z = I.z[i], w = I.w[i];
+        const double pn = (k == 0) ? z : z + beta * I.p[i];
+        const double sn = (k == 0) ? w : w + beta * I.s[i];
+        x[i] += alpha * pn;
+        rn = I.r[i] - alpha * sn;
+        I.p[i] = pn; I.s[i] = sn; I.r[i] = rn;
+      }
+      const double zn = precond_apply<double>(I.dinv[sig - 1], I.bld, I.block, i, valid, rn);
+      if (valid) {
+        I.z[i] = zn;
+        v[0] += rn * zn;
+        v[1] += rn * rn;
+      }
     }
   }
   write_partials<2>(v, I.partial + (int64_t)PART_UPD * I.nblk, I.nblk, lblk);

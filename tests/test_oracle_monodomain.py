@@ -6,7 +6,9 @@
 - charge conservation 1^T M u with I_ion = 0 (fixes the applied-current load);
 - a spatially uniform state reproduces the single-cell (0D) update (fixes the
   ionic-current interpolation coupling, since K 1 = 0);
-- CG agrees with a dense solve on tiny meshes;
+- CG agrees with a dense solve on tiny meshes, with Jacobi and with block
+  Jacobi; block Jacobi is exact (one iteration) when its blocks hold the
+  whole operator, including a ragged last block;
 - Aliev-Panfilov plane front speed approaches the bistable-front closed form;
 - activation times converge under mesh refinement.
 """
@@ -119,6 +121,63 @@ def test_cg_matches_dense_solve():
         a.step()
         b.step()
     assert np.max(np.abs(a.u - b.u)) < 1e-12
+
+
+@pytest.mark.parametrize("block", [2, 8, 64])
+def test_block_jacobi_cg_matches_dense_solve(block):
+    m = W.slab_q1(2.0, 2.0, 2.0, 0.5)
+    st = W.corner_cube_stimulus(dims=(2.0, 2.0, 2.0))
+    f, s, n = W.random_fibers(m.n_nodes, 7)
+    args = (m.xyz, m.conn, (f, s, n), (0.17, 0.019, 0.019), 140.0, 0.01, "ap", "", [st], 0.05, 2)
+    a = OM.Monodomain(*args, solver="dense")
+    b = OM.Monodomain(*args, solver="cg", rtol=1e-14, block=block)
+    for _ in range(20):
+        a.step()
+        b.step()
+    assert np.max(np.abs(a.u - b.u)) < 1e-12
+
+
+def _block_diagonal_case(n, bs, seed):
+    """SPD matrix whose couplings stay inside consecutive runs of bs rows."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(seed)
+    A = np.zeros((n, n))
+    for lo in range(0, n, bs):
+        hi = min(n, lo + bs)
+        B = rng.standard_normal((hi - lo, hi - lo))
+        A[lo:hi, lo:hi] = B @ B.T + (hi - lo) * np.eye(hi - lo)
+    return sp.csr_matrix(A), rng.standard_normal(n)
+
+
+@pytest.mark.parametrize("n,bs", [(64, 8), (61, 8), (50, 16), (7, 4)])
+def test_block_jacobi_is_exact_on_block_diagonal_operator(n, bs):
+    m = W.slab_q1(1.0, 1.0, 1.0, 0.5)  # any small instance; its operator is replaced
+    o = OM.Monodomain(m.xyz, m.conn, W.uniform_fibers(m.n_nodes), (0.1, 0.1, 0.1), 1.0, 1.0,
+                      "passive", "", (), 0.05, 1, "cg", 1e-12, block=bs)
+    A, rhs = _block_diagonal_case(n, bs, seed=n)
+    o.A = {1: A}
+    o.n = n
+    o._prec = {}
+    o.cg_iters = []
+    x = o.pcg(A, rhs, np.zeros(n), s=1)
+    assert o.cg_iters == [1]
+    assert np.allclose(A @ x, rhs, rtol=0, atol=1e-10 * np.linalg.norm(rhs))
+    # half-size blocks miss couplings: more than one iteration
+    o.block = max(1, bs // 2)
+    o._prec = {}
+    o.cg_iters = []
+    o.pcg(A, rhs, np.zeros(n), s=1)
+    assert o.cg_iters[0] > 1
+
+
+def test_block_jacobi_single_block_is_exact():
+    m = W.slab_q1(1.5, 1.0, 1.0, 0.5)
+    o = OM.Monodomain(m.xyz, m.conn, W.random_fibers(m.n_nodes, 3), (0.17, 0.02, 0.02), 1.0, 1.0,
+                      "passive", "", (), 0.05, 1, "cg", 1e-12, block=m.n_nodes + 5)
+    rhs = np.random.default_rng(1).standard_normal(m.n_nodes)
+    x = o.pcg(o.A[1], rhs, np.zeros(m.n_nodes), s=1)
+    assert o.cg_iters == [1]
+    assert np.allclose(o.A[1] @ x, rhs, rtol=0, atol=1e-10 * np.linalg.norm(rhs))
 
 
 def test_aliev_panfilov_front_speed():
