@@ -49,14 +49,16 @@ struct InstState {
   int64_t step;        // completed steps n (advanced by k_end_step only)
   int32_t it;          // CG iterations done in the current (inner) solve
   int32_t it_f;        // iteration index whose step lengths the finalize set
+  // solve-control flags, adjacent so that a kernel reads them in one load;
+  // no kernel writes a flag that another workgroup of the same kernel reads
   int32_t conv;        // 1: the step's solve is done
   int32_t conv_in;     // 1: the inner FP32 solve of this sweep is done
+  int32_t restart;     // 1: a refinement residual restarted the inner solve
   int32_t flags;       // Flag bits, sticky until cleared by the host
   int32_t outer;       // refinement sweeps in this step
   int32_t it_step;     // CG iterations in the current step (all sweeps)
   int32_t it_last;     // CG iterations of the last finished step
   int32_t it_max;      // largest per-step CG count so far
-  int32_t restart;     // 1: a refinement residual restarted the inner solve
   int64_t it_total;    // CG iterations over all steps
   int64_t outer_total;
   // step lengths of the current iteration (finalize) and of the previous

@@ -92,8 +92,20 @@ __device__ __forceinline__ void reduce_partials(const double* __restrict__ P, in
   }
 }
 
-__device__ __forceinline__ int ld_flag(const int32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Solve-control flags written by earlier kernels (kernel boundaries make them
+// visible).  Plain loads of the three adjacent words, issued together.
+struct Ctl {
+  int conv, conv_in, restart;
+};
+__device__ __forceinline__ Ctl ld_ctl(const InstState& S) {
+  return Ctl{S.conv, S.conv_in, S.restart};
+}
+// true when the CG kernels of this instance have nothing to do: the step is
+// solved, or the inner solve of this sweep is done and no refinement
+// residual has restarted it
+__device__ __forceinline__ bool cg_idle(const InstState& S) {
+  const Ctl c = ld_ctl(S);
+  return c.conv != 0 || (c.conv_in != 0 && c.restart == 0);
 }
 
 // z = P^{-1} r for the row i this lane owns.  Jacobi (block 1): one scaling.
@@ -296,7 +308,10 @@ __global__ __launch_bounds__(WG) void k_residual(InstDesc* __restrict__ insts, c
   if (lblk < 0) return;
   InstState& S = I.st;
   // a refinement sweep only restarts an instance whose inner solve is done
-  if (!WITH_RHS && (ld_flag(&S.conv) || !ld_flag(&S.conv_in))) return;
+  if (!WITH_RHS) {
+    const Ctl c = ld_ctl(S);
+    if (c.conv != 0 || c.conv_in == 0) return;
+  }
   const int sig = min(I.bdf, (int)S.step + 1);
   const double* __restrict__ x = I.u_new;
   double v[4] = {0.0, 0.0, 0.0, 0.0};
@@ -363,7 +378,7 @@ __global__ __launch_bounds__(WG) void k_cg_spmv(InstDesc* __restrict__ insts, co
   InstDesc& I = instance<SINGLE>(insts, bmap, lblk);
   if (lblk < 0) return;
   InstState& S = I.st;
-  if (ld_flag(&S.conv) || (ld_flag(&S.conv_in) && !ld_flag(&S.restart))) return;
+  if (cg_idle(S)) return;
   const int sig = min(I.bdf, (int)S.step + 1);
   const int64_t i0 = (int64_t)lblk * TILE + threadIdx.x;
   double v[1] = {0.0};
@@ -397,19 +412,25 @@ __global__ __launch_bounds__(FIN_WG) void k_cg_finalize(InstDesc* __restrict__ i
                                                         const int32_t* __restrict__ ids) {
   InstDesc& I = insts[ids[blockIdx.x]];
   InstState& S = I.st;
-  if (ld_flag(&S.conv) || (ld_flag(&S.conv_in) && !ld_flag(&S.restart))) return;
+  if (cg_idle(S)) return;
   const int nblk = I.nblk;
   const int k = S.it;
   double t[4];
   double dl[1];
-  reduce_partials<FIN_WG, 1>(I.partial + (int64_t)PART_SPMV * nblk, nblk, dl);
+  // one pass over adjacent partial streams: residual [4] + SpMV [1] at the
+  // start of a solve, SpMV [1] + update [2] afterwards
+  static_assert(PART_SPMV == PART_RES + 4 && PART_UPD == PART_SPMV + 1, "partial stream layout");
   if (k == 0) {
-    reduce_partials<FIN_WG, 4>(I.partial + (int64_t)PART_RES * nblk, nblk, t);
+    double a[5];
+    reduce_partials<FIN_WG, 5>(I.partial + (int64_t)PART_RES * nblk, nblk, a);
+    t[0] = a[0]; t[1] = a[1]; t[2] = a[2]; t[3] = a[3];
+    dl[0] = a[4];
   } else {
-    double u[2];
-    reduce_partials<FIN_WG, 2>(I.partial + (int64_t)PART_UPD * nblk, nblk, u);
-    t[0] = u[0];
-    t[1] = u[1];
+    double a[3];
+    reduce_partials<FIN_WG, 3>(I.partial + (int64_t)PART_SPMV * nblk, nblk, a);
+    dl[0] = a[0];
+    t[0] = a[1];
+    t[1] = a[2];
     t[2] = t[3] = 0.0;
   }
   if (threadIdx.x != 0) return;
@@ -496,7 +517,7 @@ __global__ __launch_bounds__(WG) void k_cg_update(InstDesc* __restrict__ insts, 
   InstDesc& I = instance<SINGLE>(insts, bmap, lblk);
   if (lblk < 0) return;
   InstState& S = I.st;
-  if (ld_flag(&S.conv) || (ld_flag(&S.conv_in) && !ld_flag(&S.restart))) return;
+  if (cg_idle(S)) return;
   const int k = S.it_f;
   const double alpha = S.alpha_cur, beta = S.beta;
   const int sig = min(I.bdf, (int)S.step + 1);
