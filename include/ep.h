@@ -71,8 +71,18 @@ enum {
   EP_OPT_INNER_RTOL = 2,    /* mixed precision: inner FP32 CG relative tolerance (1e-4)  */
   EP_OPT_MAX_OUTER = 3,     /* mixed precision: max refinement sweeps per step (30)      */
   EP_OPT_PHASE_TIMERS = 4,  /* 1: time ionic / rhs / solve / activation phases (any time) */
-  EP_OPT_KERNEL_TIMERS = 5  /* 1: bracket every kernel launch with HIP events and sum
+  EP_OPT_KERNEL_TIMERS = 5, /* 1: bracket every kernel launch with HIP events and sum
                                their durations per kernel (any time; resets the sums) */
+  /* Launch shapes (any time; also ep_pool_set_option).  They change which
+   * thread or workgroup computes a node, never the arithmetic: results are
+   * bitwise the same for every setting. */
+  EP_OPT_IONIC_NPT = 6,     /* nodes per thread of the ionic kernel: 1 (512-thread
+                               workgroups, default), 2 (256) or 4 (128)               */
+  EP_OPT_TILE_MAP = 7,      /* 0: each XCD sweeps a contiguous range of 512-row tiles
+                               (default); 1: workgroup b takes tile b                 */
+  EP_OPT_GRAPH = 8          /* 1: replay the step's launch sequences from captured
+                               HIP graphs (ignored while timers are on).  The stream
+                               must allow capture (not the legacy null stream).      */
 };
 
 /* Kernel kinds reported by ep_sim_get_kernel_times. */
@@ -207,6 +217,16 @@ ep_status ep_sim_get_stats(ep_sim* sim, ep_stats* out);
  * converged return at once and are counted too. */
 ep_status ep_sim_get_kernel_times(ep_sim* sim, double* ms, int64_t* launches);
 
+/* Launch-shape tuner (a growth direction, not in the paper): runs
+ * trial_steps steps per candidate with kernel timers on, first for the
+ * ionic nodes per thread (1, 2, 4; scored by the ionic kernel's mean time),
+ * then for the tile map (0, 1; scored by the mean SpMV + CG-update time),
+ * and keeps the fastest of each.  The 5 * trial_steps steps advance the
+ * simulation like ep_sim_step (results do not depend on the shapes).
+ * Writes the chosen EP_OPT_IONIC_NPT and EP_OPT_TILE_MAP values to the
+ * non-NULL outputs.  EP_ESTATE before finalize or while pooled. */
+ep_status ep_sim_autotune(ep_sim* sim, int trial_steps, int* ionic_npt, int* tile_map);
+
 /* Raw state in model units (after finalize).  u: [n_nodes]; w: [n_vars][n_nodes]
  * in the model's state order (AP: v; BO: v, w, s; TTP06: m h j xr1 xr2 xs s r
  * d f f2 fcass cai casr cass nai ki rr); u_prev: [bdf-1][n_nodes] holding
@@ -246,6 +266,15 @@ ep_status ep_pool_release(ep_pool* pool, int slot, ep_sim** sim_out);
  * released either way) */
 
 ep_status ep_pool_get_info(ep_pool* pool, int* n_active, size_t* bytes_in_use);
+
+/* EP_OPT_IONIC_NPT, EP_OPT_TILE_MAP (0: the workgroup list of each launch is
+ * ordered so that each XCD receives a contiguous run; 1: list order) and
+ * EP_OPT_GRAPH for the pool's own launches.  EP_EINVAL for other keys. */
+ep_status ep_pool_set_option(ep_pool* pool, int key, double value);
+
+/* ep_sim_autotune for the pool's launches: trial_steps pool steps per
+ * candidate; the steps advance every active slot. */
+ep_status ep_pool_autotune(ep_pool* pool, int trial_steps, int* ionic_npt, int* tile_map);
 void ep_pool_destroy(ep_pool* pool);
 
 /* Estimated device bytes ep_sim_finalize would allocate (sim configured, not

@@ -26,6 +26,7 @@ EP_DTYPE_F64, EP_DTYPE_F32 = 0, 1
 EP_FMT_AUTO, EP_FMT_SELL, EP_FMT_DIA = 0, 1, 2
 EP_OPT_MATRIX_FORMAT, EP_OPT_INNER_RTOL, EP_OPT_MAX_OUTER, EP_OPT_PHASE_TIMERS = 1, 2, 3, 4
 EP_OPT_KERNEL_TIMERS = 5
+EP_OPT_IONIC_NPT, EP_OPT_TILE_MAP, EP_OPT_GRAPH = 6, 7, 8
 KERNEL_KINDS = ["ionic", "rhs", "cg_spmv", "cg_update", "activation", "ir_residual", "cg_finalize"]
 
 MODEL_IDS = {"passive": EP_PASSIVE, "ap": EP_AP, "bo": EP_BO, "ttp06": EP_TTP06}
@@ -89,6 +90,13 @@ class Simulation:
 
     def set_option(self, key, value):
         check(lib.ep_sim_set_option(self._h, int(key), float(value)), "ep_sim_set_option")
+
+    def autotune(self, trial_steps: int = 10):
+        """Launch-shape tuner (advances the simulation by 5 * trial_steps
+        steps); returns (ionic nodes per thread, tile map)."""
+        a, b = C.c_int32(), C.c_int32()
+        check(lib.ep_sim_autotune(self._h, int(trial_steps), C.byref(a), C.byref(b)), "ep_sim_autotune")
+        return a.value, b.value
 
     def finalize(self):
         check(lib.ep_sim_finalize(self._h), "ep_sim_finalize")
@@ -237,6 +245,15 @@ class Pool:
         st = check(lib.ep_pool_release(self._h, int(slot), C.byref(out)), "ep_pool_release",
                    allow=(_lib.EP_ENAN, _lib.EP_ENOCONV) if allow_error else ())
         return self.sims.pop(slot), st
+
+    def set_option(self, key, value):
+        check(lib.ep_pool_set_option(self._h, int(key), float(value)), "ep_pool_set_option")
+
+    def autotune(self, trial_steps: int = 10):
+        """ep_pool_autotune; returns (ionic nodes per thread, tile map)."""
+        a, b = C.c_int32(), C.c_int32()
+        check(lib.ep_pool_autotune(self._h, int(trial_steps), C.byref(a), C.byref(b)), "ep_pool_autotune")
+        return a.value, b.value
 
     def info(self):
         a = C.c_int32()

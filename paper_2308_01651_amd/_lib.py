@@ -80,6 +80,9 @@ _SIGS = {
     "ep_pool_poll": [P, PI32, C.c_int, PI32],
     "ep_pool_release": [P, C.c_int, PP],
     "ep_pool_get_info": [P, PI32, C.POINTER(C.c_size_t)],
+    "ep_pool_set_option": [P, C.c_int, C.c_double],
+    "ep_pool_autotune": [P, C.c_int, PI32, PI32],
+    "ep_sim_autotune": [P, C.c_int, PI32, PI32],
     "ep_assemble_csr": [C.c_int, C.c_int64, PD, C.c_int64, PI32, PD, PD, PD, C.c_double, C.c_double,
                         C.c_double, C.c_double, C.c_double, PI64, PI64, PI32, PD, PD],
 }

@@ -123,6 +123,102 @@ struct Stim {
   double size, amp, t0, dur, period;
 };
 
+// Per-kernel event timers: kinds 0 ionic, 1 rhs residual, 2 cg spmv,
+// 3 cg update, 4 activation, 5 refinement residual, 6 cg finalize.
+struct KernelTimers {
+  static constexpr int K = 7;
+  int on = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[K];
+  std::vector<hipEvent_t> spare;
+  double ms[K] = {0, 0, 0, 0, 0, 0, 0};
+  int64_t count[K] = {0, 0, 0, 0, 0, 0, 0};
+  hipEvent_t get() {
+    if (!spare.empty()) {
+      hipEvent_t e = spare.back();
+      spare.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  // launch fn bracketed by events when the timers are on
+  template <typename F>
+  void timed(hipStream_t st, int kind, F&& fn) {
+    if (!on) {
+      fn();
+      return;
+    }
+    hipEvent_t a = get(), b = get();
+    if (!a || !b) {
+      fn();
+      return;
+    }
+    (void)hipEventRecord(a, st);
+    fn();
+    (void)hipEventRecord(b, st);
+    pending[kind].emplace_back(a, b);
+  }
+  // add up completed event pairs (after a stream synchronization)
+  void harvest() {
+    for (int k = 0; k < K; k++) {
+      for (auto& pr : pending[k]) {
+        float t = 0.0f;
+        if (hipEventElapsedTime(&t, pr.first, pr.second) == hipSuccess) {
+          ms[k] += t;
+          count[k] += 1;
+        }
+        spare.push_back(pr.first);
+        spare.push_back(pr.second);
+      }
+      pending[k].clear();
+    }
+  }
+  void zero() {
+    for (int k = 0; k < K; k++) {
+      ms[k] = 0.0;
+      count[k] = 0;
+    }
+  }
+  double avg_us(int k) const { return count[k] ? 1e3 * ms[k] / (double)count[k] : 0.0; }
+  void destroy() {
+    harvest();
+    for (auto e : spare) (void)hipEventDestroy(e);
+    spare.clear();
+  }
+};
+
+// The launch sequences of one step captured as HIP graphs and replayed: the
+// step prologue (ionic, rhs residual, SpMV, finalize), one and two CG rounds
+// (update, SpMV, finalize), a refinement sweep (residual, SpMV, finalize) and
+// the epilogue (activation, end of step).  Every kernel reads its per-step
+// control from device memory, so the graphs stay valid across steps; they
+// are dropped when the launch configuration changes.
+struct StepGraphs {
+  hipGraphExec_t pro = nullptr, round1 = nullptr, round2 = nullptr, ir = nullptr, epi = nullptr;
+  bool valid = false;
+  void reset() {
+    for (hipGraphExec_t* g : {&pro, &round1, &round2, &ir, &epi}) {
+      if (*g) (void)hipGraphExecDestroy(*g);
+      *g = nullptr;
+    }
+    valid = false;
+  }
+};
+
+template <typename F>
+hipError_t capture_graph(hipStream_t st, F&& fn, hipGraphExec_t* out) {
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  fn();
+  e = hipStreamEndCapture(st, &g);
+  if (e != hipSuccess) return e;
+  e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  return e;
+}
+
 }  // namespace
 
 struct ep_sim {
@@ -159,13 +255,10 @@ struct ep_sim {
   double ms_setup = 0.0;
   double ms_phase[4] = {0, 0, 0, 0};
   hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-  // per-kernel event timers: kinds 0 ionic, 1 rhs residual, 2 cg spmv,
-  // 3 cg update, 4 activation, 5 refinement residual, 6 cg finalize
-  int ktimers = 0;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> kt_pending[7];
-  std::vector<hipEvent_t> kt_free;
-  double kt_ms[7] = {0, 0, 0, 0, 0, 0, 0};
-  int64_t kt_count[7] = {0, 0, 0, 0, 0, 0, 0};
+  KernelTimers kt;
+  // launch shapes (see Launch) and graph replay of the step
+  int xmap = 0, ionic_npt = 1, use_graph = 0;
+  StepGraphs graphs;
   int32_t* d_ids = nullptr;  // device list {0}: the instance advanced by k_end_step
   InstDesc* d_desc_own = nullptr;  // the sim's own descriptor (d_desc points into a pool table while pooled)
   hipStream_t stream_own = nullptr;
@@ -185,12 +278,10 @@ ep_status check_sim(ep_sim* s) {
 }
 
 // Read the device state into pinned host memory (synchronizes the stream).
-void kt_harvest(ep_sim* s);
-
 ep_status pull_state(ep_sim* s) {
   EP_HIP(hipMemcpyAsync(s->h_st, s->d_st, sizeof(InstState), hipMemcpyDeviceToHost, s->stream));
   EP_HIP(hipStreamSynchronize(s->stream));
-  if (s->ktimers) kt_harvest(s);
+  if (s->kt.on) s->kt.harvest();
   return EP_OK;
 }
 
@@ -642,51 +733,11 @@ ep_status validate_desc(const InstDesc& D, int64_t guard) {
   return EP_OK;
 }
 
-Launch launch_of(ep_sim* s) { return Launch{s->d_desc, s->d_bmap, s->nblocks, s->stream, true}; }
-
-hipEvent_t kt_event(ep_sim* s) {
-  if (!s->kt_free.empty()) {
-    hipEvent_t e = s->kt_free.back();
-    s->kt_free.pop_back();
-    return e;
-  }
-  hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
-  return e;
-}
-
-// Launch `fn` bracketed by events when kernel timers are on.
-template <typename F>
-void timed(ep_sim* s, int kind, F&& fn) {
-  if (!s->ktimers) {
-    fn();
-    return;
-  }
-  hipEvent_t a = kt_event(s), b = kt_event(s);
-  if (!a || !b) {
-    fn();
-    return;
-  }
-  (void)hipEventRecord(a, s->stream);
-  fn();
-  (void)hipEventRecord(b, s->stream);
-  s->kt_pending[kind].emplace_back(a, b);
-}
-
-// Harvest completed event pairs (call after a stream synchronization).
-void kt_harvest(ep_sim* s) {
-  for (int k = 0; k < 7; k++) {
-    for (auto& pr : s->kt_pending[k]) {
-      float ms = 0.0f;
-      if (hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) {
-        s->kt_ms[k] += ms;
-        s->kt_count[k] += 1;
-      }
-      s->kt_free.push_back(pr.first);
-      s->kt_free.push_back(pr.second);
-    }
-    s->kt_pending[k].clear();
-  }
+Launch launch_of(ep_sim* s) {
+  Launch L{s->d_desc, s->d_bmap, s->nblocks, s->stream, true};
+  L.xmap = s->xmap;
+  L.ionic_npt = s->ionic_npt;
+  return L;
 }
 
 // One time step of one sim (host sequencing; all arithmetic on the device).
@@ -694,31 +745,70 @@ void kt_harvest(ep_sim* s) {
 // {update, SpMV, finalize}; each finalize decides convergence on the device,
 // and the host reads that flag after a chunk of rounds.  Mixed precision
 // appends an FP64 refinement residual (+ SpMV, finalize) after each inner
-// sweep.
+// sweep.  With graphs on (and no timers), the same sequences are replayed
+// from captured graphs.
 ep_status step_once(ep_sim* s) {
   const Launch L = launch_of(s);
   const bool mixed = s->prec == EP_MIXED;
-  auto fin = [&] { timed(s, 6, [&] { launch_cg_finalize(mixed, s->d_desc, s->d_ids, 1, s->stream); }); };
+  KernelTimers& kt = s->kt;
+  hipStream_t st = s->stream;
+  auto fin = [&] { kt.timed(st, 6, [&] { launch_cg_finalize(mixed, s->d_desc, s->d_ids, 1, st); }); };
   auto round = [&] {
-    timed(s, 3, [&] { launch_cg_update(mixed, L); });
-    timed(s, 2, [&] { launch_cg_spmv(mixed, L); });
+    kt.timed(st, 3, [&] { launch_cg_update(mixed, L); });
+    kt.timed(st, 2, [&] { launch_cg_spmv(mixed, L); });
     fin();
   };
-  if (s->timers) EP_HIP(hipEventRecord(s->ev[0], s->stream));
-  timed(s, 0, [&] { launch_ionic(s->model, mixed, L); });
-  if (s->timers) EP_HIP(hipEventRecord(s->ev[1], s->stream));
-  timed(s, 1, [&] { launch_residual(mixed, true, L); });
-  if (s->timers) EP_HIP(hipEventRecord(s->ev[2], s->stream));
-  timed(s, 2, [&] { launch_cg_spmv(mixed, L); });
-  fin();
+  auto pro = [&] {
+    if (s->timers) (void)hipEventRecord(s->ev[0], st);
+    kt.timed(st, 0, [&] { launch_ionic(s->model, mixed, L); });
+    if (s->timers) (void)hipEventRecord(s->ev[1], st);
+    kt.timed(st, 1, [&] { launch_residual(mixed, true, L); });
+    if (s->timers) (void)hipEventRecord(s->ev[2], st);
+    kt.timed(st, 2, [&] { launch_cg_spmv(mixed, L); });
+    fin();
+  };
+  auto ir = [&] {
+    kt.timed(st, 5, [&] { launch_residual(true, false, L); });
+    kt.timed(st, 2, [&] { launch_cg_spmv(true, L); });
+    fin();
+  };
+  auto epi = [&] {
+    if (s->timers) (void)hipEventRecord(s->ev[3], st);
+    kt.timed(st, 4, [&] { launch_activation(L); });
+    launch_end_step(s->d_desc, s->d_ids, 1, st);
+  };
+  const bool graph = s->use_graph && !kt.on && !s->timers;
+  StepGraphs& G = s->graphs;
+  if (graph && !G.valid) {
+    G.reset();
+    EP_HIP(capture_graph(st, pro, &G.pro));
+    EP_HIP(capture_graph(st, round, &G.round1));
+    EP_HIP(capture_graph(st, [&] { round(); round(); }, &G.round2));
+    if (mixed) EP_HIP(capture_graph(st, ir, &G.ir));
+    EP_HIP(capture_graph(st, epi, &G.epi));
+    G.valid = true;
+  }
+  auto rounds = [&](int c) -> hipError_t {
+    if (!graph) {
+      for (int k = 0; k < c; k++) round();
+      return hipGetLastError();
+    }
+    for (; c >= 2; c -= 2) {
+      hipError_t e = hipGraphLaunch(G.round2, st);
+      if (e != hipSuccess) return e;
+    }
+    return c ? hipGraphLaunch(G.round1, st) : hipSuccess;
+  };
+  if (graph) EP_HIP(hipGraphLaunch(G.pro, st));
+  else pro();
   if (!mixed) {
     int chunk = std::max(1, s->it_pred);
-    for (int rounds = 0;; rounds++) {
-      for (int c = 0; c < chunk; c++) round();
+    for (int n_rounds = 0;; n_rounds++) {
+      EP_HIP(rounds(chunk));
       ep_status rc = pull_state(s);
       if (rc != EP_OK) return rc;
       if (s->h_st->conv) break;
-      if (rounds > s->max_it + 2) return fail(EP_EHIP, "solver control lost (no convergence flag)");
+      if (n_rounds > s->max_it + 2) return fail(EP_EHIP, "solver control lost (no convergence flag)");
       chunk = 2;
     }
     s->it_pred = std::max(1, s->h_st->it_step);
@@ -726,10 +816,9 @@ ep_status step_once(ep_sim* s) {
     int before = 0;
     for (int sweeps = 0;; sweeps++) {
       const int chunk = std::max(1, s->in_pred);
-      for (int c = 0; c < chunk; c++) round();
-      timed(s, 5, [&] { launch_residual(true, false, L); });
-      timed(s, 2, [&] { launch_cg_spmv(true, L); });
-      fin();
+      EP_HIP(rounds(chunk));
+      if (graph) EP_HIP(hipGraphLaunch(G.ir, st));
+      else ir();
       ep_status rc = pull_state(s);
       if (rc != EP_OK) return rc;
       const int done = s->h_st->it_step - before;
@@ -740,11 +829,10 @@ ep_status step_once(ep_sim* s) {
       if (sweeps > s->max_outer + 2) return fail(EP_EHIP, "solver control lost (no convergence flag)");
     }
   }
-  if (s->timers) EP_HIP(hipEventRecord(s->ev[3], s->stream));
-  timed(s, 4, [&] { launch_activation(L); });
-  launch_end_step(s->d_desc, s->d_ids, 1, s->stream);
+  if (graph) EP_HIP(hipGraphLaunch(G.epi, st));
+  else epi();
   if (s->timers) {
-    EP_HIP(hipEventRecord(s->ev[4], s->stream));
+    EP_HIP(hipEventRecord(s->ev[4], st));
     EP_HIP(hipEventSynchronize(s->ev[4]));
     for (int k = 0; k < 4; k++) {
       float ms = 0;
@@ -755,6 +843,37 @@ ep_status step_once(ep_sim* s) {
   const int flags = s->h_st->flags;
   if (flags & F_NAN) return EP_ENAN;
   if (flags & (F_NOCONV | F_BREAKDOWN)) return EP_ENOCONV;
+  return EP_OK;
+}
+
+// Tuner core: run `trial` steps per candidate of one launch-shape setting
+// with kernel timers on, score each candidate by the mean duration of the
+// kernels it affects, keep the best.  The steps are real steps of the
+// simulation; every candidate computes bitwise the same results.
+template <typename Step, typename Set, typename Score>
+ep_status tune_one(KernelTimers& kt, hipStream_t st, int trial, const std::vector<int>& cands, Set&& set,
+                   Step&& step, Score&& score, int* best_out) {
+  double best = std::numeric_limits<double>::infinity();
+  int best_c = cands.front();
+  for (int c : cands) {
+    set(c);
+    EP_HIP(hipStreamSynchronize(st));
+    kt.harvest();
+    kt.zero();
+    for (int k = 0; k < trial; k++) {
+      ep_status rc = step();
+      if (rc != EP_OK && rc != EP_ENOCONV) return rc;
+    }
+    EP_HIP(hipStreamSynchronize(st));
+    kt.harvest();
+    const double t = score();
+    if (t < best) {
+      best = t;
+      best_c = c;
+    }
+  }
+  set(best_c);
+  *best_out = best_c;
   return EP_OK;
 }
 
@@ -881,12 +1000,22 @@ ep_status ep_sim_set_option(ep_sim* s, int key, double value) {
   }
   if (key == EP_OPT_KERNEL_TIMERS) {
     if (s->stream) (void)hipStreamSynchronize(s->stream);
-    kt_harvest(s);
-    s->ktimers = value != 0.0;
-    for (int k = 0; k < 7; k++) {
-      s->kt_ms[k] = 0.0;
-      s->kt_count[k] = 0;
-    }
+    s->kt.harvest();
+    s->kt.on = value != 0.0;
+    s->kt.zero();
+    return EP_OK;
+  }
+  if (key == EP_OPT_IONIC_NPT || key == EP_OPT_TILE_MAP || key == EP_OPT_GRAPH) {
+    const int v = (int)value;
+    if ((double)v != value) return fail(EP_EINVAL, "launch option values are integers");
+    if (key == EP_OPT_IONIC_NPT && v != 1 && v != 2 && v != 4) return fail(EP_EINVAL, "ionic nodes per thread: 1, 2 or 4");
+    if (key == EP_OPT_TILE_MAP && v != 0 && v != 1) return fail(EP_EINVAL, "tile map: 0 or 1");
+    if (key == EP_OPT_GRAPH && v != 0 && v != 1) return fail(EP_EINVAL, "graph: 0 or 1");
+    if (s->stream) EP_HIP(hipStreamSynchronize(s->stream));
+    if (key == EP_OPT_IONIC_NPT) s->ionic_npt = v;
+    if (key == EP_OPT_TILE_MAP) s->xmap = v;
+    if (key == EP_OPT_GRAPH) s->use_graph = v;
+    s->graphs.reset();
     return EP_OK;
   }
   if (s->finalized) return fail(EP_ESTATE, "sim already finalized");
@@ -940,6 +1069,35 @@ ep_status ep_sim_step(ep_sim* s, int n_steps) {
     }
   }
   return worst;
+}
+
+ep_status ep_sim_autotune(ep_sim* s, int trial_steps, int* ionic_npt, int* tile_map) {
+  if (check_sim(s)) return EP_EINVAL;
+  if (!s->finalized) return fail(EP_ESTATE, "finalize first");
+  if (s->in_pool) return fail(EP_ESTATE, "sim is stepped by its pool");
+  if (trial_steps < 1) return fail(EP_EINVAL, "trial_steps must be >= 1");
+  EP_HIP(hipSetDevice(s->device));
+  KernelTimers& kt = s->kt;
+  EP_HIP(hipStreamSynchronize(s->stream));
+  kt.harvest();
+  const int was_on = kt.on;
+  kt.on = 1;
+  auto step = [&] { return step_once(s); };
+  int npt = s->ionic_npt, xm = s->xmap;
+  ep_status rc = tune_one(
+      kt, s->stream, trial_steps, {1, 2, 4}, [&](int c) { s->ionic_npt = c; }, step,
+      [&] { return kt.avg_us(0); }, &npt);
+  if (rc == EP_OK)
+    rc = tune_one(
+        kt, s->stream, trial_steps, {0, 1}, [&](int c) { s->xmap = c; }, step,
+        [&] { return kt.avg_us(2) + kt.avg_us(3); }, &xm);
+  kt.zero();
+  kt.on = was_on;
+  s->graphs.reset();
+  if (rc != EP_OK) return rc;
+  if (ionic_npt) *ionic_npt = npt;
+  if (tile_map) *tile_map = xm;
+  return EP_OK;
 }
 
 ep_status ep_sim_sync(ep_sim* s) {
@@ -1129,10 +1287,10 @@ ep_status ep_sim_get_stats(ep_sim* s, ep_stats* o) {
 ep_status ep_sim_get_kernel_times(ep_sim* s, double* ms, int64_t* launches) {
   if (check_sim(s) || !ms || !launches) return fail(EP_EINVAL, "null argument");
   if (s->stream) EP_HIP(hipStreamSynchronize(s->stream));
-  kt_harvest(s);
+  s->kt.harvest();
   for (int k = 0; k < 7; k++) {
-    ms[k] = s->kt_ms[k];
-    launches[k] = s->kt_count[k];
+    ms[k] = s->kt.ms[k];
+    launches[k] = s->kt.count[k];
   }
   return EP_OK;
 }
@@ -1141,8 +1299,8 @@ void ep_sim_destroy(ep_sim* s) {
   if (!s) return;
   (void)hipSetDevice(s->device);
   if (s->stream) (void)hipStreamSynchronize(s->stream);
-  kt_harvest(s);
-  for (auto e : s->kt_free) (void)hipEventDestroy(e);
+  s->kt.destroy();
+  s->graphs.reset();
   for (auto& e : s->ev)
     if (e) (void)hipEventDestroy(e);
   s->mem.release();
@@ -1206,6 +1364,9 @@ struct ep_pool {
   int nb_model[4] = {0, 0, 0, 0};
   int32_t* d_ids = nullptr;
   int it_pred = 8, in_pred = 8;
+  KernelTimers kt;
+  int ionic_npt = 1, list_order = 0, use_graph = 0;  // launch shapes (EP_OPT_*)
+  StepGraphs graphs;
 };
 
 namespace {
@@ -1226,6 +1387,7 @@ std::vector<BlockMap> xcd_order(const std::vector<BlockMap>& items) {
 ep_status pool_rebuild(ep_pool* P) {
   // kernels of the previous step may still read the old tables
   EP_HIP(hipStreamSynchronize(P->stream));
+  P->graphs.reset();
   P->maps.release();
   P->active.clear();
   for (int k = 0; k < P->max_slots; k++)
@@ -1243,7 +1405,7 @@ ep_status pool_rebuild(ep_pool* P) {
     *nb = 0;
     *d = nullptr;
     if (v.empty()) return hipSuccess;
-    std::vector<BlockMap> o = xcd_order(v);
+    std::vector<BlockMap> o = P->list_order ? v : xcd_order(v);
     *nb = (int)o.size();
     hipError_t e = P->maps.alloc((void**)d, o.size() * sizeof(BlockMap));
     if (e != hipSuccess) return e;
@@ -1285,35 +1447,79 @@ int pool_iters(ep_pool* P) {
 ep_status pool_step_once(ep_pool* P) {
   const bool mixed = P->prec == EP_MIXED;
   const int ni = (int)P->active.size();
-  const Launch L{P->d_table, P->d_all, P->nb_all, P->stream, false};
-  auto fin = [&] { launch_cg_finalize(mixed, P->d_table, P->d_ids, ni, P->stream); };
+  Launch L{P->d_table, P->d_all, P->nb_all, P->stream, false};
+  L.ionic_npt = P->ionic_npt;
+  KernelTimers& kt = P->kt;
+  hipStream_t st = P->stream;
+  auto fin = [&] { kt.timed(st, 6, [&] { launch_cg_finalize(mixed, P->d_table, P->d_ids, ni, st); }); };
   auto round = [&] {
-    launch_cg_update(mixed, L);
-    launch_cg_spmv(mixed, L);
+    kt.timed(st, 3, [&] { launch_cg_update(mixed, L); });
+    kt.timed(st, 2, [&] { launch_cg_spmv(mixed, L); });
     fin();
   };
-  for (int m = 0; m < 4; m++)
-    if (P->nb_model[m] > 0) launch_ionic(m, mixed, Launch{P->d_table, P->d_model[m], P->nb_model[m], P->stream, false});
-  launch_residual(mixed, true, L);
-  launch_cg_spmv(mixed, L);
-  fin();
+  auto pro = [&] {
+    kt.timed(st, 0, [&] {
+      for (int m = 0; m < 4; m++)
+        if (P->nb_model[m] > 0) {
+          Launch Lm{P->d_table, P->d_model[m], P->nb_model[m], st, false};
+          Lm.ionic_npt = P->ionic_npt;
+          launch_ionic(m, mixed, Lm);
+        }
+    });
+    kt.timed(st, 1, [&] { launch_residual(mixed, true, L); });
+    kt.timed(st, 2, [&] { launch_cg_spmv(mixed, L); });
+    fin();
+  };
+  auto ir = [&] {
+    kt.timed(st, 5, [&] { launch_residual(true, false, L); });
+    kt.timed(st, 2, [&] { launch_cg_spmv(true, L); });
+    fin();
+  };
+  auto epi = [&] {
+    kt.timed(st, 4, [&] { launch_activation(L); });
+    launch_end_step(P->d_table, P->d_ids, ni, st);
+  };
+  const bool graph = P->use_graph && !kt.on;
+  StepGraphs& G = P->graphs;
+  if (graph && !G.valid) {
+    G.reset();
+    EP_HIP(capture_graph(st, pro, &G.pro));
+    EP_HIP(capture_graph(st, round, &G.round1));
+    EP_HIP(capture_graph(st, [&] { round(); round(); }, &G.round2));
+    if (mixed) EP_HIP(capture_graph(st, ir, &G.ir));
+    EP_HIP(capture_graph(st, epi, &G.epi));
+    G.valid = true;
+  }
+  auto rounds = [&](int c) -> hipError_t {
+    if (!graph) {
+      for (int k = 0; k < c; k++) round();
+      return hipGetLastError();
+    }
+    for (; c >= 2; c -= 2) {
+      hipError_t e = hipGraphLaunch(G.round2, st);
+      if (e != hipSuccess) return e;
+    }
+    return c ? hipGraphLaunch(G.round1, st) : hipSuccess;
+  };
+  if (graph) EP_HIP(hipGraphLaunch(G.pro, st));
+  else pro();
   int chunk = std::max(1, mixed ? P->in_pred : P->it_pred);
-  for (int rounds = 0;; rounds++) {
-    for (int c = 0; c < chunk; c++) round();
+  for (int n_rounds = 0;; n_rounds++) {
+    EP_HIP(rounds(chunk));
     if (mixed) {
-      launch_residual(true, false, L);
-      launch_cg_spmv(true, L);
-      fin();
+      if (graph) EP_HIP(hipGraphLaunch(G.ir, st));
+      else ir();
     }
     ep_status rc = pool_pull(P);
     if (rc != EP_OK) return rc;
+    if (P->kt.on) P->kt.harvest();
     if (pool_all_conv(P)) break;
-    if (rounds > 20000) return fail(EP_EHIP, "pool solver control lost (no convergence flag)");
+    if (n_rounds > 20000) return fail(EP_EHIP, "pool solver control lost (no convergence flag)");
     if (!mixed) chunk = 2;
   }
   if (!mixed) P->it_pred = std::max(1, pool_iters(P));
-  launch_activation(L);
-  launch_end_step(P->d_table, P->d_ids, ni, P->stream);
+  if (graph) EP_HIP(hipGraphLaunch(G.epi, st));
+  else epi();
   EP_HIP(hipGetLastError());
   bool changed = false;
   for (int k : P->active) {
@@ -1403,6 +1609,7 @@ ep_status ep_pool_admit(ep_pool* P, ep_sim* s, int64_t n_steps_total, int* slot)
   EP_HIP(hipStreamSynchronize(P->stream));
   s->d_desc = dst;
   s->d_st = reinterpret_cast<InstState*>(reinterpret_cast<char*>(dst) + offsetof(InstDesc, st));
+  s->graphs.reset();
   s->in_pool = true;
   s->pool_slot = free_slot;
   ep_pool::Slot& sl = P->slots[free_slot];
@@ -1452,6 +1659,7 @@ ep_status ep_pool_release(ep_pool* P, int slot, ep_sim** sim_out) {
   EP_HIP(hipStreamSynchronize(P->stream));
   s->d_desc = s->d_desc_own;
   s->d_st = reinterpret_cast<InstState*>(reinterpret_cast<char*>(s->d_desc) + offsetof(InstDesc, st));
+  s->graphs.reset();
   s->stream = s->stream_own;
   s->in_pool = false;
   s->pool_slot = -1;
@@ -1478,12 +1686,75 @@ ep_status ep_pool_get_info(ep_pool* P, int* n_active, size_t* bytes_in_use) {
   return EP_OK;
 }
 
+ep_status ep_pool_set_option(ep_pool* P, int key, double value) {
+  if (!P) return fail(EP_EINVAL, "null pool");
+  const int v = (int)value;
+  if ((double)v != value) return fail(EP_EINVAL, "launch option values are integers");
+  if (key == EP_OPT_IONIC_NPT) {
+    if (v != 1 && v != 2 && v != 4) return fail(EP_EINVAL, "ionic nodes per thread: 1, 2 or 4");
+  } else if (key == EP_OPT_TILE_MAP || key == EP_OPT_GRAPH) {
+    if (v != 0 && v != 1) return fail(EP_EINVAL, "option value: 0 or 1");
+  } else {
+    return fail(EP_EINVAL, "unknown pool option");
+  }
+  EP_HIP(hipSetDevice(P->device));
+  EP_HIP(hipStreamSynchronize(P->stream));
+  if (key == EP_OPT_IONIC_NPT) P->ionic_npt = v;
+  if (key == EP_OPT_GRAPH) P->use_graph = v;
+  if (key == EP_OPT_TILE_MAP && P->list_order != v) {
+    P->list_order = v;
+    P->dirty = true;
+  }
+  P->graphs.reset();
+  return EP_OK;
+}
+
+ep_status ep_pool_autotune(ep_pool* P, int trial_steps, int* ionic_npt, int* tile_map) {
+  if (!P || trial_steps < 1) return fail(EP_EINVAL, "bad autotune arguments");
+  EP_HIP(hipSetDevice(P->device));
+  EP_HIP(hipStreamSynchronize(P->stream));
+  KernelTimers& kt = P->kt;
+  kt.harvest();
+  kt.on = 1;
+  auto step = [&]() -> ep_status {
+    if (P->dirty) {
+      ep_status rc = pool_rebuild(P);
+      if (rc != EP_OK) return rc;
+    }
+    if (P->active.empty()) return EP_OK;
+    return pool_step_once(P);
+  };
+  int npt = P->ionic_npt, lo = P->list_order;
+  ep_status rc = tune_one(
+      kt, P->stream, trial_steps, {1, 2, 4}, [&](int c) { P->ionic_npt = c; }, step,
+      [&] { return kt.avg_us(0); }, &npt);
+  if (rc == EP_OK)
+    rc = tune_one(
+        kt, P->stream, trial_steps, {0, 1},
+        [&](int c) {
+          if (P->list_order != c) {
+            P->list_order = c;
+            P->dirty = true;
+          }
+        },
+        step, [&] { return kt.avg_us(2) + kt.avg_us(3); }, &lo);
+  kt.zero();
+  kt.on = 0;
+  P->graphs.reset();
+  if (rc != EP_OK) return rc;
+  if (ionic_npt) *ionic_npt = npt;
+  if (tile_map) *tile_map = lo;
+  return EP_OK;
+}
+
 void ep_pool_destroy(ep_pool* P) {
   if (!P) return;
   (void)hipSetDevice(P->device);
   (void)hipStreamSynchronize(P->stream);
   for (int k = 0; k < P->max_slots; k++)
     if (P->slots[k].sim) (void)ep_pool_release(P, k, nullptr);
+  P->graphs.reset();
+  P->kt.destroy();
   P->maps.release();
   P->mem.release();
   if (P->h_states) (void)hipHostFree(P->h_states);

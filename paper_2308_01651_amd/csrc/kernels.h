@@ -8,13 +8,18 @@ namespace ep {
 
 // One launch over a block map: nblocks workgroups, workgroup b working on
 // instance bmap[b].inst, node tile bmap[b].lblk.  single: the table holds one
-// instance and workgroup b works on its tile b (no block map read).
+// instance and workgroups map to its tiles without a block map read (xmap 0:
+// each XCD sweeps a contiguous range of tiles; 1: workgroup b takes tile b).
+// ionic_npt: nodes per thread of the ionic kernel (1, 2 or 4; TILE / npt
+// threads per workgroup).
 struct Launch {
   InstDesc* insts;
   const BlockMap* bmap;
   int nblocks;
   hipStream_t stream;
   bool single;
+  int xmap = 0;
+  int ionic_npt = 1;
 };
 
 void launch_ionic(int model, bool mixed, const Launch& L);

@@ -184,11 +184,17 @@ __device__ __forceinline__ A spmv_row(const InstDesc& I, const V* __restrict__ v
 // tiles, so stencil neighbours of a tile mostly sit in the same die's L2.
 // The launch has N_XCD * per workgroups; those past the last tile get
 // lblk = -1 and must leave at once.
-template <bool SINGLE>
+// XMAP = 1 maps workgroup b to tile b (dispatch order), for comparison by the
+// tuner.
+template <bool SINGLE, int XMAP = 0>
 __device__ __forceinline__ InstDesc& instance(InstDesc* __restrict__ insts, const BlockMap* __restrict__ bmap,
                                               int& lblk) {
   if (SINGLE) {
     InstDesc& I = insts[0];
+    if (XMAP == 1) {
+      lblk = (int)blockIdx.x < I.nblk ? (int)blockIdx.x : -1;
+      return I;
+    }
     const int per = (I.nblk + N_XCD - 1) / N_XCD;
     const int t = (int)(blockIdx.x % N_XCD) * per + (int)(blockIdx.x / N_XCD);
     lblk = t < I.nblk ? t : -1;
@@ -287,13 +293,20 @@ __device__ __forceinline__ void ionic_node(const InstDesc& I, int64_t n, int64_t
   I.u_new[i] = u_ext;
 }
 
-template <int MODEL, bool MIXED, bool SINGLE>
-__global__ __launch_bounds__(TILE) void k_ionic(InstDesc* __restrict__ insts, const BlockMap* __restrict__ bmap) {
+// One tile of TILE nodes per workgroup of TILE / NPT threads, NPT nodes per
+// thread (node p * TILE / NPT + t of the tile).  NPT trades occupancy for
+// registers per node; the tuner picks it per model and precision.
+template <int MODEL, bool MIXED, bool SINGLE, int NPT>
+__global__ __launch_bounds__(TILE / NPT) void k_ionic(InstDesc* __restrict__ insts,
+                                                      const BlockMap* __restrict__ bmap) {
   int lblk;
   const InstDesc& I = instance<SINGLE>(insts, bmap, lblk);
   if (lblk < 0) return;
-  const int64_t i = (int64_t)lblk * TILE + threadIdx.x;
-  if (i < I.n) ionic_node<MODEL, MIXED>(I, I.n, I.st.step, i);
+  const int64_t step = I.st.step;
+  for (int p = 0; p < NPT; p++) {
+    const int64_t i = (int64_t)lblk * TILE + p * (TILE / NPT) + threadIdx.x;
+    if (i < I.n) ionic_node<MODEL, MIXED>(I, I.n, step, i);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -301,10 +314,10 @@ __global__ __launch_bounds__(TILE) void k_ionic(InstDesc* __restrict__ insts, co
 // of a (inner) CG solve.  Partials: <r,z>, <r,r>, <b,b>, <r32,r32>.
 // ---------------------------------------------------------------------------
 
-template <bool MIXED, bool WITH_RHS, bool SINGLE>
+template <bool MIXED, bool WITH_RHS, bool SINGLE, int XMAP>
 __global__ __launch_bounds__(WG) void k_residual(InstDesc* __restrict__ insts, const BlockMap* __restrict__ bmap) {
   int lblk;
-  InstDesc& I = instance<SINGLE>(insts, bmap, lblk);
+  InstDesc& I = instance<SINGLE, XMAP>(insts, bmap, lblk);
   if (lblk < 0) return;
   InstState& S = I.st;
   // a refinement sweep only restarts an instance whose inner solve is done
@@ -372,10 +385,10 @@ __global__ __launch_bounds__(WG) void k_residual(InstDesc* __restrict__ insts, c
 // CG iteration, part 1: w = A z and the partials of <w, z>.
 // ---------------------------------------------------------------------------
 
-template <bool MIXED, bool SINGLE>
+template <bool MIXED, bool SINGLE, int XMAP>
 __global__ __launch_bounds__(WG) void k_cg_spmv(InstDesc* __restrict__ insts, const BlockMap* __restrict__ bmap) {
   int lblk;
-  InstDesc& I = instance<SINGLE>(insts, bmap, lblk);
+  InstDesc& I = instance<SINGLE, XMAP>(insts, bmap, lblk);
   if (lblk < 0) return;
   InstState& S = I.st;
   if (cg_idle(S)) return;
@@ -511,10 +524,10 @@ __global__ __launch_bounds__(FIN_WG) void k_cg_finalize(InstDesc* __restrict__ i
 // r -= alpha s, z = P^{-1} r; partials <r, z>, <r, r>.
 // ---------------------------------------------------------------------------
 
-template <bool MIXED, bool SINGLE>
+template <bool MIXED, bool SINGLE, int XMAP>
 __global__ __launch_bounds__(WG) void k_cg_update(InstDesc* __restrict__ insts, const BlockMap* __restrict__ bmap) {
   int lblk;
-  InstDesc& I = instance<SINGLE>(insts, bmap, lblk);
+  InstDesc& I = instance<SINGLE, XMAP>(insts, bmap, lblk);
   if (lblk < 0) return;
   InstState& S = I.st;
   if (cg_idle(S)) return;
@@ -647,10 +660,19 @@ __global__ void k_fill(double* __restrict__ x, int64_t n, double v) {
     else hipLaunchKernelGGL((KER<false>), GRID, BLOCK, 0, (L).stream, (L).insts, (L).bmap);        \
   } while (0)
 
+template <int M, bool MX, int NPT>
+static void ionic_dispatch_npt(const Launch& L) {
+  if (L.single)
+    hipLaunchKernelGGL((k_ionic<M, MX, true, NPT>), dim3(L.nblocks), dim3(TILE / NPT), 0, L.stream, L.insts, L.bmap);
+  else
+    hipLaunchKernelGGL((k_ionic<M, MX, false, NPT>), dim3(L.nblocks), dim3(TILE / NPT), 0, L.stream, L.insts, L.bmap);
+}
+
 template <int M, bool MX>
 static void ionic_dispatch(const Launch& L) {
-  if (L.single) hipLaunchKernelGGL((k_ionic<M, MX, true>), dim3(L.nblocks), dim3(TILE), 0, L.stream, L.insts, L.bmap);
-  else hipLaunchKernelGGL((k_ionic<M, MX, false>), dim3(L.nblocks), dim3(TILE), 0, L.stream, L.insts, L.bmap);
+  if (L.ionic_npt == 4) ionic_dispatch_npt<M, MX, 4>(L);
+  else if (L.ionic_npt == 2) ionic_dispatch_npt<M, MX, 2>(L);
+  else ionic_dispatch_npt<M, MX, 1>(L);
 }
 
 void launch_ionic(int model, bool mixed, const Launch& L) {
@@ -663,10 +685,30 @@ void launch_ionic(int model, bool mixed, const Launch& L) {
   }
 }
 
+// CG-kernel launches: a single instance with the XCD-ordered (xmap 0) or the
+// dispatch-order (xmap 1) tile map, or a batch over its block map.
 template <bool MX, bool RHS>
 static void residual_dispatch(const Launch& L) {
-  if (L.single) hipLaunchKernelGGL((k_residual<MX, RHS, true>), dim3(L.nblocks), dim3(WG), 0, L.stream, L.insts, L.bmap);
-  else hipLaunchKernelGGL((k_residual<MX, RHS, false>), dim3(L.nblocks), dim3(WG), 0, L.stream, L.insts, L.bmap);
+  const dim3 g(L.nblocks), b(WG);
+  if (!L.single) hipLaunchKernelGGL((k_residual<MX, RHS, false, 0>), g, b, 0, L.stream, L.insts, L.bmap);
+  else if (L.xmap == 1) hipLaunchKernelGGL((k_residual<MX, RHS, true, 1>), g, b, 0, L.stream, L.insts, L.bmap);
+  else hipLaunchKernelGGL((k_residual<MX, RHS, true, 0>), g, b, 0, L.stream, L.insts, L.bmap);
+}
+
+template <bool MX>
+static void spmv_dispatch(const Launch& L) {
+  const dim3 g(L.nblocks), b(WG);
+  if (!L.single) hipLaunchKernelGGL((k_cg_spmv<MX, false, 0>), g, b, 0, L.stream, L.insts, L.bmap);
+  else if (L.xmap == 1) hipLaunchKernelGGL((k_cg_spmv<MX, true, 1>), g, b, 0, L.stream, L.insts, L.bmap);
+  else hipLaunchKernelGGL((k_cg_spmv<MX, true, 0>), g, b, 0, L.stream, L.insts, L.bmap);
+}
+
+template <bool MX>
+static void update_dispatch(const Launch& L) {
+  const dim3 g(L.nblocks), b(WG);
+  if (!L.single) hipLaunchKernelGGL((k_cg_update<MX, false, 0>), g, b, 0, L.stream, L.insts, L.bmap);
+  else if (L.xmap == 1) hipLaunchKernelGGL((k_cg_update<MX, true, 1>), g, b, 0, L.stream, L.insts, L.bmap);
+  else hipLaunchKernelGGL((k_cg_update<MX, true, 0>), g, b, 0, L.stream, L.insts, L.bmap);
 }
 
 void launch_residual(bool mixed, bool with_rhs, const Launch& L) {
@@ -677,13 +719,7 @@ void launch_residual(bool mixed, bool with_rhs, const Launch& L) {
 
 void launch_cg_spmv(bool mixed, const Launch& L) {
   if (L.nblocks <= 0) return;
-  if (mixed) {
-    if (L.single) hipLaunchKernelGGL((k_cg_spmv<true, true>), dim3(L.nblocks), dim3(WG), 0, L.stream, L.insts, L.bmap);
-    else hipLaunchKernelGGL((k_cg_spmv<true, false>), dim3(L.nblocks), dim3(WG), 0, L.stream, L.insts, L.bmap);
-  } else {
-    if (L.single) hipLaunchKernelGGL((k_cg_spmv<false, true>), dim3(L.nblocks), dim3(WG), 0, L.stream, L.insts, L.bmap);
-    else hipLaunchKernelGGL((k_cg_spmv<false, false>), dim3(L.nblocks), dim3(WG), 0, L.stream, L.insts, L.bmap);
-  }
+  mixed ? spmv_dispatch<true>(L) : spmv_dispatch<false>(L);
 }
 
 void launch_cg_finalize(bool mixed, InstDesc* insts, const int32_t* ids, int n_ids, hipStream_t stream) {
@@ -694,13 +730,7 @@ void launch_cg_finalize(bool mixed, InstDesc* insts, const int32_t* ids, int n_i
 
 void launch_cg_update(bool mixed, const Launch& L) {
   if (L.nblocks <= 0) return;
-  if (mixed) {
-    if (L.single) hipLaunchKernelGGL((k_cg_update<true, true>), dim3(L.nblocks), dim3(WG), 0, L.stream, L.insts, L.bmap);
-    else hipLaunchKernelGGL((k_cg_update<true, false>), dim3(L.nblocks), dim3(WG), 0, L.stream, L.insts, L.bmap);
-  } else {
-    if (L.single) hipLaunchKernelGGL((k_cg_update<false, true>), dim3(L.nblocks), dim3(WG), 0, L.stream, L.insts, L.bmap);
-    else hipLaunchKernelGGL((k_cg_update<false, false>), dim3(L.nblocks), dim3(WG), 0, L.stream, L.insts, L.bmap);
-  }
+  mixed ? update_dispatch<true>(L) : update_dispatch<false>(L);
 }
 
 void launch_activation(const Launch& L) {
