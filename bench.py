@@ -97,13 +97,28 @@ def _traffic(kernel_kind, precision, workload):
     return (e["fetch_kib_per_dispatch"] * ff + e["write_kib_per_dispatch"] * fw) * 1024.0
 
 
-def run_gpu(spec, precision, steps, warmup, instrument_steps):
+def _warm(sim, ep, warmup, graph, autotune):
+    """Untimed warmup; the launch-shape tuner runs inside it (5 x trial steps)."""
+    launch = {"ionic_npt": 1, "tile_map": 0, "graph": bool(graph), "tuned": False}
+    left = warmup
+    if autotune and warmup >= 5:
+        trial = max(1, warmup // 5)
+        npt, tmap = sim.autotune(trial)
+        launch.update(ionic_npt=npt, tile_map=tmap, tuned=True)
+        left -= 5 * trial
+    if graph:
+        sim.set_option(ep.EP_OPT_GRAPH, 1)
+    sim.step(left)
+    sim.sync()
+    return launch
+
+
+def run_gpu(spec, precision, steps, warmup, instrument_steps, graph=True, autotune=True):
     import paper_2308_01651_amd as ep
     import torch
     sim = ep.Simulation.from_spec(spec, precision=precision)
     st0 = sim.get_stats()
-    sim.step(warmup)
-    sim.sync()
+    launch = _warm(sim, ep, warmup, graph, autotune)
     torch.cuda.synchronize()
     it0 = sim.get_stats()["cg_iters_total"]
     lat = []
@@ -132,6 +147,7 @@ def run_gpu(spec, precision, steps, warmup, instrument_steps):
         "nnz": st["nnz"],
         "device_bytes": st["device_bytes"],
         "setup_ms": st0["ms_setup"],
+        "launch": launch,
     }
     sim.close()
     # instrumented pass: a fresh simulation over the same window (same warmup,
@@ -139,6 +155,8 @@ def run_gpu(spec, precision, steps, warmup, instrument_steps):
     # breakdown describes the timed steps and not a later phase of the beat
     if instrument_steps > 0:
         sim = ep.Simulation.from_spec(spec, precision=precision)
+        sim.set_option(ep.EP_OPT_IONIC_NPT, launch["ionic_npt"])
+        sim.set_option(ep.EP_OPT_TILE_MAP, launch["tile_map"])
         sim.step(warmup)
         sim.sync()
         sim.set_option(ep.EP_OPT_KERNEL_TIMERS, 1)
@@ -178,7 +196,7 @@ def roofline(res, spec, precision_name, workload_key):
             "avg_launch_us": 1e6 * avg_s}, per_kernel
 
 
-def run_batched(specs, precision, steps, warmup):
+def run_batched(specs, precision, steps, warmup, graph=True, autotune=True):
     """All instances resident in one pool, stepped together (one launch per phase)."""
     import paper_2308_01651_amd as ep
     import torch
@@ -191,7 +209,16 @@ def run_batched(specs, precision, steps, warmup):
             raise RuntimeError("batched instance did not fit the pool")
         sims.append(s)
     setup = time.perf_counter() - t0
-    pool.step(warmup)
+    launch = {"ionic_npt": 1, "tile_map": 0, "graph": bool(graph), "tuned": False}
+    left = warmup
+    if autotune and warmup >= 5:
+        trial = max(1, warmup // 5)
+        npt, tmap = pool.autotune(trial)
+        launch.update(ionic_npt=npt, tile_map=tmap, tuned=True)
+        left -= 5 * trial
+    if graph:
+        pool.set_option(ep.EP_OPT_GRAPH, 1)
+    pool.step(left)
     torch.cuda.synchronize()
     it0 = sum(s.get_stats()["cg_iters_total"] for s in sims)
     t0 = time.perf_counter()
@@ -208,7 +235,7 @@ def run_batched(specs, precision, steps, warmup):
     pool.close()
     return {"instances": len(specs), "total_nodes": n_tot, "steps": steps, "warmup": warmup, "seconds": T,
             "node_steps_per_s": n_tot * steps / T, "ms_per_step": 1e3 * T / steps,
-            "cg_iters_per_instance_step": its, "setup_s": setup}, fields
+            "cg_iters_per_instance_step": its, "setup_s": setup, "launch": launch}, fields
 
 
 def run_serving(precision, max_slots, trace):
@@ -266,7 +293,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--batched-steps", type=int, default=400)
+    ap.add_argument("--batched-steps", type=int, default=2000)
+    ap.add_argument("--graph", type=int, default=0, choices=[0, 1],
+                    help="replay the step from captured HIP graphs (measured slower than eager "
+                         "launches on ROCm 7.2; the graph variant is reported beside the main run)")
+    ap.add_argument("--autotune", type=int, default=1, choices=[0, 1],
+                    help="pick launch shapes with the library's tuner during warmup")
     ap.add_argument("--serve-requests", type=int, default=32)
     ap.add_argument("--serve-full", action="store_true",
                     help="the configured trace: 128 requests, 1e4-1e6 nodes, 50-500 ms (long)")
@@ -294,7 +326,8 @@ def main():
     precs = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
     for pn in precs:
         print(f"[bench] {wname} {pn}: warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
-        res, u, at = run_gpu(spec, ep.EP_FP64 if pn == "fp64" else ep.EP_MIXED, args.steps, args.warmup, instr)
+        res, u, at = run_gpu(spec, ep.EP_FP64 if pn == "fp64" else ep.EP_MIXED, args.steps, args.warmup, instr,
+                             bool(args.graph), bool(args.autotune))
         if instr > 0:
             rl, pk = roofline(res, spec, pn, args.workload)
             res["roofline"] = rl
@@ -307,6 +340,15 @@ def main():
         fields[pn] = (u, at)
         print(f"[bench] {pn}: {res['node_steps_per_s']:.4g} node-steps/s, {res['ms_per_step']:.3f} ms/step, "
               f"dominant {rl['kernel']} {rl['achieved']} GB/s", file=sys.stderr, flush=True)
+    if "fp64" in out:
+        # the same run with the default launches (eager, untuned) and with graph replay, for comparison
+        for name, g, t in (("fp64_default_launches", False, False), ("fp64_graph_replay", True, bool(args.autotune))):
+            if g == bool(args.graph) and t == bool(args.autotune):
+                continue
+            r0, _, _ = run_gpu(spec, ep.EP_FP64, args.steps, args.warmup, 0, g, t)
+            out[name] = {k: r0[k] for k in ("node_steps_per_s", "ms_per_step", "step_latency_ms_p50",
+                                            "step_latency_ms_p99", "launch")}
+            print(f"[bench] {name}: {r0['node_steps_per_s']:.4g} node-steps/s", file=sys.stderr, flush=True)
     if "fp64" in fields and "mixed" in fields:
         du = fields["mixed"][0] - fields["fp64"][0]
         a64, a32 = fields["fp64"][1], fields["mixed"][1]
@@ -323,7 +365,8 @@ def main():
         bf = {}
         for pn in ("fp64", "mixed"):
             print(f"[bench] batched: 64 slab instances, {pn}", file=sys.stderr, flush=True)
-            r, f = run_batched(specs, ep.EP_FP64 if pn == "fp64" else ep.EP_MIXED, args.batched_steps, 20)
+            r, f = run_batched(specs, ep.EP_FP64 if pn == "fp64" else ep.EP_MIXED, args.batched_steps, 20,
+                               bool(args.graph), bool(args.autotune))
             batched[pn] = r
             bf[pn] = f
             print(f"[bench] batched {pn}: {r['node_steps_per_s']:.4g} node-steps/s", file=sys.stderr, flush=True)
