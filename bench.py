@@ -45,18 +45,22 @@ def _workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def kernel_bytes(kind, n, nnz, mixed, nvars_model):
+def kernel_bytes(kind, n, nnz, mixed, nvars_model, fmt="DIA", n_diag=0):
     """Algorithmic HBM bytes per launch of each kernel: every array the kernel
-    must touch read or written once (matrix values once per nonzero; DIA needs
-    no column indices)."""
+    must touch, read or written once.  The operator counts as stored: the
+    symmetric DIA format keeps n_diag diagonals (offsets >= 0) of n values
+    and no column indices; SELL keeps a value and a 4-byte column index per
+    nonzero.  Gathers of the input vector count once."""
+    def mat(vb):
+        return n_diag * n * vb if fmt == "DIA" else nnz * (vb + 4)
     if kind == "cg_spmv":
-        return nnz * (4 if mixed else 8) + n * (8 if mixed else 16)
+        return mat(4 if mixed else 8) + n * (8 if mixed else 16)
     if kind == "cg_update":
         return n * (56 if mixed else 96)
     if kind == "rhs":
-        return 2 * nnz * 8 + n * (36 if mixed else 48)
+        return 2 * mat(8) + n * (36 if mixed else 48)
     if kind == "ir_residual":
-        return nnz * 8 + n * 28
+        return mat(8) + n * 28
     if kind == "ionic":
         if nvars_model == 18:
             return n * (192 if mixed else 320)
@@ -149,6 +153,10 @@ def run_gpu(spec, precision, steps, warmup, instrument_steps, graph=True, autotu
         "setup_ms": st0["ms_setup"],
         "launch": launch,
     }
+    # kernel durations on the state the timed region ended with: HIP events
+    # around back-to-back launches on the sim's stream (SpMV and rhs only:
+    # the kernels whose outputs the next step recomputes)
+    res["loop_us"] = {"cg_spmv": sim.time_kernel_us("cg_spmv", 200), "rhs": sim.time_kernel_us("rhs", 50)}
     sim.close()
     # instrumented pass: a fresh simulation over the same window (same warmup,
     # same steps) with HIP events around every launch, so the per-kernel
@@ -164,6 +172,7 @@ def run_gpu(spec, precision, steps, warmup, instrument_steps, graph=True, autotu
         sim.step(instrument_steps)
         sim.sync()
         kt = sim.get_kernel_times()
+        res["event_pair_overhead_us"] = sim.timer_overhead_us(500)
         res["instrumented_steps"] = instrument_steps
         res["instrumented_cg_iters"] = sim.get_stats()["cg_iters_total"] - it1
         res["kernel_ms"] = {k: v[0] for k, v in kt.items()}
@@ -173,27 +182,51 @@ def run_gpu(spec, precision, steps, warmup, instrument_steps, graph=True, autotu
 
 
 def roofline(res, spec, precision_name, workload_key):
+    """Roofline of the dominant kernel (most time in the instrumented pass).
+
+    Per-launch duration: for the SpMV and rhs kernels, HIP events around 200
+    (50) back-to-back launches on the state the timed region ended with;
+    otherwise the instrumented pass's per-launch events divided by the
+    launches that did work (FP64: SpMV = CG iterations + one per step, update
+    = CG iterations; launches after convergence return at once and their time
+    is charged to the working ones).  The per-launch event durations carry
+    the events' own cost (an empty pair is measured and reported beside)."""
     n = spec.mesh.n_nodes
     nnz = res["nnz"]
     mixed = precision_name == "mixed"
     nv = {"ttp06": 18, "bo": 3, "ap": 1, "passive": 0}[spec.model]
     ms = res["kernel_ms"]
     cnt = res["kernel_launches"]
+    ovh = res.get("event_pair_overhead_us", 0.0)
+    work = dict(cnt)
+    if not mixed:
+        its, steps = res["instrumented_cg_iters"], res["instrumented_steps"]
+        work["cg_spmv"] = min(cnt["cg_spmv"], its + steps)
+        work["cg_update"] = min(cnt["cg_update"], its)
     kinds = [k for k in ms if cnt[k] > 0]
     dom = max((k for k in kinds if k != "cg_finalize"), key=lambda k: ms[k])
-    bytes_per = kernel_bytes(dom, n, nnz, mixed, nv)
-    avg_s = ms[dom] / 1e3 / cnt[dom]
+    fmt, nd = res["matrix_format"], int(res["n_diag"])
+    bytes_per = kernel_bytes(dom, n, nnz, mixed, nv, fmt, nd)
+    raw_s = ms[dom] / 1e3 / work[dom]
+    loop = res.get("loop_us", {})
+    avg_s = 1e-6 * loop[dom] if dom in loop else raw_s
     achieved = bytes_per / avg_s / 1e9
     per_kernel = {}
     for k in kinds:
-        b = kernel_bytes(k, n, nnz, mixed, nv)
-        a = ms[k] / 1e3 / cnt[k]
-        per_kernel[k] = {"avg_us": 1e6 * a, "launches": cnt[k], "share": ms[k] / sum(ms.values()),
-                         "GBps": b / a / 1e9 if b else None, "algo_bytes": b}
+        b = kernel_bytes(k, n, nnz, mixed, nv, fmt, nd)
+        a = ms[k] / 1e3 / work[k]
+        per_kernel[k] = {"avg_us_events": 1e6 * a, "launches": cnt[k], "launches_with_work": work[k],
+                         "share": ms[k] / sum(ms.values()), "GBps_events": b / a / 1e9 if b else None,
+                         "algo_bytes": b}
+        if k in loop:
+            per_kernel[k]["avg_us_loop"] = loop[k]
+            per_kernel[k]["GBps_loop"] = b / (1e-6 * loop[k]) / 1e9
     tr = _traffic(dom, precision_name, workload_key)
     return {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": tr, "algo_bytes_per_launch": bytes_per,
-            "avg_launch_us": 1e6 * avg_s}, per_kernel
+            "avg_launch_us": 1e6 * avg_s, "avg_launch_us_events": 1e6 * raw_s, "event_pair_overhead_us": ovh,
+            "duration_source": "back-to-back launches" if dom in loop else "per-launch events",
+            "launches": cnt[dom], "launches_with_work": work[dom]}, per_kernel
 
 
 def run_batched(specs, precision, steps, warmup, graph=True, autotune=True):
@@ -418,6 +451,10 @@ def main():
         "p99_step_latency_ms": main_res["step_latency_ms_p99"],
         "roofline": {k: main_res["roofline"][k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
         "roofline_kernel": main_res["roofline"]["kernel"],
+        "roofline_detail": {k: main_res["roofline"].get(k) for k in ("algo_bytes_per_launch", "avg_launch_us",
+                                                                      "duration_source",
+                                                                      "avg_launch_us_events", "event_pair_overhead_us",
+                                                                      "launches", "launches_with_work")},
         "cpu_baseline": cpu,
         "variants": out,
         "batched": batched,

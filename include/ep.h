@@ -217,6 +217,19 @@ ep_status ep_sim_get_stats(ep_sim* sim, ep_stats* out);
  * converged return at once and are counted too. */
 ep_status ep_sim_get_kernel_times(ep_sim* sim, double* ms, int64_t* launches);
 
+/* Mean elapsed time (us) of `reps` empty HIP event pairs recorded back to
+ * back on the sim's stream: the part of an EP_OPT_KERNEL_TIMERS duration
+ * that is the timer's own cost rather than the kernel's. */
+ep_status ep_sim_timer_overhead(ep_sim* sim, int reps, double* us_per_pair);
+
+/* Mean duration (us) of `reps` back-to-back launches of one kernel of the
+ * step, between steps, on the sim's stream with the sim's launch shapes:
+ * EP_K_CG_SPMV (w = A z) or EP_K_RHS (b = M g, r0 = b - A x0), the kernels
+ * whose outputs the next step recomputes before reading them.  For
+ * measurement; the simulation state is unchanged.  EP_ESTATE before finalize,
+ * while pooled or during a step. */
+ep_status ep_sim_time_kernel(ep_sim* sim, int kind, int reps, double* us_per_launch);
+
 /* Launch-shape tuner (a growth direction, not in the paper): runs
  * trial_steps steps per candidate with kernel timers on, first for the
  * ionic nodes per thread (1, 2, 4; scored by the ionic kernel's mean time),

@@ -138,6 +138,19 @@ class Simulation:
         check(lib.ep_sim_get_stats(self._h, C.byref(st)), "ep_sim_get_stats")
         return {name: getattr(st, name) for name, _ in EpStats._fields_}
 
+    def timer_overhead_us(self, reps: int = 200) -> float:
+        """Mean duration of an empty HIP event pair on the sim's stream (us)."""
+        v = C.c_double()
+        check(lib.ep_sim_timer_overhead(self._h, int(reps), C.byref(v)), "ep_sim_timer_overhead")
+        return v.value
+
+    def time_kernel_us(self, kind: str, reps: int = 200) -> float:
+        """ep_sim_time_kernel for "cg_spmv" or "rhs" (between steps)."""
+        v = C.c_double()
+        check(lib.ep_sim_time_kernel(self._h, KERNEL_KINDS.index(kind), int(reps), C.byref(v)),
+              "ep_sim_time_kernel")
+        return v.value
+
     def get_kernel_times(self) -> dict:
         ms = np.zeros(7)
         cnt = np.zeros(7, np.int64)

@@ -1295,6 +1295,67 @@ ep_status ep_sim_get_kernel_times(ep_sim* s, double* ms, int64_t* launches) {
   return EP_OK;
 }
 
+ep_status ep_sim_timer_overhead(ep_sim* s, int reps, double* us_per_pair) {
+  if (check_sim(s) || reps < 1 || !us_per_pair) return fail(EP_EINVAL, "bad timer-overhead arguments");
+  EP_HIP(hipSetDevice(s->device));
+  hipStream_t st = s->stream;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev((size_t)reps);
+  for (auto& e : ev) {
+    EP_HIP(hipEventCreate(&e.first));
+    EP_HIP(hipEventCreate(&e.second));
+  }
+  EP_HIP(hipStreamSynchronize(st));
+  for (auto& e : ev) {
+    EP_HIP(hipEventRecord(e.first, st));
+    EP_HIP(hipEventRecord(e.second, st));
+  }
+  EP_HIP(hipStreamSynchronize(st));
+  double sum = 0.0;
+  for (auto& e : ev) {
+    float ms = 0.0f;
+    EP_HIP(hipEventElapsedTime(&ms, e.first, e.second));
+    sum += ms;
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  *us_per_pair = 1e3 * sum / reps;
+  return EP_OK;
+}
+
+ep_status ep_sim_time_kernel(ep_sim* s, int kind, int reps, double* us_per_launch) {
+  if (check_sim(s) || reps < 1 || !us_per_launch) return fail(EP_EINVAL, "bad time-kernel arguments");
+  if (kind != EP_K_RHS && kind != EP_K_CG_SPMV) return fail(EP_EINVAL, "only the rhs and SpMV kernels can be repeated");
+  if (!s->finalized) return fail(EP_ESTATE, "finalize first");
+  if (s->in_pool) return fail(EP_ESTATE, "sim is stepped by its pool");
+  EP_HIP(hipSetDevice(s->device));
+  hipStream_t st = s->stream;
+  EP_HIP(hipStreamSynchronize(st));
+  EP_HIP(hipMemcpyAsync(s->h_st, s->d_st, sizeof(InstState), hipMemcpyDeviceToHost, st));
+  EP_HIP(hipStreamSynchronize(st));
+  // between steps the solve-control flags are clear, so both kernels do their
+  // full work; everything they write is recomputed by the next step
+  if (s->h_st->conv || s->h_st->conv_in || s->h_st->restart) return fail(EP_ESTATE, "a step is in progress");
+  const Launch L = launch_of(s);
+  const bool mixed = s->prec == EP_MIXED;
+  hipEvent_t a = nullptr, b = nullptr;
+  EP_HIP(hipEventCreate(&a));
+  EP_HIP(hipEventCreate(&b));
+  EP_HIP(hipEventRecord(a, st));
+  for (int k = 0; k < reps; k++) {
+    if (kind == EP_K_CG_SPMV) launch_cg_spmv(mixed, L);
+    else launch_residual(mixed, true, L);
+  }
+  EP_HIP(hipGetLastError());
+  EP_HIP(hipEventRecord(b, st));
+  EP_HIP(hipEventSynchronize(b));
+  float ms = 0.0f;
+  EP_HIP(hipEventElapsedTime(&ms, a, b));
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  *us_per_launch = 1e3 * (double)ms / reps;
+  return EP_OK;
+}
+
 void ep_sim_destroy(ep_sim* s) {
   if (!s) return;
   (void)hipSetDevice(s->device);

@@ -134,24 +134,33 @@ __device__ __forceinline__ R ttp06_step(R V, R dt, const double* mp, TtpState<R>
   using namespace ttp;
   const R one = R(1);
   // ---- gates: Rush-Larsen at V (fcass uses the old subspace calcium) ----
+  // Exponentials of (V + a) / b with a shared b come from one exp(V / b):
+  // exp((V + a) / b) = exp(a / b) exp(V / b); divisions by constants are
+  // multiplications by their reciprocals.  Each rewrite changes the result
+  // by a few ulps only.
   {
-    R t = one + m_exp((R(-56.86) - V) / R(9.03));
+    const R E5 = m_exp(V * R(0.2)), iE5 = one / E5;          // exp(V/5)
+    const R E10 = m_exp(V * R(0.1)), iE10 = one / E10;       // exp(V/10)
+    const R E20 = m_exp(V * R(0.05)), iE20 = one / E20;      // exp(V/20)
+    const R E7 = m_exp(V * R(1.0 / 7.0)), iE7 = one / E7;    // exp(V/7)
+    const R iE6 = m_exp(V * R(-1.0 / 6.0));                  // exp(-V/6)
+    R t = one + m_exp((R(-56.86) - V) * R(1.0 / 9.03));
     const R m_inf = one / (t * t);
-    const R a_m = one / (one + m_exp((R(-60.0) - V) / R(5.0)));
-    const R b_m = R(0.1) / (one + m_exp((V + R(35.0)) / R(5.0))) +
-                  R(0.1) / (one + m_exp((V - R(50.0)) / R(200.0)));
+    const R a_m = one / (one + R(6.14421235332821e-06) * iE5);               // (-60 - V)/5
+    const R b_m = R(0.1) / (one + R(1096.6331584284585) * E5) +              // (V + 35)/5
+                  R(0.1) / (one + m_exp((V - R(50.0)) * R(0.005)));
     S.g[0] = rush_larsen(S.g[0], m_inf, a_m * b_m, dt);
 
-    t = one + m_exp((V + R(71.55)) / R(7.43));
+    t = one + m_exp((V + R(71.55)) * R(1.0 / 7.43));
     const R hj_inf = one / (t * t);
     R a_h, b_h, a_j, b_j;
     if (V >= R(-40.0)) {
       a_h = R(0);
-      b_h = R(0.77) / (R(0.13) * (one + m_exp(-(V + R(10.66)) / R(11.1))));
+      b_h = R(0.77) / (R(0.13) * (one + m_exp(-(V + R(10.66)) * R(1.0 / 11.1))));
       a_j = R(0);
-      b_j = R(0.6) * m_exp(R(0.057) * V) / (one + m_exp(R(-0.1) * (V + R(32.0))));
+      b_j = R(0.6) * m_exp(R(0.057) * V) / (one + R(0.04076220397836621) * iE10);   // -0.1 (V + 32)
     } else {
-      a_h = R(0.057) * m_exp(-(V + R(80.0)) / R(6.8));
+      a_h = R(0.057) * m_exp(-(V + R(80.0)) * R(1.0 / 6.8));
       b_h = R(2.7) * m_exp(R(0.079) * V) + R(3.1e5) * m_exp(R(0.3485) * V);
       a_j = (R(-2.5428e4) * m_exp(R(0.2444) * V) - R(6.948e-6) * m_exp(R(-0.04391) * V)) *
             (V + R(37.78)) / (one + m_exp(R(0.311) * (V + R(79.23))));
@@ -160,45 +169,46 @@ __device__ __forceinline__ R ttp06_step(R V, R dt, const double* mp, TtpState<R>
     S.g[1] = rush_larsen(S.g[1], hj_inf, one / (a_h + b_h), dt);
     S.g[2] = rush_larsen(S.g[2], hj_inf, one / (a_j + b_j), dt);
 
-    const R xr1_inf = one / (one + m_exp((R(-26.0) - V) / R(7.0)));
-    const R tau_xr1 = (R(450.0) / (one + m_exp((R(-45.0) - V) / R(10.0)))) *
-                      (R(6.0) / (one + m_exp((V + R(30.0)) / R(11.5))));
+    const R xr1_inf = one / (one + R(0.0243728440732796) * iE7);            // (-26 - V)/7
+    const R tau_xr1 = (R(450.0) / (one + R(0.011108996538242306) * iE10)) *  // (-45 - V)/10
+                      (R(6.0) / (one + m_exp((V + R(30.0)) * R(1.0 / 11.5))));
     S.g[3] = rush_larsen(S.g[3], xr1_inf, tau_xr1, dt);
-    const R xr2_inf = one / (one + m_exp((V + R(88.0)) / R(24.0)));
-    const R tau_xr2 = (R(3.0) / (one + m_exp((R(-60.0) - V) / R(20.0)))) *
-                      (R(1.12) / (one + m_exp((V - R(60.0)) / R(20.0))));
+    const R xr2_inf = one / (one + m_exp((V + R(88.0)) * R(1.0 / 24.0)));
+    const R tau_xr2 = (R(3.0) / (one + R(0.049787068367863944) * iE20)) *    // (-60 - V)/20
+                      (R(1.12) / (one + R(0.049787068367863944) * E20));     // (V - 60)/20
     S.g[4] = rush_larsen(S.g[4], xr2_inf, tau_xr2, dt);
-    const R xs_inf = one / (one + m_exp((R(-5.0) - V) / R(14.0)));
-    const R tau_xs = (R(1400.0) / m_sqrt(one + m_exp((R(5.0) - V) / R(6.0)))) *
-                         (one / (one + m_exp((V - R(35.0)) / R(15.0)))) + R(80.0);
+    const R xs_inf = one / (one + m_exp((R(-5.0) - V) * R(1.0 / 14.0)));
+    const R tau_xs = (R(1400.0) / m_sqrt(one + R(2.300975890892825) * iE6)) *     // (5 - V)/6
+                         (one / (one + m_exp((V - R(35.0)) * R(1.0 / 15.0)))) + R(80.0);
     S.g[5] = rush_larsen(S.g[5], xs_inf, tau_xs, dt);
     R s_inf, tau_s;
     if (mp[16] != 0.0) {
-      s_inf = one / (one + m_exp((V + R(28.0)) / R(5.0)));
-      tau_s = R(1000.0) * m_exp(-(V + R(67.0)) * (V + R(67.0)) / R(1000.0)) + R(8.0);
+      s_inf = one / (one + R(270.42640742615254) * E5);                      // (V + 28)/5
+      tau_s = R(1000.0) * m_exp(-(V + R(67.0)) * (V + R(67.0)) * R(0.001)) + R(8.0);
     } else {
-      s_inf = one / (one + m_exp((V + R(20.0)) / R(5.0)));
-      tau_s = R(85.0) * m_exp(-(V + R(45.0)) * (V + R(45.0)) / R(320.0)) +
-              R(5.0) / (one + m_exp((V - R(20.0)) / R(5.0))) + R(3.0);
+      s_inf = one / (one + R(54.598150033144236) * E5);                      // (V + 20)/5
+      tau_s = R(85.0) * m_exp(-(V + R(45.0)) * (V + R(45.0)) * R(1.0 / 320.0)) +
+              R(5.0) / (one + R(0.01831563888873418) * E5) + R(3.0);          // (V - 20)/5
     }
     S.g[6] = rush_larsen(S.g[6], s_inf, tau_s, dt);
-    const R r_inf = one / (one + m_exp((R(20.0) - V) / R(6.0)));
-    const R tau_r = R(9.5) * m_exp(-(V + R(40.0)) * (V + R(40.0)) / R(1800.0)) + R(0.8);
+    const R r_inf = one / (one + R(28.03162489452614) * iE6);                // (20 - V)/6
+    const R tau_r = R(9.5) * m_exp(-(V + R(40.0)) * (V + R(40.0)) * R(1.0 / 1800.0)) + R(0.8);
     S.g[7] = rush_larsen(S.g[7], r_inf, tau_r, dt);
-    const R d_inf = one / (one + m_exp((R(-8.0) - V) / R(7.5)));
-    const R tau_d = (R(1.4) / (one + m_exp((R(-35.0) - V) / R(13.0))) + R(0.25)) *
-                        (R(1.4) / (one + m_exp((V + R(5.0)) / R(5.0)))) +
-                    one / (one + m_exp((R(50.0) - V) / R(20.0)));
+    const R d_inf = one / (one + m_exp((R(-8.0) - V) * R(1.0 / 7.5)));
+    const R tau_d = (R(1.4) / (one + m_exp((R(-35.0) - V) * R(1.0 / 13.0))) + R(0.25)) *
+                        (R(1.4) / (one + R(2.718281828459045) * E5)) +       // (V + 5)/5
+                    one / (one + R(12.182493960703473) * iE20);               // (50 - V)/20
     S.g[8] = rush_larsen(S.g[8], d_inf, tau_d, dt);
-    const R f_inf = one / (one + m_exp((V + R(20.0)) / R(7.0)));
-    const R tau_f = R(1102.5) * m_exp(-(V + R(27.0)) * (V + R(27.0)) / R(225.0)) +
-                    R(200.0) / (one + m_exp((R(13.0) - V) / R(10.0))) +
-                    R(180.0) / (one + m_exp((V + R(30.0)) / R(10.0))) + R(20.0);
+    const R f_inf = one / (one + R(17.41170806332765) * E7);                 // (V + 20)/7
+    const R e30 = R(20.085536923187668) * E10;                               // (V + 30)/10
+    const R tau_f = R(1102.5) * m_exp(-(V + R(27.0)) * (V + R(27.0)) * R(1.0 / 225.0)) +
+                    R(200.0) / (one + R(3.6692966676192444) * iE10) +        // (13 - V)/10
+                    R(180.0) / (one + e30) + R(20.0);
     S.g[9] = rush_larsen(S.g[9], f_inf, tau_f, dt);
-    const R f2_inf = R(0.67) / (one + m_exp((V + R(35.0)) / R(7.0))) + R(0.33);
-    const R tau_f2 = R(600.0) * m_exp(-(V + R(25.0)) * (V + R(25.0)) / R(170.0)) +
-                     R(31.0) / (one + m_exp((R(25.0) - V) / R(10.0))) +
-                     R(16.0) / (one + m_exp((V + R(30.0)) / R(10.0)));
+    const R f2_inf = R(0.67) / (one + R(148.4131591025766) * E7) + R(0.33);  // (V + 35)/7
+    const R tau_f2 = R(600.0) * m_exp(-(V + R(25.0)) * (V + R(25.0)) * R(1.0 / 170.0)) +
+                     R(31.0) / (one + R(12.182493960703473) * iE10) +         // (25 - V)/10
+                     R(16.0) / (one + e30);
     S.g[10] = rush_larsen(S.g[10], f2_inf, tau_f2, dt);
     const R cr = (S.cass / R(0.05)) * (S.cass / R(0.05));
     S.g[11] = rush_larsen(S.g[11], R(0.6) / (one + cr) + R(0.4), R(80.0) / (one + cr) + R(2.0), dt);
@@ -211,19 +221,21 @@ __device__ __forceinline__ R ttp06_step(R V, R dt, const double* mp, TtpState<R>
   const R gto = R(mp[2]) * S.g[7] * S.g[6];
   const R gKr = R(mp[3]) * S.g[3] * S.g[4];       // sqrt(Ko/5.4) = 1 at Ko = 5.4
   const R gKs = R(mp[4]) * S.g[5] * S.g[5];
-  const R z = R(2.0) * (V - R(15.0)) / rtf;
+  const R inv_rtf = R(1.0 / RTF);
+  const R Er = m_exp(V * inv_rtf), iEr = one / Er;          // exp(V F/RT)
+  const R z = R(2.0) * (V - R(15.0)) * inv_rtf;
   R zf;
   if (sizeof(R) == 8) zf = (fabs((double)z) < 1e-10) ? one - R(0.5) * z : z / m_expm1(z);
   else zf = (fabsf((float)z) < 1e-4f) ? one - R(0.5) * z : z / m_expm1(z);
-  const R ez = m_exp(z);
+  const R ez = Er * Er * R(0.3252969814969026);              // exp(z) = exp(2V F/RT) exp(-30 F/RT)
   const R gCaL = R(mp[5]) * S.g[8] * S.g[9] * S.g[10] * S.g[11] * R(2.0 * kF) * zf;
-  const R u1 = m_exp(R(gamma) * V / rtf);
-  const R u2 = m_exp(R(gamma - 1.0) * V / rtf);
+  const R u1 = m_exp(R(gamma) * V * inv_rtf);
+  const R u2 = u1 * iEr;                                     // exp((gamma - 1) V F/RT)
   const R naca_k = R(mp[10]) /
                    (R((KmNai * KmNai * KmNai + Nao * Nao * Nao) * (KmCa + Cao)) * (one + R(ksat) * u2));
   const R nak_k = R(mp[11] * Ko / (Ko + KmK)) /
-                  (one + R(0.1245) * m_exp(R(-0.1) * V / rtf) + R(0.0353) * m_exp(-V / rtf));
-  const R pk_k = R(mp[9]) / (one + m_exp((R(25.0) - V) / R(5.98)));
+                  (one + R(0.1245) * m_exp(R(-0.1) * V * inv_rtf) + R(0.0353) * iEr);
+  const R pk_k = R(mp[9]) / (one + m_exp((R(25.0) - V) * R(1.0 / 5.98)));
 
   // membrane currents at concentrations (cai, cass, nai, ki)
   struct Cur { R INa, IK1, Ito, IKr, IKs, ICaL, INaCa, INaK, IpCa, IpK, IbNa, IbCa; };
@@ -238,9 +250,12 @@ __device__ __forceinline__ R ttp06_step(R V, R dt, const double* mp, TtpState<R>
     c.Ito = gto * vk;
     c.IKr = gKr * vk;
     c.IKs = gKs * (V - E_Ks);
-    const R a_K1 = R(0.1) / (one + m_exp(R(0.06) * (vk - R(200.0))));
-    const R b_K1 = (R(3.0) * m_exp(R(0.0002) * (vk + R(100.0))) + m_exp(R(0.1) * (vk - R(10.0)))) /
-                   (one + m_exp(R(-0.5) * vk));
+    // exp(0.06 (vk - 200)), exp(0.1 (vk - 10)) and exp(-0.5 vk) are powers of q = exp(0.02 vk)
+    const R q = m_exp(R(0.02) * vk), q2 = q * q, q4 = q2 * q2, q8 = q4 * q4;
+    const R q25 = q8 * q8 * q8 * q;
+    const R a_K1 = R(0.1) / (one + R(6.14421235332821e-06) * (q2 * q));
+    const R b_K1 = (R(3.0) * m_exp(R(0.0002) * (vk + R(100.0))) + R(0.36787944117144233) * (q4 * q)) /
+                   (one + one / q25);
     c.IK1 = R(mp[1]) * (a_K1 / (a_K1 + b_K1)) * vk;
     c.ICaL = gCaL * (R(0.25) * cass * ez - R(Cao));
     const R nai3 = R(nai * nai * nai);

@@ -294,10 +294,12 @@ __device__ __forceinline__ void ionic_node(const InstDesc& I, int64_t n, int64_t
 }
 
 // One tile of TILE nodes per workgroup of TILE / NPT threads, NPT nodes per
-// thread (node p * TILE / NPT + t of the tile).  NPT trades occupancy for
-// registers per node; the tuner picks it per model and precision.
+// thread (node p * TILE / NPT + t of the tile).  NPT > 1 also asks the
+// compiler for at least 4 (NPT 2) or 5 (NPT 4) waves per SIMD, trading
+// registers (and, for the FP64 TTP06 model, some spills) for occupancy; the
+// tuner measures which shape is fastest for a model and precision.
 template <int MODEL, bool MIXED, bool SINGLE, int NPT>
-__global__ __launch_bounds__(TILE / NPT) void k_ionic(InstDesc* __restrict__ insts,
+__global__ __launch_bounds__(TILE / NPT) __attribute__((amdgpu_waves_per_eu(NPT == 1 ? 1 : (NPT == 2 ? 4 : 5)))) void k_ionic(InstDesc* __restrict__ insts,
                                                       const BlockMap* __restrict__ bmap) {
   int lblk;
   const InstDesc& I = instance<SINGLE>(insts, bmap, lblk);

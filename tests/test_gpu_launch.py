@@ -130,3 +130,23 @@ def test_pool_graph_and_autotune_match_alone(prec):
         pool.release(slot)
         s.close()
     pool.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_repeated_kernel_timing_leaves_results_unchanged(prec):
+    """ep_sim_time_kernel between steps (SpMV, rhs) must not change the run."""
+    ep = _ep()
+    spec = _spec()
+    ref = _run(spec, prec, 40)
+    s = ep.Simulation.from_spec(spec, precision=prec)
+    s.step(20)
+    t1 = s.time_kernel_us("cg_spmv", 50)
+    t2 = s.time_kernel_us("rhs", 20)
+    assert t1 > 0 and t2 > 0
+    with pytest.raises(ep.EpError):
+        s.time_kernel_us("cg_update", 5)
+    s.step(20)
+    u, w, _ = s.get_state()
+    assert np.array_equal(u, ref[0]) and np.array_equal(w, ref[1])
+    assert s.get_stats()["cg_iters_total"] == ref[3]
+    s.close()
