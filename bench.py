@@ -205,7 +205,8 @@ def roofline(res, spec, precision_name, workload_key):
         work["cg_update"] = min(cnt["cg_update"], its)
     kinds = [k for k in ms if cnt[k] > 0]
     dom = max((k for k in kinds if k != "cg_finalize"), key=lambda k: ms[k])
-    fmt, nd = res["matrix_format"], int(res["n_diag"])
+    # n_diag counts the operator's diagonals; the symmetric DIA stores the (n_diag + 1) / 2 with offset >= 0
+    fmt, nd = res["matrix_format"], (int(res["n_diag"]) + 1) // 2
     bytes_per = kernel_bytes(dom, n, nnz, mixed, nv, fmt, nd)
     raw_s = ms[dom] / 1e3 / work[dom]
     loop = res.get("loop_us", {})
