@@ -206,6 +206,20 @@ struct StepGraphs {
   }
 };
 
+// Host-side launch policy of the mixed-precision solve.  Each step runs
+// inner FP32 sweeps, each ended by an FP64 refinement residual; the host
+// launches a predicted number of inner rounds, then the refinement kernels,
+// then reads the control state.  Rounds launched after the inner solve has
+// converged, and a refinement launched before it has, return at once but
+// still cost a launch each, and a short prediction costs an extra read.  The
+// prediction is kept per sweep index (the first sweep of a step is the
+// longest) from the last step's counts, plus one round of slack.
+struct SweepPredictor {
+  int pred[3] = {8, 4, 3};
+  int rounds(int sweep) const { return std::max(1, pred[std::min(sweep, 2)]); }
+  void learn(int sweep, int its) { pred[std::min(sweep, 2)] = std::max(1, its + 1); }
+};
+
 template <typename F>
 hipError_t capture_graph(hipStream_t st, F&& fn, hipGraphExec_t* out) {
   hipGraph_t g = nullptr;
@@ -264,7 +278,7 @@ struct ep_sim {
   hipStream_t stream_own = nullptr;
   int pool_slot = -1;
   int it_pred = 8;      // CG iterations launched before the first convergence check
-  int in_pred = 8;      // inner iterations per refinement sweep (mixed)
+  SweepPredictor sweeps;  // inner rounds per refinement sweep (mixed)
   int sticky = EP_OK;
 };
 
@@ -813,20 +827,25 @@ ep_status step_once(ep_sim* s) {
     }
     s->it_pred = std::max(1, s->h_st->it_step);
   } else {
-    int before = 0;
-    for (int sweeps = 0;; sweeps++) {
-      const int chunk = std::max(1, s->in_pred);
-      EP_HIP(rounds(chunk));
+    // sweep = refinement residuals evaluated so far in this step; a sweep
+    // that has not converged after its predicted rounds continues by 2
+    int sweep = 0, sweep_start = 0;
+    bool fresh = true;
+    for (int reads = 0;; reads++) {
+      EP_HIP(rounds(fresh ? s->sweeps.rounds(sweep) : 2));
       if (graph) EP_HIP(hipGraphLaunch(G.ir, st));
       else ir();
       ep_status rc = pull_state(s);
       if (rc != EP_OK) return rc;
-      const int done = s->h_st->it_step - before;
-      before = s->h_st->it_step;
-      if (done >= chunk) s->in_pred = chunk + std::max(1, chunk / 2);
-      else if (done > 0 && done + 2 < chunk) s->in_pred = done + 1;
+      const int outer = s->h_st->outer, it_now = s->h_st->it_step;
+      fresh = outer > sweep;
+      if (fresh) {
+        s->sweeps.learn(sweep, it_now - sweep_start);
+        sweep = outer;
+        sweep_start = it_now;
+      }
       if (s->h_st->conv) break;
-      if (sweeps > s->max_outer + 2) return fail(EP_EHIP, "solver control lost (no convergence flag)");
+      if (reads > s->max_it + s->max_outer + 2) return fail(EP_EHIP, "solver control lost (no convergence flag)");
     }
   }
   if (graph) EP_HIP(hipGraphLaunch(G.epi, st));
@@ -1424,7 +1443,8 @@ struct ep_pool {
   BlockMap* d_model[4] = {nullptr, nullptr, nullptr, nullptr};
   int nb_model[4] = {0, 0, 0, 0};
   int32_t* d_ids = nullptr;
-  int it_pred = 8, in_pred = 8;
+  int it_pred = 8;
+  SweepPredictor sweeps;  // mixed: rounds per sweep (largest over the instances)
   KernelTimers kt;
   int ionic_npt = 1, list_order = 0, use_graph = 0;  // launch shapes (EP_OPT_*)
   StepGraphs graphs;
@@ -1564,7 +1584,10 @@ ep_status pool_step_once(ep_pool* P) {
   };
   if (graph) EP_HIP(hipGraphLaunch(G.pro, st));
   else pro();
-  int chunk = std::max(1, mixed ? P->in_pred : P->it_pred);
+  // mixed: sweep index = the smallest refinement count over the instances not
+  // yet converged; its rounds are predicted from the slowest instance
+  int chunk = std::max(1, mixed ? P->sweeps.rounds(0) : P->it_pred);
+  int sweep = 0, sweep_start = 0;
   for (int n_rounds = 0;; n_rounds++) {
     EP_HIP(rounds(chunk));
     if (mixed) {
@@ -1574,6 +1597,23 @@ ep_status pool_step_once(ep_pool* P) {
     ep_status rc = pool_pull(P);
     if (rc != EP_OK) return rc;
     if (P->kt.on) P->kt.harvest();
+    if (mixed) {
+      int outer = 1 << 30, it_now = 0;
+      for (int k : P->active) {
+        const InstState& S = P->h_states[k];
+        if (!S.conv) outer = std::min(outer, S.outer);
+        it_now = std::max(it_now, S.it_step);
+      }
+      const bool all = pool_all_conv(P);
+      if (all || outer > sweep) {
+        P->sweeps.learn(sweep, it_now - sweep_start);
+        sweep = all ? sweep + 1 : outer;
+        sweep_start = it_now;
+        chunk = P->sweeps.rounds(sweep);
+      } else {
+        chunk = 2;
+      }
+    }
     if (pool_all_conv(P)) break;
     if (n_rounds > 20000) return fail(EP_EHIP, "pool solver control lost (no convergence flag)");
     if (!mixed) chunk = 2;
