@@ -23,6 +23,17 @@ calcium buffering is handled with total concentrations (explicit step) and
 the exact rapid-buffer inversion.  I_ion is then evaluated at (u*, w_{n+1})
 as in the time-discrete monodomain equation.
 
+Second integrator, the paper's own (eq. of the time-discrete ionic model,
+`*_step_bdf`): (alpha w_{n+1} - w_BDF)/dt = H(u_EXT, w_EXT, w_{n+1}) with the
+BDF combination and extrapolation of the potential's order.  Variables that
+enter their own rate linearly are taken implicitly, the rest explicitly, so
+the step is solved by direct inversion: each gate y' = (y_inf - y)/tau gives
+y_{n+1} = (y_BDF + dt y_inf/tau)/(alpha + dt/tau) with y_inf, tau at
+(u_EXT, w_EXT); the Aliev-Panfilov recovery variable is implicit in its
+linear -v term with the rate factor eps(u_EXT, v_EXT); TTP06 concentrations
+(calcium as buffered totals, Na, K, RR) are explicit,
+x_{n+1} = (x_BDF + dt F(u_EXT, gates_{n+1}, c_EXT))/alpha.
+
 Parity status: rest-state fixed points (AP, BO exact; TTP06 drift bound) and
 the uniform-state reduction are pinned; the AP model is also pinned by the
 bistable-front speed.  Beyond those, the BO and TTP06 transcriptions are
@@ -69,6 +80,18 @@ def ap_step(u_star, w, dt, p=AP_DEFAULT):
     """v is not a gate: one forward-Euler step at (u*, v_n)."""
     v = w[0]
     return np.stack([v + dt * ap_dv(u_star, v, p)])
+
+
+def ap_step_bdf(u_ext, w_bdf, w_ext, dt, alpha, p=AP_DEFAULT):
+    """Recovery variable implicit in its -v term, eps(u, v) at (u_EXT, v_EXT)."""
+    eps = (p["eps0"] + p["mu1"] * w_ext[0] / (u_ext + p["mu2"])) / p["T"]
+    drive = p["k"] * u_ext * (u_ext - p["a"] - 1.0)
+    return np.stack([(w_bdf[0] - dt * eps * drive) / (alpha + dt * eps)])
+
+
+def gate_bdf(y_bdf, y_inf, tau, dt, alpha):
+    """BDF step of y' = (y_inf - y)/tau, implicit in y."""
+    return (y_bdf + dt * y_inf / tau) / (alpha + dt / tau)
 
 
 def ap_initial(n):
@@ -128,6 +151,12 @@ def bo_step(u_star, w, dt, p=BO_EPI):
     """All three variables are gates: Rush-Larsen at u*."""
     infs, taus = bo_gate_targets(u_star, p)
     return np.stack([infs[i] + (w[i] - infs[i]) * np.exp(-dt / taus[i]) for i in range(3)])
+
+
+def bo_step_bdf(u_ext, w_bdf, w_ext, dt, alpha, p=BO_EPI):
+    """All three variables are gates; targets depend on u only."""
+    infs, taus = bo_gate_targets(u_ext, p)
+    return np.stack([gate_bdf(w_bdf[i], infs[i], taus[i], dt, alpha) for i in range(3)])
 
 
 def bo_initial(n):
@@ -337,6 +366,43 @@ def ttp06_step(V_star, w, dt, p):
     return np.vstack([g, cai_n, casr_n, cass_n, nai_n, ki_n, rr_n])
 
 
+def _ttp_totals(c):
+    """Buffered total calcium (cytosol, SR, subspace) of free concentrations."""
+    K = TTP_CONST
+    cai, casr, cass = c[0], c[1], c[2]
+    return (cai + K["Bufc"] * cai / (cai + K["Kbufc"]),
+            casr + K["Bufsr"] * casr / (casr + K["Kbufsr"]),
+            cass + K["Bufss"] * cass / (cass + K["Kbufss"]))
+
+
+def ttp06_step_bdf(V_ext, w_hist, cb, ce, dt, alpha, p):
+    """Paper's scheme for TTP06.  w_hist = [w_n, w_{n-1}, ...]; cb, ce: the
+    BDF and extrapolation coefficients over that history."""
+    K = TTP_CONST
+    w_bdf = sum(c * w for c, w in zip(cb, w_hist))
+    w_ext = sum(c * w for c, w in zip(ce, w_hist))
+    infs, taus = ttp06_gate_targets(V_ext, w_ext[14], p)          # fcass at cass_EXT
+    g = np.stack([gate_bdf(w_bdf[i], infs[i], taus[i], dt, alpha) for i in range(12)])
+    c_ext = w_ext[12:]
+    cur = ttp06_currents(V_ext, g, c_ext, p)
+    cmF = K["Cm"] / K["F"]
+    d_cai_tot = (-(cur["IbCa"] + cur["IpCa"] - 2.0 * cur["INaCa"]) * cmF / (2.0 * K["Vc"])
+                 + (K["Vsr"] / K["Vc"]) * (cur["Ileak"] - cur["Iup"]) + cur["Ixfer"])
+    d_casr_tot = cur["Iup"] - cur["Ileak"] - cur["Irel"]
+    d_cass_tot = (-cur["ICaL"] * cmF / (2.0 * K["Vss"]) + (K["Vsr"] / K["Vss"]) * cur["Irel"]
+                  - (K["Vc"] / K["Vss"]) * cur["Ixfer"])
+    d_nai = -(cur["INa"] + cur["IbNa"] + 3.0 * cur["INaK"] + 3.0 * cur["INaCa"]) * cmF / K["Vc"]
+    d_ki = -(cur["IK1"] + cur["Ito"] + cur["IKr"] + cur["IKs"] - 2.0 * cur["INaK"] + cur["IpK"]) * cmF / K["Vc"]
+    tot_bdf = [sum(c * t for c, t in zip(cb, ts)) for ts in zip(*[_ttp_totals(w[12:]) for w in w_hist])]
+    cai_n = _free_from_total((tot_bdf[0] + dt * d_cai_tot) / alpha, K["Bufc"], K["Kbufc"])
+    casr_n = _free_from_total((tot_bdf[1] + dt * d_casr_tot) / alpha, K["Bufsr"], K["Kbufsr"])
+    cass_n = _free_from_total((tot_bdf[2] + dt * d_cass_tot) / alpha, K["Bufss"], K["Kbufss"])
+    nai_n = (w_bdf[15] + dt * d_nai) / alpha
+    ki_n = (w_bdf[16] + dt * d_ki) / alpha
+    rr_n = (w_bdf[17] + dt * cur["dRR"]) / alpha
+    return np.vstack([g, cai_n, casr_n, cass_n, nai_n, ki_n, rr_n])
+
+
 # ---------------------------------------------------------------------------
 # Uniform interface
 # ---------------------------------------------------------------------------
@@ -380,6 +446,19 @@ class IonicModel:
         if self.name == "ttp06":
             return ttp06_step(u_star, w, dt, self.p)
         return w
+
+    def step_bdf(self, u_ext, w_hist, cb, ce, dt, alpha):
+        """The paper's semi-implicit BDF step from w_hist = [w_n, w_{n-1}, ...]
+        with BDF / extrapolation coefficients cb, ce and leading alpha."""
+        if self.name == "ttp06":
+            return ttp06_step_bdf(u_ext, w_hist, cb, ce, dt, alpha, self.p)
+        w_bdf = sum(c * w for c, w in zip(cb, w_hist))
+        w_ext = sum(c * w for c, w in zip(ce, w_hist))
+        if self.name == "ap":
+            return ap_step_bdf(u_ext, w_bdf, w_ext, dt, alpha, self.p)
+        if self.name == "bo":
+            return bo_step_bdf(u_ext, w_bdf, w_ext, dt, alpha, self.p)
+        return w_hist[0]
 
     def iion(self, u, w):
         if self.name == "ap":

@@ -7,7 +7,9 @@ Test infrastructure.  Follows the paper's numerical discretization (Section
      standard BDF coefficients alpha, u_BDF and the explicit extrapolation
      u_EXT of the same order (the paper cites but does not print them).
   2. Ionic step at every node with u* = u_EXT (eq. of the time-discrete ionic
-     model; Rush-Larsen gates, explicit other variables, see ionic.py).
+     model): Rush-Larsen gates and explicit other variables, or the paper's
+     semi-implicit BDF of the potential's order (ionic_scheme="bdf"; the
+     ionic state then keeps sigma levels of history), see ionic.py.
   3. Ionic current interpolation: I_ion is evaluated at the nodes at
      (u_EXT, w_{n+1}) and the load vector is M I_ion (the ICI sum over
      subdomains, one subdomain here).  The applied current is treated the
@@ -78,7 +80,7 @@ class Monodomain:
     """One monodomain simulation on one subdomain."""
 
     def __init__(self, xyz, conn, fibers, sigma, chi, cm, model, variant="", stimuli=(),
-                 dt=0.05, bdf=1, solver="auto", rtol=1e-13, max_it=5000, block=1):
+                 dt=0.05, bdf=1, solver="auto", rtol=1e-13, max_it=5000, block=1, ionic_scheme="rl"):
         self.xyz = np.asarray(xyz, np.float64)
         self.n = self.xyz.shape[0]
         self.model = IonicModel(model, variant)
@@ -96,6 +98,9 @@ class Monodomain:
         self.rtol = rtol
         self.max_it = max_it
         self.block = int(block)
+        if ionic_scheme not in ("rl", "bdf"):
+            raise ValueError(ionic_scheme)
+        self.ionic_scheme = ionic_scheme
         self._lu = {}
         self._prec = {}
         self.cg_iters = []
@@ -109,10 +114,15 @@ class Monodomain:
         self.set_state(u0, w0)
 
     # -- state ------------------------------------------------------------
-    def set_state(self, u, w, u_prev=None, step_index=0):
-        """u_n, ionic state and optional earlier potentials [u_{n-1}, ...]."""
+    def set_state(self, u, w, u_prev=None, step_index=0, w_prev=None):
+        """u_n, ionic state and optional earlier potentials [u_{n-1}, ...]
+        (and, for the BDF ionic scheme, earlier states [w_{n-1}, ...];
+        copies of w when absent)."""
         u = np.array(u, np.float64)
         self.w = np.array(w, np.float64).reshape(self.model.n_vars, self.n)
+        wp = list(w_prev) if w_prev is not None else []
+        self.w_hist = [self.w] + [np.array(wp[k - 1], np.float64).reshape(self.model.n_vars, self.n)
+                                  if k - 1 < len(wp) else self.w.copy() for k in range(1, self.sigma)]
         hist = [u]
         prev = list(u_prev) if u_prev is not None else []
         for k in range(1, self.sigma):
@@ -212,7 +222,11 @@ class Monodomain:
         u_bdf = sum(c * h for c, h in zip(cb, self.hist))
         u_ext = sum(c * h for c, h in zip(ce, self.hist))
         t_new = (n + 1) * self.dt
-        self.w = self.model.step(u_ext, self.w, self.dt)
+        if self.ionic_scheme == "bdf":
+            self.w = self.model.step_bdf(u_ext, self.w_hist[:s], cb, ce, self.dt, alpha)
+            self.w_hist = [self.w] + self.w_hist[:-1]
+        else:
+            self.w = self.model.step(u_ext, self.w, self.dt)
         i_ion = self.model.iion(u_ext, self.w)
         i_app = self.applied(t_new)
         g = u_bdf / self.dt + i_app - i_ion
@@ -242,9 +256,10 @@ class Monodomain:
             -80.0 if self.model.name == "ap" else (-84.0 if self.model.name == "bo" else 0.0))
 
 
-def from_spec(spec, solver="auto", rtol=1e-13, block=1):
+def from_spec(spec, solver="auto", rtol=1e-13, block=1, ionic_scheme="rl"):
     """Build an oracle simulation from a workloads.SimSpec."""
     p = spec.phys
     return Monodomain(spec.mesh.xyz, spec.mesh.conn, spec.fibers,
                       (p.sigma_l, p.sigma_t, p.sigma_n), p.chi, p.cm, spec.model,
-                      spec.variant, spec.stimuli, spec.dt, spec.bdf, solver, rtol, block=block)
+                      spec.variant, spec.stimuli, spec.dt, spec.bdf, solver, rtol, block=block,
+                      ionic_scheme=ionic_scheme)
