@@ -80,10 +80,20 @@ enum {
                                workgroups, default), 2 (256) or 4 (128)               */
   EP_OPT_TILE_MAP = 7,      /* 0: each XCD sweeps a contiguous range of 512-row tiles
                                (default); 1: workgroup b takes tile b                 */
-  EP_OPT_GRAPH = 8          /* 1: replay the step's launch sequences from captured
+  EP_OPT_GRAPH = 8,         /* 1: replay the step's launch sequences from captured
                                HIP graphs (ignored while timers are on).  The stream
                                must allow capture (not the legacy null stream).      */
+  EP_OPT_IONIC_SCHEME = 9   /* EP_IONIC_* (before finalize)                           */
 };
+
+/* Ionic integrators (EP_OPT_IONIC_SCHEME).  EP_IONIC_RUSH_LARSEN (default):
+ * gates by the exponential at u_EXT, other variables one explicit step.
+ * EP_IONIC_BDF: the paper's time-discrete ionic model, (alpha w_{n+1} -
+ * w_BDF)/dt = H(u_EXT, w_EXT, w_{n+1}) with the potential's BDF order, gates
+ * implicit, other variables explicit (Aliev-Panfilov v implicit in its -v
+ * term); it keeps three earlier levels of the ionic state (4x its memory).
+ * ep_sim_set_state fills the earlier levels with copies of w. */
+enum { EP_IONIC_RUSH_LARSEN = 0, EP_IONIC_BDF = 1 };
 
 /* Kernel kinds reported by ep_sim_get_kernel_times. */
 enum {

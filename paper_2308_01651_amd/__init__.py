@@ -26,7 +26,8 @@ EP_DTYPE_F64, EP_DTYPE_F32 = 0, 1
 EP_FMT_AUTO, EP_FMT_SELL, EP_FMT_DIA = 0, 1, 2
 EP_OPT_MATRIX_FORMAT, EP_OPT_INNER_RTOL, EP_OPT_MAX_OUTER, EP_OPT_PHASE_TIMERS = 1, 2, 3, 4
 EP_OPT_KERNEL_TIMERS = 5
-EP_OPT_IONIC_NPT, EP_OPT_TILE_MAP, EP_OPT_GRAPH = 6, 7, 8
+EP_OPT_IONIC_NPT, EP_OPT_TILE_MAP, EP_OPT_GRAPH, EP_OPT_IONIC_SCHEME = 6, 7, 8, 9
+EP_IONIC_RUSH_LARSEN, EP_IONIC_BDF = 0, 1
 KERNEL_KINDS = ["ionic", "rhs", "cg_spmv", "cg_update", "activation", "ir_residual", "cg_finalize"]
 
 MODEL_IDS = {"passive": EP_PASSIVE, "ap": EP_AP, "bo": EP_BO, "ttp06": EP_TTP06}
@@ -197,9 +198,11 @@ class Simulation:
     # -- convenience -----------------------------------------------------------
     @classmethod
     def from_spec(cls, spec, precision=EP_FP64, device=0, stream=None, rtol=None, max_it=1000,
-                  matrix_format=EP_FMT_AUTO, finalize=True, inner_rtol=None, block=1):
+                  matrix_format=EP_FMT_AUTO, finalize=True, inner_rtol=None, block=1, ionic_scheme="rl"):
         """Configure from a workloads.SimSpec (marshalling of its arrays).
-        block > 1 selects block-Jacobi preconditioning with that block size."""
+        block > 1 selects block-Jacobi preconditioning with that block size;
+        ionic_scheme "rl" (Rush-Larsen) or "bdf" (the paper's semi-implicit
+        BDF)."""
         sim = cls(device, stream)
         m = spec.mesh
         sim.upload_mesh(m.elem, m.xyz, m.conn)
@@ -216,6 +219,8 @@ class Simulation:
             sim.set_option(EP_OPT_MATRIX_FORMAT, matrix_format)
         if inner_rtol is not None:
             sim.set_option(EP_OPT_INNER_RTOL, inner_rtol)
+        if ionic_scheme != "rl":
+            sim.set_option(EP_OPT_IONIC_SCHEME, {"bdf": EP_IONIC_BDF}[ionic_scheme])
         if finalize:
             sim.finalize()
         return sim

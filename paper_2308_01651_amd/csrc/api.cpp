@@ -250,6 +250,7 @@ struct ep_sim {
   std::vector<Stim> stims;
   double dt = 0.05, rtol = 1e-10, inner_rtol = 1e-4;
   int bdf = 1, prec = EP_FP64, precond = EP_JACOBI, block = 1, max_it = 1000, max_outer = 30;
+  int ionic_scheme = 0;   // EP_IONIC_RUSH_LARSEN or EP_IONIC_BDF
   int fmt_pref = EP_FMT_AUTO;
   int timers = 0;
   // products
@@ -317,7 +318,7 @@ size_t estimate_bytes(const ep_sim* s) {
   double per_node = 11 * 8.0 + 24.0;                            // FP64 vectors, activation
   per_node += (double)s->bdf * s->block * (mixed ? 12.0 : 8.0);  // preconditioner(s)
   per_node += mixed ? 5 * 4.0 : 0.0;
-  per_node += mixed ? (mi.nvars * 4.0 + 8.0) : mi.nvars * 8.0;
+  per_node += (mixed ? (mi.nvars * 4.0 + 8.0) : mi.nvars * 8.0) * (s->ionic_scheme == EP_IONIC_BDF ? RING : 1);
   per_node += nnz_row * ((s->bdf + 1) * 8.0 + 4.0 + (mixed ? s->bdf * 4.0 : 0.0));
   per_node += 8.0 * std::min<size_t>(s->stims.size(), MAX_STIM);
   return (size_t)(per_node * n * 1.05) + (1u << 20);
@@ -467,6 +468,7 @@ ep_status finalize_impl(ep_sim* s) {
   D.precond = s->precond;
   D.block = s->block;
   D.bld = round_up(n, 64);
+  D.ionic_scheme = s->ionic_scheme;
   default_params(s->model, s->variant, D.mp);
   for (size_t k = 0; k < s->params.size(); k++) D.mp[k] = s->params[k];
   hipStream_t st = s->stream;
@@ -636,13 +638,19 @@ ep_status finalize_impl(ep_sim* s) {
   }
   // ---- ionic state ----
   const int nvars = s->nvars;
-  if (mixed) {
-    const int n32 = (s->model == EP_TTP06) ? 16 : nvars;
-    const int n64 = (s->model == EP_TTP06) ? 2 : 0;
-    EP_HIP(m.alloc((void**)&D.st32, std::max<int64_t>(1, (int64_t)n32 * n) * sizeof(float)));
-    EP_HIP(m.alloc((void**)&D.st64, std::max<int64_t>(1, (int64_t)n64 * n) * sizeof(double)));
-  } else {
-    EP_HIP(m.alloc((void**)&D.st64, std::max<int64_t>(1, (int64_t)nvars * n) * sizeof(double)));
+  // one state array per time level under the BDF ionic scheme, one shared
+  // by all four level slots under Rush-Larsen
+  const int n_levels = s->ionic_scheme == EP_IONIC_BDF ? RING : 1;
+  const int n32 = mixed ? ((s->model == EP_TTP06) ? 16 : nvars) : 0;
+  const int n64 = mixed ? ((s->model == EP_TTP06) ? 2 : 0) : nvars;
+  for (int k = 0; k < RING; k++) {
+    if (k < n_levels) {
+      EP_HIP(m.alloc((void**)&D.st32[k], std::max<int64_t>(1, (int64_t)n32 * n) * sizeof(float)));
+      EP_HIP(m.alloc((void**)&D.st64[k], std::max<int64_t>(1, (int64_t)n64 * n) * sizeof(double)));
+    } else {
+      D.st32[k] = D.st32[0];
+      D.st64[k] = D.st64[0];
+    }
   }
   EP_HIP(m.alloc((void**)&D.smax, n * sizeof(double)));
   EP_HIP(m.alloc((void**)&D.at, n * sizeof(double)));
@@ -727,10 +735,12 @@ ep_status validate_desc(const InstDesc& D, int64_t guard) {
     if (!D.valA[q] || !D.dinv[q]) return bad("operator values");
     if (D.prec == P_MIXED && (!D.valA32[q] || !D.dinv32[q])) return bad("FP32 operator values");
   }
-  if (D.prec == P_MIXED && (!D.r32 || !D.z32 || !D.p32 || !D.s32 || !D.w32 || !D.st32)) return bad("FP32 vectors");
+  if (D.prec == P_MIXED && (!D.r32 || !D.z32 || !D.p32 || !D.s32 || !D.w32)) return bad("FP32 vectors");
+  for (int k = 0; k < RING; k++)
+    if (!D.st64[k] || !D.st32[k]) return bad("ionic state levels");
+  if (D.ionic_scheme != 0 && D.ionic_scheme != 1) return bad("ionic scheme");
   if (D.block < 1 || D.block > 64 || (D.block & (D.block - 1)) != 0 || D.bld < ((D.n + 63) / 64) * 64)
     return bad("preconditioner blocks");
-  if (D.nvars > 0 && !D.st64 && !D.st32) return bad("ionic state");
   if (D.fmt == FMT_DIA) {
     if (D.nup < 1 || D.nup > MAX_UP || D.off[0] != 0) return bad("DIA diagonals");
     for (int d = 1; d < D.nup; d++)
@@ -751,6 +761,7 @@ Launch launch_of(ep_sim* s) {
   Launch L{s->d_desc, s->d_bmap, s->nblocks, s->stream, true};
   L.xmap = s->xmap;
   L.ionic_npt = s->ionic_npt;
+  L.ionic_bdf = s->ionic_scheme == EP_IONIC_BDF;
   return L;
 }
 
@@ -1051,6 +1062,10 @@ ep_status ep_sim_set_option(ep_sim* s, int key, double value) {
       if (!(value >= 1)) return fail(EP_EINVAL, "max outer");
       s->max_outer = (int)value;
       return EP_OK;
+    case EP_OPT_IONIC_SCHEME:
+      if (value != EP_IONIC_RUSH_LARSEN && value != EP_IONIC_BDF) return fail(EP_EINVAL, "ionic scheme");
+      s->ionic_scheme = (int)value;
+      return EP_OK;
     default: return fail(EP_EINVAL, "unknown option");
   }
 }
@@ -1157,14 +1172,23 @@ ep_status ep_sim_set_state(ep_sim* s, const double* u, const double* w, const do
             else s32[(size_t)15 * n + i] = (float)x;
           }
         }
-        EP_HIP(hipMemcpyAsync(D.st64, s64.data(), s64.size() * 8, hipMemcpyHostToDevice, st));
       } else {
         s32.assign(w, w + (size_t)nv * n);
       }
-      EP_HIP(hipMemcpyAsync(D.st32, s32.data(), s32.size() * 4, hipMemcpyHostToDevice, st));
+      // level n and, for the BDF ionic scheme, levels n-1 and n-2 (copies)
+      for (int k = 0; k < 3; k++) {
+        const int slot = (int)((step_index - k) & 3);
+        if (k > 0 && D.st32[slot] == D.st32[step_index & 3]) break;
+        if (!s64.empty()) EP_HIP(hipMemcpyAsync(D.st64[slot], s64.data(), s64.size() * 8, hipMemcpyHostToDevice, st));
+        EP_HIP(hipMemcpyAsync(D.st32[slot], s32.data(), s32.size() * 4, hipMemcpyHostToDevice, st));
+      }
       EP_HIP(hipStreamSynchronize(st));
     } else {
-      EP_HIP(hipMemcpyAsync(D.st64, w, (size_t)nv * n * 8, hipMemcpyHostToDevice, st));
+      for (int k = 0; k < 3; k++) {
+        const int slot = (int)((step_index - k) & 3);
+        if (k > 0 && D.st64[slot] == D.st64[step_index & 3]) break;
+        EP_HIP(hipMemcpyAsync(D.st64[slot], w, (size_t)nv * n * 8, hipMemcpyHostToDevice, st));
+      }
     }
   }
   launch_fill(D.smax, n, -std::numeric_limits<double>::infinity(), st);
@@ -1207,8 +1231,9 @@ ep_status ep_sim_get_state(ep_sim* s, double* u, double* w, double* u_prev) {
       const int n32 = (s->model == EP_TTP06) ? 16 : nv;
       std::vector<float> s32((size_t)n32 * n);
       std::vector<double> s64(s->model == EP_TTP06 ? (size_t)2 * n : 0);
-      EP_HIP(hipMemcpyAsync(s32.data(), D.st32, s32.size() * 4, hipMemcpyDeviceToHost, st));
-      if (!s64.empty()) EP_HIP(hipMemcpyAsync(s64.data(), D.st64, s64.size() * 8, hipMemcpyDeviceToHost, st));
+      EP_HIP(hipMemcpyAsync(s32.data(), D.st32[step & 3], s32.size() * 4, hipMemcpyDeviceToHost, st));
+      if (!s64.empty())
+        EP_HIP(hipMemcpyAsync(s64.data(), D.st64[step & 3], s64.size() * 8, hipMemcpyDeviceToHost, st));
       EP_HIP(hipStreamSynchronize(st));
       if (s->model == EP_TTP06) {
         for (int v = 0; v < 18; v++)
@@ -1224,7 +1249,7 @@ ep_status ep_sim_get_state(ep_sim* s, double* u, double* w, double* u_prev) {
         for (size_t k = 0; k < s32.size(); k++) w[k] = s32[k];
       }
     } else {
-      EP_HIP(hipMemcpyAsync(w, D.st64, (size_t)nv * n * 8, hipMemcpyDeviceToHost, st));
+      EP_HIP(hipMemcpyAsync(w, D.st64[step & 3], (size_t)nv * n * 8, hipMemcpyDeviceToHost, st));
     }
   }
   EP_HIP(hipStreamSynchronize(st));
@@ -1440,8 +1465,9 @@ struct ep_pool {
   std::vector<int> active;
   BlockMap* d_all = nullptr;
   int nb_all = 0;
-  BlockMap* d_model[4] = {nullptr, nullptr, nullptr, nullptr};
-  int nb_model[4] = {0, 0, 0, 0};
+  // ionic launches per (model, ionic scheme): index 2 * model + scheme
+  BlockMap* d_model[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  int nb_model[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   int32_t* d_ids = nullptr;
   int it_pred = 8;
   SweepPredictor sweeps;  // mixed: rounds per sweep (largest over the instances)
@@ -1473,13 +1499,13 @@ ep_status pool_rebuild(ep_pool* P) {
   P->active.clear();
   for (int k = 0; k < P->max_slots; k++)
     if (P->slots[k].sim && !P->slots[k].done) P->active.push_back(k);
-  std::vector<BlockMap> all, per_model[4];
+  std::vector<BlockMap> all, per_model[8];
   for (int k : P->active) {
     const ep_sim* s = P->slots[k].sim;
     const int nt = s->desc.nblk;
     for (int t = 0; t < nt; t++) {
       all.push_back(BlockMap{k, t});
-      per_model[s->model].push_back(BlockMap{k, t});
+      per_model[2 * s->model + s->ionic_scheme].push_back(BlockMap{k, t});
     }
   }
   auto put = [&](const std::vector<BlockMap>& v, BlockMap** d, int* nb) -> hipError_t {
@@ -1495,7 +1521,7 @@ ep_status pool_rebuild(ep_pool* P) {
     return hipStreamSynchronize(P->stream);
   };
   EP_HIP(put(all, &P->d_all, &P->nb_all));
-  for (int m = 0; m < 4; m++) EP_HIP(put(per_model[m], &P->d_model[m], &P->nb_model[m]));
+  for (int m = 0; m < 8; m++) EP_HIP(put(per_model[m], &P->d_model[m], &P->nb_model[m]));
   std::vector<int32_t> ids(P->active.begin(), P->active.end());
   if (!ids.empty()) {
     EP_HIP(P->maps.alloc((void**)&P->d_ids, ids.size() * sizeof(int32_t)));
@@ -1540,11 +1566,12 @@ ep_status pool_step_once(ep_pool* P) {
   };
   auto pro = [&] {
     kt.timed(st, 0, [&] {
-      for (int m = 0; m < 4; m++)
+      for (int m = 0; m < 8; m++)
         if (P->nb_model[m] > 0) {
           Launch Lm{P->d_table, P->d_model[m], P->nb_model[m], st, false};
           Lm.ionic_npt = P->ionic_npt;
-          launch_ionic(m, mixed, Lm);
+          Lm.ionic_bdf = (m & 1) != 0;
+          launch_ionic(m / 2, mixed, Lm);
         }
     });
     kt.timed(st, 1, [&] { launch_residual(mixed, true, L); });

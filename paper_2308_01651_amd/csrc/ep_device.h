@@ -79,7 +79,8 @@ struct InstDesc {
   int32_t blk0, nblk;      // this instance's workgroups in node-parallel launches
   int32_t model, bdf, prec, fmt;
   int32_t nup, max_it, max_outer, n_stim;   // nup: stored (upper) DIA diagonals
-  int32_t nvars, precond, block, pad_;   // block: rows per preconditioner block (1: Jacobi)
+  int32_t nvars, precond, block;         // block: rows per preconditioner block (1: Jacobi)
+  int32_t ionic_scheme;    // 0: Rush-Larsen, 1: the paper's semi-implicit BDF
   int64_t bld;             // block Jacobi: leading dimension of the inverse-block columns
   double dt, inv_dt, rtol, inner_rtol, threshold;
   double mp[NPARAM];       // ionic model parameters
@@ -105,9 +106,11 @@ struct InstDesc {
   double *g, *b, *r, *z, *p, *s, *w;
   // FP32 inner-solve vectors (mixed precision)
   float *r32, *z32, *p32, *s32, *w32;
-  // ionic state, structure of arrays [var][n]
-  double* st64;            // FP64 state (all variables in FP64 mode; nai, ki in mixed)
-  float* st32;             // FP32 state (mixed mode)
+  // ionic state, structure of arrays [var][n], one array per time level: the
+  // state of level m lives in st64[m & 3] / st32[m & 3] (the BDF scheme keeps
+  // w_{n+1}, w_n, w_{n-1}, w_{n-2}; under Rush-Larsen all four alias one array)
+  double* st64[RING];      // FP64 state (all variables in FP64 mode; nai, ki in mixed)
+  float* st32[RING];       // FP32 state (mixed mode)
   // activation tracking
   double *smax, *at, *tcross;
   StimGroup stim[MAX_STIM];

@@ -7,10 +7,17 @@
 //   Bueno-Orovio minimal (2008)   EPI parameter set, u dimensionless
 //   ten Tusscher-Panfilov (2006)  endo / mid / epi cells, V in mV
 // One call advances the ionic state by dt at the extrapolated potential u*
-// (eq. of the time-discrete ionic model): gating variables by Rush-Larsen,
-// the others by one explicit step with rates at (u*, new gates, old
-// concentrations); then returns I_ion(u*, w_{n+1}), which the monodomain
-// step uses explicitly (eq. of the time-discrete monodomain equation).
+// (eq. of the time-discrete ionic model) with one of two integrators, then
+// returns I_ion(u*, w_{n+1}), which the monodomain step uses explicitly (eq.
+// of the time-discrete monodomain equation):
+//   Rush-Larsen: gating variables by the exact exponential at u*, the others
+//     by one explicit step with rates at (u*, new gates, old concentrations);
+//   the paper's semi-implicit BDF (`*_bdf`): (alpha w_{n+1} - w_BDF)/dt =
+//     H(u_EXT, w_EXT, w_{n+1}) with the potential's BDF order; gates implicit,
+//     y_{n+1} = (y_BDF + dt y_inf/tau)/(alpha + dt/tau) with y_inf, tau at
+//     (u*, w_EXT); Aliev-Panfilov v implicit in its -v term with
+//     eps(u*, v_EXT); TTP06 concentrations explicit from (u*, new gates,
+//     extrapolated concentrations), calcium as buffered totals.
 //
 // Precision: R = double (FP64 path) or float (mixed path).  The TTP06 sodium
 // and potassium concentrations stay in double in both, because their
@@ -52,6 +59,21 @@ __device__ __forceinline__ R ap_step(R u, R dt, const double* mp, R& v) {
   return (k * u * (u - a) * (u - R(1)) + u * v) * invT;
 }
 
+template <typename R>
+__device__ __forceinline__ R ap_step_bdf(R u, R dt, R alpha, const double* mp, R v_bdf, R v_ext, R& v) {
+  const R k = R(mp[0]), a = R(mp[1]), eps0 = R(mp[2]), mu1 = R(mp[3]), mu2 = R(mp[4]);
+  const R invT = R(1.0 / mp[5]);
+  const R eps = (eps0 + mu1 * v_ext / (u + mu2)) * invT;
+  v = (v_bdf - dt * eps * (k * u * (u - a - R(1)))) / (alpha + dt * eps);
+  return (k * u * (u - a) * (u - R(1)) + u * v) * invT;
+}
+
+// BDF step of a gate dy/dt = (y_inf - y)/tau, implicit in y.
+template <typename R>
+__device__ __forceinline__ R gate_bdf(R y_bdf, R y_inf, R tau, R dt, R alpha) {
+  return (y_bdf + dt * y_inf / tau) / (alpha + dt / tau);
+}
+
 // ---------------------------------------------------------------------------
 // Bueno-Orovio minimal model.  Parameter slots (EPI defaults set by the host):
 //  0 u_o  1 u_u  2 theta_v  3 theta_w  4 theta_v-  5 theta_o  6 tau_v1-
@@ -60,8 +82,11 @@ __device__ __forceinline__ R ap_step(R u, R dt, const double* mp, R& v) {
 //  21 tau_s1  22 tau_s2  23 k_s  24 u_s  25 tau_si  26 tau_winf  27 w_inf*
 // Heaviside H(x) = 1 for x > 0.  v, w, s are all gates (Rush-Larsen).
 // ---------------------------------------------------------------------------
-template <typename R>
-__device__ __forceinline__ R bo_step(R u, R dt, const double* mp, R& v, R& w, R& s) {
+// BDF = false: Rush-Larsen from (v, w, s); BDF = true: (v, w, s) are
+// overwritten with the semi-implicit BDF step from their BDF combinations yb.
+template <typename R, bool BDF = false>
+__device__ __forceinline__ R bo_step(R u, R dt, const double* mp, R& v, R& w, R& s, R alpha = R(1),
+                                     const R* yb = nullptr) {
   const bool hv = u > R(mp[2]);
   const bool hw = u > R(mp[3]);
   const bool hvm = u > R(mp[4]);
@@ -78,9 +103,15 @@ __device__ __forceinline__ R bo_step(R u, R dt, const double* mp, R& v, R& w, R&
   }
   const R s_inf = (R(1) + m_tanh(R(mp[23]) * (u - R(mp[24])))) * R(0.5);
   const R tau_s = hw ? R(mp[22]) : R(mp[21]);
-  v = rush_larsen(v, v_inf, tau_v, dt);
-  w = rush_larsen(w, w_inf, tau_w, dt);
-  s = rush_larsen(s, s_inf, tau_s, dt);
+  if (BDF) {
+    v = gate_bdf(yb[0], v_inf, tau_v, dt, alpha);
+    w = gate_bdf(yb[1], w_inf, tau_w, dt, alpha);
+    s = gate_bdf(yb[2], s_inf, tau_s, dt, alpha);
+  } else {
+    v = rush_larsen(v, v_inf, tau_v, dt);
+    w = rush_larsen(w, w_inf, tau_w, dt);
+    s = rush_larsen(s, s_inf, tau_s, dt);
+  }
   // currents at (u*, w_{n+1})
   const R J_fi = hv ? -v * (u - R(mp[2])) * (R(mp[1]) - u) / R(mp[14]) : R(0);
   R J_so;
@@ -129,10 +160,28 @@ __device__ __forceinline__ R buffered_free(R total, R B, R K) {
   return b >= R(0) ? (R(2) * K * total) / (b + disc) : R(0.5) * (disc - b);
 }
 
+// Buffered total of a free concentration c: c + B c/(c + K).
 template <typename R>
-__device__ __forceinline__ R ttp06_step(R V, R dt, const double* mp, TtpState<R>& S) {
+__device__ __forceinline__ R buffered_total(R c, R B, R K) {
+  return c + B * c / (c + K);
+}
+
+// BDF = false: Rush-Larsen, S in/out.  BDF = true: S receives w_{n+1} from the
+// BDF combinations Sb (gates, nai, ki, rr; calcium as the buffered totals
+// tb[3] of cai, casr, cass) and the extrapolations Se.
+// (The BDF leading coefficient is named a_bdf: ttp::alpha is the Na/Ca
+// exchanger's parameter.)
+template <typename R, bool BDF = false>
+__device__ __forceinline__ R ttp06_step(R V, R dt, const double* mp, TtpState<R>& S, R a_bdf = R(1),
+                                        const TtpState<R>* Sb = nullptr, const TtpState<R>* Se = nullptr,
+                                        const R* tb = nullptr) {
   using namespace ttp;
   const R one = R(1);
+  // gate update: Rush-Larsen from the old gate, or implicit BDF from its combination
+  auto gate = [&](int k, R inf, R tau) {
+    if (BDF) S.g[k] = gate_bdf(Sb->g[k], inf, tau, dt, a_bdf);
+    else S.g[k] = rush_larsen(S.g[k], inf, tau, dt);
+  };
   // ---- gates: Rush-Larsen at V (fcass uses the old subspace calcium) ----
   // Exponentials of (V + a) / b with a shared b come from one exp(V / b):
   // exp((V + a) / b) = exp(a / b) exp(V / b); divisions by constants are
@@ -149,7 +198,7 @@ __device__ __forceinline__ R ttp06_step(R V, R dt, const double* mp, TtpState<R>
     const R a_m = one / (one + R(6.14421235332821e-06) * iE5);               // (-60 - V)/5
     const R b_m = R(0.1) / (one + R(1096.6331584284585) * E5) +              // (V + 35)/5
                   R(0.1) / (one + m_exp((V - R(50.0)) * R(0.005)));
-    S.g[0] = rush_larsen(S.g[0], m_inf, a_m * b_m, dt);
+    gate(0, m_inf, a_m * b_m);
 
     t = one + m_exp((V + R(71.55)) * R(1.0 / 7.43));
     const R hj_inf = one / (t * t);
@@ -166,21 +215,21 @@ __device__ __forceinline__ R ttp06_step(R V, R dt, const double* mp, TtpState<R>
             (V + R(37.78)) / (one + m_exp(R(0.311) * (V + R(79.23))));
       b_j = R(0.02424) * m_exp(R(-0.01052) * V) / (one + m_exp(R(-0.1378) * (V + R(40.14))));
     }
-    S.g[1] = rush_larsen(S.g[1], hj_inf, one / (a_h + b_h), dt);
-    S.g[2] = rush_larsen(S.g[2], hj_inf, one / (a_j + b_j), dt);
+    gate(1, hj_inf, one / (a_h + b_h));
+    gate(2, hj_inf, one / (a_j + b_j));
 
     const R xr1_inf = one / (one + R(0.0243728440732796) * iE7);            // (-26 - V)/7
     const R tau_xr1 = (R(450.0) / (one + R(0.011108996538242306) * iE10)) *  // (-45 - V)/10
                       (R(6.0) / (one + m_exp((V + R(30.0)) * R(1.0 / 11.5))));
-    S.g[3] = rush_larsen(S.g[3], xr1_inf, tau_xr1, dt);
+    gate(3, xr1_inf, tau_xr1);
     const R xr2_inf = one / (one + m_exp((V + R(88.0)) * R(1.0 / 24.0)));
     const R tau_xr2 = (R(3.0) / (one + R(0.049787068367863944) * iE20)) *    // (-60 - V)/20
                       (R(1.12) / (one + R(0.049787068367863944) * E20));     // (V - 60)/20
-    S.g[4] = rush_larsen(S.g[4], xr2_inf, tau_xr2, dt);
+    gate(4, xr2_inf, tau_xr2);
     const R xs_inf = one / (one + m_exp((R(-5.0) - V) * R(1.0 / 14.0)));
     const R tau_xs = (R(1400.0) / m_sqrt(one + R(2.300975890892825) * iE6)) *     // (5 - V)/6
                          (one / (one + m_exp((V - R(35.0)) * R(1.0 / 15.0)))) + R(80.0);
-    S.g[5] = rush_larsen(S.g[5], xs_inf, tau_xs, dt);
+    gate(5, xs_inf, tau_xs);
     R s_inf, tau_s;
     if (mp[16] != 0.0) {
       s_inf = one / (one + R(270.42640742615254) * E5);                      // (V + 28)/5
@@ -190,28 +239,29 @@ __device__ __forceinline__ R ttp06_step(R V, R dt, const double* mp, TtpState<R>
       tau_s = R(85.0) * m_exp(-(V + R(45.0)) * (V + R(45.0)) * R(1.0 / 320.0)) +
               R(5.0) / (one + R(0.01831563888873418) * E5) + R(3.0);          // (V - 20)/5
     }
-    S.g[6] = rush_larsen(S.g[6], s_inf, tau_s, dt);
+    gate(6, s_inf, tau_s);
     const R r_inf = one / (one + R(28.03162489452614) * iE6);                // (20 - V)/6
     const R tau_r = R(9.5) * m_exp(-(V + R(40.0)) * (V + R(40.0)) * R(1.0 / 1800.0)) + R(0.8);
-    S.g[7] = rush_larsen(S.g[7], r_inf, tau_r, dt);
+    gate(7, r_inf, tau_r);
     const R d_inf = one / (one + m_exp((R(-8.0) - V) * R(1.0 / 7.5)));
     const R tau_d = (R(1.4) / (one + m_exp((R(-35.0) - V) * R(1.0 / 13.0))) + R(0.25)) *
                         (R(1.4) / (one + R(2.718281828459045) * E5)) +       // (V + 5)/5
                     one / (one + R(12.182493960703473) * iE20);               // (50 - V)/20
-    S.g[8] = rush_larsen(S.g[8], d_inf, tau_d, dt);
+    gate(8, d_inf, tau_d);
     const R f_inf = one / (one + R(17.41170806332765) * E7);                 // (V + 20)/7
     const R e30 = R(20.085536923187668) * E10;                               // (V + 30)/10
     const R tau_f = R(1102.5) * m_exp(-(V + R(27.0)) * (V + R(27.0)) * R(1.0 / 225.0)) +
                     R(200.0) / (one + R(3.6692966676192444) * iE10) +        // (13 - V)/10
                     R(180.0) / (one + e30) + R(20.0);
-    S.g[9] = rush_larsen(S.g[9], f_inf, tau_f, dt);
+    gate(9, f_inf, tau_f);
     const R f2_inf = R(0.67) / (one + R(148.4131591025766) * E7) + R(0.33);  // (V + 35)/7
     const R tau_f2 = R(600.0) * m_exp(-(V + R(25.0)) * (V + R(25.0)) * R(1.0 / 170.0)) +
                      R(31.0) / (one + R(12.182493960703473) * iE10) +         // (25 - V)/10
                      R(16.0) / (one + e30);
-    S.g[10] = rush_larsen(S.g[10], f2_inf, tau_f2, dt);
-    const R cr = (S.cass / R(0.05)) * (S.cass / R(0.05));
-    S.g[11] = rush_larsen(S.g[11], R(0.6) / (one + cr) + R(0.4), R(80.0) / (one + cr) + R(2.0), dt);
+    gate(10, f2_inf, tau_f2);
+    const R cass_g = BDF ? Se->cass : S.cass;
+    const R cr = (cass_g / R(0.05)) * (cass_g / R(0.05));
+    gate(11, R(0.6) / (one + cr) + R(0.4), R(80.0) / (one + cr) + R(2.0));
   }
 
   // ---- factors that depend on V (and the new gates) only ----
@@ -270,8 +320,9 @@ __device__ __forceinline__ R ttp06_step(R V, R dt, const double* mp, TtpState<R>
 
   // ---- explicit concentration step with currents at the old concentrations ----
   {
-    const Cur c = membrane(S.cai, S.cass, S.nai, S.ki);
-    const R cai = S.cai, casr = S.casr, cass = S.cass, rr = S.rr;
+    const TtpState<R>& C = BDF ? *Se : S;     // concentrations the explicit rates use
+    const Cur c = membrane(C.cai, C.cass, C.nai, C.ki);
+    const R cai = C.cai, casr = C.casr, cass = C.cass, rr = C.rr;
     const R Iup = R(mp[14]) / (one + R(Kup * Kup) / (cai * cai));
     const R Ileak = R(mp[13]) * (casr - cai);
     const R kq = R(EC) / casr;
@@ -289,15 +340,25 @@ __device__ __forceinline__ R ttp06_step(R V, R dt, const double* mp, TtpState<R>
     const R d_nai = -(c.INa + c.IbNa + R(3) * c.INaK + R(3) * c.INaCa) * cmF / R(Vc);
     const R d_ki = -(c.IK1 + c.Ito + c.IKr + c.IKs - R(2) * c.INaK + c.IpK) * cmF / R(Vc);
     const R d_rr = -k2 * cass * rr + R(k4) * (one - rr);
-    const R tot_i = cai + R(Bufc) * cai / (cai + R(Kbufc)) + dt * d_cai;
-    const R tot_sr = casr + R(Bufsr) * casr / (casr + R(Kbufsr)) + dt * d_casr;
-    const R tot_ss = cass + R(Bufss) * cass / (cass + R(Kbufss)) + dt * d_cass;
-    S.cai = buffered_free(tot_i, R(Bufc), R(Kbufc));
-    S.casr = buffered_free(tot_sr, R(Bufsr), R(Kbufsr));
-    S.cass = buffered_free(tot_ss, R(Bufss), R(Kbufss));
-    S.nai = S.nai + (double)(dt * d_nai);
-    S.ki = S.ki + (double)(dt * d_ki);
-    S.rr = rr + dt * d_rr;
+    if (BDF) {
+      const R ia = one / a_bdf;
+      S.cai = buffered_free((tb[0] + dt * d_cai) * ia, R(Bufc), R(Kbufc));
+      S.casr = buffered_free((tb[1] + dt * d_casr) * ia, R(Bufsr), R(Kbufsr));
+      S.cass = buffered_free((tb[2] + dt * d_cass) * ia, R(Bufss), R(Kbufss));
+      S.nai = (Sb->nai + (double)(dt * d_nai)) / (double)a_bdf;
+      S.ki = (Sb->ki + (double)(dt * d_ki)) / (double)a_bdf;
+      S.rr = (Sb->rr + dt * d_rr) * ia;
+    } else {
+      const R tot_i = buffered_total(cai, R(Bufc), R(Kbufc)) + dt * d_cai;
+      const R tot_sr = buffered_total(casr, R(Bufsr), R(Kbufsr)) + dt * d_casr;
+      const R tot_ss = buffered_total(cass, R(Bufss), R(Kbufss)) + dt * d_cass;
+      S.cai = buffered_free(tot_i, R(Bufc), R(Kbufc));
+      S.casr = buffered_free(tot_sr, R(Bufsr), R(Kbufsr));
+      S.cass = buffered_free(tot_ss, R(Bufss), R(Kbufss));
+      S.nai = S.nai + (double)(dt * d_nai);
+      S.ki = S.ki + (double)(dt * d_ki);
+      S.rr = rr + dt * d_rr;
+    }
   }
   // ---- I_ion at (V, w_{n+1}) ----
   const Cur c = membrane(S.cai, S.cass, S.nai, S.ki);

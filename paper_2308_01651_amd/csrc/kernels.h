@@ -11,7 +11,8 @@ namespace ep {
 // instance and workgroups map to its tiles without a block map read (xmap 0:
 // each XCD sweeps a contiguous range of tiles; 1: workgroup b takes tile b).
 // ionic_npt: nodes per thread of the ionic kernel (1, 2 or 4; TILE / npt
-// threads per workgroup).
+// threads per workgroup).  A batch launches the ionic kernel per (model,
+// ionic scheme) group.
 struct Launch {
   InstDesc* insts;
   const BlockMap* bmap;
@@ -20,6 +21,7 @@ struct Launch {
   bool single;
   int xmap = 0;
   int ionic_npt = 1;
+  bool ionic_bdf = false;  // the instances use the semi-implicit BDF ionic scheme
 };
 
 void launch_ionic(int model, bool mixed, const Launch& L);

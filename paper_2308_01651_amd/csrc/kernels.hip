@@ -28,6 +28,8 @@
 // depend on the batch.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "ep_device.h"
 #include "ionic_models.h"
 #include "kernels.h"
@@ -221,7 +223,33 @@ __device__ __forceinline__ double stimulus_at(const InstDesc& I, int64_t k, int6
   return iapp;
 }
 
-template <int MODEL, bool MIXED>
+// BDF / extrapolation weights over the history levels n, n-1, n-2 of order
+// sig (the potential's coefficients; the paper applies the same BDF to the
+// ionic model).
+struct BdfW {
+  double alpha, b[3], e[3];
+};
+__device__ __forceinline__ BdfW bdf_weights(int sig) {
+  if (sig == 1) return BdfW{1.0, {1.0, 0.0, 0.0}, {1.0, 0.0, 0.0}};
+  if (sig == 2) return BdfW{1.5, {2.0, -0.5, 0.0}, {2.0, -1.0, 0.0}};
+  return BdfW{11.0 / 6.0, {3.0, -1.5, 1.0 / 3.0}, {3.0, -3.0, 1.0}};
+}
+
+// BDF combination and extrapolation of one state variable over `sig` levels
+// (arrays a[0..sig-1] = levels n, n-1, n-2 of that variable at node i).
+template <typename T>
+__device__ __forceinline__ void combine(const BdfW& W, int sig, const T* const* lv, int64_t off, T& xb, T& xe) {
+  T b = T(0), e = T(0);
+  for (int k = 0; k < sig; k++) {
+    const T x = lv[k][off];
+    b += T(W.b[k]) * x;
+    e += T(W.e[k]) * x;
+  }
+  xb = b;
+  xe = e;
+}
+
+template <int MODEL, bool MIXED, bool BDFS>
 __device__ __forceinline__ void ionic_node(const InstDesc& I, int64_t n, int64_t step, int64_t i) {
   const int sig = min(I.bdf, (int)step + 1);
   const double u0 = I.u_cur[i];
@@ -238,55 +266,78 @@ __device__ __forceinline__ void ionic_node(const InstDesc& I, int64_t n, int64_t
     u_ext = 3.0 * u0 - 3.0 * u1 + u2;
     u_bdf = 3.0 * u0 - 1.5 * u1 + u2 * (1.0 / 3.0);
   }
+  // state levels: new w_{n+1}, then w_n, w_{n-1}, w_{n-2}
+  double* __restrict__ s64 = I.st64[(step + 1) & 3];
+  float* __restrict__ s32 = I.st32[(step + 1) & 3];
+  const double* l64[3] = {I.st64[step & 3], I.st64[(step - 1) & 3], I.st64[(step - 2) & 3]};
+  const float* l32[3] = {I.st32[step & 3], I.st32[(step - 1) & 3], I.st32[(step - 2) & 3]};
+  // Rush-Larsen reads level n alone (weights 1)
+  const BdfW W = bdf_weights(BDFS ? sig : 1);
+  const int lev = BDFS ? sig : 1;
   double iion = 0.0;
   if (MODEL == M_AP) {
     if (MIXED) {
-      float v = I.st32[i];
-      iion = (double)ap_step<float>((float)u_ext, (float)I.dt, I.mp, v);
-      I.st32[i] = v;
+      float vb, ve;
+      combine<float>(W, lev, l32, i, vb, ve);
+      float v = vb;
+      iion = BDFS ? (double)ap_step_bdf<float>((float)u_ext, (float)I.dt, (float)W.alpha, I.mp, vb, ve, v)
+                  : (double)ap_step<float>((float)u_ext, (float)I.dt, I.mp, v);
+      s32[i] = v;
     } else {
-      double v = I.st64[i];
-      iion = ap_step<double>(u_ext, I.dt, I.mp, v);
-      I.st64[i] = v;
+      double vb, ve;
+      combine<double>(W, lev, l64, i, vb, ve);
+      double v = vb;
+      iion = BDFS ? ap_step_bdf<double>(u_ext, I.dt, W.alpha, I.mp, vb, ve, v)
+                  : ap_step<double>(u_ext, I.dt, I.mp, v);
+      s64[i] = v;
     }
   } else if (MODEL == M_BO) {
     if (MIXED) {
-      float v = I.st32[i], w = I.st32[n + i], s = I.st32[2 * n + i];
-      iion = (double)bo_step<float>((float)u_ext, (float)I.dt, I.mp, v, w, s);
-      I.st32[i] = v; I.st32[n + i] = w; I.st32[2 * n + i] = s;
+      float yb[3], ye[3];
+      for (int k = 0; k < 3; k++) combine<float>(W, lev, l32, (int64_t)k * n + i, yb[k], ye[k]);
+      float v = yb[0], w = yb[1], s = yb[2];
+      iion = (double)bo_step<float, BDFS>((float)u_ext, (float)I.dt, I.mp, v, w, s, (float)W.alpha, yb);
+      s32[i] = v; s32[n + i] = w; s32[2 * n + i] = s;
     } else {
-      double v = I.st64[i], w = I.st64[n + i], s = I.st64[2 * n + i];
-      iion = bo_step<double>(u_ext, I.dt, I.mp, v, w, s);
-      I.st64[i] = v; I.st64[n + i] = w; I.st64[2 * n + i] = s;
+      double yb[3], ye[3];
+      for (int k = 0; k < 3; k++) combine<double>(W, lev, l64, (int64_t)k * n + i, yb[k], ye[k]);
+      double v = yb[0], w = yb[1], s = yb[2];
+      iion = bo_step<double, BDFS>(u_ext, I.dt, I.mp, v, w, s, W.alpha, yb);
+      s64[i] = v; s64[n + i] = w; s64[2 * n + i] = s;
     }
   } else if (MODEL == M_TTP06) {
-    if (MIXED) {
-      // st32 rows: 12 gates, cai, casr, cass, rr ; st64 rows: nai, ki
-      TtpState<float> S;
+    // FP64 rows in state order: 12 gates, cai, casr, cass, nai, ki, rr.
+    // Mixed: st32 rows 12 gates, cai, casr, cass, rr; st64 rows nai, ki.
+    using R = typename std::conditional<MIXED, float, double>::type;
+    TtpState<R> S, Sb, Se;
+    R tb[3] = {R(0), R(0), R(0)};
+    auto row = [&](int v) -> int64_t { return (int64_t)v * n + i; };
+    const R* const* lr = reinterpret_cast<const R* const*>(MIXED ? (const void*)l32 : (const void*)l64);
 #pragma unroll
-      for (int k = 0; k < 12; k++) S.g[k] = I.st32[k * n + i];
-      S.cai = I.st32[12 * n + i]; S.casr = I.st32[13 * n + i]; S.cass = I.st32[14 * n + i];
-      S.rr = I.st32[15 * n + i];
-      S.nai = I.st64[i]; S.ki = I.st64[n + i];
-      iion = (double)ttp06_step<float>((float)u_ext, (float)I.dt, I.mp, S);
-#pragma unroll
-      for (int k = 0; k < 12; k++) I.st32[k * n + i] = S.g[k];
-      I.st32[12 * n + i] = S.cai; I.st32[13 * n + i] = S.casr; I.st32[14 * n + i] = S.cass;
-      I.st32[15 * n + i] = S.rr;
-      I.st64[i] = S.nai; I.st64[n + i] = S.ki;
-    } else {
-      // st64 rows in state order: 12 gates, cai, casr, cass, nai, ki, rr
-      TtpState<double> S;
-#pragma unroll
-      for (int k = 0; k < 12; k++) S.g[k] = I.st64[k * n + i];
-      S.cai = I.st64[12 * n + i]; S.casr = I.st64[13 * n + i]; S.cass = I.st64[14 * n + i];
-      S.nai = I.st64[15 * n + i]; S.ki = I.st64[16 * n + i]; S.rr = I.st64[17 * n + i];
-      iion = ttp06_step<double>(u_ext, I.dt, I.mp, S);
-#pragma unroll
-      for (int k = 0; k < 12; k++) I.st64[k * n + i] = S.g[k];
-      I.st64[12 * n + i] = S.cai; I.st64[13 * n + i] = S.casr; I.st64[14 * n + i] = S.cass;
-      I.st64[15 * n + i] = S.nai; I.st64[16 * n + i] = S.ki; I.st64[17 * n + i] = S.rr;
+    for (int k = 0; k < 12; k++) combine<R>(W, lev, lr, row(k), Sb.g[k], Se.g[k]);
+    combine<R>(W, lev, lr, row(12), Sb.cai, Se.cai);
+    combine<R>(W, lev, lr, row(13), Sb.casr, Se.casr);
+    combine<R>(W, lev, lr, row(14), Sb.cass, Se.cass);
+    combine<R>(W, lev, lr, row(MIXED ? 15 : 17), Sb.rr, Se.rr);
+    combine<double>(W, lev, l64, MIXED ? i : row(15), Sb.nai, Se.nai);
+    combine<double>(W, lev, l64, MIXED ? row(1) : row(16), Sb.ki, Se.ki);
+    if (BDFS) {
+      // BDF combination of the buffered calcium totals of each level
+      for (int k = 0; k < lev; k++) {
+        tb[0] += R(W.b[k]) * buffered_total<R>(lr[k][row(12)], R(ttp::Bufc), R(ttp::Kbufc));
+        tb[1] += R(W.b[k]) * buffered_total<R>(lr[k][row(13)], R(ttp::Bufsr), R(ttp::Kbufsr));
+        tb[2] += R(W.b[k]) * buffered_total<R>(lr[k][row(14)], R(ttp::Bufss), R(ttp::Kbufss));
+      }
     }
+    S = Sb;   // Rush-Larsen (one level): Sb holds w_n
+    iion = (double)ttp06_step<R, BDFS>((R)u_ext, (R)I.dt, I.mp, S, (R)W.alpha, &Sb, &Se, tb);
+    R* sr = reinterpret_cast<R*>(MIXED ? (void*)s32 : (void*)s64);
+#pragma unroll
+    for (int k = 0; k < 12; k++) sr[row(k)] = S.g[k];
+    sr[row(12)] = S.cai; sr[row(13)] = S.casr; sr[row(14)] = S.cass;
+    sr[row(MIXED ? 15 : 17)] = S.rr;
+    s64[MIXED ? i : row(15)] = S.nai;
+    s64[MIXED ? row(1) : row(16)] = S.ki;
   }
   const double iapp = stimulus_at(I, step + 1, i);
   I.g[i] = u_bdf * I.inv_dt + iapp - iion;
@@ -298,7 +349,7 @@ __device__ __forceinline__ void ionic_node(const InstDesc& I, int64_t n, int64_t
 // compiler for at least 4 (NPT 2) or 5 (NPT 4) waves per SIMD, trading
 // registers (and, for the FP64 TTP06 model, some spills) for occupancy; the
 // tuner measures which shape is fastest for a model and precision.
-template <int MODEL, bool MIXED, bool SINGLE, int NPT>
+template <int MODEL, bool MIXED, bool SINGLE, int NPT, bool BDFS>
 __global__ __launch_bounds__(TILE / NPT) __attribute__((amdgpu_waves_per_eu(NPT == 1 ? 1 : (NPT == 2 ? 4 : 5)))) void k_ionic(InstDesc* __restrict__ insts,
                                                       const BlockMap* __restrict__ bmap) {
   int lblk;
@@ -307,7 +358,7 @@ __global__ __launch_bounds__(TILE / NPT) __attribute__((amdgpu_waves_per_eu(NPT 
   const int64_t step = I.st.step;
   for (int p = 0; p < NPT; p++) {
     const int64_t i = (int64_t)lblk * TILE + p * (TILE / NPT) + threadIdx.x;
-    if (i < I.n) ionic_node<MODEL, MIXED>(I, I.n, step, i);
+    if (i < I.n) ionic_node<MODEL, MIXED, BDFS>(I, I.n, step, i);
   }
 }
 
@@ -664,10 +715,14 @@ __global__ void k_fill(double* __restrict__ x, int64_t n, double v) {
 
 template <int M, bool MX, int NPT>
 static void ionic_dispatch_npt(const Launch& L) {
-  if (L.single)
-    hipLaunchKernelGGL((k_ionic<M, MX, true, NPT>), dim3(L.nblocks), dim3(TILE / NPT), 0, L.stream, L.insts, L.bmap);
-  else
-    hipLaunchKernelGGL((k_ionic<M, MX, false, NPT>), dim3(L.nblocks), dim3(TILE / NPT), 0, L.stream, L.insts, L.bmap);
+  const dim3 g(L.nblocks), b(TILE / NPT);
+  if (L.ionic_bdf) {
+    if (L.single) hipLaunchKernelGGL((k_ionic<M, MX, true, NPT, true>), g, b, 0, L.stream, L.insts, L.bmap);
+    else hipLaunchKernelGGL((k_ionic<M, MX, false, NPT, true>), g, b, 0, L.stream, L.insts, L.bmap);
+  } else {
+    if (L.single) hipLaunchKernelGGL((k_ionic<M, MX, true, NPT, false>), g, b, 0, L.stream, L.insts, L.bmap);
+    else hipLaunchKernelGGL((k_ionic<M, MX, false, NPT, false>), g, b, 0, L.stream, L.insts, L.bmap);
+  }
 }
 
 template <int M, bool MX>
