@@ -117,10 +117,10 @@ def _warm(sim, ep, warmup, graph, autotune):
     return launch
 
 
-def run_gpu(spec, precision, steps, warmup, instrument_steps, graph=True, autotune=True):
+def run_gpu(spec, precision, steps, warmup, instrument_steps, graph=True, autotune=True, ionic_scheme="rl"):
     import paper_2308_01651_amd as ep
     import torch
-    sim = ep.Simulation.from_spec(spec, precision=precision)
+    sim = ep.Simulation.from_spec(spec, precision=precision, ionic_scheme=ionic_scheme)
     st0 = sim.get_stats()
     launch = _warm(sim, ep, warmup, graph, autotune)
     torch.cuda.synchronize()
@@ -376,10 +376,12 @@ def main():
               f"dominant {rl['kernel']} {rl['achieved']} GB/s", file=sys.stderr, flush=True)
     if "fp64" in out:
         # the same run with the default launches (eager, untuned) and with graph replay, for comparison
-        for name, g, t in (("fp64_default_launches", False, False), ("fp64_graph_replay", True, bool(args.autotune))):
-            if g == bool(args.graph) and t == bool(args.autotune):
+        for name, g, t, sch in (("fp64_default_launches", False, False, "rl"),
+                                ("fp64_graph_replay", True, bool(args.autotune), "rl"),
+                                ("fp64_paper_bdf_ionic_scheme", bool(args.graph), bool(args.autotune), "bdf")):
+            if g == bool(args.graph) and t == bool(args.autotune) and sch == "rl":
                 continue
-            r0, _, _ = run_gpu(spec, ep.EP_FP64, args.steps, args.warmup, 0, g, t)
+            r0, _, _ = run_gpu(spec, ep.EP_FP64, args.steps, args.warmup, 0, g, t, sch)
             out[name] = {k: r0[k] for k in ("node_steps_per_s", "ms_per_step", "step_latency_ms_p50",
                                             "step_latency_ms_p99", "launch")}
             print(f"[bench] {name}: {r0['node_steps_per_s']:.4g} node-steps/s", file=sys.stderr, flush=True)
