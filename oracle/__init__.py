@@ -13,9 +13,10 @@ Layout
                 Rush-Larsen / explicit integrator
   monodomain.py BDF/IMEX time stepping with ionic current interpolation,
                 linear solvers and activation times
+  cell.py       single-cell pacing (the monodomain step without diffusion)
 
 Parity status per function is stated in each module header; every function
 listed there is pinned by a `-m "not gpu"` test unless marked
 "parity unpinned".
 """
-from . import fem, ionic, monodomain  # noqa: F401
+from . import cell, fem, ionic, monodomain  # noqa: F401
