@@ -304,6 +304,26 @@ void ep_pool_destroy(ep_pool* pool);
  * finalized); used for admission control. */
 ep_status ep_sim_device_bytes_estimate(ep_sim* sim, size_t* bytes);
 
+/* ---- single-cell pacing ------------------------------------------------------ */
+
+/* Pace n_cells independent cells on the GPU (paper, Section "Ventricular
+ * slab": ionic states initialized by long single-cell runs at the cardiac
+ * period).  Each cell is the monodomain step without diffusion, with the
+ * tissue's Rush-Larsen ionic step and BDF order: alpha u_{n+1} = u_BDF +
+ * dt (I_app - I_ion(u_EXT, w_{n+1})).  params: [n_cells][n_params]
+ * overrides of the model's first n_params parameters (NULL: defaults of
+ * model/variant); init: [n_cells][1 + n_vars] starting u and state in model
+ * units and state order (NULL: the model's initial conditions).  The
+ * stimulus of stim_mV_per_ms (divided by the model's mV per unit for AP/BO)
+ * is on during the first stim_dur_ms of every period_ms (times rounded to
+ * whole steps, as in the tissue); n_beats periods are run, all from t = 0.
+ * out: [n_cells][1 + n_vars], a row per cell in the layout
+ * ep_sim_set_ionic_model takes as init_state.  EP_ENAN if a cell produced
+ * NaN (out is still written). */
+ep_status ep_cell_pace(int device, int model, int variant, int n_cells, const double* params, int n_params,
+                       const double* init, double dt_ms, int bdf_order, double period_ms, double stim_mV_per_ms,
+                       double stim_dur_ms, int n_beats, double* out);
+
 /* ---- host-only entry points (no GPU needed) -------------------------------- */
 
 /* The library's finite-element assembly, for inspection: CSR of M and K

@@ -291,6 +291,22 @@ class Pool:
             pass
 
 
+def cell_pace(model, variant="", n_cells=1, params=None, init=None, dt=0.05, bdf=2, period=800.0,
+              stim_mV_per_ms=40.0, stim_dur=1.0, n_beats=1, device=0):
+    """ep_cell_pace: pace single cells on the GPU; returns [n_cells, 1 + n_vars]
+    (u, then the state), each row usable as an initial state."""
+    mid = MODEL_IDS[model]
+    nv = {EP_PASSIVE: 0, EP_AP: 1, EP_BO: 3, EP_TTP06: 18}[mid]
+    out = np.zeros((int(n_cells), 1 + nv))
+    p = None if params is None else _f64(np.atleast_2d(params))
+    ini = None if init is None else _f64(np.atleast_2d(init))
+    check(lib.ep_cell_pace(int(device), mid, CELL_IDS.get(variant, 0), int(n_cells), _pd(p) if p is not None else None,
+                           0 if p is None else int(p.shape[1]), _pd(ini) if ini is not None else None, float(dt),
+                           int(bdf), float(period), float(stim_mV_per_ms), float(stim_dur), int(n_beats), _pd(out)),
+          "ep_cell_pace")
+    return out
+
+
 def assemble_csr(elem, xyz, conn, fibers=None, sigma=(0.17, 0.019, 0.019), chi=140.0, cm=0.01):
     """The library's host-side FE assembly (ep_assemble_csr): (rowptr, col, valM, valK)."""
     xyz = _f64(xyz)

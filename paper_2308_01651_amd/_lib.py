@@ -85,6 +85,8 @@ _SIGS = {
     "ep_sim_autotune": [P, C.c_int, PI32, PI32],
     "ep_sim_timer_overhead": [P, C.c_int, PD],
     "ep_sim_time_kernel": [P, C.c_int, C.c_int, PD],
+    "ep_cell_pace": [C.c_int, C.c_int, C.c_int, C.c_int, PD, C.c_int, PD, C.c_double, C.c_int, C.c_double,
+                     C.c_double, C.c_double, C.c_int, PD],
     "ep_assemble_csr": [C.c_int, C.c_int64, PD, C.c_int64, PI32, PD, PD, PD, C.c_double, C.c_double,
                         C.c_double, C.c_double, C.c_double, PI64, PI64, PI32, PD, PD],
 }

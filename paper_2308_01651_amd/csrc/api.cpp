@@ -1414,6 +1414,74 @@ void ep_sim_destroy(ep_sim* s) {
   delete s;
 }
 
+ep_status ep_cell_pace(int device, int model, int variant, int n_cells, const double* params, int n_params,
+                       const double* init, double dt_ms, int bdf_order, double period_ms, double stim_mV_per_ms,
+                       double stim_dur_ms, int n_beats, double* out) {
+  if (model < EP_PASSIVE || model > EP_TTP06) return fail(EP_EINVAL, "unknown ionic model");
+  if (model == EP_TTP06 && (variant < 0 || variant > 2)) return fail(EP_EINVAL, "bad TTP06 cell type");
+  if (n_cells < 1 || !out || !(dt_ms > 0) || bdf_order < 1 || bdf_order > 3 || !(period_ms > 0) ||
+      !(stim_dur_ms >= 0) || n_beats < 0 || n_params < 0 || n_params > n_model_params(model) ||
+      (n_params > 0 && !params))
+    return fail(EP_EINVAL, "bad pacing arguments");
+  int count = 0;
+  EP_HIP(hipGetDeviceCount(&count));
+  if (device < 0 || device >= count) return fail(EP_EINVAL, "no such device");
+  EP_HIP(hipSetDevice(device));
+  const ModelInfo mi = model_info(model);
+  const int nv = mi.nvars, nc = n_cells;
+  // per-cell parameters: defaults of (model, variant), then the caller's overrides
+  std::vector<double> mp((size_t)nc * NPARAM);
+  for (int c = 0; c < nc; c++) {
+    default_params(model, variant, &mp[(size_t)c * NPARAM]);
+    for (int k = 0; k < n_params; k++) mp[(size_t)c * NPARAM + k] = params[(size_t)c * n_params + k];
+  }
+  const std::vector<double> ic = default_init(model);
+  std::vector<double> uh((size_t)3 * nc), w((size_t)std::max(nv, 1) * nc, 0.0);
+  for (int c = 0; c < nc; c++) {
+    const double* row = init ? init + (size_t)c * (1 + nv) : ic.data();
+    for (int k = 0; k < 3; k++) uh[(size_t)k * nc + c] = row[0];
+    for (int v = 0; v < nv; v++) w[(size_t)v * nc + c] = row[1 + v];
+  }
+  DevMem m;
+  struct Guard {
+    DevMem& m;
+    hipStream_t s = nullptr;
+    ~Guard() {
+      if (s) {
+        (void)hipStreamSynchronize(s);
+        (void)hipStreamDestroy(s);
+      }
+      m.release();
+    }
+  } guard{m};
+  EP_HIP(hipStreamCreateWithFlags(&guard.s, hipStreamNonBlocking));
+  hipStream_t st = guard.s;
+  double *d_uh, *d_w, *d_mp;
+  EP_HIP(upload(m, &d_uh, uh.data(), uh.size(), st));
+  EP_HIP(upload(m, &d_w, w.data(), w.size(), st));
+  EP_HIP(upload(m, &d_mp, mp.data(), mp.size(), st));
+  const int64_t period = std::max<int64_t>(1, (int64_t)std::llround(period_ms / dt_ms));
+  const int64_t dur = (int64_t)std::llround(stim_dur_ms / dt_ms);
+  const int64_t total = (int64_t)n_beats * period;
+  const int64_t chunk = 20000;  // bounds each launch's duration
+  for (int64_t s0 = 0; s0 < total; s0 += chunk) {
+    launch_cell_pace(model, d_uh, d_w, d_mp, nc, dt_ms, bdf_order, s0, std::min(chunk, total - s0), period, dur,
+                     stim_mV_per_ms / mi.mv_per_unit, st);
+    EP_HIP(hipGetLastError());
+  }
+  EP_HIP(hipMemcpyAsync(uh.data(), d_uh, uh.size() * 8, hipMemcpyDeviceToHost, st));
+  EP_HIP(hipMemcpyAsync(w.data(), d_w, w.size() * 8, hipMemcpyDeviceToHost, st));
+  EP_HIP(hipStreamSynchronize(st));
+  bool nan = false;
+  for (int c = 0; c < nc; c++) {
+    out[(size_t)c * (1 + nv)] = uh[c];
+    nan |= !(uh[c] == uh[c]);
+    for (int v = 0; v < nv; v++) out[(size_t)c * (1 + nv) + 1 + v] = w[(size_t)v * nc + c];
+  }
+  if (nan) return fail(EP_ENAN, "a paced cell produced NaN");
+  return EP_OK;
+}
+
 ep_status ep_assemble_csr(int elem, int64_t n_nodes, const double* xyz, int64_t n_elems, const int32_t* conn,
                           const double* f0, const double* s0, const double* n0, double sl, double st, double sn,
                           double chi, double cm, int64_t* nnz_out, int64_t* rowptr, int32_t* col, double* valM,

@@ -35,5 +35,11 @@ void launch_activation(const Launch& L);
 void launch_end_step(InstDesc* insts, const int32_t* ids, int n_ids, hipStream_t stream);
 void launch_fill(double* x, int64_t n, double v, hipStream_t stream);
 void launch_to_mv(void* dst, const double* u, int64_t n, double a, double b, bool f32, hipStream_t stream);
+// single-cell pacing (cell.hip): n_steps steps of nc cells from step index
+// step0; uh [3][nc] potential history (u_n, u_{n-1}, u_{n-2}), w [n_vars][nc],
+// params [nc][NPARAM]; stimulus amp (model units per ms) on steps whose
+// index k+1 mod period (in steps) lies in [1, dur]
+void launch_cell_pace(int model, double* uh, double* w, const double* params, int nc, double dt, int bdf,
+                      int64_t step0, int64_t n_steps, int64_t period, int64_t dur, double amp, hipStream_t st);
 
 }  // namespace ep
