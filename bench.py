@@ -70,12 +70,16 @@ def kernel_bytes(kind, n, nnz, mixed, nvars_model, fmt="DIA", n_diag=0):
     return 0  # cg_finalize: one workgroup, partial sums only
 
 
+# the device code compiled into the time-step kernels (single-cell pacing and
+# the host-side library are not part of what the counter runs measured)
+STEP_KERNEL_SOURCES = ("ep_device.h", "ionic_models.h", "kernels.hip")
+
+
 def _src_hash():
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2308_01651_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h")):
-            h.update(open(os.path.join(csrc, f), "rb").read())
+    for f in STEP_KERNEL_SOURCES:
+        h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -168,10 +172,23 @@ def run_gpu(spec, precision, steps, warmup, instrument_steps, graph=True, autotu
         sim.step(warmup)
         sim.sync()
         sim.set_option(ep.EP_OPT_KERNEL_TIMERS, 1)
-        it1 = sim.get_stats()["cg_iters_total"]
-        sim.step(instrument_steps)
+        st1 = sim.get_stats()
+        it1, prev_it, prev_sw = st1["cg_iters_total"], st1["cg_iters_total"], st1["ir_sweeps_total"]
+        per_step_its, per_step_sweeps = [], []
+        for _ in range(instrument_steps):
+            sim.step(1)
+            st1 = sim.get_stats()
+            per_step_its.append(st1["cg_iters_total"] - prev_it)
+            per_step_sweeps.append(st1["ir_sweeps_total"] - prev_sw)
+            prev_it, prev_sw = st1["cg_iters_total"], st1["ir_sweeps_total"]
         sim.sync()
         kt = sim.get_kernel_times()
+        # CG iterations per step (mixed: inner FP32 iterations summed over the
+        # step's refinement sweeps) and refinement sweeps per step
+        res["cg_iters_histogram"] = {str(k): int(v) for k, v in zip(*np.unique(per_step_its, return_counts=True))}
+        if precision == ep.EP_MIXED:
+            res["ir_sweeps_histogram"] = {str(k): int(v)
+                                          for k, v in zip(*np.unique(per_step_sweeps, return_counts=True))}
         res["event_pair_overhead_us"] = sim.timer_overhead_us(500)
         res["instrumented_steps"] = instrument_steps
         res["instrumented_cg_iters"] = sim.get_stats()["cg_iters_total"] - it1
@@ -296,22 +313,52 @@ while True:
     if time.perf_counter() - t0 > budget and k >= 3:
         break
 T = time.perf_counter() - t0
+import numpy as np
+np.save({out!r}, np.stack([o.potential_mv(), o.activation_times()]))
 print(json.dumps({{"steps": k, "seconds": T, "n": spec.mesh.n_nodes}}))
 """
 
 
 def cpu_baseline(h, budget_s):
+    """Time the oracle on a bounded sample (one thread); also returns its
+    potential and activation times after the sample for the parity check."""
+    import tempfile
     env = dict(os.environ)
     for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "NUMEXPR_NUM_THREADS"):
         env[v] = "1"
-    code = CPU_SAMPLE.format(root=ROOT, h=h, budget=budget_s)
+    fd, out = tempfile.mkstemp(suffix=".npy")
+    os.close(fd)
+    code = CPU_SAMPLE.format(root=ROOT, h=h, budget=budget_s, out=out)
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=900)
     if r.returncode != 0:
-        return {"error": r.stderr[-500:]}
+        return {"error": r.stderr[-500:]}, None, 0
     d = json.loads(r.stdout.strip().splitlines()[-1])
-    return {"value": d["n"] * d["steps"] / d["seconds"], "unit": "node-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"steps 2..{d['steps'] + 1} of the same {d['n']}-node TTP06 slab from rest "
-                      f"(FP64 NumPy/SciPy, Jacobi-PCG to rtol 1e-10, one thread), {d['seconds']:.1f} s"}
+    fields = np.load(out)
+    os.unlink(out)
+    return ({"value": d["n"] * d["steps"] / d["seconds"], "unit": "node-steps/s", "cores": 1, "kind": "oracle",
+             "sample": f"steps 2..{d['steps'] + 1} of the same {d['n']}-node TTP06 slab from rest "
+                       f"(FP64 NumPy/SciPy, Jacobi-PCG to rtol 1e-10, one thread), {d['seconds']:.1f} s"},
+            fields, d["steps"] + 1)
+
+
+def oracle_check(spec, fields, steps):
+    """The GPU path over the oracle sample's steps from rest, both precisions:
+    error of the potential and of the activation times against the oracle."""
+    import paper_2308_01651_amd as ep
+    out = {"steps": steps}
+    u_o, at_o = fields
+    for name, prec in (("fp64", ep.EP_FP64), ("mixed", ep.EP_MIXED)):
+        sim = ep.Simulation.from_spec(spec, precision=prec)
+        sim.step(steps)
+        u, at = sim.get_potential(), sim.get_activation_times()
+        sim.close()
+        du = u - u_o
+        ok = ~np.isnan(at_o) & ~np.isnan(at)
+        out[name] = {"rel_l2": float(np.linalg.norm(du) / np.linalg.norm(u_o)),
+                     "rms_mV": float(np.sqrt(np.mean(du * du))), "max_abs_mV": float(np.max(np.abs(du))),
+                     "activated_equal": bool(np.array_equal(np.isnan(at_o), np.isnan(at))),
+                     "max_abs_dAT_ms": float(np.max(np.abs(at[ok] - at_o[ok]))) if ok.any() else None}
+    return out
 
 
 def main():
@@ -430,9 +477,14 @@ def main():
         print("[bench] serving: sequential plain FP64", file=sys.stderr, flush=True)
         serving["sequential_fp64"] = run_serving(ep.EP_FP64, 1, trace)
     cpu = None
+    oracle_cmp = None
     if not args.no_cpu_baseline and args.workload in ("c1", "c1big"):
         print("[bench] cpu baseline (oracle, 1 thread)", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(spec.mesh.xyz[1, 0] - spec.mesh.xyz[0, 0], args.cpu_budget)
+        cpu, ofields, osteps = cpu_baseline(spec.mesh.xyz[1, 0] - spec.mesh.xyz[0, 0], args.cpu_budget)
+        if ofields is not None:
+            oracle_cmp = oracle_check(spec, ofields, osteps)
+            print(f"[bench] oracle check over {osteps} steps: fp64 rel L2 {oracle_cmp['fp64']['rel_l2']:.2e}, "
+                  f"mixed RMS {oracle_cmp['mixed']['rms_mV']:.2e} mV", file=sys.stderr, flush=True)
     main_res = out["fp64"] if "fp64" in out else out["mixed"]
     line = {
         "metric": "monodomain node-steps/s (TTP06, 442k nodes) plain vs batched/FP32; p99 latency",
@@ -459,6 +511,7 @@ def main():
                                                                       "avg_launch_us_events", "event_pair_overhead_us",
                                                                       "launches", "launches_with_work")},
         "cpu_baseline": cpu,
+        "oracle_check": oracle_cmp,
         "variants": out,
         "batched": batched,
         "serving": serving,
