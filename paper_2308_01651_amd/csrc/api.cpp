@@ -590,7 +590,8 @@ ep_status finalize_impl(ep_sim* s) {
   }
   for (int q = 0; q < nsig; q++) {
     if (s->block == 1) {
-      std::vector<double> dinv(n);
+      // padded to whole 64-row groups: the solver kernels read rows in pairs
+      std::vector<double> dinv(round_up(n, 64), 0.0);
       for (int64_t i = 0; i < n; i++) dinv[i] = 1.0 / valA[q][dpos[i]];
       hostvals.push_back(dinv);
     } else {
@@ -604,7 +605,9 @@ ep_status finalize_impl(ep_sim* s) {
   }
   // ---- vectors (guarded) ----
   const int64_t G = s->guard;
-  const int64_t nv = n + 2 * G;
+  // rows padded to whole 64-row groups (the solver kernels read rows in
+  // pairs; the SELL format has no guard cells)
+  const int64_t nv = round_up(n, 64) + 2 * G;
   auto vec_d = [&](double** p) -> hipError_t {
     double* raw;
     hipError_t e = m.alloc((void**)&raw, nv * sizeof(double));

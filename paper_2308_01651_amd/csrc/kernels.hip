@@ -36,6 +36,18 @@
 
 namespace ep {
 
+// Device arrays are global memory, but a pointer read from the instance
+// descriptor is generic, and generic accesses compile to flat instructions.
+// Flat loads also count against the scalar-load counter, so every scalar load
+// of a descriptor field (a diagonal offset, a state flag) would wait for all
+// vector loads in flight.  gmem() re-types such a pointer as global.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gptr<T> gmem(T* p) {
+  return (gptr<T>)p;
+}
+
 // ---------------------------------------------------------------------------
 // reductions
 // ---------------------------------------------------------------------------
@@ -61,7 +73,7 @@ __device__ __forceinline__ void write_partials(double (&v)[NV], double* __restri
   __syncthreads();
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int c = 0; c < NV; c++) P[(int64_t)c * nblk + lblk] = (sh[0][c] + sh[1][c]) + (sh[2][c] + sh[3][c]);
+    for (int c = 0; c < NV; c++) gmem(P)[(int64_t)c * nblk + lblk] = (sh[0][c] + sh[1][c]) + (sh[2][c] + sh[3][c]);
   }
 }
 
@@ -76,7 +88,7 @@ __device__ __forceinline__ void reduce_partials(const double* __restrict__ P, in
   for (int c = 0; c < NV; c++) acc[c] = 0.0;
   for (int b = threadIdx.x; b < nblk; b += NT) {
 #pragma unroll
-    for (int c = 0; c < NV; c++) acc[c] += P[(int64_t)c * nblk + b];
+    for (int c = 0; c < NV; c++) acc[c] += gmem(P)[(int64_t)c * nblk + b];
   }
 #pragma unroll
   for (int c = 0; c < NV; c++) acc[c] = wave_sum(acc[c]);
@@ -119,12 +131,13 @@ __device__ __forceinline__ bool cg_idle(const InstState& S) {
 template <typename T>
 __device__ __forceinline__ T precond_apply(const T* __restrict__ pinv, int64_t bld, int bs, int64_t i, bool valid,
                                            T r) {
-  if (bs == 1) return valid ? pinv[i] * r : T(0);
+  const gptr<const T> pv = gmem(pinv);
+  if (bs == 1) return valid ? pv[i] * r : T(0);
   const int base = (int)(threadIdx.x & 63) & ~(bs - 1);
   T acc = T(0);
   for (int j = 0; j < bs; j++) {
     const T rj = __shfl(r, base + j, 64);
-    if (valid) acc += pinv[(int64_t)j * bld + i] * rj;
+    if (valid) acc += pv[(int64_t)j * bld + i] * rj;
   }
   return acc;
 }
@@ -139,14 +152,16 @@ template <int NU, typename V, typename X, typename A>
 __device__ __forceinline__ A dia_row(const InstDesc& I, const V* __restrict__ val, const X* __restrict__ x,
                                      int64_t i, int nu) {
   const int64_t ld = I.ld;
-  A acc = (A)val[i] * (A)x[i];
+  const gptr<const V> va = gmem(val);
+  const gptr<const X> xa = gmem(x);
+  A acc = (A)va[i] * (A)xa[i];
   const int n_up = NU > 0 ? NU : nu;
 #pragma unroll
   for (int d = 1; d < (NU > 0 ? NU : MAX_UP); d++) {
     if (NU == 0 && d >= n_up) break;
     const int o = I.off[d];
-    acc += (A)val[d * ld + i] * (A)x[i + o];
-    acc += (A)val[d * ld + i - o] * (A)x[i - o];
+    acc += (A)va[d * ld + i] * (A)xa[i + o];
+    acc += (A)va[d * ld + i - o] * (A)xa[i - o];
   }
   return acc;
 }
@@ -161,19 +176,21 @@ __device__ __forceinline__ A spmv_row(const InstDesc& I, const V* __restrict__ v
   }
   const int64_t slice = i >> 6;
   const int lane = (int)(i & 63);
-  const int64_t o0 = I.slice_ptr[slice], o1 = I.slice_ptr[slice + 1];
+  const int64_t o0 = gmem(I.slice_ptr)[slice], o1 = gmem(I.slice_ptr)[slice + 1];
   A acc = A(0);
-  const int32_t* __restrict__ col = I.col;
+  const gptr<const int32_t> col = gmem(I.col);
+  const gptr<const V> va = gmem(val);
+  const gptr<const X> xa = gmem(x);
   int64_t o = o0 + lane;
   for (; o + 3 * 64 < o1; o += 4 * 64) {
-    const V v0 = val[o], v1 = val[o + 64], v2 = val[o + 128], v3 = val[o + 192];
+    const V v0 = va[o], v1 = va[o + 64], v2 = va[o + 128], v3 = va[o + 192];
     const int32_t c0 = col[o], c1 = col[o + 64], c2 = col[o + 128], c3 = col[o + 192];
-    acc += (A)v0 * (A)x[c0];
-    acc += (A)v1 * (A)x[c1];
-    acc += (A)v2 * (A)x[c2];
-    acc += (A)v3 * (A)x[c3];
+    acc += (A)v0 * (A)xa[c0];
+    acc += (A)v1 * (A)xa[c1];
+    acc += (A)v2 * (A)xa[c2];
+    acc += (A)v3 * (A)xa[c3];
   }
-  for (; o < o1; o += 64) acc += (A)val[o] * (A)x[col[o]];
+  for (; o < o1; o += 64) acc += (A)va[o] * (A)xa[col[o]];
   return acc;
 }
 
@@ -214,11 +231,11 @@ __device__ __forceinline__ InstDesc& instance(InstDesc* __restrict__ insts, cons
 __device__ __forceinline__ double stimulus_at(const InstDesc& I, int64_t k, int64_t i) {
   double iapp = 0.0;
   for (int gi = 0; gi < I.n_stim; gi++) {
-    const StimGroup& G = I.stim[gi];
-    int64_t q = k - G.s0;
+    const StimGroup& sg = I.stim[gi];
+    int64_t q = k - sg.s0;
     if (q < 1) continue;
-    if (G.period > 0) q = (q - 1) % G.period + 1;
-    if (q <= G.dur) iapp += G.amp * G.prof[i];
+    if (sg.period > 0) q = (q - 1) % sg.period + 1;
+    if (q <= sg.dur) iapp += sg.amp * gmem(sg.prof)[i];
   }
   return iapp;
 }
@@ -241,7 +258,7 @@ template <typename T>
 __device__ __forceinline__ void combine(const BdfW& W, int sig, const T* const* lv, int64_t off, T& xb, T& xe) {
   T b = T(0), e = T(0);
   for (int k = 0; k < sig; k++) {
-    const T x = lv[k][off];
+    const T x = gmem(lv[k])[off];
     b += T(W.b[k]) * x;
     e += T(W.e[k]) * x;
   }
@@ -252,23 +269,23 @@ __device__ __forceinline__ void combine(const BdfW& W, int sig, const T* const* 
 template <int MODEL, bool MIXED, bool BDFS>
 __device__ __forceinline__ void ionic_node(const InstDesc& I, int64_t n, int64_t step, int64_t i) {
   const int sig = min(I.bdf, (int)step + 1);
-  const double u0 = I.u_cur[i];
+  const double u0 = gmem(I.u_cur)[i];
   double u_ext, u_bdf;
   if (sig == 1) {
     u_ext = u0;
     u_bdf = u0;
   } else if (sig == 2) {
-    const double u1 = I.u_prev1[i];
+    const double u1 = gmem(I.u_prev1)[i];
     u_ext = 2.0 * u0 - u1;
     u_bdf = 2.0 * u0 - 0.5 * u1;
   } else {
-    const double u1 = I.u_prev1[i], u2 = I.u_prev2[i];
+    const double u1 = gmem(I.u_prev1)[i], u2 = gmem(I.u_prev2)[i];
     u_ext = 3.0 * u0 - 3.0 * u1 + u2;
     u_bdf = 3.0 * u0 - 1.5 * u1 + u2 * (1.0 / 3.0);
   }
   // state levels: new w_{n+1}, then w_n, w_{n-1}, w_{n-2}
-  double* __restrict__ s64 = I.st64[(step + 1) & 3];
-  float* __restrict__ s32 = I.st32[(step + 1) & 3];
+  const gptr<double> s64 = gmem(I.st64[(step + 1) & 3]);
+  const gptr<float> s32 = gmem(I.st32[(step + 1) & 3]);
   const double* l64[3] = {I.st64[step & 3], I.st64[(step - 1) & 3], I.st64[(step - 2) & 3]};
   const float* l32[3] = {I.st32[step & 3], I.st32[(step - 1) & 3], I.st32[(step - 2) & 3]};
   // Rush-Larsen reads level n alone (weights 1)
@@ -324,14 +341,14 @@ __device__ __forceinline__ void ionic_node(const InstDesc& I, int64_t n, int64_t
     if (BDFS) {
       // BDF combination of the buffered calcium totals of each level
       for (int k = 0; k < lev; k++) {
-        tb[0] += R(W.b[k]) * buffered_total<R>(lr[k][row(12)], R(ttp::Bufc), R(ttp::Kbufc));
-        tb[1] += R(W.b[k]) * buffered_total<R>(lr[k][row(13)], R(ttp::Bufsr), R(ttp::Kbufsr));
-        tb[2] += R(W.b[k]) * buffered_total<R>(lr[k][row(14)], R(ttp::Bufss), R(ttp::Kbufss));
+        tb[0] += R(W.b[k]) * buffered_total<R>(gmem(lr[k])[row(12)], R(ttp::Bufc), R(ttp::Kbufc));
+        tb[1] += R(W.b[k]) * buffered_total<R>(gmem(lr[k])[row(13)], R(ttp::Bufsr), R(ttp::Kbufsr));
+        tb[2] += R(W.b[k]) * buffered_total<R>(gmem(lr[k])[row(14)], R(ttp::Bufss), R(ttp::Kbufss));
       }
     }
     S = Sb;   // Rush-Larsen (one level): Sb holds w_n
     iion = (double)ttp06_step<R, BDFS>((R)u_ext, (R)I.dt, I.mp, S, (R)W.alpha, &Sb, &Se, tb);
-    R* sr = reinterpret_cast<R*>(MIXED ? (void*)s32 : (void*)s64);
+    const gptr<R> sr = gmem(reinterpret_cast<R*>(MIXED ? (void*)I.st32[(step + 1) & 3] : (void*)I.st64[(step + 1) & 3]));
 #pragma unroll
     for (int k = 0; k < 12; k++) sr[row(k)] = S.g[k];
     sr[row(12)] = S.cai; sr[row(13)] = S.casr; sr[row(14)] = S.cass;
@@ -340,8 +357,8 @@ __device__ __forceinline__ void ionic_node(const InstDesc& I, int64_t n, int64_t
     s64[MIXED ? row(1) : row(16)] = S.ki;
   }
   const double iapp = stimulus_at(I, step + 1, i);
-  I.g[i] = u_bdf * I.inv_dt + iapp - iion;
-  I.u_new[i] = u_ext;
+  gmem(I.g)[i] = u_bdf * I.inv_dt + iapp - iion;
+  gmem(I.u_new)[i] = u_ext;
 }
 
 // One tile of TILE nodes per workgroup of TILE / NPT threads, NPT nodes per
@@ -380,6 +397,8 @@ __global__ __launch_bounds__(WG) void k_residual(InstDesc* __restrict__ insts, c
   }
   const int sig = min(I.bdf, (int)S.step + 1);
   const double* __restrict__ x = I.u_new;
+  const gptr<double> b = gmem(I.b), r = gmem(I.r), z = gmem(I.z);
+  const gptr<float> r32 = gmem(I.r32), z32 = gmem(I.z32);
   double v[4] = {0.0, 0.0, 0.0, 0.0};
   const int64_t i0 = (int64_t)lblk * TILE + threadIdx.x;
 #pragma unroll
@@ -390,29 +409,29 @@ __global__ __launch_bounds__(WG) void k_residual(InstDesc* __restrict__ insts, c
     if (valid) {
       if (WITH_RHS) {
         bi = spmv_row<double, double, double>(I, I.valM, I.g, i);
-        I.b[i] = bi;
+        b[i] = bi;
       } else {
-        bi = I.b[i];
+        bi = b[i];
       }
       ri = bi - spmv_row<double, double, double>(I, I.valA[sig - 1], x, i);
     }
     if (!MIXED) {
       const double zi = precond_apply<double>(I.dinv[sig - 1], I.bld, I.block, i, valid, ri);
       if (valid) {
-        I.r[i] = ri;
-        I.z[i] = zi;
+        r[i] = ri;
+        z[i] = zi;
         v[0] += ri * zi;
         v[1] += ri * ri;
       }
     } else {
-      const float r32 = (float)ri;
-      const float z32 = precond_apply<float>(I.dinv32[sig - 1], I.bld, I.block, i, valid, r32);
+      const float rf = (float)ri;
+      const float zf = precond_apply<float>(I.dinv32[sig - 1], I.bld, I.block, i, valid, rf);
       if (valid) {
-        I.r32[i] = r32;
-        I.z32[i] = z32;
-        v[0] += (double)r32 * (double)z32;
+        r32[i] = rf;
+        z32[i] = zf;
+        v[0] += (double)rf * (double)zf;
         v[1] += ri * ri;
-        v[3] += (double)r32 * (double)r32;
+        v[3] += (double)rf * (double)rf;
       }
     }
     if (WITH_RHS) v[2] += bi * bi;
@@ -454,12 +473,12 @@ __global__ __launch_bounds__(WG) void k_cg_spmv(InstDesc* __restrict__ insts, co
     if (i >= I.n) break;
     if (MIXED) {
       const float wi = spmv_row<float, float, float>(I, I.valA32[sig - 1], I.z32, i);
-      I.w32[i] = wi;
-      v[0] += (double)wi * (double)I.z32[i];
+      gmem(I.w32)[i] = wi;
+      v[0] += (double)wi * (double)gmem(I.z32)[i];
     } else {
       const double wi = spmv_row<double, double, double>(I, I.valA[sig - 1], I.z, i);
-      I.w[i] = wi;
-      v[0] += wi * I.z[i];
+      gmem(I.w)[i] = wi;
+      v[0] += wi * gmem(I.z)[i];
     }
   }
   write_partials<1>(v, I.partial + (int64_t)PART_SPMV * I.nblk, I.nblk, lblk);
@@ -587,7 +606,7 @@ __global__ __launch_bounds__(WG) void k_cg_update(InstDesc* __restrict__ insts, 
   const int k = S.it_f;
   const double alpha = S.alpha_cur, beta = S.beta;
   const int sig = min(I.bdf, (int)S.step + 1);
-  double* __restrict__ x = I.u_new;
+  const gptr<double> x = gmem(I.u_new);
   const int64_t i0 = (int64_t)lblk * TILE + threadIdx.x;
   double v[2] = {0.0, 0.0};
 #pragma unroll
@@ -598,32 +617,32 @@ __global__ __launch_bounds__(WG) void k_cg_update(InstDesc* __restrict__ insts, 
       const float fb = (float)beta, fa = (float)alpha;
       float rn = 0.0f;
       if (valid) {
-        const float z = I.z32[i], w = I.w32[i];
-        const float pn = (k == 0) ? z : z + fb * I.p32[i];
-        const float sn = (k == 0) ? w : w + fb * I.s32[i];
+        const float z = gmem(I.z32)[i], w = gmem(I.w32)[i];
+        const float pn = (k == 0) ? z : z + fb * gmem(I.p32)[i];
+        const float sn = (k == 0) ? w : w + fb * gmem(I.s32)[i];
         x[i] += alpha * (double)pn;
-        rn = I.r32[i] - fa * sn;
-        I.p32[i] = pn; I.s32[i] = sn; I.r32[i] = rn;
+        rn = gmem(I.r32)[i] - fa * sn;
+        gmem(I.p32)[i] = pn; gmem(I.s32)[i] = sn; gmem(I.r32)[i] = rn;
       }
       const float zn = precond_apply<float>(I.dinv32[sig - 1], I.bld, I.block, i, valid, rn);
       if (valid) {
-        I.z32[i] = zn;
+        gmem(I.z32)[i] = zn;
         v[0] += (double)rn * (double)zn;
         v[1] += (double)rn * (double)rn;
       }
     } else {
       double rn = 0.0;
       if (valid) {
-        const double z = I.z[i], w = I.w[i];
-        const double pn = (k == 0) ? z : z + beta * I.p[i];
-        const double sn = (k == 0) ? w : w + beta * I.s[i];
+        const double z = gmem(I.z)[i], w = gmem(I.w)[i];
+        const double pn = (k == 0) ? z : z + beta * gmem(I.p)[i];
+        const double sn = (k == 0) ? w : w + beta * gmem(I.s)[i];
         x[i] += alpha * pn;
-        rn = I.r[i] - alpha * sn;
-        I.p[i] = pn; I.s[i] = sn; I.r[i] = rn;
+        rn = gmem(I.r)[i] - alpha * sn;
+        gmem(I.p)[i] = pn; gmem(I.s)[i] = sn; gmem(I.r)[i] = rn;
       }
       const double zn = precond_apply<double>(I.dinv[sig - 1], I.bld, I.block, i, valid, rn);
       if (valid) {
-        I.z[i] = zn;
+        gmem(I.z)[i] = zn;
         v[0] += rn * zn;
         v[1] += rn * rn;
       }
@@ -651,15 +670,15 @@ __global__ __launch_bounds__(TILE) void k_activation(InstDesc* __restrict__ inst
   const int64_t i = (int64_t)lblk * TILE + threadIdx.x;
   if (i >= I.n) return;
   const double t = (double)(I.st.step + 1) * I.dt;
-  const double un = I.u_new[i];
-  const double slope = (un - I.u_cur[i]) * I.inv_dt;
-  if (slope > I.smax[i]) {
-    I.smax[i] = slope;
-    I.at[i] = t;
+  const double un = gmem(I.u_new)[i];
+  const double slope = (un - gmem(I.u_cur)[i]) * I.inv_dt;
+  if (slope > gmem(I.smax)[i]) {
+    gmem(I.smax)[i] = slope;
+    gmem(I.at)[i] = t;
   }
   if (un > I.threshold) {
-    const double tc = I.tcross[i];
-    if (tc != tc) I.tcross[i] = t;
+    const double tc = gmem(I.tcross)[i];
+    if (tc != tc) gmem(I.tcross)[i] = t;
   }
 }
 
