@@ -273,6 +273,33 @@ def corner_cube_stimulus(amp: float = 50.0, edge: float = 1.5, corner=(0.0, 0.0,
 
 
 # ---------------------------------------------------------------------------
+# Element labels (material ids) for several subdomains
+# ---------------------------------------------------------------------------
+
+def element_centroids(mesh: Mesh) -> np.ndarray:
+    """Mean of each element's node coordinates, [n_elems, 3]."""
+    return mesh.xyz[mesh.conn].mean(axis=1)
+
+
+def material_layers(mesh: Mesh, axis: int, cuts) -> np.ndarray:
+    """Label k for elements whose centroid coordinate along `axis` lies
+    between cuts[k-1] and cuts[k] (layers 0 .. len(cuts)), e.g. the
+    endocardial / mid-myocardial / epicardial layers of a slab."""
+    c = element_centroids(mesh)[:, axis]
+    return np.searchsorted(np.asarray(cuts, np.float64), c).astype(np.int32)
+
+
+def material_box(mesh: Mesh, lo, hi, label: int, base=None) -> np.ndarray:
+    """Copy of `base` (zeros when None) with `label` on the elements whose
+    centroid lies inside the axis-aligned box [lo, hi] (e.g. a scar)."""
+    c = element_centroids(mesh)
+    out = np.zeros(mesh.conn.shape[0], np.int32) if base is None else np.array(base, np.int32)
+    inside = np.all((c >= np.asarray(lo)) & (c <= np.asarray(hi)), axis=1)
+    out[inside] = label
+    return out
+
+
+# ---------------------------------------------------------------------------
 # Physical parameter sets of the workloads
 # ---------------------------------------------------------------------------
 
