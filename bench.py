@@ -121,10 +121,12 @@ def _warm(sim, ep, warmup, graph, autotune):
     return launch
 
 
-def run_gpu(spec, precision, steps, warmup, instrument_steps, graph=True, autotune=True, ionic_scheme="rl"):
+def run_gpu(spec, precision, steps, warmup, instrument_steps, graph=True, autotune=True, ionic_scheme="rl",
+            material=None, regions=None):
     import paper_2308_01651_amd as ep
     import torch
-    sim = ep.Simulation.from_spec(spec, precision=precision, ionic_scheme=ionic_scheme)
+    sim = ep.Simulation.from_spec(spec, precision=precision, ionic_scheme=ionic_scheme, material=material,
+                                  regions=regions)
     st0 = sim.get_stats()
     launch = _warm(sim, ep, warmup, graph, autotune)
     torch.cuda.synchronize()
@@ -423,12 +425,20 @@ def main():
               f"dominant {rl['kernel']} {rl['achieved']} GB/s", file=sys.stderr, flush=True)
     if "fp64" in out:
         # the same run with the default launches (eager, untuned) and with graph replay, for comparison
-        for name, g, t, sch in (("fp64_default_launches", False, False, "rl"),
-                                ("fp64_graph_replay", True, bool(args.autotune), "rl"),
-                                ("fp64_paper_bdf_ionic_scheme", bool(args.graph), bool(args.autotune), "bdf")):
-            if g == bool(args.graph) and t == bool(args.autotune) and sch == "rl":
+        import workloads as W
+        # three transmural TTP06 layers (endocardial, mid-myocardial,
+        # epicardial thirds of the slab thickness), one subdomain each
+        zmax = float(spec.mesh.xyz[:, 2].max())
+        layers = W.material_layers(spec.mesh, 2, [zmax / 3, 2 * zmax / 3])
+        layer_regions = {0: dict(variant="endo"), 1: dict(variant="mid"), 2: dict(variant="epi")}
+        for name, g, t, sch, mat, regs in (
+                ("fp64_default_launches", False, False, "rl", None, None),
+                ("fp64_graph_replay", True, bool(args.autotune), "rl", None, None),
+                ("fp64_paper_bdf_ionic_scheme", bool(args.graph), bool(args.autotune), "bdf", None, None),
+                ("fp64_three_cell_layers", bool(args.graph), bool(args.autotune), "rl", layers, layer_regions)):
+            if g == bool(args.graph) and t == bool(args.autotune) and sch == "rl" and mat is None:
                 continue
-            r0, _, _ = run_gpu(spec, ep.EP_FP64, args.steps, args.warmup, 0, g, t, sch)
+            r0, _, _ = run_gpu(spec, ep.EP_FP64, args.steps, args.warmup, 0, g, t, sch, mat, regs)
             out[name] = {k: r0[k] for k in ("node_steps_per_s", "ms_per_step", "step_latency_ms_p50",
                                             "step_latency_ms_p99", "launch")}
             print(f"[bench] {name}: {r0['node_steps_per_s']:.4g} node-steps/s", file=sys.stderr, flush=True)

@@ -132,10 +132,33 @@ ep_status ep_sim_create(int device, void* hip_stream, ep_sim** out);
 /* Mesh (paper: tetrahedral or hexahedral conforming mesh).  xyz: [n_nodes][3]
  * coordinates in mm; conn: [n_elems][elem] node indices, hexahedra in
  * lexicographic corner order (corner a + 2b + 4c at reference (a, b, c)).
- * material_id must be NULL (one subdomain).  EP_EINVAL on bad sizes or
- * out-of-range indices (checked in finalize for element geometry). */
+ * material_id: NULL (one subdomain) or [n_elems] subdomain labels 0 ..
+ * EP_MAX_REGIONS - 1 (paper: Material IDs of the mesh's volumes; see
+ * ep_sim_set_region).  EP_EINVAL on bad sizes or out-of-range indices or
+ * labels (element geometry is checked in finalize). */
 ep_status ep_sim_upload_mesh(ep_sim* sim, int elem, int64_t n_nodes, const double* xyz,
                              int64_t n_elems, const int32_t* conn, const int32_t* material_id);
+
+#define EP_MAX_REGIONS 8
+
+/* Settings of subdomain `region` (paper: the monodomain problem on several
+ * subdomains with one ionic model each, eq. (2); per-subdomain parameter
+ * overrides; "disable conduction" for scar).  Applies to the elements whose
+ * material id is `region`; a region never set takes the sim's settings.
+ *   variant: EP_CELL_* (TTP06 cell type) or -1 for the sim's;
+ *   params / n_params: overrides of the model's first parameters as in
+ *     ep_sim_set_ionic_model (NULL: the sim's parameters);
+ *   sigma_l, sigma_t, sigma_n: conductivities in mS/mm (negative: the sim's);
+ *   conductive: 0 removes the region from the problem (its elements do not
+ *     enter M and K; nodes no other element uses drop out of the solve and
+ *     report NaN; they count in n_nodes but carry no unknown).
+ * The ionic state of a node on the interface of several subdomains is kept
+ * once per subdomain and the ionic load is sum_i M^i I_ion^i exactly.
+ * Several subdomains need the Rush-Larsen ionic scheme and are not admitted
+ * to pools (EP_EINVAL at finalize / admission).  Call before finalize;
+ * EP_EINVAL on a bad region, variant or parameter count. */
+ep_status ep_sim_set_region(ep_sim* sim, int region, int variant, const double* params, int n_params,
+                            double sigma_l, double sigma_t, double sigma_n, int conductive);
 
 /* Fiber, sheet and normal directions per node (paper: the orthonormal triplet
  * f0, s0, n0 of the diffusion tensor), each [n_nodes][3].  Default if never

@@ -28,6 +28,7 @@ EP_OPT_MATRIX_FORMAT, EP_OPT_INNER_RTOL, EP_OPT_MAX_OUTER, EP_OPT_PHASE_TIMERS =
 EP_OPT_KERNEL_TIMERS = 5
 EP_OPT_IONIC_NPT, EP_OPT_TILE_MAP, EP_OPT_GRAPH, EP_OPT_IONIC_SCHEME = 6, 7, 8, 9
 EP_IONIC_RUSH_LARSEN, EP_IONIC_BDF = 0, 1
+EP_MAX_REGIONS = 8
 KERNEL_KINDS = ["ionic", "rhs", "cg_spmv", "cg_update", "activation", "ir_residual", "cg_finalize"]
 
 MODEL_IDS = {"passive": EP_PASSIVE, "ap": EP_AP, "bo": EP_BO, "ttp06": EP_TTP06}
@@ -57,12 +58,26 @@ class Simulation:
         self.bdf = 1
 
     # -- configuration ---------------------------------------------------------
-    def upload_mesh(self, elem: int, xyz, conn):
+    def upload_mesh(self, elem: int, xyz, conn, material=None):
+        """material: optional per-element subdomain labels 0..EP_MAX_REGIONS-1."""
         xyz = _f64(xyz)
         conn = np.ascontiguousarray(conn, dtype=np.int32)
         self.n_nodes = xyz.shape[0]
+        mat = None if material is None else np.ascontiguousarray(material, dtype=np.int32)
         check(lib.ep_sim_upload_mesh(self._h, int(elem), xyz.shape[0], _pd(xyz), conn.shape[0],
-                                     conn.ctypes.data_as(_lib.PI32), None), "ep_sim_upload_mesh")
+                                     conn.ctypes.data_as(_lib.PI32),
+                                     None if mat is None else mat.ctypes.data_as(_lib.PI32)), "ep_sim_upload_mesh")
+
+    def set_region(self, region: int, variant=None, params=None, sigma=None, conductive=True):
+        """ep_sim_set_region: cell type (name or EP_CELL_*; None: the sim's),
+        positional parameter overrides, conductivities (l, t, n) in mS/mm
+        (None: the sim's) and whether the subdomain conducts."""
+        v = -1 if variant is None else (CELL_IDS[variant] if isinstance(variant, str) else int(variant))
+        p = None if params is None or len(params) == 0 else _f64(params)
+        sl, st, sn = (-1.0, -1.0, -1.0) if sigma is None else tuple(float(x) for x in sigma)
+        check(lib.ep_sim_set_region(self._h, int(region), v, _pd(p) if p is not None else None,
+                                    0 if p is None else p.size, sl, st, sn, 1 if conductive else 0),
+              "ep_sim_set_region")
 
     def upload_fibers(self, f0, s0, n0):
         f0, s0, n0 = _f64(f0), _f64(s0), _f64(n0)
@@ -198,14 +213,18 @@ class Simulation:
     # -- convenience -----------------------------------------------------------
     @classmethod
     def from_spec(cls, spec, precision=EP_FP64, device=0, stream=None, rtol=None, max_it=1000,
-                  matrix_format=EP_FMT_AUTO, finalize=True, inner_rtol=None, block=1, ionic_scheme="rl"):
+                  matrix_format=EP_FMT_AUTO, finalize=True, inner_rtol=None, block=1, ionic_scheme="rl",
+                  material=None, regions=None):
         """Configure from a workloads.SimSpec (marshalling of its arrays).
         block > 1 selects block-Jacobi preconditioning with that block size;
         ionic_scheme "rl" (Rush-Larsen) or "bdf" (the paper's semi-implicit
-        BDF)."""
+        BDF).  material: per-element subdomain labels; regions: {label:
+        dict(variant=, params=, sigma=, conductive=)} passed to set_region."""
         sim = cls(device, stream)
         m = spec.mesh
-        sim.upload_mesh(m.elem, m.xyz, m.conn)
+        sim.upload_mesh(m.elem, m.xyz, m.conn, material)
+        for r, cfg in (regions or {}).items():
+            sim.set_region(r, **cfg)
         if spec.fibers is not None:
             sim.upload_fibers(*spec.fibers)
         p = spec.phys

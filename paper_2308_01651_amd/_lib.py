@@ -59,6 +59,7 @@ _SIGS = {
     "ep_sim_upload_fibers": [P, PD, PD, PD],
     "ep_sim_set_conductivity": [P, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double],
     "ep_sim_set_ionic_model": [P, C.c_int, C.c_int, PD, C.c_int, PD],
+    "ep_sim_set_region": [P, C.c_int, C.c_int, PD, C.c_int, C.c_double, C.c_double, C.c_double, C.c_int],
     "ep_sim_add_stimulus": [P, C.c_int, PD, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double],
     "ep_sim_set_solver": [P, C.c_double, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int],
     "ep_sim_set_option": [P, C.c_int, C.c_double],

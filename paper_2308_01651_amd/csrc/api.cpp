@@ -252,6 +252,15 @@ struct ep_sim {
   int bdf = 1, prec = EP_FP64, precond = EP_JACOBI, block = 1, max_it = 1000, max_outer = 30;
   int ionic_scheme = 0;   // EP_IONIC_RUSH_LARSEN or EP_IONIC_BDF
   int fmt_pref = EP_FMT_AUTO;
+  // subdomains: element labels (empty: one subdomain) and per-label settings
+  std::vector<int32_t> material;
+  struct RegionCfg {
+    int variant = -1;                 // -1: the sim's
+    bool has_params = false;
+    std::vector<double> params;
+    double sig[3] = {-1.0, -1.0, -1.0};  // negative: the sim's
+    int conductive = 1;
+  } region_cfg[EP_MAX_REGIONS];
   int timers = 0;
   // products
   bool finalized = false;
@@ -279,6 +288,13 @@ struct ep_sim {
   hipStream_t stream_own = nullptr;
   int pool_slot = -1;
   int it_pred = 8;      // CG iterations launched before the first convergence check
+  // several subdomains (finalized): ionic points and the per-node primary
+  // subdomain (-1: node outside every conducting subdomain)
+  bool het = false;
+  int64_t n_pts = 0;
+  int64_t n_crow = 0;
+  std::vector<int32_t> node_reg;
+  std::vector<int32_t> sec_node;
   SweepPredictor sweeps;  // inner rounds per refinement sweep (mixed)
   int sticky = EP_OK;
 };
@@ -400,14 +416,62 @@ ep_status finalize_impl(ep_sim* s) {
   if (s->n <= 0) return fail(EP_ESTATE, "no mesh uploaded");
   if (s->model < 0) return fail(EP_ESTATE, "no ionic model set");
   EP_HIP(hipSetDevice(s->device));
+  // ---- subdomain settings ----
+  const bool het = !s->material.empty();
+  if (het && s->ionic_scheme == EP_IONIC_BDF)
+    return fail(EP_EINVAL, "several subdomains need the Rush-Larsen ionic scheme");
+  std::vector<double> rsig(3 * EP_MAX_REGIONS);
+  std::vector<unsigned char> ron(EP_MAX_REGIONS);
+  for (int r = 0; r < EP_MAX_REGIONS; r++) {
+    const ep_sim::RegionCfg& c = s->region_cfg[r];
+    const double glob[3] = {s->sl, s->st, s->sn};
+    for (int k = 0; k < 3; k++) rsig[3 * r + k] = c.sig[k] >= 0.0 ? c.sig[k] : glob[k];
+    ron[r] = (unsigned char)c.conductive;
+    if (c.has_params && (int)c.params.size() > n_model_params(s->model))
+      return fail(EP_EINVAL, "region parameters: more than the model has");
+  }
   // ---- assembly ----
   Csr A;
   std::vector<char> err;
-  if (!assemble_csr(s->elem, s->n, s->xyz.data(), s->n_elems, s->conn.data(),
-                    s->f0.empty() ? nullptr : s->f0.data(), s->s0.empty() ? nullptr : s->s0.data(),
-                    s->n0.empty() ? nullptr : s->n0.data(), s->sl, s->st, s->sn, s->chi, s->cm, A, err))
+  const double* fib0 = s->f0.empty() ? nullptr : s->f0.data();
+  const double* fib1 = s->s0.empty() ? nullptr : s->s0.data();
+  const double* fib2 = s->n0.empty() ? nullptr : s->n0.data();
+  if (!assemble_csr(s->elem, s->n, s->xyz.data(), s->n_elems, s->conn.data(), fib0, fib1, fib2, s->sl, s->st,
+                    s->sn, s->chi, s->cm, A, err, het ? s->material.data() : nullptr, rsig.data(), ron.data()))
     return fail(EP_EINVAL, std::string("assembly: ") + (err.empty() ? "failed" : err.data()));
   const int64_t n = s->n;
+  // subdomains of each node: the lowest conducting one is the node's primary
+  // subdomain (its state lives at point i = node), every further one adds an
+  // ionic point; nodes of no conducting subdomain carry no unknown
+  std::vector<int32_t> sec_reg;
+  s->het = het;
+  s->node_reg.assign(het ? n : 0, 0);
+  s->sec_node.clear();
+  if (het) {
+    const int npe = s->elem;
+    std::vector<uint8_t> mask(n, 0);
+    for (int64_t e = 0; e < s->n_elems; e++) {
+      const int r = s->material[e];
+      if (!ron[r]) continue;
+      for (int k = 0; k < npe; k++) mask[s->conn[e * npe + k]] |= (uint8_t)(1u << r);
+    }
+    for (int64_t i = 0; i < n; i++) {
+      if (!mask[i]) {
+        s->node_reg[i] = -1;
+        continue;
+      }
+      const int prim = __builtin_ctz(mask[i]);
+      s->node_reg[i] = prim;
+      for (int r = prim + 1; r < EP_MAX_REGIONS; r++)
+        if (mask[i] & (1u << r)) {
+          s->sec_node.push_back((int32_t)i);
+          sec_reg.push_back(r);
+        }
+    }
+    if (s->node_reg.end() == std::find_if(s->node_reg.begin(), s->node_reg.end(), [](int32_t r) { return r >= 0; }))
+      return fail(EP_EINVAL, "no conducting subdomain");
+  }
+  s->n_pts = n + (int64_t)s->sec_node.size();
   const int64_t nnz = A.nnz();
   s->nnz = nnz;
   const bool mixed = s->prec == EP_MIXED;
@@ -478,6 +542,11 @@ ep_status finalize_impl(ep_sim* s) {
   for (int q = 0; q < nsig; q++) {
     const double c = alphas[q] / s->dt;
     for (int64_t t = 0; t < nnz; t++) valA[q][t] = c * A.valM[t] + A.valK[t];
+    // a node outside every conducting subdomain: identity row (its row and
+    // column of M and K are zero), so it drops out of the solve
+    if (het)
+      for (int64_t i = 0; i < n; i++)
+        if (s->node_reg[i] < 0) valA[q][dpos[i]] = 1.0;
   }
   auto to_dev_d = [&](const std::vector<double>& h, const double** d) -> hipError_t {
     double* p;
@@ -646,14 +715,112 @@ ep_status finalize_impl(ep_sim* s) {
   const int n_levels = s->ionic_scheme == EP_IONIC_BDF ? RING : 1;
   const int n32 = mixed ? ((s->model == EP_TTP06) ? 16 : nvars) : 0;
   const int n64 = mixed ? ((s->model == EP_TTP06) ? 2 : 0) : nvars;
+  // stride n_pts: the nodes' states, then the extra interface points'
+  const int64_t npts = s->n_pts;
   for (int k = 0; k < RING; k++) {
     if (k < n_levels) {
-      EP_HIP(m.alloc((void**)&D.st32[k], std::max<int64_t>(1, (int64_t)n32 * n) * sizeof(float)));
-      EP_HIP(m.alloc((void**)&D.st64[k], std::max<int64_t>(1, (int64_t)n64 * n) * sizeof(double)));
+      EP_HIP(m.alloc((void**)&D.st32[k], std::max<int64_t>(1, (int64_t)n32 * npts) * sizeof(float)));
+      EP_HIP(m.alloc((void**)&D.st64[k], std::max<int64_t>(1, (int64_t)n64 * npts) * sizeof(double)));
     } else {
       D.st32[k] = D.st32[0];
       D.st64[k] = D.st64[0];
     }
+  }
+  // ---- several subdomains: points, parameter rows, interface correction ----
+  D.het = het ? 1 : 0;
+  D.n_pts = npts;
+  if (het) {
+    const int64_t nsec = npts - n;
+    std::vector<int32_t> pt_reg(s->node_reg);
+    pt_reg.insert(pt_reg.end(), sec_reg.begin(), sec_reg.end());
+    int32_t* d_reg;
+    EP_HIP(upload(m, &d_reg, pt_reg.data(), pt_reg.size(), st));
+    D.pt_reg = d_reg;
+    std::vector<int32_t> secn(s->sec_node);
+    if (secn.empty()) secn.push_back(0);
+    int32_t* d_sec;
+    EP_HIP(upload(m, &d_sec, secn.data(), secn.size(), st));
+    D.sec_node = d_sec;
+    // parameter row of each subdomain: its cell type's defaults, the sim's
+    // overrides, then the subdomain's own
+    std::vector<double> rtab((size_t)MAX_REGIONS * NPARAM, 0.0);
+    for (int r = 0; r < MAX_REGIONS; r++) {
+      const ep_sim::RegionCfg& c = s->region_cfg[r];
+      double* row = &rtab[(size_t)r * NPARAM];
+      default_params(s->model, c.variant >= 0 ? c.variant : s->variant, row);
+      for (size_t k = 0; k < s->params.size(); k++) row[k] = s->params[k];
+      if (c.has_params)
+        for (size_t k = 0; k < c.params.size(); k++) row[k] = c.params[k];
+    }
+    double* d_rtab;
+    EP_HIP(upload(m, &d_rtab, rtab.data(), rtab.size(), st));
+    D.rtab = d_rtab;
+    EP_HIP(m.alloc((void**)&D.ipt, (size_t)npts * sizeof(double)));
+    EP_HIP(hipMemsetAsync(D.ipt, 0, (size_t)npts * sizeof(double), st));
+    EP_HIP(m.alloc((void**)&D.cvec, (size_t)n * sizeof(double)));
+    EP_HIP(hipMemsetAsync(D.cvec, 0, (size_t)n * sizeof(double), st));
+    // C(j, q) = M^r(j, node_q) for the extra point q = (node_q, r), from the
+    // mass matrix of subdomain r alone
+    struct Ent {
+      int32_t row, q;
+      double v;
+    };
+    std::vector<Ent> ents;
+    const int npe = s->elem;
+    for (int r = 0; r < MAX_REGIONS; r++) {
+      std::vector<int64_t> qs;
+      for (int64_t q = 0; q < nsec; q++)
+        if (sec_reg[q] == r) qs.push_back(q);
+      if (qs.empty()) continue;
+      std::vector<int32_t> conn_r;
+      for (int64_t e = 0; e < s->n_elems; e++)
+        if (s->material[e] == r) conn_r.insert(conn_r.end(), &s->conn[e * npe], &s->conn[e * npe] + npe);
+      Csr Mr;
+      std::vector<char> err_r;
+      if (!assemble_csr(s->elem, n, s->xyz.data(), (int64_t)conn_r.size() / npe, conn_r.data(), fib0, fib1, fib2,
+                        rsig[3 * r], rsig[3 * r + 1], rsig[3 * r + 2], s->chi, s->cm, Mr, err_r))
+        return fail(EP_EINVAL, std::string("subdomain assembly: ") + (err_r.empty() ? "failed" : err_r.data()));
+      for (int64_t q : qs) {
+        const int32_t k = s->sec_node[q];
+        for (int64_t t = Mr.rowptr[k]; t < Mr.rowptr[k + 1]; t++) {
+          const int32_t j = Mr.col[t];
+          const int32_t* cj = &Mr.col[Mr.rowptr[j]];
+          const int64_t lj = Mr.rowptr[j + 1] - Mr.rowptr[j];
+          const int64_t pos = Mr.rowptr[j] + (std::lower_bound(cj, cj + lj, k) - cj);
+          ents.push_back({j, (int32_t)q, Mr.valM[pos]});
+        }
+      }
+    }
+    std::sort(ents.begin(), ents.end(), [](const Ent& a, const Ent& b) { return a.row < b.row || (a.row == b.row && a.q < b.q); });
+    std::vector<int32_t> crow, ccol;
+    std::vector<int64_t> cptr(1, 0);
+    std::vector<double> cval;
+    for (size_t t = 0; t < ents.size(); t++) {
+      if (t == 0 || ents[t].row != ents[t - 1].row) {
+        if (t > 0) cptr.push_back((int64_t)t);
+        crow.push_back(ents[t].row);
+      }
+      ccol.push_back(ents[t].q);
+      cval.push_back(ents[t].v);
+    }
+    cptr.push_back((int64_t)ents.size());
+    if (crow.empty()) cptr.assign(1, 0);
+    s->n_crow = (int64_t)crow.size();
+    D.n_crow = (int32_t)crow.size();
+    if (!crow.empty()) {
+      int32_t *d_crow, *d_ccol;
+      int64_t* d_cptr;
+      double* d_cval;
+      EP_HIP(upload(m, &d_crow, crow.data(), crow.size(), st));
+      EP_HIP(upload(m, &d_cptr, cptr.data(), cptr.size(), st));
+      EP_HIP(upload(m, &d_ccol, ccol.data(), ccol.size(), st));
+      EP_HIP(upload(m, &d_cval, cval.data(), cval.size(), st));
+      D.crow = d_crow;
+      D.cptr = d_cptr;
+      D.ccol = d_ccol;
+      D.cval = d_cval;
+    }
+    EP_HIP(hipStreamSynchronize(st));  // host vectors above are temporaries
   }
   EP_HIP(m.alloc((void**)&D.smax, n * sizeof(double)));
   EP_HIP(m.alloc((void**)&D.at, n * sizeof(double)));
@@ -734,6 +901,12 @@ ep_status validate_desc(const InstDesc& D, int64_t guard) {
     if (!D.U[k]) return bad("history ring");
   if (!D.u_new || !D.u_cur || !D.u_prev1 || !D.u_prev2) return bad("history slots");
   if (!D.valM || !D.smax || !D.at || !D.tcross) return bad("arrays");
+  if (D.het) {
+    if (D.n_pts < D.n || !D.pt_reg || !D.sec_node || !D.rtab || !D.ipt || !D.cvec) return bad("subdomain arrays");
+    if (D.n_crow > 0 && (!D.crow || !D.cptr || !D.ccol || !D.cval)) return bad("interface correction");
+  } else if (D.n_pts != D.n) {
+    return bad("ionic points");
+  }
   for (int q = 0; q < D.bdf; q++) {
     if (!D.valA[q] || !D.dinv[q]) return bad("operator values");
     if (D.prec == P_MIXED && (!D.valA32[q] || !D.dinv32[q])) return bad("FP32 operator values");
@@ -788,7 +961,14 @@ ep_status step_once(ep_sim* s) {
   };
   auto pro = [&] {
     if (s->timers) (void)hipEventRecord(s->ev[0], st);
-    kt.timed(st, 0, [&] { launch_ionic(s->model, mixed, L); });
+    kt.timed(st, 0, [&] {
+      if (s->het) {
+        launch_ionic_het(s->model, mixed, s->d_desc, s->n_pts, st);
+        launch_ici_correction(s->d_desc, s->n_crow, st);
+      } else {
+        launch_ionic(s->model, mixed, L);
+      }
+    });
     if (s->timers) (void)hipEventRecord(s->ev[1], st);
     kt.timed(st, 1, [&] { launch_residual(mixed, true, L); });
     if (s->timers) (void)hipEventRecord(s->ev[2], st);
@@ -950,8 +1130,11 @@ ep_status ep_sim_upload_mesh(ep_sim* s, int elem, int64_t n_nodes, const double*
   if (s->finalized) return fail(EP_ESTATE, "sim already finalized");
   if (elem != EP_HEX8 && elem != EP_TET4) return fail(EP_EINVAL, "elem must be EP_HEX8 or EP_TET4");
   if (n_nodes <= 0 || n_elems <= 0 || !xyz || !conn) return fail(EP_EINVAL, "empty mesh");
-  if (material_id) return fail(EP_EINVAL, "material ids (several subdomains) are not supported");
   if (n_nodes >= (int64_t)INT32_MAX) return fail(EP_EINVAL, "too many nodes");
+  if (material_id)
+    for (int64_t e = 0; e < n_elems; e++)
+      if (material_id[e] < 0 || material_id[e] >= EP_MAX_REGIONS)
+        return fail(EP_EINVAL, "material id outside 0 .. EP_MAX_REGIONS - 1");
   for (int64_t k = 0; k < n_elems * elem; k++)
     if (conn[k] < 0 || conn[k] >= n_nodes) return fail(EP_EINVAL, "connectivity index out of range");
   s->elem = elem;
@@ -959,9 +1142,29 @@ ep_status ep_sim_upload_mesh(ep_sim* s, int elem, int64_t n_nodes, const double*
   s->n_elems = n_elems;
   s->xyz.assign(xyz, xyz + 3 * n_nodes);
   s->conn.assign(conn, conn + elem * n_elems);
+  if (material_id) s->material.assign(material_id, material_id + n_elems);
+  else s->material.clear();
   s->f0.clear();
   s->s0.clear();
   s->n0.clear();
+  return EP_OK;
+}
+
+ep_status ep_sim_set_region(ep_sim* s, int region, int variant, const double* params, int n_params,
+                            double sigma_l, double sigma_t, double sigma_n, int conductive) {
+  if (check_sim(s)) return EP_EINVAL;
+  if (s->finalized) return fail(EP_ESTATE, "sim already finalized");
+  if (region < 0 || region >= EP_MAX_REGIONS) return fail(EP_EINVAL, "region outside 0 .. EP_MAX_REGIONS - 1");
+  if (variant < -1 || variant > EP_CELL_MID) return fail(EP_EINVAL, "bad cell type");
+  if (n_params < 0 || n_params > NPARAM || (n_params > 0 && !params)) return fail(EP_EINVAL, "bad parameter count");
+  ep_sim::RegionCfg& r = s->region_cfg[region];
+  r.variant = variant;
+  r.has_params = params != nullptr && n_params > 0;
+  r.params.assign(params ? params : nullptr, params ? params + n_params : nullptr);
+  r.sig[0] = sigma_l;
+  r.sig[1] = sigma_t;
+  r.sig[2] = sigma_n;
+  r.conductive = conductive != 0;
   return EP_OK;
 }
 
@@ -1159,24 +1362,35 @@ ep_status ep_sim_set_state(ep_sim* s, const double* u, const double* w, const do
     EP_HIP(hipMemcpyAsync(D.U[(step_index - k) & 3], src, n * sizeof(double), hipMemcpyHostToDevice, st));
   }
   const int nv = s->nvars;
+  // state arrays have one column per ionic point (stride np); an extra
+  // interface point starts from its node's state
+  const int64_t np = s->n_pts;
+  std::vector<double> wexp;
+  if (nv > 0 && np != n) {
+    wexp.resize((size_t)nv * np);
+    for (int v = 0; v < nv; v++)
+      for (int64_t p = 0; p < np; p++)
+        wexp[(size_t)v * np + p] = w[(size_t)v * n + (p < n ? p : s->sec_node[p - n])];
+    w = wexp.data();
+  }
   if (nv > 0) {
     if (s->prec == EP_MIXED) {
       std::vector<float> s32;
       std::vector<double> s64;
       if (s->model == EP_TTP06) {
-        s32.resize((size_t)16 * n);
-        s64.resize((size_t)2 * n);
+        s32.resize((size_t)16 * np);
+        s64.resize((size_t)2 * np);
         for (int v = 0; v < 18; v++) {
-          for (int64_t i = 0; i < n; i++) {
-            const double x = w[(size_t)v * n + i];
-            if (v < 15) s32[(size_t)v * n + i] = (float)x;
+          for (int64_t i = 0; i < np; i++) {
+            const double x = w[(size_t)v * np + i];
+            if (v < 15) s32[(size_t)v * np + i] = (float)x;
             else if (v == 15) s64[i] = x;
-            else if (v == 16) s64[n + i] = x;
-            else s32[(size_t)15 * n + i] = (float)x;
+            else if (v == 16) s64[np + i] = x;
+            else s32[(size_t)15 * np + i] = (float)x;
           }
         }
       } else {
-        s32.assign(w, w + (size_t)nv * n);
+        s32.assign(w, w + (size_t)nv * np);
       }
       // level n and, for the BDF ionic scheme, levels n-1 and n-2 (copies)
       for (int k = 0; k < 3; k++) {
@@ -1190,8 +1404,9 @@ ep_status ep_sim_set_state(ep_sim* s, const double* u, const double* w, const do
       for (int k = 0; k < 3; k++) {
         const int slot = (int)((step_index - k) & 3);
         if (k > 0 && D.st64[slot] == D.st64[step_index & 3]) break;
-        EP_HIP(hipMemcpyAsync(D.st64[slot], w, (size_t)nv * n * 8, hipMemcpyHostToDevice, st));
+        EP_HIP(hipMemcpyAsync(D.st64[slot], w, (size_t)nv * np * 8, hipMemcpyHostToDevice, st));
       }
+      EP_HIP(hipStreamSynchronize(st));   // w may point into a temporary
     }
   }
   launch_fill(D.smax, n, -std::numeric_limits<double>::infinity(), st);
@@ -1230,10 +1445,12 @@ ep_status ep_sim_get_state(ep_sim* s, double* u, double* w, double* u_prev) {
       EP_HIP(hipMemcpyAsync(u_prev + (size_t)(k - 1) * n, D.U[(step - k) & 3], n * 8, hipMemcpyDeviceToHost, st));
   const int nv = s->nvars;
   if (w && nv > 0) {
+    // the nodes' columns of the state (stride n_pts; extra points dropped)
+    const int64_t np = s->n_pts;
     if (s->prec == EP_MIXED) {
       const int n32 = (s->model == EP_TTP06) ? 16 : nv;
-      std::vector<float> s32((size_t)n32 * n);
-      std::vector<double> s64(s->model == EP_TTP06 ? (size_t)2 * n : 0);
+      std::vector<float> s32((size_t)n32 * np);
+      std::vector<double> s64(s->model == EP_TTP06 ? (size_t)2 * np : 0);
       EP_HIP(hipMemcpyAsync(s32.data(), D.st32[step & 3], s32.size() * 4, hipMemcpyDeviceToHost, st));
       if (!s64.empty())
         EP_HIP(hipMemcpyAsync(s64.data(), D.st64[step & 3], s64.size() * 8, hipMemcpyDeviceToHost, st));
@@ -1242,20 +1459,35 @@ ep_status ep_sim_get_state(ep_sim* s, double* u, double* w, double* u_prev) {
         for (int v = 0; v < 18; v++)
           for (int64_t i = 0; i < n; i++) {
             double x;
-            if (v < 15) x = s32[(size_t)v * n + i];
+            if (v < 15) x = s32[(size_t)v * np + i];
             else if (v == 15) x = s64[i];
-            else if (v == 16) x = s64[n + i];
-            else x = s32[(size_t)15 * n + i];
+            else if (v == 16) x = s64[np + i];
+            else x = s32[(size_t)15 * np + i];
             w[(size_t)v * n + i] = x;
           }
       } else {
-        for (size_t k = 0; k < s32.size(); k++) w[k] = s32[k];
+        for (int v = 0; v < nv; v++)
+          for (int64_t i = 0; i < n; i++) w[(size_t)v * n + i] = s32[(size_t)v * np + i];
       }
-    } else {
+    } else if (np == n) {
       EP_HIP(hipMemcpyAsync(w, D.st64[step & 3], (size_t)nv * n * 8, hipMemcpyDeviceToHost, st));
+    } else {
+      EP_HIP(hipMemcpy2DAsync(w, (size_t)n * 8, D.st64[step & 3], (size_t)np * 8, (size_t)n * 8, (size_t)nv,
+                              hipMemcpyDeviceToHost, st));
     }
   }
   EP_HIP(hipStreamSynchronize(st));
+  if (s->het) {
+    const double nan = std::numeric_limits<double>::quiet_NaN();
+    for (int64_t i = 0; i < n; i++)
+      if (s->node_reg[i] < 0) {
+        if (u) u[i] = nan;
+        if (u_prev)
+          for (int k = 1; k < s->bdf; k++) u_prev[(size_t)(k - 1) * n + i] = nan;
+        if (w)
+          for (int v = 0; v < nv; v++) w[(size_t)v * n + i] = nan;
+      }
+  }
   return EP_OK;
 }
 
@@ -1278,7 +1510,8 @@ ep_status ep_sim_get_potential_device(ep_sim* s, void* dst, int dtype) {
   ep_status rc = pull_state(s);
   if (rc) return rc;
   const double* src = s->desc.U[s->h_st->step & 3];
-  launch_to_mv(dst, src, s->n, s->mi.mv_per_unit, s->mi.mv_offset, dtype == EP_DTYPE_F32, s->stream);
+  launch_to_mv(dst, src, s->n, s->mi.mv_per_unit, s->mi.mv_offset, dtype == EP_DTYPE_F32, s->stream,
+               s->het ? s->desc.pt_reg : nullptr);
   EP_HIP(hipGetLastError());
   EP_HIP(hipStreamSynchronize(s->stream));
   return EP_OK;
@@ -1296,6 +1529,7 @@ static ep_status get_times(ep_sim* s, double* out, bool maxslope) {
   for (int64_t i = 0; i < n; i++) {
     if (!maxslope) out[i] = tc[i];
     else if (std::isnan(tc[i])) out[i] = std::numeric_limits<double>::quiet_NaN();
+    if (s->het && s->node_reg[i] < 0) out[i] = std::numeric_limits<double>::quiet_NaN();
   }
   return EP_OK;
 }
@@ -1785,6 +2019,7 @@ ep_status ep_pool_admit(ep_pool* P, ep_sim* s, int64_t n_steps_total, int* slot)
   if (s->finalized || s->in_pool) return fail(EP_ESTATE, "admit a configured, not yet finalized sim");
   if (s->prec != P->prec) return fail(EP_EINVAL, "sim precision differs from the pool's");
   if (s->device != P->device) return fail(EP_EINVAL, "sim device differs from the pool's");
+  if (!s->material.empty()) return fail(EP_EINVAL, "sims with several subdomains are not admitted to pools");
   int free_slot = -1;
   for (int k = 0; k < P->max_slots; k++)
     if (!P->slots[k].sim) {

@@ -133,7 +133,8 @@ bool tet_element(const double X[4][3], const double Dn[4][9], double Me[16], dou
 bool assemble_csr(int elem, int64_t n_nodes, const double* xyz, int64_t n_elems,
                   const int32_t* conn, const double* f0, const double* s0, const double* n0,
                   double sigma_l, double sigma_t, double sigma_n, double chi, double cm, Csr& A,
-                  std::vector<char>& err) {
+                  std::vector<char>& err, const int32_t* region, const double* region_sigma,
+                  const unsigned char* region_on) {
   if (elem != 8 && elem != 4) { set_err(err, "element type must be 8 (hex) or 4 (tet)"); return false; }
   if (n_nodes <= 0 || n_elems <= 0) { set_err(err, "empty mesh"); return false; }
   if (n_nodes >= (int64_t)INT32_MAX) { set_err(err, "too many nodes for int32 indices"); return false; }
@@ -160,17 +161,23 @@ bool assemble_csr(int elem, int64_t n_nodes, const double* xyz, int64_t n_elems,
   static const double ex[3] = {1, 0, 0}, ey[3] = {0, 1, 0}, ez[3] = {0, 0, 1};
   parallel_for(n_elems, [&](int64_t e) {
     double X[8][3], Dn[8][9];
+    const int r = region ? region[e] : 0;
+    const double sl = region ? region_sigma[3 * r] : sigma_l;
+    const double st = region ? region_sigma[3 * r + 1] : sigma_t;
+    const double sn = region ? region_sigma[3 * r + 2] : sigma_n;
     for (int k = 0; k < npe; k++) {
       const int64_t v = conn[e * npe + k];
       for (int c = 0; c < 3; c++) X[k][c] = xyz[3 * v + c];
       const double* f = f0 ? f0 + 3 * v : ex;
       const double* s = s0 ? s0 + 3 * v : ey;
       const double* nn = n0 ? n0 + 3 * v : ez;
-      nodal_tensor(f, s, nn, sigma_l, sigma_t, sigma_n, scale, Dn[k]);
+      nodal_tensor(f, s, nn, sl, st, sn, scale, Dn[k]);
     }
     bool ok = (npe == 8) ? hex_element(X, Dn, &Me[e * 64], &Ke[e * 64])
                          : tet_element(X, Dn, &Me[e * 16], &Ke[e * 16]);
     if (!ok) bad[0] = 1;
+    if (region && region_on && !region_on[r])
+      for (int k = 0; k < npe * npe; k++) Me[e * npe * npe + k] = Ke[e * npe * npe + k] = 0.0;
   });
   if (bad[0]) { set_err(err, "degenerate or inverted element"); return false; }
 

@@ -20,11 +20,15 @@ struct Csr {
 // nodes and interpolated with the FE basis.  elem = 8 (trilinear hexahedra,
 // 2x2x2 Gauss points) or 4 (linear tetrahedra, closed form).
 // fibers may be null (then f = e_x, s = e_y, n = e_z everywhere).
+// Several subdomains: region (per element, nullable) selects the element's
+// conductivities region_sigma[3 r .. 3 r + 2]; an element of a region with
+// region_on[r] == 0 keeps its place in the sparsity pattern with zero values.
 // Returns false and fills `err` on invalid input (bad index, inverted element).
 bool assemble_csr(int elem, int64_t n_nodes, const double* xyz, int64_t n_elems,
                   const int32_t* conn, const double* f0, const double* s0, const double* n0,
                   double sigma_l, double sigma_t, double sigma_n, double chi, double cm,
-                  Csr& out, std::vector<char>& err);
+                  Csr& out, std::vector<char>& err, const int32_t* region = nullptr,
+                  const double* region_sigma = nullptr, const unsigned char* region_on = nullptr);
 
 // Distinct column offsets j - i over the pattern, ascending.
 std::vector<int64_t> distinct_offsets(const Csr& A);

@@ -25,6 +25,7 @@ constexpr int MAX_UP = (MAX_DIAG + 1) / 2;  // stored (upper) diagonals of a sym
 constexpr int N_XCD = 8;       // accelerator complex dies; workgroups go round-robin
 constexpr int MAX_STIM = 8;    // stimulus groups per instance
 constexpr int NPARAM = 32;     // model parameter slots
+constexpr int MAX_REGIONS = 8; // subdomains of one simulation
 constexpr int RING = 4;        // potential history ring (u_{n+1}, u_n, u_{n-1}, u_{n-2})
 
 enum Fmt : int32_t { FMT_SELL = 1, FMT_DIA = 2 };
@@ -115,6 +116,23 @@ struct InstDesc {
   double *smax, *at, *tcross;
   StimGroup stim[MAX_STIM];
   double* partial;         // per-workgroup partial sums, PART_DOUBLES * nblk
+  // several subdomains (het != 0).  Ionic points: point i < n is node i with
+  // its primary subdomain; points n .. n_pts-1 are the extra (node,
+  // subdomain) pairs of interface nodes.  The ionic state arrays have stride
+  // n_pts.  The load is M g minus the interface correction cvec = C Delta,
+  // C(j, q) = M^r(j, node_q) for q = (node_q, r), Delta_q = I_q - I_node_q.
+  int32_t het;
+  int32_t n_crow;          // rows with an interface correction
+  int64_t n_pts;           // ionic points (n when het == 0)
+  const int32_t* pt_reg;   // [n_pts] subdomain of each point; -1: node outside every conducting one
+  const int32_t* sec_node; // [n_pts - n] node of each extra point
+  const double* rtab;      // [MAX_REGIONS][NPARAM] ionic parameters per subdomain
+  double* ipt;             // [n_pts] I_ion of each point
+  double* cvec;            // [n] interface correction, zero off its rows
+  const int32_t* crow;     // [n_crow] row of each correction row
+  const int64_t* cptr;     // [n_crow + 1] entries of each correction row
+  const int32_t* ccol;     // extra point (counted from 0) of each entry
+  const double* cval;      // C value of each entry
 };
 
 // Partial-sum layout inside InstDesc::partial, in units of nblk doubles:

@@ -34,7 +34,13 @@ void launch_activation(const Launch& L);
 // ids: device array of instance indices to advance by one step
 void launch_end_step(InstDesc* insts, const int32_t* ids, int n_ids, hipStream_t stream);
 void launch_fill(double* x, int64_t n, double v, hipStream_t stream);
-void launch_to_mv(void* dst, const double* u, int64_t n, double a, double b, bool f32, hipStream_t stream);
+// reg: per-node subdomain (NaN where < 0) or nullptr
+void launch_to_mv(void* dst, const double* u, int64_t n, double a, double b, bool f32, hipStream_t stream,
+                  const int32_t* reg = nullptr);
+// several subdomains: the ionic step over all n_pts ionic points, then the
+// interface correction of the load over its n_crow rows
+void launch_ionic_het(int model, bool mixed, InstDesc* insts, int64_t n_pts, hipStream_t st);
+void launch_ici_correction(InstDesc* insts, int64_t n_crow, hipStream_t st);
 // single-cell pacing (cell.hip): n_steps steps of nc cells from step index
 // step0; uh [3][nc] potential history (u_n, u_{n-1}, u_{n-2}), w [n_vars][nc],
 // params [nc][NPARAM]; stimulus amp (model units per ms) on steps whose

@@ -266,20 +266,25 @@ __device__ __forceinline__ void combine(const BdfW& W, int sig, const T* const* 
   xe = e;
 }
 
-template <int MODEL, bool MIXED, bool BDFS>
-__device__ __forceinline__ void ionic_node(const InstDesc& I, int64_t n, int64_t step, int64_t i) {
+// Ionic step of one ionic point: state index i (arrays [var][n], stride n),
+// potential of node `node`, parameters mp.  With RHS the point also writes its
+// node's load g = u_BDF/dt + I_app - I_ion and initial guess u_EXT; with
+// KEEP_I it stores I_ion(point) for the interface correction.
+template <int MODEL, bool MIXED, bool BDFS, bool RHS = true, bool KEEP_I = false>
+__device__ __forceinline__ void ionic_point(const InstDesc& I, int64_t n, int64_t step, int64_t i, int64_t node,
+                                            const double* __restrict__ mp) {
   const int sig = min(I.bdf, (int)step + 1);
-  const double u0 = gmem(I.u_cur)[i];
+  const double u0 = gmem(I.u_cur)[node];
   double u_ext, u_bdf;
   if (sig == 1) {
     u_ext = u0;
     u_bdf = u0;
   } else if (sig == 2) {
-    const double u1 = gmem(I.u_prev1)[i];
+    const double u1 = gmem(I.u_prev1)[node];
     u_ext = 2.0 * u0 - u1;
     u_bdf = 2.0 * u0 - 0.5 * u1;
   } else {
-    const double u1 = gmem(I.u_prev1)[i], u2 = gmem(I.u_prev2)[i];
+    const double u1 = gmem(I.u_prev1)[node], u2 = gmem(I.u_prev2)[node];
     u_ext = 3.0 * u0 - 3.0 * u1 + u2;
     u_bdf = 3.0 * u0 - 1.5 * u1 + u2 * (1.0 / 3.0);
   }
@@ -297,15 +302,15 @@ __device__ __forceinline__ void ionic_node(const InstDesc& I, int64_t n, int64_t
       float vb, ve;
       combine<float>(W, lev, l32, i, vb, ve);
       float v = vb;
-      iion = BDFS ? (double)ap_step_bdf<float>((float)u_ext, (float)I.dt, (float)W.alpha, I.mp, vb, ve, v)
-                  : (double)ap_step<float>((float)u_ext, (float)I.dt, I.mp, v);
+      iion = BDFS ? (double)ap_step_bdf<float>((float)u_ext, (float)I.dt, (float)W.alpha, mp, vb, ve, v)
+                  : (double)ap_step<float>((float)u_ext, (float)I.dt, mp, v);
       s32[i] = v;
     } else {
       double vb, ve;
       combine<double>(W, lev, l64, i, vb, ve);
       double v = vb;
-      iion = BDFS ? ap_step_bdf<double>(u_ext, I.dt, W.alpha, I.mp, vb, ve, v)
-                  : ap_step<double>(u_ext, I.dt, I.mp, v);
+      iion = BDFS ? ap_step_bdf<double>(u_ext, I.dt, W.alpha, mp, vb, ve, v)
+                  : ap_step<double>(u_ext, I.dt, mp, v);
       s64[i] = v;
     }
   } else if (MODEL == M_BO) {
@@ -313,13 +318,13 @@ __device__ __forceinline__ void ionic_node(const InstDesc& I, int64_t n, int64_t
       float yb[3], ye[3];
       for (int k = 0; k < 3; k++) combine<float>(W, lev, l32, (int64_t)k * n + i, yb[k], ye[k]);
       float v = yb[0], w = yb[1], s = yb[2];
-      iion = (double)bo_step<float, BDFS>((float)u_ext, (float)I.dt, I.mp, v, w, s, (float)W.alpha, yb);
+      iion = (double)bo_step<float, BDFS>((float)u_ext, (float)I.dt, mp, v, w, s, (float)W.alpha, yb);
       s32[i] = v; s32[n + i] = w; s32[2 * n + i] = s;
     } else {
       double yb[3], ye[3];
       for (int k = 0; k < 3; k++) combine<double>(W, lev, l64, (int64_t)k * n + i, yb[k], ye[k]);
       double v = yb[0], w = yb[1], s = yb[2];
-      iion = bo_step<double, BDFS>(u_ext, I.dt, I.mp, v, w, s, W.alpha, yb);
+      iion = bo_step<double, BDFS>(u_ext, I.dt, mp, v, w, s, W.alpha, yb);
       s64[i] = v; s64[n + i] = w; s64[2 * n + i] = s;
     }
   } else if (MODEL == M_TTP06) {
@@ -347,7 +352,7 @@ __device__ __forceinline__ void ionic_node(const InstDesc& I, int64_t n, int64_t
       }
     }
     S = Sb;   // Rush-Larsen (one level): Sb holds w_n
-    iion = (double)ttp06_step<R, BDFS>((R)u_ext, (R)I.dt, I.mp, S, (R)W.alpha, &Sb, &Se, tb);
+    iion = (double)ttp06_step<R, BDFS>((R)u_ext, (R)I.dt, mp, S, (R)W.alpha, &Sb, &Se, tb);
     const gptr<R> sr = gmem(reinterpret_cast<R*>(MIXED ? (void*)I.st32[(step + 1) & 3] : (void*)I.st64[(step + 1) & 3]));
 #pragma unroll
     for (int k = 0; k < 12; k++) sr[row(k)] = S.g[k];
@@ -356,9 +361,12 @@ __device__ __forceinline__ void ionic_node(const InstDesc& I, int64_t n, int64_t
     s64[MIXED ? i : row(15)] = S.nai;
     s64[MIXED ? row(1) : row(16)] = S.ki;
   }
-  const double iapp = stimulus_at(I, step + 1, i);
-  gmem(I.g)[i] = u_bdf * I.inv_dt + iapp - iion;
-  gmem(I.u_new)[i] = u_ext;
+  if (KEEP_I) gmem(I.ipt)[i] = iion;
+  if (RHS) {
+    const double iapp = stimulus_at(I, step + 1, node);
+    gmem(I.g)[node] = u_bdf * I.inv_dt + iapp - iion;
+    gmem(I.u_new)[node] = u_ext;
+  }
 }
 
 // One tile of TILE nodes per workgroup of TILE / NPT threads, NPT nodes per
@@ -375,8 +383,55 @@ __global__ __launch_bounds__(TILE / NPT) __attribute__((amdgpu_waves_per_eu(NPT 
   const int64_t step = I.st.step;
   for (int p = 0; p < NPT; p++) {
     const int64_t i = (int64_t)lblk * TILE + p * (TILE / NPT) + threadIdx.x;
-    if (i < I.n) ionic_node<MODEL, MIXED, BDFS>(I, I.n, step, i);
+    if (i < I.n) ionic_point<MODEL, MIXED, BDFS>(I, I.n, step, i, i, I.mp);
   }
+}
+
+// ---------------------------------------------------------------------------
+// several subdomains (paper: monodomain on subdomains Omega_i, one ionic model
+// each; the ionic load sum_i M^i I_ion^i)
+// ---------------------------------------------------------------------------
+
+// One thread per ionic point.  Points i < n are the nodes, each with its
+// primary subdomain's parameters; they write the node's load and initial
+// guess.  Points i >= n are the interface nodes' extra subdomains; they only
+// keep I_ion.  A node outside every conducting subdomain (pt_reg < 0) is no
+// unknown: load and guess 0, no ionic work.
+template <int MODEL, bool MIXED>
+__global__ __launch_bounds__(WG) void k_ionic_het(InstDesc* __restrict__ insts) {
+  const InstDesc& I = insts[0];
+  const int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
+  if (i >= I.n_pts) return;
+  const int64_t step = I.st.step;
+  const int r = gmem(I.pt_reg)[i];
+  if (i < I.n) {
+    if (r < 0) {
+      gmem(I.g)[i] = 0.0;
+      gmem(I.u_new)[i] = 0.0;
+      gmem(I.ipt)[i] = 0.0;
+      return;
+    }
+    ionic_point<MODEL, MIXED, false, true, true>(I, I.n_pts, step, i, i, I.rtab + (int64_t)r * NPARAM);
+  } else {
+    const int64_t node = gmem(I.sec_node)[i - I.n];
+    ionic_point<MODEL, MIXED, false, false, true>(I, I.n_pts, step, i, node, I.rtab + (int64_t)r * NPARAM);
+  }
+}
+
+// Interface correction of the load: cvec(j) = sum_q C(j, q) (I_q - I_node_q)
+// over the extra points q coupled to row j; one thread per correction row.
+__global__ __launch_bounds__(WG) void k_ici_correction(InstDesc* __restrict__ insts) {
+  const InstDesc& I = insts[0];
+  const int64_t t = (int64_t)blockIdx.x * WG + threadIdx.x;
+  if (t >= I.n_crow) return;
+  const gptr<const double> ipt = gmem((const double*)I.ipt);
+  const int64_t e0 = gmem(I.cptr)[t], e1 = gmem(I.cptr)[t + 1];
+  double acc = 0.0;
+  for (int64_t e = e0; e < e1; e++) {
+    const int32_t q = gmem(I.ccol)[e];
+    acc += gmem(I.cval)[e] * (ipt[I.n + q] - ipt[gmem(I.sec_node)[q]]);
+  }
+  gmem(I.cvec)[gmem(I.crow)[t]] = acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -409,6 +464,7 @@ __global__ __launch_bounds__(WG) void k_residual(InstDesc* __restrict__ insts, c
     if (valid) {
       if (WITH_RHS) {
         bi = spmv_row<double, double, double>(I, I.valM, I.g, i);
+        if (I.het) bi -= gmem((const double*)I.cvec)[i];
         b[i] = bi;
       } else {
         bi = b[i];
@@ -706,12 +762,13 @@ __global__ void k_end_step(InstDesc* __restrict__ insts, const int32_t* __restri
   S.restart = 0;
 }
 
-// Potential in mV into a caller-owned device buffer: dst = a u + b.
+// Potential in mV into a caller-owned device buffer: dst = a u + b (NaN at
+// nodes outside every conducting subdomain, reg[i] < 0, when reg is given).
 __global__ void k_to_mv(void* __restrict__ dst, const double* __restrict__ u, int64_t n, double a, double b,
-                        int f32) {
+                        int f32, const int32_t* __restrict__ reg) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const double v = a * u[i] + b;
+  const double v = (reg && reg[i] < 0) ? __builtin_nan("") : a * u[i] + b;
   if (f32) static_cast<float*>(dst)[i] = (float)v;
   else static_cast<double*>(dst)[i] = v;
 }
@@ -745,6 +802,12 @@ static void ionic_dispatch_npt(const Launch& L) {
 }
 
 template <int M, bool MX>
+static void ionic_het_dispatch(InstDesc* d, int64_t n_pts, hipStream_t st) {
+  const unsigned grid = (unsigned)((n_pts + WG - 1) / WG);
+  hipLaunchKernelGGL((k_ionic_het<M, MX>), dim3(grid), dim3(WG), 0, st, d);
+}
+
+template <int M, bool MX>
 static void ionic_dispatch(const Launch& L) {
   if (L.ionic_npt == 4) ionic_dispatch_npt<M, MX, 4>(L);
   else if (L.ionic_npt == 2) ionic_dispatch_npt<M, MX, 2>(L);
@@ -759,6 +822,25 @@ void launch_ionic(int model, bool mixed, const Launch& L) {
     case M_TTP06: mixed ? ionic_dispatch<M_TTP06, true>(L) : ionic_dispatch<M_TTP06, false>(L); break;
     default: mixed ? ionic_dispatch<M_PASSIVE, true>(L) : ionic_dispatch<M_PASSIVE, false>(L); break;
   }
+}
+
+void launch_ionic_het(int model, bool mixed, InstDesc* insts, int64_t n_pts, hipStream_t st) {
+  if (n_pts <= 0) return;
+  switch (model) {
+    case M_AP: mixed ? ionic_het_dispatch<M_AP, true>(insts, n_pts, st) : ionic_het_dispatch<M_AP, false>(insts, n_pts, st); break;
+    case M_BO: mixed ? ionic_het_dispatch<M_BO, true>(insts, n_pts, st) : ionic_het_dispatch<M_BO, false>(insts, n_pts, st); break;
+    case M_TTP06:
+      mixed ? ionic_het_dispatch<M_TTP06, true>(insts, n_pts, st) : ionic_het_dispatch<M_TTP06, false>(insts, n_pts, st);
+      break;
+    default:
+      mixed ? ionic_het_dispatch<M_PASSIVE, true>(insts, n_pts, st) : ionic_het_dispatch<M_PASSIVE, false>(insts, n_pts, st);
+      break;
+  }
+}
+
+void launch_ici_correction(InstDesc* insts, int64_t n_crow, hipStream_t st) {
+  if (n_crow <= 0) return;
+  hipLaunchKernelGGL(k_ici_correction, dim3((unsigned)((n_crow + WG - 1) / WG)), dim3(WG), 0, st, insts);
 }
 
 // CG-kernel launches: a single instance with the XCD-ordered (xmap 0) or the
@@ -819,10 +901,11 @@ void launch_end_step(InstDesc* insts, const int32_t* ids, int n_ids, hipStream_t
   hipLaunchKernelGGL(k_end_step, dim3((unsigned)((n_ids + 63) / 64)), dim3(64), 0, stream, insts, ids, n_ids);
 }
 
-void launch_to_mv(void* dst, const double* u, int64_t n, double a, double b, bool f32, hipStream_t stream) {
+void launch_to_mv(void* dst, const double* u, int64_t n, double a, double b, bool f32, hipStream_t stream,
+                  const int32_t* reg) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_to_mv, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, dst, u, n, a, b,
-                     f32 ? 1 : 0);
+                     f32 ? 1 : 0, reg);
 }
 
 void launch_fill(double* x, int64_t n, double v, hipStream_t stream) {

@@ -1,0 +1,166 @@
+"""GPU: several subdomains (per-subdomain cell type, parameters and
+conductivities; interface nodes with one ionic state per subdomain and the
+ionic load sum_i M^i I_ion^i; non-conductive subdomains removed) against the
+multi-subdomain oracle.
+
+Tolerances as for one subdomain: a single step from the same state at rtol
+1e-13 agrees to 1e-10 relative; trajectories at rtol 1e-10 to 1e-8 relative
+with activation times to the time step; mixed precision against FP64 at RMS
+1e-3 mV and 0.1 ms.  Removed nodes report NaN on both sides.  One subdomain,
+or several identical ones, through the subdomain path give bitwise the
+one-subdomain result (the interface correction is then exactly zero).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import regions as R
+from oracle.ionic import TTP_PARAM_NAMES
+
+pytestmark = pytest.mark.gpu
+
+
+def _ep():
+    import paper_2308_01651_amd as ep
+    return ep
+
+
+def _rel(a, b):
+    ok = np.isfinite(b)
+    return np.linalg.norm(a[ok] - b[ok]) / max(np.linalg.norm(b[ok]), 1e-300)
+
+
+def _slab(kind="q1", dims=(4.0, 2.0, 1.0), h=0.25, model="ttp06", variant="endo", bdf=2):
+    mesh = (W.slab_q1 if kind == "q1" else W.slab_p1)(*dims, h)
+    st = [W.corner_cube_stimulus(dims=dims)]
+    return W.SimSpec(mesh, W.random_fibers(mesh.n_nodes, 7), W.Physics(), model, variant, st, 0.05, bdf, 1,
+                     1e-10, "t")
+
+
+def _layers(spec, scar=False):
+    """Three TTP06 layers along x (endo / mid / epi, the epi layer with GKr
+    x1.5 and higher conductivity), optionally a non-conductive box."""
+    m = spec.mesh
+    L = m.xyz[:, 0].max()
+    mat = W.material_layers(m, 0, [L / 3, 2 * L / 3])
+    gkr = 0.153 * 1.5
+    oregs = [R.Region("endo"), R.Region("mid"),
+             R.Region("epi", params={"GKr": gkr}, sigma=(0.25, 0.03, 0.03))]
+    gregs = {0: dict(variant="endo"), 1: dict(variant="mid"),
+             2: dict(variant="epi", params=_ttp_params({"GKr": gkr}), sigma=(0.25, 0.03, 0.03))}
+    if scar:
+        mat = W.material_box(m, (0.4 * L, 0.0, 0.0), (0.6 * L, 0.6 * m.xyz[:, 1].max(), 1e9), 3, mat)
+        oregs.append(R.Region(conductive=False))
+        gregs[3] = dict(conductive=False)
+    return mat, oregs, gregs
+
+
+def _ttp_params(over):
+    """Positional TTP06 overrides up to the last named one (epi defaults)."""
+    from oracle.ionic import ttp06_params
+    p = ttp06_params("epi")
+    last = max(TTP_PARAM_NAMES.index(k) for k in over)
+    return [float(over.get(k, p[k])) for k in TTP_PARAM_NAMES[: last + 1]]
+
+
+@pytest.mark.parametrize("kind,scar", [("q1", False), ("q1", True), ("p1", False)])
+def test_regions_single_step(kind, scar):
+    ep = _ep()
+    spec = _slab(kind)
+    mat, oregs, gregs = _layers(spec, scar)
+    n = spec.mesh.n_nodes
+    u, w = W.random_state("ttp06", n, seed=61)
+    rng = np.random.default_rng(62)
+    u_prev = u + rng.normal(size=n)
+    o = R.from_spec(spec, mat, oregs, solver="splu", rtol=1e-13)
+    live = o.live
+    o.set_state(u[live], w[:, live], [u_prev[live]], 4)
+    o.step()
+    sim = ep.Simulation.from_spec(spec, rtol=1e-13, material=mat, regions=gregs)
+    sim.set_state(u, w, u_prev[None], 4)
+    sim.step(1)
+    ug, wg, _ = sim.get_state()
+    sim.close()
+    assert np.array_equal(np.isnan(ug), np.isnan(o.u))
+    assert _rel(ug, o.u) < 1e-10, _rel(ug, o.u)
+    # a node's state (get_state) is that of its lowest conducting subdomain
+    seen = np.zeros(n, bool)
+    for r in range(len(o.regions)):
+        nodes, wr = o.state(r)
+        prim = ~seen[nodes]
+        seen[nodes] = True
+        if prim.any():
+            idx = nodes[prim]
+            err = np.max(np.abs(wg[:, idx] - wr[:, prim]) / np.maximum(np.abs(wr[:, prim]), 1e-30))
+            assert err < 1e-9, (r, err)
+
+
+@pytest.mark.parametrize("kind,scar,prec", [("q1", True, 0), ("p1", False, 0), ("q1", True, 1)])
+def test_regions_trajectory(kind, scar, prec):
+    ep = _ep()
+    spec = _slab(kind, dims=(6.0, 3.0, 1.0), h=0.25)
+    mat, oregs, gregs = _layers(spec, scar)
+    steps = 300
+    o = R.from_spec(spec, mat, oregs, solver="splu")
+    ref = ep.Simulation.from_spec(spec, material=mat, regions=gregs)
+    sim = ep.Simulation.from_spec(spec, precision=prec, material=mat, regions=gregs)
+    for chunk in range(3):
+        o.run(steps // 3)
+        ref.step(steps // 3)
+        sim.step(steps // 3)
+        print(f"regions {kind} scar={scar} prec={prec}: {(chunk + 1) * steps // 3} steps", flush=True)
+        err = _rel(ref.get_potential(), o.potential_mv())
+        assert err < 1e-8, (chunk, err)
+    at_o, at_r, at_s = o.activation_times(), ref.get_activation_times(), sim.get_activation_times()
+    ok = ~np.isnan(at_o)
+    assert ok.sum() > 50 and np.array_equal(ok, ~np.isnan(at_r))
+    assert np.max(np.abs(at_o[ok] - at_r[ok])) <= spec.dt + 1e-9
+    if prec == 1:
+        du = sim.get_potential() - ref.get_potential()
+        fin = np.isfinite(du)
+        assert np.array_equal(fin, np.isfinite(ref.get_potential()))
+        assert np.sqrt(np.mean(du[fin] ** 2)) <= 1e-3
+        assert np.array_equal(ok, ~np.isnan(at_s)) and np.max(np.abs(at_s[ok] - at_r[ok])) <= 0.1
+    if scar:
+        removed = np.setdiff1d(np.arange(spec.mesh.n_nodes), o.live)
+        assert removed.size > 0 and np.all(np.isnan(ref.get_potential()[removed]))
+    ref.close()
+    sim.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_identical_subdomains_are_bitwise_one_subdomain(prec):
+    ep = _ep()
+    spec = _slab(dims=(4.0, 2.0, 1.0))
+    mat = W.material_layers(spec.mesh, 0, [1.3, 2.6])
+    one = ep.Simulation.from_spec(spec, precision=prec)
+    three = ep.Simulation.from_spec(spec, precision=prec, material=mat)
+    one.step(80)
+    three.step(80)
+    a, b = one.get_state(), three.get_state()
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    assert np.array_equal(one.get_activation_times(), three.get_activation_times(), equal_nan=True)
+    one.close()
+    three.close()
+
+
+def test_region_errors():
+    ep = _ep()
+    spec = _slab()
+    mat = W.material_layers(spec.mesh, 0, [2.0])
+    with pytest.raises(ep.EpError):
+        ep.Simulation.from_spec(spec, material=mat, ionic_scheme="bdf")
+    bad = mat.copy()
+    bad[0] = ep.EP_MAX_REGIONS
+    with pytest.raises(ep.EpError):
+        ep.Simulation.from_spec(spec, material=bad)
+    s = ep.Simulation.from_spec(spec, material=mat, finalize=False)
+    with pytest.raises(ep.EpError):
+        s.set_region(ep.EP_MAX_REGIONS)
+    with pytest.raises(ep.EpError):
+        s.set_region(0, variant=7)
+    pool = ep.Pool(1 << 30, 2, 0)
+    with pytest.raises(ep.EpError):
+        pool.admit(s, 10)
+    pool.close()
+    s.close()
