@@ -953,7 +953,7 @@ ep_status step_once(ep_sim* s) {
   const bool mixed = s->prec == EP_MIXED;
   KernelTimers& kt = s->kt;
   hipStream_t st = s->stream;
-  auto fin = [&] { kt.timed(st, 6, [&] { launch_cg_finalize(mixed, s->d_desc, s->d_ids, 1, st); }); };
+  auto fin = [&] { kt.timed(st, 6, [&] { launch_cg_finalize(mixed, s->d_desc, nullptr, 1, st); }); };
   auto round = [&] {
     kt.timed(st, 3, [&] { launch_cg_update(mixed, L); });
     kt.timed(st, 2, [&] { launch_cg_spmv(mixed, L); });

@@ -28,7 +28,8 @@ void launch_ionic(int model, bool mixed, const Launch& L);
 void launch_residual(bool mixed, bool with_rhs, const Launch& L);
 void launch_cg_spmv(bool mixed, const Launch& L);
 void launch_cg_update(bool mixed, const Launch& L);
-// one workgroup per instance listed in ids (device array of n_ids indices)
+// one workgroup per instance listed in ids (device array of n_ids indices);
+// ids == nullptr with n_ids == 1: the single instance at insts[0]
 void launch_cg_finalize(bool mixed, InstDesc* insts, const int32_t* ids, int n_ids, hipStream_t stream);
 void launch_activation(const Launch& L);
 // ids: device array of instance indices to advance by one step

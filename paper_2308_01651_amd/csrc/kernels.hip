@@ -548,14 +548,20 @@ __global__ __launch_bounds__(WG) void k_cg_spmv(InstDesc* __restrict__ insts, co
 // alpha_k = gamma_k / (delta_k - beta_k gamma_k / alpha_{k-1}).
 // ---------------------------------------------------------------------------
 
-template <bool MIXED>
+// The kernel is latency bound: the descriptor and state fields it needs are
+// loaded as one batch before any branch, and the partial sums (ordinary
+// memory) are read before the idle test, so the chain of dependent loads is
+// descriptor -> partials -> reduction.  A single instance (SINGLE) needs no
+// instance-list lookup.
+template <bool MIXED, bool SINGLE>
 __global__ __launch_bounds__(FIN_WG) void k_cg_finalize(InstDesc* __restrict__ insts,
                                                         const int32_t* __restrict__ ids) {
-  InstDesc& I = insts[ids[blockIdx.x]];
+  InstDesc& I = SINGLE ? insts[0] : insts[ids[blockIdx.x]];
   InstState& S = I.st;
-  if (cg_idle(S)) return;
+  const Ctl ctl = ld_ctl(S);
   const int nblk = I.nblk;
   const int k = S.it;
+  const double* __restrict__ P = I.partial;
   double t[4];
   double dl[1];
   // one pass over adjacent partial streams: residual [4] + SpMV [1] at the
@@ -563,17 +569,18 @@ __global__ __launch_bounds__(FIN_WG) void k_cg_finalize(InstDesc* __restrict__ i
   static_assert(PART_SPMV == PART_RES + 4 && PART_UPD == PART_SPMV + 1, "partial stream layout");
   if (k == 0) {
     double a[5];
-    reduce_partials<FIN_WG, 5>(I.partial + (int64_t)PART_RES * nblk, nblk, a);
+    reduce_partials<FIN_WG, 5>(P + (int64_t)PART_RES * nblk, nblk, a);
     t[0] = a[0]; t[1] = a[1]; t[2] = a[2]; t[3] = a[3];
     dl[0] = a[4];
   } else {
     double a[3];
-    reduce_partials<FIN_WG, 3>(I.partial + (int64_t)PART_SPMV * nblk, nblk, a);
+    reduce_partials<FIN_WG, 3>(P + (int64_t)PART_SPMV * nblk, nblk, a);
     dl[0] = a[0];
     t[0] = a[1];
     t[1] = a[2];
     t[2] = t[3] = 0.0;
   }
+  if (ctl.conv != 0 || (ctl.conv_in != 0 && ctl.restart == 0)) return;
   if (threadIdx.x != 0) return;
   S.restart = 0;
   S.conv_in = 0;
@@ -881,9 +888,15 @@ void launch_cg_spmv(bool mixed, const Launch& L) {
 }
 
 void launch_cg_finalize(bool mixed, InstDesc* insts, const int32_t* ids, int n_ids, hipStream_t stream) {
+  if (n_ids == 1 && ids == nullptr) {
+    // single instance at insts[0]
+    if (mixed) hipLaunchKernelGGL((k_cg_finalize<true, true>), dim3(1), dim3(FIN_WG), 0, stream, insts, ids);
+    else hipLaunchKernelGGL((k_cg_finalize<false, true>), dim3(1), dim3(FIN_WG), 0, stream, insts, ids);
+    return;
+  }
   if (n_ids <= 0) return;
-  if (mixed) hipLaunchKernelGGL((k_cg_finalize<true>), dim3(n_ids), dim3(FIN_WG), 0, stream, insts, ids);
-  else hipLaunchKernelGGL((k_cg_finalize<false>), dim3(n_ids), dim3(FIN_WG), 0, stream, insts, ids);
+  if (mixed) hipLaunchKernelGGL((k_cg_finalize<true, false>), dim3(n_ids), dim3(FIN_WG), 0, stream, insts, ids);
+  else hipLaunchKernelGGL((k_cg_finalize<false, false>), dim3(n_ids), dim3(FIN_WG), 0, stream, insts, ids);
 }
 
 void launch_cg_update(bool mixed, const Launch& L) {
