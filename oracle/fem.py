@@ -4,8 +4,9 @@ Follows the space discretization of the paper (Section "Cardiac
 electrophysiology: numerical discretization"): M_jk is the integral of
 phi_k phi_j over the domain, K_jk the integral of D grad(phi_k) . grad(phi_j),
 with Gauss quadrature of the fewest points that integrate M exactly:
-2x2x2 Gauss-Legendre points for trilinear hexahedra (Q1) and the symmetric
-4-point degree-2 rule for linear tetrahedra (P1).
+2x2x2 Gauss-Legendre points for trilinear hexahedra (Q1), 3x3x3 for
+triquadratic hexahedra (Q2, the paper's higher-order hexahedral elements),
+and the symmetric 4-point degree-2 rule for linear tetrahedra (P1).
 
 The diffusion tensor is the one of the monodomain model (eq. of the diffusion
 tensor): D = sigma_l f f^T + sigma_t s s^T + sigma_n n n^T, rescaled by
@@ -85,6 +86,67 @@ def q1_element_matrices(X, Dn):
 
 
 # ---------------------------------------------------------------------------
+# Q2 hexahedra (27 nodes, triquadratic)
+# ---------------------------------------------------------------------------
+
+def _lagrange2(t):
+    """Quadratic Lagrange basis on [-1, 1] with nodes -1, 0, 1: values and
+    derivatives, each [3]."""
+    v = np.array([0.5 * t * (t - 1.0), 1.0 - t * t, 0.5 * t * (t + 1.0)])
+    d = np.array([t - 0.5, -2.0 * t, t + 0.5])
+    return v, d
+
+
+def _q2_reference():
+    """Shape values [q, 27] and reference gradients [q, 27, 3] at the 3x3x3
+    Gauss points of [-1, 1]^3, and the weights.  Local node k = a + 3b + 9c
+    sits at the reference point (a - 1, b - 1, c - 1)."""
+    g = np.sqrt(0.6)
+    x1, w1 = np.array([-g, 0.0, g]), np.array([5.0, 8.0, 5.0]) / 9.0
+    pts, wts = [], []
+    for iz in range(3):
+        for iy in range(3):
+            for ix in range(3):
+                pts.append((x1[ix], x1[iy], x1[iz]))
+                wts.append(w1[ix] * w1[iy] * w1[iz])
+    N = np.zeros((27, 27))
+    dN = np.zeros((27, 27, 3))
+    for q, (x, y, z) in enumerate(pts):
+        vx, dx = _lagrange2(x)
+        vy, dy = _lagrange2(y)
+        vz, dz = _lagrange2(z)
+        for c in range(3):
+            for b in range(3):
+                for a in range(3):
+                    k = a + 3 * b + 9 * c
+                    N[q, k] = vx[a] * vy[b] * vz[c]
+                    dN[q, k] = (dx[a] * vy[b] * vz[c], vx[a] * dy[b] * vz[c], vx[a] * vy[b] * dz[c])
+    return N, dN, np.array(wts)
+
+
+def q2_element_matrices(X, Dn):
+    """Element mass and stiffness for a batch of triquadratic hexahedra
+    (isoparametric, 27 nodes in the order k = a + 3b + 9c).
+
+    X  : [E, 27, 3]; Dn : [E, 27, 3, 3]; returns Me, Ke [E, 27, 27]
+    """
+    N, dN, w = _q2_reference()
+    E = X.shape[0]
+    Me = np.zeros((E, 27, 27))
+    Ke = np.zeros((E, 27, 27))
+    for q in range(N.shape[0]):
+        J = np.einsum("ki,ekj->eij", dN[q], X)
+        detJ = np.linalg.det(J)
+        Jinv = np.linalg.inv(J)
+        G = np.einsum("eij,kj->eki", Jinv, dN[q])
+        Dq = np.einsum("k,ekij->eij", N[q], Dn)
+        wq = w[q] * detJ
+        Me += wq[:, None, None] * np.outer(N[q], N[q])[None]
+        Ke += wq[:, None, None] * np.einsum("eai,eij,ebj->eab", G, Dq, G)
+    return Me, Ke
+
+
+# ---------------------------------------------------------------------------
 # P1 tetrahedra
 # ---------------------------------------------------------------------------
 
@@ -140,7 +202,9 @@ def assemble(xyz, conn, Dnodal, chunk: int = 200000):
         c = conn[e0:e0 + chunk]
         X = xyz[c]
         Dn = Dnodal[c]
-        if npe == 8:
+        if npe == 27:
+            Me, Ke = q2_element_matrices(X, Dn)
+        elif npe == 8:
             Me, Ke = q1_element_matrices(X, Dn)
         elif npe == 4:
             Me, Ke = p1_element_matrices(X, Dn)

@@ -8,6 +8,7 @@ stencil of the Kuhn-split lattice.
 import numpy as np
 import pytest
 import scipy.sparse as sp
+import scipy.sparse.linalg as spla
 
 import workloads as W
 from oracle import fem
@@ -173,3 +174,59 @@ def test_lv_shell_mesh_is_valid():
                                     m.conn[:, [0, 2, 3]], m.conn[:, [1, 2, 3]]]), axis=1)
     _, cnt = np.unique(faces, axis=0, return_counts=True)
     assert cnt.max() == 2
+
+
+# ---------------------------------------------------------------------------
+# Q2 (27-node) hexahedra
+# ---------------------------------------------------------------------------
+
+def test_q2_integrates_quadratic_fields_exactly():
+    """Mass and stiffness are exact for quadratic fields on an affinely
+    mapped (sheared) Q2 lattice: int f g and int grad f . D grad g against
+    closed forms (a dropped term, wrong weight or wrong node order fails)."""
+    m = W.slab_q2(2.0, 1.0, 1.0, 0.5)
+    A = np.array([[1.0, 0.3, 0.0], [0.0, 1.0, 0.2], [0.1, 0.0, 1.0]])
+    xyz = m.xyz @ A.T
+    D = np.array([[2.0, 0.3, 0.1], [0.3, 1.0, 0.2], [0.1, 0.2, 0.5]])
+    Dn = np.broadcast_to(D, (m.n_nodes, 3, 3)).copy()
+    M, K = fem.assemble(xyz, m.conn, Dn)
+    # pull back to the reference box [0,2]x[0,1]x[0,1]: x = A r, dx = det A dr
+    detA = np.linalg.det(A)
+    r = m.xyz
+    f = r[:, 0] ** 2 + r[:, 1] * r[:, 2]            # quadratic in r (and in x)
+    g = r[:, 2] ** 2 - r[:, 0]
+    assert abs(np.ones(m.n_nodes) @ M @ np.ones(m.n_nodes) - 2.0 * detA) < 1e-12
+    # int f g dr over the box, by exact 1-D integrals
+    Ix = {0: 2.0, 1: 2.0, 2: 8.0 / 3.0, 3: 4.0}
+    Iy = {0: 1.0, 1: 0.5, 2: 1.0 / 3.0, 3: 0.25}
+    fg = (Ix[2] * Iy[0] * Iy[2] - Ix[3] * Iy[0] * Iy[0] + Ix[0] * Iy[1] * Iy[3] - Ix[1] * Iy[1] * Iy[1])
+    assert abs(f @ M @ g - fg * detA) < 1e-12
+    # gradients in x: grad_x f = A^{-T} grad_r f; energy = int grad_r f^T B grad_r g dr * detA
+    B = np.linalg.inv(A) @ D @ np.linalg.inv(A).T
+    # grad_r f = (2 r0, r2, r1), grad_r g = (-1, 0, 2 r2)
+    terms = {(0, 0): -2.0 * Ix[1] * Iy[0] * Iy[0], (0, 2): 4.0 * Ix[1] * Iy[0] * Iy[1],
+             (1, 0): -Ix[0] * Iy[0] * Iy[1], (1, 2): 2.0 * Ix[0] * Iy[0] * Iy[2],
+             (2, 0): -Ix[0] * Iy[1] * Iy[0], (2, 2): 2.0 * Ix[0] * Iy[1] * Iy[1]}
+    energy = sum(B[i, j] * v for (i, j), v in terms.items())
+    assert abs(f @ K @ g - energy * detA) < 1e-11
+    assert np.abs(K @ np.ones(m.n_nodes)).max() < 1e-12
+
+
+def test_q2_eigenvalue_converges_at_fourth_order():
+    """Generalized eigenvalue of the slab's cosine mode: for quadratic
+    elements the error falls as h^4 (ratio ~16 per halving); the rate pins
+    the quadratic basis and the 3x3x3 rule."""
+    L = 2.0
+    errs = []
+    for h in (0.5, 0.25):
+        m = W.slab_q2(L, 0.5, 0.5, h)
+        Dn = fem.nodal_diffusion(*W.uniform_fibers(m.n_nodes), 1.0, 1.0, 1.0, 1.0, 1.0)
+        M, K = fem.assemble(m.xyz, m.conn, Dn)
+        v = np.cos(np.pi * m.xyz[:, 0] / L)
+        lam_h = spla.eigsh(K, k=2, M=M, sigma=0.0, which="LM")[0]
+        lam = (np.pi / L) ** 2
+        errs.append(np.min(np.abs(lam_h - lam)))
+        assert np.allclose(K @ np.ones(m.n_nodes), 0.0, atol=1e-12)
+        del v
+    rate = np.log2(errs[0] / errs[1])
+    assert 3.7 < rate < 4.3, (errs, rate)
