@@ -88,6 +88,79 @@ bool hex_element(const double X[8][3], const double Dn[8][9], double Me[64], dou
   return true;
 }
 
+// Triquadratic hexahedron (27 nodes), local node k = a + 3b + 9c at the
+// reference point (a - 1, b - 1, c - 1); isoparametric map; 3x3x3
+// Gauss-Legendre quadrature (exact for the mass matrix of an affine element).
+bool hex27_element(const double X[27][3], const double Dn[27][9], double* Me, double* Ke) {
+  static const double gp[3] = {-0.77459666924148337704, 0.0, 0.77459666924148337704};  // -sqrt(3/5), 0, sqrt(3/5)
+  static const double gw[3] = {5.0 / 9.0, 8.0 / 9.0, 5.0 / 9.0};
+  std::memset(Me, 0, 27 * 27 * sizeof(double));
+  std::memset(Ke, 0, 27 * 27 * sizeof(double));
+  // 1-D quadratic Lagrange factors at the nodes -1, 0, 1 and their derivatives
+  auto lag = [](double t, double v[3], double d[3]) {
+    v[0] = 0.5 * t * (t - 1.0);
+    v[1] = (1.0 - t) * (1.0 + t);
+    v[2] = 0.5 * t * (t + 1.0);
+    d[0] = t - 0.5;
+    d[1] = -2.0 * t;
+    d[2] = t + 0.5;
+  };
+  for (int qz = 0; qz < 3; qz++)
+    for (int qy = 0; qy < 3; qy++)
+      for (int qx = 0; qx < 3; qx++) {
+        double vx[3], dx[3], vy[3], dy[3], vz[3], dz[3];
+        lag(gp[qx], vx, dx);
+        lag(gp[qy], vy, dy);
+        lag(gp[qz], vz, dz);
+        double N[27], dN[27][3];
+        for (int c = 0; c < 3; c++)
+          for (int b = 0; b < 3; b++)
+            for (int a = 0; a < 3; a++) {
+              const int k = a + 3 * b + 9 * c;
+              N[k] = vx[a] * vy[b] * vz[c];
+              dN[k][0] = dx[a] * vy[b] * vz[c];
+              dN[k][1] = vx[a] * dy[b] * vz[c];
+              dN[k][2] = vx[a] * vy[b] * dz[c];
+            }
+        double J[3][3] = {{0}};
+        for (int k = 0; k < 27; k++)
+          for (int r = 0; r < 3; r++)
+            for (int c = 0; c < 3; c++) J[r][c] += dN[k][r] * X[k][c];
+        const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                           J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                           J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+        if (!(det > 0.0)) return false;
+        double Ji[3][3];
+        Ji[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
+        Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+        Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+        Ji[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;
+        Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+        Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+        Ji[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / det;
+        Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+        Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+        double G[27][3];
+        for (int k = 0; k < 27; k++)
+          for (int r = 0; r < 3; r++)
+            G[k][r] = Ji[r][0] * dN[k][0] + Ji[r][1] * dN[k][1] + Ji[r][2] * dN[k][2];
+        double Dq[9] = {0};
+        for (int k = 0; k < 27; k++)
+          for (int e = 0; e < 9; e++) Dq[e] += N[k] * Dn[k][e];
+        double DG[27][3];
+        for (int k = 0; k < 27; k++)
+          for (int r = 0; r < 3; r++)
+            DG[k][r] = Dq[3 * r] * G[k][0] + Dq[3 * r + 1] * G[k][1] + Dq[3 * r + 2] * G[k][2];
+        const double w = gw[qx] * gw[qy] * gw[qz] * det;
+        for (int a = 0; a < 27; a++)
+          for (int b = 0; b < 27; b++) {
+            Me[27 * a + b] += w * N[a] * N[b];
+            Ke[27 * a + b] += w * (G[a][0] * DG[b][0] + G[a][1] * DG[b][1] + G[a][2] * DG[b][2]);
+          }
+      }
+  return true;
+}
+
 // Linear tetrahedron.  Gradients of the barycentric coordinates are constant;
 // with D interpolated linearly, the degree-2 rule reduces exactly to
 // K = V G^T mean(D) G, and M = V (1 + delta_ab)/20.
@@ -135,7 +208,10 @@ bool assemble_csr(int elem, int64_t n_nodes, const double* xyz, int64_t n_elems,
                   double sigma_l, double sigma_t, double sigma_n, double chi, double cm, Csr& A,
                   std::vector<char>& err, const int32_t* region, const double* region_sigma,
                   const unsigned char* region_on) {
-  if (elem != 8 && elem != 4) { set_err(err, "element type must be 8 (hex) or 4 (tet)"); return false; }
+  if (elem != 8 && elem != 4 && elem != 27) {
+    set_err(err, "element type must be 8 (hex), 27 (triquadratic hex) or 4 (tet)");
+    return false;
+  }
   if (n_nodes <= 0 || n_elems <= 0) { set_err(err, "empty mesh"); return false; }
   if (n_nodes >= (int64_t)INT32_MAX) { set_err(err, "too many nodes for int32 indices"); return false; }
   if (!(chi > 0) || !(cm > 0)) { set_err(err, "chi and C_m must be positive"); return false; }
@@ -160,7 +236,7 @@ bool assemble_csr(int elem, int64_t n_nodes, const double* xyz, int64_t n_elems,
   std::vector<char> bad(1, 0);
   static const double ex[3] = {1, 0, 0}, ey[3] = {0, 1, 0}, ez[3] = {0, 0, 1};
   parallel_for(n_elems, [&](int64_t e) {
-    double X[8][3], Dn[8][9];
+    double X[27][3], Dn[27][9];
     const int r = region ? region[e] : 0;
     const double sl = region ? region_sigma[3 * r] : sigma_l;
     const double st = region ? region_sigma[3 * r + 1] : sigma_t;
@@ -173,8 +249,9 @@ bool assemble_csr(int elem, int64_t n_nodes, const double* xyz, int64_t n_elems,
       const double* nn = n0 ? n0 + 3 * v : ez;
       nodal_tensor(f, s, nn, sl, st, sn, scale, Dn[k]);
     }
-    bool ok = (npe == 8) ? hex_element(X, Dn, &Me[e * 64], &Ke[e * 64])
-                         : tet_element(X, Dn, &Me[e * 16], &Ke[e * 16]);
+    bool ok = (npe == 27) ? hex27_element(X, Dn, &Me[e * 27 * 27], &Ke[e * 27 * 27])
+              : (npe == 8) ? hex_element(X, Dn, &Me[e * 64], &Ke[e * 64])
+                           : tet_element(X, Dn, &Me[e * 16], &Ke[e * 16]);
     if (!ok) bad[0] = 1;
     if (region && region_on && !region_on[r])
       for (int k = 0; k < npe * npe; k++) Me[e * npe * npe + k] = Ke[e * npe * npe + k] = 0.0;

@@ -1,0 +1,87 @@
+"""GPU: triquadratic (27-node) hexahedra against the oracle.
+
+The operator of the Q2 lattice has up to 125 entries per row and is stored in
+the sliced-ELL format; everything else (ionic step at every node, ICI load,
+PCG, activation) is the path of the other elements.  Tolerances as for Q1:
+a single step at rtol 1e-13 to 1e-10 relative, trajectories at rtol 1e-10 to
+1e-8 with activation times to the time step, mixed precision against FP64
+at RMS 1e-3 mV and 0.1 ms.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import monodomain as OM
+
+pytestmark = pytest.mark.gpu
+
+
+def _ep():
+    import paper_2308_01651_amd as ep
+    return ep
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def _spec(dims=(4.0, 2.0, 1.0), h=0.5, model="ttp06", variant="endo", bdf=2, curved=False):
+    mesh = W.slab_q2(*dims, h)
+    if curved:
+        rng = np.random.default_rng(8)
+        mesh.xyz = mesh.xyz + rng.uniform(-0.02, 0.02, mesh.xyz.shape)
+    st = [W.corner_cube_stimulus(dims=dims)]
+    return W.SimSpec(mesh, W.random_fibers(mesh.n_nodes, 9), W.Physics(), model, variant, st, 0.05, bdf, 1,
+                     1e-10, "t")
+
+
+@pytest.mark.parametrize("model,variant,bdf,curved", [("ttp06", "endo", 2, False), ("bo", "epi", 3, True),
+                                                      ("ap", "", 1, False)])
+def test_q2_single_step(model, variant, bdf, curved):
+    ep = _ep()
+    spec = _spec(model=model, variant=variant, bdf=bdf, curved=curved)
+    n = spec.mesh.n_nodes
+    u, w = W.random_state(model, n, seed=71)
+    rng = np.random.default_rng(72)
+    scale = 1.0 if model == "ttp06" else 0.01
+    u_prev = np.stack([u + scale * rng.normal(size=n) for _ in range(bdf - 1)]) if bdf > 1 else None
+    o = OM.from_spec(spec, solver="splu", rtol=1e-13)
+    o.set_state(u, w, list(u_prev) if u_prev is not None else None, 5)
+    o.step()
+    sim = ep.Simulation.from_spec(spec, rtol=1e-13)
+    assert sim.get_stats()["matrix_format"] == ep.EP_FMT_SELL
+    sim.set_state(u, w, u_prev, 5)
+    sim.step(1)
+    ug, wg, _ = sim.get_state()
+    sim.close()
+    assert _rel(ug, o.u) < 1e-10, _rel(ug, o.u)
+    for v in range(w.shape[0]):
+        err = np.max(np.abs(wg[v] - o.w[v])) / max(np.max(np.abs(o.w[v])), 1e-30)
+        assert err < 1e-11, (v, err)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_q2_trajectory(prec):
+    ep = _ep()
+    spec = _spec(dims=(6.0, 3.0, 1.0), h=0.5)
+    o = OM.from_spec(spec, solver="splu")
+    ref = ep.Simulation.from_spec(spec)
+    sim = ep.Simulation.from_spec(spec, precision=prec)
+    steps = 300
+    for chunk in range(3):
+        o.run(steps // 3)
+        ref.step(steps // 3)
+        sim.step(steps // 3)
+        print(f"q2 trajectory prec={prec}: {(chunk + 1) * steps // 3} steps", flush=True)
+        err = _rel(ref.get_potential(), o.potential_mv())
+        assert err < 1e-8, (chunk, err)
+    at_o, at_r, at_s = o.activation_times(), ref.get_activation_times(), sim.get_activation_times()
+    ok = ~np.isnan(at_o)
+    assert ok.sum() > 100 and np.array_equal(ok, ~np.isnan(at_r))
+    assert np.max(np.abs(at_o[ok] - at_r[ok])) <= spec.dt + 1e-9
+    if prec == 1:
+        du = sim.get_potential() - ref.get_potential()
+        assert np.sqrt(np.mean(du * du)) <= 1e-3
+        assert np.array_equal(ok, ~np.isnan(at_s)) and np.max(np.abs(at_s[ok] - at_r[ok])) <= 0.1
+    ref.close()
+    sim.close()
