@@ -6,7 +6,9 @@ phi_k phi_j over the domain, K_jk the integral of D grad(phi_k) . grad(phi_j),
 with Gauss quadrature of the fewest points that integrate M exactly:
 2x2x2 Gauss-Legendre points for trilinear hexahedra (Q1), 3x3x3 for
 triquadratic hexahedra (Q2, the paper's higher-order hexahedral elements),
-and the symmetric 4-point degree-2 rule for linear tetrahedra (P1).
+the symmetric 4-point degree-2 rule for linear tetrahedra (P1), and a
+64-point conical product rule (exact to degree 5) for quadratic tetrahedra
+(P2, the paper's higher-order tetrahedral elements).
 
 The diffusion tensor is the one of the monodomain model (eq. of the diffusion
 tensor): D = sigma_l f f^T + sigma_t s s^T + sigma_n n n^T, rescaled by
@@ -188,6 +190,74 @@ def p1_element_matrices(X, Dn):
 
 
 # ---------------------------------------------------------------------------
+# P2 tetrahedra (10 nodes, straight-sided)
+# ---------------------------------------------------------------------------
+
+TET10_EDGES = ((0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3))
+
+
+def _collapsed_tet_rule(n=4):
+    """Barycentric points [q, 4] and weights (fractions of the volume) of the
+    conical product rule: n-point Gauss-Legendre in each direction of the unit
+    cube mapped onto the tetrahedron by collapsing (l1 = u, l2 = v (1 - u),
+    l3 = w (1 - u)(1 - v), Jacobian 6 (1 - u)^2 (1 - v)).  Exact for
+    polynomials of degree 2n - 3 in the barycentric coordinates."""
+    x, wx = np.polynomial.legendre.leggauss(n)
+    x, wx = 0.5 * (x + 1.0), 0.5 * wx
+    L, W = [], []
+    for i in range(n):
+        for j in range(n):
+            for k in range(n):
+                u, v, w = x[i], x[j], x[k]
+                l1, l2, l3 = u, v * (1 - u), w * (1 - u) * (1 - v)
+                L.append((1.0 - l1 - l2 - l3, l1, l2, l3))
+                W.append(6.0 * wx[i] * wx[j] * wx[k] * (1 - u) ** 2 * (1 - v))
+    return np.array(L), np.array(W)
+
+
+def _p2_basis(L):
+    """Quadratic Lagrange values [10] and derivatives with respect to the
+    barycentric coordinates [10, 4] at one point L (vertices first, then the
+    midpoints of TET10_EDGES)."""
+    N = np.zeros(10)
+    dL = np.zeros((10, 4))
+    for i in range(4):
+        N[i] = L[i] * (2.0 * L[i] - 1.0)
+        dL[i, i] = 4.0 * L[i] - 1.0
+    for e, (a, b) in enumerate(TET10_EDGES):
+        N[4 + e] = 4.0 * L[a] * L[b]
+        dL[4 + e, a] = 4.0 * L[b]
+        dL[4 + e, b] = 4.0 * L[a]
+    return N, dL
+
+
+def p2_element_matrices(X, Dn):
+    """Element mass and stiffness for a batch of straight-sided quadratic
+    tetrahedra (geometry from the four vertices).
+
+    X  : [E, 10, 3]; Dn : [E, 10, 3, 3]; returns Me, Ke [E, 10, 10]
+    """
+    E = X.shape[0]
+    T = np.stack([X[:, 1] - X[:, 0], X[:, 2] - X[:, 0], X[:, 3] - X[:, 0]], axis=1)
+    vol = np.abs(np.linalg.det(T)) / 6.0
+    Tinv = np.linalg.inv(T)
+    GL = np.zeros((E, 4, 3))                      # gradients of the barycentric coordinates
+    GL[:, 1:, :] = np.transpose(Tinv, (0, 2, 1))
+    GL[:, 0, :] = -GL[:, 1:, :].sum(axis=1)
+    Lq, wq = _collapsed_tet_rule(4)
+    Me = np.zeros((E, 10, 10))
+    Ke = np.zeros((E, 10, 10))
+    for q in range(Lq.shape[0]):
+        N, dL = _p2_basis(Lq[q])
+        G = np.einsum("kl,elc->ekc", dL, GL)      # physical gradients [E, 10, 3]
+        Dq = np.einsum("k,ekij->eij", N, Dn)
+        w = wq[q] * vol
+        Me += w[:, None, None] * np.outer(N, N)[None]
+        Ke += w[:, None, None] * np.einsum("eai,eij,ebj->eab", G, Dq, G)
+    return Me, Ke
+
+
+# ---------------------------------------------------------------------------
 # Assembly
 # ---------------------------------------------------------------------------
 
@@ -204,6 +274,8 @@ def assemble(xyz, conn, Dnodal, chunk: int = 200000):
         Dn = Dnodal[c]
         if npe == 27:
             Me, Ke = q2_element_matrices(X, Dn)
+        elif npe == 10:
+            Me, Ke = p2_element_matrices(X, Dn)
         elif npe == 8:
             Me, Ke = q1_element_matrices(X, Dn)
         elif npe == 4:

@@ -154,6 +154,35 @@ def slab_p1(Lx: float, Ly: float, Lz: float, h: float, label: str = "") -> Mesh:
     return Mesh(q.xyz, np.ascontiguousarray(tets), (nx, ny, nz), label)
 
 
+# local edges of a 10-node tetrahedron: node 4 + e is the midpoint of edge e
+TET10_EDGES = ((0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3))
+
+
+def slab_p2(Lx: float, Ly: float, Lz: float, h: float, label: str = "") -> Mesh:
+    """Structured quadratic (10-node) tetrahedral slab: the Kuhn-split cells
+    of the lattice of spacing h, nodes on the lattice of spacing h/2.  Local
+    nodes 0-3 are the (positively oriented) vertices, node 4 + e the midpoint
+    of edge TET10_EDGES[e]."""
+    cx = int(round(Lx / h))
+    cy = int(round(Ly / h))
+    cz = int(round(Lz / h))
+    nx, ny, nz = 2 * cx + 1, 2 * cy + 1, 2 * cz + 1
+    xyz = _lattice_xyz(nx, ny, nz, Lx / (nx - 1), Ly / (ny - 1), Lz / (nz - 1))
+    ex, ey, ez = np.meshgrid(np.arange(cx), np.arange(cy), np.arange(cz), indexing="ij")
+    base = np.stack([2 * ex, 2 * ey, 2 * ez], axis=-1).transpose(2, 1, 0, 3).reshape(-1, 3)
+    corner = np.array([[2 * (k & 1), 2 * ((k >> 1) & 1), 2 * ((k >> 2) & 1)] for k in range(8)])
+    vert = base[:, None, None, :] + corner[_KUHN][None, :, :, :]          # [cells, 6, 4, 3] lattice index
+    vert = vert.reshape(-1, 4, 3)
+    ids = lambda ijk: ijk[..., 0] + nx * (ijk[..., 1] + ny * ijk[..., 2])
+    tv = ids(vert)
+    oriented = _orient_tets(xyz, tv)
+    swap = oriented[:, 1] != tv[:, 1]
+    vert[swap, 1], vert[swap, 2] = vert[swap, 2].copy(), vert[swap, 1].copy()
+    mids = np.stack([(vert[:, a] + vert[:, b]) // 2 for a, b in TET10_EDGES], axis=1)
+    conn = np.concatenate([ids(vert), ids(mids)], axis=1).astype(np.int32)
+    return Mesh(xyz, np.ascontiguousarray(conn), (nx, ny, nz), label or f"slab-p2-{Lx}x{Ly}x{Lz}-h{h}")
+
+
 # ---------------------------------------------------------------------------
 # Fibers
 # ---------------------------------------------------------------------------
