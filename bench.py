@@ -445,14 +445,16 @@ def main():
         if args.workload == "c1":
             # triquadratic elements on the same node lattice (element size 0.2 mm:
             # 100 x 35 x 15 elements, 201 x 71 x 31 nodes), operator in sliced ELL
-            q2 = W.SimSpec(W.slab_q2(20.0, 7.0, 3.0, 0.2), spec.fibers, spec.phys, spec.model, spec.variant,
-                           spec.stimuli, spec.dt, spec.bdf, spec.n_steps, spec.rtol, "q2")
-            r0, _, _ = run_gpu(q2, ep.EP_FP64, args.steps, args.warmup, 0, bool(args.graph), bool(args.autotune))
-            out["fp64_q2_elements_same_nodes"] = {k: r0[k] for k in (
-                "node_steps_per_s", "ms_per_step", "step_latency_ms_p50", "step_latency_ms_p99", "launch",
-                "cg_iters_per_step", "matrix_format", "nnz", "device_bytes")}
-            print(f"[bench] fp64_q2_elements_same_nodes: {r0['node_steps_per_s']:.4g} node-steps/s, "
-                  f"{r0['cg_iters_per_step']:.1f} CG its/step, nnz {r0['nnz']}", file=sys.stderr, flush=True)
+            # and quadratic tetrahedra (each cell Kuhn-split) on the same lattice
+            for name, gen in (("fp64_q2_elements_same_nodes", W.slab_q2), ("fp64_p2_elements_same_nodes", W.slab_p2)):
+                hi = W.SimSpec(gen(20.0, 7.0, 3.0, 0.2), spec.fibers, spec.phys, spec.model, spec.variant,
+                               spec.stimuli, spec.dt, spec.bdf, spec.n_steps, spec.rtol, name)
+                r0, _, _ = run_gpu(hi, ep.EP_FP64, args.steps, args.warmup, 0, bool(args.graph), bool(args.autotune))
+                out[name] = {k: r0[k] for k in (
+                    "node_steps_per_s", "ms_per_step", "step_latency_ms_p50", "step_latency_ms_p99", "launch",
+                    "cg_iters_per_step", "matrix_format", "nnz", "device_bytes")}
+                print(f"[bench] {name}: {r0['node_steps_per_s']:.4g} node-steps/s, "
+                      f"{r0['cg_iters_per_step']:.1f} CG its/step, nnz {r0['nnz']}", file=sys.stderr, flush=True)
     if "fp64" in fields and "mixed" in fields:
         du = fields["mixed"][0] - fields["fp64"][0]
         a64, a32 = fields["fp64"][1], fields["mixed"][1]

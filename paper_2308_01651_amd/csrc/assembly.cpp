@@ -161,6 +161,78 @@ bool hex27_element(const double X[27][3], const double Dn[27][9], double* Me, do
   return true;
 }
 
+// Quadratic tetrahedron (10 nodes: vertices 0-3, then the midpoints of the
+// edges 01, 02, 03, 12, 13, 23), straight-sided (affine map of the
+// vertices).  Quadrature: the conical product of 4-point Gauss-Legendre rules
+// on the unit cube collapsed onto the tetrahedron (64 points, exact to
+// degree 5 in the barycentric coordinates).
+bool tet10_element(const double X[10][3], const double Dn[10][9], double* Me, double* Ke) {
+  static const double gx[4] = {0.06943184420297371, 0.33000947820757187, 0.66999052179242813,
+                               0.93056815579702629};  // Gauss-Legendre nodes on [0, 1]
+  static const double gw[4] = {0.17392742256872693, 0.32607257743127307, 0.32607257743127307,
+                               0.17392742256872693};
+  static const int edge[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+  double E[3][3];
+  for (int r = 0; r < 3; r++)
+    for (int c = 0; c < 3; c++) E[r][c] = X[r + 1][c] - X[0][c];
+  const double det = E[0][0] * (E[1][1] * E[2][2] - E[1][2] * E[2][1]) -
+                     E[0][1] * (E[1][0] * E[2][2] - E[1][2] * E[2][0]) +
+                     E[0][2] * (E[1][0] * E[2][1] - E[1][1] * E[2][0]);
+  if (det == 0.0 || !std::isfinite(det)) return false;
+  const double vol = std::fabs(det) / 6.0;
+  // gradient of barycentric coordinate L_{r+1} = column r of E^{-1}
+  double Ei[3][3];
+  Ei[0][0] = (E[1][1] * E[2][2] - E[1][2] * E[2][1]) / det;
+  Ei[0][1] = (E[0][2] * E[2][1] - E[0][1] * E[2][2]) / det;
+  Ei[0][2] = (E[0][1] * E[1][2] - E[0][2] * E[1][1]) / det;
+  Ei[1][0] = (E[1][2] * E[2][0] - E[1][0] * E[2][2]) / det;
+  Ei[1][1] = (E[0][0] * E[2][2] - E[0][2] * E[2][0]) / det;
+  Ei[1][2] = (E[0][2] * E[1][0] - E[0][0] * E[1][2]) / det;
+  Ei[2][0] = (E[1][0] * E[2][1] - E[1][1] * E[2][0]) / det;
+  Ei[2][1] = (E[0][1] * E[2][0] - E[0][0] * E[2][1]) / det;
+  Ei[2][2] = (E[0][0] * E[1][1] - E[0][1] * E[1][0]) / det;
+  double GL[4][3];
+  for (int k = 0; k < 3; k++)
+    for (int c = 0; c < 3; c++) GL[k + 1][c] = Ei[c][k];
+  for (int c = 0; c < 3; c++) GL[0][c] = -(GL[1][c] + GL[2][c] + GL[3][c]);
+  std::memset(Me, 0, 100 * sizeof(double));
+  std::memset(Ke, 0, 100 * sizeof(double));
+  for (int i = 0; i < 4; i++)
+    for (int j = 0; j < 4; j++)
+      for (int k = 0; k < 4; k++) {
+        const double u = gx[i], v = gx[j], w = gx[k];
+        double L[4];
+        L[1] = u;
+        L[2] = v * (1.0 - u);
+        L[3] = w * (1.0 - u) * (1.0 - v);
+        L[0] = 1.0 - L[1] - L[2] - L[3];
+        const double wq = 6.0 * gw[i] * gw[j] * gw[k] * (1.0 - u) * (1.0 - u) * (1.0 - v) * vol;
+        double N[10], G[10][3];
+        for (int a = 0; a < 4; a++) {
+          N[a] = L[a] * (2.0 * L[a] - 1.0);
+          for (int c = 0; c < 3; c++) G[a][c] = (4.0 * L[a] - 1.0) * GL[a][c];
+        }
+        for (int e = 0; e < 6; e++) {
+          const int a = edge[e][0], b = edge[e][1];
+          N[4 + e] = 4.0 * L[a] * L[b];
+          for (int c = 0; c < 3; c++) G[4 + e][c] = 4.0 * (L[b] * GL[a][c] + L[a] * GL[b][c]);
+        }
+        double Dq[9] = {0};
+        for (int a = 0; a < 10; a++)
+          for (int t = 0; t < 9; t++) Dq[t] += N[a] * Dn[a][t];
+        double DG[10][3];
+        for (int a = 0; a < 10; a++)
+          for (int r = 0; r < 3; r++)
+            DG[a][r] = Dq[3 * r] * G[a][0] + Dq[3 * r + 1] * G[a][1] + Dq[3 * r + 2] * G[a][2];
+        for (int a = 0; a < 10; a++)
+          for (int b = 0; b < 10; b++) {
+            Me[10 * a + b] += wq * N[a] * N[b];
+            Ke[10 * a + b] += wq * (G[a][0] * DG[b][0] + G[a][1] * DG[b][1] + G[a][2] * DG[b][2]);
+          }
+      }
+  return true;
+}
+
 // Linear tetrahedron.  Gradients of the barycentric coordinates are constant;
 // with D interpolated linearly, the degree-2 rule reduces exactly to
 // K = V G^T mean(D) G, and M = V (1 + delta_ab)/20.
@@ -208,8 +280,8 @@ bool assemble_csr(int elem, int64_t n_nodes, const double* xyz, int64_t n_elems,
                   double sigma_l, double sigma_t, double sigma_n, double chi, double cm, Csr& A,
                   std::vector<char>& err, const int32_t* region, const double* region_sigma,
                   const unsigned char* region_on) {
-  if (elem != 8 && elem != 4 && elem != 27) {
-    set_err(err, "element type must be 8 (hex), 27 (triquadratic hex) or 4 (tet)");
+  if (elem != 8 && elem != 4 && elem != 27 && elem != 10) {
+    set_err(err, "element type must be 8 (hex), 27 (triquadratic hex), 4 (tet) or 10 (quadratic tet)");
     return false;
   }
   if (n_nodes <= 0 || n_elems <= 0) { set_err(err, "empty mesh"); return false; }
@@ -249,9 +321,10 @@ bool assemble_csr(int elem, int64_t n_nodes, const double* xyz, int64_t n_elems,
       const double* nn = n0 ? n0 + 3 * v : ez;
       nodal_tensor(f, s, nn, sl, st, sn, scale, Dn[k]);
     }
-    bool ok = (npe == 27) ? hex27_element(X, Dn, &Me[e * 27 * 27], &Ke[e * 27 * 27])
-              : (npe == 8) ? hex_element(X, Dn, &Me[e * 64], &Ke[e * 64])
-                           : tet_element(X, Dn, &Me[e * 16], &Ke[e * 16]);
+    bool ok = (npe == 27)  ? hex27_element(X, Dn, &Me[e * 27 * 27], &Ke[e * 27 * 27])
+              : (npe == 10) ? tet10_element(X, Dn, &Me[e * 100], &Ke[e * 100])
+              : (npe == 8)  ? hex_element(X, Dn, &Me[e * 64], &Ke[e * 64])
+                            : tet_element(X, Dn, &Me[e * 16], &Ke[e * 16]);
     if (!ok) bad[0] = 1;
     if (region && region_on && !region_on[r])
       for (int k = 0; k < npe * npe; k++) Me[e * npe * npe + k] = Ke[e * npe * npe + k] = 0.0;

@@ -1,7 +1,8 @@
-"""GPU: triquadratic (27-node) hexahedra against the oracle.
+"""GPU: triquadratic (27-node) hexahedra and quadratic (10-node) tetrahedra
+against the oracle.
 
-The operator of the Q2 lattice has up to 125 entries per row and is stored in
-the sliced-ELL format; everything else (ionic step at every node, ICI load,
+The operators of the quadratic lattices (up to 125 entries per row for Q2)
+are stored in the sliced-ELL format; everything else (ionic step at every node, ICI load,
 PCG, activation) is the path of the other elements.  Tolerances as for Q1:
 a single step at rtol 1e-13 to 1e-10 relative, trajectories at rtol 1e-10 to
 1e-8 with activation times to the time step, mixed precision against FP64
@@ -25,8 +26,8 @@ def _rel(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
 
 
-def _spec(dims=(4.0, 2.0, 1.0), h=0.5, model="ttp06", variant="endo", bdf=2, curved=False):
-    mesh = W.slab_q2(*dims, h)
+def _spec(dims=(4.0, 2.0, 1.0), h=0.5, model="ttp06", variant="endo", bdf=2, curved=False, kind="q2"):
+    mesh = (W.slab_q2 if kind == "q2" else W.slab_p2)(*dims, h)
     if curved:
         rng = np.random.default_rng(8)
         mesh.xyz = mesh.xyz + rng.uniform(-0.02, 0.02, mesh.xyz.shape)
@@ -35,11 +36,13 @@ def _spec(dims=(4.0, 2.0, 1.0), h=0.5, model="ttp06", variant="endo", bdf=2, cur
                      1e-10, "t")
 
 
-@pytest.mark.parametrize("model,variant,bdf,curved", [("ttp06", "endo", 2, False), ("bo", "epi", 3, True),
-                                                      ("ap", "", 1, False)])
-def test_q2_single_step(model, variant, bdf, curved):
+@pytest.mark.parametrize("kind,model,variant,bdf,curved", [("q2", "ttp06", "endo", 2, False),
+                                                           ("q2", "bo", "epi", 3, True), ("q2", "ap", "", 1, False),
+                                                           ("p2", "ttp06", "epi", 2, False),
+                                                           ("p2", "bo", "epi", 2, False)])
+def test_quadratic_single_step(kind, model, variant, bdf, curved):
     ep = _ep()
-    spec = _spec(model=model, variant=variant, bdf=bdf, curved=curved)
+    spec = _spec(model=model, variant=variant, bdf=bdf, curved=curved, kind=kind)
     n = spec.mesh.n_nodes
     u, w = W.random_state(model, n, seed=71)
     rng = np.random.default_rng(72)
@@ -60,10 +63,10 @@ def test_q2_single_step(model, variant, bdf, curved):
         assert err < 1e-11, (v, err)
 
 
-@pytest.mark.parametrize("prec", [0, 1])
-def test_q2_trajectory(prec):
+@pytest.mark.parametrize("kind,prec", [("q2", 0), ("q2", 1), ("p2", 0)])
+def test_quadratic_trajectory(kind, prec):
     ep = _ep()
-    spec = _spec(dims=(6.0, 3.0, 1.0), h=0.5)
+    spec = _spec(dims=(6.0, 3.0, 1.0), h=0.5, kind=kind)
     o = OM.from_spec(spec, solver="splu")
     ref = ep.Simulation.from_spec(spec)
     sim = ep.Simulation.from_spec(spec, precision=prec)
@@ -72,7 +75,7 @@ def test_q2_trajectory(prec):
         o.run(steps // 3)
         ref.step(steps // 3)
         sim.step(steps // 3)
-        print(f"q2 trajectory prec={prec}: {(chunk + 1) * steps // 3} steps", flush=True)
+        print(f"{kind} trajectory prec={prec}: {(chunk + 1) * steps // 3} steps", flush=True)
         err = _rel(ref.get_potential(), o.potential_mv())
         assert err < 1e-8, (chunk, err)
     at_o, at_r, at_s = o.activation_times(), ref.get_activation_times(), sim.get_activation_times()

@@ -3,7 +3,7 @@
 - the shared library loads and exports every function include/ep.h declares;
 - the library's C++ finite-element assembly matches the oracle's assembly
   (written independently) on hexahedral (trilinear and triquadratic),
-  tetrahedral and curved LV meshes;
+  tetrahedral (linear and quadratic) and curved LV meshes;
 - invalid input is rejected with a status and a message.
 """
 import ctypes as C
@@ -81,6 +81,11 @@ def test_assembly_matches_oracle_q2_slab():
     rng = np.random.default_rng(6)
     m.xyz = m.xyz + rng.uniform(-0.03, 0.03, m.xyz.shape)   # curved (isoparametric) elements
     _compare(m, W.random_fibers(m.n_nodes, 14))
+
+
+def test_assembly_matches_oracle_p2_slab():
+    m = W.slab_p2(3.0, 2.0, 1.0, 0.5)
+    _compare(m, W.random_fibers(m.n_nodes, 15))
 
 
 def test_invalid_input_is_rejected():
