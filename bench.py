@@ -385,6 +385,9 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=32)
     ap.add_argument("--serve-full", action="store_true",
                     help="the configured trace: 128 requests, 1e4-1e6 nodes, 50-500 ms (long)")
+    ap.add_argument("--no-element-variants", action="store_true",
+                    help="skip the quadratic-element variants (their SELL SpMV launches share the kernel "
+                         "instantiation of the C1 SpMV and would mix into its profile)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 512 MiB five times (counter calibration)")
     args = ap.parse_args()
@@ -442,7 +445,7 @@ def main():
             out[name] = {k: r0[k] for k in ("node_steps_per_s", "ms_per_step", "step_latency_ms_p50",
                                             "step_latency_ms_p99", "launch")}
             print(f"[bench] {name}: {r0['node_steps_per_s']:.4g} node-steps/s", file=sys.stderr, flush=True)
-        if args.workload == "c1":
+        if args.workload == "c1" and not args.no_element_variants:
             # triquadratic elements on the same node lattice (element size 0.2 mm:
             # 100 x 35 x 15 elements, 201 x 71 x 31 nodes), operator in sliced ELL
             # and quadratic tetrahedra (each cell Kuhn-split) on the same lattice
