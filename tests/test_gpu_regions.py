@@ -164,3 +164,44 @@ def test_region_errors():
         pool.admit(s, 10)
     pool.close()
     s.close()
+
+
+def test_ventricle_shell_with_scar_and_border_zone():
+    """Tetrahedral LV shell (BO model): a non-conductive scar through the
+    wall, a border zone around it with slower conduction and a shorter
+    tau_so1, healthy tissue elsewhere (the paper's pathological-ventricle
+    setup in miniature, on a generated shell).  Trajectory parity with the
+    multi-subdomain oracle; removed nodes NaN on both sides."""
+    ep = _ep()
+    mesh, fib, endo = W.lv_shell(5, 48, 20)
+    # a wide, strong Gaussian: this coarse shell (about 2.6 mm elements
+    # around the circumference) needs it to start a front
+    st = [W.Stimulus(W.GAUSS, tuple(mesh.xyz[endo[7]]), 5.0, 200.0, 0.0, 2.0, 0.0)]
+    spec = W.SimSpec(mesh, fib, W.Physics(0.17, 0.0425, 0.0425), "bo", "epi", st, 0.05, 2, 1, 1e-10, "t")
+    c = W.element_centroids(mesh)
+    ang = np.arctan2(c[:, 1], c[:, 0])
+    zc = c[:, 2]
+    mat = np.zeros(mesh.n_elems, np.int32)
+    mat[(np.abs(ang - 1.0) < 0.45) & (zc < -12.0) & (zc > -28.0)] = 1      # border zone
+    mat[(np.abs(ang - 1.0) < 0.25) & (zc < -15.0) & (zc > -25.0)] = 2      # scar
+    assert (mat == 1).sum() > 50 and (mat == 2).sum() > 20
+    bz_params = [0.0, 1.55, 0.3, 0.13, 0.006, 0.006, 60.0, 1150.0, 1.4506, 60.0, 15.0, 65.0, 0.03, 200.0,
+                 0.11, 400.0, 6.0, 20.0]              # BO EPI with tau_so1 30.0181 -> 20
+    o = R.from_spec(spec, mat, [R.Region(), R.Region(params={"tau_so1": 20.0}, sigma=(0.08, 0.02, 0.02)),
+                                R.Region(conductive=False)], solver="splu")
+    sim = ep.Simulation.from_spec(spec, material=mat, regions={
+        1: dict(params=bz_params, sigma=(0.08, 0.02, 0.02)), 2: dict(conductive=False)})
+    for chunk in range(2):
+        o.run(150)
+        sim.step(150)
+        err = _rel(sim.get_potential(), o.potential_mv())
+        print(f"ventricle scar: {(chunk + 1) * 150} steps, rel {err:.2e}", flush=True)
+        assert err < 1e-8, (chunk, err)
+    u = sim.get_potential()
+    assert np.array_equal(np.isnan(u), np.isnan(o.potential_mv()))
+    assert np.isnan(u).sum() > 0
+    at_o, at_g = o.activation_times(), sim.get_activation_times()
+    ok = ~np.isnan(at_o)
+    assert ok.sum() > 100 and np.array_equal(ok, ~np.isnan(at_g))
+    assert np.max(np.abs(at_o[ok] - at_g[ok])) <= spec.dt + 1e-9
+    sim.close()
