@@ -59,8 +59,9 @@ def test_assembly_matches_oracle_q1_slab():
     _compare(m, W.random_fibers(m.n_nodes, 11))
 
 
-def test_assembly_matches_oracle_p1_slab():
-    m = W.slab_p1(3.0, 2.0, 1.5, 0.5)
+@pytest.mark.parametrize("split", ["kuhn", "mirrored"])
+def test_assembly_matches_oracle_p1_slab(split):
+    m = W.slab_p1(3.0, 2.0, 1.5, 0.5, split=split)
     _compare(m, W.random_fibers(m.n_nodes, 12))
 
 

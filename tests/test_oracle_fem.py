@@ -159,6 +159,33 @@ def test_kuhn_lattice_p1_is_seven_point_stencil():
     assert abs(M.sum() - 8.0) < 1e-12
 
 
+def test_mirrored_kuhn_lattice_is_valid():
+    """The mirrored split (input generator) is a conforming, positively
+    oriented tetrahedral mesh of the slab whose long edges run along all four
+    body diagonals equally; its P1 operators keep K 1 = 0 and 1^T M 1 = |slab|."""
+    h = 0.25
+    m = W.slab_p1(2.0, 1.5, 1.0, h, split="mirrored")
+    X = m.xyz[m.conn]
+    vol = np.einsum("ij,ij->i", np.cross(X[:, 1] - X[:, 0], X[:, 2] - X[:, 0]), X[:, 3] - X[:, 0]) / 6
+    assert vol.min() > 0 and abs(vol.sum() - 3.0) < 1e-12
+    faces = np.sort(np.concatenate([m.conn[:, [0, 1, 2]], m.conn[:, [0, 1, 3]],
+                                    m.conn[:, [0, 2, 3]], m.conn[:, [1, 2, 3]]]), axis=1)
+    _, cnt = np.unique(faces, axis=0, return_counts=True)
+    nx, ny, nz = m.dims
+    assert cnt.max() == 2
+    assert (cnt == 1).sum() == 4 * ((nx - 1) * (ny - 1) + (ny - 1) * (nz - 1) + (nx - 1) * (nz - 1))
+    e = np.concatenate([m.conn[:, [a, b]] for a in range(4) for b in range(a + 1, 4)])
+    dv = m.xyz[e[:, 1]] - m.xyz[e[:, 0]]
+    body = np.all(np.abs(np.abs(dv) - h) < 1e-12, axis=1)
+    sgn = np.sign(dv[body]) * np.sign(dv[body][:, :1])
+    dirs, num = np.unique(sgn, axis=0, return_counts=True)
+    assert dirs.shape[0] == 4 and num.min() == num.max()
+    f, s, n = W.uniform_fibers(m.n_nodes)
+    M, K = fem.assemble(m.xyz, m.conn, fem.nodal_diffusion(f, s, n, 0.9, 0.5, 0.3, 1.0, 1.0))
+    assert np.max(np.abs(K @ np.ones(m.n_nodes))) < 1e-13
+    assert abs(M.sum() - 3.0) < 1e-12
+
+
 def test_lv_shell_mesh_is_valid():
     m, (f, s, n), endo = W.lv_shell(4, 24, 10)
     X = m.xyz[m.conn]

@@ -143,13 +143,29 @@ def _orient_tets(xyz: np.ndarray, tets: np.ndarray) -> np.ndarray:
     return tets
 
 
-def slab_p1(Lx: float, Ly: float, Lz: float, h: float, label: str = "") -> Mesh:
-    """Structured P1 tetrahedral slab: the Q1 lattice with each cell Kuhn-split."""
+def slab_p1(Lx: float, Ly: float, Lz: float, h: float, label: str = "", split: str = "kuhn") -> Mesh:
+    """Structured P1 tetrahedral slab: the Q1 lattice with each cell Kuhn-split.
+
+    split "kuhn": every cell split the same way, so every long diagonal runs
+    along (1, 1, 1).  split "mirrored": the split of a cell is reflected
+    across each axis along which the cell's index is odd, so neighbouring
+    cells use different body diagonals (no preferred direction on the scale of
+    two cells, closer to an unstructured mesh).  Both are conforming: a face
+    between two cells is cut along the same diagonal from both sides.
+    """
     q = slab_q1(Lx, Ly, Lz, h)
     nx, ny, nz = q.dims
     base = _lattice_cells(nx, ny, nz)
     corner = _cell_corner_offsets(nx, ny)
-    tets = (base[:, None, None] + corner[_KUHN][None, :, :]).reshape(-1, 4)
+    if split == "kuhn":
+        local = _KUHN[None, :, :]
+    elif split == "mirrored":
+        # reflecting across axis a maps corner index bit a to its complement
+        flip = (base % nx & 1) + 2 * (base // nx % ny & 1) + 4 * (base // (nx * ny) & 1)
+        local = _KUHN[None, :, :] ^ flip[:, None, None]
+    else:
+        raise ValueError(f"unknown split {split!r}")
+    tets = (base[:, None, None] + corner[local]).reshape(-1, 4)
     tets = _orient_tets(q.xyz, tets).astype(np.int32)
     return Mesh(q.xyz, np.ascontiguousarray(tets), (nx, ny, nz), label)
 
