@@ -6,6 +6,7 @@ phi_k phi_j over the domain, K_jk the integral of D grad(phi_k) . grad(phi_j),
 with Gauss quadrature of the fewest points that integrate M exactly:
 2x2x2 Gauss-Legendre points for trilinear hexahedra (Q1), 3x3x3 for
 triquadratic hexahedra (Q2, the paper's higher-order hexahedral elements),
+4x4x4 for tricubic hexahedra (Q3),
 the symmetric 4-point degree-2 rule for linear tetrahedra (P1), and a
 64-point conical product rule (exact to degree 5) for quadratic tetrahedra
 (P2, the paper's higher-order tetrahedral elements).
@@ -148,6 +149,74 @@ def q2_element_matrices(X, Dn):
     return Me, Ke
 
 
+def _lagrange3(t):
+    """Cubic Lagrange basis on [-1, 1] with the equispaced nodes -1, -1/3,
+    1/3, 1: values and derivatives, each [4], from the product formula."""
+    nodes = np.array([-1.0, -1.0 / 3.0, 1.0 / 3.0, 1.0])
+    v = np.ones(4)
+    d = np.zeros(4)
+    for j in range(4):
+        others = [m for m in range(4) if m != j]
+        for m in others:
+            v[j] *= (t - nodes[m]) / (nodes[j] - nodes[m])
+        for k in others:
+            term = 1.0 / (nodes[j] - nodes[k])
+            for m in others:
+                if m != k:
+                    term *= (t - nodes[m]) / (nodes[j] - nodes[m])
+            d[j] += term
+    return v, d
+
+
+def _q3_reference():
+    """Shape values [q, 64] and reference gradients [q, 64, 3] at the 4x4x4
+    Gauss points of [-1, 1]^3, and the weights.  Local node k = a + 4b + 16c
+    sits at the reference point (2a/3 - 1, 2b/3 - 1, 2c/3 - 1)."""
+    x1, w1 = np.polynomial.legendre.leggauss(4)
+    N = np.zeros((64, 64))
+    dN = np.zeros((64, 64, 3))
+    wts = np.zeros(64)
+    q = 0
+    for iz in range(4):
+        for iy in range(4):
+            for ix in range(4):
+                vx, dx = _lagrange3(x1[ix])
+                vy, dy = _lagrange3(x1[iy])
+                vz, dz = _lagrange3(x1[iz])
+                wts[q] = w1[ix] * w1[iy] * w1[iz]
+                for c in range(4):
+                    for b in range(4):
+                        for a in range(4):
+                            k = a + 4 * b + 16 * c
+                            N[q, k] = vx[a] * vy[b] * vz[c]
+                            dN[q, k] = (dx[a] * vy[b] * vz[c], vx[a] * dy[b] * vz[c], vx[a] * vy[b] * dz[c])
+                q += 1
+    return N, dN, wts
+
+
+def q3_element_matrices(X, Dn):
+    """Element mass and stiffness for a batch of tricubic hexahedra
+    (isoparametric, 64 nodes in the order k = a + 4b + 16c; the paper's
+    hexahedral Q_p spaces with p = 3).
+
+    X  : [E, 64, 3]; Dn : [E, 64, 3, 3]; returns Me, Ke [E, 64, 64]
+    """
+    N, dN, w = _q3_reference()
+    E = X.shape[0]
+    Me = np.zeros((E, 64, 64))
+    Ke = np.zeros((E, 64, 64))
+    for q in range(N.shape[0]):
+        J = np.einsum("ki,ekj->eij", dN[q], X)
+        detJ = np.linalg.det(J)
+        Jinv = np.linalg.inv(J)
+        G = np.einsum("eij,kj->eki", Jinv, dN[q])
+        Dq = np.einsum("k,ekij->eij", N[q], Dn)
+        wq = w[q] * detJ
+        Me += wq[:, None, None] * np.outer(N[q], N[q])[None]
+        Ke += wq[:, None, None] * np.einsum("eai,eij,ebj->eab", G, Dq, G)
+    return Me, Ke
+
+
 # ---------------------------------------------------------------------------
 # P1 tetrahedra
 # ---------------------------------------------------------------------------
@@ -272,7 +341,9 @@ def assemble(xyz, conn, Dnodal, chunk: int = 200000):
         c = conn[e0:e0 + chunk]
         X = xyz[c]
         Dn = Dnodal[c]
-        if npe == 27:
+        if npe == 64:
+            Me, Ke = q3_element_matrices(X, Dn)
+        elif npe == 27:
             Me, Ke = q2_element_matrices(X, Dn)
         elif npe == 10:
             Me, Ke = p2_element_matrices(X, Dn)

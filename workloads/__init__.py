@@ -118,6 +118,22 @@ def slab_q2(Lx: float, Ly: float, Lz: float, h: float, label: str = "") -> Mesh:
     return Mesh(xyz, conn, (nx, ny, nz), label or f"slab-q2-{Lx}x{Ly}x{Lz}-h{h}")
 
 
+def slab_q3(Lx: float, Ly: float, Lz: float, h: float, label: str = "") -> Mesh:
+    """Structured tricubic (64-node) hexahedral mesh of [0,Lx]x[0,Ly]x[0,Lz]
+    with element size ~h: nodes on the lattice of spacing h/3, element-local
+    node k = a + 4b + 16c at the element's lattice point (a, b, c)."""
+    cx = int(round(Lx / h))
+    cy = int(round(Ly / h))
+    cz = int(round(Lz / h))
+    nx, ny, nz = 3 * cx + 1, 3 * cy + 1, 3 * cz + 1
+    xyz = _lattice_xyz(nx, ny, nz, Lx / (nx - 1), Ly / (ny - 1), Lz / (nz - 1))
+    ex, ey, ez = np.meshgrid(np.arange(cx), np.arange(cy), np.arange(cz), indexing="ij")
+    base = (3 * ex + nx * (3 * ey + ny * 3 * ez)).transpose(2, 1, 0).ravel()
+    loc = np.array([a + nx * (b + ny * c) for c in range(4) for b in range(4) for a in range(4)])
+    conn = (base[:, None] + loc[None, :]).astype(np.int32)
+    return Mesh(xyz, conn, (nx, ny, nz), label or f"slab-q3-{Lx}x{Ly}x{Lz}-h{h}")
+
+
 def lattice_q1(nx: int, ny: int, nz: int, hx: float, hy: float, hz: float,
                label: str = "") -> Mesh:
     xyz = _lattice_xyz(nx, ny, nz, hx, hy, hz)
