@@ -447,10 +447,16 @@ def main():
             print(f"[bench] {name}: {r0['node_steps_per_s']:.4g} node-steps/s", file=sys.stderr, flush=True)
         if args.workload == "c1" and not args.no_element_variants:
             # triquadratic elements on the same node lattice (element size 0.2 mm:
-            # 100 x 35 x 15 elements, 201 x 71 x 31 nodes), operator in sliced ELL
-            # and quadratic tetrahedra (each cell Kuhn-split) on the same lattice
-            for name, gen in (("fp64_q2_elements_same_nodes", W.slab_q2), ("fp64_p2_elements_same_nodes", W.slab_p2)):
-                hi = W.SimSpec(gen(20.0, 7.0, 3.0, 0.2), spec.fibers, spec.phys, spec.model, spec.variant,
+            # 100 x 35 x 15 elements, 201 x 71 x 31 nodes), operator in sliced ELL,
+            # quadratic tetrahedra (each cell Kuhn-split) on the same lattice, and
+            # tricubic elements of 0.3 mm (67 x 23 x 10 elements, 202 x 70 x 31
+            # nodes: the C1 node count within 1 %)
+            for name, gen, h in (("fp64_q2_elements_same_nodes", W.slab_q2, 0.2),
+                                 ("fp64_p2_elements_same_nodes", W.slab_p2, 0.2),
+                                 ("fp64_q3_elements_438k_nodes", W.slab_q3, 0.3)):
+                mesh = gen(20.0, 7.0, 3.0, h)
+                fib = spec.fibers if mesh.n_nodes == spec.mesh.n_nodes else W.uniform_fibers(mesh.n_nodes)
+                hi = W.SimSpec(mesh, fib, spec.phys, spec.model, spec.variant,
                                spec.stimuli, spec.dt, spec.bdf, spec.n_steps, spec.rtol, name)
                 r0, _, _ = run_gpu(hi, ep.EP_FP64, args.steps, args.warmup, 0, bool(args.graph), bool(args.autotune))
                 out[name] = {k: r0[k] for k in (

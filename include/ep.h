@@ -56,7 +56,7 @@ typedef enum {
   EP_ESTATE = -7    /* call not valid in the object's current state          */
 } ep_status;
 
-enum { EP_TET4 = 4, EP_TET10 = 10, EP_HEX8 = 8, EP_HEX27 = 27 };     /* element types   */
+enum { EP_TET4 = 4, EP_TET10 = 10, EP_HEX8 = 8, EP_HEX27 = 27, EP_HEX64 = 64 };  /* element types */
 enum { EP_PASSIVE = 0, EP_AP = 1, EP_BO = 2, EP_TTP06 = 3 };          /* ionic models    */
 enum { EP_CELL_EPI = 0, EP_CELL_ENDO = 1, EP_CELL_MID = 2 };          /* TTP06 variants  */
 enum { EP_CUBE = 0, EP_SPHERE = 1, EP_GAUSS = 2 };                    /* stimulus shapes */
@@ -132,8 +132,9 @@ ep_status ep_sim_create(int device, void* hip_stream, ep_sim** out);
 /* Mesh (paper: tetrahedral or hexahedral conforming mesh).  xyz: [n_nodes][3]
  * coordinates in mm; conn: [n_elems][elem] node indices, hexahedra in
  * lexicographic corner order (corner a + 2b + 4c at reference (a, b, c)).
- * EP_HEX27: triquadratic hexahedra (paper: the higher-order hexahedral Q_p
- * spaces, here p = 2), node a + 3b + 9c at reference (a/2, b/2, c/2).
+ * EP_HEX27 / EP_HEX64: triquadratic / tricubic hexahedra (paper: the
+ * higher-order hexahedral Q_p spaces, here p = 2 and 3), node a + 3b + 9c at
+ * reference (a/2, b/2, c/2), resp. a + 4b + 16c at (a/3, b/3, c/3).
  * EP_TET10: quadratic tetrahedra (paper: P2), straight-sided, vertices 0-3
  * then the midpoints of the edges 01, 02, 03, 12, 13, 23.  Quadratic
  * elements' operators are stored in the sliced-ELL format.

@@ -328,7 +328,8 @@ double stim_profile(const Stim& t, const double* x) {
 
 size_t estimate_bytes(const ep_sim* s) {
   const int64_t n = s->n;
-  const double nnz_row = (s->elem == EP_HEX27) ? 64.0 : (s->elem == EP_TET10) ? 40.0 : (s->elem == EP_HEX8) ? 27.0 : 16.0;
+  const double nnz_row = (s->elem == EP_HEX64) ? 125.0 : (s->elem == EP_HEX27) ? 64.0
+                         : (s->elem == EP_TET10) ? 40.0 : (s->elem == EP_HEX8) ? 27.0 : 16.0;
   const bool mixed = s->prec == EP_MIXED;
   const ModelInfo mi = model_info(s->model);
   double per_node = 11 * 8.0 + 24.0;                            // FP64 vectors, activation
@@ -1128,8 +1129,8 @@ ep_status ep_sim_upload_mesh(ep_sim* s, int elem, int64_t n_nodes, const double*
                              const int32_t* conn, const int32_t* material_id) {
   if (check_sim(s)) return EP_EINVAL;
   if (s->finalized) return fail(EP_ESTATE, "sim already finalized");
-  if (elem != EP_HEX8 && elem != EP_TET4 && elem != EP_HEX27 && elem != EP_TET10)
-    return fail(EP_EINVAL, "elem must be EP_HEX8, EP_HEX27, EP_TET4 or EP_TET10");
+  if (elem != EP_HEX8 && elem != EP_TET4 && elem != EP_HEX27 && elem != EP_HEX64 && elem != EP_TET10)
+    return fail(EP_EINVAL, "elem must be EP_HEX8, EP_HEX27, EP_HEX64, EP_TET4 or EP_TET10");
   if (n_nodes <= 0 || n_elems <= 0 || !xyz || !conn) return fail(EP_EINVAL, "empty mesh");
   if (n_nodes >= (int64_t)INT32_MAX) return fail(EP_EINVAL, "too many nodes");
   if (material_id)

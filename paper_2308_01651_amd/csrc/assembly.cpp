@@ -161,6 +161,88 @@ bool hex27_element(const double X[27][3], const double Dn[27][9], double* Me, do
   return true;
 }
 
+// Tricubic hexahedron (64 nodes), local node k = a + 4b + 16c at the
+// reference point (2a/3 - 1, 2b/3 - 1, 2c/3 - 1); isoparametric map; 4x4x4
+// Gauss-Legendre quadrature (exact for the mass matrix of an affine element).
+bool hex64_element(const double X[64][3], const double Dn[64][9], double* Me, double* Ke) {
+  static const double gp[4] = {-0.86113631159405257522, -0.33998104358485626480, 0.33998104358485626480,
+                               0.86113631159405257522};
+  static const double gw[4] = {0.34785484513745385737, 0.65214515486254614263, 0.65214515486254614263,
+                               0.34785484513745385737};
+  std::memset(Me, 0, 64 * 64 * sizeof(double));
+  std::memset(Ke, 0, 64 * 64 * sizeof(double));
+  // 1-D cubic Lagrange factors at the nodes -1, -1/3, 1/3, 1 (product form;
+  // the derivative accumulates by the product rule)
+  auto lag = [](double t, double v[4], double d[4]) {
+    static const double z[4] = {-1.0, -1.0 / 3.0, 1.0 / 3.0, 1.0};
+    for (int j = 0; j < 4; j++) {
+      double val = 1.0, der = 0.0;
+      for (int m = 0; m < 4; m++) {
+        if (m == j) continue;
+        const double f = (t - z[m]) / (z[j] - z[m]);
+        der = der * f + val / (z[j] - z[m]);
+        val *= f;
+      }
+      v[j] = val;
+      d[j] = der;
+    }
+  };
+  for (int qz = 0; qz < 4; qz++)
+    for (int qy = 0; qy < 4; qy++)
+      for (int qx = 0; qx < 4; qx++) {
+        double vx[4], dx[4], vy[4], dy[4], vz[4], dz[4];
+        lag(gp[qx], vx, dx);
+        lag(gp[qy], vy, dy);
+        lag(gp[qz], vz, dz);
+        double N[64], dN[64][3];
+        for (int c = 0; c < 4; c++)
+          for (int b = 0; b < 4; b++)
+            for (int a = 0; a < 4; a++) {
+              const int k = a + 4 * b + 16 * c;
+              N[k] = vx[a] * vy[b] * vz[c];
+              dN[k][0] = dx[a] * vy[b] * vz[c];
+              dN[k][1] = vx[a] * dy[b] * vz[c];
+              dN[k][2] = vx[a] * vy[b] * dz[c];
+            }
+        double J[3][3] = {{0}};
+        for (int k = 0; k < 64; k++)
+          for (int r = 0; r < 3; r++)
+            for (int c = 0; c < 3; c++) J[r][c] += dN[k][r] * X[k][c];
+        const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                           J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                           J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+        if (!(det > 0.0)) return false;
+        double Ji[3][3];
+        Ji[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
+        Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+        Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+        Ji[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;
+        Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+        Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+        Ji[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / det;
+        Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+        Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+        double G[64][3];
+        for (int k = 0; k < 64; k++)
+          for (int r = 0; r < 3; r++)
+            G[k][r] = Ji[r][0] * dN[k][0] + Ji[r][1] * dN[k][1] + Ji[r][2] * dN[k][2];
+        double Dq[9] = {0};
+        for (int k = 0; k < 64; k++)
+          for (int e = 0; e < 9; e++) Dq[e] += N[k] * Dn[k][e];
+        double DG[64][3];
+        for (int k = 0; k < 64; k++)
+          for (int r = 0; r < 3; r++)
+            DG[k][r] = Dq[3 * r] * G[k][0] + Dq[3 * r + 1] * G[k][1] + Dq[3 * r + 2] * G[k][2];
+        const double w = gw[qx] * gw[qy] * gw[qz] * det;
+        for (int a = 0; a < 64; a++)
+          for (int b = 0; b < 64; b++) {
+            Me[64 * a + b] += w * N[a] * N[b];
+            Ke[64 * a + b] += w * (G[a][0] * DG[b][0] + G[a][1] * DG[b][1] + G[a][2] * DG[b][2]);
+          }
+      }
+  return true;
+}
+
 // Quadratic tetrahedron (10 nodes: vertices 0-3, then the midpoints of the
 // edges 01, 02, 03, 12, 13, 23), straight-sided (affine map of the
 // vertices).  Quadrature: the conical product of 4-point Gauss-Legendre rules
@@ -280,8 +362,9 @@ bool assemble_csr(int elem, int64_t n_nodes, const double* xyz, int64_t n_elems,
                   double sigma_l, double sigma_t, double sigma_n, double chi, double cm, Csr& A,
                   std::vector<char>& err, const int32_t* region, const double* region_sigma,
                   const unsigned char* region_on) {
-  if (elem != 8 && elem != 4 && elem != 27 && elem != 10) {
-    set_err(err, "element type must be 8 (hex), 27 (triquadratic hex), 4 (tet) or 10 (quadratic tet)");
+  if (elem != 8 && elem != 4 && elem != 27 && elem != 64 && elem != 10) {
+    set_err(err, "element type must be 8 (hex), 27 (triquadratic hex), 64 (tricubic hex), 4 (tet) or 10 "
+                 "(quadratic tet)");
     return false;
   }
   if (n_nodes <= 0 || n_elems <= 0) { set_err(err, "empty mesh"); return false; }
@@ -308,7 +391,7 @@ bool assemble_csr(int elem, int64_t n_nodes, const double* xyz, int64_t n_elems,
   std::vector<char> bad(1, 0);
   static const double ex[3] = {1, 0, 0}, ey[3] = {0, 1, 0}, ez[3] = {0, 0, 1};
   parallel_for(n_elems, [&](int64_t e) {
-    double X[27][3], Dn[27][9];
+    double X[64][3], Dn[64][9];
     const int r = region ? region[e] : 0;
     const double sl = region ? region_sigma[3 * r] : sigma_l;
     const double st = region ? region_sigma[3 * r + 1] : sigma_t;
@@ -321,7 +404,8 @@ bool assemble_csr(int elem, int64_t n_nodes, const double* xyz, int64_t n_elems,
       const double* nn = n0 ? n0 + 3 * v : ez;
       nodal_tensor(f, s, nn, sl, st, sn, scale, Dn[k]);
     }
-    bool ok = (npe == 27)  ? hex27_element(X, Dn, &Me[e * 27 * 27], &Ke[e * 27 * 27])
+    bool ok = (npe == 64)  ? hex64_element(X, Dn, &Me[e * 64 * 64], &Ke[e * 64 * 64])
+              : (npe == 27) ? hex27_element(X, Dn, &Me[e * 27 * 27], &Ke[e * 27 * 27])
               : (npe == 10) ? tet10_element(X, Dn, &Me[e * 100], &Ke[e * 100])
               : (npe == 8)  ? hex_element(X, Dn, &Me[e * 64], &Ke[e * 64])
                             : tet_element(X, Dn, &Me[e * 16], &Ke[e * 16]);

@@ -18,7 +18,9 @@ struct Csr {
 // Assemble M_jk = int phi_k phi_j and K_jk = int D grad phi_k . grad phi_j with
 // D = (sigma_l f f^T + sigma_t s s^T + sigma_n n n^T)/(chi C_m) given at the
 // nodes and interpolated with the FE basis.  elem = 8 (trilinear hexahedra,
-// 2x2x2 Gauss points) or 4 (linear tetrahedra, closed form).
+// 2x2x2 Gauss points), 27 (triquadratic hexahedra, 3x3x3), 64 (tricubic
+// hexahedra, 4x4x4), 4 (linear tetrahedra, closed form) or 10 (quadratic
+// tetrahedra, 64-point conical product rule).
 // fibers may be null (then f = e_x, s = e_y, n = e_z everywhere).
 // Several subdomains: region (per element, nullable) selects the element's
 // conductivities region_sigma[3 r .. 3 r + 2]; an element of a region with

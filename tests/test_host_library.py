@@ -84,6 +84,13 @@ def test_assembly_matches_oracle_q2_slab():
     _compare(m, W.random_fibers(m.n_nodes, 14))
 
 
+def test_assembly_matches_oracle_q3_slab():
+    m = W.slab_q3(2.0, 1.0, 1.0, 0.5)
+    rng = np.random.default_rng(16)
+    m.xyz = m.xyz + rng.uniform(-0.02, 0.02, m.xyz.shape)   # curved (isoparametric) elements
+    _compare(m, W.random_fibers(m.n_nodes, 17))
+
+
 def test_assembly_matches_oracle_p2_slab():
     m = W.slab_p2(3.0, 2.0, 1.0, 0.5)
     _compare(m, W.random_fibers(m.n_nodes, 15))
