@@ -9,7 +9,8 @@ triquadratic hexahedra (Q2, the paper's higher-order hexahedral elements),
 4x4x4 for tricubic hexahedra (Q3),
 the symmetric 4-point degree-2 rule for linear tetrahedra (P1), and a
 64-point conical product rule (exact to degree 5) for quadratic tetrahedra
-(P2, the paper's higher-order tetrahedral elements).
+(P2, the paper's higher-order tetrahedral elements, isoparametric like the
+hexahedra).
 
 The diffusion tensor is the one of the monodomain model (eq. of the diffusion
 tensor): D = sigma_l f f^T + sigma_t s s^T + sigma_n n n^T, rescaled by
@@ -301,26 +302,29 @@ def _p2_basis(L):
 
 
 def p2_element_matrices(X, Dn):
-    """Element mass and stiffness for a batch of straight-sided quadratic
-    tetrahedra (geometry from the four vertices).
+    """Element mass and stiffness for a batch of isoparametric quadratic
+    tetrahedra: the geometry is interpolated with the same 10-node basis, so
+    an element whose midside nodes sit off its edge midpoints is integrated on
+    its curved shape (for straight-sided elements the map is affine).
 
     X  : [E, 10, 3]; Dn : [E, 10, 3, 3]; returns Me, Ke [E, 10, 10]
     """
     E = X.shape[0]
-    T = np.stack([X[:, 1] - X[:, 0], X[:, 2] - X[:, 0], X[:, 3] - X[:, 0]], axis=1)
-    vol = np.abs(np.linalg.det(T)) / 6.0
-    Tinv = np.linalg.inv(T)
-    GL = np.zeros((E, 4, 3))                      # gradients of the barycentric coordinates
-    GL[:, 1:, :] = np.transpose(Tinv, (0, 2, 1))
-    GL[:, 0, :] = -GL[:, 1:, :].sum(axis=1)
+    # derivatives of the barycentric coordinates with respect to the three
+    # independent reference coordinates (l1, l2, l3), l0 = 1 - l1 - l2 - l3
+    dl = np.array([[-1.0, -1.0, -1.0], [1.0, 0.0, 0.0], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0]])
     Lq, wq = _collapsed_tet_rule(4)
     Me = np.zeros((E, 10, 10))
     Ke = np.zeros((E, 10, 10))
     for q in range(Lq.shape[0]):
         N, dL = _p2_basis(Lq[q])
-        G = np.einsum("kl,elc->ekc", dL, GL)      # physical gradients [E, 10, 3]
+        dN = dL @ dl                                  # reference gradients [10, 3]
+        J = np.einsum("kr,ekc->erc", dN, X)           # J[e, r, c] = d x_c / d l_r
+        detJ = np.linalg.det(J)
+        Jinv = np.linalg.inv(J)
+        G = np.einsum("ecr,kr->ekc", Jinv, dN)        # physical gradients [E, 10, 3]
         Dq = np.einsum("k,ekij->eij", N, Dn)
-        w = wq[q] * vol
+        w = wq[q] / 6.0 * np.abs(detJ)                # the reference tetrahedron has volume 1/6
         Me += w[:, None, None] * np.outer(N, N)[None]
         Ke += w[:, None, None] * np.einsum("eai,eij,ebj->eab", G, Dq, G)
     return Me, Ke

@@ -259,6 +259,31 @@ def test_q2_eigenvalue_converges_at_fourth_order():
     assert 3.7 < rate < 4.3, (errs, rate)
 
 
+def test_p2_curved_elements_are_isoparametric():
+    """Quadratic tetrahedra whose interior nodes (midside nodes included)
+    are moved off the lattice are curved; the domain is still the box.  The
+    isoparametric space contains the linear fields of physical space, so
+    1^T M 1 = |box|, int x dx = |box| * centroid, and the energy of linear
+    fields a.x, b.x is a^T D b |box| exactly.  Geometry taken from the four
+    vertices alone (midside nodes ignored) fails the last two."""
+    m = W.slab_p2(2.0, 1.0, 1.0, 0.5)
+    lo, hi = m.xyz.min(axis=0), m.xyz.max(axis=0)
+    interior = np.all((m.xyz > lo + 1e-9) & (m.xyz < hi - 1e-9), axis=1)
+    rng = np.random.default_rng(21)
+    xyz = m.xyz.copy()
+    xyz[interior] += rng.uniform(-0.05, 0.05, (interior.sum(), 3))
+    D = np.array([[2.0, 0.3, 0.1], [0.3, 1.0, 0.2], [0.1, 0.2, 0.5]])
+    M, K = fem.assemble(xyz, m.conn, np.broadcast_to(D, (m.n_nodes, 3, 3)).copy())
+    vol = 2.0
+    one = np.ones(m.n_nodes)
+    assert abs(one @ M @ one - vol) < 1e-12
+    centroid = np.array([1.0, 0.5, 0.5])
+    assert np.max(np.abs(xyz.T @ (M @ one) - vol * centroid)) < 1e-12
+    a, b = np.array([0.7, -1.1, 0.4]), np.array([-0.2, 0.5, 1.3])
+    assert abs((xyz @ a) @ K @ (xyz @ b) - a @ D @ b * vol) < 1e-11
+    assert np.abs(K @ one).max() < 1e-12
+
+
 # ---------------------------------------------------------------------------
 # Q3 (64-node) hexahedra
 # ---------------------------------------------------------------------------
