@@ -135,9 +135,11 @@ ep_status ep_sim_create(int device, void* hip_stream, ep_sim** out);
  * EP_HEX27 / EP_HEX64: triquadratic / tricubic hexahedra (paper: the
  * higher-order hexahedral Q_p spaces, here p = 2 and 3), node a + 3b + 9c at
  * reference (a/2, b/2, c/2), resp. a + 4b + 16c at (a/3, b/3, c/3).
- * EP_TET10: quadratic tetrahedra (paper: P2), straight-sided, vertices 0-3
- * then the midpoints of the edges 01, 02, 03, 12, 13, 23.  Quadratic
- * elements' operators are stored in the sliced-ELL format.
+ * EP_TET10: quadratic tetrahedra (paper: P2), vertices 0-3 then the nodes of
+ * the edges 01, 02, 03, 12, 13, 23.  All higher-order elements are
+ * isoparametric: edge nodes off the edge midpoints make a curved element;
+ * finalize rejects (EP_EINVAL) an element whose map folds over.
+ * Higher-order elements' operators are stored in the sliced-ELL format.
  * material_id: NULL (one subdomain) or [n_elems] subdomain labels 0 ..
  * EP_MAX_REGIONS - 1 (paper: Material IDs of the mesh's volumes; see
  * ep_sim_set_region).  EP_EINVAL on bad sizes or out-of-range indices or

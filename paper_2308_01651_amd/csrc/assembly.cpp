@@ -243,40 +243,30 @@ bool hex64_element(const double X[64][3], const double Dn[64][9], double* Me, do
   return true;
 }
 
-// Quadratic tetrahedron (10 nodes: vertices 0-3, then the midpoints of the
-// edges 01, 02, 03, 12, 13, 23), straight-sided (affine map of the
-// vertices).  Quadrature: the conical product of 4-point Gauss-Legendre rules
-// on the unit cube collapsed onto the tetrahedron (64 points, exact to
-// degree 5 in the barycentric coordinates).
+// Quadratic tetrahedron (10 nodes: vertices 0-3, then the nodes of the edges
+// 01, 02, 03, 12, 13, 23), isoparametric: the map from the reference
+// tetrahedron uses all ten nodes, so an element whose edge nodes sit off the
+// edge midpoints is curved (straight-sided elements give an affine map).
+// Quadrature: the conical product of 4-point Gauss-Legendre rules on the
+// unit cube collapsed onto the tetrahedron (64 points, exact to degree 5 in
+// the barycentric coordinates).  The Jacobian determinant must keep the
+// sign of the vertex orientation at every point (no folded element).
 bool tet10_element(const double X[10][3], const double Dn[10][9], double* Me, double* Ke) {
   static const double gx[4] = {0.06943184420297371, 0.33000947820757187, 0.66999052179242813,
                                0.93056815579702629};  // Gauss-Legendre nodes on [0, 1]
   static const double gw[4] = {0.17392742256872693, 0.32607257743127307, 0.32607257743127307,
                                0.17392742256872693};
   static const int edge[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+  // d L_a / d l_r for the independent reference coordinates l_1, l_2, l_3
+  static const double dl[4][3] = {{-1, -1, -1}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
   double E[3][3];
   for (int r = 0; r < 3; r++)
     for (int c = 0; c < 3; c++) E[r][c] = X[r + 1][c] - X[0][c];
-  const double det = E[0][0] * (E[1][1] * E[2][2] - E[1][2] * E[2][1]) -
-                     E[0][1] * (E[1][0] * E[2][2] - E[1][2] * E[2][0]) +
-                     E[0][2] * (E[1][0] * E[2][1] - E[1][1] * E[2][0]);
-  if (det == 0.0 || !std::isfinite(det)) return false;
-  const double vol = std::fabs(det) / 6.0;
-  // gradient of barycentric coordinate L_{r+1} = column r of E^{-1}
-  double Ei[3][3];
-  Ei[0][0] = (E[1][1] * E[2][2] - E[1][2] * E[2][1]) / det;
-  Ei[0][1] = (E[0][2] * E[2][1] - E[0][1] * E[2][2]) / det;
-  Ei[0][2] = (E[0][1] * E[1][2] - E[0][2] * E[1][1]) / det;
-  Ei[1][0] = (E[1][2] * E[2][0] - E[1][0] * E[2][2]) / det;
-  Ei[1][1] = (E[0][0] * E[2][2] - E[0][2] * E[2][0]) / det;
-  Ei[1][2] = (E[0][2] * E[1][0] - E[0][0] * E[1][2]) / det;
-  Ei[2][0] = (E[1][0] * E[2][1] - E[1][1] * E[2][0]) / det;
-  Ei[2][1] = (E[0][1] * E[2][0] - E[0][0] * E[2][1]) / det;
-  Ei[2][2] = (E[0][0] * E[1][1] - E[0][1] * E[1][0]) / det;
-  double GL[4][3];
-  for (int k = 0; k < 3; k++)
-    for (int c = 0; c < 3; c++) GL[k + 1][c] = Ei[c][k];
-  for (int c = 0; c < 3; c++) GL[0][c] = -(GL[1][c] + GL[2][c] + GL[3][c]);
+  const double det0 = E[0][0] * (E[1][1] * E[2][2] - E[1][2] * E[2][1]) -
+                      E[0][1] * (E[1][0] * E[2][2] - E[1][2] * E[2][0]) +
+                      E[0][2] * (E[1][0] * E[2][1] - E[1][1] * E[2][0]);
+  if (det0 == 0.0 || !std::isfinite(det0)) return false;
+  const double orient = det0 > 0.0 ? 1.0 : -1.0;
   std::memset(Me, 0, 100 * sizeof(double));
   std::memset(Ke, 0, 100 * sizeof(double));
   for (int i = 0; i < 4; i++)
@@ -288,17 +278,40 @@ bool tet10_element(const double X[10][3], const double Dn[10][9], double* Me, do
         L[2] = v * (1.0 - u);
         L[3] = w * (1.0 - u) * (1.0 - v);
         L[0] = 1.0 - L[1] - L[2] - L[3];
-        const double wq = 6.0 * gw[i] * gw[j] * gw[k] * (1.0 - u) * (1.0 - u) * (1.0 - v) * vol;
-        double N[10], G[10][3];
+        double N[10], dN[10][3];
         for (int a = 0; a < 4; a++) {
           N[a] = L[a] * (2.0 * L[a] - 1.0);
-          for (int c = 0; c < 3; c++) G[a][c] = (4.0 * L[a] - 1.0) * GL[a][c];
+          for (int r = 0; r < 3; r++) dN[a][r] = (4.0 * L[a] - 1.0) * dl[a][r];
         }
         for (int e = 0; e < 6; e++) {
           const int a = edge[e][0], b = edge[e][1];
           N[4 + e] = 4.0 * L[a] * L[b];
-          for (int c = 0; c < 3; c++) G[4 + e][c] = 4.0 * (L[b] * GL[a][c] + L[a] * GL[b][c]);
+          for (int r = 0; r < 3; r++) dN[4 + e][r] = 4.0 * (L[b] * dl[a][r] + L[a] * dl[b][r]);
         }
+        double J[3][3] = {{0}};
+        for (int a = 0; a < 10; a++)
+          for (int r = 0; r < 3; r++)
+            for (int c = 0; c < 3; c++) J[r][c] += dN[a][r] * X[a][c];
+        const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                           J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                           J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+        if (!(orient * det > 0.0)) return false;
+        double Ji[3][3];
+        Ji[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
+        Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+        Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+        Ji[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;
+        Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+        Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+        Ji[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / det;
+        Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+        Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+        double G[10][3];
+        for (int a = 0; a < 10; a++)
+          for (int c = 0; c < 3; c++) G[a][c] = Ji[c][0] * dN[a][0] + Ji[c][1] * dN[a][1] + Ji[c][2] * dN[a][2];
+        // collapsed-cube weight times |det J| (the reference tetrahedron's
+        // volume 1/6 cancels the factor 6 of the collapse)
+        const double wq = gw[i] * gw[j] * gw[k] * (1.0 - u) * (1.0 - u) * (1.0 - v) * orient * det;
         double Dq[9] = {0};
         for (int a = 0; a < 10; a++)
           for (int t = 0; t < 9; t++) Dq[t] += N[a] * Dn[a][t];

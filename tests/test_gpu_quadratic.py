@@ -41,6 +41,7 @@ def _spec(dims=(4.0, 2.0, 1.0), h=0.5, model="ttp06", variant="endo", bdf=2, cur
                                                            ("q3", "ttp06", "endo", 2, False),
                                                            ("q3", "bo", "epi", 3, True),
                                                            ("p2", "ttp06", "epi", 2, False),
+                                                           ("p2", "ttp06", "endo", 2, True),
                                                            ("p2", "bo", "epi", 2, False)])
 def test_quadratic_single_step(kind, model, variant, bdf, curved):
     ep = _ep()

@@ -91,8 +91,12 @@ def test_assembly_matches_oracle_q3_slab():
     _compare(m, W.random_fibers(m.n_nodes, 17))
 
 
-def test_assembly_matches_oracle_p2_slab():
+@pytest.mark.parametrize("curved", [False, True])
+def test_assembly_matches_oracle_p2_slab(curved):
     m = W.slab_p2(3.0, 2.0, 1.0, 0.5)
+    if curved:   # edge nodes off the midpoints: isoparametric elements
+        rng = np.random.default_rng(18)
+        m.xyz = m.xyz + rng.uniform(-0.03, 0.03, m.xyz.shape)
     _compare(m, W.random_fibers(m.n_nodes, 15))
 
 
@@ -118,3 +122,17 @@ def test_no_device_fails_loudly_without_gpu():
     with pytest.raises(ep.EpError) as ei:
         ep.Simulation(0)
     assert ei.value.status in (ep._lib.EP_EHIP, ep._lib.EP_EINVAL)
+
+
+def test_folded_quadratic_tetrahedron_is_rejected():
+    """An edge node moved past the far vertex of its edge folds the
+    isoparametric map (its Jacobian changes sign inside the element)."""
+    import paper_2308_01651_amd as ep
+    m = W.slab_p2(1.0, 1.0, 1.0, 1.0)
+    xyz = m.xyz.copy()
+    el = m.conn[0]
+    a, b = W.TET10_EDGES[0]
+    xyz[el[4]] = xyz[el[a]] + 1.6 * (xyz[el[b]] - xyz[el[a]])
+    with pytest.raises(ep.EpError):
+        ep.assemble_csr(m.elem, xyz, m.conn, None, (0.17, 0.019, 0.019), 140.0, 0.01)
+    ep.assemble_csr(m.elem, m.xyz, m.conn, None, (0.17, 0.019, 0.019), 140.0, 0.01)
