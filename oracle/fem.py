@@ -6,7 +6,7 @@ phi_k phi_j over the domain, K_jk the integral of D grad(phi_k) . grad(phi_j),
 with Gauss quadrature of the fewest points that integrate M exactly:
 2x2x2 Gauss-Legendre points for trilinear hexahedra (Q1), 3x3x3 for
 triquadratic hexahedra (Q2, the paper's higher-order hexahedral elements),
-4x4x4 for tricubic hexahedra (Q3),
+4x4x4 for tricubic hexahedra (Q3), (p+1)^3 for degree p = 4..6,
 the symmetric 4-point degree-2 rule for linear tetrahedra (P1), and a
 64-point conical product rule (exact to degree 5) for quadratic tetrahedra
 (P2, the paper's higher-order tetrahedral elements, isoparametric like the
@@ -218,6 +218,59 @@ def q3_element_matrices(X, Dn):
     return Me, Ke
 
 
+def _lagrange_equispaced(t, p):
+    """Lagrange basis of degree p on [-1, 1] with the p + 1 equispaced nodes
+    -1 + 2j/p: values and derivatives, each [p + 1], from the product formula."""
+    nodes = -1.0 + 2.0 * np.arange(p + 1) / p
+    v = np.ones(p + 1)
+    d = np.zeros(p + 1)
+    for j in range(p + 1):
+        others = [m for m in range(p + 1) if m != j]
+        for m in others:
+            v[j] *= (t - nodes[m]) / (nodes[j] - nodes[m])
+        for k in others:
+            term = 1.0 / (nodes[j] - nodes[k])
+            for m in others:
+                if m != k:
+                    term *= (t - nodes[m]) / (nodes[j] - nodes[m])
+            d[j] += term
+    return v, d
+
+
+def qp_element_matrices(X, Dn, p):
+    """Element mass and stiffness for a batch of isoparametric hexahedra of
+    degree p (the paper's hexahedral Q_p spaces), (p + 1)^3 nodes in the
+    order k = a + (p + 1) b + (p + 1)^2 c at the reference point
+    (2a/p - 1, 2b/p - 1, 2c/p - 1), (p + 1)^3 Gauss-Legendre points.
+
+    X  : [E, (p+1)^3, 3]; Dn : [E, (p+1)^3, 3, 3]
+    """
+    n1 = p + 1
+    npe = n1 ** 3
+    x1, w1 = np.polynomial.legendre.leggauss(n1)
+    E = X.shape[0]
+    Me = np.zeros((E, npe, npe))
+    Ke = np.zeros((E, npe, npe))
+    for iz in range(n1):
+        for iy in range(n1):
+            for ix in range(n1):
+                vx, dx = _lagrange_equispaced(x1[ix], p)
+                vy, dy = _lagrange_equispaced(x1[iy], p)
+                vz, dz = _lagrange_equispaced(x1[iz], p)
+                N = np.einsum("c,b,a->cba", vz, vy, vx).ravel()
+                dN = np.stack([np.einsum("c,b,a->cba", vz, vy, dx).ravel(),
+                               np.einsum("c,b,a->cba", vz, dy, vx).ravel(),
+                               np.einsum("c,b,a->cba", dz, vy, vx).ravel()], axis=1)
+                J = np.einsum("ki,ekj->eij", dN, X)
+                detJ = np.linalg.det(J)
+                G = np.einsum("eij,kj->eki", np.linalg.inv(J), dN)
+                Dq = np.einsum("k,ekij->eij", N, Dn)
+                wq = w1[ix] * w1[iy] * w1[iz] * detJ
+                Me += wq[:, None, None] * np.outer(N, N)[None]
+                Ke += wq[:, None, None] * np.einsum("eai,eij,ebj->eab", G, Dq, G)
+    return Me, Ke
+
+
 # ---------------------------------------------------------------------------
 # P1 tetrahedra
 # ---------------------------------------------------------------------------
@@ -345,7 +398,9 @@ def assemble(xyz, conn, Dnodal, chunk: int = 200000):
         c = conn[e0:e0 + chunk]
         X = xyz[c]
         Dn = Dnodal[c]
-        if npe == 64:
+        if npe in (125, 216, 343):
+            Me, Ke = qp_element_matrices(X, Dn, round(npe ** (1.0 / 3.0)) - 1)
+        elif npe == 64:
             Me, Ke = q3_element_matrices(X, Dn)
         elif npe == 27:
             Me, Ke = q2_element_matrices(X, Dn)

@@ -361,6 +361,57 @@ def test_q3_eigenvalue_converges_at_sixth_order():
     assert 5.6 < rate < 6.4, (errs, rate)
 
 
+def test_qp_degree4_integrates_quartic_fields_exactly():
+    """Generic degree-p hexahedra at p = 4 (125 nodes): mass and stiffness
+    exact for quartic fields (degree 8 in one variable in the mass) on a
+    sheared lattice with an anisotropic D; K 1 = 0."""
+    m = W.slab_qp(2.0, 1.0, 1.0, 1.0, 4)
+    A = np.array([[1.0, 0.3, 0.0], [0.0, 1.0, 0.2], [0.1, 0.0, 1.0]])
+    D = np.array([[2.0, 0.3, 0.1], [0.3, 1.0, 0.2], [0.1, 0.2, 0.5]])
+    M, K = fem.assemble(m.xyz @ A.T, m.conn, np.broadcast_to(D, (m.n_nodes, 3, 3)).copy())
+    detA = np.linalg.det(A)
+    box = (2.0, 1.0, 1.0)
+    f = {(4, 0, 0): 1.0, (1, 2, 1): -1.5, (0, 0, 2): 0.5}
+    g = {(4, 0, 0): -0.5, (0, 3, 1): 1.0, (1, 0, 0): 2.0}
+    fv, gv = _poly_eval(f, m.xyz), _poly_eval(g, m.xyz)
+    exact_m = _box_integral(f, g, box) * detA
+    assert abs(fv @ M @ gv - exact_m) < 1e-11 * max(1.0, abs(exact_m))
+    B = np.linalg.inv(A) @ D @ np.linalg.inv(A).T
+    gf, gg = _poly_grad(f), _poly_grad(g)
+    exact_k = sum(B[i, j] * _box_integral(gf[i], gg[j], box) for i in range(3) for j in range(3)) * detA
+    assert abs(fv @ K @ gv - exact_k) < 1e-10 * max(1.0, abs(exact_k))
+    assert np.abs(K @ np.ones(m.n_nodes)).max() < 1e-11
+
+
+def test_qp_degree4_eigenvalue_converges_at_eighth_order():
+    L = 2.0
+    errs = []
+    for h in (1.0, 0.5):
+        m = W.slab_qp(L, 1.0, 1.0, h, 4)
+        Dn = fem.nodal_diffusion(*W.uniform_fibers(m.n_nodes), 1.0, 1.0, 1.0, 1.0, 1.0)
+        M, K = fem.assemble(m.xyz, m.conn, Dn)
+        lam_h = spla.eigsh(K, k=2, M=M, sigma=0.0, which="LM")[0]
+        errs.append(np.min(np.abs(lam_h - (np.pi / L) ** 2)))
+    rate = np.log2(errs[0] / errs[1])
+    assert 7.5 < rate < 8.5, (errs, rate)
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_qp_generic_matches_dedicated_elements(p):
+    """The generic degree-p routine equals the separately pinned Q2 / Q3
+    routines on curved elements, and slab_qp equals slab_q2 / slab_q3."""
+    gen, ded = {2: (W.slab_q2, fem.q2_element_matrices), 3: (W.slab_q3, fem.q3_element_matrices)}[p]
+    a, b = W.slab_qp(2.0, 1.0, 1.0, 0.5, p), gen(2.0, 1.0, 1.0, 0.5)
+    assert np.array_equal(a.conn, b.conn) and np.allclose(a.xyz, b.xyz, rtol=0, atol=1e-15)
+    rng = np.random.default_rng(p)
+    X = a.xyz[a.conn[:4]] + rng.uniform(-0.02, 0.02, (4, a.conn.shape[1], 3))
+    Dn = fem.nodal_diffusion(*W.random_fibers(a.conn.shape[1], p), 0.9, 0.3, 0.2, 1.0, 1.0)
+    Dn = np.broadcast_to(Dn, (4,) + Dn.shape).copy()
+    M1, K1 = fem.qp_element_matrices(X, Dn, p)
+    M2, K2 = ded(X, Dn)
+    assert np.max(np.abs(M1 - M2)) < 1e-15 and np.max(np.abs(K1 - K2)) < 1e-13
+
+
 # ---------------------------------------------------------------------------
 # P2 (10-node) tetrahedra
 # ---------------------------------------------------------------------------

@@ -134,6 +134,24 @@ def slab_q3(Lx: float, Ly: float, Lz: float, h: float, label: str = "") -> Mesh:
     return Mesh(xyz, conn, (nx, ny, nz), label or f"slab-q3-{Lx}x{Ly}x{Lz}-h{h}")
 
 
+def slab_qp(Lx: float, Ly: float, Lz: float, h: float, p: int, label: str = "") -> Mesh:
+    """Structured hexahedral mesh of degree p ((p + 1)^3 nodes per element)
+    of [0,Lx]x[0,Ly]x[0,Lz] with element size ~h: nodes on the lattice of
+    spacing h/p, element-local node k = a + (p + 1) b + (p + 1)^2 c at the
+    element's lattice point (a, b, c)."""
+    cx = int(round(Lx / h))
+    cy = int(round(Ly / h))
+    cz = int(round(Lz / h))
+    nx, ny, nz = p * cx + 1, p * cy + 1, p * cz + 1
+    xyz = _lattice_xyz(nx, ny, nz, Lx / (nx - 1), Ly / (ny - 1), Lz / (nz - 1))
+    ex, ey, ez = np.meshgrid(np.arange(cx), np.arange(cy), np.arange(cz), indexing="ij")
+    base = (p * ex + nx * (p * ey + ny * p * ez)).transpose(2, 1, 0).ravel()
+    r = range(p + 1)
+    loc = np.array([a + nx * (b + ny * c) for c in r for b in r for a in r])
+    conn = (base[:, None] + loc[None, :]).astype(np.int32)
+    return Mesh(xyz, conn, (nx, ny, nz), label or f"slab-q{p}-{Lx}x{Ly}x{Lz}-h{h}")
+
+
 def lattice_q1(nx: int, ny: int, nz: int, hx: float, hy: float, hz: float,
                label: str = "") -> Mesh:
     xyz = _lattice_xyz(nx, ny, nz, hx, hy, hz)
