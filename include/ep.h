@@ -56,7 +56,10 @@ typedef enum {
   EP_ESTATE = -7    /* call not valid in the object's current state          */
 } ep_status;
 
-enum { EP_TET4 = 4, EP_TET10 = 10, EP_HEX8 = 8, EP_HEX27 = 27, EP_HEX64 = 64 };  /* element types */
+/* element types: tetrahedra of degree 1, 2; hexahedra of degree p = 1..6
+ * ((p + 1)^3 nodes) */
+enum { EP_TET4 = 4, EP_TET10 = 10, EP_HEX8 = 8, EP_HEX27 = 27, EP_HEX64 = 64, EP_HEX125 = 125,
+       EP_HEX216 = 216, EP_HEX343 = 343 };
 enum { EP_PASSIVE = 0, EP_AP = 1, EP_BO = 2, EP_TTP06 = 3 };          /* ionic models    */
 enum { EP_CELL_EPI = 0, EP_CELL_ENDO = 1, EP_CELL_MID = 2 };          /* TTP06 variants  */
 enum { EP_CUBE = 0, EP_SPHERE = 1, EP_GAUSS = 2 };                    /* stimulus shapes */
@@ -132,9 +135,9 @@ ep_status ep_sim_create(int device, void* hip_stream, ep_sim** out);
 /* Mesh (paper: tetrahedral or hexahedral conforming mesh).  xyz: [n_nodes][3]
  * coordinates in mm; conn: [n_elems][elem] node indices, hexahedra in
  * lexicographic corner order (corner a + 2b + 4c at reference (a, b, c)).
- * EP_HEX27 / EP_HEX64: triquadratic / tricubic hexahedra (paper: the
- * higher-order hexahedral Q_p spaces, here p = 2 and 3), node a + 3b + 9c at
- * reference (a/2, b/2, c/2), resp. a + 4b + 16c at (a/3, b/3, c/3).
+ * EP_HEX27 .. EP_HEX343: hexahedra of degree p = 2 .. 6 (paper: the
+ * higher-order hexahedral Q_p spaces), node a + (p+1) b + (p+1)^2 c at
+ * reference (a/p, b/p, c/p), e.g. a + 3b + 9c at (a/2, b/2, c/2) for p = 2.
  * EP_TET10: quadratic tetrahedra (paper: P2), vertices 0-3 then the nodes of
  * the edges 01, 02, 03, 12, 13, 23.  All higher-order elements are
  * isoparametric: edge nodes off the edge midpoints make a curved element;

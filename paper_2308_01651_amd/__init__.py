@@ -15,7 +15,7 @@ from . import _lib
 from ._lib import EpError, EpStats, check, lib
 
 # constants (include/ep.h)
-EP_TET4, EP_TET10, EP_HEX8, EP_HEX27, EP_HEX64 = 4, 10, 8, 27, 64
+EP_TET4, EP_TET10, EP_HEX8, EP_HEX27, EP_HEX64, EP_HEX125, EP_HEX216, EP_HEX343 = 4, 10, 8, 27, 64, 125, 216, 343
 EP_PASSIVE, EP_AP, EP_BO, EP_TTP06 = 0, 1, 2, 3
 EP_CELL_EPI, EP_CELL_ENDO, EP_CELL_MID = 0, 1, 2
 EP_CUBE, EP_SPHERE, EP_GAUSS = 0, 1, 2

@@ -328,8 +328,10 @@ double stim_profile(const Stim& t, const double* x) {
 
 size_t estimate_bytes(const ep_sim* s) {
   const int64_t n = s->n;
-  const double nnz_row = (s->elem == EP_HEX64) ? 125.0 : (s->elem == EP_HEX27) ? 64.0
-                         : (s->elem == EP_TET10) ? 40.0 : (s->elem == EP_HEX8) ? 27.0 : 16.0;
+  // a hexahedral lattice of degree p couples a node to (p + 2)^3 nodes on average
+  const int hex_p = s->elem == EP_HEX8 ? 1 : s->elem == EP_HEX27 ? 2 : s->elem == EP_HEX64 ? 3
+                  : s->elem == EP_HEX125 ? 4 : s->elem == EP_HEX216 ? 5 : s->elem == EP_HEX343 ? 6 : 0;
+  const double nnz_row = hex_p ? std::pow(hex_p + 2.0, 3.0) : (s->elem == EP_TET10) ? 40.0 : 16.0;
   const bool mixed = s->prec == EP_MIXED;
   const ModelInfo mi = model_info(s->model);
   double per_node = 11 * 8.0 + 24.0;                            // FP64 vectors, activation
@@ -1129,8 +1131,9 @@ ep_status ep_sim_upload_mesh(ep_sim* s, int elem, int64_t n_nodes, const double*
                              const int32_t* conn, const int32_t* material_id) {
   if (check_sim(s)) return EP_EINVAL;
   if (s->finalized) return fail(EP_ESTATE, "sim already finalized");
-  if (elem != EP_HEX8 && elem != EP_TET4 && elem != EP_HEX27 && elem != EP_HEX64 && elem != EP_TET10)
-    return fail(EP_EINVAL, "elem must be EP_HEX8, EP_HEX27, EP_HEX64, EP_TET4 or EP_TET10");
+  if (elem != EP_HEX8 && elem != EP_TET4 && elem != EP_HEX27 && elem != EP_HEX64 && elem != EP_HEX125 &&
+      elem != EP_HEX216 && elem != EP_HEX343 && elem != EP_TET10)
+    return fail(EP_EINVAL, "elem must be EP_TET4, EP_TET10 or EP_HEX8 .. EP_HEX343");
   if (n_nodes <= 0 || n_elems <= 0 || !xyz || !conn) return fail(EP_EINVAL, "empty mesh");
   if (n_nodes >= (int64_t)INT32_MAX) return fail(EP_EINVAL, "too many nodes");
   if (material_id)

@@ -243,6 +243,113 @@ bool hex64_element(const double X[64][3], const double Dn[64][9], double* Me, do
   return true;
 }
 
+// Gauss-Legendre points and weights of order n on [-1, 1]: Newton's method on
+// the Legendre polynomial P_n (three-term recurrence), started from the
+// asymptotic estimate cos(pi (i + 3/4) / (n + 1/2)) of the i-th root;
+// w_i = 2 / ((1 - x_i^2) P_n'(x_i)^2).
+static void gauss_legendre(int n, double* x, double* w) {
+  for (int i = 0; i < n; i++) {
+    double t = std::cos(std::acos(-1.0) * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; it++) {
+      double p0 = 1.0, p1 = t;
+      for (int j = 1; j < n; j++) {
+        const double p2 = ((2.0 * j + 1.0) * t * p1 - j * p0) / (j + 1.0);
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (t * p1 - p0) / (t * t - 1.0);
+      const double step = p1 / dp;
+      t -= step;
+      if (std::fabs(step) < 1e-16) break;
+    }
+    x[n - 1 - i] = t;
+    w[n - 1 - i] = 2.0 / ((1.0 - t * t) * dp * dp);
+  }
+}
+
+// Hexahedron of degree p = 4..6 ((p + 1)^3 nodes), local node
+// k = a + (p + 1) b + (p + 1)^2 c at the reference point
+// (2a/p - 1, 2b/p - 1, 2c/p - 1); isoparametric map; (p + 1)^3 Gauss-Legendre
+// points (exact for the mass matrix of an affine element).
+bool hexp_element(int p, const double (*X)[3], const double (*Dn)[9], double* Me, double* Ke) {
+  if (p < 4 || p > 6) return false;
+  const int n1 = p + 1, npe = n1 * n1 * n1;
+  double gp[7], gw[7], z[7];
+  gauss_legendre(n1, gp, gw);
+  for (int j = 0; j < n1; j++) z[j] = -1.0 + 2.0 * j / p;
+  // 1-D Lagrange factors at the equispaced nodes and their derivatives at
+  // every Gauss point (product form, derivative by the product rule)
+  double V[7][7], Dv[7][7];
+  for (int q = 0; q < n1; q++)
+    for (int j = 0; j < n1; j++) {
+      double val = 1.0, der = 0.0;
+      for (int m = 0; m < n1; m++) {
+        if (m == j) continue;
+        const double f = (gp[q] - z[m]) / (z[j] - z[m]);
+        der = der * f + val / (z[j] - z[m]);
+        val *= f;
+      }
+      V[q][j] = val;
+      Dv[q][j] = der;
+    }
+  std::memset(Me, 0, (size_t)npe * npe * sizeof(double));
+  std::memset(Ke, 0, (size_t)npe * npe * sizeof(double));
+  std::vector<double> N(npe), dN(3 * npe), G(3 * npe), DG(3 * npe);
+  for (int qz = 0; qz < n1; qz++)
+    for (int qy = 0; qy < n1; qy++)
+      for (int qx = 0; qx < n1; qx++) {
+        for (int c = 0; c < n1; c++)
+          for (int b = 0; b < n1; b++)
+            for (int a = 0; a < n1; a++) {
+              const int k = a + n1 * (b + n1 * c);
+              N[k] = V[qx][a] * V[qy][b] * V[qz][c];
+              dN[3 * k] = Dv[qx][a] * V[qy][b] * V[qz][c];
+              dN[3 * k + 1] = V[qx][a] * Dv[qy][b] * V[qz][c];
+              dN[3 * k + 2] = V[qx][a] * V[qy][b] * Dv[qz][c];
+            }
+        double J[3][3] = {{0}};
+        for (int k = 0; k < npe; k++)
+          for (int r = 0; r < 3; r++)
+            for (int c = 0; c < 3; c++) J[r][c] += dN[3 * k + r] * X[k][c];
+        const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                           J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                           J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+        if (!(det > 0.0)) return false;
+        double Ji[3][3];
+        Ji[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
+        Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+        Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+        Ji[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;
+        Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+        Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+        Ji[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / det;
+        Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+        Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+        for (int k = 0; k < npe; k++)
+          for (int r = 0; r < 3; r++)
+            G[3 * k + r] = Ji[r][0] * dN[3 * k] + Ji[r][1] * dN[3 * k + 1] + Ji[r][2] * dN[3 * k + 2];
+        double Dq[9] = {0};
+        for (int k = 0; k < npe; k++)
+          for (int e = 0; e < 9; e++) Dq[e] += N[k] * Dn[k][e];
+        for (int k = 0; k < npe; k++)
+          for (int r = 0; r < 3; r++)
+            DG[3 * k + r] = Dq[3 * r] * G[3 * k] + Dq[3 * r + 1] * G[3 * k + 1] + Dq[3 * r + 2] * G[3 * k + 2];
+        const double w = gw[qx] * gw[qy] * gw[qz] * det;
+        for (int a = 0; a < npe; a++) {
+          const double wn = w * N[a];
+          const double g0 = w * G[3 * a], g1 = w * G[3 * a + 1], g2 = w * G[3 * a + 2];
+          double* mrow = Me + (size_t)npe * a;
+          double* krow = Ke + (size_t)npe * a;
+          for (int b = 0; b < npe; b++) {
+            mrow[b] += wn * N[b];
+            krow[b] += g0 * DG[3 * b] + g1 * DG[3 * b + 1] + g2 * DG[3 * b + 2];
+          }
+        }
+      }
+  return true;
+}
+
 // Quadratic tetrahedron (10 nodes: vertices 0-3, then the nodes of the edges
 // 01, 02, 03, 12, 13, 23), isoparametric: the map from the reference
 // tetrahedron uses all ten nodes, so an element whose edge nodes sit off the
@@ -375,8 +482,9 @@ bool assemble_csr(int elem, int64_t n_nodes, const double* xyz, int64_t n_elems,
                   double sigma_l, double sigma_t, double sigma_n, double chi, double cm, Csr& A,
                   std::vector<char>& err, const int32_t* region, const double* region_sigma,
                   const unsigned char* region_on) {
-  if (elem != 8 && elem != 4 && elem != 27 && elem != 64 && elem != 10) {
-    set_err(err, "element type must be 8 (hex), 27 (triquadratic hex), 64 (tricubic hex), 4 (tet) or 10 "
+  if (elem != 8 && elem != 4 && elem != 27 && elem != 64 && elem != 125 && elem != 216 && elem != 343 &&
+      elem != 10) {
+    set_err(err, "element type must be (p + 1)^3 for a hexahedron of degree p = 1..6, 4 (tet) or 10 "
                  "(quadratic tet)");
     return false;
   }
@@ -404,7 +512,7 @@ bool assemble_csr(int elem, int64_t n_nodes, const double* xyz, int64_t n_elems,
   std::vector<char> bad(1, 0);
   static const double ex[3] = {1, 0, 0}, ey[3] = {0, 1, 0}, ez[3] = {0, 0, 1};
   parallel_for(n_elems, [&](int64_t e) {
-    double X[64][3], Dn[64][9];
+    double X[343][3], Dn[343][9];
     const int r = region ? region[e] : 0;
     const double sl = region ? region_sigma[3 * r] : sigma_l;
     const double st = region ? region_sigma[3 * r + 1] : sigma_t;
@@ -417,7 +525,9 @@ bool assemble_csr(int elem, int64_t n_nodes, const double* xyz, int64_t n_elems,
       const double* nn = n0 ? n0 + 3 * v : ez;
       nodal_tensor(f, s, nn, sl, st, sn, scale, Dn[k]);
     }
-    bool ok = (npe == 64)  ? hex64_element(X, Dn, &Me[e * 64 * 64], &Ke[e * 64 * 64])
+    const size_t eo = (size_t)e * npe * npe;
+    bool ok = (npe >= 125) ? hexp_element(npe == 125 ? 4 : npe == 216 ? 5 : 6, X, Dn, &Me[eo], &Ke[eo])
+              : (npe == 64) ? hex64_element(X, Dn, &Me[e * 64 * 64], &Ke[e * 64 * 64])
               : (npe == 27) ? hex27_element(X, Dn, &Me[e * 27 * 27], &Ke[e * 27 * 27])
               : (npe == 10) ? tet10_element(X, Dn, &Me[e * 100], &Ke[e * 100])
               : (npe == 8)  ? hex_element(X, Dn, &Me[e * 64], &Ke[e * 64])

@@ -1,8 +1,8 @@
-"""GPU: triquadratic (27-node) and tricubic (64-node) hexahedra and quadratic
-(10-node) tetrahedra against the oracle.
+"""GPU: hexahedra of degree 2 to 5 ((p + 1)^3 nodes) and quadratic (10-node)
+tetrahedra against the oracle.
 
-The operators of these lattices (up to 125 entries per row for Q2, 343 for
-Q3) are stored in the sliced-ELL format; everything else (ionic step at every node, ICI load,
+The operators of these lattices ((2p + 1)^3 entries in a row of an element
+vertex: 125 for Q2 up to 1,331 for Q5) are stored in the sliced-ELL format; everything else (ionic step at every node, ICI load,
 PCG, activation) is the path of the other elements.  Tolerances as for Q1:
 a single step at rtol 1e-13 to 1e-10 relative, trajectories at rtol 1e-10 to
 1e-8 with activation times to the time step, mixed precision against FP64
@@ -27,19 +27,28 @@ def _rel(a, b):
 
 
 def _spec(dims=(4.0, 2.0, 1.0), h=0.5, model="ttp06", variant="endo", bdf=2, curved=False, kind="q2"):
-    mesh = {"q2": W.slab_q2, "q3": W.slab_q3, "p2": W.slab_p2}[kind](*dims, h)
+    if kind in ("q4", "q5"):
+        mesh = W.slab_qp(*dims, h, int(kind[1]))
+    else:
+        mesh = {"q2": W.slab_q2, "q3": W.slab_q3, "p2": W.slab_p2}[kind](*dims, h)
     if curved:
         rng = np.random.default_rng(8)
         mesh.xyz = mesh.xyz + rng.uniform(-0.02, 0.02, mesh.xyz.shape)
     st = [W.corner_cube_stimulus(dims=dims)]
-    return W.SimSpec(mesh, W.random_fibers(mesh.n_nodes, 9), W.Physics(), model, variant, st, 0.05, bdf, 1,
-                     1e-10, "t")
+    # degree >= 4: the equispaced Lagrange basis has large negative lobes, so
+    # a nodal D that jumps from node to node (random fibers) interpolates to
+    # an indefinite tensor at some quadrature points and K loses definiteness;
+    # these elements get a smooth (transmurally rotating) fiber field
+    fib = W.rotating_fibers(mesh.xyz) if kind in ("q4", "q5") else W.random_fibers(mesh.n_nodes, 9)
+    return W.SimSpec(mesh, fib, W.Physics(), model, variant, st, 0.05, bdf, 1, 1e-10, "t")
 
 
 @pytest.mark.parametrize("kind,model,variant,bdf,curved", [("q2", "ttp06", "endo", 2, False),
                                                            ("q2", "bo", "epi", 3, True), ("q2", "ap", "", 1, False),
                                                            ("q3", "ttp06", "endo", 2, False),
                                                            ("q3", "bo", "epi", 3, True),
+                                                           ("q4", "ttp06", "endo", 2, False),
+                                                           ("q5", "bo", "epi", 3, False),
                                                            ("p2", "ttp06", "epi", 2, False),
                                                            ("p2", "ttp06", "endo", 2, True),
                                                            ("p2", "bo", "epi", 2, False)])
@@ -66,7 +75,7 @@ def test_quadratic_single_step(kind, model, variant, bdf, curved):
         assert err < 1e-11, (v, err)
 
 
-@pytest.mark.parametrize("kind,prec", [("q2", 0), ("q2", 1), ("q3", 0), ("q3", 1), ("p2", 0)])
+@pytest.mark.parametrize("kind,prec", [("q2", 0), ("q2", 1), ("q3", 0), ("q3", 1), ("q4", 0), ("p2", 0)])
 def test_quadratic_trajectory(kind, prec):
     ep = _ep()
     spec = _spec(dims=(6.0, 3.0, 1.0), h=0.5, kind=kind)

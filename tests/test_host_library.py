@@ -91,6 +91,15 @@ def test_assembly_matches_oracle_q3_slab():
     _compare(m, W.random_fibers(m.n_nodes, 17))
 
 
+@pytest.mark.parametrize("p", [4, 5, 6])
+def test_assembly_matches_oracle_degree_p_hex(p):
+    m = W.slab_qp(2.0, 1.0, 1.0, 1.0, p)
+    rng = np.random.default_rng(30 + p)
+    # curved (isoparametric) elements; 2 % of the node spacing keeps det J > 0
+    m.xyz = m.xyz + rng.uniform(-0.02 / p, 0.02 / p, m.xyz.shape)
+    _compare(m, W.random_fibers(m.n_nodes, 19))
+
+
 @pytest.mark.parametrize("curved", [False, True])
 def test_assembly_matches_oracle_p2_slab(curved):
     m = W.slab_p2(3.0, 2.0, 1.0, 0.5)

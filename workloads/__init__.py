@@ -246,6 +246,20 @@ def uniform_fibers(n_nodes: int, f=(1.0, 0.0, 0.0), s=(0.0, 1.0, 0.0),
     return F, S, N
 
 
+def rotating_fibers(xyz: np.ndarray, angle0: float = -60.0, angle1: float = 60.0):
+    """Fibers in the x-y plane whose angle to x turns linearly with z from
+    angle0 to angle1 degrees across the slab (the transmural rotation of
+    myocardial fibers); sheets follow in the plane, normals along z."""
+    z = xyz[:, 2]
+    t = (z - z.min()) / max(z.max() - z.min(), 1e-300)
+    th = np.deg2rad(angle0 + (angle1 - angle0) * t)
+    zero = np.zeros_like(th)
+    F = np.stack([np.cos(th), np.sin(th), zero], axis=1)
+    S = np.stack([-np.sin(th), np.cos(th), zero], axis=1)
+    N = np.tile(np.array([0.0, 0.0, 1.0]), (xyz.shape[0], 1))
+    return F, S, N
+
+
 def random_fibers(n_nodes: int, seed: int):
     """Random orthonormal triplets per node (for anisotropy tests)."""
     rng = np.random.default_rng(seed)
