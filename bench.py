@@ -401,7 +401,8 @@ def main():
         print(json.dumps({"copy_bytes_each_way": a.numel() * 8, "copies": 5}))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is designed, not built",
+        print(json.dumps({"error": "the time step runs on one GPU per simulation; sharding a mesh over several "
+                                   "GPUs is not implemented",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import paper_2308_01651_amd as ep
