@@ -454,3 +454,30 @@ def test_p2_eigenvalue_converges_at_about_fourth_order():
         errs.append(np.min(np.abs(lam_h - (np.pi / 2.0) ** 2)))
     rate = np.log2(errs[0] / errs[1])
     assert 3.3 < rate < 4.5, (errs, rate)
+
+
+def _min_eig_interpolated_d(mesh, fibers, p):
+    """Smallest eigenvalue of the nodal D interpolated with the degree-p
+    basis, over the Gauss points of every element."""
+    Dn = fem.nodal_diffusion(*fibers, 0.17, 0.019, 0.019, 1.0, 1.0)[mesh.conn]   # [E, npe, 3, 3]
+    x1, _ = np.polynomial.legendre.leggauss(p + 1)
+    lo = np.inf
+    for z in x1:
+        for y in x1:
+            for x in x1:
+                N = np.einsum("c,b,a->cba", fem._lagrange_equispaced(z, p)[0], fem._lagrange_equispaced(y, p)[0],
+                              fem._lagrange_equispaced(x, p)[0]).ravel()
+                lo = min(lo, np.linalg.eigvalsh(np.einsum("k,ekij->eij", N, Dn)).min())
+    return lo
+
+
+def test_interpolated_diffusion_tensor_definiteness():
+    """The reading that interpolates nodal D with the element basis keeps D
+    positive semi-definite at quadrature points for a smooth fiber field,
+    but not at p = 4 for fibers drawn at random per node (the basis has
+    negative lobes); trilinear elements stay definite either way."""
+    m4 = W.slab_qp(2.0, 1.0, 1.0, 0.5, 4)
+    assert _min_eig_interpolated_d(m4, W.rotating_fibers(m4.xyz), 4) > 0.0
+    assert _min_eig_interpolated_d(m4, W.random_fibers(m4.n_nodes, 9), 4) < 0.0
+    m1 = W.slab_q1(2.0, 1.0, 1.0, 0.25)
+    assert _min_eig_interpolated_d(m1, W.random_fibers(m1.n_nodes, 9), 1) > 0.0
