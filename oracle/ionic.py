@@ -34,11 +34,25 @@ linear -v term with the rate factor eps(u_EXT, v_EXT); TTP06 concentrations
 (calcium as buffered totals, Na, K, RR) are explicit,
 x_{n+1} = (x_BDF + dt F(u_EXT, gates_{n+1}, c_EXT))/alpha.
 
-Parity status: rest-state fixed points (AP, BO exact; TTP06 drift bound) and
-the uniform-state reduction are pinned; the AP model is also pinned by the
-bistable-front speed.  Beyond those, the BO and TTP06 transcriptions are
-"parity unpinned" on the CPU; TTP06 is pinned end to end by the N-version
-slab activation time through the GPU path, which must match this oracle.
+Parity status.  Pinned on the CPU: the rest-state fixed points (AP, BO
+exact; TTP06 drift bound), the uniform-state reduction, the AP excitation
+term by the bistable-front speed, the Rush-Larsen and BDF gate updates
+(brute-force and closed-form integration of frozen gate ODEs), the
+rapid-buffer inversion, the rewritten I_CaL against its GHK form, and the
+TTP06 concentration bookkeeping of both integrators (`ttp06_step`,
+`ttp06_step_bdf`) by charge conservation: the membrane currents equal the
+valence- and volume-weighted change of Na, K and total Ca.
+
+Parity unpinned (the publications' equations and traces are not available
+here, and no closed form or invariant fixes them):
+  ap_dv                 the Aliev-Panfilov recovery rate away from rest;
+  bo_gate_targets       the Bueno-Orovio gate targets and time constants;
+  bo_iion               the Bueno-Orovio currents J_fi, J_so, J_si;
+  ttp06_gate_targets    the 12 TTP06 steady states and time constants;
+  ttp06_currents        the TTP06 current and flux formulas (except I_CaL's
+                        rewrite and the stoichiometry the conservation pin fixes).
+TTP06 is pinned end to end by the N-version slab activation time through the
+GPU path (the paper's 42.0 / 41.8 ms), which must match this oracle.
 """
 from __future__ import annotations
 
