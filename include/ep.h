@@ -295,6 +295,9 @@ ep_status ep_sim_set_state(ep_sim* sim, const double* u, const double* w, const 
 ep_status ep_sim_get_state(ep_sim* sim, double* u, double* w, double* u_prev);
 int ep_sim_n_vars(const ep_sim* sim);
 
+/* Free the sim and its device memory.  A sim that is still admitted to a
+ * pool is released from it first (its slot frees; the pool keeps stepping
+ * its other slots). */
 void ep_sim_destroy(ep_sim* sim);
 
 /* ---- batched / serving pool (many uneven simulations, one launch per phase) */

@@ -287,6 +287,7 @@ struct ep_sim {
   InstDesc* d_desc_own = nullptr;  // the sim's own descriptor (d_desc points into a pool table while pooled)
   hipStream_t stream_own = nullptr;
   int pool_slot = -1;
+  ep_pool* pool = nullptr;   // the pool that steps this sim while in_pool
   int it_pred = 8;      // CG iterations launched before the first convergence check
   // several subdomains (finalized): ionic points and the per-node primary
   // subdomain (-1: node outside every conducting subdomain)
@@ -1644,6 +1645,9 @@ ep_status ep_sim_time_kernel(ep_sim* s, int kind, int reps, double* us_per_launc
 
 void ep_sim_destroy(ep_sim* s) {
   if (!s) return;
+  // a pooled sim leaves its pool first, so that the pool's table never
+  // points at freed memory
+  if (s->in_pool && s->pool) (void)ep_pool_release(s->pool, s->pool_slot, nullptr);
   (void)hipSetDevice(s->device);
   if (s->stream) (void)hipStreamSynchronize(s->stream);
   s->kt.destroy();
@@ -2051,6 +2055,7 @@ ep_status ep_pool_admit(ep_pool* P, ep_sim* s, int64_t n_steps_total, int* slot)
   s->graphs.reset();
   s->in_pool = true;
   s->pool_slot = free_slot;
+  s->pool = P;
   ep_pool::Slot& sl = P->slots[free_slot];
   sl.sim = s;
   sl.target = n_steps_total;
@@ -2102,6 +2107,7 @@ ep_status ep_pool_release(ep_pool* P, int slot, ep_sim** sim_out) {
   s->stream = s->stream_own;
   s->in_pool = false;
   s->pool_slot = -1;
+  s->pool = nullptr;
   const size_t need = estimate_bytes(s);
   P->in_use -= std::min(P->in_use, std::max(need, s->mem.bytes));
   const int status = P->slots[slot].status;

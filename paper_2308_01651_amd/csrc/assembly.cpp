@@ -29,9 +29,26 @@ inline void nodal_tensor(const double* f, const double* s, const double* nn, dou
       D[3 * a + b] = scale * (sl * f[a] * f[b] + st * s[a] * s[b] + sn * nn[a] * nn[b]);
 }
 
+// Positive semi-definiteness of a symmetric 3x3 tensor (row-major): every
+// principal minor nonnegative, up to rounding relative to the trace.  The
+// basis of an element of degree p >= 2 has negative lobes, so interpolating
+// nodal tensors that change abruptly from node to node can leave the cone of
+// such tensors; K is then no longer positive semi-definite.
+bool psd3(const double D[9]) {
+  const double tr = std::fabs(D[0]) + std::fabs(D[4]) + std::fabs(D[8]);
+  const double tol = 1e-12;
+  if (D[0] < -tol * tr || D[4] < -tol * tr || D[8] < -tol * tr) return false;
+  const double t2 = tol * tr * tr;
+  if (D[0] * D[4] - D[1] * D[3] < -t2 || D[0] * D[8] - D[2] * D[6] < -t2 || D[4] * D[8] - D[5] * D[7] < -t2)
+    return false;
+  const double det = D[0] * (D[4] * D[8] - D[5] * D[7]) - D[1] * (D[3] * D[8] - D[5] * D[6]) +
+                     D[2] * (D[3] * D[7] - D[4] * D[6]);
+  return det >= -tol * tr * tr * tr;
+}
+
 // Trilinear hexahedron, local corner k = a + 2b + 4c at reference (2a-1, 2b-1, 2c-1).
 // Element matrices by 2x2x2 Gauss-Legendre quadrature.
-bool hex_element(const double X[8][3], const double Dn[8][9], double Me[64], double Ke[64]) {
+int hex_element(const double X[8][3], const double Dn[8][9], double Me[64], double Ke[64]) {
   static const double g = 0.57735026918962576451;  // 1/sqrt(3)
   std::memset(Me, 0, 64 * sizeof(double));
   std::memset(Ke, 0, 64 * sizeof(double));
@@ -56,7 +73,7 @@ bool hex_element(const double X[8][3], const double Dn[8][9], double Me[64], dou
         const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
                            J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
                            J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
-        if (!(det > 0.0)) return false;
+        if (!(det > 0.0)) return 1;
         double Ji[3][3];
         Ji[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
         Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
@@ -85,13 +102,13 @@ bool hex_element(const double X[8][3], const double Dn[8][9], double Me[64], dou
             Ke[8 * a + b] += det * (G[a][0] * DG[b][0] + G[a][1] * DG[b][1] + G[a][2] * DG[b][2]);
           }
       }
-  return true;
+  return 0;
 }
 
 // Triquadratic hexahedron (27 nodes), local node k = a + 3b + 9c at the
 // reference point (a - 1, b - 1, c - 1); isoparametric map; 3x3x3
 // Gauss-Legendre quadrature (exact for the mass matrix of an affine element).
-bool hex27_element(const double X[27][3], const double Dn[27][9], double* Me, double* Ke) {
+int hex27_element(const double X[27][3], const double Dn[27][9], double* Me, double* Ke) {
   static const double gp[3] = {-0.77459666924148337704, 0.0, 0.77459666924148337704};  // -sqrt(3/5), 0, sqrt(3/5)
   static const double gw[3] = {5.0 / 9.0, 8.0 / 9.0, 5.0 / 9.0};
   std::memset(Me, 0, 27 * 27 * sizeof(double));
@@ -129,7 +146,7 @@ bool hex27_element(const double X[27][3], const double Dn[27][9], double* Me, do
         const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
                            J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
                            J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
-        if (!(det > 0.0)) return false;
+        if (!(det > 0.0)) return 1;
         double Ji[3][3];
         Ji[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
         Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
@@ -147,6 +164,7 @@ bool hex27_element(const double X[27][3], const double Dn[27][9], double* Me, do
         double Dq[9] = {0};
         for (int k = 0; k < 27; k++)
           for (int e = 0; e < 9; e++) Dq[e] += N[k] * Dn[k][e];
+        if (!psd3(Dq)) return 2;
         double DG[27][3];
         for (int k = 0; k < 27; k++)
           for (int r = 0; r < 3; r++)
@@ -158,13 +176,13 @@ bool hex27_element(const double X[27][3], const double Dn[27][9], double* Me, do
             Ke[27 * a + b] += w * (G[a][0] * DG[b][0] + G[a][1] * DG[b][1] + G[a][2] * DG[b][2]);
           }
       }
-  return true;
+  return 0;
 }
 
 // Tricubic hexahedron (64 nodes), local node k = a + 4b + 16c at the
 // reference point (2a/3 - 1, 2b/3 - 1, 2c/3 - 1); isoparametric map; 4x4x4
 // Gauss-Legendre quadrature (exact for the mass matrix of an affine element).
-bool hex64_element(const double X[64][3], const double Dn[64][9], double* Me, double* Ke) {
+int hex64_element(const double X[64][3], const double Dn[64][9], double* Me, double* Ke) {
   static const double gp[4] = {-0.86113631159405257522, -0.33998104358485626480, 0.33998104358485626480,
                                0.86113631159405257522};
   static const double gw[4] = {0.34785484513745385737, 0.65214515486254614263, 0.65214515486254614263,
@@ -211,7 +229,7 @@ bool hex64_element(const double X[64][3], const double Dn[64][9], double* Me, do
         const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
                            J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
                            J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
-        if (!(det > 0.0)) return false;
+        if (!(det > 0.0)) return 1;
         double Ji[3][3];
         Ji[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
         Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
@@ -229,6 +247,7 @@ bool hex64_element(const double X[64][3], const double Dn[64][9], double* Me, do
         double Dq[9] = {0};
         for (int k = 0; k < 64; k++)
           for (int e = 0; e < 9; e++) Dq[e] += N[k] * Dn[k][e];
+        if (!psd3(Dq)) return 2;
         double DG[64][3];
         for (int k = 0; k < 64; k++)
           for (int r = 0; r < 3; r++)
@@ -240,7 +259,7 @@ bool hex64_element(const double X[64][3], const double Dn[64][9], double* Me, do
             Ke[64 * a + b] += w * (G[a][0] * DG[b][0] + G[a][1] * DG[b][1] + G[a][2] * DG[b][2]);
           }
       }
-  return true;
+  return 0;
 }
 
 // Gauss-Legendre points and weights of order n on [-1, 1]: Newton's method on
@@ -272,8 +291,8 @@ static void gauss_legendre(int n, double* x, double* w) {
 // k = a + (p + 1) b + (p + 1)^2 c at the reference point
 // (2a/p - 1, 2b/p - 1, 2c/p - 1); isoparametric map; (p + 1)^3 Gauss-Legendre
 // points (exact for the mass matrix of an affine element).
-bool hexp_element(int p, const double (*X)[3], const double (*Dn)[9], double* Me, double* Ke) {
-  if (p < 4 || p > 6) return false;
+int hexp_element(int p, const double (*X)[3], const double (*Dn)[9], double* Me, double* Ke) {
+  if (p < 4 || p > 6) return 1;
   const int n1 = p + 1, npe = n1 * n1 * n1;
   double gp[7], gw[7], z[7];
   gauss_legendre(n1, gp, gw);
@@ -315,7 +334,7 @@ bool hexp_element(int p, const double (*X)[3], const double (*Dn)[9], double* Me
         const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
                            J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
                            J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
-        if (!(det > 0.0)) return false;
+        if (!(det > 0.0)) return 1;
         double Ji[3][3];
         Ji[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
         Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
@@ -332,6 +351,7 @@ bool hexp_element(int p, const double (*X)[3], const double (*Dn)[9], double* Me
         double Dq[9] = {0};
         for (int k = 0; k < npe; k++)
           for (int e = 0; e < 9; e++) Dq[e] += N[k] * Dn[k][e];
+        if (!psd3(Dq)) return 2;
         for (int k = 0; k < npe; k++)
           for (int r = 0; r < 3; r++)
             DG[3 * k + r] = Dq[3 * r] * G[3 * k] + Dq[3 * r + 1] * G[3 * k + 1] + Dq[3 * r + 2] * G[3 * k + 2];
@@ -347,7 +367,7 @@ bool hexp_element(int p, const double (*X)[3], const double (*Dn)[9], double* Me
           }
         }
       }
-  return true;
+  return 0;
 }
 
 // Quadratic tetrahedron (10 nodes: vertices 0-3, then the nodes of the edges
@@ -358,7 +378,7 @@ bool hexp_element(int p, const double (*X)[3], const double (*Dn)[9], double* Me
 // unit cube collapsed onto the tetrahedron (64 points, exact to degree 5 in
 // the barycentric coordinates).  The Jacobian determinant must keep the
 // sign of the vertex orientation at every point (no folded element).
-bool tet10_element(const double X[10][3], const double Dn[10][9], double* Me, double* Ke) {
+int tet10_element(const double X[10][3], const double Dn[10][9], double* Me, double* Ke) {
   static const double gx[4] = {0.06943184420297371, 0.33000947820757187, 0.66999052179242813,
                                0.93056815579702629};  // Gauss-Legendre nodes on [0, 1]
   static const double gw[4] = {0.17392742256872693, 0.32607257743127307, 0.32607257743127307,
@@ -372,7 +392,7 @@ bool tet10_element(const double X[10][3], const double Dn[10][9], double* Me, do
   const double det0 = E[0][0] * (E[1][1] * E[2][2] - E[1][2] * E[2][1]) -
                       E[0][1] * (E[1][0] * E[2][2] - E[1][2] * E[2][0]) +
                       E[0][2] * (E[1][0] * E[2][1] - E[1][1] * E[2][0]);
-  if (det0 == 0.0 || !std::isfinite(det0)) return false;
+  if (det0 == 0.0 || !std::isfinite(det0)) return 1;
   const double orient = det0 > 0.0 ? 1.0 : -1.0;
   std::memset(Me, 0, 100 * sizeof(double));
   std::memset(Ke, 0, 100 * sizeof(double));
@@ -402,7 +422,7 @@ bool tet10_element(const double X[10][3], const double Dn[10][9], double* Me, do
         const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
                            J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
                            J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
-        if (!(orient * det > 0.0)) return false;
+        if (!(orient * det > 0.0)) return 1;
         double Ji[3][3];
         Ji[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
         Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
@@ -422,6 +442,7 @@ bool tet10_element(const double X[10][3], const double Dn[10][9], double* Me, do
         double Dq[9] = {0};
         for (int a = 0; a < 10; a++)
           for (int t = 0; t < 9; t++) Dq[t] += N[a] * Dn[a][t];
+        if (!psd3(Dq)) return 2;
         double DG[10][3];
         for (int a = 0; a < 10; a++)
           for (int r = 0; r < 3; r++)
@@ -432,20 +453,20 @@ bool tet10_element(const double X[10][3], const double Dn[10][9], double* Me, do
             Ke[10 * a + b] += wq * (G[a][0] * DG[b][0] + G[a][1] * DG[b][1] + G[a][2] * DG[b][2]);
           }
       }
-  return true;
+  return 0;
 }
 
 // Linear tetrahedron.  Gradients of the barycentric coordinates are constant;
 // with D interpolated linearly, the degree-2 rule reduces exactly to
 // K = V G^T mean(D) G, and M = V (1 + delta_ab)/20.
-bool tet_element(const double X[4][3], const double Dn[4][9], double Me[16], double Ke[16]) {
+int tet_element(const double X[4][3], const double Dn[4][9], double Me[16], double Ke[16]) {
   double E[3][3];
   for (int r = 0; r < 3; r++)
     for (int c = 0; c < 3; c++) E[r][c] = X[r + 1][c] - X[0][c];
   const double det = E[0][0] * (E[1][1] * E[2][2] - E[1][2] * E[2][1]) -
                      E[0][1] * (E[1][0] * E[2][2] - E[1][2] * E[2][0]) +
                      E[0][2] * (E[1][0] * E[2][1] - E[1][1] * E[2][0]);
-  if (det == 0.0 || !std::isfinite(det)) return false;
+  if (det == 0.0 || !std::isfinite(det)) return 1;
   const double vol = std::fabs(det) / 6.0;
   // rows of E^{-T} ... gradient of L_{r+1} is column r of E^{-1}
   double Ei[3][3];
@@ -472,7 +493,7 @@ bool tet_element(const double X[4][3], const double Dn[4][9], double Me[16], dou
         for (int c = 0; c < 3; c++) acc += G[a][r] * Dm[3 * r + c] * G[b][c];
       Ke[4 * a + b] = vol * acc;
     }
-  return true;
+  return 0;
 }
 
 }  // namespace
@@ -507,37 +528,6 @@ bool assemble_csr(int elem, int64_t n_nodes, const double* xyz, int64_t n_elems,
       for (int k = 0; k < npe; k++) ne_idx[fill[conn[e * npe + k]]++] = e * npe + k;  // element*npe + local
   }
 
-  // element matrices
-  std::vector<double> Me((size_t)n_elems * npe * npe), Ke((size_t)n_elems * npe * npe);
-  std::vector<char> bad(1, 0);
-  static const double ex[3] = {1, 0, 0}, ey[3] = {0, 1, 0}, ez[3] = {0, 0, 1};
-  parallel_for(n_elems, [&](int64_t e) {
-    double X[343][3], Dn[343][9];
-    const int r = region ? region[e] : 0;
-    const double sl = region ? region_sigma[3 * r] : sigma_l;
-    const double st = region ? region_sigma[3 * r + 1] : sigma_t;
-    const double sn = region ? region_sigma[3 * r + 2] : sigma_n;
-    for (int k = 0; k < npe; k++) {
-      const int64_t v = conn[e * npe + k];
-      for (int c = 0; c < 3; c++) X[k][c] = xyz[3 * v + c];
-      const double* f = f0 ? f0 + 3 * v : ex;
-      const double* s = s0 ? s0 + 3 * v : ey;
-      const double* nn = n0 ? n0 + 3 * v : ez;
-      nodal_tensor(f, s, nn, sl, st, sn, scale, Dn[k]);
-    }
-    const size_t eo = (size_t)e * npe * npe;
-    bool ok = (npe >= 125) ? hexp_element(npe == 125 ? 4 : npe == 216 ? 5 : 6, X, Dn, &Me[eo], &Ke[eo])
-              : (npe == 64) ? hex64_element(X, Dn, &Me[e * 64 * 64], &Ke[e * 64 * 64])
-              : (npe == 27) ? hex27_element(X, Dn, &Me[e * 27 * 27], &Ke[e * 27 * 27])
-              : (npe == 10) ? tet10_element(X, Dn, &Me[e * 100], &Ke[e * 100])
-              : (npe == 8)  ? hex_element(X, Dn, &Me[e * 64], &Ke[e * 64])
-                            : tet_element(X, Dn, &Me[e * 16], &Ke[e * 16]);
-    if (!ok) bad[0] = 1;
-    if (region && region_on && !region_on[r])
-      for (int k = 0; k < npe * npe; k++) Me[e * npe * npe + k] = Ke[e * npe * npe + k] = 0.0;
-  });
-  if (bad[0]) { set_err(err, "degenerate or inverted element"); return false; }
-
   // sparsity pattern: row i = union of the nodes of its elements
   A.n = n_nodes;
   A.rowptr.assign(n_nodes + 1, 0);
@@ -564,23 +554,75 @@ bool assemble_csr(int elem, int64_t n_nodes, const double* xyz, int64_t n_elems,
   parallel_for(n_nodes, [&](int64_t i) {
     thread_local std::vector<int32_t> buf;
     gather_row(i, buf);
-    const int len = (int)buf.size();
-    int32_t* c = &A.col[A.rowptr[i]];
-    std::copy(buf.begin(), buf.end(), c);
-    double* m = &A.valM[A.rowptr[i]];
-    double* kk = &A.valK[A.rowptr[i]];
-    // row i gathers the element rows of its local index
-    for (int64_t t = ne_ptr[i]; t < ne_ptr[i + 1]; t++) {
-      const int64_t e = ne_idx[t] / npe;
-      const int a = (int)(ne_idx[t] % npe);
-      for (int b = 0; b < npe; b++) {
-        const int32_t j = conn[e * npe + b];
-        const int pos = (int)(std::lower_bound(c, c + len, j) - c);
-        m[pos] += Me[(e * npe + a) * npe + b];
-        kk[pos] += Ke[(e * npe + a) * npe + b];
-      }
-    }
+    std::copy(buf.begin(), buf.end(), &A.col[A.rowptr[i]]);
   });
+
+  // element matrices, in chunks of elements whose matrices take at most
+  // about 256 MiB (a degree-6 element alone holds 343^2 entries of M and K,
+  // 1.9 MB), each chunk added row by row into the pattern above
+  const int64_t per_elem = (int64_t)npe * npe;
+  const int64_t chunk = std::max<int64_t>(1, ((int64_t)1 << 28) / (per_elem * 2 * (int64_t)sizeof(double)));
+  std::vector<double> Me((size_t)std::min(chunk, n_elems) * per_elem), Ke(Me.size());
+  std::vector<char> bad(2, 0);   // [0]: degenerate or inverted element, [1]: indefinite tensor
+  static const double ex[3] = {1, 0, 0}, ey[3] = {0, 1, 0}, ez[3] = {0, 0, 1};
+  for (int64_t e0 = 0; e0 < n_elems; e0 += chunk) {
+    const int64_t e1 = std::min(n_elems, e0 + chunk);
+    parallel_for(e1 - e0, [&](int64_t le) {
+      const int64_t e = e0 + le;
+      double X[343][3], Dn[343][9];
+      const int r = region ? region[e] : 0;
+      const double sl = region ? region_sigma[3 * r] : sigma_l;
+      const double st = region ? region_sigma[3 * r + 1] : sigma_t;
+      const double sn = region ? region_sigma[3 * r + 2] : sigma_n;
+      for (int k = 0; k < npe; k++) {
+        const int64_t v = conn[e * npe + k];
+        for (int c = 0; c < 3; c++) X[k][c] = xyz[3 * v + c];
+        const double* f = f0 ? f0 + 3 * v : ex;
+        const double* s = s0 ? s0 + 3 * v : ey;
+        const double* nn = n0 ? n0 + 3 * v : ez;
+        nodal_tensor(f, s, nn, sl, st, sn, scale, Dn[k]);
+      }
+      double* me = &Me[(size_t)le * per_elem];
+      double* ke = &Ke[(size_t)le * per_elem];
+      const int rc = (npe >= 125) ? hexp_element(npe == 125 ? 4 : npe == 216 ? 5 : 6, X, Dn, me, ke)
+                     : (npe == 64) ? hex64_element(X, Dn, me, ke)
+                     : (npe == 27) ? hex27_element(X, Dn, me, ke)
+                     : (npe == 10) ? tet10_element(X, Dn, me, ke)
+                     : (npe == 8)  ? hex_element(X, Dn, me, ke)
+                                   : tet_element(X, Dn, me, ke);
+      if (rc == 1) bad[0] = 1;
+      if (rc == 2) bad[1] = 1;
+      if (region && region_on && !region_on[r])
+        for (int64_t k = 0; k < per_elem; k++) me[k] = ke[k] = 0.0;
+    });
+    if (bad[0]) { set_err(err, "degenerate or inverted element"); return false; }
+    if (bad[1]) {
+      set_err(err, "the diffusion tensor interpolated from the nodal fibers is indefinite at a quadrature point "
+                   "(the fiber field varies too abruptly for this element degree)");
+      return false;
+    }
+    // row i gathers the element rows of its local index, for the elements of
+    // this chunk (a node's incidences are listed in increasing element order)
+    parallel_for(n_nodes, [&](int64_t i) {
+      const int32_t* c = &A.col[A.rowptr[i]];
+      const int len = (int)(A.rowptr[i + 1] - A.rowptr[i]);
+      double* m = &A.valM[A.rowptr[i]];
+      double* kk = &A.valK[A.rowptr[i]];
+      const int64_t* lo = std::lower_bound(&ne_idx[ne_ptr[i]], &ne_idx[ne_ptr[i + 1]], e0 * npe);
+      for (const int64_t* t = lo; t < &ne_idx[0] + ne_ptr[i + 1] && *t < e1 * npe; t++) {
+        const int64_t e = *t / npe;
+        const int a = (int)(*t % npe);
+        const double* mrow = &Me[((size_t)(e - e0) * npe + a) * npe];
+        const double* krow = &Ke[((size_t)(e - e0) * npe + a) * npe];
+        for (int b = 0; b < npe; b++) {
+          const int32_t j = conn[e * npe + b];
+          const int pos = (int)(std::lower_bound(c, c + len, j) - c);
+          m[pos] += mrow[b];
+          kk[pos] += krow[b];
+        }
+      }
+    });
+  }
   return true;
 }
 

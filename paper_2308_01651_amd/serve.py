@@ -38,8 +38,10 @@ class Record:
 
 
 def serve(requests, hbm_budget_bytes: int, max_slots: int, precision: int = EP_FP64,
-          steps_per_tick: int = 20, device: int = 0, progress=None) -> dict:
-    """Run a trace of workloads.Request to completion; returns records and aggregates."""
+          steps_per_tick: int = 20, device: int = 0, progress=None, on_done=None) -> dict:
+    """Run a trace of workloads.Request to completion; returns records and
+    aggregates.  on_done(request index, Simulation), if given, is called for
+    each finished request before its simulation is freed (to read results)."""
     reqs = sorted(enumerate(requests), key=lambda t: t[1].arrival_s)
     recs: List[Record] = [Record(i, r.spec.mesh.n_nodes, r.spec.n_steps, r.arrival_s) for i, r in reqs]
     by_id = {r.rid: r for r in recs}
@@ -74,6 +76,8 @@ def serve(requests, hbm_budget_bytes: int, max_slots: int, precision: int = EP_F
             rid = slot_of.pop(slot)
             by_id[rid].done_s = time.perf_counter() - t0
             by_id[rid].status = int(st)
+            if on_done is not None:
+                on_done(rid, sim)
             sim.close()
             pending -= 1
         if progress and time.perf_counter() - t0 - last_print > 5.0:

@@ -1,8 +1,8 @@
-"""GPU: hexahedra of degree 2 to 5 ((p + 1)^3 nodes) and quadratic (10-node)
+"""GPU: hexahedra of degree 2 to 6 ((p + 1)^3 nodes) and quadratic (10-node)
 tetrahedra against the oracle.
 
 The operators of these lattices ((2p + 1)^3 entries in a row of an element
-vertex: 125 for Q2 up to 1,331 for Q5) are stored in the sliced-ELL format; everything else (ionic step at every node, ICI load,
+vertex: 125 for Q2 up to 2,197 for Q6) are stored in the sliced-ELL format; everything else (ionic step at every node, ICI load,
 PCG, activation) is the path of the other elements.  Tolerances as for Q1:
 a single step at rtol 1e-13 to 1e-10 relative, trajectories at rtol 1e-10 to
 1e-8 with activation times to the time step, mixed precision against FP64
@@ -27,7 +27,7 @@ def _rel(a, b):
 
 
 def _spec(dims=(4.0, 2.0, 1.0), h=0.5, model="ttp06", variant="endo", bdf=2, curved=False, kind="q2"):
-    if kind in ("q4", "q5"):
+    if kind in ("q4", "q5", "q6"):
         mesh = W.slab_qp(*dims, h, int(kind[1]))
     else:
         mesh = {"q2": W.slab_q2, "q3": W.slab_q3, "p2": W.slab_p2}[kind](*dims, h)
@@ -35,11 +35,11 @@ def _spec(dims=(4.0, 2.0, 1.0), h=0.5, model="ttp06", variant="endo", bdf=2, cur
         rng = np.random.default_rng(8)
         mesh.xyz = mesh.xyz + rng.uniform(-0.02, 0.02, mesh.xyz.shape)
     st = [W.corner_cube_stimulus(dims=dims)]
-    # degree >= 4: the equispaced Lagrange basis has large negative lobes, so
-    # a nodal D that jumps from node to node (random fibers) interpolates to
-    # an indefinite tensor at some quadrature points and K loses definiteness;
-    # these elements get a smooth (transmurally rotating) fiber field
-    fib = W.rotating_fibers(mesh.xyz) if kind in ("q4", "q5") else W.random_fibers(mesh.n_nodes, 9)
+    # the Lagrange basis of degree >= 2 has negative lobes, so a nodal D that
+    # jumps from node to node (random fibers) interpolates to an indefinite
+    # tensor at some quadrature points, which finalize rejects; these
+    # elements get a smooth fiber field that turns in all three directions
+    fib = W.smooth_fibers(mesh.xyz, 9)
     return W.SimSpec(mesh, fib, W.Physics(), model, variant, st, 0.05, bdf, 1, 1e-10, "t")
 
 
@@ -49,6 +49,7 @@ def _spec(dims=(4.0, 2.0, 1.0), h=0.5, model="ttp06", variant="endo", bdf=2, cur
                                                            ("q3", "bo", "epi", 3, True),
                                                            ("q4", "ttp06", "endo", 2, False),
                                                            ("q5", "bo", "epi", 3, False),
+                                                           ("q6", "ttp06", "endo", 2, False),
                                                            ("p2", "ttp06", "epi", 2, False),
                                                            ("p2", "ttp06", "endo", 2, True),
                                                            ("p2", "bo", "epi", 2, False)])
@@ -75,10 +76,11 @@ def test_quadratic_single_step(kind, model, variant, bdf, curved):
         assert err < 1e-11, (v, err)
 
 
-@pytest.mark.parametrize("kind,prec", [("q2", 0), ("q2", 1), ("q3", 0), ("q3", 1), ("q4", 0), ("p2", 0)])
+@pytest.mark.parametrize("kind,prec", [("q2", 0), ("q2", 1), ("q3", 0), ("q3", 1), ("q4", 0), ("q4", 1), ("q5", 0),
+                                       ("p2", 0)])
 def test_quadratic_trajectory(kind, prec):
     ep = _ep()
-    spec = _spec(dims=(6.0, 3.0, 1.0), h=0.5, kind=kind)
+    spec = _spec(dims=(6.0, 3.0, 1.0), h=0.5 if kind != "q5" else 1.0, kind=kind)
     o = OM.from_spec(spec, solver="splu")
     ref = ep.Simulation.from_spec(spec)
     sim = ep.Simulation.from_spec(spec, precision=prec)

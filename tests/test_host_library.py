@@ -4,7 +4,8 @@
 - the library's C++ finite-element assembly matches the oracle's assembly
   (written independently) on hexahedral (trilinear and triquadratic),
   tetrahedral (linear and quadratic) and curved LV meshes;
-- invalid input is rejected with a status and a message.
+- invalid input is rejected with a status and a message, including a fiber
+  field whose interpolated diffusion tensor is indefinite.
 """
 import ctypes as C
 import os
@@ -81,14 +82,14 @@ def test_assembly_matches_oracle_q2_slab():
     m = W.slab_q2(3.0, 2.0, 1.0, 0.5)
     rng = np.random.default_rng(6)
     m.xyz = m.xyz + rng.uniform(-0.03, 0.03, m.xyz.shape)   # curved (isoparametric) elements
-    _compare(m, W.random_fibers(m.n_nodes, 14))
+    _compare(m, W.smooth_fibers(m.xyz, 14))
 
 
 def test_assembly_matches_oracle_q3_slab():
     m = W.slab_q3(2.0, 1.0, 1.0, 0.5)
     rng = np.random.default_rng(16)
     m.xyz = m.xyz + rng.uniform(-0.02, 0.02, m.xyz.shape)   # curved (isoparametric) elements
-    _compare(m, W.random_fibers(m.n_nodes, 17))
+    _compare(m, W.smooth_fibers(m.xyz, 17))
 
 
 @pytest.mark.parametrize("p", [4, 5, 6])
@@ -97,7 +98,7 @@ def test_assembly_matches_oracle_degree_p_hex(p):
     rng = np.random.default_rng(30 + p)
     # curved (isoparametric) elements; 2 % of the node spacing keeps det J > 0
     m.xyz = m.xyz + rng.uniform(-0.02 / p, 0.02 / p, m.xyz.shape)
-    _compare(m, W.random_fibers(m.n_nodes, 19))
+    _compare(m, W.smooth_fibers(m.xyz, 19))
 
 
 @pytest.mark.parametrize("curved", [False, True])
@@ -106,7 +107,7 @@ def test_assembly_matches_oracle_p2_slab(curved):
     if curved:   # edge nodes off the midpoints: isoparametric elements
         rng = np.random.default_rng(18)
         m.xyz = m.xyz + rng.uniform(-0.03, 0.03, m.xyz.shape)
-    _compare(m, W.random_fibers(m.n_nodes, 15))
+    _compare(m, W.smooth_fibers(m.xyz, 15))
 
 
 def test_invalid_input_is_rejected():
@@ -145,3 +146,40 @@ def test_folded_quadratic_tetrahedron_is_rejected():
     with pytest.raises(ep.EpError):
         ep.assemble_csr(m.elem, xyz, m.conn, None, (0.17, 0.019, 0.019), 140.0, 0.01)
     ep.assemble_csr(m.elem, m.xyz, m.conn, None, (0.17, 0.019, 0.019), 140.0, 0.01)
+
+
+@pytest.mark.parametrize("kind", ["q2", "q4", "p2"])
+def test_indefinite_interpolated_tensor_is_rejected(kind):
+    """Elements of degree >= 2 interpolate the nodal tensor with a basis that
+    has negative lobes: fibers drawn at random per node leave the cone of
+    positive semi-definite tensors at some quadrature point, and K would not
+    be positive semi-definite.  Assembly refuses such input (EP_EINVAL); the
+    same mesh with a smooth field, and linear elements with random fibers,
+    are accepted."""
+    import paper_2308_01651_amd as ep
+    m = {"q2": lambda: W.slab_q2(3.0, 2.0, 1.0, 0.5), "q4": lambda: W.slab_qp(2.0, 1.0, 1.0, 0.5, 4),
+         "p2": lambda: W.slab_p2(3.0, 2.0, 1.0, 0.5)}[kind]()
+    with pytest.raises(ep.EpError) as ei:
+        ep.assemble_csr(m.elem, m.xyz, m.conn, W.random_fibers(m.n_nodes, 9))
+    assert ei.value.status == ep._lib.EP_EINVAL and "indefinite" in str(ei.value)
+    ep.assemble_csr(m.elem, m.xyz, m.conn, W.smooth_fibers(m.xyz, 9))
+    m1 = W.slab_q1(2.0, 1.0, 1.0, 0.25)
+    ep.assemble_csr(m1.elem, m1.xyz, m1.conn, W.random_fibers(m1.n_nodes, 9))
+    p1 = W.slab_p1(2.0, 1.0, 1.0, 0.25)
+    ep.assemble_csr(p1.elem, p1.xyz, p1.conn, W.random_fibers(p1.n_nodes, 9))
+
+
+def test_degree_six_element_matrices_are_assembled_in_chunks():
+    """150 degree-6 hexahedra need 282 MB of element matrices; assembly holds
+    at most 256 MiB of them at a time (two chunks here) and the result keeps
+    the exact volume and the constants in the kernel of K (the per-degree
+    comparison with the oracle above covers a single chunk)."""
+    import paper_2308_01651_amd as ep
+    m = W.slab_qp(6.0, 5.0, 5.0, 1.0, 6)     # 6 x 5 x 5 elements of 1 mm
+    assert m.conn.shape[0] * 343 * 343 * 16 > (1 << 28)
+    rowptr, col, vm, vk = ep.assemble_csr(m.elem, m.xyz, m.conn, W.smooth_fibers(m.xyz, 3))
+    import scipy.sparse as sp
+    M = sp.csr_matrix((vm, col, rowptr), shape=(m.n_nodes, m.n_nodes))
+    K = sp.csr_matrix((vk, col, rowptr), shape=(m.n_nodes, m.n_nodes))
+    assert abs(M.sum() - 150.0) < 1e-10 * 150.0        # volume of the block
+    assert np.max(np.abs(K @ np.ones(m.n_nodes))) < 1e-12 * abs(K).max()

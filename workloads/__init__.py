@@ -260,6 +260,29 @@ def rotating_fibers(xyz: np.ndarray, angle0: float = -60.0, angle1: float = 60.0
     return F, S, N
 
 
+def smooth_fibers(xyz: np.ndarray, seed: int, rate: float = 0.25):
+    """Orthonormal triplets that turn smoothly through space in all three
+    directions: the fiber's azimuth and elevation and the sheet's roll are
+    sums of seeded low-frequency waves of the coordinates, each changing by
+    at most about `rate` radians per mm (a varied tensor that stays as smooth
+    as a myocardial fiber field)."""
+    rng = np.random.default_rng(seed)
+    ang = []
+    for _ in range(3):
+        k = rng.uniform(-1.0, 1.0, (3, 3))
+        ph = rng.uniform(0.0, 2.0 * np.pi, 3)
+        a = sum(np.sin(xyz @ k[j] + ph[j]) / (3.0 * max(np.abs(k[j]).sum(), 1e-12)) for j in range(3))
+        ang.append(rate * 3.0 * a)
+    az, el, roll = ang
+    f = np.stack([np.cos(az) * np.cos(el), np.sin(az) * np.cos(el), np.sin(el)], axis=1)
+    # a unit vector orthogonal to f, then turned about f by the roll angle
+    e = np.stack([-np.sin(az), np.cos(az), np.zeros_like(az)], axis=1)
+    g = np.cross(f, e)
+    s = np.cos(roll)[:, None] * e + np.sin(roll)[:, None] * g
+    n = np.cross(f, s)
+    return f, s, n
+
+
 def random_fibers(n_nodes: int, seed: int):
     """Random orthonormal triplets per node (for anisotropy tests)."""
     rng = np.random.default_rng(seed)
