@@ -361,6 +361,26 @@ ep_status ep_cell_pace(int device, int model, int variant, int n_cells, const do
                        const double* init, double dt_ms, int bdf_order, double period_ms, double stim_mV_per_ms,
                        double stim_dur_ms, int n_beats, double* out);
 
+/* ep_cell_pace for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same pacing and arithmetic, enqueued on hip_stream (NULL: the null
+ * stream) of `device`, calling no hipMalloc, hipFree or stream creation and
+ * not synchronizing.  params [n_cells][n_params] (or NULL), init
+ * [n_cells][1 + n_vars] (or NULL) and out [n_cells][1 + n_vars] are DEVICE
+ * pointers owned by the caller, laid out as in ep_cell_pace; out is valid once
+ * the stream has reached the call (a cell that produced NaN shows NaN in out;
+ * no status reports it).  The cells' potential history, state and parameter
+ * rows are staged in a fixed device array of the library (about 6.9 MB per
+ * device, held until the process ends), so n_cells is limited to 16384
+ * (EP_EINVAL beyond).  Every call on a device uses that device's one array:
+ * calls that overlap on one device (different streams, or threads without
+ * ordering) race and give undefined results.  EP_EINVAL for bad arguments,
+ * EP_EHIP if a launch fails. */
+ep_status ep_cell_pace_device(int device, void* hip_stream, int model, int variant, int n_cells,
+                              const double* params, int n_params, const double* init, double dt_ms,
+                              int bdf_order, double period_ms, double stim_mV_per_ms, double stim_dur_ms,
+                              int n_beats, double* out);
+
 /* ---- host-only entry points (no GPU needed) -------------------------------- */
 
 /* The library's finite-element assembly, for inspection: CSR of M and K

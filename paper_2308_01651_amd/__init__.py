@@ -326,6 +326,19 @@ def cell_pace(model, variant="", n_cells=1, params=None, init=None, dt=0.05, bdf
     return out
 
 
+def cell_pace_device(model, variant="", n_cells=1, params_ptr=0, n_params=0, init_ptr=0, out_ptr=0, dt=0.05,
+                     bdf=2, period=800.0, stim_mV_per_ms=40.0, stim_dur=1.0, n_beats=1, device=0, stream=0):
+    """ep_cell_pace_device: ep_cell_pace on caller-owned device buffers (raw
+    device addresses, e.g. torch tensors' data_ptr()), enqueued on `stream`
+    without allocating or synchronizing."""
+    check(lib.ep_cell_pace_device(int(device), C.c_void_p(stream) if stream else None, MODEL_IDS[model],
+                                  CELL_IDS.get(variant, 0), int(n_cells),
+                                  C.c_void_p(params_ptr) if params_ptr else None, int(n_params),
+                                  C.c_void_p(init_ptr) if init_ptr else None, float(dt), int(bdf), float(period),
+                                  float(stim_mV_per_ms), float(stim_dur), int(n_beats), C.c_void_p(out_ptr)),
+          "ep_cell_pace_device")
+
+
 def assemble_csr(elem, xyz, conn, fibers=None, sigma=(0.17, 0.019, 0.019), chi=140.0, cm=0.01):
     """The library's host-side FE assembly (ep_assemble_csr): (rowptr, col, valM, valK)."""
     xyz = _f64(xyz)

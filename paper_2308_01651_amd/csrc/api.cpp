@@ -1728,6 +1728,51 @@ ep_status ep_cell_pace(int device, int model, int variant, int n_cells, const do
   return EP_OK;
 }
 
+ep_status ep_cell_pace_device(int device, void* hip_stream, int model, int variant, int n_cells, const double* params,
+                              int n_params, const double* init, double dt_ms, int bdf_order, double period_ms,
+                              double stim_mV_per_ms, double stim_dur_ms, int n_beats, double* out) {
+  if (model < EP_PASSIVE || model > EP_TTP06) return fail(EP_EINVAL, "unknown ionic model");
+  if (model == EP_TTP06 && (variant < 0 || variant > 2)) return fail(EP_EINVAL, "bad TTP06 cell type");
+  if (n_cells < 1 || !out || !(dt_ms > 0) || bdf_order < 1 || bdf_order > 3 || !(period_ms > 0) ||
+      !(stim_dur_ms >= 0) || n_beats < 0 || n_params < 0 || n_params > n_model_params(model) ||
+      (n_params > 0 && !params))
+    return fail(EP_EINVAL, "bad pacing arguments");
+  if (n_cells > PACE_MAX_CELLS)
+    return fail(EP_EINVAL, "ep_cell_pace_device: more than " + std::to_string(PACE_MAX_CELLS) +
+                               " cells (the size of its fixed device scratch); use ep_cell_pace");
+  int count = 0;
+  EP_HIP(hipGetDeviceCount(&count));
+  if (device < 0 || device >= count) return fail(EP_EINVAL, "no such device");
+  EP_HIP(hipSetDevice(device));
+  double* base = nullptr;
+  EP_HIP(pace_scratch(device, &base));
+  const ModelInfo mi = model_info(model);
+  const int nv = mi.nvars, nc = n_cells;
+  PaceDefaults def{};
+  default_params(model, variant, def.mp);
+  const std::vector<double> ic = default_init(model);
+  for (size_t k = 0; k < ic.size() && k < 19; k++) def.init[k] = ic[k];
+  // scratch layout: uh [3][nc], w [18][nc], parameter rows [nc][NPARAM]
+  double* d_uh = base;
+  double* d_w = d_uh + (size_t)3 * nc;
+  double* d_mp = d_w + (size_t)18 * nc;
+  hipStream_t st = (hipStream_t)hip_stream;
+  launch_pace_stage(def, n_params > 0 ? params : nullptr, n_params, init, nv, nc, d_uh, d_w, d_mp, st);
+  EP_HIP(hipGetLastError());
+  const int64_t period = std::max<int64_t>(1, (int64_t)std::llround(period_ms / dt_ms));
+  const int64_t dur = (int64_t)std::llround(stim_dur_ms / dt_ms);
+  const int64_t total = (int64_t)n_beats * period;
+  const int64_t chunk = 20000;  // bounds each launch's duration
+  for (int64_t s0 = 0; s0 < total; s0 += chunk) {
+    launch_cell_pace(model, d_uh, d_w, d_mp, nc, dt_ms, bdf_order, s0, std::min(chunk, total - s0), period, dur,
+                     stim_mV_per_ms / mi.mv_per_unit, st);
+    EP_HIP(hipGetLastError());
+  }
+  launch_pace_unstage(d_uh, d_w, nv, nc, out, st);
+  EP_HIP(hipGetLastError());
+  return EP_OK;
+}
+
 ep_status ep_assemble_csr(int elem, int64_t n_nodes, const double* xyz, int64_t n_elems, const int32_t* conn,
                           const double* f0, const double* s0, const double* n0, double sl, double st, double sn,
                           double chi, double cm, int64_t* nnz_out, int64_t* rowptr, int32_t* col, double* valM,

@@ -8,6 +8,8 @@
 // launches chunks until the requested number of beats is done.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "ep_device.h"
 #include "ionic_models.h"
 #include "kernels.h"
@@ -69,6 +71,75 @@ __global__ __launch_bounds__(256) void k_cell_pace(double* __restrict__ uh, doub
 #pragma unroll
   for (int v = 0; v < 18; v++)
     if (v < nv) w[(int64_t)v * nc + c] = x[v];
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free pacing: the staging of the cells' potential history, state
+// and parameter rows lives in one file-scope device array.  Host code never
+// uses the array's name as an address: each device's copy is looked up once
+// with hipGetSymbolAddress and that pointer is what the kernels receive.
+// ---------------------------------------------------------------------------
+
+static __device__ __align__(256) double scratch[PACE_SCRATCH_DOUBLES];
+
+namespace {
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[PACE_MAX_DEVICES] = {};
+}  // namespace
+
+hipError_t pace_scratch(int device, double** ptr) {
+  *ptr = nullptr;
+  if (device < 0 || device >= PACE_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    // the caller has made `device` current
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = static_cast<double*>(p);
+  }
+  *ptr = g_scratch_ptr[device];
+  return hipSuccess;
+}
+
+// Staging of nc cells into the scratch layout the pacing kernel reads:
+// parameter rows (defaults, then the first n_params entries of the cell's
+// row of params when params is given), the potential history (three copies
+// of the starting u) and the state rows [var][cell].  init: [nc][1 + nv] or
+// null (the model's initial conditions for every cell).
+__global__ __launch_bounds__(256) void k_pace_stage(PaceDefaults def, const double* __restrict__ params,
+                                                    int n_params, const double* __restrict__ init, int nv, int nc,
+                                                    double* __restrict__ uh, double* __restrict__ w,
+                                                    double* __restrict__ mp) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  for (int k = 0; k < NPARAM; k++)
+    mp[(int64_t)c * NPARAM + k] = (params && k < n_params) ? params[(int64_t)c * n_params + k] : def.mp[k];
+  const double u0 = init ? init[(int64_t)c * (1 + nv)] : def.init[0];
+  for (int k = 0; k < 3; k++) uh[(int64_t)k * nc + c] = u0;
+  for (int v = 0; v < nv; v++) w[(int64_t)v * nc + c] = init ? init[(int64_t)c * (1 + nv) + 1 + v] : def.init[1 + v];
+}
+
+// Paced cells back into rows [nc][1 + nv] (u, then the state).
+__global__ __launch_bounds__(256) void k_pace_unstage(const double* __restrict__ uh, const double* __restrict__ w,
+                                                      int nv, int nc, double* __restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  out[(int64_t)c * (1 + nv)] = uh[c];
+  for (int v = 0; v < nv; v++) out[(int64_t)c * (1 + nv) + 1 + v] = w[(int64_t)v * nc + c];
+}
+
+void launch_pace_stage(const PaceDefaults& def, const double* params, int n_params, const double* init, int nv,
+                       int nc, double* uh, double* w, double* mp, hipStream_t st) {
+  if (nc <= 0) return;
+  hipLaunchKernelGGL(k_pace_stage, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st, def, params, n_params,
+                     init, nv, nc, uh, w, mp);
+}
+
+void launch_pace_unstage(const double* uh, const double* w, int nv, int nc, double* out, hipStream_t st) {
+  if (nc <= 0) return;
+  hipLaunchKernelGGL(k_pace_unstage, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st, uh, w, nv, nc, out);
 }
 
 void launch_cell_pace(int model, double* uh, double* w, const double* params, int nc, double dt, int bdf,

@@ -49,4 +49,23 @@ void launch_ici_correction(InstDesc* insts, int64_t n_crow, hipStream_t st);
 void launch_cell_pace(int model, double* uh, double* w, const double* params, int nc, double dt, int bdf,
                       int64_t step0, int64_t n_steps, int64_t period, int64_t dur, double amp, hipStream_t st);
 
+
+// Allocation-free pacing (cell.hip).  The staging of up to PACE_MAX_CELLS
+// cells (potential history [3][nc], state [18][nc], parameter rows
+// [nc][NPARAM]) lives in a file-scope device array of PACE_SCRATCH_DOUBLES
+// doubles, one copy per device, shared by every call on that device.
+constexpr int PACE_MAX_CELLS = 16384;
+constexpr int PACE_MAX_DEVICES = 64;
+constexpr size_t PACE_SCRATCH_DOUBLES = (size_t)PACE_MAX_CELLS * (3 + 18 + NPARAM);
+struct PaceDefaults {
+  double mp[NPARAM];   // parameter row of the model and cell type
+  double init[19];     // u, then the state (model initial conditions)
+};
+// device address of the current device's copy of the pacing scratch array
+// (looked up once per device); `device` must be the current device
+hipError_t pace_scratch(int device, double** ptr);
+void launch_pace_stage(const PaceDefaults& def, const double* params, int n_params, const double* init, int nv,
+                       int nc, double* uh, double* w, double* mp, hipStream_t st);
+void launch_pace_unstage(const double* uh, const double* w, int nv, int nc, double* out, hipStream_t st);
+
 }  // namespace ep
