@@ -18,11 +18,21 @@ subdomains (Section "Cardiac electrophysiology: numerical discretization"):
     out of the problem: its elements are dropped, and nodes no other element
     uses are removed from the unknowns (their outputs are NaN).
 
+  - a subdomain may run an ionic model other than the simulation's (eq. (2)
+    gives each Omega_i its own I_ion^i and H^i).  The potential u is one
+    field, kept in the simulation model's units (mV for TTP06, the
+    dimensionless variable of AP / BO, u_mV = a u + b); a subdomain whose
+    model has units (a_i, b_i) sees u_i = (a u + b - b_i) / a_i, and since
+    du_mV/dt = -a_i I_ion^i, its current enters the load in the field's
+    units as (a_i / a) I_ion^i(u_i, w^i).  With one model this is the
+    identity.
+
 Elements are labelled by material ids 0..R-1 (one id per subdomain, the
-paper's Material IDs).  Everything else (BDF start-up, u_BDF / u_EXT, Rush-
-Larsen ionic step, applied current as M I_app, CG or direct solve,
-activation times) is the single-subdomain oracle's, see monodomain.py; the
-semi-implicit BDF ionic scheme is not offered here.
+paper's Material IDs).  Everything else (BDF start-up, u_BDF / u_EXT, the
+ionic step - Rush-Larsen or the paper's semi-implicit BDF scheme, each
+subdomain keeping its own state history -, applied current as M I_app in the
+field's units, CG or direct solve, activation times) is the
+single-subdomain oracle's, see monodomain.py.
 """
 from __future__ import annotations
 
@@ -31,24 +41,25 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from . import fem
-from .ionic import IonicModel
+from .ionic import MV_OFFSET, IonicModel
 from .monodomain import BDF_COEFFS, Monodomain, stimulus_profile, stimulus_active  # noqa: F401
 
 
 @dataclass
 class Region:
     """One subdomain: TTP06 cell type, parameter overrides (names of the
-    model's parameter dict), conductivities (None: the global ones) and
-    whether it conducts."""
+    model's parameter dict), conductivities (None: the global ones), whether
+    it conducts, and its ionic model (None: the simulation's)."""
     variant: str = ""
     params: dict = field(default_factory=dict)
     sigma: tuple | None = None
     conductive: bool = True
+    model: str | None = None
 
 
 class MultiRegion:
     def __init__(self, xyz, conn, material, regions, fibers, sigma, chi, cm, model, stimuli=(),
-                 dt=0.05, bdf=1, solver="auto", rtol=1e-13, max_it=5000):
+                 dt=0.05, bdf=1, solver="auto", rtol=1e-13, max_it=5000, ionic_scheme="rl"):
         xyz = np.asarray(xyz, np.float64)
         conn = np.asarray(conn, np.int64)
         material = np.asarray(material, np.int64)
@@ -56,6 +67,9 @@ class MultiRegion:
             raise ValueError("one material id per element")
         if material.min() < 0 or material.max() >= len(regions):
             raise ValueError("material id without a region")
+        if ionic_scheme not in ("rl", "bdf"):
+            raise ValueError(ionic_scheme)
+        self.ionic_scheme = ionic_scheme
         self.n_full = xyz.shape[0]
         keep = np.array([regions[m].conductive for m in material], bool)
         live = np.unique(conn[keep])
@@ -80,7 +94,7 @@ class MultiRegion:
             Dn = fem.nodal_diffusion(f0, s0, n0, *s, chi, cm)
             Mr, Kr = fem.assemble(xyz_c, conn_c[el], Dn)
             nodes = np.unique(conn_c[el])
-            m = IonicModel(model, reg.variant)
+            m = IonicModel(reg.model or model, reg.variant)
             m.p.update(reg.params)
             self.regions.append(dict(nodes=nodes, M=Mr[:, nodes].tocsr(), model=m))
             self.M = Mr if self.M is None else self.M + Mr
@@ -90,14 +104,23 @@ class MultiRegion:
         base = Monodomain.__new__(Monodomain)
         base.xyz = xyz_c
         base.n = self.n
-        base.model = self.regions[0]["model"]
+        # the field's units, threshold and initial potential: the simulation's
+        # model (the first conducting subdomain's when that one runs it)
+        first = self.regions[0]["model"]
+        base.model = first if first.name == model else IonicModel(model, "")
+        a0, b0 = base.model.mv_per_unit, MV_OFFSET[model]
+        for reg in self.regions:
+            mr = reg["model"]
+            ar, br = mr.mv_per_unit, MV_OFFSET[mr.name]
+            # u_i = (a0 u + b0 - br) / ar;  I in the field's units = (ar / a0) I_i
+            reg["u_scale"], reg["u_shift"], reg["i_scale"] = a0 / ar, (b0 - br) / ar, ar / a0
         base.chi, base.cm, base.dt, base.sigma = chi, cm, self.dt, self.sigma
         base.M, base.K = self.M.tocsr(), self.K.tocsr()
         base.A = {s: (BDF_COEFFS[s][0] / self.dt) * base.M + base.K for s in range(1, self.sigma + 1)}
         if solver == "auto":
             solver = "dense" if self.n <= 2000 else ("splu" if self.n <= 60000 else "cg")
         base.solver, base.rtol, base.max_it, base.block = solver, rtol, max_it, 1
-        base.ionic_scheme = "rl"
+        base.ionic_scheme = ionic_scheme
         base._lu, base._prec, base.cg_iters = {}, {}, []
         scale = 1.0 / (chi * cm * base.model.mv_per_unit)
         base.stims = []
@@ -111,14 +134,17 @@ class MultiRegion:
     def set_state(self, u, w, u_prev=None, step_index=0):
         """u on the conductive nodes (compact numbering); w: one state array
         [n_vars, n] per compact node, copied to every subdomain the node
-        belongs to (None: each model's initial state)."""
+        belongs to that runs the simulation's model (None, and subdomains of
+        another model: that model's initial state).  Earlier ionic states
+        of the BDF ionic scheme start as copies."""
         for reg in self.regions:
             nodes = reg["nodes"]
-            if w is None:
+            if w is None or reg["model"].name != self.base.model.name:
                 _, w0 = reg["model"].initial(nodes.size)
             else:
                 w0 = np.asarray(w, np.float64)[:, nodes]
             reg["w"] = np.array(w0, np.float64)
+            reg["w_hist"] = [reg["w"]] + [reg["w"].copy() for _ in range(1, self.sigma)]
         b = self.base
         u = np.array(u, np.float64)
         prev = list(u_prev) if u_prev is not None else []
@@ -140,8 +166,14 @@ class MultiRegion:
         load = np.zeros(self.n)
         for reg in self.regions:
             nodes = reg["nodes"]
-            reg["w"] = reg["model"].step(u_ext[nodes], reg["w"], self.dt)
-            load += reg["M"] @ reg["model"].iion(u_ext[nodes], reg["w"])
+            m = reg["model"]
+            ui = reg["u_scale"] * u_ext[nodes] + reg["u_shift"]
+            if self.ionic_scheme == "bdf":
+                reg["w"] = m.step_bdf(ui, reg["w_hist"][:s], cb, ce, self.dt, alpha)
+                reg["w_hist"] = [reg["w"]] + reg["w_hist"][:-1]
+            else:
+                reg["w"] = m.step(ui, reg["w"], self.dt)
+            load += reg["M"] @ (reg["i_scale"] * m.iion(ui, reg["w"]))
         rhs = b.M @ (u_bdf / self.dt + b.applied(t_new)) - load
         u_new = b.solve(s, rhs, u_ext)
         slope = (u_new - b.hist[0]) / self.dt
@@ -182,9 +214,9 @@ class MultiRegion:
         return self.live[reg["nodes"]], reg["w"]
 
 
-def from_spec(spec, material, regions, solver="auto", rtol=1e-13):
+def from_spec(spec, material, regions, solver="auto", rtol=1e-13, ionic_scheme="rl"):
     """Multi-subdomain oracle for a workloads.SimSpec and element labels."""
     p = spec.phys
     return MultiRegion(spec.mesh.xyz, spec.mesh.conn, material, regions, spec.fibers,
                        (p.sigma_l, p.sigma_t, p.sigma_n), p.chi, p.cm, spec.model, spec.stimuli,
-                       spec.dt, spec.bdf, solver, rtol)
+                       spec.dt, spec.bdf, solver, rtol, ionic_scheme=ionic_scheme)

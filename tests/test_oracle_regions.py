@@ -160,3 +160,87 @@ def test_scar_band_blocks_conduction():
     o2 = R.from_spec(spec, mat, [R.Region("endo"), R.Region("endo")], solver="splu")
     o2.run(int(25.0 / 0.05))
     assert np.all(np.isfinite(o2.activation_times()))
+
+
+# ---- a subdomain with its own ionic model; the BDF ionic scheme -------------
+
+def test_whole_slab_in_another_model_is_the_affine_image_of_that_model():
+    """The field keeps the simulation model's units (TTP06: mV).  When every
+    element belongs to a Bueno-Orovio subdomain, the run must be the plain
+    Bueno-Orovio simulation (a separate code path, its own dimensionless
+    units) mapped by u_mV = 85.7 u - 84: the semi-discrete problem and the
+    BDF / extrapolation weights (which sum to alpha and 1) commute with an
+    affine change of the potential because K 1 = 0.  A wrong scale, shift
+    or direction of the conversion, or a current not rescaled, fails it."""
+    mesh = W.slab_q1(3.0, 1.5, 1.0, 0.25)
+    dims = tuple(mesh.xyz.max(axis=0))
+    stim = [W.Stimulus(W.CUBE, (0.0, 0.0, 0.0), 1.5, 50.0, 0.0, 2.0, 0.0)]
+    spec_bo = _spec(mesh, "bo", "epi", dims=dims, stim=stim)
+    plain = OM.from_spec(spec_bo, solver="splu")
+    spec_t = _spec(mesh, "ttp06", "endo", dims=dims, stim=stim)
+    mat = np.zeros(mesh.n_elems, np.int32)
+    mixed = R.from_spec(spec_t, mat, [R.Region(model="bo")], solver="splu")
+    # same initial potential: the BO rest state in mV
+    u0, w0 = IonicModel("bo").initial(mesh.n_nodes)
+    mixed.set_state(85.7 * u0 - 84.0, None)
+    for _ in range(120):
+        plain.step()
+        mixed.step()
+    ref = 85.7 * plain.u - 84.0
+    assert np.max(np.abs(ref)) > 10.0                 # an action potential is under way
+    assert np.max(np.abs(mixed.u - ref)) < 1e-9 * np.max(np.abs(ref)), np.max(np.abs(mixed.u - ref))
+
+
+def test_aliev_panfilov_subdomain_in_a_bueno_orovio_field():
+    """Same identity between two dimensionless models: an AP subdomain
+    covering the slab in a BO-unit field equals the plain AP run mapped by
+    u_BO = (100 u_AP - 80 + 84) / 85.7."""
+    mesh = W.slab_q1(3.0, 1.5, 1.0, 0.25)
+    dims = tuple(mesh.xyz.max(axis=0))
+    stim = [W.Stimulus(W.CUBE, (0.0, 0.0, 0.0), 1.5, 50.0, 0.0, 2.0, 0.0)]
+    plain = OM.from_spec(_spec(mesh, "ap", "", dims=dims, stim=stim), solver="splu")
+    mixed = R.from_spec(_spec(mesh, "bo", "epi", dims=dims, stim=stim), np.zeros(mesh.n_elems, np.int32),
+                        [R.Region(model="ap")], solver="splu")
+    mixed.set_state((100.0 * plain.u - 80.0 + 84.0) / 85.7, None)
+    for _ in range(120):
+        plain.step()
+        mixed.step()
+    ref = (100.0 * plain.u + 4.0) / 85.7
+    assert np.max(ref) > 0.5
+    assert np.max(np.abs(mixed.u - ref)) < 1e-9 * np.max(np.abs(ref))
+
+
+def test_two_models_across_an_interface():
+    """TTP06 (endo) and a BO border zone in one slab: interface nodes carry
+    both states, the load adds both currents in the field's units, and the
+    front crosses the interface into the BO half."""
+    mesh = W.slab_q1(6.0, 1.0, 0.5, 0.25)
+    spec = _spec(mesh, "ttp06", "endo", dims=tuple(mesh.xyz.max(axis=0)))
+    mat = W.material_box(mesh, (3.0, 0.0, 0.0), (6.0, 1.0, 0.5), 1)
+    o = R.from_spec(spec, mat, [R.Region("endo"), R.Region(model="bo")], solver="splu")
+    names = [reg["model"].name for reg in o.regions]
+    assert names == ["ttp06", "bo"] and o.regions[1]["w"].shape[0] == 3
+    o.run(400)
+    at = o.activation_times()
+    far = mesh.xyz[:, 0] > 5.5
+    assert np.all(np.isfinite(at[far])) and np.all(at[far] < 20.0)
+    # the BO half uses its own units: at rest its potential is BO rest in mV
+    assert np.all(np.isfinite(o.u))
+
+
+def test_identical_subdomains_reproduce_one_subdomain_bdf_ionic_scheme():
+    """The paper's semi-implicit BDF ionic scheme on three identical
+    subdomains reproduces the one-subdomain oracle's BDF scheme."""
+    mesh = W.slab_q1(4.0, 2.0, 1.0, 0.25)
+    spec = _spec(mesh, bdf=3)
+    mat = W.material_layers(mesh, 0, [1.3, 2.6])
+    one = OM.from_spec(spec, solver="splu", ionic_scheme="bdf")
+    three = R.from_spec(spec, mat, [R.Region("endo")] * 3, solver="splu", ionic_scheme="bdf")
+    for _ in range(60):
+        one.step()
+        three.step()
+    assert np.max(np.abs(one.u - three.u)) < 1e-10 * np.max(np.abs(one.u))
+    # and differs from the Rush-Larsen run (the scheme is really used)
+    rl = R.from_spec(spec, mat, [R.Region("endo")] * 3, solver="splu")
+    rl.run(60)
+    assert np.max(np.abs(rl.u - three.u)) > 1e-6
