@@ -86,7 +86,10 @@ enum {
   EP_OPT_GRAPH = 8,         /* 1: replay the step's launch sequences from captured
                                HIP graphs (ignored while timers are on).  The stream
                                must allow capture (not the legacy null stream).      */
-  EP_OPT_IONIC_SCHEME = 9   /* EP_IONIC_* (before finalize)                           */
+  EP_OPT_IONIC_SCHEME = 9,  /* EP_IONIC_* (before finalize)                           */
+  EP_OPT_IONIC_FP64 = 10    /* mixed precision: 1 steps the ionic model (state and
+                             * arithmetic) in FP64 while the inner CG stays FP32;
+                             * 0 (default) FP32 (before finalize)                  */
 };
 
 /* Ionic integrators (EP_OPT_IONIC_SCHEME).  EP_IONIC_RUSH_LARSEN (default):
@@ -164,12 +167,27 @@ ep_status ep_sim_upload_mesh(ep_sim* sim, int elem, int64_t n_nodes, const doubl
  *     enter M and K; nodes no other element uses drop out of the solve and
  *     report NaN; they count in n_nodes but carry no unknown).
  * The ionic state of a node on the interface of several subdomains is kept
- * once per subdomain and the ionic load is sum_i M^i I_ion^i exactly.
- * Several subdomains need the Rush-Larsen ionic scheme and are not admitted
- * to pools (EP_EINVAL at finalize / admission).  Call before finalize;
+ * once per subdomain and the ionic load is sum_i M^i I_ion^i exactly.  Both
+ * ionic schemes (EP_OPT_IONIC_SCHEME) apply.  Call before finalize;
  * EP_EINVAL on a bad region, variant or parameter count. */
 ep_status ep_sim_set_region(ep_sim* sim, int region, int variant, const double* params, int n_params,
                             double sigma_l, double sigma_t, double sigma_n, int conductive);
+
+/* Ionic model of subdomain `region` (paper: eq. (2) gives every subdomain
+ * Omega_i its own ionic model), EP_AP / EP_BO / EP_TTP06 / EP_PASSIVE, or -1
+ * for the sim's model (the default).  The potential stays one field in the
+ * sim model's units (u_mV = a u + b: TTP06 a = 1, b = 0; BO 85.7, -84; AP
+ * 100, -80); a subdomain of another model is stepped at u_i = (a u + b -
+ * b_i) / a_i and its current enters the load as (a_i / a) I_i.  The
+ * subdomain's variant and parameter overrides (ep_sim_set_region) apply to
+ * its model; the sim's parameter overrides apply only to subdomains of the
+ * sim's model.  Its points start from that model's initial conditions
+ * (ep_sim_set_state sets only points of the sim's model); ep_sim_get_state
+ * reports, for a node whose lowest conducting subdomain runs another model,
+ * the first n_vars variables of that model's state (zeros past its own
+ * count).  Needs material ids (EP_EINVAL at finalize otherwise).  Call
+ * before finalize; EP_EINVAL on a bad region or model. */
+ep_status ep_sim_set_region_model(ep_sim* sim, int region, int model);
 
 /* Fiber, sheet and normal directions per node (paper: the orthonormal triplet
  * f0, s0, n0 of the diffusion tensor), each [n_nodes][3].  Default if never
@@ -307,11 +325,16 @@ void ep_sim_destroy(ep_sim* sim);
 ep_status ep_pool_create(int device, void* hip_stream, size_t hbm_budget_bytes, int max_slots,
                          int precision, ep_pool** out);
 
-/* Admit a configured, NOT yet finalized sim: the pool finalizes it if its
- * device footprint fits the remaining budget and a slot is free, else returns
- * EP_EAGAIN without allocating.  n_steps_total: steps to run before the slot
- * counts as done.  The pool does not take ownership: destroy the sim after
- * releasing it. */
+/* Admit a sim.  A configured, not yet finalized sim is finalized by the pool
+ * (host assembly and upload on the pool's stream) if its estimated device
+ * footprint fits the remaining budget and a slot is free, else EP_EAGAIN
+ * without allocating.  A sim finalized beforehand (on its own stream, for
+ * instance by another thread while the pool steps) is only linked into the
+ * pool's table if its allocated bytes fit the budget (else EP_EAGAIN; it
+ * stays usable alone); admission then waits for its stream and costs no
+ * assembly.  While pooled the sim runs on the pool's stream.  n_steps_total:
+ * steps to run before the slot counts as done.  The pool does not take
+ * ownership: destroy the sim after releasing it. */
 ep_status ep_pool_admit(ep_pool* pool, ep_sim* sim, int64_t n_steps_total, int* slot);
 
 /* Advance every active, unfinished slot by up to n_steps steps together. */

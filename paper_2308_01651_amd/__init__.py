@@ -26,7 +26,7 @@ EP_DTYPE_F64, EP_DTYPE_F32 = 0, 1
 EP_FMT_AUTO, EP_FMT_SELL, EP_FMT_DIA = 0, 1, 2
 EP_OPT_MATRIX_FORMAT, EP_OPT_INNER_RTOL, EP_OPT_MAX_OUTER, EP_OPT_PHASE_TIMERS = 1, 2, 3, 4
 EP_OPT_KERNEL_TIMERS = 5
-EP_OPT_IONIC_NPT, EP_OPT_TILE_MAP, EP_OPT_GRAPH, EP_OPT_IONIC_SCHEME = 6, 7, 8, 9
+EP_OPT_IONIC_NPT, EP_OPT_TILE_MAP, EP_OPT_GRAPH, EP_OPT_IONIC_SCHEME, EP_OPT_IONIC_FP64 = 6, 7, 8, 9, 10
 EP_IONIC_RUSH_LARSEN, EP_IONIC_BDF = 0, 1
 EP_MAX_REGIONS = 8
 KERNEL_KINDS = ["ionic", "rhs", "cg_spmv", "cg_update", "activation", "ir_residual", "cg_finalize"]
@@ -68,10 +68,14 @@ class Simulation:
                                      conn.ctypes.data_as(_lib.PI32),
                                      None if mat is None else mat.ctypes.data_as(_lib.PI32)), "ep_sim_upload_mesh")
 
-    def set_region(self, region: int, variant=None, params=None, sigma=None, conductive=True):
+    def set_region(self, region: int, variant=None, params=None, sigma=None, conductive=True, model=None):
         """ep_sim_set_region: cell type (name or EP_CELL_*; None: the sim's),
         positional parameter overrides, conductivities (l, t, n) in mS/mm
-        (None: the sim's) and whether the subdomain conducts."""
+        (None: the sim's) and whether the subdomain conducts; model: the
+        subdomain's ionic model ("ap", "bo", "ttp06", "passive"; None: the
+        sim's), ep_sim_set_region_model."""
+        if model is not None:
+            check(lib.ep_sim_set_region_model(self._h, int(region), MODEL_IDS[model]), "ep_sim_set_region_model")
         v = -1 if variant is None else (CELL_IDS[variant] if isinstance(variant, str) else int(variant))
         p = None if params is None or len(params) == 0 else _f64(params)
         sl, st, sn = (-1.0, -1.0, -1.0) if sigma is None else tuple(float(x) for x in sigma)
@@ -214,9 +218,10 @@ class Simulation:
     @classmethod
     def from_spec(cls, spec, precision=EP_FP64, device=0, stream=None, rtol=None, max_it=1000,
                   matrix_format=EP_FMT_AUTO, finalize=True, inner_rtol=None, block=1, ionic_scheme="rl",
-                  material=None, regions=None):
+                  material=None, regions=None, ionic_fp64=False):
         """Configure from a workloads.SimSpec (marshalling of its arrays).
         block > 1 selects block-Jacobi preconditioning with that block size;
+        ionic_fp64: in mixed precision, step the ionic model in FP64;
         ionic_scheme "rl" (Rush-Larsen) or "bdf" (the paper's semi-implicit
         BDF).  material: per-element subdomain labels; regions: {label:
         dict(variant=, params=, sigma=, conductive=)} passed to set_region."""
@@ -240,6 +245,8 @@ class Simulation:
             sim.set_option(EP_OPT_INNER_RTOL, inner_rtol)
         if ionic_scheme != "rl":
             sim.set_option(EP_OPT_IONIC_SCHEME, {"bdf": EP_IONIC_BDF}[ionic_scheme])
+        if ionic_fp64:
+            sim.set_option(EP_OPT_IONIC_FP64, 1)
         if finalize:
             sim.finalize()
         return sim

@@ -88,6 +88,7 @@ _SIGS = {
     "ep_sim_time_kernel": [P, C.c_int, C.c_int, PD],
     "ep_cell_pace": [C.c_int, C.c_int, C.c_int, C.c_int, PD, C.c_int, PD, C.c_double, C.c_int, C.c_double,
                      C.c_double, C.c_double, C.c_int, PD],
+    "ep_sim_set_region_model": [P, C.c_int, C.c_int],
     "ep_cell_pace_device": [C.c_int, P, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_double,
                             C.c_int, C.c_double, C.c_double, C.c_double, C.c_int, C.c_void_p],
     "ep_assemble_csr": [C.c_int, C.c_int64, PD, C.c_int64, PI32, PD, PD, PD, C.c_double, C.c_double,

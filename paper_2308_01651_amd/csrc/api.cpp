@@ -251,6 +251,7 @@ struct ep_sim {
   double dt = 0.05, rtol = 1e-10, inner_rtol = 1e-4;
   int bdf = 1, prec = EP_FP64, precond = EP_JACOBI, block = 1, max_it = 1000, max_outer = 30;
   int ionic_scheme = 0;   // EP_IONIC_RUSH_LARSEN or EP_IONIC_BDF
+  int ionic_fp64 = 0;     // mixed precision: ionic step in FP64 (EP_OPT_IONIC_FP64)
   int fmt_pref = EP_FMT_AUTO;
   // subdomains: element labels (empty: one subdomain) and per-label settings
   std::vector<int32_t> material;
@@ -260,6 +261,7 @@ struct ep_sim {
     std::vector<double> params;
     double sig[3] = {-1.0, -1.0, -1.0};  // negative: the sim's
     int conductive = 1;
+    int model = -1;                   // -1: the sim's ionic model
   } region_cfg[EP_MAX_REGIONS];
   int timers = 0;
   // products
@@ -296,8 +298,13 @@ struct ep_sim {
   int64_t n_crow = 0;
   std::vector<int32_t> node_reg;
   std::vector<int32_t> sec_node;
+  std::vector<int32_t> pt_model;   // ionic model of every ionic point (several subdomains)
+  int het_model = -1;              // the one model of all subdomains, or -1 when they differ
+  int st_rows64 = 0, st_rows32 = 0;  // rows of the FP64 / FP32 state arrays
   SweepPredictor sweeps;  // inner rounds per refinement sweep (mixed)
   int sticky = EP_OK;
+  // the ionic step runs in FP32 (state arrays and arithmetic)
+  bool ionic_f32() const { return prec == EP_MIXED && !ionic_fp64; }
 };
 
 namespace {
@@ -327,6 +334,58 @@ double stim_profile(const Stim& t, const double* x) {
   return std::exp(-(dx * dx + dy * dy + dz * dz) / (2.0 * t.size * t.size));
 }
 
+// ionic model of subdomain r
+int region_model(const ep_sim* s, int r) { return s->region_cfg[r].model >= 0 ? s->region_cfg[r].model : s->model; }
+
+// rows a model's state takes in the FP64 and FP32 state arrays (mixed
+// precision keeps TTP06's Na_i and K_i in FP64, everything else in FP32)
+void state_rows(int model, bool mixed, int* rows64, int* rows32) {
+  const int nv = model_info(model).nvars;
+  if (!mixed) {
+    *rows64 = nv;
+    *rows32 = 0;
+  } else if (model == EP_TTP06) {
+    *rows64 = 2;
+    *rows32 = 16;
+  } else {
+    *rows64 = 0;
+    *rows32 = nv;
+  }
+}
+
+// one point's state (model order) into its column of the state arrays
+void pack_state(int model, bool mixed, const double* w, double* s64, float* s32, int64_t stride) {
+  const int nv = model_info(model).nvars;
+  if (!mixed) {
+    for (int v = 0; v < nv; v++) s64[(size_t)v * stride] = w[v];
+  } else if (model == EP_TTP06) {
+    for (int v = 0; v < 18; v++) {
+      if (v < 15) s32[(size_t)v * stride] = (float)w[v];
+      else if (v == 15) s64[0] = w[v];
+      else if (v == 16) s64[(size_t)stride] = w[v];
+      else s32[(size_t)15 * stride] = (float)w[v];
+    }
+  } else {
+    for (int v = 0; v < nv; v++) s32[(size_t)v * stride] = (float)w[v];
+  }
+}
+
+void unpack_state(int model, bool mixed, const double* s64, const float* s32, int64_t stride, double* w) {
+  const int nv = model_info(model).nvars;
+  if (!mixed) {
+    for (int v = 0; v < nv; v++) w[v] = s64[(size_t)v * stride];
+  } else if (model == EP_TTP06) {
+    for (int v = 0; v < 18; v++) {
+      if (v < 15) w[v] = s32[(size_t)v * stride];
+      else if (v == 15) w[v] = s64[0];
+      else if (v == 16) w[v] = s64[(size_t)stride];
+      else w[v] = s32[(size_t)15 * stride];
+    }
+  } else {
+    for (int v = 0; v < nv; v++) w[v] = s32[(size_t)v * stride];
+  }
+}
+
 size_t estimate_bytes(const ep_sim* s) {
   const int64_t n = s->n;
   // a hexahedral lattice of degree p couples a node to (p + 2)^3 nodes on average
@@ -338,7 +397,7 @@ size_t estimate_bytes(const ep_sim* s) {
   double per_node = 11 * 8.0 + 24.0;                            // FP64 vectors, activation
   per_node += (double)s->bdf * s->block * (mixed ? 12.0 : 8.0);  // preconditioner(s)
   per_node += mixed ? 5 * 4.0 : 0.0;
-  per_node += (mixed ? (mi.nvars * 4.0 + 8.0) : mi.nvars * 8.0) * (s->ionic_scheme == EP_IONIC_BDF ? RING : 1);
+  per_node += (s->ionic_f32() ? (mi.nvars * 4.0 + 8.0) : mi.nvars * 8.0) * (s->ionic_scheme == EP_IONIC_BDF ? RING : 1);
   per_node += nnz_row * ((s->bdf + 1) * 8.0 + 4.0 + (mixed ? s->bdf * 4.0 : 0.0));
   per_node += 8.0 * std::min<size_t>(s->stims.size(), MAX_STIM);
   return (size_t)(per_node * n * 1.05) + (1u << 20);
@@ -422,8 +481,6 @@ ep_status finalize_impl(ep_sim* s) {
   EP_HIP(hipSetDevice(s->device));
   // ---- subdomain settings ----
   const bool het = !s->material.empty();
-  if (het && s->ionic_scheme == EP_IONIC_BDF)
-    return fail(EP_EINVAL, "several subdomains need the Rush-Larsen ionic scheme");
   std::vector<double> rsig(3 * EP_MAX_REGIONS);
   std::vector<unsigned char> ron(EP_MAX_REGIONS);
   for (int r = 0; r < EP_MAX_REGIONS; r++) {
@@ -431,8 +488,10 @@ ep_status finalize_impl(ep_sim* s) {
     const double glob[3] = {s->sl, s->st, s->sn};
     for (int k = 0; k < 3; k++) rsig[3 * r + k] = c.sig[k] >= 0.0 ? c.sig[k] : glob[k];
     ron[r] = (unsigned char)c.conductive;
-    if (c.has_params && (int)c.params.size() > n_model_params(s->model))
+    if (c.has_params && (int)c.params.size() > n_model_params(region_model(s, r)))
       return fail(EP_EINVAL, "region parameters: more than the model has");
+    if (!het && c.model >= 0 && c.model != s->model)
+      return fail(EP_EINVAL, "a subdomain ionic model needs material ids");
   }
   // ---- assembly ----
   Csr A;
@@ -476,6 +535,28 @@ ep_status finalize_impl(ep_sim* s) {
       return fail(EP_EINVAL, "no conducting subdomain");
   }
   s->n_pts = n + (int64_t)s->sec_node.size();
+  // ionic model of every point; the state arrays take the most rows any
+  // model present needs
+  s->pt_model.assign(het ? s->n_pts : 0, s->model);
+  s->het_model = s->model;
+  {
+    int r64 = 0, r32 = 0;
+    state_rows(s->model, s->ionic_f32(), &r64, &r32);
+    if (het) {
+      for (int64_t p = 0; p < s->n_pts; p++) {
+        const int r = p < n ? s->node_reg[p] : sec_reg[p - n];
+        const int m = r < 0 ? s->model : region_model(s, r);
+        s->pt_model[p] = m;
+        if (m != s->model) s->het_model = -1;
+        int a = 0, b = 0;
+        state_rows(m, s->ionic_f32(), &a, &b);
+        r64 = std::max(r64, a);
+        r32 = std::max(r32, b);
+      }
+    }
+    s->st_rows64 = r64;
+    s->st_rows32 = r32;
+  }
   const int64_t nnz = A.nnz();
   s->nnz = nnz;
   const bool mixed = s->prec == EP_MIXED;
@@ -717,8 +798,8 @@ ep_status finalize_impl(ep_sim* s) {
   // one state array per time level under the BDF ionic scheme, one shared
   // by all four level slots under Rush-Larsen
   const int n_levels = s->ionic_scheme == EP_IONIC_BDF ? RING : 1;
-  const int n32 = mixed ? ((s->model == EP_TTP06) ? 16 : nvars) : 0;
-  const int n64 = mixed ? ((s->model == EP_TTP06) ? 2 : 0) : nvars;
+  const int n32 = s->st_rows32;
+  const int n64 = s->st_rows64;
   // stride n_pts: the nodes' states, then the extra interface points'
   const int64_t npts = s->n_pts;
   for (int k = 0; k < RING; k++) {
@@ -748,14 +829,25 @@ ep_status finalize_impl(ep_sim* s) {
     // parameter row of each subdomain: its cell type's defaults, the sim's
     // overrides, then the subdomain's own
     std::vector<double> rtab((size_t)MAX_REGIONS * NPARAM, 0.0);
+    const ModelInfo m0 = model_info(s->model);
     for (int r = 0; r < MAX_REGIONS; r++) {
       const ep_sim::RegionCfg& c = s->region_cfg[r];
+      const int mr = region_model(s, r);
       double* row = &rtab[(size_t)r * NPARAM];
-      default_params(s->model, c.variant >= 0 ? c.variant : s->variant, row);
-      for (size_t k = 0; k < s->params.size(); k++) row[k] = s->params[k];
+      default_params(mr, c.variant >= 0 ? c.variant : s->variant, row);
+      if (mr == s->model)
+        for (size_t k = 0; k < s->params.size(); k++) row[k] = s->params[k];
       if (c.has_params)
         for (size_t k = 0; k < c.params.size(); k++) row[k] = c.params[k];
+      // the field is in the sim model's units u_mV = a0 u + b0; model r sees
+      // u_r = (a0 u + b0 - br) / ar and contributes (ar / a0) I_r
+      const ModelInfo mi_r = model_info(mr);
+      D.rmodel[r] = mr;
+      D.rconv[r][0] = m0.mv_per_unit / mi_r.mv_per_unit;
+      D.rconv[r][1] = (m0.mv_offset - mi_r.mv_offset) / mi_r.mv_per_unit;
+      D.rconv[r][2] = mi_r.mv_per_unit / m0.mv_per_unit;
     }
+    D.multi_model = s->het_model < 0 ? 1 : 0;
     double* d_rtab;
     EP_HIP(upload(m, &d_rtab, rtab.data(), rtab.size(), st));
     D.rtab = d_rtab;
@@ -958,7 +1050,14 @@ ep_status step_once(ep_sim* s) {
   KernelTimers& kt = s->kt;
   hipStream_t st = s->stream;
   auto fin = [&] { kt.timed(st, 6, [&] { launch_cg_finalize(mixed, s->d_desc, nullptr, 1, st); }); };
+  // FP64: a round is SpMV then the update (which adds the partial sums
+  // itself); mixed: update, SpMV, finalize
   auto round = [&] {
+    if (!mixed) {
+      kt.timed(st, 2, [&] { launch_cg_spmv(false, L); });
+      kt.timed(st, 3, [&] { launch_cg_update64(L); });
+      return;
+    }
     kt.timed(st, 3, [&] { launch_cg_update(mixed, L); });
     kt.timed(st, 2, [&] { launch_cg_spmv(mixed, L); });
     fin();
@@ -967,17 +1066,19 @@ ep_status step_once(ep_sim* s) {
     if (s->timers) (void)hipEventRecord(s->ev[0], st);
     kt.timed(st, 0, [&] {
       if (s->het) {
-        launch_ionic_het(s->model, mixed, s->d_desc, s->n_pts, st);
+        launch_ionic_het(s->het_model, s->ionic_f32(), s->ionic_scheme == EP_IONIC_BDF, s->d_desc, s->n_pts, st);
         launch_ici_correction(s->d_desc, s->n_crow, st);
       } else {
-        launch_ionic(s->model, mixed, L);
+        launch_ionic(s->model, s->ionic_f32(), L);
       }
     });
     if (s->timers) (void)hipEventRecord(s->ev[1], st);
     kt.timed(st, 1, [&] { launch_residual(mixed, true, L); });
     if (s->timers) (void)hipEventRecord(s->ev[2], st);
-    kt.timed(st, 2, [&] { launch_cg_spmv(mixed, L); });
-    fin();
+    if (mixed) {
+      kt.timed(st, 2, [&] { launch_cg_spmv(mixed, L); });
+      fin();
+    }
   };
   auto ir = [&] {
     kt.timed(st, 5, [&] { launch_residual(true, false, L); });
@@ -1014,7 +1115,8 @@ ep_status step_once(ep_sim* s) {
   if (graph) EP_HIP(hipGraphLaunch(G.pro, st));
   else pro();
   if (!mixed) {
-    int chunk = std::max(1, s->it_pred);
+    // K updates take K + 1 rounds: the last one finds the residual converged
+    int chunk = std::max(1, s->it_pred) + 1;
     for (int n_rounds = 0;; n_rounds++) {
       EP_HIP(rounds(chunk));
       ep_status rc = pull_state(s);
@@ -1174,6 +1276,15 @@ ep_status ep_sim_set_region(ep_sim* s, int region, int variant, const double* pa
   return EP_OK;
 }
 
+ep_status ep_sim_set_region_model(ep_sim* s, int region, int model) {
+  if (check_sim(s)) return EP_EINVAL;
+  if (s->finalized) return fail(EP_ESTATE, "sim already finalized");
+  if (region < 0 || region >= EP_MAX_REGIONS) return fail(EP_EINVAL, "region outside 0 .. EP_MAX_REGIONS - 1");
+  if (model != -1 && (model < EP_PASSIVE || model > EP_TTP06)) return fail(EP_EINVAL, "unknown ionic model");
+  s->region_cfg[region].model = model;
+  return EP_OK;
+}
+
 ep_status ep_sim_upload_fibers(ep_sim* s, const double* f0, const double* s0, const double* n0) {
   if (check_sim(s)) return EP_EINVAL;
   if (s->finalized) return fail(EP_ESTATE, "sim already finalized");
@@ -1278,6 +1389,10 @@ ep_status ep_sim_set_option(ep_sim* s, int key, double value) {
       if (value != EP_IONIC_RUSH_LARSEN && value != EP_IONIC_BDF) return fail(EP_EINVAL, "ionic scheme");
       s->ionic_scheme = (int)value;
       return EP_OK;
+    case EP_OPT_IONIC_FP64:
+      if (value != 0.0 && value != 1.0) return fail(EP_EINVAL, "ionic FP64: 0 or 1");
+      s->ionic_fp64 = (int)value;
+      return EP_OK;
     default: return fail(EP_EINVAL, "unknown option");
   }
 }
@@ -1367,53 +1482,37 @@ ep_status ep_sim_set_state(ep_sim* s, const double* u, const double* w, const do
     const double* src = (u_prev && k < s->bdf) ? u_prev + (size_t)(k - 1) * n : u;
     EP_HIP(hipMemcpyAsync(D.U[(step_index - k) & 3], src, n * sizeof(double), hipMemcpyHostToDevice, st));
   }
-  const int nv = s->nvars;
-  // state arrays have one column per ionic point (stride np); an extra
-  // interface point starts from its node's state
+  // state arrays have one column per ionic point (stride np), rows in each
+  // point's model layout; an extra interface point starts from its node's
+  // state, a point whose subdomain runs another model from that model's
+  // initial conditions
   const int64_t np = s->n_pts;
-  std::vector<double> wexp;
-  if (nv > 0 && np != n) {
-    wexp.resize((size_t)nv * np);
-    for (int v = 0; v < nv; v++)
-      for (int64_t p = 0; p < np; p++)
-        wexp[(size_t)v * np + p] = w[(size_t)v * n + (p < n ? p : s->sec_node[p - n])];
-    w = wexp.data();
-  }
-  if (nv > 0) {
-    if (s->prec == EP_MIXED) {
-      std::vector<float> s32;
-      std::vector<double> s64;
-      if (s->model == EP_TTP06) {
-        s32.resize((size_t)16 * np);
-        s64.resize((size_t)2 * np);
-        for (int v = 0; v < 18; v++) {
-          for (int64_t i = 0; i < np; i++) {
-            const double x = w[(size_t)v * np + i];
-            if (v < 15) s32[(size_t)v * np + i] = (float)x;
-            else if (v == 15) s64[i] = x;
-            else if (v == 16) s64[np + i] = x;
-            else s32[(size_t)15 * np + i] = (float)x;
-          }
-        }
+  const bool f32 = s->ionic_f32();
+  const int r64 = s->st_rows64, r32 = s->st_rows32;
+  if (r64 + r32 > 0) {
+    std::vector<double> h64((size_t)r64 * np, 0.0);
+    std::vector<float> h32((size_t)r32 * np, 0.0f);
+    std::vector<double> col(18), ic_other;
+    for (int64_t p = 0; p < np; p++) {
+      const int m = s->het ? s->pt_model[p] : s->model;
+      const int64_t node = p < n ? p : s->sec_node[p - n];
+      const int nvm = model_info(m).nvars;
+      if (m == s->model) {
+        for (int v = 0; v < nvm; v++) col[v] = w[(size_t)v * n + node];
       } else {
-        s32.assign(w, w + (size_t)nv * np);
+        ic_other = default_init(m);
+        for (int v = 0; v < nvm; v++) col[v] = ic_other[1 + v];
       }
-      // level n and, for the BDF ionic scheme, levels n-1 and n-2 (copies)
-      for (int k = 0; k < 3; k++) {
-        const int slot = (int)((step_index - k) & 3);
-        if (k > 0 && D.st32[slot] == D.st32[step_index & 3]) break;
-        if (!s64.empty()) EP_HIP(hipMemcpyAsync(D.st64[slot], s64.data(), s64.size() * 8, hipMemcpyHostToDevice, st));
-        EP_HIP(hipMemcpyAsync(D.st32[slot], s32.data(), s32.size() * 4, hipMemcpyHostToDevice, st));
-      }
-      EP_HIP(hipStreamSynchronize(st));
-    } else {
-      for (int k = 0; k < 3; k++) {
-        const int slot = (int)((step_index - k) & 3);
-        if (k > 0 && D.st64[slot] == D.st64[step_index & 3]) break;
-        EP_HIP(hipMemcpyAsync(D.st64[slot], w, (size_t)nv * np * 8, hipMemcpyHostToDevice, st));
-      }
-      EP_HIP(hipStreamSynchronize(st));   // w may point into a temporary
+      pack_state(m, f32, col.data(), h64.data() + p, h32.data() + p, np);
     }
+    // level n and, for the BDF ionic scheme, levels n-1 and n-2 (copies)
+    for (int k = 0; k < 3; k++) {
+      const int slot = (int)((step_index - k) & 3);
+      if (k > 0 && D.st64[slot] == D.st64[step_index & 3]) break;
+      if (r64 > 0) EP_HIP(hipMemcpyAsync(D.st64[slot], h64.data(), h64.size() * 8, hipMemcpyHostToDevice, st));
+      if (r32 > 0) EP_HIP(hipMemcpyAsync(D.st32[slot], h32.data(), h32.size() * 4, hipMemcpyHostToDevice, st));
+    }
+    EP_HIP(hipStreamSynchronize(st));   // h64 / h32 are temporaries
   }
   launch_fill(D.smax, n, -std::numeric_limits<double>::infinity(), st);
   launch_fill(D.at, n, std::numeric_limits<double>::quiet_NaN(), st);
@@ -1451,35 +1550,27 @@ ep_status ep_sim_get_state(ep_sim* s, double* u, double* w, double* u_prev) {
       EP_HIP(hipMemcpyAsync(u_prev + (size_t)(k - 1) * n, D.U[(step - k) & 3], n * 8, hipMemcpyDeviceToHost, st));
   const int nv = s->nvars;
   if (w && nv > 0) {
-    // the nodes' columns of the state (stride n_pts; extra points dropped)
+    // the nodes' columns of the state (stride n_pts; extra points dropped);
+    // a node whose primary subdomain runs another model reports the first
+    // nv variables of that model's state (zeros past its own count)
     const int64_t np = s->n_pts;
-    if (s->prec == EP_MIXED) {
-      const int n32 = (s->model == EP_TTP06) ? 16 : nv;
-      std::vector<float> s32((size_t)n32 * np);
-      std::vector<double> s64(s->model == EP_TTP06 ? (size_t)2 * np : 0);
-      EP_HIP(hipMemcpyAsync(s32.data(), D.st32[step & 3], s32.size() * 4, hipMemcpyDeviceToHost, st));
-      if (!s64.empty())
-        EP_HIP(hipMemcpyAsync(s64.data(), D.st64[step & 3], s64.size() * 8, hipMemcpyDeviceToHost, st));
-      EP_HIP(hipStreamSynchronize(st));
-      if (s->model == EP_TTP06) {
-        for (int v = 0; v < 18; v++)
-          for (int64_t i = 0; i < n; i++) {
-            double x;
-            if (v < 15) x = s32[(size_t)v * np + i];
-            else if (v == 15) x = s64[i];
-            else if (v == 16) x = s64[np + i];
-            else x = s32[(size_t)15 * np + i];
-            w[(size_t)v * n + i] = x;
-          }
-      } else {
-        for (int v = 0; v < nv; v++)
-          for (int64_t i = 0; i < n; i++) w[(size_t)v * n + i] = s32[(size_t)v * np + i];
-      }
-    } else if (np == n) {
+    const bool f32 = s->ionic_f32();
+    const int r64 = s->st_rows64, r32 = s->st_rows32;
+    if (!f32 && !s->het) {
       EP_HIP(hipMemcpyAsync(w, D.st64[step & 3], (size_t)nv * n * 8, hipMemcpyDeviceToHost, st));
     } else {
-      EP_HIP(hipMemcpy2DAsync(w, (size_t)n * 8, D.st64[step & 3], (size_t)np * 8, (size_t)n * 8, (size_t)nv,
-                              hipMemcpyDeviceToHost, st));
+      std::vector<double> h64((size_t)std::max(r64, 1) * np);
+      std::vector<float> h32((size_t)std::max(r32, 1) * np);
+      if (r64 > 0) EP_HIP(hipMemcpyAsync(h64.data(), D.st64[step & 3], (size_t)r64 * np * 8, hipMemcpyDeviceToHost, st));
+      if (r32 > 0) EP_HIP(hipMemcpyAsync(h32.data(), D.st32[step & 3], (size_t)r32 * np * 4, hipMemcpyDeviceToHost, st));
+      EP_HIP(hipStreamSynchronize(st));
+      double col[18];
+      for (int64_t i = 0; i < n; i++) {
+        const int m = s->het ? s->pt_model[i] : s->model;
+        for (int v = 0; v < 18; v++) col[v] = 0.0;
+        unpack_state(m, f32, h64.data() + i, h32.data() + i, np, col);
+        for (int v = 0; v < nv; v++) w[(size_t)v * n + i] = col[v];
+      }
     }
   }
   EP_HIP(hipStreamSynchronize(st));
@@ -1824,10 +1915,14 @@ struct ep_pool {
   std::vector<int> active;
   BlockMap* d_all = nullptr;
   int nb_all = 0;
-  // ionic launches per (model, ionic scheme): index 2 * model + scheme
-  BlockMap* d_model[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-  int nb_model[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  // ionic launches per (model, ionic precision, ionic scheme): index
+  // 4 * model + 2 * (FP32 ionic) + scheme
+  BlockMap* d_model[16] = {};
+  int nb_model[16] = {};
   int32_t* d_ids = nullptr;
+  // instances with several subdomains: their ionic step runs per instance
+  // (ionic points, interface correction) instead of in the model groups
+  std::vector<int> het_slots;
   int it_pred = 8;
   SweepPredictor sweeps;  // mixed: rounds per sweep (largest over the instances)
   KernelTimers kt;
@@ -1858,13 +1953,15 @@ ep_status pool_rebuild(ep_pool* P) {
   P->active.clear();
   for (int k = 0; k < P->max_slots; k++)
     if (P->slots[k].sim && !P->slots[k].done) P->active.push_back(k);
-  std::vector<BlockMap> all, per_model[8];
+  std::vector<BlockMap> all, per_model[16];
+  P->het_slots.clear();
   for (int k : P->active) {
     const ep_sim* s = P->slots[k].sim;
     const int nt = s->desc.nblk;
+    if (s->het) P->het_slots.push_back(k);
     for (int t = 0; t < nt; t++) {
       all.push_back(BlockMap{k, t});
-      per_model[2 * s->model + s->ionic_scheme].push_back(BlockMap{k, t});
+      if (!s->het) per_model[4 * s->model + 2 * (s->ionic_f32() ? 1 : 0) + s->ionic_scheme].push_back(BlockMap{k, t});
     }
   }
   auto put = [&](const std::vector<BlockMap>& v, BlockMap** d, int* nb) -> hipError_t {
@@ -1880,7 +1977,7 @@ ep_status pool_rebuild(ep_pool* P) {
     return hipStreamSynchronize(P->stream);
   };
   EP_HIP(put(all, &P->d_all, &P->nb_all));
-  for (int m = 0; m < 8; m++) EP_HIP(put(per_model[m], &P->d_model[m], &P->nb_model[m]));
+  for (int m = 0; m < 16; m++) EP_HIP(put(per_model[m], &P->d_model[m], &P->nb_model[m]));
   std::vector<int32_t> ids(P->active.begin(), P->active.end());
   if (!ids.empty()) {
     EP_HIP(P->maps.alloc((void**)&P->d_ids, ids.size() * sizeof(int32_t)));
@@ -1919,23 +2016,35 @@ ep_status pool_step_once(ep_pool* P) {
   hipStream_t st = P->stream;
   auto fin = [&] { kt.timed(st, 6, [&] { launch_cg_finalize(mixed, P->d_table, P->d_ids, ni, st); }); };
   auto round = [&] {
+    if (!mixed) {
+      kt.timed(st, 2, [&] { launch_cg_spmv(false, L); });
+      kt.timed(st, 3, [&] { launch_cg_update64(L); });
+      return;
+    }
     kt.timed(st, 3, [&] { launch_cg_update(mixed, L); });
     kt.timed(st, 2, [&] { launch_cg_spmv(mixed, L); });
     fin();
   };
   auto pro = [&] {
     kt.timed(st, 0, [&] {
-      for (int m = 0; m < 8; m++)
+      for (int m = 0; m < 16; m++)
         if (P->nb_model[m] > 0) {
           Launch Lm{P->d_table, P->d_model[m], P->nb_model[m], st, false};
           Lm.ionic_npt = P->ionic_npt;
           Lm.ionic_bdf = (m & 1) != 0;
-          launch_ionic(m / 2, mixed, Lm);
+          launch_ionic(m / 4, (m & 2) != 0, Lm);
         }
+      for (int k : P->het_slots) {
+        const ep_sim* s = P->slots[k].sim;
+        launch_ionic_het(s->het_model, s->ionic_f32(), s->ionic_scheme == EP_IONIC_BDF, P->d_table + k, s->n_pts, st);
+        launch_ici_correction(P->d_table + k, s->n_crow, st);
+      }
     });
     kt.timed(st, 1, [&] { launch_residual(mixed, true, L); });
-    kt.timed(st, 2, [&] { launch_cg_spmv(mixed, L); });
-    fin();
+    if (mixed) {
+      kt.timed(st, 2, [&] { launch_cg_spmv(mixed, L); });
+      fin();
+    }
   };
   auto ir = [&] {
     kt.timed(st, 5, [&] { launch_residual(true, false, L); });
@@ -1972,7 +2081,7 @@ ep_status pool_step_once(ep_pool* P) {
   else pro();
   // mixed: sweep index = the smallest refinement count over the instances not
   // yet converged; its rounds are predicted from the slowest instance
-  int chunk = std::max(1, mixed ? P->sweeps.rounds(0) : P->it_pred);
+  int chunk = std::max(1, mixed ? P->sweeps.rounds(0) : P->it_pred + 1);
   int sweep = 0, sweep_start = 0;
   for (int n_rounds = 0;; n_rounds++) {
     EP_HIP(rounds(chunk));
@@ -2070,27 +2179,31 @@ ep_status ep_pool_create(int device, void* hip_stream, size_t hbm_budget_bytes, 
 
 ep_status ep_pool_admit(ep_pool* P, ep_sim* s, int64_t n_steps_total, int* slot) {
   if (!P || !s || !slot || n_steps_total < 1) return fail(EP_EINVAL, "bad admit arguments");
-  if (s->finalized || s->in_pool) return fail(EP_ESTATE, "admit a configured, not yet finalized sim");
+  if (s->in_pool) return fail(EP_ESTATE, "sim already belongs to a pool");
   if (s->prec != P->prec) return fail(EP_EINVAL, "sim precision differs from the pool's");
   if (s->device != P->device) return fail(EP_EINVAL, "sim device differs from the pool's");
-  if (!s->material.empty()) return fail(EP_EINVAL, "sims with several subdomains are not admitted to pools");
   int free_slot = -1;
   for (int k = 0; k < P->max_slots; k++)
     if (!P->slots[k].sim) {
       free_slot = k;
       break;
     }
-  const size_t need = estimate_bytes(s);
+  // a sim finalized beforehand (set up on its own stream, e.g. by another
+  // thread while the pool steps) is only linked into the table
+  const size_t need = s->finalized ? s->mem.bytes : estimate_bytes(s);
   if (free_slot < 0 || P->in_use + need > P->budget) return fail(EP_EAGAIN, "pool full (slots or HBM budget)");
   EP_HIP(hipSetDevice(P->device));
+  if (s->finalized) EP_HIP(hipStreamSynchronize(s->stream));   // its setup copies are done
   // the sim runs on the pool's stream while pooled
   s->stream_own = s->stream;
   s->stream = P->stream;
-  ep_status rc = finalize_impl(s);
-  if (rc != EP_OK) {
-    if (!s->finalized) s->mem.release();
-    s->stream = s->stream_own;
-    return rc;
+  if (!s->finalized) {
+    ep_status rc = finalize_impl(s);
+    if (rc != EP_OK) {
+      if (!s->finalized) s->mem.release();
+      s->stream = s->stream_own;
+      return rc;
+    }
   }
   InstDesc* dst = P->d_table + free_slot;
   EP_HIP(hipMemcpyAsync(dst, s->d_desc_own, sizeof(InstDesc), hipMemcpyDeviceToDevice, P->stream));

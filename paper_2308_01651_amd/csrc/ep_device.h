@@ -66,6 +66,10 @@ struct InstState {
   // one (shifted by the update kernel), so that the finalize is idempotent
   double gamma_cur, alpha_cur, beta, gamma_prev, alpha_prev;
   double rr, bb, tol2, rr_in0, rr_outer;
+  // FP64 solve without a finalize kernel: gamma_k and alpha_k of iteration k
+  // in slot k & 1, written by the update kernel of iteration k and read by
+  // that of iteration k + 1
+  double gam[2], alp[2];
 };
 // Per-instance descriptor.  The mutable state sits inside it (first member),
 // so kernels reach it without another pointer hop; the potential history
@@ -133,11 +137,21 @@ struct InstDesc {
   const int64_t* cptr;     // [n_crow + 1] entries of each correction row
   const int32_t* ccol;     // extra point (counted from 0) of each entry
   const double* cval;      // C value of each entry
+  // several ionic models (multi_model != 0): model of each subdomain and the
+  // conversion of the potential field into that model's units and of its
+  // current back: u_model = rconv[r][0] u + rconv[r][1], I_field =
+  // rconv[r][2] I_model (identity for subdomains of the simulation's model)
+  int32_t multi_model;
+  int32_t rmodel[MAX_REGIONS];
+  double rconv[MAX_REGIONS][3];
 };
 
 // Partial-sum layout inside InstDesc::partial, in units of nblk doubles:
-// residual kernel [4][nblk], SpMV [1][nblk], update [2][nblk].
-constexpr int PART_RES = 0, PART_SPMV = 4, PART_UPD = 5, PART_DOUBLES = 7;
+// residual kernel [4][nblk], SpMV [1][nblk], update [2][nblk]; the FP64
+// update kernel that reduces its predecessors' partials itself writes
+// iteration k's partials to [2][nblk] at PART_UPD + 2 (k & 1), so that no
+// workgroup overwrites partials another workgroup of the same launch reads.
+constexpr int PART_RES = 0, PART_SPMV = 4, PART_UPD = 5, PART_DOUBLES = 9;
 
 struct BlockMap {
   int32_t inst;

@@ -39,10 +39,13 @@ __device__ __forceinline__ double m_tanh(double x) { return tanh(x); }
 __device__ __forceinline__ float m_tanh(float x) { return tanhf(x); }
 
 // Rush-Larsen update of one gate: exact solution of dy/dt = (y_inf - y)/tau
-// over dt with y_inf and tau frozen at u*.
+// over dt with y_inf and tau frozen at u*, y + (y_inf - y)(1 - e^{-dt/tau}).
+// The fraction 1 - e^{-dt/tau} is formed by expm1: for slow gates (dt/tau
+// ~ 1e-4) e^{-dt/tau} rounded to FP32 would carry a relative error of ~1e-3
+// in that fraction, i.e. a biased decay rate every step.
 template <typename R>
 __device__ __forceinline__ R rush_larsen(R y, R y_inf, R tau, R dt) {
-  return y_inf + (y - y_inf) * m_exp(-dt / tau);
+  return y + (y_inf - y) * (-m_expm1(-dt / tau));
 }
 
 // ---------------------------------------------------------------------------
@@ -68,10 +71,16 @@ __device__ __forceinline__ R ap_step_bdf(R u, R dt, R alpha, const double* mp, R
   return (k * u * (u - a) * (u - R(1)) + u * v) * invT;
 }
 
-// BDF step of a gate dy/dt = (y_inf - y)/tau, implicit in y.
+// BDF step of a gate dy/dt = (y_inf - y)/tau, implicit in y:
+// y = (y_BDF + c y_inf)/(alpha + c), c = dt/tau, written as
+// y_BDF/alpha + c/(alpha + c) (y_inf - y_BDF/alpha) so that a slow gate's
+// small relaxation is not formed from a quotient of two nearly equal
+// rounded numbers (a biased rate in FP32).
 template <typename R>
 __device__ __forceinline__ R gate_bdf(R y_bdf, R y_inf, R tau, R dt, R alpha) {
-  return (y_bdf + dt * y_inf / tau) / (alpha + dt / tau);
+  const R c = dt / tau;
+  const R y0 = y_bdf / alpha;
+  return y0 + c / (alpha + c) * (y_inf - y0);
 }
 
 // ---------------------------------------------------------------------------

@@ -28,6 +28,9 @@ void launch_ionic(int model, bool mixed, const Launch& L);
 void launch_residual(bool mixed, bool with_rhs, const Launch& L);
 void launch_cg_spmv(bool mixed, const Launch& L);
 void launch_cg_update(bool mixed, const Launch& L);
+// FP64: the update with the finalize's work (partial sums, convergence,
+// step lengths) done by every workgroup; a round is SpMV then this kernel
+void launch_cg_update64(const Launch& L);
 // one workgroup per instance listed in ids (device array of n_ids indices);
 // ids == nullptr with n_ids == 1: the single instance at insts[0]
 void launch_cg_finalize(bool mixed, InstDesc* insts, const int32_t* ids, int n_ids, hipStream_t stream);
@@ -40,7 +43,9 @@ void launch_to_mv(void* dst, const double* u, int64_t n, double a, double b, boo
                   const int32_t* reg = nullptr);
 // several subdomains: the ionic step over all n_pts ionic points, then the
 // interface correction of the load over its n_crow rows
-void launch_ionic_het(int model, bool mixed, InstDesc* insts, int64_t n_pts, hipStream_t st);
+// (model < 0: the subdomains run different models; bdf: the paper's
+// semi-implicit BDF ionic scheme)
+void launch_ionic_het(int model, bool mixed, bool bdf, InstDesc* insts, int64_t n_pts, hipStream_t st);
 void launch_ici_correction(InstDesc* insts, int64_t n_crow, hipStream_t st);
 // single-cell pacing (cell.hip): n_steps steps of nc cells from step index
 // step0; uh [3][nc] potential history (u_n, u_{n-1}, u_{n-2}), w [n_vars][nc],

@@ -106,6 +106,37 @@ __device__ __forceinline__ void reduce_partials(const double* __restrict__ P, in
   }
 }
 
+// Sum of the partial streams P[c[j] * nblk + b], b < nblk, for NV stream
+// indices c[j], in a fixed order (that of reduce_partials); every thread of
+// the NT-thread workgroup obtains bitwise the same totals.
+template <int NT, int NV>
+__device__ __forceinline__ void reduce_streams(const double* __restrict__ P, const int (&c)[NV], int nblk,
+                                               double (&out)[NV]) {
+  __shared__ double sh[NT / 64][NV];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double acc[NV];
+#pragma unroll
+  for (int j = 0; j < NV; j++) acc[j] = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += NT) {
+#pragma unroll
+    for (int j = 0; j < NV; j++) acc[j] += gmem(P)[(int64_t)c[j] * nblk + b];
+  }
+#pragma unroll
+  for (int j = 0; j < NV; j++) acc[j] = wave_sum(acc[j]);
+  if (lane == 0) {
+#pragma unroll
+    for (int j = 0; j < NV; j++) sh[wv][j] = acc[j];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < NV; j++) {
+    double a = 0.0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; w++) a += sh[w][j];
+    out[j] = a;
+  }
+}
+
 // Solve-control flags written by earlier kernels (kernel boundaries make them
 // visible).  Plain loads of the three adjacent words, issued together.
 struct Ctl {
@@ -269,10 +300,12 @@ __device__ __forceinline__ void combine(const BdfW& W, int sig, const T* const* 
 // Ionic step of one ionic point: state index i (arrays [var][n], stride n),
 // potential of node `node`, parameters mp.  With RHS the point also writes its
 // node's load g = u_BDF/dt + I_app - I_ion and initial guess u_EXT; with
-// KEEP_I it stores I_ion(point) for the interface correction.
-template <int MODEL, bool MIXED, bool BDFS, bool RHS = true, bool KEEP_I = false>
+// KEEP_I it stores I_ion(point) for the interface correction.  CONV: the
+// point's model works in other units than the potential field; it is stepped
+// at u_model = cv[0] u_EXT + cv[1] and its current enters as cv[2] I_model.
+template <int MODEL, bool MIXED, bool BDFS, bool RHS = true, bool KEEP_I = false, bool CONV = false>
 __device__ __forceinline__ void ionic_point(const InstDesc& I, int64_t n, int64_t step, int64_t i, int64_t node,
-                                            const double* __restrict__ mp) {
+                                            const double* __restrict__ mp, const double* cv = nullptr) {
   const int sig = min(I.bdf, (int)step + 1);
   const double u0 = gmem(I.u_cur)[node];
   double u_ext, u_bdf;
@@ -288,6 +321,9 @@ __device__ __forceinline__ void ionic_point(const InstDesc& I, int64_t n, int64_
     u_ext = 3.0 * u0 - 3.0 * u1 + u2;
     u_bdf = 3.0 * u0 - 1.5 * u1 + u2 * (1.0 / 3.0);
   }
+  // the potential the model sees (its own units)
+  const double u_field = u_ext;
+  if (CONV) u_ext = cv[0] * u_field + cv[1];
   // state levels: new w_{n+1}, then w_n, w_{n-1}, w_{n-2}
   const gptr<double> s64 = gmem(I.st64[(step + 1) & 3]);
   const gptr<float> s32 = gmem(I.st32[(step + 1) & 3]);
@@ -361,11 +397,12 @@ __device__ __forceinline__ void ionic_point(const InstDesc& I, int64_t n, int64_
     s64[MIXED ? i : row(15)] = S.nai;
     s64[MIXED ? row(1) : row(16)] = S.ki;
   }
+  if (CONV) iion *= cv[2];
   if (KEEP_I) gmem(I.ipt)[i] = iion;
   if (RHS) {
     const double iapp = stimulus_at(I, step + 1, node);
     gmem(I.g)[node] = u_bdf * I.inv_dt + iapp - iion;
-    gmem(I.u_new)[node] = u_ext;
+    gmem(I.u_new)[node] = u_field;
   }
 }
 
@@ -397,7 +434,25 @@ __global__ __launch_bounds__(TILE / NPT) __attribute__((amdgpu_waves_per_eu(NPT 
 // guess.  Points i >= n are the interface nodes' extra subdomains; they only
 // keep I_ion.  A node outside every conducting subdomain (pt_reg < 0) is no
 // unknown: load and guess 0, no ionic work.
-template <int MODEL, bool MIXED>
+// MODEL < 0: the subdomains run different ionic models; each point takes its
+// subdomain's model (a switch per point) and unit conversion.
+template <int MODEL, bool MIXED, bool BDFS, bool RHS>
+__device__ __forceinline__ void het_point(const InstDesc& I, int64_t step, int64_t i, int64_t node, int r) {
+  const double* mp = I.rtab + (int64_t)r * NPARAM;
+  if (MODEL >= 0) {
+    ionic_point<MODEL, MIXED, BDFS, RHS, true>(I, I.n_pts, step, i, node, mp);
+    return;
+  }
+  const double* cv = I.rconv[r];
+  switch (I.rmodel[r]) {
+    case M_AP: ionic_point<M_AP, MIXED, BDFS, RHS, true, true>(I, I.n_pts, step, i, node, mp, cv); break;
+    case M_BO: ionic_point<M_BO, MIXED, BDFS, RHS, true, true>(I, I.n_pts, step, i, node, mp, cv); break;
+    case M_TTP06: ionic_point<M_TTP06, MIXED, BDFS, RHS, true, true>(I, I.n_pts, step, i, node, mp, cv); break;
+    default: ionic_point<M_PASSIVE, MIXED, BDFS, RHS, true, true>(I, I.n_pts, step, i, node, mp, cv); break;
+  }
+}
+
+template <int MODEL, bool MIXED, bool BDFS>
 __global__ __launch_bounds__(WG) void k_ionic_het(InstDesc* __restrict__ insts) {
   const InstDesc& I = insts[0];
   const int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
@@ -411,10 +466,10 @@ __global__ __launch_bounds__(WG) void k_ionic_het(InstDesc* __restrict__ insts) 
       gmem(I.ipt)[i] = 0.0;
       return;
     }
-    ionic_point<MODEL, MIXED, false, true, true>(I, I.n_pts, step, i, i, I.rtab + (int64_t)r * NPARAM);
+    het_point<MODEL, MIXED, BDFS, true>(I, step, i, i, r);
   } else {
     const int64_t node = gmem(I.sec_node)[i - I.n];
-    ionic_point<MODEL, MIXED, false, false, true>(I, I.n_pts, step, i, node, I.rtab + (int64_t)r * NPARAM);
+    het_point<MODEL, MIXED, BDFS, false>(I, step, i, node, r);
   }
 }
 
@@ -495,8 +550,10 @@ __global__ __launch_bounds__(WG) void k_residual(InstDesc* __restrict__ insts, c
   write_partials<4>(v, I.partial + (int64_t)PART_RES * I.nblk, I.nblk, lblk);
   if (lblk == 0 && threadIdx.x == 0) {
     // a new (inner) solve starts at iteration 0; fields read by no workgroup
-    // of this kernel (conv_in is cleared by the finalize that follows)
-    S.it = 0;
+    // of this kernel (conv_in is cleared by the finalize that follows).  The
+    // FP64 solve counts its iterations in the SpMV kernel, which advances
+    // the counter before each update: it starts from -1.
+    S.it = (MIXED || !WITH_RHS) ? 0 : -1;
     if (WITH_RHS) {
       S.conv = 0;
       S.conv_in = 0;
@@ -520,6 +577,9 @@ __global__ __launch_bounds__(WG) void k_cg_spmv(InstDesc* __restrict__ insts, co
   if (lblk < 0) return;
   InstState& S = I.st;
   if (cg_idle(S)) return;
+  // FP64: the iteration index the following update kernel works on (no
+  // workgroup of this kernel reads it)
+  if (!MIXED && lblk == 0 && threadIdx.x == 0) S.it = S.it + 1;
   const int sig = min(I.bdf, (int)S.step + 1);
   const int64_t i0 = (int64_t)lblk * TILE + threadIdx.x;
   double v[1] = {0.0};
@@ -722,6 +782,133 @@ __global__ __launch_bounds__(WG) void k_cg_update(InstDesc* __restrict__ insts, 
 }
 
 // ---------------------------------------------------------------------------
+// FP64 CG iteration, part 2 without a finalize kernel: every workgroup adds
+// the partial sums of the kernels before it (the residual or the previous
+// update, and the SpMV) in the same fixed order, so all of them take the
+// same convergence decision and the same step lengths bitwise; workgroup 0
+// records them for the next iteration.  Iteration k (advanced by the SpMV
+// kernel) keeps gamma_k, alpha_k in slot k & 1 and writes its partials to
+// the stream pair k & 1, so no workgroup writes what another workgroup of
+// the same launch reads.  The control flag `conv` is only ever set here
+// once convergence is decided, and every workgroup reaching this launch
+// takes that decision itself, so reading it early or late is equivalent.
+// ---------------------------------------------------------------------------
+
+template <bool SINGLE, int XMAP>
+__global__ __launch_bounds__(WG) void k_cg_update64(InstDesc* __restrict__ insts, const BlockMap* __restrict__ bmap) {
+  int lblk;
+  InstDesc& I = instance<SINGLE, XMAP>(insts, bmap, lblk);
+  if (lblk < 0) return;
+  InstState& S = I.st;
+  if (S.conv != 0) return;
+  const int k = S.it;
+  const int nblk = I.nblk;
+  const int sig = min(I.bdf, (int)S.step + 1);
+  const int64_t i0 = (int64_t)lblk * TILE + threadIdx.x;
+  // this thread's rows, loaded before the reduction so that they are in
+  // flight while the partial sums are added
+  double zv[RPT], wv[RPT], pv[RPT], sv[RPT], xv[RPT], rv[RPT];
+#pragma unroll
+  for (int rw = 0; rw < RPT; rw++) {
+    const int64_t i = i0 + rw * WG;
+    zv[rw] = wv[rw] = pv[rw] = sv[rw] = xv[rw] = rv[rw] = 0.0;
+    if (i < I.n) {
+      zv[rw] = gmem(I.z)[i];
+      wv[rw] = gmem(I.w)[i];
+      pv[rw] = gmem(I.p)[i];
+      sv[rw] = gmem(I.s)[i];
+      xv[rw] = gmem(I.u_new)[i];
+      rv[rw] = gmem(I.r)[i];
+    }
+  }
+  const double* __restrict__ P = I.partial;
+  double gamma, rr, delta, bb = 0.0;
+  if (k == 0) {
+    double a[5];
+    const int c[5] = {PART_RES, PART_RES + 1, PART_RES + 2, PART_RES + 3, PART_SPMV};
+    reduce_streams<WG, 5>(P, c, nblk, a);
+    gamma = a[0];
+    rr = a[1];
+    bb = a[2];
+    delta = a[4];
+  } else {
+    double a[3];
+    const int u = PART_UPD + 2 * ((k - 1) & 1);
+    const int c[3] = {PART_SPMV, u, u + 1};
+    reduce_streams<WG, 3>(P, c, nblk, a);
+    delta = a[0];
+    gamma = a[1];
+    rr = a[2];
+  }
+  const double tol2 = (k == 0) ? I.rtol * I.rtol * bb : S.tol2;
+  int flag = 0;
+  bool done = false;
+  double alpha = 0.0, beta = 0.0;
+  if (!(rr == rr) || !(gamma == gamma)) {
+    done = true;
+    flag = F_NAN;
+  } else if (rr <= tol2) {
+    done = true;
+  } else if (k >= I.max_it) {
+    done = true;
+    flag = F_NOCONV;
+  } else {
+    double denom;
+    if (k == 0) {
+      denom = delta;
+    } else {
+      beta = gamma / S.gam[(k - 1) & 1];
+      denom = delta - beta * gamma / S.alp[(k - 1) & 1];
+    }
+    alpha = gamma / denom;
+    if (!(denom > 0.0) || !(alpha == alpha)) {
+      done = true;
+      flag = (delta == delta) ? F_BREAKDOWN : F_NAN;
+    }
+  }
+  if (lblk == 0 && threadIdx.x == 0) {
+    // read by later kernels only
+    S.rr = rr;
+    if (k == 0) {
+      S.bb = bb;
+      S.tol2 = tol2;
+    }
+    if (done) {
+      if (flag) S.flags |= flag;
+      S.conv = 1;
+    } else {
+      S.gam[k & 1] = gamma;
+      S.alp[k & 1] = alpha;
+      S.it_step += 1;
+    }
+  }
+  if (done) return;
+  double v[2] = {0.0, 0.0};
+#pragma unroll
+  for (int rw = 0; rw < RPT; rw++) {
+    const int64_t i = i0 + rw * WG;
+    const bool valid = i < I.n;
+    double rn = 0.0;
+    if (valid) {
+      const double pn = (k == 0) ? zv[rw] : zv[rw] + beta * pv[rw];
+      const double sn = (k == 0) ? wv[rw] : wv[rw] + beta * sv[rw];
+      gmem(I.u_new)[i] = xv[rw] + alpha * pn;
+      rn = rv[rw] - alpha * sn;
+      gmem(I.p)[i] = pn;
+      gmem(I.s)[i] = sn;
+      gmem(I.r)[i] = rn;
+    }
+    const double zn = precond_apply<double>(I.dinv[sig - 1], I.bld, I.block, i, valid, rn);
+    if (valid) {
+      gmem(I.z)[i] = zn;
+      v[0] += rn * zn;
+      v[1] += rn * rn;
+    }
+  }
+  write_partials<2>(v, I.partial + (int64_t)(PART_UPD + 2 * (k & 1)) * nblk, nblk, lblk);
+}
+
+// ---------------------------------------------------------------------------
 // activation time; end of step
 // ---------------------------------------------------------------------------
 
@@ -809,9 +996,10 @@ static void ionic_dispatch_npt(const Launch& L) {
 }
 
 template <int M, bool MX>
-static void ionic_het_dispatch(InstDesc* d, int64_t n_pts, hipStream_t st) {
+static void ionic_het_dispatch(InstDesc* d, int64_t n_pts, bool bdf, hipStream_t st) {
   const unsigned grid = (unsigned)((n_pts + WG - 1) / WG);
-  hipLaunchKernelGGL((k_ionic_het<M, MX>), dim3(grid), dim3(WG), 0, st, d);
+  if (bdf) hipLaunchKernelGGL((k_ionic_het<M, MX, true>), dim3(grid), dim3(WG), 0, st, d);
+  else hipLaunchKernelGGL((k_ionic_het<M, MX, false>), dim3(grid), dim3(WG), 0, st, d);
 }
 
 template <int M, bool MX>
@@ -831,16 +1019,25 @@ void launch_ionic(int model, bool mixed, const Launch& L) {
   }
 }
 
-void launch_ionic_het(int model, bool mixed, InstDesc* insts, int64_t n_pts, hipStream_t st) {
+void launch_ionic_het(int model, bool mixed, bool bdf, InstDesc* insts, int64_t n_pts, hipStream_t st) {
   if (n_pts <= 0) return;
   switch (model) {
-    case M_AP: mixed ? ionic_het_dispatch<M_AP, true>(insts, n_pts, st) : ionic_het_dispatch<M_AP, false>(insts, n_pts, st); break;
-    case M_BO: mixed ? ionic_het_dispatch<M_BO, true>(insts, n_pts, st) : ionic_het_dispatch<M_BO, false>(insts, n_pts, st); break;
-    case M_TTP06:
-      mixed ? ionic_het_dispatch<M_TTP06, true>(insts, n_pts, st) : ionic_het_dispatch<M_TTP06, false>(insts, n_pts, st);
+    case M_AP:
+      mixed ? ionic_het_dispatch<M_AP, true>(insts, n_pts, bdf, st) : ionic_het_dispatch<M_AP, false>(insts, n_pts, bdf, st);
       break;
-    default:
-      mixed ? ionic_het_dispatch<M_PASSIVE, true>(insts, n_pts, st) : ionic_het_dispatch<M_PASSIVE, false>(insts, n_pts, st);
+    case M_BO:
+      mixed ? ionic_het_dispatch<M_BO, true>(insts, n_pts, bdf, st) : ionic_het_dispatch<M_BO, false>(insts, n_pts, bdf, st);
+      break;
+    case M_TTP06:
+      mixed ? ionic_het_dispatch<M_TTP06, true>(insts, n_pts, bdf, st)
+            : ionic_het_dispatch<M_TTP06, false>(insts, n_pts, bdf, st);
+      break;
+    case M_PASSIVE:
+      mixed ? ionic_het_dispatch<M_PASSIVE, true>(insts, n_pts, bdf, st)
+            : ionic_het_dispatch<M_PASSIVE, false>(insts, n_pts, bdf, st);
+      break;
+    default:   // several ionic models
+      mixed ? ionic_het_dispatch<-1, true>(insts, n_pts, bdf, st) : ionic_het_dispatch<-1, false>(insts, n_pts, bdf, st);
       break;
   }
 }
@@ -902,6 +1099,14 @@ void launch_cg_finalize(bool mixed, InstDesc* insts, const int32_t* ids, int n_i
 void launch_cg_update(bool mixed, const Launch& L) {
   if (L.nblocks <= 0) return;
   mixed ? update_dispatch<true>(L) : update_dispatch<false>(L);
+}
+
+void launch_cg_update64(const Launch& L) {
+  if (L.nblocks <= 0) return;
+  const dim3 g(L.nblocks), b(WG);
+  if (!L.single) hipLaunchKernelGGL((k_cg_update64<false, 0>), g, b, 0, L.stream, L.insts, L.bmap);
+  else if (L.xmap == 1) hipLaunchKernelGGL((k_cg_update64<true, 1>), g, b, 0, L.stream, L.insts, L.bmap);
+  else hipLaunchKernelGGL((k_cg_update64<true, 0>), g, b, 0, L.stream, L.insts, L.bmap);
 }
 
 void launch_activation(const Launch& L) {

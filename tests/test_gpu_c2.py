@@ -7,13 +7,9 @@ ventricle", on a generated prolate-spheroid shell).
   workload runs in (the operator format the library picks; block-Jacobi 32
   and Jacobi), compared in
   full with the oracle's step (CG to 1e-13);
-- 600 steps (30 ms) in mixed precision against FP64: RMS over nodes (held
-  against the FP64 run's own sensitivity to its solver tolerance) and the
-  threshold-crossing times.  The max-slope activation time is compared too,
-  within five steps: where the slope has a nearly flat top (inside the
-  stimulated regions the slope is set by the constant applied current for
-  2 ms) its argmax is ill-conditioned, and two FP64 runs with different
-  preconditioners at rtol 1e-10 already differ by up to five steps.
+- 600 steps (30 ms) in mixed precision against FP64 at the fixed bar: RMS
+  over nodes <= 1e-3 mV, threshold-crossing and max-slope activation times
+  within 0.1 ms.
 """
 import numpy as np
 import pytest
@@ -55,45 +51,38 @@ def test_c2_full_size_single_step():
 
 
 def test_c2_full_size_mixed_precision_trajectory():
-    """Mixed precision against FP64 over 30 ms.  While the five fronts sweep
-    the shell, the potential on a steep BO upstroke turns tiny timing shifts
-    into mV: two FP64 runs at rtol 1e-10 and 1e-12 already differ by about
-    7e-3 mV RMS at 30 ms, above the 1e-3 mV mixed-precision budget.  The
-    potential is therefore held to the larger of 1e-3 mV and ten times that
-    FP64-to-FP64 difference, measured in the same run; threshold-crossing
-    times to 0.1 ms."""
+    """Mixed precision against FP64 over 30 ms, at the fixed bar (RMS <= 1e-3
+    mV, threshold-crossing and max-slope activation times within 0.1 ms).
+    While the five fronts sweep the shell the potential is extremely
+    sensitive: FP64 runs at rtol 1e-10 and 1e-13 already differ by about
+    7e-3 mV RMS, so both sides solve tightly (FP64 reference at rtol 1e-13,
+    mixed outer refinement at rtol 1e-12).  The Bueno-Orovio step runs in
+    FP64 (EP_OPT_IONIC_FP64) with the inner CG in FP32: its FP32 step
+    perturbs the fronts by about 2e-2 mV RMS (measured), above the bar."""
     import paper_2308_01651_amd as ep
     spec = W.config_c2(n_steps=600)
-    ref = ep.Simulation.from_spec(spec)
-    tight = ep.Simulation.from_spec(spec, rtol=1e-12)
-    mix = ep.Simulation.from_spec(spec, precision=ep.EP_MIXED)
+    ref = ep.Simulation.from_spec(spec, rtol=1e-13)
+    mix = ep.Simulation.from_spec(spec, precision=ep.EP_MIXED, rtol=1e-12, ionic_fp64=True)
     for k in range(3):
-        for s in (ref, tight, mix):
+        for s in (ref, mix):
             s.step(200)
         print(f"C2 mixed vs FP64: {(k + 1) * 10} ms", flush=True)
+    st = mix.get_stats()
+    assert st["ir_sweeps_total"] >= 600          # the refinement loop really ran
     u_ref = ref.get_potential()
     du = mix.get_potential() - u_ref
-    dt_ = tight.get_potential() - u_ref
     rms = float(np.sqrt(np.mean(du * du)))
-    rms_fp64 = float(np.sqrt(np.mean(dt_ * dt_)))
     tc_m, tc_r = mix.get_threshold_times(), ref.get_threshold_times()
     at_m, at_r = mix.get_activation_times(), ref.get_activation_times()
     ok = ~np.isnan(tc_r)
-    print(f"C2 mixed: rms {rms:.2e} mV (FP64 rtol 1e-12 vs 1e-10: {rms_fp64:.2e} mV), "
-          f"{ok.sum()} nodes crossed threshold", flush=True)
-    t_end = 600 * spec.dt
+    print(f"C2 mixed: rms {rms:.2e} mV, max {np.max(np.abs(du)):.2e} mV, {ok.sum()} nodes crossed threshold",
+          flush=True)
     assert ok.sum() > 100000
-    assert rms <= max(1e-3, 10.0 * rms_fp64), (rms, rms_fp64)
-
-    def same_times(a, b, tol):
-        # nodes activated in one run only must have activated within tol of the end
-        both = ~np.isnan(a) & ~np.isnan(b)
-        only = np.isnan(a) ^ np.isnan(b)
-        late = np.where(np.isnan(a), b, a)[only]
-        assert np.all(late >= t_end - tol - 1e-9), np.min(late)
-        return np.max(np.abs(a[both] - b[both]))
-
-    assert same_times(tc_m, tc_r, 0.1) <= 0.1
-    assert same_times(at_m, at_r, 5 * spec.dt) <= 5 * spec.dt + 1e-9
-    for s in (ref, tight, mix):
+    assert rms <= 1e-3, rms
+    assert np.array_equal(np.isnan(tc_m), np.isnan(tc_r))
+    assert np.max(np.abs(tc_m[ok] - tc_r[ok])) <= 0.1
+    both = ~np.isnan(at_m) & ~np.isnan(at_r)
+    assert np.array_equal(np.isnan(at_m), np.isnan(at_r))
+    assert np.max(np.abs(at_m[both] - at_r[both])) <= 0.1
+    for s in (ref, mix):
         s.close()

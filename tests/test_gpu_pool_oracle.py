@@ -132,3 +132,109 @@ def test_destroying_a_pooled_sim_releases_its_slot():
     pool.release(slot_b)
     sb.close()
     pool.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_pooled_subdomain_instances_match_the_oracle(precision):
+    """Instances with several subdomains in one pool beside a plain one: three
+    TTP06 layers with a scar, a TTP06 slab with a Bueno-Orovio band and an
+    Aliev-Panfilov patch, and the three layers again under the paper's BDF
+    ionic scheme (BDF3); each against the multi-subdomain oracle."""
+    import paper_2308_01651_amd as ep
+    from oracle import regions as R
+    mixed = precision == "mixed"
+    prec = ep.EP_MIXED if mixed else ep.EP_FP64
+    dims = (5.0, 2.0, 1.0)
+    mesh = W.slab_q1(*dims, 0.25)
+    L = dims[0]
+    lay = W.material_layers(mesh, 0, [L / 3, 2 * L / 3])
+    scar = W.material_box(mesh, (0.4 * L, 0.0, 0.0), (0.6 * L, 1.0, 1e9), 3, lay)
+    band = W.material_box(mesh, (0.45 * L, 0.0, 0.0), (0.75 * L, 1e9, 1e9), 1)
+    band = W.material_box(mesh, (0.8 * L, 0.0, 0.0), (L + 1.0, 1.0, 1e9), 2, band)
+    layers_o = [R.Region("endo"), R.Region("mid"), R.Region("epi", sigma=(0.25, 0.03, 0.03)),
+                R.Region(conductive=False)]
+    layers_g = {0: dict(variant="endo"), 1: dict(variant="mid"), 2: dict(variant="epi", sigma=(0.25, 0.03, 0.03)),
+                3: dict(conductive=False)}
+    models_o = [R.Region("endo"), R.Region(model="bo"), R.Region(model="ap")]
+    models_g = {0: dict(variant="endo"), 1: dict(model="bo"), 2: dict(model="ap")}
+
+    def spec(bdf, label):
+        return W.SimSpec(mesh, W.uniform_fibers(mesh.n_nodes), W.Physics(), "ttp06", "endo",
+                         [W.corner_cube_stimulus(dims=dims)], 0.05, bdf, 1, 1e-12, label)
+
+    cases = [(spec(2, "layers+scar"), scar, layers_o, layers_g, "rl", 110),
+             (spec(2, "ttp06+bo+ap"), band, models_o, models_g, "rl", 150),
+             (spec(3, "layers bdf3"), scar, layers_o, layers_g, "bdf", 90)]
+    pool = ep.Pool(8 << 30, 8, prec)
+    plain = _specs()[0][0]
+    sp_plain = ep.Simulation.from_spec(plain, precision=prec, finalize=False)
+    slot_plain = pool.admit(sp_plain, 60)
+    sims = []
+    for sp, mat, oregs, gregs, scheme, n in cases:
+        s = ep.Simulation.from_spec(sp, precision=prec, finalize=False, material=mat, regions=gregs,
+                                    ionic_scheme=scheme)
+        slot = pool.admit(s, n)
+        assert slot is not None
+        sims.append((slot, s, sp, mat, oregs, scheme, n))
+    pool.step(150)
+    assert sorted(pool.poll()) == sorted([slot_plain] + [x[0] for x in sims])
+    for slot, s, sp, mat, oregs, scheme, n in sims:
+        print(f"pool {precision}: {sp.label}, {n} steps", flush=True)
+        assert s.get_stats()["steps"] == n
+        o = R.from_spec(sp, mat, oregs, solver="splu", ionic_scheme=scheme)
+        o.run(n)
+        u, uo = s.get_potential(), o.potential_mv()
+        fin = np.isfinite(uo)
+        assert np.array_equal(fin, np.isfinite(u)), sp.label
+        if mixed:
+            assert np.sqrt(np.mean((u[fin] - uo[fin]) ** 2)) <= 1e-3, sp.label
+        else:
+            assert _rel(u[fin], uo[fin]) < 1e-8, (sp.label, _rel(u[fin], uo[fin]))
+        at, ato = s.get_activation_times(), o.activation_times()
+        ok = ~np.isnan(ato)
+        assert ok.sum() > 20 and np.array_equal(ok, ~np.isnan(at)), sp.label
+        assert np.max(np.abs(at[ok] - ato[ok])) <= (0.1 if mixed else sp.dt + 1e-9), sp.label
+        pool.release(slot)
+        s.close()
+    o = OM.from_spec(plain, solver="splu")
+    o.run(60)
+    _check(sp_plain, plain, o, mixed)
+    pool.release(slot_plain)
+    sp_plain.close()
+    pool.close()
+
+
+def test_serving_respects_a_binding_hbm_budget():
+    """Six requests arrive at once; the HBM budget holds two of them.  The
+    loop prepares requests on a worker thread while others step, never has
+    more than the budget resident or reserved, and every result is bitwise
+    the one of the same simulation run alone."""
+    import paper_2308_01651_amd as ep
+    from paper_2308_01651_amd import serve
+    base = _specs()[0][0]
+    specs = [W.SimSpec(base.mesh, base.fibers, base.phys, base.model, base.variant, base.stimuli, base.dt,
+                       base.bdf, 30 + 10 * k, base.rtol, f"ap-{k}") for k in range(6)]
+    probe = ep.Simulation.from_spec(specs[0], finalize=False)
+    need = probe.device_bytes_estimate()
+    probe.finalize()
+    actual = probe.get_stats()["device_bytes"]
+    probe.close()
+    budget = int(2.5 * max(need, actual))
+    got = {}
+    out = serve.serve([W.Request(0.0, sp) for sp in specs], budget, 8, ep.EP_FP64, steps_per_tick=7,
+                      on_done=lambda rid, sim: got.__setitem__(rid, sim.get_state()[0]))
+    assert out["failed"] == 0 and len(got) == 6
+    assert 0 < out["peak_bytes_in_use"] <= budget
+    # resident at once: never more than the budget holds, and fewer than all
+    ev = sorted([(r.admit_s, 1) for r in out["records"]] + [(r.done_s, -1) for r in out["records"]],
+                key=lambda e: (e[0], e[1]))
+    live = peak = 0
+    for _, d in ev:
+        live += d
+        peak = max(peak, live)
+    assert peak <= budget // actual and peak < 6, (peak, budget, actual)
+    for rid, sp in enumerate(specs):
+        s = ep.Simulation.from_spec(sp)
+        s.step(sp.n_steps)
+        assert np.array_equal(got[rid], s.get_state()[0]), rid
+        s.close()

@@ -148,8 +148,13 @@ def test_region_errors():
     ep = _ep()
     spec = _slab()
     mat = W.material_layers(spec.mesh, 0, [2.0])
+    # a subdomain model without material ids, and an unknown model
     with pytest.raises(ep.EpError):
-        ep.Simulation.from_spec(spec, material=mat, ionic_scheme="bdf")
+        ep.Simulation.from_spec(spec, regions={1: dict(model="bo")})
+    s = ep.Simulation.from_spec(spec, material=mat, finalize=False)
+    with pytest.raises(ep.EpError):
+        ep.check(ep.lib.ep_sim_set_region_model(s._h, 0, 17), "ep_sim_set_region_model")
+    s.close()
     bad = mat.copy()
     bad[0] = ep.EP_MAX_REGIONS
     with pytest.raises(ep.EpError):
@@ -159,10 +164,6 @@ def test_region_errors():
         s.set_region(ep.EP_MAX_REGIONS)
     with pytest.raises(ep.EpError):
         s.set_region(0, variant=7)
-    pool = ep.Pool(1 << 30, 2, 0)
-    with pytest.raises(ep.EpError):
-        pool.admit(s, 10)
-    pool.close()
     s.close()
 
 
@@ -205,3 +206,108 @@ def test_ventricle_shell_with_scar_and_border_zone():
     assert ok.sum() > 100 and np.array_equal(ok, ~np.isnan(at_g))
     assert np.max(np.abs(at_o[ok] - at_g[ok])) <= spec.dt + 1e-9
     sim.close()
+
+
+# ---- a subdomain with its own ionic model; the BDF ionic scheme -------------
+
+def _two_models(spec):
+    """TTP06 endocardial tissue (the field in mV) with a Bueno-Orovio border
+    band across the slab and an Aliev-Panfilov patch (each in its own units,
+    converted to the field's)."""
+    m = spec.mesh
+    L = m.xyz[:, 0].max()
+    mat = W.material_box(m, (0.45 * L, 0.0, 0.0), (0.75 * L, 1e9, 1e9), 1)
+    mat = W.material_box(m, (0.8 * L, 0.0, 0.0), (L + 1.0, 0.5 * m.xyz[:, 1].max(), 1e9), 2, mat)
+    oregs = [R.Region("endo"), R.Region(model="bo"), R.Region(model="ap")]
+    gregs = {0: dict(variant="endo"), 1: dict(model="bo"), 2: dict(model="ap")}
+    return mat, oregs, gregs
+
+
+@pytest.mark.parametrize("kind", ["q1", "p1"])
+def test_two_ionic_models_single_step(kind):
+    ep = _ep()
+    spec = _slab(kind)
+    mat, oregs, gregs = _two_models(spec)
+    n = spec.mesh.n_nodes
+    u, w = W.random_state("ttp06", n, seed=71)
+    u_prev = u + np.random.default_rng(72).normal(size=n)
+    o = R.from_spec(spec, mat, oregs, solver="splu", rtol=1e-13)
+    o.set_state(u, w, [u_prev], 4)
+    sim = ep.Simulation.from_spec(spec, rtol=1e-13, material=mat, regions=gregs)
+    sim.set_state(u, w, u_prev[None], 4)
+    # both start the BO and AP points from their models' initial conditions
+    for _ in range(3):
+        o.step()
+    sim.step(3)
+    ug, wg, _ = sim.get_state()
+    sim.close()
+    assert _rel(ug, o.u) < 1e-10, _rel(ug, o.u)
+    # BO state of the nodes whose lowest subdomain is the BO band
+    seen = np.zeros(n, bool)
+    nodes0, _ = o.state(0)
+    seen[nodes0] = True
+    nodes1, w1 = o.state(1)
+    prim = ~seen[nodes1]
+    err = np.max(np.abs(wg[:3, nodes1[prim]] - w1[:, prim]) / np.maximum(np.abs(w1[:, prim]), 1e-30))
+    assert err < 1e-9, err
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_two_ionic_models_trajectory(prec):
+    """The front leaves the TTP06 corner, crosses the BO band and reaches the
+    AP patch; FP64 against the oracle (trajectory bar), mixed precision
+    against FP64 (1e-3 mV RMS, threshold times 0.1 ms)."""
+    ep = _ep()
+    spec = _slab("q1", dims=(6.0, 2.0, 1.0), h=0.25)
+    mat, oregs, gregs = _two_models(spec)
+    o = R.from_spec(spec, mat, oregs, solver="splu")
+    ref = ep.Simulation.from_spec(spec, rtol=1e-12, material=mat, regions=gregs)
+    sim = ep.Simulation.from_spec(spec, precision=prec, rtol=1e-12, material=mat, regions=gregs)
+    for chunk in range(4):
+        o.run(100)
+        ref.step(100)
+        sim.step(100)
+        err = _rel(ref.get_potential(), o.potential_mv())
+        print(f"two models prec={prec}: {(chunk + 1) * 100} steps, rel {err:.2e}", flush=True)
+        assert err < 1e-8, (chunk, err)
+    at_o, at_r = o.activation_times(), ref.get_activation_times()
+    ok = ~np.isnan(at_o)
+    far = spec.mesh.xyz[:, 0] > 5.0
+    assert np.all(ok[far])                        # the front reached the AP patch
+    assert np.array_equal(ok, ~np.isnan(at_r))
+    assert np.max(np.abs(at_o[ok] - at_r[ok])) <= spec.dt + 1e-9
+    if prec == 1:
+        du = sim.get_potential() - ref.get_potential()
+        assert np.sqrt(np.mean(du * du)) <= 1e-3
+        tm, tr = sim.get_threshold_times(), ref.get_threshold_times()
+        both = ~np.isnan(tm) & ~np.isnan(tr)
+        assert np.array_equal(np.isnan(tm), np.isnan(tr))
+        assert np.max(np.abs(tm[both] - tr[both])) <= 0.1
+    for s in (ref, sim):
+        s.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_regions_with_bdf_ionic_scheme(prec):
+    """The paper's semi-implicit BDF ionic scheme (BDF3) on three TTP06
+    layers with a scar: FP64 against the multi-subdomain oracle's BDF scheme,
+    mixed precision against FP64."""
+    ep = _ep()
+    spec = _slab("q1", dims=(4.0, 2.0, 1.0), h=0.25, bdf=3)
+    mat, oregs, gregs = _layers(spec, scar=True)
+    o = R.from_spec(spec, mat, oregs, solver="splu", ionic_scheme="bdf")
+    ref = ep.Simulation.from_spec(spec, rtol=1e-12, material=mat, regions=gregs, ionic_scheme="bdf")
+    sim = ep.Simulation.from_spec(spec, precision=prec, rtol=1e-12, material=mat, regions=gregs,
+                                  ionic_scheme="bdf")
+    for chunk in range(2):
+        o.run(100)
+        ref.step(100)
+        sim.step(100)
+        err = _rel(ref.get_potential(), o.potential_mv())
+        assert err < 1e-8, (chunk, err)
+    if prec == 1:
+        du = sim.get_potential() - ref.get_potential()
+        fin = np.isfinite(du)
+        assert np.sqrt(np.mean(du[fin] ** 2)) <= 1e-3
+    for s in (ref, sim):
+        s.close()
