@@ -66,11 +66,17 @@ enum { EP_CUBE = 0, EP_SPHERE = 1, EP_GAUSS = 2 };                    /* stimulu
 enum { EP_FP64 = 0, EP_MIXED = 1 };                                   /* precision       */
 enum { EP_JACOBI = 0, EP_BJACOBI = 1 };                               /* preconditioner  */
 enum { EP_DTYPE_F64 = 0, EP_DTYPE_F32 = 1 };
-enum { EP_FMT_AUTO = 0, EP_FMT_SELL = 1, EP_FMT_DIA = 2 };            /* matrix format   */
+enum { EP_FMT_AUTO = 0, EP_FMT_SELL = 1, EP_FMT_DIA = 2, EP_FMT_MF = 3 };  /* operator format */
 
 /* Options for ep_sim_set_option (before finalize unless stated). */
 enum {
-  EP_OPT_MATRIX_FORMAT = 1, /* EP_FMT_*; AUTO picks DIA when it moves fewer bytes      */
+  EP_OPT_MATRIX_FORMAT = 1, /* EP_FMT_*; AUTO picks DIA when it moves fewer bytes than
+                             * SELL.  EP_FMT_MF: no assembled operator on the device;
+                             * hexahedra of degree 2 or 3 (EP_HEX27, EP_HEX64), FP64,
+                             * one subdomain, Jacobi, not in pools (EP_EINVAL at
+                             * finalize otherwise): the operator is applied element by
+                             * element by sum factorization on the Gauss points of the
+                             * assembly (paper: matrix-free high-order solvers on GPUs) */
   EP_OPT_INNER_RTOL = 2,    /* mixed precision: inner FP32 CG relative tolerance (1e-4)  */
   EP_OPT_MAX_OUTER = 3,     /* mixed precision: max refinement sweeps per step (30)      */
   EP_OPT_PHASE_TIMERS = 4,  /* 1: time ionic / rhs / solve / activation phases (any time) */
@@ -121,7 +127,7 @@ typedef struct ep_stats {
   int32_t cg_iters_max;     /* largest per-step count                               */
   int64_t ir_sweeps_total;  /* mixed precision: FP64 refinement sweeps              */
   double rel_residual_last; /* ||b - A u||_2 / ||b||_2 at the end of the last solve */
-  int32_t matrix_format;    /* EP_FMT_SELL or EP_FMT_DIA                            */
+  int32_t matrix_format;    /* EP_FMT_SELL, EP_FMT_DIA or EP_FMT_MF                  */
   int32_t n_diag;           /* DIA diagonals (0 for SELL)                           */
   int64_t device_bytes;     /* device memory held by the sim                        */
   double ms_ionic, ms_rhs, ms_solve, ms_activation; /* phase times (if enabled)     */

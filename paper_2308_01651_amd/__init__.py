@@ -23,7 +23,7 @@ EP_FP64, EP_MIXED = 0, 1
 EP_JACOBI = 0
 EP_BJACOBI = 1
 EP_DTYPE_F64, EP_DTYPE_F32 = 0, 1
-EP_FMT_AUTO, EP_FMT_SELL, EP_FMT_DIA = 0, 1, 2
+EP_FMT_AUTO, EP_FMT_SELL, EP_FMT_DIA, EP_FMT_MF = 0, 1, 2, 3
 EP_OPT_MATRIX_FORMAT, EP_OPT_INNER_RTOL, EP_OPT_MAX_OUTER, EP_OPT_PHASE_TIMERS = 1, 2, 3, 4
 EP_OPT_KERNEL_TIMERS = 5
 EP_OPT_IONIC_NPT, EP_OPT_TILE_MAP, EP_OPT_GRAPH, EP_OPT_IONIC_SCHEME, EP_OPT_IONIC_FP64 = 6, 7, 8, 9, 10

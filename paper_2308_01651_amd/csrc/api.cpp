@@ -493,6 +493,18 @@ ep_status finalize_impl(ep_sim* s) {
     if (!het && c.model >= 0 && c.model != s->model)
       return fail(EP_EINVAL, "a subdomain ionic model needs material ids");
   }
+  // the matrix-free operator (hexahedra of degree 2 or 3, FP64, one
+  // subdomain, Jacobi): the device applies it element by element; the host
+  // still assembles once, for the Jacobi diagonal
+  const bool mf = s->fmt_pref == EP_FMT_MF;
+  if (mf) {
+    if (s->elem != EP_HEX27 && s->elem != EP_HEX64)
+      return fail(EP_EINVAL, "the matrix-free operator takes hexahedra of degree 2 or 3");
+    if (s->prec != EP_FP64) return fail(EP_EINVAL, "the matrix-free operator runs in FP64");
+    if (het) return fail(EP_EINVAL, "the matrix-free operator takes one subdomain");
+    if (s->block != 1) return fail(EP_EINVAL, "the matrix-free operator uses the Jacobi preconditioner");
+    if (s->in_pool) return fail(EP_EINVAL, "matrix-free sims are not admitted to pools");
+  }
   // ---- assembly ----
   Csr A;
   std::vector<char> err;
@@ -591,7 +603,9 @@ ep_status finalize_impl(ep_sim* s) {
   for (int64_t o : up)
     if (o > 0 && !std::binary_search(offs.begin(), offs.end(), -o)) sym_pattern = false;
   bool use_dia = false;
-  if (sym_pattern && (int)offs.size() <= MAX_DIAG && (int)up.size() <= MAX_UP) {
+  if (mf) {
+    // no assembled operator on the device
+  } else if (sym_pattern && (int)offs.size() <= MAX_DIAG && (int)up.size() <= MAX_UP) {
     const double dia_bytes = (double)up.size() * stride * vb;
     const double sell_bytes = (double)sell_nnz * (vb + 4.0);
     use_dia = (s->fmt_pref == EP_FMT_DIA) || (s->fmt_pref == EP_FMT_AUTO && dia_bytes < sell_bytes);
@@ -648,7 +662,38 @@ ep_status finalize_impl(ep_sim* s) {
     return e;
   };
   std::vector<std::vector<double>> hostvals;  // keep alive until sync
-  if (use_dia) {
+  if (mf) {
+    MfData mfd;
+    std::vector<char> err_mf;
+    if (!mf_setup(s->elem, n, s->xyz.data(), s->n_elems, s->conn.data(), fib0, fib1, fib2, s->sl, s->st, s->sn,
+                  s->chi, s->cm, mfd, err_mf))
+      return fail(EP_EINVAL, std::string("matrix-free setup: ") + (err_mf.empty() ? "failed" : err_mf.data()));
+    D.fmt = FMT_MF;
+    D.nup = 0;
+    s->guard = 0;
+    D.mf_p = mfd.p;
+    D.n_elems = s->n_elems;
+    const int n1 = mfd.p + 1;
+    for (int k = 0; k < n1 * n1; k++) {
+      D.mfV[k] = mfd.V[k];
+      D.mfD[k] = mfd.Dv[k];
+    }
+    const double* geo;
+    EP_HIP(to_dev_d(mfd.geo, &geo));
+    D.geo = geo;
+    int32_t* dconn;
+    EP_HIP(upload(m, &dconn, s->conn.data(), s->conn.size(), st));
+    D.econn = dconn;
+    int64_t* dptr;
+    EP_HIP(upload(m, &dptr, mfd.adj_ptr.data(), mfd.adj_ptr.size(), st));
+    D.adj_ptr = dptr;
+    int32_t* dadj;
+    EP_HIP(upload(m, &dadj, mfd.adj.data(), mfd.adj.size(), st));
+    D.adj = dadj;
+    EP_HIP(m.alloc((void**)&D.yA, (size_t)s->n_elems * s->elem * sizeof(double)));
+    EP_HIP(m.alloc((void**)&D.yM, (size_t)s->n_elems * s->elem * sizeof(double)));
+    EP_HIP(hipStreamSynchronize(st));   // mfd is a temporary
+  } else if (use_dia) {
     D.fmt = FMT_DIA;
     D.nup = (int)up.size();
     const int64_t g = up.back();
@@ -996,7 +1041,7 @@ ep_status validate_desc(const InstDesc& D, int64_t guard) {
   for (int k = 0; k < RING; k++)
     if (!D.U[k]) return bad("history ring");
   if (!D.u_new || !D.u_cur || !D.u_prev1 || !D.u_prev2) return bad("history slots");
-  if (!D.valM || !D.smax || !D.at || !D.tcross) return bad("arrays");
+  if ((!D.valM && D.fmt != FMT_MF) || !D.smax || !D.at || !D.tcross) return bad("arrays");
   if (D.het) {
     if (D.n_pts < D.n || !D.pt_reg || !D.sec_node || !D.rtab || !D.ipt || !D.cvec) return bad("subdomain arrays");
     if (D.n_crow > 0 && (!D.crow || !D.cptr || !D.ccol || !D.cval)) return bad("interface correction");
@@ -1004,7 +1049,7 @@ ep_status validate_desc(const InstDesc& D, int64_t guard) {
     return bad("ionic points");
   }
   for (int q = 0; q < D.bdf; q++) {
-    if (!D.valA[q] || !D.dinv[q]) return bad("operator values");
+    if ((!D.valA[q] && D.fmt != FMT_MF) || !D.dinv[q]) return bad("operator values");
     if (D.prec == P_MIXED && (!D.valA32[q] || !D.dinv32[q])) return bad("FP32 operator values");
   }
   if (D.prec == P_MIXED && (!D.r32 || !D.z32 || !D.p32 || !D.s32 || !D.w32)) return bad("FP32 vectors");
@@ -1020,6 +1065,10 @@ ep_status validate_desc(const InstDesc& D, int64_t guard) {
     if (D.ld < ((D.n + 63) / 64) * 64 + guard) return bad("DIA leading dimension");
   } else if (D.fmt == FMT_SELL) {
     if (!D.col || !D.slice_ptr) return bad("SELL arrays");
+  } else if (D.fmt == FMT_MF) {
+    if ((D.mf_p != 2 && D.mf_p != 3) || D.n_elems <= 0 || !D.geo || !D.econn || !D.yA || !D.yM || !D.adj_ptr ||
+        !D.adj || D.prec != P_FP64 || D.het)
+      return bad("matrix-free operator arrays");
   } else {
     return bad("matrix format");
   }
@@ -1031,6 +1080,10 @@ ep_status validate_desc(const InstDesc& D, int64_t guard) {
 
 Launch launch_of(ep_sim* s) {
   Launch L{s->d_desc, s->d_bmap, s->nblocks, s->stream, true};
+  if (s->desc.fmt == FMT_MF) {
+    L.mf_p = s->desc.mf_p;
+    L.mf_elems = s->n_elems;
+  }
   L.xmap = s->xmap;
   L.ionic_npt = s->ionic_npt;
   L.ionic_bdf = s->ionic_scheme == EP_IONIC_BDF;
@@ -1374,7 +1427,8 @@ ep_status ep_sim_set_option(ep_sim* s, int key, double value) {
   if (s->finalized) return fail(EP_ESTATE, "sim already finalized");
   switch (key) {
     case EP_OPT_MATRIX_FORMAT:
-      if (value != EP_FMT_AUTO && value != EP_FMT_SELL && value != EP_FMT_DIA) return fail(EP_EINVAL, "format");
+      if (value != EP_FMT_AUTO && value != EP_FMT_SELL && value != EP_FMT_DIA && value != EP_FMT_MF)
+        return fail(EP_EINVAL, "format");
       s->fmt_pref = (int)value;
       return EP_OK;
     case EP_OPT_INNER_RTOL:
@@ -1651,7 +1705,7 @@ ep_status ep_sim_get_stats(ep_sim* s, ep_stats* o) {
   o->rel_residual_last = S.bb > 0 ? std::sqrt(S.rr_outer / S.bb) : 0.0;
   if (s->prec != EP_MIXED && S.bb > 0) o->rel_residual_last = std::sqrt(S.rr / S.bb);
   if (s->prec != EP_MIXED && S.bb == 0) o->rel_residual_last = 0.0;
-  o->matrix_format = s->desc.fmt == FMT_DIA ? EP_FMT_DIA : EP_FMT_SELL;
+  o->matrix_format = s->desc.fmt == FMT_DIA ? EP_FMT_DIA : (s->desc.fmt == FMT_MF ? EP_FMT_MF : EP_FMT_SELL);
   o->n_diag = s->desc.fmt == FMT_DIA ? 2 * s->desc.nup - 1 : 0;
   o->device_bytes = (int64_t)s->mem.bytes;
   o->ms_ionic = s->ms_phase[0];
@@ -2181,6 +2235,8 @@ ep_status ep_pool_admit(ep_pool* P, ep_sim* s, int64_t n_steps_total, int* slot)
   if (!P || !s || !slot || n_steps_total < 1) return fail(EP_EINVAL, "bad admit arguments");
   if (s->in_pool) return fail(EP_ESTATE, "sim already belongs to a pool");
   if (s->prec != P->prec) return fail(EP_EINVAL, "sim precision differs from the pool's");
+  if (s->fmt_pref == EP_FMT_MF || (s->finalized && s->desc.fmt == FMT_MF))
+    return fail(EP_EINVAL, "matrix-free sims are not admitted to pools");
   if (s->device != P->device) return fail(EP_EINVAL, "sim device differs from the pool's");
   int free_slot = -1;
   for (int k = 0; k < P->max_slots; k++)

@@ -498,6 +498,129 @@ int tet_element(const double X[4][3], const double Dn[4][9], double Me[16], doub
 
 }  // namespace
 
+bool mf_setup(int elem, int64_t n_nodes, const double* xyz, int64_t n_elems, const int32_t* conn,
+              const double* f0, const double* s0, const double* n0, double sigma_l, double sigma_t,
+              double sigma_n, double chi, double cm, MfData& out, std::vector<char>& err) {
+  if (elem != 27 && elem != 64) {
+    set_err(err, "the matrix-free operator takes hexahedra of degree 2 or 3 (27 or 64 nodes)");
+    return false;
+  }
+  if (n_nodes <= 0 || n_elems <= 0) { set_err(err, "empty mesh"); return false; }
+  if (!(chi > 0) || !(cm > 0)) { set_err(err, "chi and C_m must be positive"); return false; }
+  const int npe = elem, p = elem == 27 ? 2 : 3, n1 = p + 1, Q = n1 * n1 * n1;
+  for (int64_t e = 0; e < n_elems * npe; e++)
+    if (conn[e] < 0 || conn[e] >= n_nodes) { set_err(err, "connectivity index out of range"); return false; }
+  double gp[4], gw[4], z[4];
+  gauss_legendre(n1, gp, gw);
+  for (int j = 0; j < n1; j++) z[j] = -1.0 + 2.0 * j / p;
+  out.p = p;
+  out.n_elems = n_elems;
+  out.V.assign((size_t)n1 * n1, 0.0);
+  out.Dv.assign((size_t)n1 * n1, 0.0);
+  for (int q = 0; q < n1; q++)
+    for (int j = 0; j < n1; j++) {
+      double val = 1.0, der = 0.0;
+      for (int m = 0; m < n1; m++) {
+        if (m == j) continue;
+        const double f = (gp[q] - z[m]) / (z[j] - z[m]);
+        der = der * f + val / (z[j] - z[m]);
+        val *= f;
+      }
+      out.V[(size_t)q * n1 + j] = val;
+      out.Dv[(size_t)q * n1 + j] = der;
+    }
+  out.geo.assign((size_t)n_elems * 7 * Q, 0.0);
+  const double scale = 1.0 / (chi * cm);
+  static const double ex[3] = {1, 0, 0}, ey[3] = {0, 1, 0}, ez[3] = {0, 0, 1};
+  std::vector<char> bad(2, 0);
+  const std::vector<double>& V = out.V;
+  const std::vector<double>& Dv = out.Dv;
+  parallel_for(n_elems, [&](int64_t e) {
+    double X[64][3], Dn[64][9];
+    for (int k = 0; k < npe; k++) {
+      const int64_t v = conn[e * npe + k];
+      for (int c = 0; c < 3; c++) X[k][c] = xyz[3 * v + c];
+      nodal_tensor(f0 ? f0 + 3 * v : ex, s0 ? s0 + 3 * v : ey, n0 ? n0 + 3 * v : ez, sigma_l, sigma_t, sigma_n,
+                   scale, Dn[k]);
+    }
+    double* g = &out.geo[(size_t)e * 7 * Q];
+    for (int qz = 0; qz < n1; qz++)
+      for (int qy = 0; qy < n1; qy++)
+        for (int qx = 0; qx < n1; qx++) {
+          const int q = qx + n1 * (qy + n1 * qz);
+          double J[3][3] = {{0}}, Dq[9] = {0};
+          for (int c = 0; c < n1; c++)
+            for (int b = 0; b < n1; b++)
+              for (int a = 0; a < n1; a++) {
+                const int k = a + n1 * (b + n1 * c);
+                const double N = V[qx * n1 + a] * V[qy * n1 + b] * V[qz * n1 + c];
+                const double d0 = Dv[qx * n1 + a] * V[qy * n1 + b] * V[qz * n1 + c];
+                const double d1 = V[qx * n1 + a] * Dv[qy * n1 + b] * V[qz * n1 + c];
+                const double d2 = V[qx * n1 + a] * V[qy * n1 + b] * Dv[qz * n1 + c];
+                for (int cc = 0; cc < 3; cc++) {
+                  J[0][cc] += d0 * X[k][cc];
+                  J[1][cc] += d1 * X[k][cc];
+                  J[2][cc] += d2 * X[k][cc];
+                }
+                for (int t = 0; t < 9; t++) Dq[t] += N * Dn[k][t];
+              }
+          const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                             J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                             J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+          if (!(det > 0.0)) {
+            bad[0] = 1;
+            return;
+          }
+          if (!psd3(Dq)) {
+            bad[1] = 1;
+            return;
+          }
+          double Ji[3][3];
+          Ji[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
+          Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+          Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+          Ji[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;
+          Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+          Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+          Ji[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / det;
+          Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+          Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+          // physical gradient component r of a function = sum_s Ji[r][s] d_s;
+          // C[s][u] = w det sum_{r,t} Ji[r][s] Dq[r][t] Ji[t][u]
+          const double w = gw[qx] * gw[qy] * gw[qz] * det;
+          double DJ[3][3];
+          for (int r = 0; r < 3; r++)
+            for (int u = 0; u < 3; u++)
+              DJ[r][u] = Dq[3 * r] * Ji[0][u] + Dq[3 * r + 1] * Ji[1][u] + Dq[3 * r + 2] * Ji[2][u];
+          double C[3][3];
+          for (int s2 = 0; s2 < 3; s2++)
+            for (int u = 0; u < 3; u++)
+              C[s2][u] = w * (Ji[0][s2] * DJ[0][u] + Ji[1][s2] * DJ[1][u] + Ji[2][s2] * DJ[2][u]);
+          g[0 * Q + q] = C[0][0];
+          g[1 * Q + q] = 0.5 * (C[0][1] + C[1][0]);
+          g[2 * Q + q] = 0.5 * (C[0][2] + C[2][0]);
+          g[3 * Q + q] = C[1][1];
+          g[4 * Q + q] = 0.5 * (C[1][2] + C[2][1]);
+          g[5 * Q + q] = C[2][2];
+          g[6 * Q + q] = w;
+        }
+  });
+  if (bad[0]) { set_err(err, "degenerate or inverted element"); return false; }
+  if (bad[1]) {
+    set_err(err, "the diffusion tensor interpolated from the nodal fibers is indefinite at a quadrature point");
+    return false;
+  }
+  // node adjacency (element * npe + local index), ascending per node
+  out.adj_ptr.assign(n_nodes + 1, 0);
+  for (int64_t t = 0; t < n_elems * npe; t++) out.adj_ptr[conn[t] + 1]++;
+  for (int64_t i = 0; i < n_nodes; i++) out.adj_ptr[i + 1] += out.adj_ptr[i];
+  if (out.adj_ptr[n_nodes] >= (int64_t)INT32_MAX) { set_err(err, "too many element entries for int32"); return false; }
+  out.adj.assign(out.adj_ptr[n_nodes], 0);
+  std::vector<int64_t> fill(out.adj_ptr.begin(), out.adj_ptr.end() - 1);
+  for (int64_t t = 0; t < n_elems * npe; t++) out.adj[fill[conn[t]]++] = (int32_t)t;
+  return true;
+}
+
 bool assemble_csr(int elem, int64_t n_nodes, const double* xyz, int64_t n_elems,
                   const int32_t* conn, const double* f0, const double* s0, const double* n0,
                   double sigma_l, double sigma_t, double sigma_n, double chi, double cm, Csr& A,

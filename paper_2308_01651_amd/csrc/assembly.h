@@ -32,6 +32,28 @@ bool assemble_csr(int elem, int64_t n_nodes, const double* xyz, int64_t n_elems,
                   Csr& out, std::vector<char>& err, const int32_t* region = nullptr,
                   const double* region_sigma = nullptr, const unsigned char* region_on = nullptr);
 
+// Data of the matrix-free operator of hexahedra of degree p = 2 or 3
+// (sum factorization on the (p + 1)^3 Gauss points the assembly uses).
+// Per element and quadrature point q (x fastest), stored component-major
+// per element, geo[(e * 7 + c) * Q + q]:
+//   c = 0..5: the symmetric C = w det(J) J^-1 D J^-T (in the reference
+//   frame: xx, xy, xz, yy, yz, zz), so that K_e x = sum_q dN^T C dN x;
+//   c = 6: m = w det(J), so that M_e x = sum_q N m N^T x.
+// V[q * n1 + j], Dv[q * n1 + j]: 1-D Lagrange factor j (equispaced nodes)
+// and its derivative at Gauss point q.  Node adjacency for the gather:
+// entries (e * npe + k) of node i, ascending, in adj_ptr[i] .. adj_ptr[i+1].
+struct MfData {
+  int p = 0;
+  int64_t n_elems = 0;
+  std::vector<double> geo;
+  std::vector<double> V, Dv;
+  std::vector<int64_t> adj_ptr;
+  std::vector<int32_t> adj;
+};
+bool mf_setup(int elem, int64_t n_nodes, const double* xyz, int64_t n_elems, const int32_t* conn,
+              const double* f0, const double* s0, const double* n0, double sigma_l, double sigma_t,
+              double sigma_n, double chi, double cm, MfData& out, std::vector<char>& err);
+
 // Distinct column offsets j - i over the pattern, ascending.
 std::vector<int64_t> distinct_offsets(const Csr& A);
 

@@ -28,7 +28,7 @@ constexpr int NPARAM = 32;     // model parameter slots
 constexpr int MAX_REGIONS = 8; // subdomains of one simulation
 constexpr int RING = 4;        // potential history ring (u_{n+1}, u_n, u_{n-1}, u_{n-2})
 
-enum Fmt : int32_t { FMT_SELL = 1, FMT_DIA = 2 };
+enum Fmt : int32_t { FMT_SELL = 1, FMT_DIA = 2, FMT_MF = 3 };
 enum Model : int32_t { M_PASSIVE = 0, M_AP = 1, M_BO = 2, M_TTP06 = 3 };
 enum Prec : int32_t { P_FP64 = 0, P_MIXED = 1 };
 enum Flag : int32_t { F_NAN = 1, F_NOCONV = 2, F_BREAKDOWN = 4 };
@@ -144,6 +144,18 @@ struct InstDesc {
   int32_t multi_model;
   int32_t rmodel[MAX_REGIONS];
   double rconv[MAX_REGIONS][3];
+  // matrix-free operator (fmt == FMT_MF, FP64): hexahedra of degree mf_p,
+  // applied element by element by sum factorization into element results,
+  // which the row kernels add up per node (A z: yA; the rhs's M g: yM)
+  int32_t mf_p;
+  int64_t n_elems;
+  const int32_t* econn;    // [n_elems][(mf_p + 1)^3] element nodes
+  const double* geo;       // [n_elems][7][(mf_p + 1)^3] quadrature-point factors
+  double* yA;              // [n_elems][(mf_p + 1)^3]
+  double* yM;              // [n_elems][(mf_p + 1)^3]
+  const int64_t* adj_ptr;  // [n + 1] element entries of each node
+  const int32_t* adj;      // entry e * npe + k, ascending
+  double mfV[16], mfD[16]; // 1-D basis factor j and derivative at Gauss point q: [q * (p + 1) + j]
 };
 
 // Partial-sum layout inside InstDesc::partial, in units of nblk doubles:

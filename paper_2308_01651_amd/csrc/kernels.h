@@ -22,6 +22,11 @@ struct Launch {
   int xmap = 0;
   int ionic_npt = 1;
   bool ionic_bdf = false;  // the instances use the semi-implicit BDF ionic scheme
+  // matrix-free operator (single instance, FP64): degree of its hexahedra
+  // (0: assembled) and element count; the SpMV and rhs launches then run
+  // the element kernels first
+  int mf_p = 0;
+  int64_t mf_elems = 0;
 };
 
 void launch_ionic(int model, bool mixed, const Launch& L);

@@ -153,6 +153,215 @@ __device__ __forceinline__ bool cg_idle(const InstState& S) {
   return c.conv != 0 || (c.conv_in != 0 && c.restart == 0);
 }
 
+
+// ---------------------------------------------------------------------------
+// matrix-free operator of hexahedra of degree P (2 or 3): element results by
+// sum factorization on the (P + 1)^3 Gauss points (the paper lists
+// matrix-free high-order solvers as the route to GPUs).  y_e = sum_q
+// [N m_q u(q) + dN^T C_q grad_ref u(q)] with u = x_e interpolated; the
+// 1-D factors (V, Dv) act one direction at a time: n1^4 operations per
+// contraction instead of n1^6 for the element matrix.  n1^2 threads per
+// element, each holding one column of n1 values in registers; the x and y
+// directions go through LDS.  One wavefront per workgroup carries
+// 64 / n1^2 elements.  The node sums are taken by the row kernels
+// (mf_row), in ascending entry order.
+// ---------------------------------------------------------------------------
+
+template <int P>
+struct MfShape {
+  static constexpr int N1 = P + 1, T = N1 * N1, NPE = N1 * N1 * N1, EPW = 64 / T;
+};
+
+// WHICH 0: yA = (c M + K) z; 1: yM = M g; 2: yA = (c M + K) x0 (rhs residual)
+template <int P, int WHICH>
+__global__ __launch_bounds__(64) void k_mf_apply(InstDesc* __restrict__ insts) {
+  using S_ = MfShape<P>;
+  constexpr int N1 = S_::N1, T = S_::T, NPE = S_::NPE, EPW = S_::EPW;
+  constexpr bool STIFF = WHICH != 1;
+  const InstDesc& I = insts[0];
+  const InstState& St = I.st;
+  if (WHICH == 0 && cg_idle(St)) return;
+  __shared__ double buf[EPW > 0 ? EPW : 1][5][NPE];
+  const int slot = threadIdx.x / T, t = threadIdx.x % T;
+  const int64_t e = (int64_t)blockIdx.x * EPW + slot;
+  const bool live = slot < EPW && e < I.n_elems;
+  const int ts = live ? slot : 0;          // idle threads keep in-range LDS indices
+  double (*B)[NPE] = buf[ts];
+  const int i1 = t % N1, i2 = t / N1;      // the thread's two in-plane indices
+  auto L = [](int x, int y, int z) { return x + N1 * (y + N1 * z); };
+  const double* __restrict__ V = I.mfV;
+  const double* __restrict__ Dv = I.mfD;
+  const double* xin = WHICH == 0 ? I.z : (WHICH == 1 ? I.g : I.u_new);
+  const int sig = min(I.bdf, (int)St.step + 1);
+  const double cmass = (sig == 1 ? 1.0 : (sig == 2 ? 1.5 : 11.0 / 6.0)) * I.inv_dt;
+  // ---- forward: column (a, b) = (i1, i2) ----
+  double X[N1], Y[N1], Yd[N1];
+  if (live) {
+#pragma unroll
+    for (int c = 0; c < N1; c++) X[c] = gmem(xin)[gmem(I.econn)[e * NPE + L(i1, i2, c)]];
+  } else {
+#pragma unroll
+    for (int c = 0; c < N1; c++) X[c] = 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < N1; q++) {
+    double y = 0.0, yd = 0.0;
+#pragma unroll
+    for (int c = 0; c < N1; c++) {
+      y += V[q * N1 + c] * X[c];
+      if (STIFF) yd += Dv[q * N1 + c] * X[c];
+    }
+    Y[q] = y;
+    Yd[q] = yd;
+  }
+  if (live) {
+#pragma unroll
+    for (int q = 0; q < N1; q++) {
+      B[0][L(i1, i2, q)] = Y[q];
+      if (STIFF) B[1][L(i1, i2, q)] = Yd[q];
+    }
+  }
+  __syncthreads();
+  // y direction: thread (a, qy) = (i1, i2)
+  if (live) {
+#pragma unroll
+    for (int qz = 0; qz < N1; qz++) {
+      double w = 0.0, wy = 0.0, wz = 0.0;
+#pragma unroll
+      for (int b = 0; b < N1; b++) {
+        const double y0 = B[0][L(i1, b, qz)];
+        w += V[i2 * N1 + b] * y0;
+        if (STIFF) {
+          wy += Dv[i2 * N1 + b] * y0;
+          wz += V[i2 * N1 + b] * B[1][L(i1, b, qz)];
+        }
+      }
+      B[2][L(i1, i2, qz)] = w;
+      if (STIFF) {
+        B[3][L(i1, i2, qz)] = wy;
+        B[4][L(i1, i2, qz)] = wz;
+      }
+    }
+  }
+  __syncthreads();
+  // x direction and the quadrature point: thread (qx, qy) = (i1, i2)
+  double Mq[N1], F0[N1], F1[N1], F2[N1];
+  const gptr<const double> geo = gmem(I.geo) + (live ? e : 0) * 7 * NPE;
+#pragma unroll
+  for (int qz = 0; qz < N1; qz++) {
+    double u = 0.0, ux = 0.0, uy = 0.0, uz = 0.0;
+    if (live) {
+#pragma unroll
+      for (int a = 0; a < N1; a++) {
+        const double w = B[2][L(a, i2, qz)];
+        u += V[i1 * N1 + a] * w;
+        if (STIFF) {
+          ux += Dv[i1 * N1 + a] * w;
+          uy += V[i1 * N1 + a] * B[3][L(a, i2, qz)];
+          uz += V[i1 * N1 + a] * B[4][L(a, i2, qz)];
+        }
+      }
+    }
+    const int q = L(i1, i2, qz);
+    const double m = live ? geo[6 * NPE + q] : 0.0;
+    Mq[qz] = (STIFF ? cmass : 1.0) * m * u;
+    if (STIFF) {
+      double c0 = 0, c1 = 0, c2 = 0, c3 = 0, c4 = 0, c5 = 0;
+      if (live) {
+        c0 = geo[q]; c1 = geo[NPE + q]; c2 = geo[2 * NPE + q];
+        c3 = geo[3 * NPE + q]; c4 = geo[4 * NPE + q]; c5 = geo[5 * NPE + q];
+      }
+      F0[qz] = c0 * ux + c1 * uy + c2 * uz;
+      F1[qz] = c1 * ux + c3 * uy + c4 * uz;
+      F2[qz] = c2 * ux + c4 * uy + c5 * uz;
+    }
+  }
+  __syncthreads();   // every read of the forward buffers is done
+  if (live) {
+#pragma unroll
+    for (int qz = 0; qz < N1; qz++) {
+      B[0][L(i1, i2, qz)] = Mq[qz];
+      if (STIFF) {
+        B[1][L(i1, i2, qz)] = F0[qz];
+        B[2][L(i1, i2, qz)] = F1[qz];
+        B[3][L(i1, i2, qz)] = F2[qz];
+      }
+    }
+  }
+  __syncthreads();
+  // ---- backward (transposes) ----
+  // x: thread (a, qy) = (i1, i2)
+  double G0[N1], G1[N1], G2[N1];
+#pragma unroll
+  for (int qz = 0; qz < N1; qz++) {
+    double g0 = 0.0, g1 = 0.0, g2 = 0.0;
+    if (live) {
+#pragma unroll
+      for (int qx = 0; qx < N1; qx++) {
+        g0 += V[qx * N1 + i1] * B[0][L(qx, i2, qz)];
+        if (STIFF) {
+          g0 += Dv[qx * N1 + i1] * B[1][L(qx, i2, qz)];
+          g1 += V[qx * N1 + i1] * B[2][L(qx, i2, qz)];
+          g2 += V[qx * N1 + i1] * B[3][L(qx, i2, qz)];
+        }
+      }
+    }
+    G0[qz] = g0;
+    G1[qz] = g1;
+    G2[qz] = g2;
+  }
+  __syncthreads();
+  if (live) {
+#pragma unroll
+    for (int qz = 0; qz < N1; qz++) {
+      B[0][L(i1, i2, qz)] = G0[qz];
+      if (STIFF) {
+        B[1][L(i1, i2, qz)] = G1[qz];
+        B[4][L(i1, i2, qz)] = G2[qz];
+      }
+    }
+  }
+  __syncthreads();
+  // y: thread (a, b) = (i1, i2); then z in registers
+  if (!live) return;
+  double H0[N1], H2[N1];
+#pragma unroll
+  for (int qz = 0; qz < N1; qz++) {
+    double h0 = 0.0, h2 = 0.0;
+#pragma unroll
+    for (int qy = 0; qy < N1; qy++) {
+      h0 += V[qy * N1 + i2] * B[0][L(i1, qy, qz)];
+      if (STIFF) {
+        h0 += Dv[qy * N1 + i2] * B[1][L(i1, qy, qz)];
+        h2 += V[qy * N1 + i2] * B[4][L(i1, qy, qz)];
+      }
+    }
+    H0[qz] = h0;
+    H2[qz] = h2;
+  }
+  const gptr<double> yout = gmem(WHICH == 1 ? I.yM : I.yA) + e * NPE;
+#pragma unroll
+  for (int c = 0; c < N1; c++) {
+    double y = 0.0;
+#pragma unroll
+    for (int qz = 0; qz < N1; qz++) {
+      y += V[qz * N1 + c] * H0[qz];
+      if (STIFF) y += Dv[qz * N1 + c] * H2[qz];
+    }
+    yout[L(i1, i2, c)] = y;
+  }
+}
+
+// Node sum of element results: the value of row i of the operator product.
+__device__ __forceinline__ double mf_row(const InstDesc& I, const double* __restrict__ y, int64_t i) {
+  const gptr<const int64_t> ap = gmem(I.adj_ptr);
+  const gptr<const int32_t> ad = gmem(I.adj);
+  const gptr<const double> yv = gmem(y);
+  double acc = 0.0;
+  for (int64_t j = ap[i]; j < ap[i + 1]; j++) acc += yv[ad[j]];
+  return acc;
+}
+
 // z = P^{-1} r for the row i this lane owns.  Jacobi (block 1): one scaling.
 // Block Jacobi: a block of `bs` consecutive rows lies inside one wavefront
 // (bs divides 64 and tiles start at multiples of 64), so the block's
@@ -517,14 +726,15 @@ __global__ __launch_bounds__(WG) void k_residual(InstDesc* __restrict__ insts, c
     const bool valid = i < I.n;
     double bi = 0.0, ri = 0.0;
     if (valid) {
+      const bool mf = !MIXED && I.fmt == FMT_MF;
       if (WITH_RHS) {
-        bi = spmv_row<double, double, double>(I, I.valM, I.g, i);
+        bi = mf ? mf_row(I, I.yM, i) : spmv_row<double, double, double>(I, I.valM, I.g, i);
         if (I.het) bi -= gmem((const double*)I.cvec)[i];
         b[i] = bi;
       } else {
         bi = b[i];
       }
-      ri = bi - spmv_row<double, double, double>(I, I.valA[sig - 1], x, i);
+      ri = bi - (mf ? mf_row(I, I.yA, i) : spmv_row<double, double, double>(I, I.valA[sig - 1], x, i));
     }
     if (!MIXED) {
       const double zi = precond_apply<double>(I.dinv[sig - 1], I.bld, I.block, i, valid, ri);
@@ -592,7 +802,8 @@ __global__ __launch_bounds__(WG) void k_cg_spmv(InstDesc* __restrict__ insts, co
       gmem(I.w32)[i] = wi;
       v[0] += (double)wi * (double)gmem(I.z32)[i];
     } else {
-      const double wi = spmv_row<double, double, double>(I, I.valA[sig - 1], I.z, i);
+      const double wi = I.fmt == FMT_MF ? mf_row(I, I.yA, i)
+                                         : spmv_row<double, double, double>(I, I.valA[sig - 1], I.z, i);
       gmem(I.w)[i] = wi;
       v[0] += wi * gmem(I.z)[i];
     }
@@ -1073,14 +1284,34 @@ static void update_dispatch(const Launch& L) {
   else hipLaunchKernelGGL((k_cg_update<MX, true, 0>), g, b, 0, L.stream, L.insts, L.bmap);
 }
 
+template <int P>
+static void mf_apply(int which, const Launch& L) {
+  constexpr int EPW = MfShape<P>::EPW;
+  const unsigned grid = (unsigned)((L.mf_elems + EPW - 1) / EPW);
+  if (grid == 0) return;
+  if (which == 0) hipLaunchKernelGGL((k_mf_apply<P, 0>), dim3(grid), dim3(64), 0, L.stream, L.insts);
+  else if (which == 1) hipLaunchKernelGGL((k_mf_apply<P, 1>), dim3(grid), dim3(64), 0, L.stream, L.insts);
+  else hipLaunchKernelGGL((k_mf_apply<P, 2>), dim3(grid), dim3(64), 0, L.stream, L.insts);
+}
+
+static void launch_mf_apply(int which, const Launch& L) {
+  if (L.mf_p == 2) mf_apply<2>(which, L);
+  else if (L.mf_p == 3) mf_apply<3>(which, L);
+}
+
 void launch_residual(bool mixed, bool with_rhs, const Launch& L) {
   if (L.nblocks <= 0) return;
+  if (L.mf_p && with_rhs) {
+    launch_mf_apply(1, L);   // M g
+    launch_mf_apply(2, L);   // A x0
+  }
   if (mixed) with_rhs ? residual_dispatch<true, true>(L) : residual_dispatch<true, false>(L);
   else with_rhs ? residual_dispatch<false, true>(L) : residual_dispatch<false, false>(L);
 }
 
 void launch_cg_spmv(bool mixed, const Launch& L) {
   if (L.nblocks <= 0) return;
+  if (L.mf_p) launch_mf_apply(0, L);
   mixed ? spmv_dispatch<true>(L) : spmv_dispatch<false>(L);
 }
 

@@ -102,3 +102,79 @@ def test_quadratic_trajectory(kind, prec):
         assert np.array_equal(ok, ~np.isnan(at_s)) and np.max(np.abs(at_s[ok] - at_r[ok])) <= 0.1
     ref.close()
     sim.close()
+
+
+# ---- matrix-free operator (sum factorization) -------------------------------
+
+@pytest.mark.parametrize("kind,model,variant,bdf,curved", [("q2", "ttp06", "endo", 2, False),
+                                                           ("q2", "bo", "epi", 3, True),
+                                                           ("q3", "ttp06", "endo", 2, False),
+                                                           ("q3", "ap", "", 1, True)])
+def test_matrix_free_single_step(kind, model, variant, bdf, curved):
+    """One step with the operator applied element by element (no assembled
+    matrix on the device) against the oracle's assembled step, from the same
+    random state, at rtol 1e-13: 1e-10 relative."""
+    ep = _ep()
+    spec = _spec(model=model, variant=variant, bdf=bdf, curved=curved, kind=kind)
+    n = spec.mesh.n_nodes
+    u, w = W.random_state(model, n, seed=73)
+    rng = np.random.default_rng(74)
+    scale = 1.0 if model == "ttp06" else 0.01
+    u_prev = np.stack([u + scale * rng.normal(size=n) for _ in range(bdf - 1)]) if bdf > 1 else None
+    o = OM.from_spec(spec, solver="splu", rtol=1e-13)
+    o.set_state(u, w, list(u_prev) if u_prev is not None else None, 5)
+    o.step()
+    sim = ep.Simulation.from_spec(spec, rtol=1e-13, matrix_format=ep.EP_FMT_MF)
+    assert sim.get_stats()["matrix_format"] == ep.EP_FMT_MF
+    sim.set_state(u, w, u_prev, 5)
+    sim.step(1)
+    ug, wg, _ = sim.get_state()
+    sim.close()
+    assert _rel(ug, o.u) < 1e-10, _rel(ug, o.u)
+    for v in range(w.shape[0]):
+        err = np.max(np.abs(wg[v] - o.w[v])) / max(np.max(np.abs(o.w[v])), 1e-30)
+        assert err < 1e-11, (v, err)
+
+
+@pytest.mark.parametrize("kind", ["q2", "q3"])
+def test_matrix_free_trajectory_matches_oracle_and_assembled(kind):
+    """300 steps with the matrix-free operator: against the oracle (1e-8
+    relative, activation times to the step) and against the assembled
+    (sliced ELL) run of the same workload."""
+    ep = _ep()
+    spec = _spec(dims=(6.0, 3.0, 1.0), h=0.5, kind=kind)
+    o = OM.from_spec(spec, solver="splu")
+    mf = ep.Simulation.from_spec(spec, matrix_format=ep.EP_FMT_MF)
+    sell = ep.Simulation.from_spec(spec)
+    for chunk in range(3):
+        o.run(100)
+        mf.step(100)
+        sell.step(100)
+        err = _rel(mf.get_potential(), o.potential_mv())
+        print(f"{kind} matrix-free: {(chunk + 1) * 100} steps, rel {err:.2e}", flush=True)
+        assert err < 1e-8, (chunk, err)
+    assert _rel(mf.get_potential(), sell.get_potential()) < 1e-8
+    at_o, at_m = o.activation_times(), mf.get_activation_times()
+    ok = ~np.isnan(at_o)
+    assert ok.sum() > 100 and np.array_equal(ok, ~np.isnan(at_m))
+    assert np.max(np.abs(at_o[ok] - at_m[ok])) <= spec.dt + 1e-9
+    mf.close()
+    sell.close()
+
+
+def test_matrix_free_rejections():
+    ep = _ep()
+    spec = _spec(kind="q2")
+    for kw in (dict(precision=ep.EP_MIXED), dict(block=4)):
+        with pytest.raises(ep.EpError):
+            ep.Simulation.from_spec(spec, matrix_format=ep.EP_FMT_MF, **kw)
+    q1 = W.SimSpec(W.slab_q1(2.0, 1.0, 1.0, 0.25), None, W.Physics(), "ap", "", [], 0.05, 1, 1, 1e-10, "t")
+    q1.fibers = W.uniform_fibers(q1.mesh.n_nodes)
+    with pytest.raises(ep.EpError):
+        ep.Simulation.from_spec(q1, matrix_format=ep.EP_FMT_MF)
+    pool = ep.Pool(1 << 30, 2, ep.EP_FP64)
+    s = ep.Simulation.from_spec(spec, matrix_format=ep.EP_FMT_MF, finalize=False)
+    with pytest.raises(ep.EpError):
+        pool.admit(s, 10)
+    s.close()
+    pool.close()
