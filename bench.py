@@ -83,20 +83,41 @@ def _src_hash():
     return h.hexdigest()[:16]
 
 
-def _traffic(kernel_kind, precision, workload):
-    """HBM bytes per launch from committed rocprofv3 counter runs (FETCH_SIZE,
-    WRITE_SIZE, scaled by the copy-kernel calibration), or None when no run
-    exists for the current kernel sources."""
-    p = os.path.join(ROOT, "profiles", "traffic.json")
+def _shape_key(kernel_kind, launch):
+    """Launch-shape suffix of a counter entry: the tile map of the CG and rhs
+    kernels, the nodes per thread of the ionic kernel."""
+    if kernel_kind in ("cg_spmv", "cg_update", "rhs", "ir_residual"):
+        return f"@xmap{launch.get('tile_map', 0)}"
+    if kernel_kind == "ionic":
+        return f"@npt{launch.get('ionic_npt', 1)}"
+    return ""
+
+
+def _counters(name, kernel_kind, precision, workload, launch):
+    """Entry of a committed counter summary (profiles/<name>) for this kernel,
+    precision, workload and launch shape, or None when there is none for the
+    current kernel sources."""
+    p = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(p):
-        return None
+        return None, None
     try:
         d = json.load(open(p))
     except Exception:
-        return None
-    key = f"{workload}:{precision}:{kernel_kind}"
+        return None, None
+    key = f"{workload}:{precision}:{kernel_kind}{_shape_key(kernel_kind, launch)}"
     e = d.get("entries", {}).get(key)
-    if not e or e.get("src_hash") != _src_hash():
+    h = _src_hash()
+    if not e or e.get("src_hash", d.get("src_hash")) != h:
+        return None, d
+    return e, d
+
+
+def _traffic(kernel_kind, precision, workload, launch):
+    """HBM bytes per launch from committed rocprofv3 counter runs (FETCH_SIZE,
+    WRITE_SIZE, scaled by the copy-kernel calibration), or None when no run
+    exists for the current kernel sources and this launch shape."""
+    e, d = _counters("traffic.json", kernel_kind, precision, workload, launch)
+    if e is None:
         return None
     f = d.get("copy_calibration", {})
     ff, fw = f.get("fetch_factor"), f.get("write_factor")
@@ -105,36 +126,64 @@ def _traffic(kernel_kind, precision, workload):
     return (e["fetch_kib_per_dispatch"] * ff + e["write_kib_per_dispatch"] * fw) * 1024.0
 
 
+FP64_VECTOR_TFLOPS, FP32_VECTOR_TFLOPS = 78.6, 157.3
+
+
+def _alu(kernel_kind, precision, workload, launch, avg_s):
+    """ALU roofline of a kernel from committed counter runs: its FP64 and FP32
+    flops per launch (SQ_INSTS_VALU_FLOPS_* x 64 lanes) over the live average
+    launch duration, against the vector peaks, and the VALU busy share the
+    counter run measured; None without a run for the current sources."""
+    e, _ = _counters("valu.json", kernel_kind, precision, workload, launch)
+    if e is None:
+        return None
+    r64 = e["fp64_flops_per_dispatch"] / avg_s / 1e12
+    r32 = e["fp32_flops_per_dispatch"] / avg_s / 1e12
+    return {"bound": "alu", "fp64_TFLOPs": r64, "fp32_TFLOPs": r32,
+            "peak": {"fp64": FP64_VECTOR_TFLOPS, "fp32": FP32_VECTOR_TFLOPS}, "unit": "TFLOP/s",
+            "frac": r64 / FP64_VECTOR_TFLOPS + r32 / FP32_VECTOR_TFLOPS,
+            "valu_busy_counters": e["valu_busy_pct"] / 100.0,
+            "flops_per_launch": e["fp64_flops_per_dispatch"] + e["fp32_flops_per_dispatch"]}
+
+
 TUNE_TRIAL = 3   # steps per candidate launch shape (the tuner runs 5 candidates)
 
 
-def _warm(sim, ep, warmup, graph, autotune):
-    """Untimed: the launch-shape tuner (5 x TUNE_TRIAL steps of the
-    simulation, before the warmup), then graph capture and at least two
-    warmup steps, so that neither tuning nor capture falls in the timed
-    region.  Returns the launch settings and the steps taken."""
+def _warm(sim, ep, warmup, graph, autotune, make_scratch):
+    """Untimed: the launch-shape tuner on a scratch copy of the simulation
+    (make_scratch() builds it; the tuner steps it 5 x TUNE_TRIAL times), then
+    the tuned shapes and graph capture on `sim` and `warmup` steps (at least
+    two with graphs, so that capture does not fall in the timed region).  The
+    timed steps of `sim` are then steps warmup + 1 onwards.  Returns the
+    launch settings and the steps taken."""
     launch = {"ionic_npt": 1, "tile_map": 0, "graph": bool(graph), "tuned": False}
-    taken = 0
     if autotune:
-        npt, tmap = sim.autotune(TUNE_TRIAL)
-        launch.update(ionic_npt=npt, tile_map=tmap, tuned=True, tuning_steps=5 * TUNE_TRIAL)
-        taken += 5 * TUNE_TRIAL
+        scratch = make_scratch()
+        npt, tmap = scratch.autotune(TUNE_TRIAL)
+        scratch.close()
+        sim.set_option(ep.EP_OPT_IONIC_NPT, npt)
+        sim.set_option(ep.EP_OPT_TILE_MAP, tmap)
+        launch.update(ionic_npt=npt, tile_map=tmap, tuned=True, tuning_steps=5 * TUNE_TRIAL,
+                      tuned_on="scratch copy")
     if graph:
         sim.set_option(ep.EP_OPT_GRAPH, 1)
-    w = max(2, warmup)
-    sim.step(w)
+    w = max(2, warmup) if graph else max(0, warmup)
+    if w:
+        sim.step(w)
     sim.sync()
-    return launch, taken + w
+    return launch, w
 
 
 def run_gpu(spec, precision, steps, warmup, instrument_steps, graph=True, autotune=True, ionic_scheme="rl",
-            material=None, regions=None):
+            material=None, regions=None, matrix_format=0):
     import paper_2308_01651_amd as ep
     import torch
-    sim = ep.Simulation.from_spec(spec, precision=precision, ionic_scheme=ionic_scheme, material=material,
-                                  regions=regions)
+    def make():
+        return ep.Simulation.from_spec(spec, precision=precision, ionic_scheme=ionic_scheme, material=material,
+                                       regions=regions, matrix_format=matrix_format)
+    sim = make()
     st0 = sim.get_stats()
-    launch, pre_steps = _warm(sim, ep, warmup, graph, autotune)
+    launch, pre_steps = _warm(sim, ep, warmup, graph, autotune, make)
     torch.cuda.synchronize()
     it0 = sim.get_stats()["cg_iters_total"]
     lat = []
@@ -158,7 +207,7 @@ def run_gpu(spec, precision, steps, warmup, instrument_steps, graph=True, autotu
         "cg_iters_per_step": (st["cg_iters_total"] - it0) / steps,
         "ir_sweeps_total": st["ir_sweeps_total"],
         "rel_residual_last": st["rel_residual_last"],
-        "matrix_format": {1: "SELL", 2: "DIA"}[st["matrix_format"]],
+        "matrix_format": {1: "SELL", 2: "DIA", 3: "MF"}[st["matrix_format"]],
         "n_diag": st["n_diag"],
         "nnz": st["nnz"],
         "device_bytes": st["device_bytes"],
@@ -174,7 +223,7 @@ def run_gpu(spec, precision, steps, warmup, instrument_steps, graph=True, autotu
     # same steps) with HIP events around every launch, so the per-kernel
     # breakdown describes the timed steps and not a later phase of the beat
     if instrument_steps > 0:
-        sim = ep.Simulation.from_spec(spec, precision=precision)
+        sim = make()
         sim.set_option(ep.EP_OPT_IONIC_NPT, launch["ionic_npt"])
         sim.set_option(ep.EP_OPT_TILE_MAP, launch["tile_map"])
         sim.step(pre_steps)
@@ -216,6 +265,7 @@ def roofline(res, spec, precision_name, workload_key):
     = CG iterations; launches after convergence return at once and their time
     is charged to the working ones).  The per-launch event durations carry
     the events' own cost (an empty pair is measured and reported beside)."""
+    launch = res.get("launch", {})
     n = spec.mesh.n_nodes
     nnz = res["nnz"]
     mixed = precision_name == "mixed"
@@ -247,7 +297,13 @@ def roofline(res, spec, precision_name, workload_key):
         if k in loop:
             per_kernel[k]["avg_us_loop"] = loop[k]
             per_kernel[k]["GBps_loop"] = b / (1e-6 * loop[k]) / 1e9
-    tr = _traffic(dom, precision_name, workload_key)
+        t = _traffic(k, precision_name, workload_key, launch)
+        if t is not None:
+            per_kernel[k]["traffic"] = t
+        al = _alu(k, precision_name, workload_key, launch, 1e-6 * per_kernel[k].get("avg_us_loop", 1e6 * a))
+        if al is not None:
+            per_kernel[k]["alu"] = al
+    tr = _traffic(dom, precision_name, workload_key, launch)
     return {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": tr, "algo_bytes_per_launch": bytes_per,
             "avg_launch_us": 1e6 * avg_s, "avg_launch_us_events": 1e6 * raw_s, "event_pair_overhead_us": ovh,
@@ -482,14 +538,17 @@ def main():
             # quadratic tetrahedra (each cell Kuhn-split) on the same lattice, and
             # tricubic elements of 0.3 mm (67 x 23 x 10 elements, 202 x 70 x 31
             # nodes: the C1 node count within 1 %)
-            for name, gen, h in (("fp64_q2_elements_same_nodes", W.slab_q2, 0.2),
-                                 ("fp64_p2_elements_same_nodes", W.slab_p2, 0.2),
-                                 ("fp64_q3_elements_438k_nodes", W.slab_q3, 0.3)):
+            for name, gen, h, fmt in (("fp64_q2_elements_same_nodes", W.slab_q2, 0.2, 0),
+                                      ("fp64_q2_matrix_free_same_nodes", W.slab_q2, 0.2, ep.EP_FMT_MF),
+                                      ("fp64_p2_elements_same_nodes", W.slab_p2, 0.2, 0),
+                                      ("fp64_q3_elements_438k_nodes", W.slab_q3, 0.3, 0),
+                                      ("fp64_q3_matrix_free_438k_nodes", W.slab_q3, 0.3, ep.EP_FMT_MF)):
                 mesh = gen(20.0, 7.0, 3.0, h)
                 fib = spec.fibers if mesh.n_nodes == spec.mesh.n_nodes else W.uniform_fibers(mesh.n_nodes)
                 hi = W.SimSpec(mesh, fib, spec.phys, spec.model, spec.variant,
                                spec.stimuli, spec.dt, spec.bdf, spec.n_steps, spec.rtol, name)
-                r0, _, _ = run_gpu(hi, ep.EP_FP64, args.steps, args.warmup, 0, bool(args.graph), bool(args.autotune))
+                r0, _, _ = run_gpu(hi, ep.EP_FP64, args.steps, args.warmup, 0, bool(args.graph), bool(args.autotune),
+                                   matrix_format=fmt)
                 out[name] = {k: r0[k] for k in (
                     "node_steps_per_s", "ms_per_step", "step_latency_ms_p50", "step_latency_ms_p99", "launch",
                     "cg_iters_per_step", "matrix_format", "nnz", "device_bytes")}
