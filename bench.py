@@ -45,14 +45,22 @@ def _workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def kernel_bytes(kind, n, nnz, mixed, nvars_model, fmt="DIA", n_diag=0):
+def kernel_bytes(kind, n, nnz, mixed, nvars_model, fmt="DIA", n_diag=0, pipe=False):
     """Algorithmic HBM bytes per launch of each kernel: every array the kernel
     must touch, read or written once.  The operator counts as stored: the
     symmetric DIA format keeps n_diag diagonals (offsets >= 0) of n values
     and no column indices; SELL keeps a value and a 4-byte column index per
-    nonzero.  Gathers of the input vector count once."""
+    nonzero.  Gathers of the input vector count once.  pipe: the FP64
+    pipelined CG, whose "cg_spmv" is its start kernel (w_0 = A u_0 and
+    m_0 = P^-1 w_0: reads z, dinv, writes w, m_0) and whose iteration kernel
+    "cg_pipe" reads m (gathered), dinv, z, w, p, s, x, r and writes z, s, p,
+    x, r, w, m'."""
     def mat(vb):
         return n_diag * n * vb if fmt == "DIA" else nnz * (vb + 4)
+    if kind == "cg_pipe":
+        return mat(8) + n * 120
+    if kind == "cg_spmv" and pipe and not mixed:
+        return mat(8) + n * 32
     if kind == "cg_spmv":
         return mat(4 if mixed else 8) + n * (8 if mixed else 16)
     if kind == "cg_update":
@@ -175,12 +183,13 @@ def _warm(sim, ep, warmup, graph, autotune, make_scratch):
 
 
 def run_gpu(spec, precision, steps, warmup, instrument_steps, graph=True, autotune=True, ionic_scheme="rl",
-            material=None, regions=None, matrix_format=0):
+            material=None, regions=None, matrix_format=0, cg_variant=0):
     import paper_2308_01651_amd as ep
     import torch
+
     def make():
         return ep.Simulation.from_spec(spec, precision=precision, ionic_scheme=ionic_scheme, material=material,
-                                       regions=regions, matrix_format=matrix_format)
+                                       regions=regions, matrix_format=matrix_format, cg_variant=cg_variant)
     sim = make()
     st0 = sim.get_stats()
     launch, pre_steps = _warm(sim, ep, warmup, graph, autotune, make)
@@ -217,7 +226,11 @@ def run_gpu(spec, precision, steps, warmup, instrument_steps, graph=True, autotu
     # kernel durations on the state the timed region ended with: HIP events
     # around back-to-back launches on the sim's stream (SpMV and rhs only:
     # the kernels whose outputs the next step recomputes)
-    res["loop_us"] = {"cg_spmv": sim.time_kernel_us("cg_spmv", 200), "rhs": sim.time_kernel_us("rhs", 50)}
+    try:
+        res["loop_us"] = {"cg_pipe": sim.time_kernel_us("cg_pipe", 200)}   # pipelined FP64 CG
+    except ep.EpError:
+        res["loop_us"] = {"cg_spmv": sim.time_kernel_us("cg_spmv", 200)}
+    res["loop_us"]["rhs"] = sim.time_kernel_us("rhs", 50)
     sim.close()
     # instrumented pass: a fresh simulation over the same window (same warmup,
     # same steps) with HIP events around every launch, so the per-kernel
@@ -274,22 +287,27 @@ def roofline(res, spec, precision_name, workload_key):
     cnt = res["kernel_launches"]
     ovh = res.get("event_pair_overhead_us", 0.0)
     work = dict(cnt)
+    pipe = cnt.get("cg_pipe", 0) > 0
     if not mixed:
         its, steps = res["instrumented_cg_iters"], res["instrumented_steps"]
-        work["cg_spmv"] = min(cnt["cg_spmv"], its + steps)
-        work["cg_update"] = min(cnt["cg_update"], its)
+        if pipe:
+            work["cg_pipe"] = min(cnt["cg_pipe"], its)
+            work["cg_spmv"] = min(cnt["cg_spmv"], steps)
+        else:
+            work["cg_spmv"] = min(cnt["cg_spmv"], its + steps)
+            work["cg_update"] = min(cnt["cg_update"], its)
     kinds = [k for k in ms if cnt[k] > 0]
     dom = max((k for k in kinds if k != "cg_finalize"), key=lambda k: ms[k])
     # n_diag counts the operator's diagonals; the symmetric DIA stores the (n_diag + 1) / 2 with offset >= 0
     fmt, nd = res["matrix_format"], (int(res["n_diag"]) + 1) // 2
-    bytes_per = kernel_bytes(dom, n, nnz, mixed, nv, fmt, nd)
+    bytes_per = kernel_bytes(dom, n, nnz, mixed, nv, fmt, nd, pipe)
     raw_s = ms[dom] / 1e3 / work[dom]
     loop = res.get("loop_us", {})
     avg_s = 1e-6 * loop[dom] if dom in loop else raw_s
     achieved = bytes_per / avg_s / 1e9
     per_kernel = {}
     for k in kinds:
-        b = kernel_bytes(k, n, nnz, mixed, nv, fmt, nd)
+        b = kernel_bytes(k, n, nnz, mixed, nv, fmt, nd, pipe)
         a = ms[k] / 1e3 / work[k]
         per_kernel[k] = {"avg_us_events": 1e6 * a, "launches": cnt[k], "launches_with_work": work[k],
                          "share": ms[k] / sum(ms.values()), "GBps_events": b / a / 1e9 if b else None,
@@ -521,15 +539,16 @@ def main():
         zmax = float(spec.mesh.xyz[:, 2].max())
         layers = W.material_layers(spec.mesh, 2, [zmax / 3, 2 * zmax / 3])
         layer_regions = {0: dict(variant="endo"), 1: dict(variant="mid"), 2: dict(variant="epi")}
-        for name, g, t, sch, mat, regs in (
-                ("fp64_default_launches", False, False, "rl", None, None),
-                ("fp64_graph_replay", True, bool(args.autotune), "rl", None, None),
-                ("fp64_paper_bdf_ionic_scheme", bool(args.graph), bool(args.autotune), "bdf", None, None),
-                ("fp64_three_cell_layers", bool(args.graph), bool(args.autotune), "rl", layers, layer_regions)):
-            if g == bool(args.graph) and t == bool(args.autotune) and sch == "rl" and mat is None:
+        for name, g, t, sch, mat, regs, cgv in (
+                ("fp64_default_launches", False, False, "rl", None, None, 0),
+                ("fp64_graph_replay", True, bool(args.autotune), "rl", None, None, 0),
+                ("fp64_chronopoulos_gear_cg", bool(args.graph), bool(args.autotune), "rl", None, None, 2),
+                ("fp64_paper_bdf_ionic_scheme", bool(args.graph), bool(args.autotune), "bdf", None, None, 0),
+                ("fp64_three_cell_layers", bool(args.graph), bool(args.autotune), "rl", layers, layer_regions, 0)):
+            if g == bool(args.graph) and t == bool(args.autotune) and sch == "rl" and mat is None and cgv == 0:
                 continue
-            r0, _, _ = run_gpu(spec, ep.EP_FP64, args.steps, args.warmup, 0, g, t, sch, mat, regs)
-            out[name] = {k: r0[k] for k in ("node_steps_per_s", "ms_per_step", "step_latency_ms_p50",
+            r0, _, _ = run_gpu(spec, ep.EP_FP64, args.steps, args.warmup, 0, g, t, sch, mat, regs, cg_variant=cgv)
+            out[name] = {k: r0[k] for k in ("node_steps_per_s", "ms_per_step", "cg_iters_per_step", "step_latency_ms_p50",
                                             "step_latency_ms_p99", "launch")}
             print(f"[bench] {name}: {r0['node_steps_per_s']:.4g} node-steps/s", file=sys.stderr, flush=True)
         if args.workload == "c1" and not args.no_element_variants:

@@ -93,10 +93,28 @@ enum {
                                HIP graphs (ignored while timers are on).  The stream
                                must allow capture (not the legacy null stream).      */
   EP_OPT_IONIC_SCHEME = 9,  /* EP_IONIC_* (before finalize)                           */
-  EP_OPT_IONIC_FP64 = 10    /* mixed precision: 1 steps the ionic model (state and
+  EP_OPT_IONIC_FP64 = 10,   /* mixed precision: 1 steps the ionic model (state and
                              * arithmetic) in FP64 while the inner CG stays FP32;
                              * 0 (default) FP32 (before finalize)                  */
+  EP_OPT_CG_VARIANT = 11    /* FP64 solver: EP_CG_* (before finalize); ignored in
+                             * mixed precision, whose inner solve is always
+                             * Chronopoulos-Gear.  Both formulations are PCG with
+                             * the same preconditioner; results agree to the
+                             * solver tolerance, not bitwise.                     */
 };
+
+/* FP64 CG formulations (EP_OPT_CG_VARIANT).  EP_CG_PIPELINED: one kernel per
+ * iteration (the SpMV of m = P^-1 w, the global sums and all vector updates
+ * of the pipelined recurrences; a reformulation of CG not in the paper, which
+ * names the preconditioned CG solve).  Its extra recurrences (w = A u,
+ * z = A q) carry rounding from iteration to iteration, which limits the
+ * attainable residual on ill-conditioned systems: a degree-5 hexahedral
+ * operator stalled above rtol 1e-13.  EP_CG_CHRONOPOULOS_GEAR: two kernels
+ * per iteration (SpMV, then the fused update).  EP_CG_AUTO (default):
+ * pipelined for linear elements (EP_HEX8, EP_TET4), Chronopoulos-Gear for
+ * higher degrees.  A pool steps its FP64 members with one formulation:
+ * ep_pool_admit rejects a sim that resolves to the other. */
+enum { EP_CG_AUTO = 0, EP_CG_PIPELINED = 1, EP_CG_CHRONOPOULOS_GEAR = 2 };
 
 /* Ionic integrators (EP_OPT_IONIC_SCHEME).  EP_IONIC_RUSH_LARSEN (default):
  * gates by the exponential at u_EXT, other variables one explicit step.
@@ -115,8 +133,11 @@ enum {
   EP_K_CG_UPDATE = 3,  /* fused CG vector update with <r, z>, <r, r>       */
   EP_K_ACTIVATION = 4, /* activation-time tracking, end of step            */
   EP_K_IR_RESIDUAL = 5,/* FP64 refinement residual (mixed precision)       */
-  EP_K_CG_FINALIZE = 6 /* per-instance reduction, convergence, step lengths */
+  EP_K_CG_FINALIZE = 6,/* per-instance reduction, convergence, step lengths */
+  EP_K_CG_PIPE = 7     /* pipelined CG iteration (FP64; its start kernel,    */
+                       /* w_0 = A u_0, counts as EP_K_CG_SPMV)               */
 };
+#define EP_N_KERNEL_KINDS 8
 
 typedef struct ep_stats {
   int64_t n_nodes;
@@ -280,7 +301,7 @@ ep_status ep_sim_get_threshold_times(ep_sim* sim, double* out_ms);
 ep_status ep_sim_get_stats(ep_sim* sim, ep_stats* out);
 
 /* Summed durations (ms, from HIP events on the sim's stream) and launch
- * counts per kernel kind (EP_K_*), both arrays [7], since
+ * counts per kernel kind (EP_K_*), both arrays [EP_N_KERNEL_KINDS], since
  * EP_OPT_KERNEL_TIMERS was last set.  Launches that found their solve already
  * converged return at once and are counted too. */
 ep_status ep_sim_get_kernel_times(ep_sim* sim, double* ms, int64_t* launches);
@@ -293,9 +314,13 @@ ep_status ep_sim_timer_overhead(ep_sim* sim, int reps, double* us_per_pair);
 /* Mean duration (us) of `reps` back-to-back launches of one kernel of the
  * step, between steps, on the sim's stream with the sim's launch shapes:
  * EP_K_CG_SPMV (w = A z) or EP_K_RHS (b = M g, r0 = b - A x0), the kernels
- * whose outputs the next step recomputes before reading them.  For
- * measurement; the simulation state is unchanged.  EP_ESTATE before finalize,
- * while pooled or during a step. */
+ * whose outputs the next step recomputes before reading them, or
+ * EP_K_CG_PIPE (pipelined FP64 sims): the solver state is saved to a device
+ * buffer (allocated on first use, about 9 vectors), the iteration is
+ * launched `reps` times past the last step's solution with the stopping test
+ * disabled, and the state is restored; EP_ESTATE if a launch stopped early
+ * (breakdown).  For measurement; the simulation state is unchanged (bitwise).
+ * EP_ESTATE before finalize, while pooled or during a step. */
 ep_status ep_sim_time_kernel(ep_sim* sim, int kind, int reps, double* us_per_launch);
 
 /* Launch-shape tuner (a growth direction, not in the paper): runs

@@ -27,9 +27,11 @@ EP_FMT_AUTO, EP_FMT_SELL, EP_FMT_DIA, EP_FMT_MF = 0, 1, 2, 3
 EP_OPT_MATRIX_FORMAT, EP_OPT_INNER_RTOL, EP_OPT_MAX_OUTER, EP_OPT_PHASE_TIMERS = 1, 2, 3, 4
 EP_OPT_KERNEL_TIMERS = 5
 EP_OPT_IONIC_NPT, EP_OPT_TILE_MAP, EP_OPT_GRAPH, EP_OPT_IONIC_SCHEME, EP_OPT_IONIC_FP64 = 6, 7, 8, 9, 10
+EP_OPT_CG_VARIANT = 11
+EP_CG_AUTO, EP_CG_PIPELINED, EP_CG_CHRONOPOULOS_GEAR = 0, 1, 2
 EP_IONIC_RUSH_LARSEN, EP_IONIC_BDF = 0, 1
 EP_MAX_REGIONS = 8
-KERNEL_KINDS = ["ionic", "rhs", "cg_spmv", "cg_update", "activation", "ir_residual", "cg_finalize"]
+KERNEL_KINDS = ["ionic", "rhs", "cg_spmv", "cg_update", "activation", "ir_residual", "cg_finalize", "cg_pipe"]
 
 MODEL_IDS = {"passive": EP_PASSIVE, "ap": EP_AP, "bo": EP_BO, "ttp06": EP_TTP06}
 CELL_IDS = {"": EP_CELL_EPI, "epi": EP_CELL_EPI, "endo": EP_CELL_ENDO, "mid": EP_CELL_MID}
@@ -165,15 +167,15 @@ class Simulation:
         return v.value
 
     def time_kernel_us(self, kind: str, reps: int = 200) -> float:
-        """ep_sim_time_kernel for "cg_spmv" or "rhs" (between steps)."""
+        """ep_sim_time_kernel for "cg_spmv", "rhs" or "cg_pipe" (between steps)."""
         v = C.c_double()
         check(lib.ep_sim_time_kernel(self._h, KERNEL_KINDS.index(kind), int(reps), C.byref(v)),
               "ep_sim_time_kernel")
         return v.value
 
     def get_kernel_times(self) -> dict:
-        ms = np.zeros(7)
-        cnt = np.zeros(7, np.int64)
+        ms = np.zeros(len(KERNEL_KINDS))
+        cnt = np.zeros(len(KERNEL_KINDS), np.int64)
         check(lib.ep_sim_get_kernel_times(self._h, _pd(ms), cnt.ctypes.data_as(_lib.PI64)),
               "ep_sim_get_kernel_times")
         return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(KERNEL_KINDS)}
@@ -218,13 +220,14 @@ class Simulation:
     @classmethod
     def from_spec(cls, spec, precision=EP_FP64, device=0, stream=None, rtol=None, max_it=1000,
                   matrix_format=EP_FMT_AUTO, finalize=True, inner_rtol=None, block=1, ionic_scheme="rl",
-                  material=None, regions=None, ionic_fp64=False):
+                  material=None, regions=None, ionic_fp64=False, cg_variant=EP_CG_AUTO):
         """Configure from a workloads.SimSpec (marshalling of its arrays).
         block > 1 selects block-Jacobi preconditioning with that block size;
         ionic_fp64: in mixed precision, step the ionic model in FP64;
         ionic_scheme "rl" (Rush-Larsen) or "bdf" (the paper's semi-implicit
         BDF).  material: per-element subdomain labels; regions: {label:
-        dict(variant=, params=, sigma=, conductive=)} passed to set_region."""
+        dict(variant=, params=, sigma=, conductive=)} passed to set_region;
+        cg_variant: the FP64 CG formulation (EP_CG_*)."""
         sim = cls(device, stream)
         m = spec.mesh
         sim.upload_mesh(m.elem, m.xyz, m.conn, material)
@@ -247,6 +250,8 @@ class Simulation:
             sim.set_option(EP_OPT_IONIC_SCHEME, {"bdf": EP_IONIC_BDF}[ionic_scheme])
         if ionic_fp64:
             sim.set_option(EP_OPT_IONIC_FP64, 1)
+        if cg_variant != EP_CG_AUTO:
+            sim.set_option(EP_OPT_CG_VARIANT, cg_variant)
         if finalize:
             sim.finalize()
         return sim

@@ -99,6 +99,7 @@ std::vector<double> default_init(int model) {
 
 struct DevMem {
   std::vector<void*> ptrs;
+  std::vector<size_t> sizes;   // bytes of each allocation, as ptrs
   size_t bytes = 0;
   hipError_t alloc(void** p, size_t nbytes) {
     *p = nullptr;
@@ -106,13 +107,24 @@ struct DevMem {
     hipError_t e = hipMalloc(p, nbytes);
     if (e == hipSuccess) {
       ptrs.push_back(*p);
+      sizes.push_back(nbytes);
       bytes += nbytes;
     }
     return e;
   }
+  // [lo, lo + nbytes) lies inside one allocation of this set
+  bool covers(const void* lo, size_t nbytes) const {
+    const uintptr_t a = reinterpret_cast<uintptr_t>(lo);
+    for (size_t k = 0; k < ptrs.size(); k++) {
+      const uintptr_t b = reinterpret_cast<uintptr_t>(ptrs[k]);
+      if (a >= b && a - b <= sizes[k] && nbytes <= sizes[k] - (a - b)) return true;
+    }
+    return false;
+  }
   void release() {
     for (void* p : ptrs) (void)hipFree(p);
     ptrs.clear();
+    sizes.clear();
     bytes = 0;
   }
 };
@@ -124,14 +136,15 @@ struct Stim {
 };
 
 // Per-kernel event timers: kinds 0 ionic, 1 rhs residual, 2 cg spmv,
-// 3 cg update, 4 activation, 5 refinement residual, 6 cg finalize.
+// 3 cg update, 4 activation, 5 refinement residual, 6 cg finalize,
+// 7 pipelined cg iteration.
 struct KernelTimers {
-  static constexpr int K = 7;
+  static constexpr int K = EP_N_KERNEL_KINDS;
   int on = 0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[K];
   std::vector<hipEvent_t> spare;
-  double ms[K] = {0, 0, 0, 0, 0, 0, 0};
-  int64_t count[K] = {0, 0, 0, 0, 0, 0, 0};
+  double ms[K] = {};
+  int64_t count[K] = {};
   hipEvent_t get() {
     if (!spare.empty()) {
       hipEvent_t e = spare.back();
@@ -252,6 +265,7 @@ struct ep_sim {
   int bdf = 1, prec = EP_FP64, precond = EP_JACOBI, block = 1, max_it = 1000, max_outer = 30;
   int ionic_scheme = 0;   // EP_IONIC_RUSH_LARSEN or EP_IONIC_BDF
   int ionic_fp64 = 0;     // mixed precision: ionic step in FP64 (EP_OPT_IONIC_FP64)
+  int cg_variant = EP_CG_AUTO;   // FP64 CG formulation (EP_OPT_CG_VARIANT)
   int fmt_pref = EP_FMT_AUTO;
   // subdomains: element labels (empty: one subdomain) and per-label settings
   std::vector<int32_t> material;
@@ -301,8 +315,11 @@ struct ep_sim {
   std::vector<int32_t> pt_model;   // ionic model of every ionic point (several subdomains)
   int het_model = -1;              // the one model of all subdomains, or -1 when they differ
   int st_rows64 = 0, st_rows32 = 0;  // rows of the FP64 / FP32 state arrays
+  int64_t sell_nnz = 0;   // stored entries of the SELL operator (slices padded to their widest row)
+  int64_t n_cent = 0;     // entries of the interface correction
   SweepPredictor sweeps;  // inner rounds per refinement sweep (mixed)
   int sticky = EP_OK;
+  double* tk_save = nullptr;   // saved solver state for timing the pipelined CG kernel
   // the ionic step runs in FP32 (state arrays and arithmetic)
   bool ionic_f32() const { return prec == EP_MIXED && !ionic_fp64; }
 };
@@ -317,6 +334,14 @@ ep_status check_sim(ep_sim* s) {
 }
 
 // Read the device state into pinned host memory (synchronizes the stream).
+// The FP64 CG formulation a sim runs: EP_CG_AUTO takes the pipelined one
+// for linear elements (small condition numbers; its recurrences reach every
+// tolerance tested there) and Chronopoulos-Gear for higher degrees.
+int cg_resolved(const ep_sim* s) {
+  if (s->cg_variant != EP_CG_AUTO) return s->cg_variant;
+  return (s->elem == EP_HEX8 || s->elem == EP_TET4) ? EP_CG_PIPELINED : EP_CG_CHRONOPOULOS_GEAR;
+}
+
 ep_status pull_state(ep_sim* s) {
   EP_HIP(hipMemcpyAsync(s->h_st, s->d_st, sizeof(InstState), hipMemcpyDeviceToHost, s->stream));
   EP_HIP(hipStreamSynchronize(s->stream));
@@ -592,6 +617,7 @@ ep_status finalize_impl(ep_sim* s) {
     slice_ptr[sl + 1] = slice_ptr[sl] + w * SLICE;
   }
   const int64_t sell_nnz = slice_ptr[n_slices];
+  s->sell_nnz = sell_nnz;
   const int64_t stride = round_up(n, 64);
   const double vb = mixed ? 4.0 : 8.0;
   // symmetric DIA keeps the offsets >= 0; the pattern of an FE operator is
@@ -945,6 +971,7 @@ ep_status finalize_impl(ep_sim* s) {
       cval.push_back(ents[t].v);
     }
     cptr.push_back((int64_t)ents.size());
+    s->n_cent = (int64_t)ents.size();
     if (crow.empty()) cptr.assign(1, 0);
     s->n_crow = (int64_t)crow.size();
     D.n_crow = (int32_t)crow.size();
@@ -999,6 +1026,11 @@ ep_status finalize_impl(ep_sim* s) {
   // single-instance launches cover N_XCD * ceil(tiles / N_XCD) workgroups
   s->nblocks = N_XCD * ((ntiles + N_XCD - 1) / N_XCD);
   EP_HIP(m.alloc((void**)&D.partial, (size_t)ntiles * PART_DOUBLES * sizeof(double)));
+  D.cg_pipe = (s->prec == EP_FP64 && cg_resolved(s) == EP_CG_PIPELINED) ? 1 : 0;
+  if (D.cg_pipe) {
+    EP_HIP(m.alloc((void**)&D.pipe_rec, (size_t)ntiles * 4 * sizeof(double)));
+    EP_HIP(hipMemsetAsync(D.pipe_rec, 0, (size_t)ntiles * 4 * sizeof(double), st));
+  }
   {
     const int32_t zero = 0;
     EP_HIP(upload(m, &s->d_ids, &zero, 1, st));
@@ -1030,10 +1062,13 @@ ep_status finalize_impl(ep_sim* s) {
 }
 
 // Host-side consistency check of a descriptor before kernels use it: every
-// array the configured path touches is present and the DIA geometry keeps all
-// shifted accesses inside the guard cells.  A failure is a library bug; it
-// is reported instead of launching.
-ep_status validate_desc(const InstDesc& D, int64_t guard) {
+// array the configured path touches is present, lies with the whole range
+// the kernels address (guard cells, padded rows, DIA diagonals, SELL slices,
+// state rows, element arrays) inside one of the sim's allocations, and the
+// DIA geometry keeps all shifted accesses inside the guard cells.  A
+// failure is a library bug; it is reported instead of launching.
+ep_status validate_desc(const ep_sim* s, const InstDesc& D) {
+  const int64_t guard = s->guard;
   auto bad = [](const char* what) { return fail(EP_EHIP, std::string("internal descriptor check: ") + what); };
   if (D.n <= 0 || D.nblk != (int)((D.n + TILE - 1) / TILE)) return bad("tile count");
   if (D.bdf < 1 || D.bdf > 3) return bad("bdf");
@@ -1075,6 +1110,65 @@ ep_status validate_desc(const InstDesc& D, int64_t guard) {
   if (D.n_stim < 0 || D.n_stim > MAX_STIM) return bad("stimuli");
   for (int k = 0; k < D.n_stim; k++)
     if (!D.stim[k].prof) return bad("stimulus profile");
+  // ---- address ranges ----
+  const DevMem& m = s->mem;
+  const int64_t n = D.n, n64 = ((n + 63) / 64) * 64, G = guard, npts = D.n_pts;
+  auto in = [&](const void* p, int64_t lo_elems, int64_t elems, size_t esz) {
+    return m.covers(static_cast<const char*>(p) - (size_t)lo_elems * esz, (size_t)elems * esz);
+  };
+  // vectors: rows up to the 64-row padding, with G guard cells on each side
+  const double* v64[] = {D.g, D.b, D.r, D.z, D.p, D.s, D.w, D.U[0], D.U[1], D.U[2], D.U[3]};
+  for (const double* v : v64)
+    if (!in(v, G, n64 + 2 * G, 8)) return bad("vector range");
+  if (D.prec == P_MIXED) {
+    const float* v32[] = {D.r32, D.z32, D.p32, D.s32, D.w32};
+    for (const float* v : v32)
+      if (!in(v, G, n64 + 2 * G, 4)) return bad("FP32 vector range");
+  }
+  const int nsig = D.bdf;
+  for (int q = 0; q < nsig; q++) {
+    if (!in(D.dinv[q], 0, D.block == 1 ? n64 : D.bld * D.block, 8)) return bad("preconditioner range");
+    if (D.prec == P_MIXED && !in(D.dinv32[q], 0, D.block == 1 ? n64 : D.bld * D.block, 4))
+      return bad("FP32 preconditioner range");
+  }
+  if (D.fmt == FMT_DIA) {
+    const int64_t span = (int64_t)D.nup * D.ld;
+    for (int q = 0; q <= nsig; q++) {
+      const double* v = q < nsig ? D.valA[q] : D.valM;
+      if (!in(v, G, span + G, 8)) return bad("DIA value range");
+      if (q < nsig && D.prec == P_MIXED && !in(D.valA32[q], G, span + G, 4)) return bad("FP32 DIA value range");
+    }
+  } else if (D.fmt == FMT_SELL) {
+    const int64_t ns = (n + SLICE - 1) / SLICE;
+    if (!in(D.slice_ptr, 0, ns + 1, 8) || !in(D.col, 0, s->sell_nnz, 4)) return bad("SELL index range");
+    for (int q = 0; q <= nsig; q++) {
+      const double* v = q < nsig ? D.valA[q] : D.valM;
+      if (!in(v, 0, s->sell_nnz, 8)) return bad("SELL value range");
+      if (q < nsig && D.prec == P_MIXED && !in(D.valA32[q], 0, s->sell_nnz, 4)) return bad("FP32 SELL value range");
+    }
+  } else {
+    const int64_t npe = s->elem, ent = D.n_elems * npe, Q = npe;
+    if (D.n_elems != s->n_elems || !in(D.econn, 0, ent, 4) || !in(D.geo, 0, D.n_elems * 7 * Q, 8) ||
+        !in(D.yA, 0, ent, 8) || !in(D.yM, 0, ent, 8) || !in(D.adj_ptr, 0, n + 1, 8) || !in(D.adj, 0, ent, 4))
+      return bad("matrix-free array range");
+  }
+  for (int k = 0; k < RING; k++)
+    if (!in(D.st64[k], 0, std::max<int64_t>(1, (int64_t)s->st_rows64 * npts), 8) ||
+        !in(D.st32[k], 0, std::max<int64_t>(1, (int64_t)s->st_rows32 * npts), 4))
+      return bad("ionic state range");
+  if (!in(D.smax, 0, n, 8) || !in(D.at, 0, n, 8) || !in(D.tcross, 0, n, 8)) return bad("activation range");
+  if (!in(D.partial, 0, (int64_t)D.nblk * PART_DOUBLES, 8)) return bad("partial sums range");
+  if (D.cg_pipe && (D.prec != P_FP64 || !in(D.pipe_rec, 0, (int64_t)D.nblk * 4, 8))) return bad("pipelined CG records");
+  for (int k = 0; k < D.n_stim; k++)
+    if (!in(D.stim[k].prof, 0, n, 8)) return bad("stimulus profile range");
+  if (D.het) {
+    if (!in(D.pt_reg, 0, npts, 4) || !in(D.sec_node, 0, std::max<int64_t>(1, npts - n), 4) ||
+        !in(D.rtab, 0, (int64_t)MAX_REGIONS * NPARAM, 8) || !in(D.ipt, 0, npts, 8) || !in(D.cvec, 0, n, 8))
+      return bad("subdomain array range");
+    if (D.n_crow > 0 && (!in(D.crow, 0, D.n_crow, 4) || !in(D.cptr, 0, D.n_crow + 1, 8) ||
+                         !in(D.ccol, 0, s->n_cent, 4) || !in(D.cval, 0, s->n_cent, 8)))
+      return bad("interface correction range");
+  }
   return EP_OK;
 }
 
@@ -1087,16 +1181,19 @@ Launch launch_of(ep_sim* s) {
   L.xmap = s->xmap;
   L.ionic_npt = s->ionic_npt;
   L.ionic_bdf = s->ionic_scheme == EP_IONIC_BDF;
+  L.pipe_op = (s->desc.fmt == FMT_DIA && s->desc.nup == 14 && s->desc.block == 1) ? 1 : 0;
   return L;
 }
 
 // One time step of one sim (host sequencing; all arithmetic on the device).
-// Kernel order: ionic, residual(+rhs), SpMV, finalize, then rounds of
-// {update, SpMV, finalize}; each finalize decides convergence on the device,
-// and the host reads that flag after a chunk of rounds.  Mixed precision
-// appends an FP64 refinement residual (+ SpMV, finalize) after each inner
-// sweep.  With graphs on (and no timers), the same sequences are replayed
-// from captured graphs.
+// Kernel order: ionic, residual(+rhs), then the solve.  FP64 pipelined CG:
+// the start kernel, then rounds of one iteration kernel; FP64
+// Chronopoulos-Gear: rounds of {SpMV, update}; mixed: SpMV, finalize, then
+// rounds of {update, SpMV, finalize}, with an FP64 refinement residual
+// (+ SpMV, finalize) after each inner sweep.  The kernels decide convergence
+// on the device; the host reads that flag after a chunk of rounds.  With
+// graphs on (and no timers), the same sequences are replayed from captured
+// graphs.
 ep_status step_once(ep_sim* s) {
   const Launch L = launch_of(s);
   const bool mixed = s->prec == EP_MIXED;
@@ -1105,7 +1202,12 @@ ep_status step_once(ep_sim* s) {
   auto fin = [&] { kt.timed(st, 6, [&] { launch_cg_finalize(mixed, s->d_desc, nullptr, 1, st); }); };
   // FP64: a round is SpMV then the update (which adds the partial sums
   // itself); mixed: update, SpMV, finalize
+  const bool pipe = !mixed && s->desc.cg_pipe;
   auto round = [&] {
+    if (pipe) {
+      kt.timed(st, 7, [&] { launch_cg_pipe(L); });
+      return;
+    }
     if (!mixed) {
       kt.timed(st, 2, [&] { launch_cg_spmv(false, L); });
       kt.timed(st, 3, [&] { launch_cg_update64(L); });
@@ -1128,6 +1230,7 @@ ep_status step_once(ep_sim* s) {
     if (s->timers) (void)hipEventRecord(s->ev[1], st);
     kt.timed(st, 1, [&] { launch_residual(mixed, true, L); });
     if (s->timers) (void)hipEventRecord(s->ev[2], st);
+    if (pipe) kt.timed(st, 2, [&] { launch_cg_pipe_start(L); });
     if (mixed) {
       kt.timed(st, 2, [&] { launch_cg_spmv(mixed, L); });
       fin();
@@ -1447,6 +1550,11 @@ ep_status ep_sim_set_option(ep_sim* s, int key, double value) {
       if (value != 0.0 && value != 1.0) return fail(EP_EINVAL, "ionic FP64: 0 or 1");
       s->ionic_fp64 = (int)value;
       return EP_OK;
+    case EP_OPT_CG_VARIANT:
+      if (value != EP_CG_AUTO && value != EP_CG_PIPELINED && value != EP_CG_CHRONOPOULOS_GEAR)
+        return fail(EP_EINVAL, "CG variant");
+      s->cg_variant = (int)value;
+      return EP_OK;
     default: return fail(EP_EINVAL, "unknown option");
   }
 }
@@ -1505,7 +1613,7 @@ ep_status ep_sim_autotune(ep_sim* s, int trial_steps, int* ionic_npt, int* tile_
   if (rc == EP_OK)
     rc = tune_one(
         kt, s->stream, trial_steps, {0, 1}, [&](int c) { s->xmap = c; }, step,
-        [&] { return kt.avg_us(2) + kt.avg_us(3); }, &xm);
+        [&] { return kt.avg_us(2) + kt.avg_us(3) + kt.avg_us(7); }, &xm);
   kt.zero();
   kt.on = was_on;
   s->graphs.reset();
@@ -1581,7 +1689,7 @@ ep_status ep_sim_set_state(ep_sim* s, const double* u, const double* w, const do
   D.u_prev1 = D.U[(step_index - 1) & 3];
   D.u_prev2 = D.U[(step_index - 2) & 3];
   {
-    ep_status vr = validate_desc(D, s->guard);
+    ep_status vr = validate_desc(s, D);
     if (vr != EP_OK) return vr;
   }
   EP_HIP(hipMemcpyAsync(s->d_desc, &D, sizeof(InstDesc), hipMemcpyHostToDevice, st));
@@ -1720,7 +1828,7 @@ ep_status ep_sim_get_kernel_times(ep_sim* s, double* ms, int64_t* launches) {
   if (check_sim(s) || !ms || !launches) return fail(EP_EINVAL, "null argument");
   if (s->stream) EP_HIP(hipStreamSynchronize(s->stream));
   s->kt.harvest();
-  for (int k = 0; k < 7; k++) {
+  for (int k = 0; k < KernelTimers::K; k++) {
     ms[k] = s->kt.ms[k];
     launches[k] = s->kt.count[k];
   }
@@ -1754,9 +1862,90 @@ ep_status ep_sim_timer_overhead(ep_sim* s, int reps, double* us_per_pair) {
   return EP_OK;
 }
 
+// Back-to-back launches of the pipelined CG iteration on a copy of a
+// mid-solve state: the vectors, partial sums, tile records and control state
+// the kernel touches are saved, then, in batches, restored, the stopping
+// test disabled (tol2 = 0) and the iteration launched `batch` times under
+// HIP events; afterwards everything is restored.  The state between steps
+// is that of the last step's final iteration, which found the residual
+// converged: past that test the recurrences continue as in a longer solve.
+ep_status time_pipe(ep_sim* s, int reps, double* us_per_launch) {
+  const InstDesc& D = s->desc;
+  if (!D.cg_pipe) return fail(EP_EINVAL, "the sim does not use the pipelined CG");
+  hipStream_t st = s->stream;
+  const int64_t G = s->guard, nv = ((s->n + 63) / 64) * 64 + 2 * G;
+  const int64_t step = s->h_st->step;
+  double* vec[8] = {D.z, D.w, D.p, D.s, D.U[(step + 1) & 3], D.r, D.g, D.b};
+  const int64_t npart = (int64_t)D.nblk * PART_DOUBLES, nrec = (int64_t)D.nblk * 4;
+  const int64_t total = 8 * nv + npart + nrec;
+  if (!s->tk_save) EP_HIP(s->mem.alloc((void**)&s->tk_save, (size_t)total * sizeof(double)));
+  double* sv = s->tk_save;
+  auto copy = [&](bool save) -> hipError_t {
+    for (int k = 0; k < 8; k++) {
+      double* a = vec[k] - G;
+      double* b = sv + k * nv;
+      hipError_t e = hipMemcpyAsync(save ? b : a, save ? a : b, nv * 8, hipMemcpyDeviceToDevice, st);
+      if (e != hipSuccess) return e;
+    }
+    hipError_t e = hipMemcpyAsync(save ? sv + 8 * nv : D.partial, save ? D.partial : sv + 8 * nv, npart * 8,
+                                  hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(save ? sv + 8 * nv + npart : D.pipe_rec, save ? D.pipe_rec : sv + 8 * nv + npart, nrec * 8,
+                         hipMemcpyDeviceToDevice, st);
+    return e;
+  };
+  const InstState saved = *s->h_st;
+  InstState armed = saved;
+  armed.tol2 = 0.0;
+  armed.conv = 0;
+  std::vector<double> rec((size_t)nrec);
+  EP_HIP(hipMemcpyAsync(rec.data(), D.pipe_rec, nrec * 8, hipMemcpyDeviceToHost, st));
+  EP_HIP(hipStreamSynchronize(st));
+  const int batch = std::min(reps, 16);
+  if ((int)rec[0] + 1 + batch >= s->max_it) return fail(EP_ESTATE, "too few iterations left below max_it");
+  EP_HIP(copy(true));
+  const Launch L = launch_of(s);
+  hipEvent_t a = nullptr, b = nullptr;
+  EP_HIP(hipEventCreate(&a));
+  EP_HIP(hipEventCreate(&b));
+  double ms_total = 0.0;
+  int done = 0;
+  bool short_run = false;
+  hipError_t err = hipSuccess;
+  while (done < reps && err == hipSuccess) {
+    const int nb = std::min(batch, reps - done);
+    err = copy(false);
+    if (err == hipSuccess) err = hipMemcpyAsync(s->d_st, &armed, sizeof(InstState), hipMemcpyHostToDevice, st);
+    if (err == hipSuccess) err = hipEventRecord(a, st);
+    for (int k = 0; k < nb && err == hipSuccess; k++) launch_cg_pipe(L);
+    if (err == hipSuccess) err = hipGetLastError();
+    if (err == hipSuccess) err = hipEventRecord(b, st);
+    if (err == hipSuccess) err = hipMemcpyAsync(s->h_st, s->d_st, sizeof(InstState), hipMemcpyDeviceToHost, st);
+    if (err == hipSuccess) err = hipStreamSynchronize(st);
+    if (err != hipSuccess) break;
+    float ms = 0.0f;
+    err = hipEventElapsedTime(&ms, a, b);
+    ms_total += ms;
+    if (s->h_st->it_step != armed.it_step + nb || s->h_st->conv) short_run = true;
+    done += nb;
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  // restore the state whatever happened above
+  EP_HIP(copy(false));
+  *s->h_st = saved;
+  EP_HIP(hipMemcpyAsync(s->d_st, &saved, sizeof(InstState), hipMemcpyHostToDevice, st));
+  EP_HIP(hipStreamSynchronize(st));
+  EP_HIP(err);
+  if (short_run) return fail(EP_ESTATE, "a timed iteration stopped early (breakdown)");
+  *us_per_launch = 1e3 * ms_total / reps;
+  return EP_OK;
+}
+
 ep_status ep_sim_time_kernel(ep_sim* s, int kind, int reps, double* us_per_launch) {
   if (check_sim(s) || reps < 1 || !us_per_launch) return fail(EP_EINVAL, "bad time-kernel arguments");
-  if (kind != EP_K_RHS && kind != EP_K_CG_SPMV) return fail(EP_EINVAL, "only the rhs and SpMV kernels can be repeated");
+  if (kind != EP_K_RHS && kind != EP_K_CG_SPMV && kind != EP_K_CG_PIPE)
+    return fail(EP_EINVAL, "only the rhs, SpMV and pipelined CG kernels can be timed");
   if (!s->finalized) return fail(EP_ESTATE, "finalize first");
   if (s->in_pool) return fail(EP_ESTATE, "sim is stepped by its pool");
   EP_HIP(hipSetDevice(s->device));
@@ -1767,6 +1956,7 @@ ep_status ep_sim_time_kernel(ep_sim* s, int kind, int reps, double* us_per_launc
   // between steps the solve-control flags are clear, so both kernels do their
   // full work; everything they write is recomputed by the next step
   if (s->h_st->conv || s->h_st->conv_in || s->h_st->restart) return fail(EP_ESTATE, "a step is in progress");
+  if (kind == EP_K_CG_PIPE) return time_pipe(s, reps, us_per_launch);
   const Launch L = launch_of(s);
   const bool mixed = s->prec == EP_MIXED;
   hipEvent_t a = nullptr, b = nullptr;
@@ -1982,6 +2172,7 @@ struct ep_pool {
   KernelTimers kt;
   int ionic_npt = 1, list_order = 0, use_graph = 0;  // launch shapes (EP_OPT_*)
   StepGraphs graphs;
+  int cg_variant = -1;  // FP64: the CG formulation of the members (-1: no member yet)
 };
 
 namespace {
@@ -2063,6 +2254,7 @@ int pool_iters(ep_pool* P) {
 
 ep_status pool_step_once(ep_pool* P) {
   const bool mixed = P->prec == EP_MIXED;
+  const bool pipe = !mixed && P->cg_variant == EP_CG_PIPELINED;
   const int ni = (int)P->active.size();
   Launch L{P->d_table, P->d_all, P->nb_all, P->stream, false};
   L.ionic_npt = P->ionic_npt;
@@ -2070,6 +2262,10 @@ ep_status pool_step_once(ep_pool* P) {
   hipStream_t st = P->stream;
   auto fin = [&] { kt.timed(st, 6, [&] { launch_cg_finalize(mixed, P->d_table, P->d_ids, ni, st); }); };
   auto round = [&] {
+    if (pipe) {
+      kt.timed(st, 7, [&] { launch_cg_pipe(L); });
+      return;
+    }
     if (!mixed) {
       kt.timed(st, 2, [&] { launch_cg_spmv(false, L); });
       kt.timed(st, 3, [&] { launch_cg_update64(L); });
@@ -2095,6 +2291,7 @@ ep_status pool_step_once(ep_pool* P) {
       }
     });
     kt.timed(st, 1, [&] { launch_residual(mixed, true, L); });
+    if (pipe) kt.timed(st, 2, [&] { launch_cg_pipe_start(L); });
     if (mixed) {
       kt.timed(st, 2, [&] { launch_cg_spmv(mixed, L); });
       fin();
@@ -2238,6 +2435,11 @@ ep_status ep_pool_admit(ep_pool* P, ep_sim* s, int64_t n_steps_total, int* slot)
   if (s->fmt_pref == EP_FMT_MF || (s->finalized && s->desc.fmt == FMT_MF))
     return fail(EP_EINVAL, "matrix-free sims are not admitted to pools");
   if (s->device != P->device) return fail(EP_EINVAL, "sim device differs from the pool's");
+  bool empty = true;
+  for (int k = 0; k < P->max_slots; k++)
+    if (P->slots[k].sim) empty = false;
+  if (P->prec == EP_FP64 && !empty && cg_resolved(s) != P->cg_variant)
+    return fail(EP_EINVAL, "sim CG variant differs from the pool members'");
   int free_slot = -1;
   for (int k = 0; k < P->max_slots; k++)
     if (!P->slots[k].sim) {
@@ -2272,6 +2474,7 @@ ep_status ep_pool_admit(ep_pool* P, ep_sim* s, int64_t n_steps_total, int* slot)
   s->pool = P;
   ep_pool::Slot& sl = P->slots[free_slot];
   sl.sim = s;
+  if (empty) P->cg_variant = cg_resolved(s);
   sl.target = n_steps_total;
   sl.done_steps = 0;
   sl.done = false;
@@ -2396,7 +2599,7 @@ ep_status ep_pool_autotune(ep_pool* P, int trial_steps, int* ionic_npt, int* til
             P->dirty = true;
           }
         },
-        step, [&] { return kt.avg_us(2) + kt.avg_us(3); }, &lo);
+        step, [&] { return kt.avg_us(2) + kt.avg_us(3) + kt.avg_us(7); }, &lo);
   kt.zero();
   kt.on = 0;
   P->graphs.reset();

@@ -156,6 +156,14 @@ struct InstDesc {
   const int64_t* adj_ptr;  // [n + 1] element entries of each node
   const int32_t* adj;      // entry e * npe + k, ascending
   double mfV[16], mfD[16]; // 1-D basis factor j and derivative at Gauss point q: [q * (p + 1) + j]
+  // FP64 pipelined CG (cg_pipe != 0): one kernel per iteration.  Its
+  // iteration index and the previous step lengths live in one record per
+  // tile, pipe_rec[4 * lblk + {0: k, 1: gamma_k, 2: alpha_k}], read and
+  // written only by the workgroup of that tile, so no workgroup of a launch
+  // can see another's update of the same launch.  m = P^-1 w alternates
+  // between b (even k) and g (odd k), both free during the FP64 solve.
+  int32_t cg_pipe;
+  double* pipe_rec;        // [nblk][4]
 };
 
 // Partial-sum layout inside InstDesc::partial, in units of nblk doubles:
@@ -163,7 +171,9 @@ struct InstDesc {
 // update kernel that reduces its predecessors' partials itself writes
 // iteration k's partials to [2][nblk] at PART_UPD + 2 (k & 1), so that no
 // workgroup overwrites partials another workgroup of the same launch reads.
-constexpr int PART_RES = 0, PART_SPMV = 4, PART_UPD = 5, PART_DOUBLES = 9;
+// The pipelined CG kernel writes iteration k's three partials
+// (<r, P^-1 r>, <w, P^-1 r>, <r, r>) to [3][nblk] at PART_PIPE + 3 (k & 1).
+constexpr int PART_RES = 0, PART_SPMV = 4, PART_UPD = 5, PART_PIPE = 5, PART_DOUBLES = 11;
 
 struct BlockMap {
   int32_t inst;

@@ -27,6 +27,9 @@ struct Launch {
   // the element kernels first
   int mf_p = 0;
   int64_t mf_elems = 0;
+  // pipelined CG of a single instance whose operator is the 14-diagonal
+  // symmetric DIA with Jacobi preconditioning: the specialized kernel
+  int pipe_op = 0;
 };
 
 void launch_ionic(int model, bool mixed, const Launch& L);
@@ -36,6 +39,10 @@ void launch_cg_update(bool mixed, const Launch& L);
 // FP64: the update with the finalize's work (partial sums, convergence,
 // step lengths) done by every workgroup; a round is SpMV then this kernel
 void launch_cg_update64(const Launch& L);
+// FP64 pipelined CG: the start (w_0 = A u_0, m_0, delta_0) after the
+// residual, then one launch per iteration (instances without cg_pipe skip)
+void launch_cg_pipe_start(const Launch& L);
+void launch_cg_pipe(const Launch& L);
 // one workgroup per instance listed in ids (device array of n_ids indices);
 // ids == nullptr with n_ids == 1: the single instance at insts[0]
 void launch_cg_finalize(bool mixed, InstDesc* insts, const int32_t* ids, int n_ids, hipStream_t stream);

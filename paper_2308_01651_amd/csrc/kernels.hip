@@ -172,7 +172,8 @@ struct MfShape {
   static constexpr int N1 = P + 1, T = N1 * N1, NPE = N1 * N1 * N1, EPW = 64 / T;
 };
 
-// WHICH 0: yA = (c M + K) z; 1: yM = M g; 2: yA = (c M + K) x0 (rhs residual)
+// WHICH 0: yA = (c M + K) z; 1: yM = M g; 2: yA = (c M + K) x0 (rhs residual);
+// 3: yA = (c M + K) m_k of the pipelined CG (k from tile 0's record)
 template <int P, int WHICH>
 __global__ __launch_bounds__(64) void k_mf_apply(InstDesc* __restrict__ insts) {
   using S_ = MfShape<P>;
@@ -180,7 +181,7 @@ __global__ __launch_bounds__(64) void k_mf_apply(InstDesc* __restrict__ insts) {
   constexpr bool STIFF = WHICH != 1;
   const InstDesc& I = insts[0];
   const InstState& St = I.st;
-  if (WHICH == 0 && cg_idle(St)) return;
+  if ((WHICH == 0 || WHICH == 3) && cg_idle(St)) return;
   __shared__ double buf[EPW > 0 ? EPW : 1][5][NPE];
   const int slot = threadIdx.x / T, t = threadIdx.x % T;
   const int64_t e = (int64_t)blockIdx.x * EPW + slot;
@@ -191,7 +192,8 @@ __global__ __launch_bounds__(64) void k_mf_apply(InstDesc* __restrict__ insts) {
   auto L = [](int x, int y, int z) { return x + N1 * (y + N1 * z); };
   const double* __restrict__ V = I.mfV;
   const double* __restrict__ Dv = I.mfD;
-  const double* xin = WHICH == 0 ? I.z : (WHICH == 1 ? I.g : I.u_new);
+  const double* xin = WHICH == 0 ? I.z : (WHICH == 1 ? I.g : (WHICH == 2 ? I.u_new : nullptr));
+  if (WHICH == 3) xin = (((int)gmem(I.pipe_rec)[0] + 1) & 1) ? I.g : I.b;
   const int sig = min(I.bdf, (int)St.step + 1);
   const double cmass = (sig == 1 ? 1.0 : (sig == 2 ? 1.5 : 11.0 / 6.0)) * I.inv_dt;
   // ---- forward: column (a, b) = (i1, i2) ----
@@ -386,6 +388,14 @@ __device__ __forceinline__ T precond_apply(const T* __restrict__ pinv, int64_t b
 // sparse row products
 // ---------------------------------------------------------------------------
 
+// Rounded product and fused multiply-add, spelled out so that the result
+// does not depend on how the compiler contracts the code around an inlined
+// row product (kernels that share a row product give the same bits).
+__device__ __forceinline__ double mul_rn(double a, double b) { return __dmul_rn(a, b); }
+__device__ __forceinline__ float mul_rn(float a, float b) { return __fmul_rn(a, b); }
+__device__ __forceinline__ double fmad(double a, double b, double c) { return fma(a, b, c); }
+__device__ __forceinline__ float fmad(float a, float b, float c) { return fmaf(a, b, c); }
+
 // Symmetric DIA: diagonal 0 plus, for each stored offset o > 0, the entry at
 // +o (stored at row i) and its mirror at -o (stored at row i - o).
 template <int NU, typename V, typename X, typename A>
@@ -394,14 +404,14 @@ __device__ __forceinline__ A dia_row(const InstDesc& I, const V* __restrict__ va
   const int64_t ld = I.ld;
   const gptr<const V> va = gmem(val);
   const gptr<const X> xa = gmem(x);
-  A acc = (A)va[i] * (A)xa[i];
+  A acc = mul_rn((A)va[i], (A)xa[i]);
   const int n_up = NU > 0 ? NU : nu;
 #pragma unroll
   for (int d = 1; d < (NU > 0 ? NU : MAX_UP); d++) {
     if (NU == 0 && d >= n_up) break;
     const int o = I.off[d];
-    acc += (A)va[d * ld + i] * (A)xa[i + o];
-    acc += (A)va[d * ld + i - o] * (A)xa[i - o];
+    acc = fmad((A)va[d * ld + i], (A)xa[i + o], acc);
+    acc = fmad((A)va[d * ld + i - o], (A)xa[i - o], acc);
   }
   return acc;
 }
@@ -758,6 +768,13 @@ __global__ __launch_bounds__(WG) void k_residual(InstDesc* __restrict__ insts, c
     if (WITH_RHS) v[2] += bi * bi;
   }
   write_partials<4>(v, I.partial + (int64_t)PART_RES * I.nblk, I.nblk, lblk);
+  if (!MIXED && WITH_RHS && I.cg_pipe && threadIdx.x == 0) {
+    // pipelined CG: this tile's record restarts at iteration -1
+    const gptr<double> rec = gmem(I.pipe_rec) + 4 * (int64_t)lblk;
+    rec[0] = -1.0;
+    rec[1] = 1.0;
+    rec[2] = 1.0;
+  }
   if (lblk == 0 && threadIdx.x == 0) {
     // a new (inner) solve starts at iteration 0; fields read by no workgroup
     // of this kernel (conv_in is cleared by the finalize that follows).  The
@@ -1120,6 +1137,196 @@ __global__ __launch_bounds__(WG) void k_cg_update64(InstDesc* __restrict__ insts
 }
 
 // ---------------------------------------------------------------------------
+// FP64 pipelined PCG (Ghysels and Vanroose's reformulation of CG, in which
+// the SpMV of an iteration acts on a vector the previous launch finished, so
+// that the SpMV, the global sums and the vector updates share one launch).
+// With P the (block) Jacobi preconditioner, u = P^-1 r and m = P^-1 w are
+// formed on the fly (q = P^-1 s is never needed: z = A q is carried by its
+// own recurrence).  Iteration k, given gamma_k = <r_k, u_k>, delta_k =
+// <w_k, u_k> and <r_k, r_k> from the partials of the previous launch:
+//   beta_k = gamma_k / gamma_{k-1}, alpha_k = gamma_k / (delta_k - beta_k gamma_k / alpha_{k-1})
+//   z = A m_k + beta z,  s = w + beta s,  p = u + beta p
+//   x += alpha p,  r -= alpha s,  w -= alpha z,  m_{k+1} = P^-1 w
+// In exact arithmetic this is the same iteration as the Chronopoulos-Gear
+// CG above; rounding differs, so results agree to the solver tolerance, not
+// bitwise.  Start (after the residual kernel, whose z is u_0):
+// k_cg_pipe_start forms w_0 = A u_0, m_0 = P^-1 w_0 and delta_0.
+// ---------------------------------------------------------------------------
+
+template <bool SINGLE, int XMAP>
+__global__ __launch_bounds__(WG) void k_cg_pipe_start(InstDesc* __restrict__ insts,
+                                                      const BlockMap* __restrict__ bmap) {
+  int lblk;
+  InstDesc& I = instance<SINGLE, XMAP>(insts, bmap, lblk);
+  if (lblk < 0) return;
+  const InstState& S = I.st;
+  if (!I.cg_pipe || S.conv != 0) return;
+  const int sig = min(I.bdf, (int)S.step + 1);
+  const int64_t i0 = (int64_t)lblk * TILE + threadIdx.x;
+  double v[1] = {0.0};
+#pragma unroll
+  for (int rw = 0; rw < RPT; rw++) {
+    const int64_t i = i0 + rw * WG;
+    const bool valid = i < I.n;
+    double wi = 0.0;
+    if (valid) {
+      wi = I.fmt == FMT_MF ? mf_row(I, I.yA, i) : spmv_row<double, double, double>(I, I.valA[sig - 1], I.z, i);
+      gmem(I.w)[i] = wi;
+      v[0] += wi * gmem(I.z)[i];
+    }
+    // every lane takes part (block Jacobi shuffles across the wavefront)
+    const double mi = precond_apply<double>(I.dinv[sig - 1], I.bld, I.block, i, valid, wi);
+    if (valid) gmem(I.b)[i] = mi;
+  }
+  write_partials<1>(v, I.partial + (int64_t)PART_SPMV * I.nblk, I.nblk, lblk);
+}
+
+// OP 1: the operator is the 14-diagonal symmetric DIA of the Q1 lattice and
+// the preconditioner Jacobi (the row product and the inverse diagonal are
+// then fixed at compile time); OP 0: any format and preconditioner.
+template <bool SINGLE, int XMAP, int OP>
+__global__ __launch_bounds__(WG) void k_cg_pipe(InstDesc* __restrict__ insts, const BlockMap* __restrict__ bmap) {
+  int lblk;
+  InstDesc& I = instance<SINGLE, XMAP>(insts, bmap, lblk);
+  if (lblk < 0) return;
+  InstState& S = I.st;
+  if (!I.cg_pipe || S.conv != 0) return;
+  const int nblk = I.nblk;
+  const int sig = min(I.bdf, (int)S.step + 1);
+  const gptr<double> rec = gmem(I.pipe_rec) + 4 * (int64_t)lblk;
+  const int k = (int)rec[0] + 1;
+  const double gam_prev = rec[1], alp_prev = rec[2];
+  const int64_t i0 = (int64_t)lblk * TILE + threadIdx.x;
+  // this thread's rows, loaded before the reduction so that they are in
+  // flight while the partial sums are added
+  const double* dinv = I.dinv[sig - 1];
+  double zv[RPT], wv[RPT], pv[RPT], sv[RPT], xv[RPT], rv[RPT], dv[RPT];
+#pragma unroll
+  for (int rw = 0; rw < RPT; rw++) {
+    const int64_t i = i0 + rw * WG;
+    zv[rw] = wv[rw] = pv[rw] = sv[rw] = xv[rw] = rv[rw] = dv[rw] = 0.0;
+    if (i < I.n) {
+      zv[rw] = gmem(I.z)[i];
+      wv[rw] = gmem(I.w)[i];
+      pv[rw] = gmem(I.p)[i];
+      sv[rw] = gmem(I.s)[i];
+      xv[rw] = gmem(I.u_new)[i];
+      rv[rw] = gmem(I.r)[i];
+      if (OP == 1) dv[rw] = gmem(dinv)[i];
+    }
+  }
+  const double* __restrict__ P = I.partial;
+  double gamma, delta, rr, bb = 0.0;
+  if (k == 0) {
+    double a[4];
+    const int c[4] = {PART_RES, PART_SPMV, PART_RES + 1, PART_RES + 2};
+    reduce_streams<WG, 4>(P, c, nblk, a);
+    gamma = a[0];
+    delta = a[1];
+    rr = a[2];
+    bb = a[3];
+  } else {
+    double a[3];
+    const int u = PART_PIPE + 3 * ((k - 1) & 1);
+    const int c[3] = {u, u + 1, u + 2};
+    reduce_streams<WG, 3>(P, c, nblk, a);
+    gamma = a[0];
+    delta = a[1];
+    rr = a[2];
+  }
+  const double tol2 = (k == 0) ? I.rtol * I.rtol * bb : S.tol2;
+  int flag = 0;
+  bool done = false;
+  double alpha = 0.0, beta = 0.0;
+  if (!(rr == rr) || !(gamma == gamma)) {
+    done = true;
+    flag = F_NAN;
+  } else if (rr <= tol2) {
+    done = true;
+  } else if (k >= I.max_it) {
+    done = true;
+    flag = F_NOCONV;
+  } else {
+    double denom = delta;
+    if (k > 0) {
+      beta = gamma / gam_prev;
+      denom = delta - beta * gamma / alp_prev;
+    }
+    alpha = gamma / denom;
+    if (!(denom > 0.0) || !(alpha == alpha)) {
+      done = true;
+      flag = (delta == delta) ? F_BREAKDOWN : F_NAN;
+    }
+  }
+  if (lblk == 0 && threadIdx.x == 0) {
+    S.rr = rr;
+    if (k == 0) {
+      S.bb = bb;
+      S.tol2 = tol2;
+    }
+    if (done) {
+      if (flag) S.flags |= flag;
+      S.conv = 1;
+    } else {
+      S.it_step += 1;
+    }
+  }
+  if (done) return;
+  // every thread has read the record (before the reduction's barrier)
+  if (threadIdx.x == 0) {
+    rec[0] = (double)k;
+    rec[1] = gamma;
+    rec[2] = alpha;
+  }
+  const double* m_in = (k & 1) ? I.g : I.b;
+  const gptr<double> m_out = gmem((k & 1) ? I.b : I.g);
+  const bool jacobi = OP == 1 || I.block == 1;
+  double v[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int rw = 0; rw < RPT; rw++) {
+    const int64_t i = i0 + rw * WG;
+    const bool valid = i < I.n;
+    double ni = 0.0, di = dv[rw];
+    if (valid) {
+      if (OP == 1) {
+        ni = dia_row<14, double, double, double>(I, I.valA[sig - 1], m_in, i, 14);
+      } else {
+        ni = I.fmt == FMT_MF ? mf_row(I, I.yA, i) : spmv_row<double, double, double>(I, I.valA[sig - 1], m_in, i);
+        if (jacobi) di = gmem(dinv)[i];
+      }
+    }
+    // u = P^-1 r (every lane takes part in the block-Jacobi shuffles)
+    // Every rounding step is written out (products by __dmul_rn, fused
+    // multiply-adds by fma), so the compiler cannot contract differently in
+    // the specialized and the generic instantiation: both give the same bits.
+    const double ui = jacobi ? __dmul_rn(di, rv[rw]) : precond_apply<double>(dinv, I.bld, I.block, i, valid, rv[rw]);
+    double wn = 0.0, rn = 0.0;
+    if (valid) {
+      const double zn = fma(beta, zv[rw], ni);
+      const double sn = fma(beta, sv[rw], wv[rw]);
+      const double pn = fma(beta, pv[rw], ui);
+      gmem(I.u_new)[i] = fma(alpha, pn, xv[rw]);
+      rn = fma(-alpha, sn, rv[rw]);
+      wn = fma(-alpha, zn, wv[rw]);
+      gmem(I.z)[i] = zn;
+      gmem(I.s)[i] = sn;
+      gmem(I.p)[i] = pn;
+      gmem(I.r)[i] = rn;
+      gmem(I.w)[i] = wn;
+    }
+    const double mn = jacobi ? __dmul_rn(di, wn) : precond_apply<double>(dinv, I.bld, I.block, i, valid, wn);
+    const double un = jacobi ? __dmul_rn(di, rn) : precond_apply<double>(dinv, I.bld, I.block, i, valid, rn);
+    if (valid) {
+      m_out[i] = mn;
+      v[0] = fma(rn, un, v[0]);
+      v[1] = fma(wn, un, v[1]);
+      v[2] = fma(rn, rn, v[2]);
+    }
+  }
+  write_partials<3>(v, I.partial + (int64_t)(PART_PIPE + 3 * (k & 1)) * nblk, nblk, lblk);
+}
+
+// ---------------------------------------------------------------------------
 // activation time; end of step
 // ---------------------------------------------------------------------------
 
@@ -1291,7 +1498,8 @@ static void mf_apply(int which, const Launch& L) {
   if (grid == 0) return;
   if (which == 0) hipLaunchKernelGGL((k_mf_apply<P, 0>), dim3(grid), dim3(64), 0, L.stream, L.insts);
   else if (which == 1) hipLaunchKernelGGL((k_mf_apply<P, 1>), dim3(grid), dim3(64), 0, L.stream, L.insts);
-  else hipLaunchKernelGGL((k_mf_apply<P, 2>), dim3(grid), dim3(64), 0, L.stream, L.insts);
+  else if (which == 2) hipLaunchKernelGGL((k_mf_apply<P, 2>), dim3(grid), dim3(64), 0, L.stream, L.insts);
+  else hipLaunchKernelGGL((k_mf_apply<P, 3>), dim3(grid), dim3(64), 0, L.stream, L.insts);
 }
 
 static void launch_mf_apply(int which, const Launch& L) {
@@ -1313,6 +1521,26 @@ void launch_cg_spmv(bool mixed, const Launch& L) {
   if (L.nblocks <= 0) return;
   if (L.mf_p) launch_mf_apply(0, L);
   mixed ? spmv_dispatch<true>(L) : spmv_dispatch<false>(L);
+}
+
+void launch_cg_pipe_start(const Launch& L) {
+  if (L.nblocks <= 0) return;
+  if (L.mf_p) launch_mf_apply(0, L);   // A u_0
+  const dim3 g(L.nblocks), b(WG);
+  if (!L.single) hipLaunchKernelGGL((k_cg_pipe_start<false, 0>), g, b, 0, L.stream, L.insts, L.bmap);
+  else if (L.xmap == 1) hipLaunchKernelGGL((k_cg_pipe_start<true, 1>), g, b, 0, L.stream, L.insts, L.bmap);
+  else hipLaunchKernelGGL((k_cg_pipe_start<true, 0>), g, b, 0, L.stream, L.insts, L.bmap);
+}
+
+void launch_cg_pipe(const Launch& L) {
+  if (L.nblocks <= 0) return;
+  if (L.mf_p) launch_mf_apply(3, L);   // A m_k
+  const dim3 g(L.nblocks), b(WG);
+  if (!L.single) hipLaunchKernelGGL((k_cg_pipe<false, 0, 0>), g, b, 0, L.stream, L.insts, L.bmap);
+  else if (L.pipe_op == 1 && L.xmap == 1) hipLaunchKernelGGL((k_cg_pipe<true, 1, 1>), g, b, 0, L.stream, L.insts, L.bmap);
+  else if (L.pipe_op == 1) hipLaunchKernelGGL((k_cg_pipe<true, 0, 1>), g, b, 0, L.stream, L.insts, L.bmap);
+  else if (L.xmap == 1) hipLaunchKernelGGL((k_cg_pipe<true, 1, 0>), g, b, 0, L.stream, L.insts, L.bmap);
+  else hipLaunchKernelGGL((k_cg_pipe<true, 0, 0>), g, b, 0, L.stream, L.insts, L.bmap);
 }
 
 void launch_cg_finalize(bool mixed, InstDesc* insts, const int32_t* ids, int n_ids, hipStream_t stream) {

@@ -1,0 +1,168 @@
+"""GPU: the two FP64 CG formulations (pipelined: one kernel per iteration;
+Chronopoulos-Gear: SpMV + update) against each other and the oracle.
+
+Both are preconditioned CG with the same preconditioner and stopping test,
+so they agree to the solver tolerance, not bitwise.  Against the oracle's
+direct solves a trajectory at rtol 1e-10 may drift by at most the solver
+tolerance per step (the time scheme is stable, so per-step errors add at most
+linearly): relative error <= steps x rtol; the two formulations within 1e-10
+of each other; activation times within one step; iteration counts within one
+per step on average.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import monodomain as OM
+
+pytestmark = pytest.mark.gpu
+
+
+def _ep():
+    import paper_2308_01651_amd as ep
+    return ep
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def _slab(h=0.25, model="ttp06", variant="endo", bdf=2, dims=(6.0, 3.0, 1.5)):
+    mesh = W.slab_q1(*dims, h)
+    return W.SimSpec(mesh, W.uniform_fibers(mesh.n_nodes), W.Physics(), model, variant,
+                     [W.corner_cube_stimulus(dims=dims)], 0.05, bdf, 1, 1e-10, "t")
+
+
+@pytest.mark.parametrize("model,variant,bdf,block", [("ttp06", "endo", 2, 1), ("bo", "epi", 3, 1),
+                                                     ("ap", "", 1, 4)])
+def test_pipelined_and_chronopoulos_gear_match_the_oracle(model, variant, bdf, block):
+    ep = _ep()
+    spec = _slab(model=model, variant=variant, bdf=bdf)
+    o = OM.from_spec(spec, solver="splu")
+    pipe = ep.Simulation.from_spec(spec, block=block)
+    cgg = ep.Simulation.from_spec(spec, block=block, cg_variant=ep.EP_CG_CHRONOPOULOS_GEAR)
+    for chunk in range(3):
+        o.run(80)
+        pipe.step(80)
+        cgg.step(80)
+        e_p = _rel(pipe.get_potential(), o.potential_mv())
+        e_c = _rel(cgg.get_potential(), o.potential_mv())
+        print(f"{model} block {block}: {(chunk + 1) * 80} steps, pipelined {e_p:.2e}, CG-CG {e_c:.2e}", flush=True)
+        bound = (chunk + 1) * 80 * spec.rtol
+        assert e_p < bound and e_c < bound, (chunk, e_p, e_c)
+        assert _rel(pipe.get_potential(), cgg.get_potential()) < 1e-10
+    at_o, at_p = o.activation_times(), pipe.get_activation_times()
+    ok = ~np.isnan(at_o)
+    assert ok.sum() > 50 and np.array_equal(ok, ~np.isnan(at_p))
+    assert np.max(np.abs(at_o[ok] - at_p[ok])) <= spec.dt + 1e-9
+    sp, sc = pipe.get_stats(), cgg.get_stats()
+    assert abs(sp["cg_iters_total"] - sc["cg_iters_total"]) <= sp["steps"]
+    pipe.close()
+    cgg.close()
+
+
+@pytest.mark.parametrize("fmt", ["dia", "sell"])
+def test_pipelined_single_step_tight_tolerance(fmt):
+    """One step from a random state at rtol 1e-13 against the oracle's direct
+    solve: 1e-10 relative (the pipelined recurrences reach the tight
+    tolerance)."""
+    ep = _ep()
+    spec = _slab(h=0.25)
+    n = spec.mesh.n_nodes
+    u, w = W.random_state("ttp06", n, seed=81)
+    rng = np.random.default_rng(82)
+    u_prev = (u + rng.normal(size=n))[None, :]
+    o = OM.from_spec(spec, solver="splu", rtol=1e-13)
+    o.set_state(u, w, [u_prev[0]], 7)
+    o.step()
+    f = ep.EP_FMT_DIA if fmt == "dia" else ep.EP_FMT_SELL
+    sim = ep.Simulation.from_spec(spec, rtol=1e-13, matrix_format=f)
+    sim.set_state(u, w, u_prev, 7)
+    sim.step(1)
+    assert _rel(sim.get_state()[0], o.u) < 1e-10
+    sim.close()
+
+
+def test_time_kernel_pipe_leaves_the_run_unchanged():
+    ep = _ep()
+    spec = _slab(h=0.125, dims=(10.0, 3.5, 1.5))
+    ref = ep.Simulation.from_spec(spec)
+    ref.step(40)
+    s = ep.Simulation.from_spec(spec)
+    s.step(20)
+    t = s.time_kernel_us("cg_pipe", 40)
+    assert t > 0
+    s.step(20)
+    assert np.array_equal(s.get_state()[0], ref.get_state()[0])
+    assert np.array_equal(s.get_state()[1], ref.get_state()[1])
+    assert s.get_stats()["cg_iters_total"] == ref.get_stats()["cg_iters_total"]
+    kt = s.get_kernel_times()
+    assert "cg_pipe" in kt
+    s.close()
+    ref.close()
+    c = ep.Simulation.from_spec(spec, cg_variant=ep.EP_CG_CHRONOPOULOS_GEAR)
+    c.step(2)
+    with pytest.raises(ep.EpError):
+        c.time_kernel_us("cg_pipe", 5)
+    c.close()
+
+
+def test_kernel_counts_one_launch_per_iteration():
+    ep = _ep()
+    spec = _slab()
+    s = ep.Simulation.from_spec(spec)
+    s.step(3)
+    s.set_option(ep.EP_OPT_KERNEL_TIMERS, 1)
+    it0 = s.get_stats()["cg_iters_total"]
+    s.step(10)
+    kt = s.get_kernel_times()
+    its = s.get_stats()["cg_iters_total"] - it0
+    assert kt["cg_update"][1] == 0 and kt["cg_finalize"][1] == 0
+    assert kt["cg_spmv"][1] == 10                  # the start kernel, once per step
+    assert kt["cg_pipe"][1] >= its + 10            # K iterations take K + 1 launches
+    s.close()
+
+
+def test_pool_members_share_one_cg_variant():
+    ep = _ep()
+    spec = _slab()
+    pool = ep.Pool(1 << 30, 4, ep.EP_FP64)
+    a = ep.Simulation.from_spec(spec, finalize=False)
+    assert pool.admit(a, 10) is not None
+    b = ep.Simulation.from_spec(spec, finalize=False, cg_variant=ep.EP_CG_CHRONOPOULOS_GEAR)
+    with pytest.raises(ep.EpError):
+        pool.admit(b, 10)
+    b.close()
+    pool.step(10)
+    for slot in list(pool.poll()):
+        pool.release(slot)
+    a.close()
+    # an emptied pool takes either variant
+    c = ep.Simulation.from_spec(spec, finalize=False, cg_variant=ep.EP_CG_CHRONOPOULOS_GEAR)
+    assert pool.admit(c, 5) is not None
+    pool.step(5)
+    for slot in list(pool.poll()):
+        pool.release(slot)
+    c.close()
+    pool.close()
+
+
+def test_auto_variant_by_element_degree():
+    """EP_CG_AUTO: pipelined for linear elements, Chronopoulos-Gear for
+    higher degrees; the pipelined formulation chosen explicitly on
+    triquadratic elements still matches at the workload tolerance."""
+    ep = _ep()
+    mesh = W.slab_q2(4.0, 2.0, 1.0, 0.5)
+    spec = W.SimSpec(mesh, W.smooth_fibers(mesh.xyz, 9), W.Physics(), "ttp06", "endo",
+                     [W.corner_cube_stimulus(dims=(4.0, 2.0, 1.0))], 0.05, 2, 1, 1e-10, "t")
+    auto = ep.Simulation.from_spec(spec)
+    pipe = ep.Simulation.from_spec(spec, cg_variant=ep.EP_CG_PIPELINED)
+    for s in (auto, pipe):
+        s.set_option(ep.EP_OPT_KERNEL_TIMERS, 1)
+        s.step(100)
+    ka, kp = auto.get_kernel_times(), pipe.get_kernel_times()
+    assert ka["cg_pipe"][1] == 0 and ka["cg_update"][1] > 0
+    assert kp["cg_pipe"][1] > 0 and kp["cg_update"][1] == 0
+    assert _rel(pipe.get_potential(), auto.get_potential()) < 100 * spec.rtol
+    auto.close()
+    pipe.close()
