@@ -42,10 +42,19 @@ def _workload(name):
         return W.config_c1(h=0.05, n_steps=200), "ttp06-slab-20x7x3mm-h0.05-3449001nodes-bdf2-dt0.05"
     if name == "c0":
         return W.config_c0(), "ap-slab-20x7x3mm-h0.5-4305nodes-bdf1-dt0.05"
+    if name in ("c1q2", "c1q3"):
+        # the C1 slab with triquadratic elements of 0.2 mm (the same 442,401
+        # nodes) or tricubic elements of 0.3 mm (438,340 nodes)
+        c1 = W.config_c1(h=0.1, n_steps=2000)
+        mesh = W.slab_q2(20.0, 7.0, 3.0, 0.2) if name == "c1q2" else W.slab_q3(20.0, 7.0, 3.0, 0.3)
+        fib = c1.fibers if mesh.n_nodes == c1.mesh.n_nodes else W.uniform_fibers(mesh.n_nodes)
+        spec = W.SimSpec(mesh, fib, c1.phys, c1.model, c1.variant, c1.stimuli, c1.dt, c1.bdf, c1.n_steps,
+                         c1.rtol, name)
+        return spec, f"ttp06-slab-20x7x3mm-{name[2:]}-{mesh.n_nodes}nodes-bdf2-dt0.05"
     raise SystemExit(f"unknown workload {name}")
 
 
-def kernel_bytes(kind, n, nnz, mixed, nvars_model, fmt="DIA", n_diag=0, pipe=False):
+def kernel_bytes(kind, n, nnz, mixed, nvars_model, fmt="DIA", n_diag=0, pipe=False, ent=0):
     """Algorithmic HBM bytes per launch of each kernel: every array the kernel
     must touch, read or written once.  The operator counts as stored: the
     symmetric DIA format keeps n_diag diagonals (offsets >= 0) of n values
@@ -54,7 +63,16 @@ def kernel_bytes(kind, n, nnz, mixed, nvars_model, fmt="DIA", n_diag=0, pipe=Fal
     pipelined CG, whose "cg_spmv" is its start kernel (w_0 = A u_0 and
     m_0 = P^-1 w_0: reads z, dinv, writes w, m_0) and whose iteration kernel
     "cg_pipe" reads m (gathered), dinv, z, w, p, s, x, r and writes z, s, p,
-    x, r, w, m'."""
+    x, r, w, m'.  MF (matrix-free, ent = element-node entries): an operator
+    application reads per entry the gathered x, 7 geometry factors and the
+    node index and writes the element result (76 B), and the node sums read
+    each result with its 4-byte entry index (12 B); the mass-only application
+    of the rhs reads 1 geometry factor (28 B per entry)."""
+    if fmt == "MF":
+        if kind in ("cg_spmv", "cg_pipe"):
+            return 88 * ent + n * (24 if kind == "cg_spmv" else 112)
+        if kind == "rhs":
+            return (28 + 76 + 24) * ent + n * 48
     def mat(vb):
         return n_diag * n * vb if fmt == "DIA" else nnz * (vb + 4)
     if kind == "cg_pipe":
@@ -94,7 +112,7 @@ def _src_hash():
 def _shape_key(kernel_kind, launch):
     """Launch-shape suffix of a counter entry: the tile map of the CG and rhs
     kernels, the nodes per thread of the ionic kernel."""
-    if kernel_kind in ("cg_spmv", "cg_update", "rhs", "ir_residual"):
+    if kernel_kind in ("cg_spmv", "cg_update", "rhs", "ir_residual", "cg_pipe", "cg_spmv_pipe_start"):
         return f"@xmap{launch.get('tile_map', 0)}"
     if kernel_kind == "ionic":
         return f"@npt{launch.get('ionic_npt', 1)}"
@@ -300,14 +318,15 @@ def roofline(res, spec, precision_name, workload_key):
     dom = max((k for k in kinds if k != "cg_finalize"), key=lambda k: ms[k])
     # n_diag counts the operator's diagonals; the symmetric DIA stores the (n_diag + 1) / 2 with offset >= 0
     fmt, nd = res["matrix_format"], (int(res["n_diag"]) + 1) // 2
-    bytes_per = kernel_bytes(dom, n, nnz, mixed, nv, fmt, nd, pipe)
+    ent = int(spec.mesh.conn.size)
+    bytes_per = kernel_bytes(dom, n, nnz, mixed, nv, fmt, nd, pipe, ent)
     raw_s = ms[dom] / 1e3 / work[dom]
     loop = res.get("loop_us", {})
     avg_s = 1e-6 * loop[dom] if dom in loop else raw_s
     achieved = bytes_per / avg_s / 1e9
     per_kernel = {}
     for k in kinds:
-        b = kernel_bytes(k, n, nnz, mixed, nv, fmt, nd, pipe)
+        b = kernel_bytes(k, n, nnz, mixed, nv, fmt, nd, pipe, ent)
         a = ms[k] / 1e3 / work[k]
         per_kernel[k] = {"avg_us_events": 1e6 * a, "launches": cnt[k], "launches_with_work": work[k],
                          "share": ms[k] / sum(ms.values()), "GBps_events": b / a / 1e9 if b else None,
@@ -315,10 +334,12 @@ def roofline(res, spec, precision_name, workload_key):
         if k in loop:
             per_kernel[k]["avg_us_loop"] = loop[k]
             per_kernel[k]["GBps_loop"] = b / (1e-6 * loop[k]) / 1e9
-        t = _traffic(k, precision_name, workload_key, launch)
+        # the pipelined solve's "cg_spmv" launches are its start kernel
+        ck = "cg_spmv_pipe_start" if (pipe and k == "cg_spmv") else k
+        t = _traffic(ck, precision_name, workload_key, launch)
         if t is not None:
             per_kernel[k]["traffic"] = t
-        al = _alu(k, precision_name, workload_key, launch, 1e-6 * per_kernel[k].get("avg_us_loop", 1e6 * a))
+        al = _alu(ck, precision_name, workload_key, launch, 1e-6 * per_kernel[k].get("avg_us_loop", 1e6 * a))
         if al is not None:
             per_kernel[k]["alu"] = al
     tr = _traffic(dom, precision_name, workload_key, launch)
@@ -489,6 +510,10 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=32)
     ap.add_argument("--serve-full", action="store_true",
                     help="the configured trace: 128 requests, 1e4-1e6 nodes, 50-500 ms (long)")
+    ap.add_argument("--matrix-format", default="auto", choices=["auto", "sell", "dia", "mf"],
+                    help="operator storage of the main runs (mf: matrix-free, hexahedra of degree 2 or 3)")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="only the main runs (no launch, solver, scheme or subdomain variants)")
     ap.add_argument("--no-element-variants", action="store_true",
                     help="skip the quadratic-element variants (their SELL SpMV launches share the kernel "
                          "instantiation of the C1 SpMV and would mix into its profile)")
@@ -517,8 +542,9 @@ def main():
     precs = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
     for pn in precs:
         print(f"[bench] {wname} {pn}: warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
+        fmt = {"auto": 0, "sell": ep.EP_FMT_SELL, "dia": ep.EP_FMT_DIA, "mf": ep.EP_FMT_MF}[args.matrix_format]
         res, u, at = run_gpu(spec, ep.EP_FP64 if pn == "fp64" else ep.EP_MIXED, args.steps, args.warmup, instr,
-                             bool(args.graph), bool(args.autotune))
+                             bool(args.graph), bool(args.autotune), matrix_format=fmt)
         if instr > 0:
             rl, pk = roofline(res, spec, pn, args.workload)
             res["roofline"] = rl
@@ -531,7 +557,7 @@ def main():
         fields[pn] = (u, at)
         print(f"[bench] {pn}: {res['node_steps_per_s']:.4g} node-steps/s, {res['ms_per_step']:.3f} ms/step, "
               f"dominant {rl['kernel']} {rl['achieved']} GB/s", file=sys.stderr, flush=True)
-    if "fp64" in out:
+    if "fp64" in out and not args.no_variants:
         # the same run with the default launches (eager, untuned) and with graph replay, for comparison
         import workloads as W
         # three transmural TTP06 layers (endocardial, mid-myocardial,
