@@ -1682,6 +1682,9 @@ ep_status ep_sim_set_state(ep_sim* s, const double* u, const double* w, const do
   EP_HIP(hipGetLastError());
   std::memset(s->h_st, 0, sizeof(InstState));
   s->h_st->step = step_index;
+  // earlier levels not given are copies of u: a constant history, consistent
+  // at every order; given ones are consistent up to the BDF order
+  s->h_st->hist = u_prev ? s->bdf : 3;
   // descriptor with a fresh control state and the history slots of step n
   D.st = *s->h_st;
   D.u_new = D.U[(step_index + 1) & 3];

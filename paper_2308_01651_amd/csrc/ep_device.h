@@ -62,6 +62,8 @@ struct InstState {
   int32_t it_max;      // largest per-step CG count so far
   int64_t it_total;    // CG iterations over all steps
   int64_t outer_total;
+  int32_t hist;        // potential levels u_n, u_{n-1}, ... that form a consistent history (1..3)
+  int32_t pad_hist;
   // step lengths of the current iteration (finalize) and of the previous
   // one (shifted by the update kernel), so that the finalize is idempotent
   double gamma_cur, alpha_cur, beta, gamma_prev, alpha_prev;

@@ -621,7 +621,15 @@ __device__ __forceinline__ void ionic_point(const InstDesc& I, int64_t n, int64_
   if (RHS) {
     const double iapp = stimulus_at(I, step + 1, node);
     gmem(I.g)[node] = u_bdf * I.inv_dt + iapp - iion;
-    gmem(I.u_new)[node] = u_field;
+    // initial guess of the linear solve: the potential extrapolated from
+    // the last three solutions once they form a consistent history (one
+    // order above u_EXT for BDF2; only the iteration count depends on it)
+    double x0 = u_field;
+    if (I.st.hist >= 3) {
+      const double a1 = gmem(I.u_prev1)[node], a2 = gmem(I.u_prev2)[node];
+      x0 = 3.0 * u0 - 3.0 * a1 + a2;
+    }
+    gmem(I.u_new)[node] = x0;
   }
 }
 
@@ -1363,6 +1371,7 @@ __global__ void k_end_step(InstDesc* __restrict__ insts, const int32_t* __restri
   I.u_cur = I.u_new;
   I.u_new = freed;
   S.step += 1;
+  S.hist = S.hist < 3 ? S.hist + 1 : 3;
   S.it_last = S.it_step;
   if (S.it_step > S.it_max) S.it_max = S.it_step;
   S.it_total += S.it_step;
