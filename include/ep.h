@@ -96,11 +96,11 @@ enum {
   EP_OPT_IONIC_FP64 = 10,   /* mixed precision: 1 steps the ionic model (state and
                              * arithmetic) in FP64 while the inner CG stays FP32;
                              * 0 (default) FP32 (before finalize)                  */
-  EP_OPT_CG_VARIANT = 11    /* FP64 solver: EP_CG_* (before finalize); ignored in
-                             * mixed precision, whose inner solve is always
-                             * Chronopoulos-Gear.  Both formulations are PCG with
-                             * the same preconditioner; results agree to the
-                             * solver tolerance, not bitwise.                     */
+  EP_OPT_CG_VARIANT = 11    /* CG formulation, EP_CG_* (before finalize): of the FP64
+                             * solve, or of the FP32 inner solve of each mixed-
+                             * precision refinement sweep.  Both formulations are
+                             * PCG with the same preconditioner; results agree to
+                             * the solver tolerance, not bitwise.                 */
 };
 
 /* FP64 CG formulations (EP_OPT_CG_VARIANT).  EP_CG_PIPELINED: one kernel per
@@ -112,7 +112,7 @@ enum {
  * operator stalled above rtol 1e-13.  EP_CG_CHRONOPOULOS_GEAR: two kernels
  * per iteration (SpMV, then the fused update).  EP_CG_AUTO (default):
  * pipelined for linear elements (EP_HEX8, EP_TET4), Chronopoulos-Gear for
- * higher degrees.  A pool steps its FP64 members with one formulation:
+ * higher degrees.  A pool steps its members with one formulation:
  * ep_pool_admit rejects a sim that resolves to the other. */
 enum { EP_CG_AUTO = 0, EP_CG_PIPELINED = 1, EP_CG_CHRONOPOULOS_GEAR = 2 };
 

@@ -318,6 +318,7 @@ struct ep_sim {
   int64_t sell_nnz = 0;   // stored entries of the SELL operator (slices padded to their widest row)
   int64_t n_cent = 0;     // entries of the interface correction
   SweepPredictor sweeps;  // inner rounds per refinement sweep (mixed)
+  int sweeps_last = 1;    // refinement sweeps the last step needed (mixed)
   int sticky = EP_OK;
   double* tk_save = nullptr;   // saved solver state for timing the pipelined CG kernel
   // the ionic step runs in FP32 (state arrays and arithmetic)
@@ -1026,10 +1027,14 @@ ep_status finalize_impl(ep_sim* s) {
   // single-instance launches cover N_XCD * ceil(tiles / N_XCD) workgroups
   s->nblocks = N_XCD * ((ntiles + N_XCD - 1) / N_XCD);
   EP_HIP(m.alloc((void**)&D.partial, (size_t)ntiles * PART_DOUBLES * sizeof(double)));
-  D.cg_pipe = (s->prec == EP_FP64 && cg_resolved(s) == EP_CG_PIPELINED) ? 1 : 0;
+  D.cg_pipe = cg_resolved(s) == EP_CG_PIPELINED ? 1 : 0;
   if (D.cg_pipe) {
-    EP_HIP(m.alloc((void**)&D.pipe_rec, (size_t)ntiles * 4 * sizeof(double)));
-    EP_HIP(hipMemsetAsync(D.pipe_rec, 0, (size_t)ntiles * 4 * sizeof(double), st));
+    EP_HIP(m.alloc((void**)&D.pipe_rec, (size_t)ntiles * PIPE_REC * sizeof(double)));
+    EP_HIP(hipMemsetAsync(D.pipe_rec, 0, (size_t)ntiles * PIPE_REC * sizeof(double), st));
+    if (mixed) {
+      EP_HIP(vec_f(&D.m32[0]));
+      EP_HIP(vec_f(&D.m32[1]));
+    }
   }
   {
     const int32_t zero = 0;
@@ -1158,7 +1163,9 @@ ep_status validate_desc(const ep_sim* s, const InstDesc& D) {
       return bad("ionic state range");
   if (!in(D.smax, 0, n, 8) || !in(D.at, 0, n, 8) || !in(D.tcross, 0, n, 8)) return bad("activation range");
   if (!in(D.partial, 0, (int64_t)D.nblk * PART_DOUBLES, 8)) return bad("partial sums range");
-  if (D.cg_pipe && (D.prec != P_FP64 || !in(D.pipe_rec, 0, (int64_t)D.nblk * 4, 8))) return bad("pipelined CG records");
+  if (D.cg_pipe && !in(D.pipe_rec, 0, (int64_t)D.nblk * PIPE_REC, 8)) return bad("pipelined CG records");
+  if (D.cg_pipe && D.prec == P_MIXED && (!in(D.m32[0], G, n64 + 2 * G, 4) || !in(D.m32[1], G, n64 + 2 * G, 4)))
+    return bad("pipelined FP32 vector range");
   for (int k = 0; k < D.n_stim; k++)
     if (!in(D.stim[k].prof, 0, n, 8)) return bad("stimulus profile range");
   if (D.het) {
@@ -1202,10 +1209,10 @@ ep_status step_once(ep_sim* s) {
   auto fin = [&] { kt.timed(st, 6, [&] { launch_cg_finalize(mixed, s->d_desc, nullptr, 1, st); }); };
   // FP64: a round is SpMV then the update (which adds the partial sums
   // itself); mixed: update, SpMV, finalize
-  const bool pipe = !mixed && s->desc.cg_pipe;
+  const bool pipe = s->desc.cg_pipe;
   auto round = [&] {
     if (pipe) {
-      kt.timed(st, 7, [&] { launch_cg_pipe(L); });
+      kt.timed(st, 7, [&] { mixed ? launch_cg_pipe32(L) : launch_cg_pipe(L); });
       return;
     }
     if (!mixed) {
@@ -1230,14 +1237,22 @@ ep_status step_once(ep_sim* s) {
     if (s->timers) (void)hipEventRecord(s->ev[1], st);
     kt.timed(st, 1, [&] { launch_residual(mixed, true, L); });
     if (s->timers) (void)hipEventRecord(s->ev[2], st);
-    if (pipe) kt.timed(st, 2, [&] { launch_cg_pipe_start(L); });
-    if (mixed) {
+    if (pipe) {
+      kt.timed(st, 2, [&] { mixed ? launch_cg_pipe32_start(L) : launch_cg_pipe_start(L); });
+    } else if (mixed) {
       kt.timed(st, 2, [&] { launch_cg_spmv(mixed, L); });
       fin();
     }
   };
   auto ir = [&] {
     kt.timed(st, 5, [&] { launch_residual(true, false, L); });
+    if (pipe) {
+      // the start and the sweep's first iteration, which takes the outer
+      // decision, so the host's next read sees it
+      kt.timed(st, 2, [&] { launch_cg_pipe32_start(L); });
+      kt.timed(st, 7, [&] { launch_cg_pipe32(L); });
+      return;
+    }
     kt.timed(st, 2, [&] { launch_cg_spmv(true, L); });
     fin();
   };
@@ -1284,18 +1299,36 @@ ep_status step_once(ep_sim* s) {
     s->it_pred = std::max(1, s->h_st->it_step);
   } else {
     // sweep = refinement residuals evaluated so far in this step; a sweep
-    // that has not converged after its predicted rounds continues by 2
-    int sweep = 0, sweep_start = 0;
+    // that has not converged after its predicted rounds continues by 2.
+    // Pipelined inner solve: the sweeps the last step needed are enqueued
+    // before the first read (a sweep's launches do nothing once the step
+    // has converged, and a refinement residual does nothing before its
+    // sweep's inner solve is done), and each sweep's inner iteration count
+    // comes from the device state.
+    int sweep = 0, sweep_start = 0, learned = 0;
     bool fresh = true;
+    const int ahead = pipe ? std::max(1, std::min(s->sweeps_last, 3)) : 1;
     for (int reads = 0;; reads++) {
-      EP_HIP(rounds(fresh ? s->sweeps.rounds(sweep) : 2));
-      if (graph) EP_HIP(hipGraphLaunch(G.ir, st));
-      else ir();
+      const int nsw = reads == 0 ? ahead : 1;
+      for (int j = 0; j < nsw; j++) {
+        EP_HIP(rounds(fresh ? s->sweeps.rounds(sweep + j) : 2));
+        if (graph) EP_HIP(hipGraphLaunch(G.ir, st));
+        else ir();
+      }
       ep_status rc = pull_state(s);
       if (rc != EP_OK) return rc;
       const int outer = s->h_st->outer, it_now = s->h_st->it_step;
       fresh = outer > sweep;
-      if (fresh) {
+      if (pipe) {
+        // sweep j's inner solve stopped at iteration sw_its[j]; its rounds
+        // were that many plus the first (sweep 0) or without it (the first
+        // iteration of later sweeps runs with their refinement residual)
+        for (; learned < outer; learned++) {
+          const int k_stop = s->h_st->sw_its[std::min(learned, 2)];
+          s->sweeps.learn(learned, learned == 0 ? k_stop : k_stop - 1);
+        }
+        sweep = outer;
+      } else if (fresh) {
         s->sweeps.learn(sweep, it_now - sweep_start);
         sweep = outer;
         sweep_start = it_now;
@@ -1303,6 +1336,7 @@ ep_status step_once(ep_sim* s) {
       if (s->h_st->conv) break;
       if (reads > s->max_it + s->max_outer + 2) return fail(EP_EHIP, "solver control lost (no convergence flag)");
     }
+    s->sweeps_last = s->h_st->outer;
   }
   if (graph) EP_HIP(hipGraphLaunch(G.epi, st));
   else epi();
@@ -1874,12 +1908,12 @@ ep_status ep_sim_timer_overhead(ep_sim* s, int reps, double* us_per_pair) {
 // converged: past that test the recurrences continue as in a longer solve.
 ep_status time_pipe(ep_sim* s, int reps, double* us_per_launch) {
   const InstDesc& D = s->desc;
-  if (!D.cg_pipe) return fail(EP_EINVAL, "the sim does not use the pipelined CG");
+  if (!D.cg_pipe || D.prec != P_FP64) return fail(EP_EINVAL, "the sim does not use the FP64 pipelined CG");
   hipStream_t st = s->stream;
   const int64_t G = s->guard, nv = ((s->n + 63) / 64) * 64 + 2 * G;
   const int64_t step = s->h_st->step;
   double* vec[8] = {D.z, D.w, D.p, D.s, D.U[(step + 1) & 3], D.r, D.g, D.b};
-  const int64_t npart = (int64_t)D.nblk * PART_DOUBLES, nrec = (int64_t)D.nblk * 4;
+  const int64_t npart = (int64_t)D.nblk * PART_DOUBLES, nrec = (int64_t)D.nblk * PIPE_REC;
   const int64_t total = 8 * nv + npart + nrec;
   if (!s->tk_save) EP_HIP(s->mem.alloc((void**)&s->tk_save, (size_t)total * sizeof(double)));
   double* sv = s->tk_save;
@@ -2257,7 +2291,7 @@ int pool_iters(ep_pool* P) {
 
 ep_status pool_step_once(ep_pool* P) {
   const bool mixed = P->prec == EP_MIXED;
-  const bool pipe = !mixed && P->cg_variant == EP_CG_PIPELINED;
+  const bool pipe = P->cg_variant == EP_CG_PIPELINED;
   const int ni = (int)P->active.size();
   Launch L{P->d_table, P->d_all, P->nb_all, P->stream, false};
   L.ionic_npt = P->ionic_npt;
@@ -2266,7 +2300,7 @@ ep_status pool_step_once(ep_pool* P) {
   auto fin = [&] { kt.timed(st, 6, [&] { launch_cg_finalize(mixed, P->d_table, P->d_ids, ni, st); }); };
   auto round = [&] {
     if (pipe) {
-      kt.timed(st, 7, [&] { launch_cg_pipe(L); });
+      kt.timed(st, 7, [&] { mixed ? launch_cg_pipe32(L) : launch_cg_pipe(L); });
       return;
     }
     if (!mixed) {
@@ -2294,14 +2328,22 @@ ep_status pool_step_once(ep_pool* P) {
       }
     });
     kt.timed(st, 1, [&] { launch_residual(mixed, true, L); });
-    if (pipe) kt.timed(st, 2, [&] { launch_cg_pipe_start(L); });
-    if (mixed) {
+    if (pipe) {
+      kt.timed(st, 2, [&] { mixed ? launch_cg_pipe32_start(L) : launch_cg_pipe_start(L); });
+    } else if (mixed) {
       kt.timed(st, 2, [&] { launch_cg_spmv(mixed, L); });
       fin();
     }
   };
   auto ir = [&] {
     kt.timed(st, 5, [&] { launch_residual(true, false, L); });
+    if (pipe) {
+      // the start and the sweep's first iteration, which takes the outer
+      // decision, so the host's next read sees it
+      kt.timed(st, 2, [&] { launch_cg_pipe32_start(L); });
+      kt.timed(st, 7, [&] { launch_cg_pipe32(L); });
+      return;
+    }
     kt.timed(st, 2, [&] { launch_cg_spmv(true, L); });
     fin();
   };
@@ -2441,7 +2483,7 @@ ep_status ep_pool_admit(ep_pool* P, ep_sim* s, int64_t n_steps_total, int* slot)
   bool empty = true;
   for (int k = 0; k < P->max_slots; k++)
     if (P->slots[k].sim) empty = false;
-  if (P->prec == EP_FP64 && !empty && cg_resolved(s) != P->cg_variant)
+  if (!empty && cg_resolved(s) != P->cg_variant)
     return fail(EP_EINVAL, "sim CG variant differs from the pool members'");
   int free_slot = -1;
   for (int k = 0; k < P->max_slots; k++)

@@ -63,7 +63,7 @@ struct InstState {
   int64_t it_total;    // CG iterations over all steps
   int64_t outer_total;
   int32_t hist;        // potential levels u_n, u_{n-1}, ... that form a consistent history (1..3)
-  int32_t pad_hist;
+  int32_t sw_its[3];   // pipelined mixed: inner iteration at which sweep 0, 1, 2+ of this step stopped
   // step lengths of the current iteration (finalize) and of the previous
   // one (shifted by the update kernel), so that the finalize is idempotent
   double gamma_cur, alpha_cur, beta, gamma_prev, alpha_prev;
@@ -158,15 +158,20 @@ struct InstDesc {
   const int64_t* adj_ptr;  // [n + 1] element entries of each node
   const int32_t* adj;      // entry e * npe + k, ascending
   double mfV[16], mfD[16]; // 1-D basis factor j and derivative at Gauss point q: [q * (p + 1) + j]
-  // FP64 pipelined CG (cg_pipe != 0): one kernel per iteration.  Its
-  // iteration index and the previous step lengths live in one record per
-  // tile, pipe_rec[4 * lblk + {0: k, 1: gamma_k, 2: alpha_k}], read and
-  // written only by the workgroup of that tile, so no workgroup of a launch
-  // can see another's update of the same launch.  m = P^-1 w alternates
-  // between b (even k) and g (odd k), both free during the FP64 solve.
+  // Pipelined CG (cg_pipe != 0; the FP64 solve, or the FP32 inner solve of
+  // mixed precision): one kernel per iteration.  Its iteration index, the
+  // previous step lengths and the inner-solve state live in one record per
+  // tile, pipe_rec[PIPE_REC * lblk + {0: k, 1: gamma_k, 2: alpha_k, 3: this
+  // sweep's inner solve done, 4: the sweep's initial inner residual}], read
+  // and written only by the workgroup of that tile, so no workgroup of a
+  // launch can see another's update of the same launch.  m = P^-1 w
+  // alternates: FP64 between b (even k) and g (odd k), both free during the
+  // FP64 solve; FP32 between m32[0] and m32[1].
   int32_t cg_pipe;
-  double* pipe_rec;        // [nblk][4]
+  double* pipe_rec;        // [nblk][PIPE_REC]
+  float* m32[2];
 };
+constexpr int PIPE_REC = 8;
 
 // Partial-sum layout inside InstDesc::partial, in units of nblk doubles:
 // residual kernel [4][nblk], SpMV [1][nblk], update [2][nblk]; the FP64

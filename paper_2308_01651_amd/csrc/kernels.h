@@ -43,6 +43,10 @@ void launch_cg_update64(const Launch& L);
 // residual, then one launch per iteration (instances without cg_pipe skip)
 void launch_cg_pipe_start(const Launch& L);
 void launch_cg_pipe(const Launch& L);
+// mixed precision: the pipelined FP32 inner solve (start after each
+// residual, then one launch per inner iteration)
+void launch_cg_pipe32_start(const Launch& L);
+void launch_cg_pipe32(const Launch& L);
 // one workgroup per instance listed in ids (device array of n_ids indices);
 // ids == nullptr with n_ids == 1: the single instance at insts[0]
 void launch_cg_finalize(bool mixed, InstDesc* insts, const int32_t* ids, int n_ids, hipStream_t stream);

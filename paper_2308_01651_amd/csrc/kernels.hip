@@ -728,9 +728,16 @@ __global__ __launch_bounds__(WG) void k_residual(InstDesc* __restrict__ insts, c
   if (lblk < 0) return;
   InstState& S = I.st;
   // a refinement sweep only restarts an instance whose inner solve is done
+  const gptr<double> rec = gmem(I.pipe_rec) + PIPE_REC * (int64_t)lblk;
   if (!WITH_RHS) {
-    const Ctl c = ld_ctl(S);
-    if (c.conv != 0 || c.conv_in == 0) return;
+    // a refinement residual runs once the sweep's inner solve is done (the
+    // pipelined inner solve records that per tile)
+    if (MIXED && I.cg_pipe) {
+      if (S.conv != 0 || rec[3] == 0.0) return;
+    } else {
+      const Ctl c = ld_ctl(S);
+      if (c.conv != 0 || c.conv_in == 0) return;
+    }
   }
   const int sig = min(I.bdf, (int)S.step + 1);
   const double* __restrict__ x = I.u_new;
@@ -776,12 +783,13 @@ __global__ __launch_bounds__(WG) void k_residual(InstDesc* __restrict__ insts, c
     if (WITH_RHS) v[2] += bi * bi;
   }
   write_partials<4>(v, I.partial + (int64_t)PART_RES * I.nblk, I.nblk, lblk);
-  if (!MIXED && WITH_RHS && I.cg_pipe && threadIdx.x == 0) {
-    // pipelined CG: this tile's record restarts at iteration -1
-    const gptr<double> rec = gmem(I.pipe_rec) + 4 * (int64_t)lblk;
+  if ((MIXED || WITH_RHS) && I.cg_pipe && threadIdx.x == 0) {
+    // pipelined CG: this tile's record restarts at iteration -1 of a
+    // (inner) solve that is not done
     rec[0] = -1.0;
     rec[1] = 1.0;
     rec[2] = 1.0;
+    rec[3] = 0.0;
   }
   if (lblk == 0 && threadIdx.x == 0) {
     // a new (inner) solve starts at iteration 0; fields read by no workgroup
@@ -1201,7 +1209,7 @@ __global__ __launch_bounds__(WG) void k_cg_pipe(InstDesc* __restrict__ insts, co
   if (!I.cg_pipe || S.conv != 0) return;
   const int nblk = I.nblk;
   const int sig = min(I.bdf, (int)S.step + 1);
-  const gptr<double> rec = gmem(I.pipe_rec) + 4 * (int64_t)lblk;
+  const gptr<double> rec = gmem(I.pipe_rec) + PIPE_REC * (int64_t)lblk;
   const int k = (int)rec[0] + 1;
   const double gam_prev = rec[1], alp_prev = rec[2];
   const int64_t i0 = (int64_t)lblk * TILE + threadIdx.x;
@@ -1329,6 +1337,226 @@ __global__ __launch_bounds__(WG) void k_cg_pipe(InstDesc* __restrict__ insts, co
       v[0] = fma(rn, un, v[0]);
       v[1] = fma(wn, un, v[1]);
       v[2] = fma(rn, rn, v[2]);
+    }
+  }
+  write_partials<3>(v, I.partial + (int64_t)(PART_PIPE + 3 * (k & 1)) * nblk, nblk, lblk);
+}
+
+// ---------------------------------------------------------------------------
+// Mixed precision: the FP32 inner solve of each refinement sweep in the
+// pipelined form (the same recurrences as k_cg_pipe in FP32 with FP64
+// partial sums; the solution accumulates in FP64).  The start kernel runs
+// right after a residual (the tile's record at iteration -1): w = A z,
+// m = P^-1 w, delta.  The iteration kernel takes, at k = 0, the outer
+// decisions of the sweep (FP64 residual against the tolerance, sweep limit)
+// and afterwards stops the inner solve at inner_rtol relative to the
+// sweep's first inner residual, recording that in the tile's record, which
+// the next refinement residual reads.
+// ---------------------------------------------------------------------------
+
+// Relative inner residual below which an FP32 solve stops gaining accuracy
+// on the FP64 residual (the FP32 operator differs from the FP64 one by about
+// 6e-8 relative).
+constexpr double INNER_FLOOR = 1e-5;
+
+template <bool SINGLE, int XMAP>
+__global__ __launch_bounds__(WG) void k_cg_pipe32_start(InstDesc* __restrict__ insts,
+                                                        const BlockMap* __restrict__ bmap) {
+  int lblk;
+  InstDesc& I = instance<SINGLE, XMAP>(insts, bmap, lblk);
+  if (lblk < 0) return;
+  const InstState& S = I.st;
+  if (!I.cg_pipe || S.conv != 0) return;
+  if (gmem(I.pipe_rec)[PIPE_REC * (int64_t)lblk] != -1.0) return;   // not right after a residual
+  const int sig = min(I.bdf, (int)S.step + 1);
+  const int64_t i0 = (int64_t)lblk * TILE + threadIdx.x;
+  double v[1] = {0.0};
+#pragma unroll
+  for (int rw = 0; rw < RPT; rw++) {
+    const int64_t i = i0 + rw * WG;
+    const bool valid = i < I.n;
+    float wi = 0.0f;
+    if (valid) {
+      wi = spmv_row<float, float, float>(I, I.valA32[sig - 1], I.z32, i);
+      gmem(I.w32)[i] = wi;
+      v[0] += (double)wi * (double)gmem(I.z32)[i];
+    }
+    const float mi = precond_apply<float>(I.dinv32[sig - 1], I.bld, I.block, i, valid, wi);
+    if (valid) gmem(I.m32[0])[i] = mi;
+  }
+  write_partials<1>(v, I.partial + (int64_t)PART_SPMV * I.nblk, I.nblk, lblk);
+}
+
+template <bool SINGLE, int XMAP>
+__global__ __launch_bounds__(WG) void k_cg_pipe32(InstDesc* __restrict__ insts, const BlockMap* __restrict__ bmap) {
+  int lblk;
+  InstDesc& I = instance<SINGLE, XMAP>(insts, bmap, lblk);
+  if (lblk < 0) return;
+  InstState& S = I.st;
+  if (!I.cg_pipe || S.conv != 0) return;
+  const gptr<double> rec = gmem(I.pipe_rec) + PIPE_REC * (int64_t)lblk;
+  if (rec[3] != 0.0) return;   // this sweep's inner solve is done
+  const int nblk = I.nblk;
+  const int sig = min(I.bdf, (int)S.step + 1);
+  const int k = (int)rec[0] + 1;
+  const double gam_prev = rec[1], alp_prev = rec[2], rr_in0_rec = rec[4], f2_rec = rec[5];
+  const int64_t i0 = (int64_t)lblk * TILE + threadIdx.x;
+  float zv[RPT], wv[RPT], pv[RPT], sv[RPT], rv[RPT];
+  double xv[RPT];
+#pragma unroll
+  for (int rw = 0; rw < RPT; rw++) {
+    const int64_t i = i0 + rw * WG;
+    zv[rw] = wv[rw] = pv[rw] = sv[rw] = rv[rw] = 0.0f;
+    xv[rw] = 0.0;
+    if (i < I.n) {
+      zv[rw] = gmem(I.z32)[i];
+      wv[rw] = gmem(I.w32)[i];
+      pv[rw] = gmem(I.p32)[i];
+      sv[rw] = gmem(I.s32)[i];
+      rv[rw] = gmem(I.r32)[i];
+      xv[rw] = gmem(I.u_new)[i];
+    }
+  }
+  const double* __restrict__ P = I.partial;
+  double gamma, delta, rr, rr_outer = 0.0, bb = 0.0;
+  if (k == 0) {
+    double a[5];
+    const int c[5] = {PART_RES, PART_SPMV, PART_RES + 3, PART_RES + 1, PART_RES + 2};
+    reduce_streams<WG, 5>(P, c, nblk, a);
+    gamma = a[0];
+    delta = a[1];
+    rr = a[2];
+    rr_outer = a[3];
+    bb = a[4];
+  } else {
+    double a[3];
+    const int u = PART_PIPE + 3 * ((k - 1) & 1);
+    const int c[3] = {u, u + 1, u + 2};
+    reduce_streams<WG, 3>(P, c, nblk, a);
+    gamma = a[0];
+    delta = a[1];
+    rr = a[2];
+  }
+  const bool first = k == 0 && S.outer == 0;
+  const double tol2 = first ? I.rtol * I.rtol * bb : S.tol2;
+  const double rr_in0 = k == 0 ? rr : rr_in0_rec;
+  // the sweep's inner target (squared reduction of the inner residual):
+  // inner_rtol, or tighter when that finishes the step in this sweep: the
+  // reduction that brings the FP64 residual to half the tolerance, if an
+  // FP32 solve can reach it (not below INNER_FLOOR; otherwise another sweep
+  // follows anyway and inner_rtol is the cheaper target)
+  double f2 = f2_rec;
+  if (k == 0) {
+    const double want = 0.25 * tol2 / rr_outer, hi = I.inner_rtol * I.inner_rtol;
+    f2 = (want >= INNER_FLOOR * INNER_FLOOR && want < hi) ? want : hi;
+  }
+  int flag = 0;
+  bool done = false, stop_in = false;
+  if (k == 0) {
+    if (!(rr_outer == rr_outer) || !(gamma == gamma)) {
+      done = true;
+      flag = F_NAN;
+    } else if (rr_outer <= tol2) {
+      done = true;
+    } else if (S.outer > I.max_outer) {
+      done = true;
+      flag = F_NOCONV;
+    }
+  } else if (!(rr == rr)) {
+    done = true;
+    flag = F_NAN;
+  } else {
+    stop_in = rr <= f2 * rr_in0 || k >= I.max_it;
+  }
+  double alpha = 0.0, beta = 0.0;
+  if (!done && !stop_in) {
+    double denom = delta;
+    if (k > 0) {
+      beta = gamma / gam_prev;
+      denom = delta - beta * gamma / alp_prev;
+    }
+    alpha = gamma / denom;
+    if (!(denom > 0.0) || !(alpha == alpha)) {
+      if (delta == delta) {
+        flag |= F_BREAKDOWN;
+        stop_in = true;
+      } else {
+        flag |= F_NAN;
+        done = true;
+      }
+    }
+  }
+  if (lblk == 0 && threadIdx.x == 0) {
+    S.rr = rr;
+    if (k == 0) {
+      S.rr_outer = rr_outer;
+      S.rr_in0 = rr;
+    }
+    if (first) {
+      S.bb = bb;
+      S.tol2 = tol2;
+    }
+    if (flag) S.flags |= flag;
+    if (done) {
+      S.conv = 1;
+    } else if (stop_in) {
+      S.conv_in = 1;
+      S.sw_its[S.outer < 2 ? S.outer : 2] = k;
+    } else {
+      S.it_step += 1;
+    }
+  }
+  // every thread has read the record (before the reduction's barrier)
+  if (threadIdx.x == 0) {
+    if (k == 0) {
+      rec[4] = rr;
+      rec[5] = f2;
+    }
+    if (stop_in && !done) rec[3] = 1.0;
+  }
+  if (done || stop_in) return;
+  if (threadIdx.x == 0) {
+    rec[0] = (double)k;
+    rec[1] = gamma;
+    rec[2] = alpha;
+  }
+  const float* m_in = I.m32[k & 1];
+  const gptr<float> m_out = gmem(I.m32[(k + 1) & 1]);
+  const float* dinv = I.dinv32[sig - 1];
+  const bool jacobi = I.block == 1;
+  const float fa = (float)alpha, fb = (float)beta;
+  double v[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int rw = 0; rw < RPT; rw++) {
+    const int64_t i = i0 + rw * WG;
+    const bool valid = i < I.n;
+    float ni = 0.0f, di = 0.0f;
+    if (valid) {
+      ni = spmv_row<float, float, float>(I, I.valA32[sig - 1], m_in, i);
+      if (jacobi) di = gmem(dinv)[i];
+    }
+    const float ui = jacobi ? __fmul_rn(di, rv[rw]) : precond_apply<float>(dinv, I.bld, I.block, i, valid, rv[rw]);
+    float wn = 0.0f, rn = 0.0f;
+    if (valid) {
+      const float zn = fmaf(fb, zv[rw], ni);
+      const float sn = fmaf(fb, sv[rw], wv[rw]);
+      const float pn = fmaf(fb, pv[rw], ui);
+      gmem(I.u_new)[i] = fma(alpha, (double)pn, xv[rw]);
+      rn = fmaf(-fa, sn, rv[rw]);
+      wn = fmaf(-fa, zn, wv[rw]);
+      gmem(I.z32)[i] = zn;
+      gmem(I.s32)[i] = sn;
+      gmem(I.p32)[i] = pn;
+      gmem(I.r32)[i] = rn;
+      gmem(I.w32)[i] = wn;
+    }
+    const float mn = jacobi ? __fmul_rn(di, wn) : precond_apply<float>(dinv, I.bld, I.block, i, valid, wn);
+    const float un = jacobi ? __fmul_rn(di, rn) : precond_apply<float>(dinv, I.bld, I.block, i, valid, rn);
+    if (valid) {
+      m_out[i] = mn;
+      v[0] = fma((double)rn, (double)un, v[0]);
+      v[1] = fma((double)wn, (double)un, v[1]);
+      v[2] = fma((double)rn, (double)rn, v[2]);
     }
   }
   write_partials<3>(v, I.partial + (int64_t)(PART_PIPE + 3 * (k & 1)) * nblk, nblk, lblk);
@@ -1530,6 +1758,22 @@ void launch_cg_spmv(bool mixed, const Launch& L) {
   if (L.nblocks <= 0) return;
   if (L.mf_p) launch_mf_apply(0, L);
   mixed ? spmv_dispatch<true>(L) : spmv_dispatch<false>(L);
+}
+
+void launch_cg_pipe32_start(const Launch& L) {
+  if (L.nblocks <= 0) return;
+  const dim3 g(L.nblocks), b(WG);
+  if (!L.single) hipLaunchKernelGGL((k_cg_pipe32_start<false, 0>), g, b, 0, L.stream, L.insts, L.bmap);
+  else if (L.xmap == 1) hipLaunchKernelGGL((k_cg_pipe32_start<true, 1>), g, b, 0, L.stream, L.insts, L.bmap);
+  else hipLaunchKernelGGL((k_cg_pipe32_start<true, 0>), g, b, 0, L.stream, L.insts, L.bmap);
+}
+
+void launch_cg_pipe32(const Launch& L) {
+  if (L.nblocks <= 0) return;
+  const dim3 g(L.nblocks), b(WG);
+  if (!L.single) hipLaunchKernelGGL((k_cg_pipe32<false, 0>), g, b, 0, L.stream, L.insts, L.bmap);
+  else if (L.xmap == 1) hipLaunchKernelGGL((k_cg_pipe32<true, 1>), g, b, 0, L.stream, L.insts, L.bmap);
+  else hipLaunchKernelGGL((k_cg_pipe32<true, 0>), g, b, 0, L.stream, L.insts, L.bmap);
 }
 
 void launch_cg_pipe_start(const Launch& L) {

@@ -166,3 +166,34 @@ def test_auto_variant_by_element_degree():
     assert _rel(pipe.get_potential(), auto.get_potential()) < 100 * spec.rtol
     auto.close()
     pipe.close()
+
+
+@pytest.mark.parametrize("model,variant,bdf", [("ttp06", "endo", 2), ("bo", "epi", 2)])
+def test_mixed_pipelined_inner_solve(model, variant, bdf):
+    """Mixed precision with the pipelined FP32 inner solve (the default for
+    linear elements) against the Chronopoulos-Gear inner solve and against
+    FP64: the bar of the mixed form, RMS <= 1e-3 mV and activation times
+    within 0.1 ms; one kernel per inner iteration (no finalize, no update)."""
+    ep = _ep()
+    spec = _slab(model=model, variant=variant, bdf=bdf)
+    ref = ep.Simulation.from_spec(spec, rtol=1e-12)
+    pipe = ep.Simulation.from_spec(spec, precision=ep.EP_MIXED)
+    cgg = ep.Simulation.from_spec(spec, precision=ep.EP_MIXED, cg_variant=ep.EP_CG_CHRONOPOULOS_GEAR)
+    pipe.set_option(ep.EP_OPT_KERNEL_TIMERS, 1)
+    for s in (ref, pipe, cgg):
+        s.step(240)
+    mv = 100.0 if model == "ap" else 1.0
+    at_r = ref.get_activation_times()
+    ok = ~np.isnan(at_r)
+    assert ok.sum() > 50
+    for s in (pipe, cgg):
+        du = (s.get_potential() - ref.get_potential()) * mv
+        assert np.sqrt(np.mean(du * du)) <= 1e-3, np.sqrt(np.mean(du * du))
+        at = s.get_activation_times()
+        assert np.array_equal(ok, ~np.isnan(at)) and np.max(np.abs(at[ok] - at_r[ok])) <= 0.1
+    kt = pipe.get_kernel_times()
+    assert kt["cg_finalize"][1] == 0 and kt["cg_update"][1] == 0 and kt["cg_pipe"][1] > 0
+    st = pipe.get_stats()
+    assert st["ir_sweeps_total"] >= st["steps"]
+    for s in (ref, pipe, cgg):
+        s.close()
