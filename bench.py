@@ -76,9 +76,10 @@ def kernel_bytes(kind, n, nnz, mixed, nvars_model, fmt="DIA", n_diag=0, pipe=Fal
     def mat(vb):
         return n_diag * n * vb if fmt == "DIA" else nnz * (vb + 4)
     if kind == "cg_pipe":
-        return mat(8) + n * 120
-    if kind == "cg_spmv" and pipe and not mixed:
-        return mat(8) + n * 32
+        # FP32 inner form: FP32 operator and vectors, the solution in FP64
+        return mat(4) + n * 68 if mixed else mat(8) + n * 120
+    if kind == "cg_spmv" and pipe:
+        return mat(4) + n * 16 if mixed else mat(8) + n * 32
     if kind == "cg_spmv":
         return mat(4 if mixed else 8) + n * (8 if mixed else 16)
     if kind == "cg_update":
