@@ -111,9 +111,12 @@ enum {
  * attainable residual on ill-conditioned systems: a degree-5 hexahedral
  * operator stalled above rtol 1e-13.  EP_CG_CHRONOPOULOS_GEAR: two kernels
  * per iteration (SpMV, then the fused update).  EP_CG_AUTO (default):
- * pipelined for linear elements (EP_HEX8, EP_TET4), Chronopoulos-Gear for
- * higher degrees.  A pool steps its members with one formulation:
- * ep_pool_admit rejects a sim that resolves to the other. */
+ * pipelined for linear elements (EP_HEX8, EP_TET4) when the iteration's data
+ * (about 232 B per node in FP64, 124 B per node in the FP32 inner solve)
+ * fits in 192 MB, three quarters of the GPU's 256 MB last-level cache;
+ * Chronopoulos-Gear for larger meshes and higher degrees.  A pool may hold
+ * members of both formulations: it launches the kernels of each one
+ * present, and each kernel skips the other's members. */
 enum { EP_CG_AUTO = 0, EP_CG_PIPELINED = 1, EP_CG_CHRONOPOULOS_GEAR = 2 };
 
 /* Ionic integrators (EP_OPT_IONIC_SCHEME).  EP_IONIC_RUSH_LARSEN (default):

@@ -335,12 +335,20 @@ ep_status check_sim(ep_sim* s) {
 }
 
 // Read the device state into pinned host memory (synchronizes the stream).
-// The FP64 CG formulation a sim runs: EP_CG_AUTO takes the pipelined one
-// for linear elements (small condition numbers; its recurrences reach every
-// tolerance tested there) and Chronopoulos-Gear for higher degrees.
+// The CG formulation a sim runs: EP_CG_AUTO takes the pipelined one for
+// linear elements (small condition numbers; its recurrences reach every
+// tolerance tested there) whose iteration's data (operator and vectors, about
+// 232 B per node in FP64, 124 B in the FP32 inner solve) fits in three
+// quarters of the 256 MB last-level cache, and Chronopoulos-Gear otherwise:
+// once the data streams from HBM, the fused iteration is no faster in FP64
+// (C1 at h = 0.05 mm, 3.45M nodes: 6.64 against 6.68 ms per step) and much
+// slower in FP32 (5.62 against 3.81 ms: the separate SpMV keeps its FP32
+// operator in the cache).
 int cg_resolved(const ep_sim* s) {
   if (s->cg_variant != EP_CG_AUTO) return s->cg_variant;
-  return (s->elem == EP_HEX8 || s->elem == EP_TET4) ? EP_CG_PIPELINED : EP_CG_CHRONOPOULOS_GEAR;
+  if (s->elem != EP_HEX8 && s->elem != EP_TET4) return EP_CG_CHRONOPOULOS_GEAR;
+  const double bytes = (double)s->n * (s->prec == EP_MIXED ? 124.0 : 232.0);
+  return bytes <= 0.75 * 256e6 ? EP_CG_PIPELINED : EP_CG_CHRONOPOULOS_GEAR;
 }
 
 ep_status pull_state(ep_sim* s) {
@@ -2209,7 +2217,9 @@ struct ep_pool {
   KernelTimers kt;
   int ionic_npt = 1, list_order = 0, use_graph = 0;  // launch shapes (EP_OPT_*)
   StepGraphs graphs;
-  int cg_variant = -1;  // FP64: the CG formulation of the members (-1: no member yet)
+  // CG formulations among the active members: the pool launches the kernels
+  // of each one present (the kernels of one form skip the other's members)
+  bool has_pipe = false, has_cgg = false;
 };
 
 namespace {
@@ -2235,6 +2245,8 @@ ep_status pool_rebuild(ep_pool* P) {
   P->active.clear();
   for (int k = 0; k < P->max_slots; k++)
     if (P->slots[k].sim && !P->slots[k].done) P->active.push_back(k);
+  P->has_pipe = P->has_cgg = false;
+  for (int k : P->active) (P->slots[k].sim->desc.cg_pipe ? P->has_pipe : P->has_cgg) = true;
   std::vector<BlockMap> all, per_model[16];
   P->het_slots.clear();
   for (int k : P->active) {
@@ -2291,7 +2303,7 @@ int pool_iters(ep_pool* P) {
 
 ep_status pool_step_once(ep_pool* P) {
   const bool mixed = P->prec == EP_MIXED;
-  const bool pipe = P->cg_variant == EP_CG_PIPELINED;
+  const bool pipe = P->has_pipe, cgg = P->has_cgg;
   const int ni = (int)P->active.size();
   Launch L{P->d_table, P->d_all, P->nb_all, P->stream, false};
   L.ionic_npt = P->ionic_npt;
@@ -2299,10 +2311,8 @@ ep_status pool_step_once(ep_pool* P) {
   hipStream_t st = P->stream;
   auto fin = [&] { kt.timed(st, 6, [&] { launch_cg_finalize(mixed, P->d_table, P->d_ids, ni, st); }); };
   auto round = [&] {
-    if (pipe) {
-      kt.timed(st, 7, [&] { mixed ? launch_cg_pipe32(L) : launch_cg_pipe(L); });
-      return;
-    }
+    if (pipe) kt.timed(st, 7, [&] { mixed ? launch_cg_pipe32(L) : launch_cg_pipe(L); });
+    if (!cgg) return;
     if (!mixed) {
       kt.timed(st, 2, [&] { launch_cg_spmv(false, L); });
       kt.timed(st, 3, [&] { launch_cg_update64(L); });
@@ -2328,9 +2338,8 @@ ep_status pool_step_once(ep_pool* P) {
       }
     });
     kt.timed(st, 1, [&] { launch_residual(mixed, true, L); });
-    if (pipe) {
-      kt.timed(st, 2, [&] { mixed ? launch_cg_pipe32_start(L) : launch_cg_pipe_start(L); });
-    } else if (mixed) {
+    if (pipe) kt.timed(st, 2, [&] { mixed ? launch_cg_pipe32_start(L) : launch_cg_pipe_start(L); });
+    if (cgg && mixed) {
       kt.timed(st, 2, [&] { launch_cg_spmv(mixed, L); });
       fin();
     }
@@ -2342,10 +2351,11 @@ ep_status pool_step_once(ep_pool* P) {
       // decision, so the host's next read sees it
       kt.timed(st, 2, [&] { launch_cg_pipe32_start(L); });
       kt.timed(st, 7, [&] { launch_cg_pipe32(L); });
-      return;
     }
-    kt.timed(st, 2, [&] { launch_cg_spmv(true, L); });
-    fin();
+    if (cgg) {
+      kt.timed(st, 2, [&] { launch_cg_spmv(true, L); });
+      fin();
+    }
   };
   auto epi = [&] {
     kt.timed(st, 4, [&] { launch_activation(L); });
@@ -2480,11 +2490,6 @@ ep_status ep_pool_admit(ep_pool* P, ep_sim* s, int64_t n_steps_total, int* slot)
   if (s->fmt_pref == EP_FMT_MF || (s->finalized && s->desc.fmt == FMT_MF))
     return fail(EP_EINVAL, "matrix-free sims are not admitted to pools");
   if (s->device != P->device) return fail(EP_EINVAL, "sim device differs from the pool's");
-  bool empty = true;
-  for (int k = 0; k < P->max_slots; k++)
-    if (P->slots[k].sim) empty = false;
-  if (!empty && cg_resolved(s) != P->cg_variant)
-    return fail(EP_EINVAL, "sim CG variant differs from the pool members'");
   int free_slot = -1;
   for (int k = 0; k < P->max_slots; k++)
     if (!P->slots[k].sim) {
@@ -2519,7 +2524,6 @@ ep_status ep_pool_admit(ep_pool* P, ep_sim* s, int64_t n_steps_total, int* slot)
   s->pool = P;
   ep_pool::Slot& sl = P->slots[free_slot];
   sl.sim = s;
-  if (empty) P->cg_variant = cg_resolved(s);
   sl.target = n_steps_total;
   sl.done_steps = 0;
   sl.done = false;

@@ -819,7 +819,8 @@ __global__ __launch_bounds__(WG) void k_cg_spmv(InstDesc* __restrict__ insts, co
   InstDesc& I = instance<SINGLE, XMAP>(insts, bmap, lblk);
   if (lblk < 0) return;
   InstState& S = I.st;
-  if (cg_idle(S)) return;
+  // a pool may hold instances of the pipelined form, which skip this kernel
+  if (cg_idle(S) || (!SINGLE && I.cg_pipe)) return;
   // FP64: the iteration index the following update kernel works on (no
   // workgroup of this kernel reads it)
   if (!MIXED && lblk == 0 && threadIdx.x == 0) S.it = S.it + 1;
@@ -884,7 +885,7 @@ __global__ __launch_bounds__(FIN_WG) void k_cg_finalize(InstDesc* __restrict__ i
     t[1] = a[2];
     t[2] = t[3] = 0.0;
   }
-  if (ctl.conv != 0 || (ctl.conv_in != 0 && ctl.restart == 0)) return;
+  if (ctl.conv != 0 || (ctl.conv_in != 0 && ctl.restart == 0) || (!SINGLE && I.cg_pipe)) return;
   if (threadIdx.x != 0) return;
   S.restart = 0;
   S.conv_in = 0;
@@ -969,7 +970,7 @@ __global__ __launch_bounds__(WG) void k_cg_update(InstDesc* __restrict__ insts, 
   InstDesc& I = instance<SINGLE, XMAP>(insts, bmap, lblk);
   if (lblk < 0) return;
   InstState& S = I.st;
-  if (cg_idle(S)) return;
+  if (cg_idle(S) || (!SINGLE && I.cg_pipe)) return;
   const int k = S.it_f;
   const double alpha = S.alpha_cur, beta = S.beta;
   const int sig = min(I.bdf, (int)S.step + 1);
@@ -1044,7 +1045,7 @@ __global__ __launch_bounds__(WG) void k_cg_update64(InstDesc* __restrict__ insts
   InstDesc& I = instance<SINGLE, XMAP>(insts, bmap, lblk);
   if (lblk < 0) return;
   InstState& S = I.st;
-  if (S.conv != 0) return;
+  if (S.conv != 0 || (!SINGLE && I.cg_pipe)) return;
   const int k = S.it;
   const int nblk = I.nblk;
   const int sig = min(I.bdf, (int)S.step + 1);

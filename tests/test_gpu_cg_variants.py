@@ -123,28 +123,33 @@ def test_kernel_counts_one_launch_per_iteration():
     s.close()
 
 
-def test_pool_members_share_one_cg_variant():
+def test_pool_with_both_cg_variants():
+    """A pool holding members of both formulations (FP64 and mixed): each
+    member bitwise equal to its run alone."""
     ep = _ep()
-    spec = _slab()
-    pool = ep.Pool(1 << 30, 4, ep.EP_FP64)
-    a = ep.Simulation.from_spec(spec, finalize=False)
-    assert pool.admit(a, 10) is not None
-    b = ep.Simulation.from_spec(spec, finalize=False, cg_variant=ep.EP_CG_CHRONOPOULOS_GEAR)
-    with pytest.raises(ep.EpError):
-        pool.admit(b, 10)
-    b.close()
-    pool.step(10)
-    for slot in list(pool.poll()):
-        pool.release(slot)
-    a.close()
-    # an emptied pool takes either variant
-    c = ep.Simulation.from_spec(spec, finalize=False, cg_variant=ep.EP_CG_CHRONOPOULOS_GEAR)
-    assert pool.admit(c, 5) is not None
-    pool.step(5)
-    for slot in list(pool.poll()):
-        pool.release(slot)
-    c.close()
-    pool.close()
+    for prec in (ep.EP_FP64, ep.EP_MIXED):
+        specs = [(_slab(), ep.EP_CG_PIPELINED), (_slab(model="bo", variant="epi"), ep.EP_CG_CHRONOPOULOS_GEAR),
+                 (_slab(model="ap", variant="", bdf=1), ep.EP_CG_PIPELINED)]
+        alone = []
+        for sp, cgv in specs:
+            s = ep.Simulation.from_spec(sp, precision=prec, cg_variant=cgv)
+            s.step(60)
+            alone.append(s.get_state()[0])
+            s.close()
+        pool = ep.Pool(1 << 30, 4, prec)
+        sims = []
+        for sp, cgv in specs:
+            s = ep.Simulation.from_spec(sp, precision=prec, cg_variant=cgv, finalize=False)
+            slot = pool.admit(s, 60)
+            assert slot is not None
+            sims.append((slot, s))
+        pool.step(60)
+        assert sorted(pool.poll()) == sorted(sl for sl, _ in sims)
+        for (slot, s), ref in zip(sims, alone):
+            assert np.array_equal(s.get_state()[0], ref), (prec, slot)
+            pool.release(slot)
+            s.close()
+        pool.close()
 
 
 def test_auto_variant_by_element_degree():
