@@ -41,14 +41,19 @@ term by the bistable-front speed, the Rush-Larsen and BDF gate updates
 rapid-buffer inversion, the rewritten I_CaL against its GHK form, and the
 TTP06 concentration bookkeeping of both integrators (`ttp06_step`,
 `ttp06_step_bdf`) by charge conservation: the membrane currents equal the
-valence- and volume-weighted change of Na, K and total Ca.
+valence- and volume-weighted change of Na, K and total Ca; and the
+steady states of the TTP06 gates m, xr2, s (epicardial), r and d against
+the paper's printed rest state (those gates relax within milliseconds, so
+y_inf(-85.23 mV) must give the printed values).
 
 Parity unpinned (the publications' equations and traces are not available
 here, and no closed form or invariant fixes them):
   ap_dv                 the Aliev-Panfilov recovery rate away from rest;
   bo_gate_targets       the Bueno-Orovio gate targets and time constants;
   bo_iion               the Bueno-Orovio currents J_fi, J_so, J_si;
-  ttp06_gate_targets    the 12 TTP06 steady states and time constants;
+  ttp06_gate_targets    the TTP06 time constants and the steady states of
+                        h, j, xr1, xs, f, f2, fcass (those of m, xr2, s,
+                        r, d are pinned, above);
   ttp06_currents        the TTP06 current and flux formulas (except I_CaL's
                         rewrite and the stoichiometry the conservation pin fixes).
 TTP06 is pinned end to end by the N-version slab activation time through the
