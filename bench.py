@@ -202,13 +202,14 @@ def _warm(sim, ep, warmup, graph, autotune, make_scratch):
 
 
 def run_gpu(spec, precision, steps, warmup, instrument_steps, graph=True, autotune=True, ionic_scheme="rl",
-            material=None, regions=None, matrix_format=0, cg_variant=0):
+            material=None, regions=None, matrix_format=0, cg_variant=0, initial_guess=0):
     import paper_2308_01651_amd as ep
     import torch
 
     def make():
         return ep.Simulation.from_spec(spec, precision=precision, ionic_scheme=ionic_scheme, material=material,
-                                       regions=regions, matrix_format=matrix_format, cg_variant=cg_variant)
+                                       regions=regions, matrix_format=matrix_format, cg_variant=cg_variant,
+                                       initial_guess=initial_guess)
     sim = make()
     st0 = sim.get_stats()
     launch, pre_steps = _warm(sim, ep, warmup, graph, autotune, make)
@@ -566,15 +567,18 @@ def main():
         zmax = float(spec.mesh.xyz[:, 2].max())
         layers = W.material_layers(spec.mesh, 2, [zmax / 3, 2 * zmax / 3])
         layer_regions = {0: dict(variant="endo"), 1: dict(variant="mid"), 2: dict(variant="epi")}
-        for name, g, t, sch, mat, regs, cgv in (
-                ("fp64_default_launches", False, False, "rl", None, None, 0),
-                ("fp64_graph_replay", True, bool(args.autotune), "rl", None, None, 0),
-                ("fp64_chronopoulos_gear_cg", bool(args.graph), bool(args.autotune), "rl", None, None, 2),
-                ("fp64_paper_bdf_ionic_scheme", bool(args.graph), bool(args.autotune), "bdf", None, None, 0),
-                ("fp64_three_cell_layers", bool(args.graph), bool(args.autotune), "rl", layers, layer_regions, 0)):
-            if g == bool(args.graph) and t == bool(args.autotune) and sch == "rl" and mat is None and cgv == 0:
+        for name, g, t, sch, mat, regs, cgv, x0 in (
+                ("fp64_default_launches", False, False, "rl", None, None, 0, 0),
+                ("fp64_graph_replay", True, bool(args.autotune), "rl", None, None, 0, 0),
+                ("fp64_chronopoulos_gear_cg", bool(args.graph), bool(args.autotune), "rl", None, None, 2, 0),
+                ("fp64_extrapolated_initial_guess", bool(args.graph), bool(args.autotune), "rl", None, None, 0, 1),
+                ("fp64_paper_bdf_ionic_scheme", bool(args.graph), bool(args.autotune), "bdf", None, None, 0, 0),
+                ("fp64_three_cell_layers", bool(args.graph), bool(args.autotune), "rl", layers, layer_regions, 0, 0)):
+            if g == bool(args.graph) and t == bool(args.autotune) and sch == "rl" and mat is None and cgv == 0 \
+                    and x0 == 0:
                 continue
-            r0, _, _ = run_gpu(spec, ep.EP_FP64, args.steps, args.warmup, 0, g, t, sch, mat, regs, cg_variant=cgv)
+            r0, _, _ = run_gpu(spec, ep.EP_FP64, args.steps, args.warmup, 0, g, t, sch, mat, regs, cg_variant=cgv,
+                               initial_guess=x0)
             out[name] = {k: r0[k] for k in ("node_steps_per_s", "ms_per_step", "cg_iters_per_step", "step_latency_ms_p50",
                                             "step_latency_ms_p99", "launch")}
             print(f"[bench] {name}: {r0['node_steps_per_s']:.4g} node-steps/s", file=sys.stderr, flush=True)

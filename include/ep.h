@@ -96,11 +96,18 @@ enum {
   EP_OPT_IONIC_FP64 = 10,   /* mixed precision: 1 steps the ionic model (state and
                              * arithmetic) in FP64 while the inner CG stays FP32;
                              * 0 (default) FP32 (before finalize)                  */
-  EP_OPT_CG_VARIANT = 11    /* CG formulation, EP_CG_* (before finalize): of the FP64
+  EP_OPT_CG_VARIANT = 11,   /* CG formulation, EP_CG_* (before finalize): of the FP64
                              * solve, or of the FP32 inner solve of each mixed-
                              * precision refinement sweep.  Both formulations are
                              * PCG with the same preconditioner; results agree to
                              * the solver tolerance, not bitwise.                 */
+  EP_OPT_INITIAL_GUESS = 12 /* initial guess of each step's solve (before finalize):
+                             * EP_X0_EXT (default; u_EXT, the reading the oracle
+                             * uses) or EP_X0_EXTRAP3 (third-order extrapolation of
+                             * the potential once three consistent levels exist:
+                             * about 4 % fewer CG iterations on C1; not in the
+                             * paper).  Changes results within the solver
+                             * tolerance only.                                    */
 };
 
 /* FP64 CG formulations (EP_OPT_CG_VARIANT).  EP_CG_PIPELINED: one kernel per
@@ -118,6 +125,9 @@ enum {
  * members of both formulations: it launches the kernels of each one
  * present, and each kernel skips the other's members. */
 enum { EP_CG_AUTO = 0, EP_CG_PIPELINED = 1, EP_CG_CHRONOPOULOS_GEAR = 2 };
+
+/* Initial guesses (EP_OPT_INITIAL_GUESS). */
+enum { EP_X0_EXT = 0, EP_X0_EXTRAP3 = 1 };
 
 /* Ionic integrators (EP_OPT_IONIC_SCHEME).  EP_IONIC_RUSH_LARSEN (default):
  * gates by the exponential at u_EXT, other variables one explicit step.

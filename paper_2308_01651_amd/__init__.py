@@ -27,7 +27,8 @@ EP_FMT_AUTO, EP_FMT_SELL, EP_FMT_DIA, EP_FMT_MF = 0, 1, 2, 3
 EP_OPT_MATRIX_FORMAT, EP_OPT_INNER_RTOL, EP_OPT_MAX_OUTER, EP_OPT_PHASE_TIMERS = 1, 2, 3, 4
 EP_OPT_KERNEL_TIMERS = 5
 EP_OPT_IONIC_NPT, EP_OPT_TILE_MAP, EP_OPT_GRAPH, EP_OPT_IONIC_SCHEME, EP_OPT_IONIC_FP64 = 6, 7, 8, 9, 10
-EP_OPT_CG_VARIANT = 11
+EP_OPT_CG_VARIANT, EP_OPT_INITIAL_GUESS = 11, 12
+EP_X0_EXT, EP_X0_EXTRAP3 = 0, 1
 EP_CG_AUTO, EP_CG_PIPELINED, EP_CG_CHRONOPOULOS_GEAR = 0, 1, 2
 EP_IONIC_RUSH_LARSEN, EP_IONIC_BDF = 0, 1
 EP_MAX_REGIONS = 8
@@ -220,14 +221,15 @@ class Simulation:
     @classmethod
     def from_spec(cls, spec, precision=EP_FP64, device=0, stream=None, rtol=None, max_it=1000,
                   matrix_format=EP_FMT_AUTO, finalize=True, inner_rtol=None, block=1, ionic_scheme="rl",
-                  material=None, regions=None, ionic_fp64=False, cg_variant=EP_CG_AUTO):
+                  material=None, regions=None, ionic_fp64=False, cg_variant=EP_CG_AUTO,
+                  initial_guess=EP_X0_EXT):
         """Configure from a workloads.SimSpec (marshalling of its arrays).
         block > 1 selects block-Jacobi preconditioning with that block size;
         ionic_fp64: in mixed precision, step the ionic model in FP64;
         ionic_scheme "rl" (Rush-Larsen) or "bdf" (the paper's semi-implicit
         BDF).  material: per-element subdomain labels; regions: {label:
         dict(variant=, params=, sigma=, conductive=)} passed to set_region;
-        cg_variant: the FP64 CG formulation (EP_CG_*)."""
+        cg_variant: the CG formulation (EP_CG_*); initial_guess: EP_X0_*."""
         sim = cls(device, stream)
         m = spec.mesh
         sim.upload_mesh(m.elem, m.xyz, m.conn, material)
@@ -252,6 +254,8 @@ class Simulation:
             sim.set_option(EP_OPT_IONIC_FP64, 1)
         if cg_variant != EP_CG_AUTO:
             sim.set_option(EP_OPT_CG_VARIANT, cg_variant)
+        if initial_guess != EP_X0_EXT:
+            sim.set_option(EP_OPT_INITIAL_GUESS, initial_guess)
         if finalize:
             sim.finalize()
         return sim

@@ -266,6 +266,7 @@ struct ep_sim {
   int ionic_scheme = 0;   // EP_IONIC_RUSH_LARSEN or EP_IONIC_BDF
   int ionic_fp64 = 0;     // mixed precision: ionic step in FP64 (EP_OPT_IONIC_FP64)
   int cg_variant = EP_CG_AUTO;   // FP64 CG formulation (EP_OPT_CG_VARIANT)
+  int x0_extrap = 0;             // EP_OPT_INITIAL_GUESS
   int fmt_pref = EP_FMT_AUTO;
   // subdomains: element labels (empty: one subdomain) and per-label settings
   std::vector<int32_t> material;
@@ -1036,6 +1037,7 @@ ep_status finalize_impl(ep_sim* s) {
   s->nblocks = N_XCD * ((ntiles + N_XCD - 1) / N_XCD);
   EP_HIP(m.alloc((void**)&D.partial, (size_t)ntiles * PART_DOUBLES * sizeof(double)));
   D.cg_pipe = cg_resolved(s) == EP_CG_PIPELINED ? 1 : 0;
+  D.x0_extrap = s->x0_extrap;
   if (D.cg_pipe) {
     EP_HIP(m.alloc((void**)&D.pipe_rec, (size_t)ntiles * PIPE_REC * sizeof(double)));
     EP_HIP(hipMemsetAsync(D.pipe_rec, 0, (size_t)ntiles * PIPE_REC * sizeof(double), st));
@@ -1591,6 +1593,10 @@ ep_status ep_sim_set_option(ep_sim* s, int key, double value) {
     case EP_OPT_IONIC_FP64:
       if (value != 0.0 && value != 1.0) return fail(EP_EINVAL, "ionic FP64: 0 or 1");
       s->ionic_fp64 = (int)value;
+      return EP_OK;
+    case EP_OPT_INITIAL_GUESS:
+      if (value != EP_X0_EXT && value != EP_X0_EXTRAP3) return fail(EP_EINVAL, "initial guess");
+      s->x0_extrap = value == EP_X0_EXTRAP3 ? 1 : 0;
       return EP_OK;
     case EP_OPT_CG_VARIANT:
       if (value != EP_CG_AUTO && value != EP_CG_PIPELINED && value != EP_CG_CHRONOPOULOS_GEAR)

@@ -168,6 +168,7 @@ struct InstDesc {
   // alternates: FP64 between b (even k) and g (odd k), both free during the
   // FP64 solve; FP32 between m32[0] and m32[1].
   int32_t cg_pipe;
+  int32_t x0_extrap;       // 1: initial guess by third-order extrapolation (else u_EXT)
   double* pipe_rec;        // [nblk][PIPE_REC]
   float* m32[2];
 };

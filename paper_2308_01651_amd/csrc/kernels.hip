@@ -621,11 +621,12 @@ __device__ __forceinline__ void ionic_point(const InstDesc& I, int64_t n, int64_
   if (RHS) {
     const double iapp = stimulus_at(I, step + 1, node);
     gmem(I.g)[node] = u_bdf * I.inv_dt + iapp - iion;
-    // initial guess of the linear solve: the potential extrapolated from
-    // the last three solutions once they form a consistent history (one
-    // order above u_EXT for BDF2; only the iteration count depends on it)
+    // initial guess of the linear solve: u_EXT, or (option) the potential
+    // extrapolated from the last three solutions once they form a
+    // consistent history (one order above u_EXT for BDF2; only the
+    // iteration count depends on it)
     double x0 = u_field;
-    if (I.st.hist >= 3) {
+    if (I.x0_extrap && I.st.hist >= 3) {
       const double a1 = gmem(I.u_prev1)[node], a2 = gmem(I.u_prev2)[node];
       x0 = 3.0 * u0 - 3.0 * a1 + a2;
     }

@@ -202,3 +202,24 @@ def test_mixed_pipelined_inner_solve(model, variant, bdf):
     assert st["ir_sweeps_total"] >= st["steps"]
     for s in (ref, pipe, cgg):
         s.close()
+
+
+def test_extrapolated_initial_guess_option():
+    """EP_X0_EXTRAP3 changes only the iteration count: the trajectory stays
+    within steps x rtol of the default (x0 = u_EXT) and of the oracle, and
+    needs no more iterations."""
+    ep = _ep()
+    spec = _slab()
+    o = OM.from_spec(spec, solver="splu")
+    ref = ep.Simulation.from_spec(spec)
+    ext = ep.Simulation.from_spec(spec, initial_guess=ep.EP_X0_EXTRAP3)
+    o.run(200)
+    ref.step(200)
+    ext.step(200)
+    assert _rel(ext.get_potential(), ref.get_potential()) < 200 * spec.rtol
+    assert _rel(ext.get_potential(), o.potential_mv()) < 200 * spec.rtol
+    assert ext.get_stats()["cg_iters_total"] <= ref.get_stats()["cg_iters_total"]
+    with pytest.raises(ep.EpError):
+        ep.Simulation.from_spec(spec, initial_guess=7)
+    ref.close()
+    ext.close()
