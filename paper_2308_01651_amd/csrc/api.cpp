@@ -2226,6 +2226,7 @@ struct ep_pool {
   // CG formulations among the active members: the pool launches the kernels
   // of each one present (the kernels of one form skip the other's members)
   bool has_pipe = false, has_cgg = false;
+  bool all_dia14 = false;   // every active member: 14-diagonal DIA, Jacobi (specialized kernels)
 };
 
 namespace {
@@ -2252,7 +2253,12 @@ ep_status pool_rebuild(ep_pool* P) {
   for (int k = 0; k < P->max_slots; k++)
     if (P->slots[k].sim && !P->slots[k].done) P->active.push_back(k);
   P->has_pipe = P->has_cgg = false;
-  for (int k : P->active) (P->slots[k].sim->desc.cg_pipe ? P->has_pipe : P->has_cgg) = true;
+  P->all_dia14 = !P->active.empty();
+  for (int k : P->active) {
+    const InstDesc& D = P->slots[k].sim->desc;
+    (D.cg_pipe ? P->has_pipe : P->has_cgg) = true;
+    if (!(D.fmt == FMT_DIA && D.nup == 14 && D.block == 1)) P->all_dia14 = false;
+  }
   std::vector<BlockMap> all, per_model[16];
   P->het_slots.clear();
   for (int k : P->active) {
@@ -2313,6 +2319,7 @@ ep_status pool_step_once(ep_pool* P) {
   const int ni = (int)P->active.size();
   Launch L{P->d_table, P->d_all, P->nb_all, P->stream, false};
   L.ionic_npt = P->ionic_npt;
+  L.pipe_op = P->all_dia14 ? 1 : 0;
   KernelTimers& kt = P->kt;
   hipStream_t st = P->stream;
   auto fin = [&] { kt.timed(st, 6, [&] { launch_cg_finalize(mixed, P->d_table, P->d_ids, ni, st); }); };

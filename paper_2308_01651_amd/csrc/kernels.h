@@ -27,8 +27,8 @@ struct Launch {
   // the element kernels first
   int mf_p = 0;
   int64_t mf_elems = 0;
-  // pipelined CG of a single instance whose operator is the 14-diagonal
-  // symmetric DIA with Jacobi preconditioning: the specialized kernel
+  // pipelined CG of instances whose operators are all 14-diagonal symmetric
+  // DIA with Jacobi preconditioning: the specialized kernels
   int pipe_op = 0;
 };
 

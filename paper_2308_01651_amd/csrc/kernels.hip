@@ -1389,7 +1389,8 @@ __global__ __launch_bounds__(WG) void k_cg_pipe32_start(InstDesc* __restrict__ i
   write_partials<1>(v, I.partial + (int64_t)PART_SPMV * I.nblk, I.nblk, lblk);
 }
 
-template <bool SINGLE, int XMAP>
+// OP as for k_cg_pipe: 1 = the 14-diagonal symmetric DIA with Jacobi.
+template <bool SINGLE, int XMAP, int OP>
 __global__ __launch_bounds__(WG) void k_cg_pipe32(InstDesc* __restrict__ insts, const BlockMap* __restrict__ bmap) {
   int lblk;
   InstDesc& I = instance<SINGLE, XMAP>(insts, bmap, lblk);
@@ -1403,12 +1404,13 @@ __global__ __launch_bounds__(WG) void k_cg_pipe32(InstDesc* __restrict__ insts, 
   const int k = (int)rec[0] + 1;
   const double gam_prev = rec[1], alp_prev = rec[2], rr_in0_rec = rec[4], f2_rec = rec[5];
   const int64_t i0 = (int64_t)lblk * TILE + threadIdx.x;
-  float zv[RPT], wv[RPT], pv[RPT], sv[RPT], rv[RPT];
+  const float* dinv = I.dinv32[sig - 1];
+  float zv[RPT], wv[RPT], pv[RPT], sv[RPT], rv[RPT], dv[RPT];
   double xv[RPT];
 #pragma unroll
   for (int rw = 0; rw < RPT; rw++) {
     const int64_t i = i0 + rw * WG;
-    zv[rw] = wv[rw] = pv[rw] = sv[rw] = rv[rw] = 0.0f;
+    zv[rw] = wv[rw] = pv[rw] = sv[rw] = rv[rw] = dv[rw] = 0.0f;
     xv[rw] = 0.0;
     if (i < I.n) {
       zv[rw] = gmem(I.z32)[i];
@@ -1417,6 +1419,7 @@ __global__ __launch_bounds__(WG) void k_cg_pipe32(InstDesc* __restrict__ insts, 
       sv[rw] = gmem(I.s32)[i];
       rv[rw] = gmem(I.r32)[i];
       xv[rw] = gmem(I.u_new)[i];
+      if (OP == 1) dv[rw] = gmem(dinv)[i];
     }
   }
   const double* __restrict__ P = I.partial;
@@ -1524,18 +1527,21 @@ __global__ __launch_bounds__(WG) void k_cg_pipe32(InstDesc* __restrict__ insts, 
   }
   const float* m_in = I.m32[k & 1];
   const gptr<float> m_out = gmem(I.m32[(k + 1) & 1]);
-  const float* dinv = I.dinv32[sig - 1];
-  const bool jacobi = I.block == 1;
+  const bool jacobi = OP == 1 || I.block == 1;
   const float fa = (float)alpha, fb = (float)beta;
   double v[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int rw = 0; rw < RPT; rw++) {
     const int64_t i = i0 + rw * WG;
     const bool valid = i < I.n;
-    float ni = 0.0f, di = 0.0f;
+    float ni = 0.0f, di = dv[rw];
     if (valid) {
-      ni = spmv_row<float, float, float>(I, I.valA32[sig - 1], m_in, i);
-      if (jacobi) di = gmem(dinv)[i];
+      if (OP == 1) {
+        ni = dia_row<14, float, float, float>(I, I.valA32[sig - 1], m_in, i, 14);
+      } else {
+        ni = spmv_row<float, float, float>(I, I.valA32[sig - 1], m_in, i);
+        if (jacobi) di = gmem(dinv)[i];
+      }
     }
     const float ui = jacobi ? __fmul_rn(di, rv[rw]) : precond_apply<float>(dinv, I.bld, I.block, i, valid, rv[rw]);
     float wn = 0.0f, rn = 0.0f;
@@ -1773,9 +1779,12 @@ void launch_cg_pipe32_start(const Launch& L) {
 void launch_cg_pipe32(const Launch& L) {
   if (L.nblocks <= 0) return;
   const dim3 g(L.nblocks), b(WG);
-  if (!L.single) hipLaunchKernelGGL((k_cg_pipe32<false, 0>), g, b, 0, L.stream, L.insts, L.bmap);
-  else if (L.xmap == 1) hipLaunchKernelGGL((k_cg_pipe32<true, 1>), g, b, 0, L.stream, L.insts, L.bmap);
-  else hipLaunchKernelGGL((k_cg_pipe32<true, 0>), g, b, 0, L.stream, L.insts, L.bmap);
+  if (!L.single && L.pipe_op == 1) hipLaunchKernelGGL((k_cg_pipe32<false, 0, 1>), g, b, 0, L.stream, L.insts, L.bmap);
+  else if (!L.single) hipLaunchKernelGGL((k_cg_pipe32<false, 0, 0>), g, b, 0, L.stream, L.insts, L.bmap);
+  else if (L.pipe_op == 1 && L.xmap == 1) hipLaunchKernelGGL((k_cg_pipe32<true, 1, 1>), g, b, 0, L.stream, L.insts, L.bmap);
+  else if (L.pipe_op == 1) hipLaunchKernelGGL((k_cg_pipe32<true, 0, 1>), g, b, 0, L.stream, L.insts, L.bmap);
+  else if (L.xmap == 1) hipLaunchKernelGGL((k_cg_pipe32<true, 1, 0>), g, b, 0, L.stream, L.insts, L.bmap);
+  else hipLaunchKernelGGL((k_cg_pipe32<true, 0, 0>), g, b, 0, L.stream, L.insts, L.bmap);
 }
 
 void launch_cg_pipe_start(const Launch& L) {
@@ -1791,7 +1800,8 @@ void launch_cg_pipe(const Launch& L) {
   if (L.nblocks <= 0) return;
   if (L.mf_p) launch_mf_apply(3, L);   // A m_k
   const dim3 g(L.nblocks), b(WG);
-  if (!L.single) hipLaunchKernelGGL((k_cg_pipe<false, 0, 0>), g, b, 0, L.stream, L.insts, L.bmap);
+  if (!L.single && L.pipe_op == 1) hipLaunchKernelGGL((k_cg_pipe<false, 0, 1>), g, b, 0, L.stream, L.insts, L.bmap);
+  else if (!L.single) hipLaunchKernelGGL((k_cg_pipe<false, 0, 0>), g, b, 0, L.stream, L.insts, L.bmap);
   else if (L.pipe_op == 1 && L.xmap == 1) hipLaunchKernelGGL((k_cg_pipe<true, 1, 1>), g, b, 0, L.stream, L.insts, L.bmap);
   else if (L.pipe_op == 1) hipLaunchKernelGGL((k_cg_pipe<true, 0, 1>), g, b, 0, L.stream, L.insts, L.bmap);
   else if (L.xmap == 1) hipLaunchKernelGGL((k_cg_pipe<true, 1, 0>), g, b, 0, L.stream, L.insts, L.bmap);
