@@ -174,6 +174,7 @@ def _alu(kernel_kind, precision, workload, launch, avg_s):
 
 
 TUNE_TRIAL = 3   # steps per candidate launch shape (the tuner runs 5 candidates)
+TUNE_TRIAL_POOL = 8   # the same for the batched pool, whose step times vary more between candidates
 
 
 def _warm(sim, ep, warmup, graph, autotune, make_scratch):
@@ -361,14 +362,14 @@ def run_batched(specs, precision, steps, warmup, graph=True, autotune=True):
     t0 = time.perf_counter()
     for sp in specs:
         s = ep.Simulation.from_spec(sp, precision=precision, finalize=False)
-        if pool.admit(s, 5 * TUNE_TRIAL + max(2, warmup) + steps + 1) is None:
+        if pool.admit(s, 5 * TUNE_TRIAL_POOL + max(2, warmup) + steps + 1) is None:
             raise RuntimeError("batched instance did not fit the pool")
         sims.append(s)
     setup = time.perf_counter() - t0
     launch = {"ionic_npt": 1, "tile_map": 0, "graph": bool(graph), "tuned": False}
     if autotune:
-        npt, tmap = pool.autotune(TUNE_TRIAL)
-        launch.update(ionic_npt=npt, tile_map=tmap, tuned=True, tuning_steps=5 * TUNE_TRIAL)
+        npt, tmap = pool.autotune(TUNE_TRIAL_POOL)
+        launch.update(ionic_npt=npt, tile_map=tmap, tuned=True, tuning_steps=5 * TUNE_TRIAL_POOL)
     if graph:
         pool.set_option(ep.EP_OPT_GRAPH, 1)
     pool.step(max(2, warmup))
