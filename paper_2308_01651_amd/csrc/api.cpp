@@ -709,6 +709,8 @@ ep_status finalize_impl(ep_sim* s) {
     s->guard = 0;
     D.mf_p = mfd.p;
     D.n_elems = s->n_elems;
+    D.mf_cmp = mfd.cmp ? 1 : 0;
+    for (int k = 0; k < 4; k++) D.mfW[k] = mfd.W[k];
     const int n1 = mfd.p + 1;
     for (int k = 0; k < n1 * n1; k++) {
       D.mfV[k] = mfd.V[k];
@@ -1163,7 +1165,7 @@ ep_status validate_desc(const ep_sim* s, const InstDesc& D) {
     }
   } else {
     const int64_t npe = s->elem, ent = D.n_elems * npe, Q = npe;
-    if (D.n_elems != s->n_elems || !in(D.econn, 0, ent, 4) || !in(D.geo, 0, D.n_elems * 7 * Q, 8) ||
+    if (D.n_elems != s->n_elems || !in(D.econn, 0, ent, 4) || !in(D.geo, 0, D.n_elems * 7 * (D.mf_cmp ? 1 : Q), 8) ||
         !in(D.yA, 0, ent, 8) || !in(D.yM, 0, ent, 8) || !in(D.adj_ptr, 0, n + 1, 8) || !in(D.adj, 0, ent, 4))
       return bad("matrix-free array range");
   }
@@ -1194,6 +1196,7 @@ Launch launch_of(ep_sim* s) {
   if (s->desc.fmt == FMT_MF) {
     L.mf_p = s->desc.mf_p;
     L.mf_elems = s->n_elems;
+    L.mf_cmp = s->desc.mf_cmp != 0;
   }
   L.xmap = s->xmap;
   L.ionic_npt = s->ionic_npt;

@@ -9,6 +9,8 @@
 // given per node and interpolated with the FE basis.
 #include "assembly.h"
 
+#include <atomic>
+#include <cfloat>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -609,6 +611,53 @@ bool mf_setup(int elem, int64_t n_nodes, const double* xyz, int64_t n_elems, con
   if (bad[1]) {
     set_err(err, "the diffusion tensor interpolated from the nodal fibers is indefinite at a quadrature point");
     return false;
+  }
+  // compression: every element's factors equal (product of the point's 1-D
+  // Gauss weights) x (an element constant) to rounding.  The Jacobian is
+  // interpolated from coordinates of magnitude R on an element of extent d,
+  // so its rounding is about eps R / d relative; an affine element passes at
+  // 64 eps (1 + R / d), a curved one or a varying tensor (relative changes of
+  // the order of the element size) does not
+  {
+    std::vector<double> wq(Q);
+    for (int qz = 0; qz < n1; qz++)
+      for (int qy = 0; qy < n1; qy++)
+        for (int qx = 0; qx < n1; qx++) wq[qx + n1 * (qy + n1 * qz)] = gw[qx] * gw[qy] * gw[qz];
+    std::atomic<bool> uniform{true};
+    parallel_for(n_elems, [&](int64_t e) {
+      if (!uniform.load(std::memory_order_relaxed)) return;
+      const double* g = &out.geo[(size_t)e * 7 * Q];
+      double R = 0.0, d = 0.0;
+      const int64_t v0 = conn[e * npe];
+      for (int k = 0; k < npe; k++) {
+        const int64_t v = conn[e * npe + k];
+        for (int c = 0; c < 3; c++) {
+          R = std::max(R, std::fabs(xyz[3 * v + c]));
+          d = std::max(d, std::fabs(xyz[3 * v + c] - xyz[3 * v0 + c]));
+        }
+      }
+      const double tol = 64.0 * DBL_EPSILON * (1.0 + R / d);
+      // each part against its own magnitude: the 3x3 factor, and det J
+      double scale_c = 0.0;
+      for (int c2 = 0; c2 < 6; c2++) scale_c = std::max(scale_c, std::fabs(g[c2 * Q] / wq[0]));
+      for (int c = 0; c < 7; c++) {
+        const double k = g[c * Q] / wq[0];
+        const double scale = c < 6 ? scale_c : std::fabs(k);
+        for (int q = 1; q < Q; q++)
+          if (std::fabs(g[c * Q + q] - k * wq[q]) > tol * scale * wq[q]) {
+            uniform.store(false, std::memory_order_relaxed);
+            return;
+          }
+      }
+    });
+    if (uniform.load()) {
+      std::vector<double> gc((size_t)n_elems * 7);
+      for (int64_t e = 0; e < n_elems; e++)
+        for (int c = 0; c < 7; c++) gc[(size_t)e * 7 + c] = out.geo[(size_t)e * 7 * Q + (size_t)c * Q] / wq[0];
+      out.geo.swap(gc);
+      out.cmp = true;
+      for (int j = 0; j < n1; j++) out.W[j] = gw[j];
+    }
   }
   // node adjacency (element * npe + local index), ascending per node
   out.adj_ptr.assign(n_nodes + 1, 0);

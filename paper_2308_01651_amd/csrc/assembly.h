@@ -45,7 +45,13 @@ bool assemble_csr(int elem, int64_t n_nodes, const double* xyz, int64_t n_elems,
 struct MfData {
   int p = 0;
   int64_t n_elems = 0;
+  // per element and quadrature point: [e][7][Q] (xx, xy, xz, yy, yz, zz of
+  // w det J J^-1 D J^-T, then w det J); compressed (every element affine
+  // with one D, so each factor is the product of the point's Gauss weights
+  // and an element constant): [e][7] with W the 1-D Gauss weights
+  bool cmp = false;
   std::vector<double> geo;
+  double W[4] = {0, 0, 0, 0};
   std::vector<double> V, Dv;
   std::vector<int64_t> adj_ptr;
   std::vector<int32_t> adj;

@@ -152,12 +152,14 @@ struct InstDesc {
   int32_t mf_p;
   int64_t n_elems;
   const int32_t* econn;    // [n_elems][(mf_p + 1)^3] element nodes
-  const double* geo;       // [n_elems][7][(mf_p + 1)^3] quadrature-point factors
+  const double* geo;       // [n_elems][7][(mf_p + 1)^3] quadrature-point factors ([n_elems][7] if mf_cmp)
   double* yA;              // [n_elems][(mf_p + 1)^3]
   double* yM;              // [n_elems][(mf_p + 1)^3]
   const int64_t* adj_ptr;  // [n + 1] element entries of each node
   const int32_t* adj;      // entry e * npe + k, ascending
   double mfV[16], mfD[16]; // 1-D basis factor j and derivative at Gauss point q: [q * (p + 1) + j]
+  int32_t mf_cmp;          // geo compressed to [n_elems][7] element constants x Gauss weights mfW
+  double mfW[4];
   // Pipelined CG (cg_pipe != 0; the FP64 solve, or the FP32 inner solve of
   // mixed precision): one kernel per iteration.  Its iteration index, the
   // previous step lengths and the inner-solve state live in one record per

@@ -27,6 +27,7 @@ struct Launch {
   // the element kernels first
   int mf_p = 0;
   int64_t mf_elems = 0;
+  bool mf_cmp = false;     // compressed geometry factors (element constants)
   // pipelined CG of instances whose operators are all 14-diagonal symmetric
   // DIA with Jacobi preconditioning: the specialized kernels
   int pipe_op = 0;

@@ -174,7 +174,9 @@ struct MfShape {
 
 // WHICH 0: yA = (c M + K) z; 1: yM = M g; 2: yA = (c M + K) x0 (rhs residual);
 // 3: yA = (c M + K) m_k of the pipelined CG (k from tile 0's record)
-template <int P, int WHICH>
+// CMP: every element's factors are an element constant times the point's
+// Gauss weight (affine elements with one D): 7 loads per element.
+template <int P, int WHICH, bool CMP>
 __global__ __launch_bounds__(64) void k_mf_apply(InstDesc* __restrict__ insts) {
   using S_ = MfShape<P>;
   constexpr int N1 = S_::N1, T = S_::T, NPE = S_::NPE, EPW = S_::EPW;
@@ -248,7 +250,12 @@ __global__ __launch_bounds__(64) void k_mf_apply(InstDesc* __restrict__ insts) {
   __syncthreads();
   // x direction and the quadrature point: thread (qx, qy) = (i1, i2)
   double Mq[N1], F0[N1], F1[N1], F2[N1];
-  const gptr<const double> geo = gmem(I.geo) + (live ? e : 0) * 7 * NPE;
+  const gptr<const double> geo = gmem(I.geo) + (live ? e : 0) * 7 * (CMP ? 1 : NPE);
+  double ge[7];
+  if (CMP) {
+#pragma unroll
+    for (int c = 0; c < 7; c++) ge[c] = live ? geo[c] : 0.0;
+  }
 #pragma unroll
   for (int qz = 0; qz < N1; qz++) {
     double u = 0.0, ux = 0.0, uy = 0.0, uz = 0.0;
@@ -265,11 +272,15 @@ __global__ __launch_bounds__(64) void k_mf_apply(InstDesc* __restrict__ insts) {
       }
     }
     const int q = L(i1, i2, qz);
-    const double m = live ? geo[6 * NPE + q] : 0.0;
+    const double wq = CMP ? I.mfW[i1] * I.mfW[i2] * I.mfW[qz] : 0.0;
+    const double m = !live ? 0.0 : (CMP ? ge[6] * wq : geo[6 * NPE + q]);
     Mq[qz] = (STIFF ? cmass : 1.0) * m * u;
     if (STIFF) {
       double c0 = 0, c1 = 0, c2 = 0, c3 = 0, c4 = 0, c5 = 0;
-      if (live) {
+      if (live && CMP) {
+        c0 = ge[0] * wq; c1 = ge[1] * wq; c2 = ge[2] * wq;
+        c3 = ge[3] * wq; c4 = ge[4] * wq; c5 = ge[5] * wq;
+      } else if (live) {
         c0 = geo[q]; c1 = geo[NPE + q]; c2 = geo[2 * NPE + q];
         c3 = geo[3 * NPE + q]; c4 = geo[4 * NPE + q]; c5 = geo[5 * NPE + q];
       }
@@ -1736,20 +1747,20 @@ static void update_dispatch(const Launch& L) {
   else hipLaunchKernelGGL((k_cg_update<MX, true, 0>), g, b, 0, L.stream, L.insts, L.bmap);
 }
 
-template <int P>
+template <int P, bool CMP>
 static void mf_apply(int which, const Launch& L) {
   constexpr int EPW = MfShape<P>::EPW;
   const unsigned grid = (unsigned)((L.mf_elems + EPW - 1) / EPW);
   if (grid == 0) return;
-  if (which == 0) hipLaunchKernelGGL((k_mf_apply<P, 0>), dim3(grid), dim3(64), 0, L.stream, L.insts);
-  else if (which == 1) hipLaunchKernelGGL((k_mf_apply<P, 1>), dim3(grid), dim3(64), 0, L.stream, L.insts);
-  else if (which == 2) hipLaunchKernelGGL((k_mf_apply<P, 2>), dim3(grid), dim3(64), 0, L.stream, L.insts);
-  else hipLaunchKernelGGL((k_mf_apply<P, 3>), dim3(grid), dim3(64), 0, L.stream, L.insts);
+  if (which == 0) hipLaunchKernelGGL((k_mf_apply<P, 0, CMP>), dim3(grid), dim3(64), 0, L.stream, L.insts);
+  else if (which == 1) hipLaunchKernelGGL((k_mf_apply<P, 1, CMP>), dim3(grid), dim3(64), 0, L.stream, L.insts);
+  else if (which == 2) hipLaunchKernelGGL((k_mf_apply<P, 2, CMP>), dim3(grid), dim3(64), 0, L.stream, L.insts);
+  else hipLaunchKernelGGL((k_mf_apply<P, 3, CMP>), dim3(grid), dim3(64), 0, L.stream, L.insts);
 }
 
 static void launch_mf_apply(int which, const Launch& L) {
-  if (L.mf_p == 2) mf_apply<2>(which, L);
-  else if (L.mf_p == 3) mf_apply<3>(which, L);
+  if (L.mf_p == 2) L.mf_cmp ? mf_apply<2, true>(which, L) : mf_apply<2, false>(which, L);
+  else if (L.mf_p == 3) L.mf_cmp ? mf_apply<3, true>(which, L) : mf_apply<3, false>(which, L);
 }
 
 void launch_residual(bool mixed, bool with_rhs, const Launch& L) {
