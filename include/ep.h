@@ -88,7 +88,10 @@ enum {
   EP_OPT_IONIC_NPT = 6,     /* nodes per thread of the ionic kernel: 1 (512-thread
                                workgroups, default), 2 (256) or 4 (128)               */
   EP_OPT_TILE_MAP = 7,      /* 0: each XCD sweeps a contiguous range of 512-row tiles
-                               (default); 1: workgroup b takes tile b                 */
+                               (default); 1: workgroup b takes tile b; 2: on the
+                               14-diagonal DIA of a Q1 hexahedral lattice, each XCD
+                               takes the tiles of one band of lattice lines through
+                               every plane (other operators run map 0)             */
   EP_OPT_GRAPH = 8,         /* 1: replay the step's launch sequences from captured
                                HIP graphs (ignored while timers are on).  The stream
                                must allow capture (not the legacy null stream).      */
@@ -339,8 +342,8 @@ ep_status ep_sim_time_kernel(ep_sim* sim, int kind, int reps, double* us_per_lau
 /* Launch-shape tuner (a growth direction, not in the paper): runs
  * trial_steps steps per candidate with kernel timers on, first for the
  * ionic nodes per thread (1, 2, 4; scored by the ionic kernel's mean time),
- * then for the tile map (0, 1; scored by the mean SpMV + CG-update time),
- * and keeps the fastest of each.  The 5 * trial_steps steps advance the
+ * then for the tile map (0 and 2 on the Q1 lattice DIA, 0 and 1 otherwise;
+ * scored by the mean time of the CG kernels), and keeps the fastest of each.  The 5 * trial_steps steps advance the
  * simulation like ep_sim_step (results do not depend on the shapes).
  * Writes the chosen EP_OPT_IONIC_NPT and EP_OPT_TILE_MAP values to the
  * non-NULL outputs.  EP_ESTATE before finalize or while pooled. */

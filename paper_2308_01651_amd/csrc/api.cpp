@@ -508,6 +508,46 @@ bool block_inverses(const Csr& A, const std::vector<double>& val, int bs, int64_
   return ok;
 }
 
+// Tile map 2 of a single instance on a hexahedral lattice (the 14-diagonal
+// DIA of Q1 elements, offsets 0, 1, nx - 1 .. nx + 1 and P + {-nx, 0, nx} +
+// {-1, 0, 1} with P = nx ny the plane): the tiles, ordered by the lattice
+// line y of their middle row (then by index), are cut into N_XCD runs of
+// ceil(tiles / N_XCD); workgroup b takes the (b / N_XCD)-th tile of run
+// b mod N_XCD, in ascending tile order (workgroups go round-robin over the
+// dies, so each die receives one run: one band of lines through every plane).
+// Empty if the operator is not such a lattice.
+std::vector<int32_t> lattice_tile_table(const InstDesc& D, int64_t n, int ntiles, int nblocks) {
+  std::vector<int32_t> tab;
+  if (D.fmt != FMT_DIA || D.nup != 14) return tab;
+  const int64_t nx = D.off[3], P = D.off[9];
+  if (nx < 3 || P < 3 * nx || P % nx != 0 || n <= 0) return tab;
+  int k = 0;
+  for (int64_t dz = 0; dz <= 1; dz++)
+    for (int64_t dy = -1; dy <= 1; dy++)
+      for (int64_t dx = -1; dx <= 1; dx++) {
+        const int64_t o = dz * P + dy * nx + dx;
+        if (o < 0) continue;
+        if (k >= 14 || D.off[k] != o) return tab;
+        k++;
+      }
+  std::vector<std::pair<int64_t, int32_t>> key((size_t)ntiles);
+  for (int32_t t = 0; t < ntiles; t++) {
+    const int64_t rm = std::min<int64_t>((int64_t)t * TILE + TILE / 2, n - 1);
+    key[(size_t)t] = {(rm % P) / nx, t};
+  }
+  std::sort(key.begin(), key.end());
+  const int per = (ntiles + N_XCD - 1) / N_XCD;
+  if (nblocks != N_XCD * per) return tab;
+  tab.assign((size_t)nblocks, -1);
+  for (int x = 0; x < N_XCD; x++) {
+    std::vector<int32_t> run;
+    for (int j = x * per; j < std::min(ntiles, (x + 1) * per); j++) run.push_back(key[(size_t)j].second);
+    std::sort(run.begin(), run.end());
+    for (size_t j = 0; j < run.size(); j++) tab[j * N_XCD + (size_t)x] = run[j];
+  }
+  return tab;
+}
+
 ep_status finalize_impl(ep_sim* s) {
   auto t0 = std::chrono::steady_clock::now();
   if (s->finalized) return fail(EP_ESTATE, "sim already finalized");
@@ -1037,6 +1077,15 @@ ep_status finalize_impl(ep_sim* s) {
   D.nblk = ntiles;
   // single-instance launches cover N_XCD * ceil(tiles / N_XCD) workgroups
   s->nblocks = N_XCD * ((ntiles + N_XCD - 1) / N_XCD);
+  D.tile_tab = nullptr;
+  {
+    std::vector<int32_t> tab = lattice_tile_table(D, n, ntiles, s->nblocks);
+    if (!tab.empty()) {
+      int32_t* dt;
+      EP_HIP(upload(m, &dt, tab.data(), tab.size(), st));
+      D.tile_tab = dt;
+    }
+  }
   EP_HIP(m.alloc((void**)&D.partial, (size_t)ntiles * PART_DOUBLES * sizeof(double)));
   D.cg_pipe = cg_resolved(s) == EP_CG_PIPELINED ? 1 : 0;
   D.x0_extrap = s->x0_extrap;
@@ -1176,6 +1225,7 @@ ep_status validate_desc(const ep_sim* s, const InstDesc& D) {
   if (!in(D.smax, 0, n, 8) || !in(D.at, 0, n, 8) || !in(D.tcross, 0, n, 8)) return bad("activation range");
   if (!in(D.partial, 0, (int64_t)D.nblk * PART_DOUBLES, 8)) return bad("partial sums range");
   if (D.cg_pipe && !in(D.pipe_rec, 0, (int64_t)D.nblk * PIPE_REC, 8)) return bad("pipelined CG records");
+  if (D.tile_tab && !in(D.tile_tab, 0, s->nblocks, 4)) return bad("tile table range");
   if (D.cg_pipe && D.prec == P_MIXED && (!in(D.m32[0], G, n64 + 2 * G, 4) || !in(D.m32[1], G, n64 + 2 * G, 4)))
     return bad("pipelined FP32 vector range");
   for (int k = 0; k < D.n_stim; k++)
@@ -1198,7 +1248,7 @@ Launch launch_of(ep_sim* s) {
     L.mf_elems = s->n_elems;
     L.mf_cmp = s->desc.mf_cmp != 0;
   }
-  L.xmap = s->xmap;
+  L.xmap = (s->xmap == 2 && !s->desc.tile_tab) ? 0 : s->xmap;   // map 2 needs a lattice
   L.ionic_npt = s->ionic_npt;
   L.ionic_bdf = s->ionic_scheme == EP_IONIC_BDF;
   L.pipe_op = (s->desc.fmt == FMT_DIA && s->desc.nup == 14 && s->desc.block == 1) ? 1 : 0;
@@ -1565,7 +1615,7 @@ ep_status ep_sim_set_option(ep_sim* s, int key, double value) {
     const int v = (int)value;
     if ((double)v != value) return fail(EP_EINVAL, "launch option values are integers");
     if (key == EP_OPT_IONIC_NPT && v != 1 && v != 2 && v != 4) return fail(EP_EINVAL, "ionic nodes per thread: 1, 2 or 4");
-    if (key == EP_OPT_TILE_MAP && v != 0 && v != 1) return fail(EP_EINVAL, "tile map: 0 or 1");
+    if (key == EP_OPT_TILE_MAP && v != 0 && v != 1 && v != 2) return fail(EP_EINVAL, "tile map: 0, 1 or 2");
     if (key == EP_OPT_GRAPH && v != 0 && v != 1) return fail(EP_EINVAL, "graph: 0 or 1");
     if (s->stream) EP_HIP(hipStreamSynchronize(s->stream));
     if (key == EP_OPT_IONIC_NPT) s->ionic_npt = v;
@@ -1663,7 +1713,8 @@ ep_status ep_sim_autotune(ep_sim* s, int trial_steps, int* ionic_npt, int* tile_
       [&] { return kt.avg_us(0); }, &npt);
   if (rc == EP_OK)
     rc = tune_one(
-        kt, s->stream, trial_steps, {0, 1}, [&](int c) { s->xmap = c; }, step,
+        kt, s->stream, trial_steps, s->desc.tile_tab ? std::vector<int>{0, 2} : std::vector<int>{0, 1},
+        [&](int c) { s->xmap = c; }, step,
         [&] { return kt.avg_us(2) + kt.avg_us(3) + kt.avg_us(7); }, &xm);
   kt.zero();
   kt.on = was_on;

@@ -173,6 +173,10 @@ struct InstDesc {
   int32_t x0_extrap;       // 1: initial guess by third-order extrapolation (else u_EXT)
   double* pipe_rec;        // [nblk][PIPE_REC]
   float* m32[2];
+  // tile of each workgroup of a single-instance launch under tile map 2
+  // (lattice operators: each XCD takes the tiles of a band of lattice lines
+  // across all planes; -1 past the last tile of a band), or null
+  const int32_t* tile_tab;
 };
 constexpr int PIPE_REC = 8;
 

@@ -465,7 +465,11 @@ __device__ __forceinline__ A spmv_row(const InstDesc& I, const V* __restrict__ v
 // The launch has N_XCD * per workgroups; those past the last tile get
 // lblk = -1 and must leave at once.
 // XMAP = 1 maps workgroup b to tile b (dispatch order), for comparison by the
-// tuner.
+// tuner.  XMAP = 2 (lattice operators) reads the tile from a table in which
+// each die holds the tiles of one band of lattice lines (y) across all
+// planes (z): the far stencil neighbours of a row, one plane away, then lie
+// in the same die's L2 except at the band's two edge lines, where the
+// contiguous ranges of XMAP 0 cross dies once every plane's worth of rows.
 template <bool SINGLE, int XMAP = 0>
 __device__ __forceinline__ InstDesc& instance(InstDesc* __restrict__ insts, const BlockMap* __restrict__ bmap,
                                               int& lblk) {
@@ -473,6 +477,10 @@ __device__ __forceinline__ InstDesc& instance(InstDesc* __restrict__ insts, cons
     InstDesc& I = insts[0];
     if (XMAP == 1) {
       lblk = (int)blockIdx.x < I.nblk ? (int)blockIdx.x : -1;
+      return I;
+    }
+    if (XMAP == 2) {
+      lblk = gmem(I.tile_tab)[blockIdx.x];
       return I;
     }
     const int per = (I.nblk + N_XCD - 1) / N_XCD;
@@ -1721,13 +1729,15 @@ void launch_ici_correction(InstDesc* insts, int64_t n_crow, hipStream_t st) {
   hipLaunchKernelGGL(k_ici_correction, dim3((unsigned)((n_crow + WG - 1) / WG)), dim3(WG), 0, st, insts);
 }
 
-// CG-kernel launches: a single instance with the XCD-ordered (xmap 0) or the
-// dispatch-order (xmap 1) tile map, or a batch over its block map.
+// CG-kernel launches: a single instance with the XCD-ordered (xmap 0), the
+// dispatch-order (xmap 1) or the lattice-band (xmap 2) tile map, or a batch
+// over its block map.
 template <bool MX, bool RHS>
 static void residual_dispatch(const Launch& L) {
   const dim3 g(L.nblocks), b(WG);
   if (!L.single) hipLaunchKernelGGL((k_residual<MX, RHS, false, 0>), g, b, 0, L.stream, L.insts, L.bmap);
   else if (L.xmap == 1) hipLaunchKernelGGL((k_residual<MX, RHS, true, 1>), g, b, 0, L.stream, L.insts, L.bmap);
+  else if (L.xmap == 2) hipLaunchKernelGGL((k_residual<MX, RHS, true, 2>), g, b, 0, L.stream, L.insts, L.bmap);
   else hipLaunchKernelGGL((k_residual<MX, RHS, true, 0>), g, b, 0, L.stream, L.insts, L.bmap);
 }
 
@@ -1736,6 +1746,7 @@ static void spmv_dispatch(const Launch& L) {
   const dim3 g(L.nblocks), b(WG);
   if (!L.single) hipLaunchKernelGGL((k_cg_spmv<MX, false, 0>), g, b, 0, L.stream, L.insts, L.bmap);
   else if (L.xmap == 1) hipLaunchKernelGGL((k_cg_spmv<MX, true, 1>), g, b, 0, L.stream, L.insts, L.bmap);
+  else if (L.xmap == 2) hipLaunchKernelGGL((k_cg_spmv<MX, true, 2>), g, b, 0, L.stream, L.insts, L.bmap);
   else hipLaunchKernelGGL((k_cg_spmv<MX, true, 0>), g, b, 0, L.stream, L.insts, L.bmap);
 }
 
@@ -1744,6 +1755,7 @@ static void update_dispatch(const Launch& L) {
   const dim3 g(L.nblocks), b(WG);
   if (!L.single) hipLaunchKernelGGL((k_cg_update<MX, false, 0>), g, b, 0, L.stream, L.insts, L.bmap);
   else if (L.xmap == 1) hipLaunchKernelGGL((k_cg_update<MX, true, 1>), g, b, 0, L.stream, L.insts, L.bmap);
+  else if (L.xmap == 2) hipLaunchKernelGGL((k_cg_update<MX, true, 2>), g, b, 0, L.stream, L.insts, L.bmap);
   else hipLaunchKernelGGL((k_cg_update<MX, true, 0>), g, b, 0, L.stream, L.insts, L.bmap);
 }
 
@@ -1784,6 +1796,7 @@ void launch_cg_pipe32_start(const Launch& L) {
   const dim3 g(L.nblocks), b(WG);
   if (!L.single) hipLaunchKernelGGL((k_cg_pipe32_start<false, 0>), g, b, 0, L.stream, L.insts, L.bmap);
   else if (L.xmap == 1) hipLaunchKernelGGL((k_cg_pipe32_start<true, 1>), g, b, 0, L.stream, L.insts, L.bmap);
+  else if (L.xmap == 2) hipLaunchKernelGGL((k_cg_pipe32_start<true, 2>), g, b, 0, L.stream, L.insts, L.bmap);
   else hipLaunchKernelGGL((k_cg_pipe32_start<true, 0>), g, b, 0, L.stream, L.insts, L.bmap);
 }
 
@@ -1793,8 +1806,10 @@ void launch_cg_pipe32(const Launch& L) {
   if (!L.single && L.pipe_op == 1) hipLaunchKernelGGL((k_cg_pipe32<false, 0, 1>), g, b, 0, L.stream, L.insts, L.bmap);
   else if (!L.single) hipLaunchKernelGGL((k_cg_pipe32<false, 0, 0>), g, b, 0, L.stream, L.insts, L.bmap);
   else if (L.pipe_op == 1 && L.xmap == 1) hipLaunchKernelGGL((k_cg_pipe32<true, 1, 1>), g, b, 0, L.stream, L.insts, L.bmap);
+  else if (L.pipe_op == 1 && L.xmap == 2) hipLaunchKernelGGL((k_cg_pipe32<true, 2, 1>), g, b, 0, L.stream, L.insts, L.bmap);
   else if (L.pipe_op == 1) hipLaunchKernelGGL((k_cg_pipe32<true, 0, 1>), g, b, 0, L.stream, L.insts, L.bmap);
   else if (L.xmap == 1) hipLaunchKernelGGL((k_cg_pipe32<true, 1, 0>), g, b, 0, L.stream, L.insts, L.bmap);
+  else if (L.xmap == 2) hipLaunchKernelGGL((k_cg_pipe32<true, 2, 0>), g, b, 0, L.stream, L.insts, L.bmap);
   else hipLaunchKernelGGL((k_cg_pipe32<true, 0, 0>), g, b, 0, L.stream, L.insts, L.bmap);
 }
 
@@ -1804,6 +1819,7 @@ void launch_cg_pipe_start(const Launch& L) {
   const dim3 g(L.nblocks), b(WG);
   if (!L.single) hipLaunchKernelGGL((k_cg_pipe_start<false, 0>), g, b, 0, L.stream, L.insts, L.bmap);
   else if (L.xmap == 1) hipLaunchKernelGGL((k_cg_pipe_start<true, 1>), g, b, 0, L.stream, L.insts, L.bmap);
+  else if (L.xmap == 2) hipLaunchKernelGGL((k_cg_pipe_start<true, 2>), g, b, 0, L.stream, L.insts, L.bmap);
   else hipLaunchKernelGGL((k_cg_pipe_start<true, 0>), g, b, 0, L.stream, L.insts, L.bmap);
 }
 
@@ -1814,8 +1830,10 @@ void launch_cg_pipe(const Launch& L) {
   if (!L.single && L.pipe_op == 1) hipLaunchKernelGGL((k_cg_pipe<false, 0, 1>), g, b, 0, L.stream, L.insts, L.bmap);
   else if (!L.single) hipLaunchKernelGGL((k_cg_pipe<false, 0, 0>), g, b, 0, L.stream, L.insts, L.bmap);
   else if (L.pipe_op == 1 && L.xmap == 1) hipLaunchKernelGGL((k_cg_pipe<true, 1, 1>), g, b, 0, L.stream, L.insts, L.bmap);
+  else if (L.pipe_op == 1 && L.xmap == 2) hipLaunchKernelGGL((k_cg_pipe<true, 2, 1>), g, b, 0, L.stream, L.insts, L.bmap);
   else if (L.pipe_op == 1) hipLaunchKernelGGL((k_cg_pipe<true, 0, 1>), g, b, 0, L.stream, L.insts, L.bmap);
   else if (L.xmap == 1) hipLaunchKernelGGL((k_cg_pipe<true, 1, 0>), g, b, 0, L.stream, L.insts, L.bmap);
+  else if (L.xmap == 2) hipLaunchKernelGGL((k_cg_pipe<true, 2, 0>), g, b, 0, L.stream, L.insts, L.bmap);
   else hipLaunchKernelGGL((k_cg_pipe<true, 0, 0>), g, b, 0, L.stream, L.insts, L.bmap);
 }
 
@@ -1841,6 +1859,7 @@ void launch_cg_update64(const Launch& L) {
   const dim3 g(L.nblocks), b(WG);
   if (!L.single) hipLaunchKernelGGL((k_cg_update64<false, 0>), g, b, 0, L.stream, L.insts, L.bmap);
   else if (L.xmap == 1) hipLaunchKernelGGL((k_cg_update64<true, 1>), g, b, 0, L.stream, L.insts, L.bmap);
+  else if (L.xmap == 2) hipLaunchKernelGGL((k_cg_update64<true, 2>), g, b, 0, L.stream, L.insts, L.bmap);
   else hipLaunchKernelGGL((k_cg_update64<true, 0>), g, b, 0, L.stream, L.insts, L.bmap);
 }
 

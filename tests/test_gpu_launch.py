@@ -53,6 +53,8 @@ def test_launch_shapes_and_graphs_are_bitwise_neutral(model, variant, prec):
         [(ep.EP_OPT_IONIC_NPT, 4), (ep.EP_OPT_TILE_MAP, 1)],
         [(ep.EP_OPT_GRAPH, 1)],
         [(ep.EP_OPT_GRAPH, 1), (ep.EP_OPT_IONIC_NPT, 2), (ep.EP_OPT_TILE_MAP, 1)],
+        [(ep.EP_OPT_TILE_MAP, 2)],
+        [(ep.EP_OPT_GRAPH, 1), (ep.EP_OPT_TILE_MAP, 2)],
     ]
     for opts in variants:
         got = _run(spec, prec, 60, opts)
@@ -85,7 +87,7 @@ def test_autotune_is_bitwise_neutral(prec):
     ref = _run(spec, prec, 80)
     got = _run(spec, prec, 80, tune=6)
     npt, tmap = got[4]
-    assert npt in (1, 2, 4) and tmap in (0, 1)
+    assert npt in (1, 2, 4) and tmap in (0, 1, 2)
     assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
     assert got[3] == ref[3]
 
@@ -93,12 +95,36 @@ def test_autotune_is_bitwise_neutral(prec):
 def test_launch_options_rejected():
     ep = _ep()
     s = ep.Simulation.from_spec(_spec())
-    for k, v in [(ep.EP_OPT_IONIC_NPT, 3), (ep.EP_OPT_TILE_MAP, 2), (ep.EP_OPT_GRAPH, 0.5), (99, 1)]:
+    for k, v in [(ep.EP_OPT_IONIC_NPT, 3), (ep.EP_OPT_TILE_MAP, 3), (ep.EP_OPT_GRAPH, 0.5), (99, 1)]:
         with pytest.raises(ep.EpError):
             s.set_option(k, v)
     with pytest.raises(ep.EpError):
         s.autotune(0)
     s.close()
+
+
+@pytest.mark.parametrize("case", ["c1", "q2", "p1"])
+def test_lattice_band_tile_map(case):
+    """Tile map 2 on the C1 lattice (865 tiles; every tile taken by exactly
+    one workgroup or results would differ) and on operators that are not the
+    Q1 lattice DIA (sliced-ELL Q2, the Kuhn P1 DIA), where it runs map 0:
+    bitwise equal to the default launches."""
+    ep = _ep()
+    if case == "c1":
+        spec = W.config_c1(h=0.1, n_steps=1)
+        steps = 20
+    else:
+        dims = (4.0, 2.0, 1.0)
+        mesh = W.slab_q2(*dims, 0.5) if case == "q2" else W.slab_p1(*dims, 0.25)
+        spec = W.SimSpec(mesh, W.uniform_fibers(mesh.n_nodes), W.Physics(), "ttp06", "endo",
+                         [W.corner_cube_stimulus(dims=dims)], 0.05, 2, 1, 1e-10, "t")
+        steps = 60
+    for prec in (0, 1):
+        ref = _run(spec, prec, steps)
+        got = _run(spec, prec, steps, [(ep.EP_OPT_TILE_MAP, 2)])
+        print(f"{case} prec {prec}: {steps} steps, {ref[3]} CG iterations", flush=True)
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), (case, prec)
+        assert got[3] == ref[3]
 
 
 @pytest.mark.parametrize("prec", [0, 1])
