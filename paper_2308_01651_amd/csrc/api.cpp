@@ -1418,30 +1418,61 @@ ep_status step_once(ep_sim* s) {
   return EP_OK;
 }
 
-// Tuner core: run `trial` steps per candidate of one launch-shape setting
-// with kernel timers on, score each candidate by the mean duration of the
-// kernels it affects, keep the best.  The steps are real steps of the
-// simulation; every candidate computes bitwise the same results.
+// Kernel-timer totals of one tuner candidate.
+struct TimerSums {
+  double ms[KernelTimers::K] = {};
+  int64_t count[KernelTimers::K] = {};
+  double avg_us(int k) const { return count[k] ? 1e3 * ms[k] / (double)count[k] : 0.0; }
+};
+
+// Tile-map score: the mean durations of the kernels that work on tiles (rhs
+// and refinement residuals, SpMV or pipelined start, updates, pipelined
+// iterations), each kind once.
+static double tile_kernels_us(const TimerSums& a) {
+  return a.avg_us(1) + a.avg_us(2) + a.avg_us(3) + a.avg_us(5) + a.avg_us(7);
+}
+
+// Tuner core: `trial` steps per candidate of one launch-shape setting with
+// kernel timers on, in up to three rounds that visit the candidates in
+// alternating order (A B C, C B A, A B C), so that the drift of the
+// simulation's work from step to step (iteration counts follow the
+// propagation phase) weighs on every candidate alike; each candidate is
+// scored on the mean durations, over its rounds, of the kernels it affects;
+// the best is kept.  The steps are real steps of the simulation; every
+// candidate computes bitwise the same results.
 template <typename Step, typename Set, typename Score>
 ep_status tune_one(KernelTimers& kt, hipStream_t st, int trial, const std::vector<int>& cands, Set&& set,
                    Step&& step, Score&& score, int* best_out) {
+  const int nc = (int)cands.size();
+  std::vector<TimerSums> acc((size_t)nc);
+  const int rounds = std::min(trial, 3);
+  for (int r = 0; r < rounds; r++) {
+    const int steps = trial / rounds + (r < trial % rounds ? 1 : 0);
+    for (int j = 0; j < nc; j++) {
+      const int ci = (r & 1) ? nc - 1 - j : j;
+      set(cands[(size_t)ci]);
+      EP_HIP(hipStreamSynchronize(st));
+      kt.harvest();
+      kt.zero();
+      for (int k = 0; k < steps; k++) {
+        ep_status rc = step();
+        if (rc != EP_OK && rc != EP_ENOCONV) return rc;
+      }
+      EP_HIP(hipStreamSynchronize(st));
+      kt.harvest();
+      for (int k = 0; k < KernelTimers::K; k++) {
+        acc[(size_t)ci].ms[k] += kt.ms[k];
+        acc[(size_t)ci].count[k] += kt.count[k];
+      }
+    }
+  }
   double best = std::numeric_limits<double>::infinity();
   int best_c = cands.front();
-  for (int c : cands) {
-    set(c);
-    EP_HIP(hipStreamSynchronize(st));
-    kt.harvest();
-    kt.zero();
-    for (int k = 0; k < trial; k++) {
-      ep_status rc = step();
-      if (rc != EP_OK && rc != EP_ENOCONV) return rc;
-    }
-    EP_HIP(hipStreamSynchronize(st));
-    kt.harvest();
-    const double t = score();
+  for (int ci = 0; ci < nc; ci++) {
+    const double t = score(acc[(size_t)ci]);
     if (t < best) {
       best = t;
-      best_c = c;
+      best_c = cands[(size_t)ci];
     }
   }
   set(best_c);
@@ -1710,12 +1741,12 @@ ep_status ep_sim_autotune(ep_sim* s, int trial_steps, int* ionic_npt, int* tile_
   int npt = s->ionic_npt, xm = s->xmap;
   ep_status rc = tune_one(
       kt, s->stream, trial_steps, {1, 2, 4}, [&](int c) { s->ionic_npt = c; }, step,
-      [&] { return kt.avg_us(0); }, &npt);
+      [](const TimerSums& a) { return a.avg_us(0); }, &npt);
   if (rc == EP_OK)
     rc = tune_one(
         kt, s->stream, trial_steps, s->desc.tile_tab ? std::vector<int>{0, 2} : std::vector<int>{0, 1},
         [&](int c) { s->xmap = c; }, step,
-        [&] { return kt.avg_us(2) + kt.avg_us(3) + kt.avg_us(7); }, &xm);
+        [](const TimerSums& a) { return tile_kernels_us(a); }, &xm);
   kt.zero();
   kt.on = was_on;
   s->graphs.reset();
@@ -2705,7 +2736,7 @@ ep_status ep_pool_autotune(ep_pool* P, int trial_steps, int* ionic_npt, int* til
   int npt = P->ionic_npt, lo = P->list_order;
   ep_status rc = tune_one(
       kt, P->stream, trial_steps, {1, 2, 4}, [&](int c) { P->ionic_npt = c; }, step,
-      [&] { return kt.avg_us(0); }, &npt);
+      [](const TimerSums& a) { return a.avg_us(0); }, &npt);
   if (rc == EP_OK)
     rc = tune_one(
         kt, P->stream, trial_steps, {0, 1},
@@ -2715,7 +2746,7 @@ ep_status ep_pool_autotune(ep_pool* P, int trial_steps, int* ionic_npt, int* til
             P->dirty = true;
           }
         },
-        step, [&] { return kt.avg_us(2) + kt.avg_us(3) + kt.avg_us(7); }, &lo);
+        step, [](const TimerSums& a) { return tile_kernels_us(a); }, &lo);
   kt.zero();
   kt.on = 0;
   P->graphs.reset();
