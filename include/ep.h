@@ -344,7 +344,8 @@ ep_status ep_sim_time_kernel(ep_sim* sim, int kind, int reps, double* us_per_lau
  * ionic nodes per thread (1, 2, 4; scored by the ionic kernel's mean time),
  * then for the tile map (0 and 2 on the Q1 lattice DIA, 0 and 1 otherwise;
  * scored by the mean durations of the residual, SpMV, update and pipelined
- * iteration kernels), and keeps the fastest of each.  Each candidate's
+ * iteration kernels, each weighted by its launch count), and keeps the
+ * fastest of each.  Each candidate's
  * trial_steps are split over up to three rounds that visit the candidates
  * in alternating order, so that the simulation's drift in work from step to
  * step weighs on all of them alike.  The 5 * trial_steps steps advance the

@@ -1427,9 +1427,12 @@ struct TimerSums {
 
 // Tile-map score: the mean durations of the kernels that work on tiles (rhs
 // and refinement residuals, SpMV or pipelined start, updates, pipelined
-// iterations), each kind once.
-static double tile_kernels_us(const TimerSums& a) {
-  return a.avg_us(1) + a.avg_us(2) + a.avg_us(3) + a.avg_us(5) + a.avg_us(7);
+// iterations), each weighted by how often that kind ran over all candidates'
+// trial steps (the same weights for every candidate).
+static double tile_kernels_us(const TimerSums& a, const TimerSums& all) {
+  double t = 0.0;
+  for (int k : {1, 2, 3, 5, 7}) t += a.avg_us(k) * (double)all.count[k];
+  return t;
 }
 
 // Tuner core: `trial` steps per candidate of one launch-shape setting with
@@ -1437,8 +1440,9 @@ static double tile_kernels_us(const TimerSums& a) {
 // alternating order (A B C, C B A, A B C), so that the drift of the
 // simulation's work from step to step (iteration counts follow the
 // propagation phase) weighs on every candidate alike; each candidate is
-// scored on the mean durations, over its rounds, of the kernels it affects;
-// the best is kept.  The steps are real steps of the simulation; every
+// scored on the mean durations, over its rounds, of the kernels it affects
+// (weighted, where several kinds count, by the launches of each kind over
+// all candidates); the best is kept.  The steps are real steps of the simulation; every
 // candidate computes bitwise the same results.
 template <typename Step, typename Set, typename Score>
 ep_status tune_one(KernelTimers& kt, hipStream_t st, int trial, const std::vector<int>& cands, Set&& set,
@@ -1466,10 +1470,16 @@ ep_status tune_one(KernelTimers& kt, hipStream_t st, int trial, const std::vecto
       }
     }
   }
+  TimerSums all;
+  for (const TimerSums& a : acc)
+    for (int k = 0; k < KernelTimers::K; k++) {
+      all.ms[k] += a.ms[k];
+      all.count[k] += a.count[k];
+    }
   double best = std::numeric_limits<double>::infinity();
   int best_c = cands.front();
   for (int ci = 0; ci < nc; ci++) {
-    const double t = score(acc[(size_t)ci]);
+    const double t = score(acc[(size_t)ci], all);
     if (t < best) {
       best = t;
       best_c = cands[(size_t)ci];
@@ -1741,12 +1751,12 @@ ep_status ep_sim_autotune(ep_sim* s, int trial_steps, int* ionic_npt, int* tile_
   int npt = s->ionic_npt, xm = s->xmap;
   ep_status rc = tune_one(
       kt, s->stream, trial_steps, {1, 2, 4}, [&](int c) { s->ionic_npt = c; }, step,
-      [](const TimerSums& a) { return a.avg_us(0); }, &npt);
+      [](const TimerSums& a, const TimerSums&) { return a.avg_us(0); }, &npt);
   if (rc == EP_OK)
     rc = tune_one(
         kt, s->stream, trial_steps, s->desc.tile_tab ? std::vector<int>{0, 2} : std::vector<int>{0, 1},
         [&](int c) { s->xmap = c; }, step,
-        [](const TimerSums& a) { return tile_kernels_us(a); }, &xm);
+        [](const TimerSums& a, const TimerSums& all) { return tile_kernels_us(a, all); }, &xm);
   kt.zero();
   kt.on = was_on;
   s->graphs.reset();
@@ -2736,7 +2746,7 @@ ep_status ep_pool_autotune(ep_pool* P, int trial_steps, int* ionic_npt, int* til
   int npt = P->ionic_npt, lo = P->list_order;
   ep_status rc = tune_one(
       kt, P->stream, trial_steps, {1, 2, 4}, [&](int c) { P->ionic_npt = c; }, step,
-      [](const TimerSums& a) { return a.avg_us(0); }, &npt);
+      [](const TimerSums& a, const TimerSums&) { return a.avg_us(0); }, &npt);
   if (rc == EP_OK)
     rc = tune_one(
         kt, P->stream, trial_steps, {0, 1},
@@ -2746,7 +2756,7 @@ ep_status ep_pool_autotune(ep_pool* P, int trial_steps, int* ionic_npt, int* til
             P->dirty = true;
           }
         },
-        step, [](const TimerSums& a) { return tile_kernels_us(a); }, &lo);
+        step, [](const TimerSums& a, const TimerSums& all) { return tile_kernels_us(a, all); }, &lo);
   kt.zero();
   kt.on = 0;
   P->graphs.reset();
