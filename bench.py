@@ -54,7 +54,8 @@ def _workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def kernel_bytes(kind, n, nnz, mixed, nvars_model, fmt="DIA", n_diag=0, pipe=False, ent=0):
+def kernel_bytes(kind, n, nnz, mixed, nvars_model, fmt="DIA", n_diag=0, pipe=False, ent=0, n_elems=0,
+                 mf_cmp=False):
     """Algorithmic HBM bytes per launch of each kernel: every array the kernel
     must touch, read or written once.  The operator counts as stored: the
     symmetric DIA format keeps n_diag diagonals (offsets >= 0) of n values
@@ -63,16 +64,20 @@ def kernel_bytes(kind, n, nnz, mixed, nvars_model, fmt="DIA", n_diag=0, pipe=Fal
     pipelined CG, whose "cg_spmv" is its start kernel (w_0 = A u_0 and
     m_0 = P^-1 w_0: reads z, dinv, writes w, m_0) and whose iteration kernel
     "cg_pipe" reads m (gathered), dinv, z, w, p, s, x, r and writes z, s, p,
-    x, r, w, m'.  MF (matrix-free, ent = element-node entries): an operator
-    application reads per entry the gathered x, 7 geometry factors and the
-    node index and writes the element result (76 B), and the node sums read
-    each result with its 4-byte entry index (12 B); the mass-only application
-    of the rhs reads 1 geometry factor (28 B per entry)."""
+    x, r, w, m'.  MF (matrix-free, ent = element-node entries over n_elems
+    elements): an operator application reads per entry the gathered x and
+    the node index and writes the element result (20 B), plus 7 geometry
+    factors per entry (56 B) or, compressed (mf_cmp), 7 constants per
+    element; the node sums read each result with its 4-byte entry index
+    (12 B); the mass-only application of the rhs reads 1 geometry factor per
+    entry, or 1 constant per element compressed."""
     if fmt == "MF":
+        geo7 = 56 * (n_elems if mf_cmp else ent)
+        geo1 = 8 * (n_elems if mf_cmp else ent)
         if kind in ("cg_spmv", "cg_pipe"):
-            return 88 * ent + n * (24 if kind == "cg_spmv" else 112)
+            return 32 * ent + geo7 + n * (24 if kind == "cg_spmv" else 112)
         if kind == "rhs":
-            return (28 + 76 + 24) * ent + n * 48
+            return (20 + 20 + 24) * ent + geo1 + geo7 + n * 48
     def mat(vb):
         return n_diag * n * vb if fmt == "DIA" else nnz * (vb + 4)
     if kind == "cg_pipe":
@@ -239,6 +244,7 @@ def run_gpu(spec, precision, steps, warmup, instrument_steps, graph=True, autotu
         "rel_residual_last": st["rel_residual_last"],
         "matrix_format": {1: "SELL", 2: "DIA", 3: "MF"}[st["matrix_format"]],
         "n_diag": st["n_diag"],
+        "mf_compressed": bool(st["mf_compressed"]),
         "nnz": st["nnz"],
         "device_bytes": st["device_bytes"],
         "setup_ms": st0["ms_setup"],
@@ -321,15 +327,15 @@ def roofline(res, spec, precision_name, workload_key):
     dom = max((k for k in kinds if k != "cg_finalize"), key=lambda k: ms[k])
     # n_diag counts the operator's diagonals; the symmetric DIA stores the (n_diag + 1) / 2 with offset >= 0
     fmt, nd = res["matrix_format"], (int(res["n_diag"]) + 1) // 2
-    ent = int(spec.mesh.conn.size)
-    bytes_per = kernel_bytes(dom, n, nnz, mixed, nv, fmt, nd, pipe, ent)
+    ent, n_el, cmp = int(spec.mesh.conn.size), int(spec.mesh.conn.shape[0]), bool(res.get("mf_compressed"))
+    bytes_per = kernel_bytes(dom, n, nnz, mixed, nv, fmt, nd, pipe, ent, n_el, cmp)
     raw_s = ms[dom] / 1e3 / work[dom]
     loop = res.get("loop_us", {})
     avg_s = 1e-6 * loop[dom] if dom in loop else raw_s
     achieved = bytes_per / avg_s / 1e9
     per_kernel = {}
     for k in kinds:
-        b = kernel_bytes(k, n, nnz, mixed, nv, fmt, nd, pipe, ent)
+        b = kernel_bytes(k, n, nnz, mixed, nv, fmt, nd, pipe, ent, n_el, cmp)
         a = ms[k] / 1e3 / work[k]
         per_kernel[k] = {"avg_us_events": 1e6 * a, "launches": cnt[k], "launches_with_work": work[k],
                          "share": ms[k] / sum(ms.values()), "GBps_events": b / a / 1e9 if b else None,

@@ -169,6 +169,9 @@ typedef struct ep_stats {
   int64_t device_bytes;     /* device memory held by the sim                        */
   double ms_ionic, ms_rhs, ms_solve, ms_activation; /* phase times (if enabled)     */
   double ms_setup;          /* host assembly + upload in ep_sim_finalize            */
+  int32_t mf_compressed;    /* EP_FMT_MF: 1 if every element keeps 7 geometry
+                               constants (affine elements with one diffusion
+                               tensor), 0 if 7 factors per quadrature point      */
 } ep_stats;
 
 /* ---- simulation lifecycle -------------------------------------------------- */

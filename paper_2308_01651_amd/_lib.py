@@ -30,7 +30,7 @@ class EpStats(C.Structure):
                 ("rel_residual_last", C.c_double), ("matrix_format", C.c_int32),
                 ("n_diag", C.c_int32), ("device_bytes", C.c_int64), ("ms_ionic", C.c_double),
                 ("ms_rhs", C.c_double), ("ms_solve", C.c_double), ("ms_activation", C.c_double),
-                ("ms_setup", C.c_double)]
+                ("ms_setup", C.c_double), ("mf_compressed", C.c_int32)]
 
 
 if not os.path.exists(LIB_PATH):

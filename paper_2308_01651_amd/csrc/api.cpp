@@ -1961,6 +1961,7 @@ ep_status ep_sim_get_stats(ep_sim* s, ep_stats* o) {
   if (s->prec != EP_MIXED && S.bb == 0) o->rel_residual_last = 0.0;
   o->matrix_format = s->desc.fmt == FMT_DIA ? EP_FMT_DIA : (s->desc.fmt == FMT_MF ? EP_FMT_MF : EP_FMT_SELL);
   o->n_diag = s->desc.fmt == FMT_DIA ? 2 * s->desc.nup - 1 : 0;
+  o->mf_compressed = s->desc.fmt == FMT_MF && s->desc.mf_cmp ? 1 : 0;
   o->device_bytes = (int64_t)s->mem.bytes;
   o->ms_ionic = s->ms_phase[0];
   o->ms_rhs = s->ms_phase[1];

@@ -216,5 +216,7 @@ def test_matrix_free_compressed_geometry(kind):
     n_el = mesh.conn.shape[0]
     saved = full.get_stats()["device_bytes"] - mf.get_stats()["device_bytes"]
     assert saved >= 0.9 * n_el * 7 * (q - 1) * 8, (saved, n_el)
+    assert mf.get_stats()["mf_compressed"] == 1 and full.get_stats()["mf_compressed"] == 0
+    assert sell.get_stats()["mf_compressed"] == 0
     for s in (mf, sell, full):
         s.close()
