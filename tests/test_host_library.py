@@ -183,3 +183,29 @@ def test_degree_six_element_matrices_are_assembled_in_chunks():
     K = sp.csr_matrix((vk, col, rowptr), shape=(m.n_nodes, m.n_nodes))
     assert abs(M.sum() - 150.0) < 1e-10 * 150.0        # volume of the block
     assert np.max(np.abs(K @ np.ones(m.n_nodes))) < 1e-12 * abs(K).max()
+
+
+def _c_struct_fields(name):
+    """(field, C type) of `typedef struct name { ... } name;` in include/ep.h, in order."""
+    txt = open(os.path.join(ROOT, "include", "ep.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    body = re.search(r"typedef struct %s \{(.*?)\} %s;" % (name, name), txt, flags=re.S).group(1)
+    out = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        ctype, names = decl.split(None, 1)
+        out += [(n.strip(), ctype) for n in names.split(",")]
+    return out
+
+
+def test_stats_struct_matches_the_header():
+    """The binding's ep_stats mirror has the header's fields, in order and
+    with the same C types (a mismatch would shift every later field)."""
+    import ctypes as C
+    import paper_2308_01651_amd as ep
+    ctypes_of = {"int64_t": C.c_int64, "int32_t": C.c_int32, "double": C.c_double}
+    fields = _c_struct_fields("ep_stats")
+    assert len(fields) >= 17 and fields[-1][0] == "mf_compressed"
+    assert [(n, ctypes_of[t]) for n, t in fields] == list(ep._lib.EpStats._fields_)
