@@ -1,6 +1,6 @@
 """Pins of the oracle's time stepping against closed forms and invariants.
 
-- cosine eigenmode of the slab with I_ion = 0 decays by the BDF1 / BDF2
+- cosine eigenmode of the slab with I_ion = 0 decays by the BDF1 / BDF2 / BDF3
   recurrences (fixes M, K, the RHS and the BDF coefficients; with the
   printed u_EXT history term BDF2 would follow another recurrence);
 - charge conservation 1^T M u with I_ion = 0 (fixes the applied-current load);
@@ -217,3 +217,33 @@ def test_activation_time_converges_under_refinement():
     d1 = abs(ats[0] - ats[1])
     d2 = abs(ats[1] - ats[2])
     assert d2 < 0.7 * d1, ats
+
+
+def test_cosine_mode_bdf3_recurrence():
+    """BDF3 (the paper's BDF of order up to 3): after the BDF1 and BDF2
+    start-up steps the mode amplitude follows
+    (11/6 a_{n+1} - 3 a_n + 3/2 a_{n-1} - 1/3 a_{n-2}) / dt = -mu a_{n+1}."""
+    D = (0.12, 0.013, 0.009)
+    m = W.slab_q1(20.0, 7.0, 3.0, 0.5)
+    o = _passive(m, D, 3)
+    v = np.cos(3 * np.pi * m.xyz[:, 0] / 20.0) * np.cos(2 * np.pi * m.xyz[:, 2] / 3.0)
+    o.set_state(v, np.zeros((0, m.n_nodes)))
+    h = 0.5
+
+    def lam(kk, N):
+        th = kk * np.pi / N
+        return 6 / h ** 2 * (1 - np.cos(th)) / (2 + np.cos(th))
+
+    mu = D[0] * lam(3, m.dims[0] - 1) + D[2] * lam(2, m.dims[2] - 1)
+    dt = 0.05
+    a = [1.0]
+    o.step()                                        # BDF1
+    a.append(a[-1] / (1 + dt * mu))
+    assert np.max(np.abs(o.u - a[-1] * v)) < 1e-12
+    o.step()                                        # BDF2
+    a.append((2 * a[-1] - 0.5 * a[-2]) / (1.5 + dt * mu))
+    assert np.max(np.abs(o.u - a[-1] * v)) < 1e-12
+    for _ in range(30):
+        o.step()
+        a.append((3 * a[-1] - 1.5 * a[-2] + a[-3] / 3) / (11 / 6 + dt * mu))
+        assert np.max(np.abs(o.u - a[-1] * v)) < 1e-12
