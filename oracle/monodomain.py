@@ -25,9 +25,11 @@ Test infrastructure.  Follows the paper's numerical discretization (Section
 Solvers: dense LU for tiny meshes, sparse LU (factorized once per BDF order)
 for small ones, textbook Jacobi-preconditioned CG for large ones.
 
-Pins: cosine eigenmode decay (BDF1 and BDF2 closed forms), charge
+Pins: cosine eigenmode decay (BDF1, BDF2 and BDF3 closed forms), charge
 conservation, uniform-state reduction to the 0D ionic ODE, dense-solve
-agreement, bistable-front speed, activation-time self-convergence.
+agreement, bistable-front speed, activation-time self-convergence; the
+applied current's profiles (lattice counts, the Gaussian load against its
+integral to the trapezoid rule's leading error term) and pulse windows.
 """
 from __future__ import annotations
 
