@@ -247,3 +247,25 @@ def test_cosine_mode_bdf3_recurrence():
         o.step()
         a.append((3 * a[-1] - 1.5 * a[-2] + a[-3] / 3) / (11 / 6 + dt * mu))
         assert np.max(np.abs(o.u - a[-1] * v)) < 1e-12
+
+
+@pytest.mark.parametrize("model,variant,bdf", [("ap", "", 1), ("bo", "epi", 2)])
+def test_activation_time_is_the_steepest_step_of_the_trajectory(model, variant, bdf):
+    """With the whole domain stimulated every node follows the single-cell
+    trajectory u_0, u_1, ...; its activation time is then t_{k+1} for the
+    first k maximizing (u_{k+1} - u_k) / dt (found here by argmax over the
+    recorded trajectory), reported because u crossed the threshold."""
+    m = W.slab_q1(3.0, 2.0, 1.0, 0.5)
+    big = W.Stimulus(W.CUBE, (1.5, 1.0, 0.5), 10.0, 50.0, 0.0, 1.0, 0.0)
+    f, s, n = W.uniform_fibers(m.n_nodes)
+    o = OM.Monodomain(m.xyz, m.conn, (f, s, n), (0.17, 0.019, 0.019), 140.0, 0.01, model, variant,
+                      [big], 0.05, bdf, "dense")
+    traj = [o.u[0]]
+    for _ in range(160):
+        o.step()
+        traj.append(o.u[0])
+    traj = np.array(traj)
+    assert np.max(traj) > o.model.threshold
+    k = int(np.argmax(np.diff(traj)))
+    at = o.activation_times()
+    assert np.all(np.abs(at - (k + 1) * 0.05) < 1e-12), (at[:3], (k + 1) * 0.05)
