@@ -209,3 +209,27 @@ def test_stats_struct_matches_the_header():
     fields = _c_struct_fields("ep_stats")
     assert len(fields) >= 17 and fields[-1][0] == "mf_compressed"
     assert [(n, ctypes_of[t]) for n, t in fields] == list(ep._lib.EpStats._fields_)
+
+
+def test_binding_constants_match_the_header():
+    """Every numeric constant of include/ep.h that the binding names has the
+    header's value (status codes in _lib); the binding's kernel-kind list is
+    indexed by the header's EP_K_* values."""
+    import paper_2308_01651_amd as ep
+    txt = open(os.path.join(ROOT, "include", "ep.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    consts = dict(re.findall(r"\b(EP_[A-Z0-9_]+)\s*=\s*(-?\d+)", txt))
+    consts.update(re.findall(r"#define\s+(EP_[A-Z0-9_]+)\s+(-?\d+)", txt))
+    checked = 0
+    for name, v in consts.items():
+        if name.startswith("EP_K_") or name == "EP_N_KERNEL_KINDS":
+            continue
+        mod = ep if hasattr(ep, name) else ep._lib
+        assert hasattr(mod, name), name
+        assert getattr(mod, name) == int(v), (name, getattr(mod, name), v)
+        checked += 1
+    assert checked >= 40
+    kinds = {n: int(v) for n, v in consts.items() if n.startswith("EP_K_")}
+    assert len(ep.KERNEL_KINDS) == int(consts["EP_N_KERNEL_KINDS"]) == len(kinds)
+    for n, v in kinds.items():
+        assert ep.KERNEL_KINDS[v] == n[len("EP_K_"):].lower(), (n, v, ep.KERNEL_KINDS[v])
